@@ -1,0 +1,474 @@
+"""FP64 oracle: the dG Arakawa bracket, the LDG Laplacian, CG, SSP-RK3 and
+the invariants, written plainly from the paper's definitions.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never used by the
+product path.
+
+Layout.  Public functions take and return fields in the canonical cell-major
+layout ``u[cy, cx, j, i]`` (numpy shape ``(Ny, Nx, n, n)``): cell (cx, cy),
+y-node j, x-node i, holding nodal values at the Gauss-Legendre points
+("X-space", Sec. 4.3 last paragraph).  Internally the oracle works on the
+image layout ``U[cy*n + j, cx*n + i]`` where a 1D operator along x is a right
+multiplication by its transpose and one along y a left multiplication
+(Sec. 4.3, the Kronecker-product extension to two dimensions).
+
+Parity status of each function is stated in its docstring; every function is
+pinned by a test in ``tests/test_oracle_*.py`` against something other than
+itself (library routines, closed forms, printed values, invariants).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+from numpy.polynomial.legendre import leggauss
+
+__all__ = [
+    "legendre_values", "ReferenceElement", "Grid1D", "Grid2D",
+    "to_image", "from_image", "dx", "dy", "dx_form", "dy_form",
+    "bracket_forms", "bracket", "laplacian", "inner", "wmean",
+    "cg_poisson", "rhs", "rk3_step", "PsiHistory", "invariants",
+    "dense_operators", "dense_poisson_solve", "arakawa_fd_jacobian",
+    "five_point_laplacian",
+]
+
+
+# --------------------------------------------------------------------------
+# Reference element (Sec. 4.1)
+# --------------------------------------------------------------------------
+def legendre_values(nk: int, x) -> np.ndarray:
+    """p_0..p_{nk-1} at the points x by the three-term recursion
+    (k+1) p_{k+1} = (2k+1) x p_k - k p_{k-1}, p_0 = 1, p_1 = x (Sec. 4.1,
+    eq. recursion).  Returns shape (nk, len(x))."""
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    out = np.zeros((nk, x.size))
+    out[0] = 1.0
+    if nk > 1:
+        out[1] = x
+    for k in range(1, nk - 1):
+        out[k + 1] = ((2 * k + 1) * x * out[k] - k * out[k - 1]) / (k + 1)
+    return out
+
+
+@dataclass
+class ReferenceElement:
+    """All P x P pieces of Sec. 4.1 for P = n polynomials per cell.
+
+    xi, w   Gauss-Legendre abscissas (ascending) and weights on [-1, 1].
+    B       backward transform, B[j, k] = p_k(xi_j)  (L-space -> X-space).
+    F       forward transform, F[k, j] = (2k+1)/2 w_j p_k(xi_j).
+    D       D[i, j] = int_{-1}^{1} p_i p_j' (Sec. 4.1, eq. legendre_operators),
+            from the closed form 1 - (-1)^(i+j) for i <= j-1, else 0.
+    R, L, RL, LR   products of end values p_i(+-1) p_j(+-1).
+    That    diag(2k+1), so that T = That / h (Sec. 4.1, eq. diagonal).
+    """
+    n: int
+    xi: np.ndarray = field(init=False)
+    w: np.ndarray = field(init=False)
+    B: np.ndarray = field(init=False)
+    F: np.ndarray = field(init=False)
+    D: np.ndarray = field(init=False)
+    R: np.ndarray = field(init=False)
+    L: np.ndarray = field(init=False)
+    RL: np.ndarray = field(init=False)
+    LR: np.ndarray = field(init=False)
+    That: np.ndarray = field(init=False)
+
+    def __post_init__(self):
+        n = self.n
+        if not (1 <= n <= 5):
+            raise ValueError("oracle supports 1 <= n <= 5")
+        self.xi, self.w = leggauss(n)
+        P = legendre_values(n, self.xi)          # P[k, j] = p_k(xi_j)
+        self.B = P.T.copy()
+        k = np.arange(n)
+        self.F = ((2 * k + 1) / 2.0)[:, None] * self.w[None, :] * P
+        D = np.zeros((n, n))
+        for i in range(n):
+            for j in range(n):
+                if i <= j - 1:
+                    D[i, j] = 1.0 - (-1.0) ** (i + j)
+        self.D = D
+        pr = np.ones(n)                          # p_k(+1) = 1
+        pl = (-1.0) ** k                         # p_k(-1) = (-1)^k
+        self.R = np.outer(pr, pr)
+        self.L = np.outer(pl, pl)
+        self.RL = np.outer(pr, pl)
+        self.LR = np.outer(pl, pr)
+        self.That = np.diag(2.0 * k + 1.0)
+
+
+# --------------------------------------------------------------------------
+# 1D grid and derivative matrices (Sec. 3 eq. discrete_derivative,
+# Sec. 4.2 eqs. discrete_der, matrix_xspace)
+# --------------------------------------------------------------------------
+def _shift(N: int, offset: int) -> sp.csr_matrix:
+    """Periodic shift 1^+ (offset=+1: (1^+ f)^m = f^{m+1}) or 1^- (offset=-1)
+    (Sec. 4.2, eq. operator_one; periodic wrap as in the periodic closure of
+    Sec. 3)."""
+    rows = np.arange(N)
+    cols = (rows + offset) % N
+    return sp.csr_matrix((np.ones(N), (rows, cols)), shape=(N, N))
+
+
+class Grid1D:
+    """Equidistant periodic 1D grid on [a, b] with N cells of size h
+    (Sec. 4.1) and n polynomials per cell."""
+
+    def __init__(self, n: int, N: int, a: float, b: float):
+        self.el = ReferenceElement(n)
+        self.n, self.N, self.a, self.b = n, N, float(a), float(b)
+        self.h = (self.b - self.a) / N
+        self._cache = {}
+
+    def nodes(self) -> np.ndarray:
+        """x_{mj} = x_m + (h/2) xi_j with x_m the cell centre (Sec. 4.1)."""
+        centres = self.a + (np.arange(self.N) + 0.5) * self.h
+        return (centres[:, None] + 0.5 * self.h * self.el.xi[None, :]).ravel()
+
+    def weights(self) -> np.ndarray:
+        """Diagonal of 1 (x) W, W = diag(h w_j / 2) (Sec. 4.1, eq. diagonal)."""
+        return np.tile(0.5 * self.h * self.el.w, self.N)
+
+    def lspace_operator(self, theta: float) -> sp.csr_matrix:
+        """L-space matrix Mbar_theta of the weak dG derivative with numerical
+        flux fhat = theta f^+ + (1 - theta) f^- at every face
+        (Sec. 3, eq. discrete_derivative):
+
+          fbar_x^{m i} = T^{ii} [ fhat_{m+1/2} p_i(1) - fhat_{m-1/2} p_i(-1)
+                                  - sum_k fbar^{m k} D_{k i} ].
+
+        Writing the face values with the end values of the neighbouring cells
+        gives  Mbar = 1^+ (x) theta RL + 1 (x) (-theta L + (1-theta) R - D^T)
+                      - 1^- (x) (1-theta) LR.
+        theta = 1/2 is the standard (centred) flux of eq. standard-flux;
+        theta = 1 / 0 are the one-sided fluxes used by the LDG Laplacian."""
+        e = self.el
+        N = self.N
+        self_block = -theta * e.L + (1.0 - theta) * e.R - e.D.T
+        M = (sp.kron(_shift(N, +1), theta * e.RL)
+             + sp.kron(sp.identity(N), self_block)
+             - sp.kron(_shift(N, -1), (1.0 - theta) * e.LR))
+        return M.tocsr()
+
+    def derivative(self, kind: str = "centred") -> sp.csr_matrix:
+        """X-space derivative f_x = (1 (x) V) M f with
+        M = (1 (x) F^T) Mbar (1 (x) F) and the mass-matrix inverse T = That/h
+        folded in (Sec. 4.2, eq. matrix_xspace):
+            f_x = (1 (x) V F^T) Mbar (1 (x) F) f .
+        kind: 'centred' (theta=1/2), 'forward' (theta=1), 'backward' (0)."""
+        if kind in self._cache:
+            return self._cache[kind]
+        theta = {"centred": 0.5, "forward": 1.0, "backward": 0.0}[kind]
+        e = self.el
+        N = self.N
+        V = np.diag(2.0 / (self.h * e.w))
+        left = sp.kron(sp.identity(N), V @ e.F.T)
+        right = sp.kron(sp.identity(N), e.F)
+        op = (left @ self.lspace_operator(theta) @ right).tocsr()
+        self._cache[kind] = op
+        return op
+
+    def laplacian(self) -> sp.csr_matrix:
+        """1D LDG second derivative D_backward D_forward (alternating fluxes,
+        no penalty; the reading of Sec. 6's LDG Laplacian)."""
+        if "lap" not in self._cache:
+            self._cache["lap"] = (self.derivative("backward")
+                                  @ self.derivative("forward")).tocsr()
+        return self._cache["lap"]
+
+
+class Grid2D:
+    """Tensor-product periodic grid [x0,x1] x [y0,y1], Nx x Ny cells, n
+    polynomials per cell and direction (Sec. 4.3, two dimensions)."""
+
+    def __init__(self, n: int, Nx: int, Ny: int, x0=0.0, x1=2 * math.pi,
+                 y0=0.0, y1=2 * math.pi):
+        self.n, self.Nx, self.Ny = n, Nx, Ny
+        self.gx = Grid1D(n, Nx, x0, x1)
+        self.gy = Grid1D(n, Ny, y0, y1)
+        self.hx, self.hy = self.gx.h, self.gy.h
+
+    @property
+    def shape(self):
+        return (self.Ny, self.Nx, self.n, self.n)
+
+    def node_coords(self):
+        """(X, Y) of every node in the canonical layout (Sec. 4.1 nodes)."""
+        xs = self.gx.nodes().reshape(self.Nx, self.n)
+        ys = self.gy.nodes().reshape(self.Ny, self.n)
+        X = np.broadcast_to(xs[None, :, None, :], self.shape).copy()
+        Y = np.broadcast_to(ys[:, None, :, None], self.shape).copy()
+        return X, Y
+
+    def weights(self) -> np.ndarray:
+        """Gauss weights W[cy,cx,j,i] = (hx w_i / 2)(hy w_j / 2)
+        (Sec. 4.1, eq. def_norm, tensor product)."""
+        wx = self.gx.weights().reshape(self.Nx, self.n)
+        wy = self.gy.weights().reshape(self.Ny, self.n)
+        return wy[:, None, :, None] * wx[None, :, None, :]
+
+
+# --------------------------------------------------------------------------
+# Layout conversion
+# --------------------------------------------------------------------------
+def to_image(u: np.ndarray) -> np.ndarray:
+    """[cy, cx, j, i] -> U[cy*n + j, cx*n + i]."""
+    Ny, Nx, n, _ = u.shape
+    return np.ascontiguousarray(u.transpose(0, 2, 1, 3)).reshape(Ny * n, Nx * n)
+
+
+def from_image(U: np.ndarray, n: int) -> np.ndarray:
+    """Inverse of to_image."""
+    Ny, Nx = U.shape[0] // n, U.shape[1] // n
+    return np.ascontiguousarray(U.reshape(Ny, n, Nx, n).transpose(0, 2, 1, 3))
+
+
+def _apply_x(op: sp.csr_matrix, U: np.ndarray) -> np.ndarray:
+    return np.asarray((op @ U.T).T)
+
+
+def _apply_y(op: sp.csr_matrix, U: np.ndarray) -> np.ndarray:
+    return np.asarray(op @ U)
+
+
+# --------------------------------------------------------------------------
+# Derivatives, bracket, Laplacian
+# --------------------------------------------------------------------------
+def dx_form(g: Grid2D, U: np.ndarray, kind="centred") -> np.ndarray:
+    """D_x on an image-layout field: acts along (cx, i) (Sec. 4.3)."""
+    return _apply_x(g.gx.derivative(kind), U)
+
+
+def dy_form(g: Grid2D, U: np.ndarray, kind="centred") -> np.ndarray:
+    """D_y on an image-layout field: acts along (cy, j) (Sec. 4.3)."""
+    return _apply_y(g.gy.derivative(kind), U)
+
+
+def dx(g: Grid2D, u: np.ndarray, kind="centred") -> np.ndarray:
+    return from_image(dx_form(g, to_image(u), kind), g.n)
+
+
+def dy(g: Grid2D, u: np.ndarray, kind="centred") -> np.ndarray:
+    return from_image(dy_form(g, to_image(u), kind), g.n)
+
+
+def bracket_forms(g: Grid2D, f: np.ndarray, h: np.ndarray):
+    """The three dG Jacobians of Sec. 2 eq. J / Sec. 3 with products taken
+    node-wise in X-space (Sec. 4.3, last equation):
+        J++ = Dx(f) Dy(h) - Dy(f) Dx(h)
+        J+x = Dx(f Dy(h)) - Dy(f Dx(h))
+        Jx+ = Dy(Dx(f) h) - Dx(Dy(f) h)
+    Each is evaluated literally (no regrouping).  Returns (Jpp, Jpx, Jxp) in
+    the canonical layout."""
+    F, G = to_image(f), to_image(h)
+    Fx, Fy = dx_form(g, F), dy_form(g, F)
+    Gx, Gy = dx_form(g, G), dy_form(g, G)
+    Jpp = Fx * Gy - Fy * Gx
+    Jpx = dx_form(g, F * Gy) - dy_form(g, F * Gx)
+    Jxp = dy_form(g, Fx * G) - dx_form(g, Fy * G)
+    return tuple(from_image(J, g.n) for J in (Jpp, Jpx, Jxp))
+
+
+def bracket(g: Grid2D, f: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """Conservative dG Arakawa bracket J = (J++ + J+x + Jx+)/3 (Sec. 2 eq. J,
+    Sec. 3 end)."""
+    Jpp, Jpx, Jxp = bracket_forms(g, f, h)
+    return (Jpp + Jpx + Jxp) / 3.0
+
+
+def laplacian(g: Grid2D, u: np.ndarray) -> np.ndarray:
+    """LDG Laplacian with alternating fluxes:
+    Delta_h u = Dx_b(Dx_f u) + Dy_b(Dy_f u) (Sec. 6 first paragraph; the
+    fluxes are the reading stated in the design notes)."""
+    U = to_image(u)
+    Lx = _apply_x(g.gx.derivative("backward"),
+                  _apply_x(g.gx.derivative("forward"), U))
+    Ly = _apply_y(g.gy.derivative("backward"),
+                  _apply_y(g.gy.derivative("forward"), U))
+    return from_image(Lx + Ly, g.n)
+
+
+# --------------------------------------------------------------------------
+# Inner products (Sec. 4.1, eq. def_norm)
+# --------------------------------------------------------------------------
+def inner(g: Grid2D, u: np.ndarray, v: np.ndarray) -> float:
+    """<u, v> = sum W u v with Gauss weights (Sec. 4.1, eq. def_norm)."""
+    return float(np.sum(g.weights() * u * v))
+
+
+def wmean(g: Grid2D, u: np.ndarray) -> float:
+    W = g.weights()
+    return float(np.sum(W * u) / np.sum(W))
+
+
+# --------------------------------------------------------------------------
+# Conjugate gradient for -Delta_h psi = omega (Sec. 6, first paragraph)
+# --------------------------------------------------------------------------
+@dataclass
+class CGResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    rel_residual: float
+
+
+def cg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
+               max_iter=100000) -> CGResult:
+    """Plain conjugate gradient on -Delta_h psi = b in the W inner product
+    (A = -Delta_h is W-self-adjoint), b = omega minus its W-mean (periodic
+    problem: constants span the null space).  The initial guess has its
+    W-mean removed; iteration stops when ||r||_W <= rtol ||b||_W, tested on
+    r_0 and after every update; iters counts operator applications after r_0.
+    The returned psi has zero W-mean.  ||b||_W = 0 returns psi = 0."""
+    W = g.weights()
+
+    def dot(u, v):
+        return float(np.sum(W * u * v))
+
+    b = omega - wmean(g, omega)
+    bnorm = math.sqrt(dot(b, b))
+    if bnorm == 0.0:
+        return CGResult(np.zeros_like(omega), 0, True, 0.0)
+    x = np.zeros_like(omega) if guess is None else guess - wmean(g, guess)
+    r = b + laplacian(g, x)                      # r = b - A x
+    rr = dot(r, r)
+    it = 0
+    converged = math.sqrt(rr) <= rtol * bnorm
+    p = r.copy()
+    while not converged and it < max_iter:
+        q = -laplacian(g, p)                     # q = A p
+        alpha = rr / dot(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        rr_new = dot(r, r)
+        if math.sqrt(rr_new) <= rtol * bnorm:
+            converged = True
+            rr = rr_new
+            break
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    x = x - wmean(g, x)
+    return CGResult(x, it, converged, math.sqrt(rr) / bnorm)
+
+
+# --------------------------------------------------------------------------
+# Right-hand side and SSP-RK3
+# --------------------------------------------------------------------------
+def rhs(g: Grid2D, omega: np.ndarray, psi: np.ndarray, D: float) -> np.ndarray:
+    """R(omega) = -J(psi, omega) + D Delta_h omega for
+    d_t omega + {psi, omega} = D Delta omega (Sec. 1, eq. vorticity)."""
+    return -bracket(g, psi, omega) + D * laplacian(g, omega)
+
+
+class PsiHistory:
+    """The last two Poisson solutions and their times; the CG initial guess
+    is the linear-in-time extrapolation through them (Sec. 6, "extrapolating
+    the solutions of the last two time steps", read for three RK stages per
+    step: the two most recent solves)."""
+
+    def __init__(self):
+        self.items = []          # [(t, psi)] most recent first
+
+    def guess(self, t: float):
+        if not self.items:
+            return None
+        if len(self.items) == 1 or self.items[0][0] == self.items[1][0]:
+            return self.items[0][1].copy()
+        (ta, pa), (tb, pb) = self.items[0], self.items[1]
+        theta = (t - ta) / (ta - tb)
+        return pa + theta * (pa - pb)
+
+    def push(self, t: float, psi: np.ndarray):
+        self.items = [(t, psi.copy())] + self.items[:1]
+
+
+def rk3_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float,
+             hist: PsiHistory, rtol=1e-12, max_iter=100000):
+    """One Shu-Osher SSP-RK3 step of d_t omega = R(omega); stage times t,
+    t+dt, t+dt/2; each stage solves the Poisson problem for its psi.
+    Returns (omega_new, [cg iteration counts])."""
+    iters = []
+
+    def stage_rhs(w, ts):
+        res = cg_poisson(g, w, hist.guess(ts), rtol, max_iter)
+        hist.push(ts, res.x)
+        iters.append(res.iters)
+        return rhs(g, w, res.x, D)
+
+    u1 = omega + dt * stage_rhs(omega, t)
+    u2 = 0.75 * omega + 0.25 * (u1 + dt * stage_rhs(u1, t + dt))
+    u3 = omega / 3.0 + (2.0 / 3.0) * (u2 + dt * stage_rhs(u2, t + 0.5 * dt))
+    return u3, iters
+
+
+# --------------------------------------------------------------------------
+# Invariants (Sec. 2, eq. quantities; integrals by Gauss quadrature)
+# --------------------------------------------------------------------------
+def invariants(g: Grid2D, omega: np.ndarray, psi: np.ndarray):
+    """(V, E, Omega) = (int omega, 1/2 int psi omega, 1/2 int omega^2)
+    with the Gauss inner product (Sec. 2 eq. quantities and the identity
+    E = 1/2 int psi omega; Sec. 4.1 eq. def_norm)."""
+    W = g.weights()
+    return (float(np.sum(W * omega)), 0.5 * float(np.sum(W * psi * omega)),
+            0.5 * float(np.sum(W * omega * omega)))
+
+
+# --------------------------------------------------------------------------
+# Dense brute force (tiny grids)
+# --------------------------------------------------------------------------
+def dense_operators(g: Grid2D):
+    """Dense matrices acting on the flattened image layout:
+    Dx = I (x) Mx, Dy = My (x) I, Lap = I (x) Lx + Ly (x) I (Sec. 4.3,
+    Kronecker products)."""
+    Ix = np.identity(g.Nx * g.n)
+    Iy = np.identity(g.Ny * g.n)
+    Mx = g.gx.derivative("centred").toarray()
+    My = g.gy.derivative("centred").toarray()
+    Lx = g.gx.laplacian().toarray()
+    Ly = g.gy.laplacian().toarray()
+    return np.kron(Iy, Mx), np.kron(My, Ix), np.kron(Iy, Lx) + np.kron(Ly, Ix)
+
+
+def dense_poisson_solve(g: Grid2D, omega: np.ndarray) -> np.ndarray:
+    """Minimum-norm least-squares solution of -Lap psi = omega - mean, then
+    the W-mean removed: the exact zero-mean solution on a tiny grid."""
+    _, _, Lap = dense_operators(g)
+    b = to_image(omega - wmean(g, omega)).ravel()
+    psi, *_ = np.linalg.lstsq(-Lap, b, rcond=None)
+    psi = from_image(psi.reshape(g.Ny * g.n, g.Nx * g.n), g.n)
+    return psi - wmean(g, psi)
+
+
+# --------------------------------------------------------------------------
+# Independent finite-difference formulas for the P = 1 reductions
+# --------------------------------------------------------------------------
+def arakawa_fd_jacobian(psi2d: np.ndarray, zeta2d: np.ndarray, hx: float,
+                        hy: float) -> np.ndarray:
+    """Arakawa's 1966 energy- and enstrophy-conserving 9-point Jacobian on a
+    periodic grid, written with index shifts (array axis 0 = y, axis 1 = x).
+    At P = 1 the dG bracket reduces to it (Sec. 2, the remark after eq. J;
+    Sec. 3, P = 1 and the standard flux)."""
+    def s(a, di, dj):            # value at (x + di, y + dj)
+        return np.roll(np.roll(a, -di, axis=1), -dj, axis=0)
+    p, z = psi2d, zeta2d
+    j1 = ((s(p, 1, 0) - s(p, -1, 0)) * (s(z, 0, 1) - s(z, 0, -1))
+          - (s(p, 0, 1) - s(p, 0, -1)) * (s(z, 1, 0) - s(z, -1, 0)))
+    j2 = (s(p, 1, 0) * (s(z, 1, 1) - s(z, 1, -1))
+          - s(p, -1, 0) * (s(z, -1, 1) - s(z, -1, -1))
+          - s(p, 0, 1) * (s(z, 1, 1) - s(z, -1, 1))
+          + s(p, 0, -1) * (s(z, 1, -1) - s(z, -1, -1)))
+    j3 = (s(z, 0, 1) * (s(p, 1, 1) - s(p, -1, 1))
+          - s(z, 0, -1) * (s(p, 1, -1) - s(p, -1, -1))
+          - s(z, 1, 0) * (s(p, 1, 1) - s(p, 1, -1))
+          + s(z, -1, 0) * (s(p, -1, 1) - s(p, -1, -1)))
+    return (j1 + j2 + j3) / (12.0 * hx * hy)
+
+
+def five_point_laplacian(u2d: np.ndarray, hx: float, hy: float) -> np.ndarray:
+    """Periodic 5-point Laplacian (axis 0 = y, axis 1 = x)."""
+    return ((np.roll(u2d, -1, 1) - 2 * u2d + np.roll(u2d, 1, 1)) / hx ** 2
+            + (np.roll(u2d, -1, 0) - 2 * u2d + np.roll(u2d, 1, 0)) / hy ** 2)

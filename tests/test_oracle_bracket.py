@@ -1,0 +1,91 @@
+"""Pins of the oracle's bracket: Table 2's printed values, the conservation
+identities of Sec. 2 eqs. average1-3, the P = 1 reduction to Arakawa's
+9-point Jacobian and the order of accuracy."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1311_7477_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_table2():
+    rows = {}
+    with open(os.path.join(GOLDEN, "table2_conservation.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, *vals = line.split()
+            rows[name] = [float(v) for v in vals]
+    return rows
+
+
+def test_table2_periodic_rows():
+    printed = _read_table2()
+    g = O.Grid2D(3, 112, 112, 0.0, math.pi, 0.0, math.pi)
+    f, h = I.conservation_pair(3, 112)
+    Jpp, Jpx, Jxp = O.bracket_forms(g, f, h)
+    J = (Jpp + Jpx + Jxp) / 3
+    one = np.ones_like(f)
+    for name, JJ in (("Jpp", Jpp), ("Jpx", Jpx), ("Jxp", Jxp), ("J", J)):
+        got = [O.inner(g, one, JJ), O.inner(g, f, JJ), O.inner(g, h, JJ)]
+        for v, p in zip(got, printed[name]):
+            if abs(p) < 1e-10:          # printed roundoff zero
+                assert abs(v) < 1e-13, (name, v, p)
+            else:                       # two printed significant digits
+                assert round(v, 3) == p, (name, v, p)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_conservation_identities_random_fields(n):
+    # eqs. average1-3 hold to roundoff for arbitrary (discontinuous) fields
+    g = O.Grid2D(n, 7, 5, 0.0, 2.0, 0.0, 3.0)
+    rng = np.random.default_rng(n)
+    f, h = rng.standard_normal((2,) + g.shape)
+    J = O.bracket(g, f, h)
+    W = g.weights()
+    scale = np.sum(W * np.abs(J)) * max(np.abs(f).max(), np.abs(h).max(), 1.0)
+    for v in (np.ones_like(f), f, h):
+        assert abs(O.inner(g, v, J)) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_bracket_algebra(n):
+    g = O.Grid2D(n, 6, 6)
+    rng = np.random.default_rng(7)
+    f, h, k = rng.standard_normal((3,) + g.shape)
+    J = O.bracket(g, f, h)
+    s = np.abs(J).max()
+    np.testing.assert_allclose(O.bracket(g, h, f), -J, atol=1e-13 * s)
+    assert np.abs(O.bracket(g, f, f)).max() == 0.0
+    assert np.abs(O.bracket(g, f, 2.5 * f + 0.75)).max() < 1e-12 * s
+    np.testing.assert_allclose(O.bracket(g, f, 2 * h + 3 * k),
+                               2 * J + 3 * O.bracket(g, f, k), atol=1e-12 * s)
+
+
+def test_p1_is_arakawa_jacobian():
+    # P = 1 reduction: Arakawa 1966 (Sec. 2, remark after eq. J)
+    g = O.Grid2D(1, 16, 12, 0.0, 2 * math.pi, 0.0, 3.0)
+    rng = np.random.default_rng(0)
+    a, b = rng.standard_normal((2,) + g.shape)
+    Jd = O.bracket(g, a, b)[:, :, 0, 0]
+    Jf = O.arakawa_fd_jacobian(a[:, :, 0, 0], b[:, :, 0, 0], g.hx, g.hy)
+    np.testing.assert_allclose(Jd, Jf, atol=1e-14 * np.abs(Jf).max() * 10)
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_bracket_order(n):
+    errs = []
+    for N in (16, 32):
+        g = O.Grid2D(n, N, N)
+        X, Y = g.node_coords()
+        f, h = np.sin(2 * X) * np.cos(Y), np.cos(X) * np.sin(3 * Y)
+        fx, fy = 2 * np.cos(2 * X) * np.cos(Y), -np.sin(2 * X) * np.sin(Y)
+        hx, hy = -np.sin(X) * np.sin(3 * Y), 3 * np.cos(X) * np.cos(3 * Y)
+        e = O.bracket(g, f, h) - (fx * hy - fy * hx)
+        errs.append(math.sqrt(O.inner(g, e, e)))
+    assert math.log2(errs[0] / errs[1]) > n - 0.3
