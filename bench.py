@@ -1,0 +1,198 @@
+"""Benchmark: DG cell-updates/s per RHS (bracket + CG) on one MI355X.
+
+Workload: periodic [0, 2pi]^2, n = 4 Legendre coefficients per direction,
+512 x 512 cells; decaying 2D turbulence from a seeded random-spectrum
+vorticity (peak |k| = 10, zero mean, energy 1/2), D = 1e-4, dt from CFL 0.1,
+CG rtol 1e-12 with the extrapolated initial guess.  A step is one SSP-RK3
+step = three right-hand sides (each: CG setup, CG iterations, fused
+bracket/viscous/stage kernel).  value = Nx * Ny * RHS / second.
+
+Also reported: p50/p99 of the per-RHS device time (HIP events), CG
+iterations per RHS, the roofline figure of the dominant kernel (the CG
+direction-update kernel, timed live with HIP events on the solve stream),
+and the FP64 oracle timed on the host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("DG cell-updates/s per RHS (bracket+CG) at n=4, 512², 1 GPU; "
+          "p50/p99 latency")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_dir_traffic_n4_512.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1311_7477_amd", "csrc", "kernels.hip")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(F_bytes):
+    """HBM bytes per launch of the direction kernel from committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE counters, or None when they are missing or were
+    taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(n, N, omega0, psi0, D, dt, iters_per_rhs):
+    """Time the oracle on the host on a bounded sample of the workload: one
+    bracket + viscous evaluation, one CG setup and a few CG iterations at the
+    full 512 x 512 size; per-RHS time = rhs + setup + k * iteration with k
+    the GPU's mean CG iterations per RHS (a full oracle solve at this size
+    takes tens of minutes)."""
+    import oracle as O
+    g = O.Grid2D(n, N, N)
+    t0 = time.perf_counter()
+    O.rhs(g, omega0, psi0, D)
+    t_rhs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.cg_poisson(g, omega0, psi0, rtol=1e-12, max_iter=0)
+    t_setup = time.perf_counter() - t0
+    k = 8
+    t0 = time.perf_counter()
+    O.cg_poisson(g, omega0, psi0, rtol=1e-30, max_iter=k)
+    t_iter = max(time.perf_counter() - t0 - t_setup, 1e-9) / k
+    t_per_rhs = t_rhs + t_setup + iters_per_rhs * t_iter
+    return {
+        "value": N * N / t_per_rhs,
+        "unit": "cell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"numpy/scipy FP64 oracle at n={n}, {N}x{N}: 1 bracket+viscous "
+                   f"({t_rhs:.2f} s), 1 CG setup ({t_setup:.2f} s), {k} CG iterations "
+                   f"({t_iter * 1e3:.0f} ms each); per RHS = rhs + setup + "
+                   f"{iters_per_rhs:.0f} x iteration (GPU mean iterations/RHS)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=4)
+    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--D", type=float, default=1e-4)
+    ap.add_argument("--rtol", type=float, default=1e-12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the single-instance RHS is not "
+              "sharded across GPUs in this build (see the design notes for the "
+              "domain-decomposition plan).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1311_7477_amd import dg, inputs
+
+    n, N = args.n, args.N
+    torch.cuda.set_device(0)
+    omega0, umax = inputs.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
+    dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
+    grid = dg.Grid(n, N, N)
+    ws = dg.Workspace(grid)
+    st = dg.State(grid)
+    w = torch.from_numpy(omega0).cuda()
+    opts = dg.cg_opts(rtol=args.rtol)
+    print(f"[bench] n={n} N={N} D={args.D} dt={dt:.3e} warmup={args.warmup} "
+          f"steps={args.steps}", file=sys.stderr, flush=True)
+
+    for k in range(args.warmup):
+        r = dg.rk_step(grid, w, st, ws, dt, args.D, opts, record_times=True)
+        print(f"[bench] warmup step {k}: iters {r.cg_iters} ms {r.stage_ms}",
+              file=sys.stderr, flush=True)
+
+    ws.read_profile()           # reset
+    ws.profile(True)
+    stage_ms, iters = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = dg.rk_step(grid, w, st, ws, dt, args.D, opts, record_times=True)
+        stage_ms.extend(r.stage_ms)
+        iters.extend(r.cg_iters)
+        print(f"[bench] step {k}: iters {r.cg_iters} ms "
+              f"{[round(x, 2) for x in r.stage_ms]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    ws.profile(False)
+    ms_dir, n_dir, ms_res, n_res = ws.read_profile()
+
+    rhs = 3 * args.steps
+    value = N * N * rhs / T
+    F = 8 * N * N * n * n
+    # algorithmic bytes per direction-update launch: read r, p_old, x;
+    # write x, p  (5 fields)
+    alg_bytes = 5 * F
+    achieved = alg_bytes / (ms_dir * 1e-3) / 1e9
+    traffic = measured_traffic(F)
+    srt = sorted(stage_ms)
+
+    def pct(q):
+        return srt[min(len(srt) - 1, int(math.ceil(q * len(srt))) - 1)]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"decaying 2D turbulence, periodic [0,2pi]^2, n={n}, "
+                         f"{N}x{N} cells, random-spectrum omega0 (k0=10, seed 1), "
+                         f"D={args.D}, dt={dt:.4e} (CFL 0.1), SSP-RK3, CG rtol "
+                         f"{args.rtol}, extrapolated guess; step = 1 RK3 step = 3 RHS"),
+            "n": n, "Nx": N, "Ny": N, "rhs_per_step": 3,
+        },
+        "latency_ms_per_rhs": {"p50": pct(0.50), "p99": pct(0.99),
+                               "mean": statistics.mean(stage_ms)},
+        "cg_iters_per_rhs": {"mean": statistics.mean(iters), "max": max(iters)},
+        "roofline": {
+            "kernel": "k_cg_dir (CG direction update: x += a p, p = r + b p, <p, A p>)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "avg_launch_ms": ms_dir,
+            "samples": n_dir,
+            "residual_kernel_avg_ms": ms_res,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        psi0 = st.psi().cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(n, N, w.cpu().numpy(), psi0, args.D, dt,
+                                           statistics.mean(iters))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * dgark.h -- C ABI of the MI355X (gfx950) library for one right-hand-side
+ * evaluation of the conservative discontinuous-Galerkin Arakawa scheme
+ * (Einkemmer & Wiesenberger, "A conservative discontinuous Galerkin scheme
+ * for the 2D incompressible Navier-Stokes equations"):
+ *
+ *     d_t omega + {psi, omega} = D Lap omega,    -Lap psi = omega      (Sec. 1)
+ *
+ * on a periodic rectangle, with the dG Arakawa bracket J = (J++ + J+x + Jx+)/3
+ * (Sec. 2 eq. J, Sec. 3), the LDG Laplacian and a conjugate-gradient Poisson
+ * solve (Sec. 6), advanced by SSP-RK3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status      Every function returning int returns DG_OK (0) or a negative
+ *             DG_E_* code; dg_last_error() gives a thread-local message for
+ *             the last failure on the calling thread.  Nothing throws.
+ * Fields      Device pointers to FP64 arrays of dg_field_elems(grid) doubles,
+ *             8-byte aligned, on the current HIP device, in the cell-major
+ *             layout [cy][cx][j][i]: cell (cx, cy), y-node j, x-node i.  Node
+ *             (i, j) of cell (cx, cy) sits at
+ *                x = x0 + (cx + 1/2 + xi_i / 2) hx,  y = y0 + (cy + 1/2 + xi_j / 2) hy
+ *             with xi the ascending Gauss-Legendre abscissas; the stored values
+ *             are nodal values ("X-space", Sec. 4.3 last paragraph).
+ * Ownership   The caller owns every field buffer; the library never frees
+ *             caller memory.  A dg_grid is host-only and immutable (shareable
+ *             across threads and streams).  A dg_workspace and a dg_state own
+ *             device memory and serve one stream at a time.
+ * Streams     `stream` is a hipStream_t passed as void* (NULL = default
+ *             stream).  Calls are asynchronous on that stream unless stated
+ *             otherwise; calls that return host scalars synchronise it.
+ * Aliasing    An output that aliases an input it must not alias gives
+ *             DG_E_ALIAS before any work is queued.
+ */
+#ifndef DGARK_H
+#define DGARK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DG_OK              0
+#define DG_E_INVAL        -1   /* invalid argument (null pointer, bad size, n out of range) */
+#define DG_E_ALIAS        -2   /* an output aliases an input */
+#define DG_E_NOMEM        -3   /* device or pinned-host allocation failed */
+#define DG_E_HIP          -4   /* a HIP runtime call failed; message holds hipError text */
+#define DG_E_NOCONV       -5   /* CG hit max_iter; outputs hold the last iterate, stats filled */
+#define DG_E_UNSUPPORTED  -6   /* valid request this build does not implement */
+#define DG_E_WORKSPACE    -7   /* workspace made for another grid or mode */
+
+/* boundary conditions */
+#define DG_BC_PERIODIC   0
+#define DG_BC_DIRICHLET  1      /* returns DG_E_UNSUPPORTED */
+
+/* CG precision modes */
+#define DG_PREC_FP64   0
+#define DG_PREC_MIXED  1        /* FP32 inner CG, FP64 residual refinement */
+
+/* single Jacobian forms for dg_bracket_form (Sec. 2 eq. J) */
+#define DG_FORM_ARAKAWA 0       /* (J++ + J+x + Jx+)/3 */
+#define DG_FORM_PP      1       /* J++ = Dx f Dy g - Dy f Dx g   */
+#define DG_FORM_PX      2       /* J+x = Dx(f Dy g) - Dy(f Dx g) */
+#define DG_FORM_XP      3       /* Jx+ = Dy(Dx f g) - Dx(Dy f g) */
+
+typedef struct dg_grid dg_grid;
+typedef struct dg_workspace dg_workspace;
+typedef struct dg_state dg_state;
+
+typedef struct {
+    double rtol;        /* stop when ||r||_W <= rtol ||b||_W (FP64 mode), or
+                           the outer FP64 residual meets it (mixed mode) */
+    int    max_iter;    /* operator applications allowed (inner ones in mixed mode) */
+    int    precision;   /* DG_PREC_FP64 or DG_PREC_MIXED */
+    double inner_rtol;  /* mixed mode: relative reduction of each FP32 inner solve */
+    int    check_every; /* iterations between host polls of the device
+                           convergence flag (0 = library default) */
+} dg_cg_opts;
+
+typedef struct {
+    int    iters;         /* operator applications after r_0 (all inner ones in mixed mode) */
+    int    outer_iters;   /* mixed mode: FP64 refinement steps; FP64 mode: 0 */
+    double rel_residual;  /* final ||r||_W / ||b||_W (FP64 residual) */
+    int    converged;     /* 1 if the tolerance was met */
+} dg_cg_stats;
+
+typedef struct {
+    double     dt;          /* time step */
+    double     D;           /* viscosity */
+    dg_cg_opts cg;          /* options of the three Poisson solves */
+    int        record_times;/* 1: time each stage with HIP events (stats.stage_ms) */
+} dg_step_opts;
+
+typedef struct {
+    int   cg_iters[3];      /* CG operator applications of each stage's solve */
+    float stage_ms[3];      /* device time of each stage (solve + RHS), if recorded */
+    int   converged;        /* 1 if all three solves converged */
+} dg_step_stats;
+
+/* Text of the last error on this thread ("" if none). */
+const char* dg_last_error(void);
+
+/* ---------------------------------------------------------------- grid --- */
+/* Build the per-grid operator tables on the host: Gauss-Legendre nodes and
+ * weights (Sec. 4.1), the X-space centred derivative blocks (Sec. 4.2 eqs.
+ * discrete_der, matrix_xspace) and the LDG Laplacian blocks (Sec. 6).
+ * n in [1, 5] polynomials per cell and direction, nx, ny >= 1 cells, finite
+ * x0 < x1 and y0 < y1, bc_x = bc_y = DG_BC_PERIODIC.  Touches no GPU.
+ * Errors: DG_E_INVAL, DG_E_UNSUPPORTED (Dirichlet), DG_E_NOMEM. */
+int  dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
+                    double y1, int bc_x, int bc_y, dg_grid** out);
+void dg_grid_destroy(dg_grid* grid);                 /* NULL-safe */
+/* Number of doubles in one field: ny * nx * n * n. */
+size_t dg_field_elems(const dg_grid* grid);
+/* Copy the grid's host tables into `out` (capacity `len` doubles), in the
+ * order: xi[n], w[n], C0[n*n], cR[n], sR[n], cL[n], sL[n] (centred, h = 1),
+ * L0[n*n], eR[n], lR[n], eL[n], lL[n] (LDG second derivative, h = 1).
+ * A 1D centred derivative is (1/h)[C0 u_m + cR (sR.u_{m+1}) + cL (sL.u_{m-1})],
+ * the 1D LDG part (1/h^2)[L0 u_m + eR (lR.u_{m+1}) + eL (lL.u_{m-1})], all
+ * n x n blocks row-major.  Returns the number of doubles written, or a
+ * negative status (DG_E_INVAL if len is too small). */
+int  dg_grid_tables(const dg_grid* grid, double* out, int len);
+
+/* ----------------------------------------------------------- workspace --- */
+/* Device bytes a workspace for (grid, mode) holds: CG vectors r and p, the
+ * two RK stage fields, reduction partials and scalars, plus FP32 copies in
+ * DG_PREC_MIXED mode.  This is the figure that admission control budgets. */
+int  dg_workspace_bytes(const dg_grid* grid, int mode, size_t* bytes);
+/* Allocate a workspace on the current device (hipMalloc + pinned host
+ * scalars).  Errors: DG_E_INVAL, DG_E_NOMEM, DG_E_HIP. */
+int  dg_workspace_create(const dg_grid* grid, int mode, dg_workspace** out);
+void dg_workspace_destroy(dg_workspace* ws);         /* NULL-safe */
+
+/* Measurement support.  While enabled, every CG polling chunk of a solve on
+ * this workspace brackets one direction-update kernel launch and one
+ * residual-update kernel launch with HIP events on the solve's stream (only
+ * iterations the device really executed are counted).  dg_profile_read
+ * stores {sum_ms_direction, launches, sum_ms_residual, launches} accumulated
+ * since the previous read and resets them.  Host-only bookkeeping. */
+int  dg_profile_enable(dg_workspace* ws, int on);
+int  dg_profile_read(dg_workspace* ws, double* out4);
+
+/* ------------------------------------------------------------ operators --- */
+/* out = J(f, g), the conservative dG Arakawa bracket
+ * (J++ + J+x + Jx+)/3 with products taken node-wise in X-space
+ * (Sec. 2 eq. J, Sec. 3 last paragraphs, Sec. 4.3 last equation).
+ * out must not alias f or g (DG_E_ALIAS).  Asynchronous. */
+int  dg_poisson_bracket(const dg_grid* grid, const double* f, const double* g,
+                        double* out, void* stream);
+/* out = one of the single forms J++, J+x, Jx+ or the Arakawa average
+ * (form = DG_FORM_*), Sec. 2 eq. J.  Same rules as dg_poisson_bracket. */
+int  dg_bracket_form(const dg_grid* grid, const double* f, const double* g,
+                     double* out, int form, void* stream);
+/* out = Lap_h f, the LDG Laplacian with alternating fluxes,
+ * Dx_backward Dx_forward + Dy_backward Dy_forward (Sec. 6; the flux choice is
+ * the reading stated with the design).  -W Lap_h is symmetric positive
+ * semi-definite with the constants as null space.  out != f.  Asynchronous. */
+int  dg_laplace_apply(const dg_grid* grid, const double* f, double* out,
+                      void* stream);
+
+/* ----------------------------------------------------------------- CG --- */
+/* Solve -Lap_h psi = omega - mean_W(omega) by conjugate gradients in the
+ * Gauss inner product (Sec. 6: symmetric system, CG; Sec. 4.1 eq. def_norm).
+ * On entry psi holds the initial guess (its W-mean is removed); on exit the
+ * zero-mean solution.  ||omega - mean|| = 0 gives psi = 0.  ws must be made
+ * for this grid and, for DG_PREC_MIXED, in mixed mode.  Synchronises the
+ * stream (convergence polling).  Returns DG_E_NOCONV when max_iter was hit
+ * (psi holds the last iterate).  psi must not alias omega. */
+int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
+                         const dg_cg_opts* opts, dg_cg_stats* stats,
+                         dg_workspace* ws, void* stream);
+
+/* ------------------------------------------------------------ stepping --- */
+/* History of Poisson solutions used for the CG initial guess: the
+ * linear-in-time extrapolation of the two most recent solves (Sec. 6,
+ * initial guess from the last two solutions).  Owns three device fields. */
+int  dg_state_create(const dg_grid* grid, double t0, dg_state** out);
+void dg_state_destroy(dg_state* st);                 /* NULL-safe */
+/* Device pointer to the most recent psi (NULL before the first solve). */
+const double* dg_state_psi(const dg_state* st);
+/* Copy the most recent psi into out (device, dg_field_elems doubles);
+ * asynchronous.  DG_E_INVAL before the first solve. */
+int  dg_state_copy_psi(const dg_state* st, double* out, void* stream);
+double dg_state_time(const dg_state* st);
+/* One SSP-RK3 (Shu-Osher) step of d_t omega = -J(psi, omega) + D Lap_h omega
+ * with stage times t, t+dt, t+dt/2; each stage solves -Lap_h psi = omega_s
+ * by CG (opts->cg) from the extrapolated guess, then one fused kernel forms
+ * the bracket, the viscous term and the stage combination.  omega is updated
+ * in place; state->t advances by dt.  Synchronises the stream.  Returns
+ * DG_E_NOCONV if a solve hit max_iter (the step is still completed). */
+int  dg_rk_step(const dg_grid* grid, double* omega, dg_state* state,
+                const dg_step_opts* opts, dg_step_stats* stats,
+                dg_workspace* ws, void* stream);
+
+/* --------------------------------------------------------- invariants --- */
+/* out[0..2] = (V, E, Omega) = (int omega, 1/2 int psi omega, 1/2 int omega^2)
+ * (Sec. 2 eq. quantities, E by the Green identity) with Gauss quadrature
+ * (Sec. 4.1 eq. def_norm), summed in a fixed order (deterministic).
+ * dg_invariants writes host memory and synchronises the stream;
+ * dg_invariants_dev writes 3 doubles to device memory asynchronously. */
+int  dg_invariants(const dg_grid* grid, const double* omega, const double* psi,
+                   double* out_host3, dg_workspace* ws, void* stream);
+int  dg_invariants_dev(const dg_grid* grid, const double* omega,
+                       const double* psi, double* out_dev3, dg_workspace* ws,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGARK_H */

@@ -1,0 +1,675 @@
+// C ABI of libdgark: argument validation, device memory of workspaces and
+// states, the host side of the CG and SSP-RK3 drivers.  Every step of the
+// computation runs in the kernels of kernels.hip; this file only queues
+// them and polls the device convergence flag.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/dgark.h"
+#include "dg_internal.h"
+#include "dg_launch.h"
+
+using namespace dgk;
+
+struct dg_grid {
+    int n, nx, ny;
+    double x0, x1, y0, y1, hx, hy, area;
+    HostTables t;
+    OpConst<double> k64;
+    OpConst<float> k32;
+    Geom geom;
+    size_t elems;
+};
+
+struct dg_workspace {
+    int n, nx, ny, mode, device;
+    size_t elems;
+    double *r, *p0, *p1, *s1, *s2;
+    float *r32, *e32, *q0, *q1;
+    DevScratch d;
+    CgScalars* inner;          // device scalars of the mixed inner solve
+    CgScalars* host;           // pinned, 4 slots (2 poll slots x {outer, inner})
+    hipEvent_t ev[2];
+    hipEvent_t tev[4];
+    size_t bytes;
+    // live kernel timing (measurement support)
+    int prof_on;
+    hipEvent_t pev[2][4];
+    int pev_iter[2];           // iteration index sampled in that poll slot (-1: none)
+    double prof_ms[2];         // summed ms of sampled direction / residual launches
+    double prof_n[2];
+};
+
+struct dg_state {
+    int n, nx, ny;
+    size_t elems;
+    double* buf[3];
+    int ia, ib;                // indices of the newest / previous solution (-1 none)
+    double ta, tb, t;
+    int count;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(DG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                 \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+template <class T>
+void fill_const(const dg_grid& g, OpConst<T>& k) {
+    std::memset(&k, 0, sizeof k);
+    const int n = g.n;
+    for (int i = 0; i < n * n; ++i) {
+        k.C0[i] = (T)g.t.C0[i];
+        k.L0[i] = (T)g.t.L0[i];
+    }
+    for (int i = 0; i < n; ++i) {
+        k.cR[i] = (T)g.t.cR[i]; k.sR[i] = (T)g.t.sR[i];
+        k.cL[i] = (T)g.t.cL[i]; k.sL[i] = (T)g.t.sL[i];
+        k.eR[i] = (T)g.t.eR[i]; k.lR[i] = (T)g.t.lR[i];
+        k.eL[i] = (T)g.t.eL[i]; k.lL[i] = (T)g.t.lL[i];
+        k.w[i] = (T)g.t.w[i];
+    }
+    k.ihx = (T)(1.0 / g.hx);
+    k.ihy = (T)(1.0 / g.hy);
+    k.ihx2 = (T)(1.0 / (g.hx * g.hx));
+    k.ihy2 = (T)(1.0 / (g.hy * g.hy));
+    k.wq = 0.25 * g.hx * g.hy;
+}
+
+bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+int check_ws(const dg_grid* g, const dg_workspace* ws) {
+    if (!ws) return fail(DG_E_INVAL, "workspace is NULL");
+    if (ws->n != g->n || ws->nx != g->nx || ws->ny != g->ny)
+        return fail(DG_E_WORKSPACE, "workspace was made for another grid");
+    return DG_OK;
+}
+
+size_t mixed_extra(size_t elems) { return 4 * elems * sizeof(float); }
+
+size_t ws_bytes(const dg_grid* g, int mode) {
+    const size_t F = g->elems * sizeof(double);
+    int blocks = stencil_blocks(g->geom);
+    if (blocks < pointwise_block_cap()) blocks = pointwise_block_cap();
+    size_t b = 5 * F;                                   // r, p0, p1, s1, s2
+    b += (size_t)blocks * 4 * sizeof(double);           // partials
+    b += 2 * sizeof(CgScalars) + kCntCount * sizeof(unsigned) + 4 * sizeof(double);
+    if (mode == DG_PREC_MIXED) b += mixed_extra(g->elems);
+    return b;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// Copy the device scalars (outer and, if given, inner) to pinned host memory
+// and wait for them.
+int read_scalars(dg_workspace* ws, const CgScalars* dev, CgScalars* host,
+                 hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(host, dev, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)ws;
+    return DG_OK;
+}
+
+// Queue CG iterations in chunks and poll the device `done` flag one chunk
+// behind, so the device never waits for the host.  Iterations queued after
+// convergence exit at their first instruction.
+// Fold the sampled kernel durations of a completed poll slot into the
+// workspace totals; a sample counts only if the device really executed that
+// iteration (iterations queued after convergence exit immediately).
+int harvest_profile(dg_workspace* ws, int slot, int device_iter) {
+    if (ws->pev_iter[slot] < 0) return DG_OK;
+    if (device_iter > ws->pev_iter[slot]) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, ws->pev[slot][0], ws->pev[slot][1]));
+        HIP_TRY(hipEventElapsedTime(&b, ws->pev[slot][2], ws->pev[slot][3]));
+        ws->prof_ms[0] += a;
+        ws->prof_ms[1] += b;
+        ws->prof_n[0] += 1;
+        ws->prof_n[1] += 1;
+    }
+    ws->pev_iter[slot] = -1;
+    return DG_OK;
+}
+
+template <class T>
+int cg_loop(const Geom& geom, const OpConst<T>& k, T* x, T* r, T* p0, T* p1,
+            CgScalars* sc, int max_iter, int check_every, dg_workspace* ws,
+            hipStream_t s, CgScalars* final_host) {
+    const int chunk = check_every > 0 ? check_every : 32;
+    int issued = 0, round = 0, prev = -1;
+    ws->pev_iter[0] = ws->pev_iter[1] = -1;
+    for (;;) {
+        int m = max_iter - issued;
+        if (m > chunk) m = chunk;
+        const int slot = round & 1;
+        for (int i = 0; i < m; ++i) {
+            const int par = (issued + i) & 1;
+            hipError_t e;
+            if (ws->prof_on && i == 0) {
+                HIP_TRY(hipEventRecord(ws->pev[slot][0], s));
+                e = launch_cg_dir<T>(geom, k, x, r, p0, p1, par, sc, ws->d, s);
+                if (e != hipSuccess) return hip_fail(e, "cg direction launch");
+                HIP_TRY(hipEventRecord(ws->pev[slot][1], s));
+                HIP_TRY(hipEventRecord(ws->pev[slot][2], s));
+                e = launch_cg_res<T>(geom, k, r, p0, p1, par, sc, ws->d, s);
+                if (e != hipSuccess) return hip_fail(e, "cg residual launch");
+                HIP_TRY(hipEventRecord(ws->pev[slot][3], s));
+                ws->pev_iter[slot] = issued;
+            } else {
+                e = launch_cg_iter<T>(geom, k, x, r, p0, p1, par, sc, ws->d, s);
+                if (e != hipSuccess) return hip_fail(e, "cg iteration launch");
+            }
+        }
+        issued += m;
+        HIP_TRY(hipMemcpyAsync(&ws->host[slot], sc, sizeof(CgScalars),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(ws->ev[slot], s));
+        if (issued >= max_iter) {
+            HIP_TRY(hipEventSynchronize(ws->ev[slot]));
+            *final_host = ws->host[slot];
+            if (prev >= 0) {
+                int rc = harvest_profile(ws, prev, final_host->iter);
+                if (rc != DG_OK) return rc;
+            }
+            return harvest_profile(ws, slot, final_host->iter);
+        }
+        if (prev >= 0) {
+            HIP_TRY(hipEventSynchronize(ws->ev[prev]));
+            int rc = harvest_profile(ws, prev, ws->host[prev].iter);
+            if (rc != DG_OK) return rc;
+            if (ws->host[prev].done) {
+                *final_host = ws->host[prev];
+                // the newer slot's sample ran after convergence: drop it
+                ws->pev_iter[slot] = -1;
+                return DG_OK;
+            }
+        }
+        prev = slot;
+        ++round;
+    }
+}
+
+// FP64 CG from the guess ca*pa + cb*pb into x (x must not alias pa or pb).
+int cg_fp64(const dg_grid* g, const double* omega, double* x, const double* pa,
+            double ca, const double* pb, double cb, const dg_cg_opts& o,
+            dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+    const double tol2 = o.rtol * o.rtol;
+    hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
+                                  tol2, o.max_iter, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg mean launch");
+    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, x, ws->r, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg init launch");
+    CgScalars fin;
+    int rc = cg_loop<double>(g->geom, g->k64, x, ws->r, ws->p0, ws->p1, ws->d.sc,
+                             o.max_iter, o.check_every, ws, s, &fin);
+    if (rc != DG_OK) return rc;
+    e = launch_cg_finish(g->geom, g->k64, x, ws->p0, ws->p1, g->area, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
+    rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+    if (rc != DG_OK) return rc;
+    const CgScalars& h = ws->host[2];
+    if (st) {
+        st->iters = h.iter;
+        st->outer_iters = 0;
+        st->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        st->converged = h.converged;
+    }
+    if (!h.converged)
+        return fail(DG_E_NOCONV, "CG stopped after %d iterations, relative residual %.3e%s",
+                    h.iter, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0,
+                    h.breakdown ? " (breakdown or non-finite data)" : "");
+    return DG_OK;
+}
+
+// Mixed precision: FP64 residual r = b - A psi, FP32 CG on A e = r, psi += e,
+// repeated until ||r||_W <= rtol ||b||_W.
+int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
+             double ca, const double* pb, double cb, const dg_cg_opts& o,
+             dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+    const double tol2 = o.rtol * o.rtol;
+    const double itol = o.inner_rtol > 0 ? o.inner_rtol : 1e-5;
+    hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
+                                  tol2, o.max_iter, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg mean launch");
+    // x = guess - mean(guess): reuse the finish kernel's mean subtraction
+    e = launch_guess((long)g->elems, x, pa, pb, ca, cb, s);
+    if (e != hipSuccess) return hip_fail(e, "guess launch");
+    e = launch_cg_finish(g->geom, g->k64, x, ws->p0, ws->p1, g->area, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "mean launch");
+    int total_inner = 0, outer = 0;
+    CgScalars oh, ih;
+    for (;;) {
+        e = launch_mixed_residual(g->geom, g->k64, omega, x, ws->r32, ws->e32,
+                                  itol * itol, o.max_iter, ws->d.sc, ws->inner,
+                                  ws->d, s);
+        if (e != hipSuccess) return hip_fail(e, "mixed residual launch");
+        int rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+        if (rc != DG_OK) return rc;
+        oh = ws->host[2];
+        if (oh.converged || total_inner >= o.max_iter || outer >= 100) break;
+        rc = cg_loop<float>(g->geom, g->k32, ws->e32, ws->r32, ws->q0, ws->q1,
+                            ws->inner, o.max_iter - total_inner, o.check_every, ws,
+                            s, &ih);
+        if (rc != DG_OK) return rc;
+        total_inner += ih.iter;
+        e = launch_mixed_update(g->geom, x, ws->e32, ws->q0, ws->q1, ws->inner, s);
+        if (e != hipSuccess) return hip_fail(e, "mixed update launch");
+        ++outer;
+        if (ih.iter == 0) {  // inner solve could not move: stagnation
+            e = launch_mixed_residual(g->geom, g->k64, omega, x, ws->r32, ws->e32,
+                                      itol * itol, 0, ws->d.sc, ws->inner, ws->d, s);
+            if (e != hipSuccess) return hip_fail(e, "mixed residual launch");
+            rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+            if (rc != DG_OK) return rc;
+            oh = ws->host[2];
+            break;
+        }
+    }
+    // final W-mean removal of psi (pending = 0 in the outer scalars)
+    e = launch_cg_finish(g->geom, g->k64, x, ws->p0, ws->p1, g->area, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
+    HIP_TRY(hipStreamSynchronize(s));
+    if (st) {
+        st->iters = total_inner;
+        st->outer_iters = outer;
+        st->rel_residual = oh.bb > 0 ? std::sqrt(oh.rr / oh.bb) : 0.0;
+        st->converged = oh.converged;
+    }
+    if (!oh.converged)
+        return fail(DG_E_NOCONV, "mixed CG stopped: %d inner, %d outer iterations, "
+                    "relative residual %.3e", total_inner, outer,
+                    oh.bb > 0 ? std::sqrt(oh.rr / oh.bb) : 0.0);
+    return DG_OK;
+}
+
+int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* pa,
+                double ca, const double* pb, double cb, const dg_cg_opts* opts,
+                dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+    dg_cg_opts o;
+    if (opts) o = *opts;
+    else { o.rtol = 1e-12; o.max_iter = 100000; o.precision = DG_PREC_FP64;
+           o.inner_rtol = 1e-5; o.check_every = 0; }
+    if (!(o.rtol > 0) || o.max_iter < 0)
+        return fail(DG_E_INVAL, "rtol must be > 0 and max_iter >= 0");
+    if (o.precision == DG_PREC_MIXED) {
+        if (ws->mode != DG_PREC_MIXED)
+            return fail(DG_E_WORKSPACE, "mixed precision needs a DG_PREC_MIXED workspace");
+        return cg_mixed(g, omega, x, pa, ca, pb, cb, o, st, ws, s);
+    }
+    if (o.precision != DG_PREC_FP64) return fail(DG_E_INVAL, "unknown precision %d", o.precision);
+    return cg_fp64(g, omega, x, pa, ca, pb, cb, o, st, ws, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+int dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
+                   double y1, int bc_x, int bc_y, dg_grid** out) {
+    if (!out) return fail(DG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > kMaxN) return fail(DG_E_INVAL, "n = %d outside [1, 5]", n);
+    if (nx < 1 || ny < 1) return fail(DG_E_INVAL, "nx, ny must be >= 1");
+    if ((long)nx * ny > (1L << 28)) return fail(DG_E_INVAL, "grid too large");
+    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(y0) ||
+        !std::isfinite(y1) || !(x1 > x0) || !(y1 > y0))
+        return fail(DG_E_INVAL, "domain bounds must be finite with x0 < x1, y0 < y1");
+    if (bc_x == DG_BC_DIRICHLET || bc_y == DG_BC_DIRICHLET)
+        return fail(DG_E_UNSUPPORTED, "Dirichlet boundaries are not implemented");
+    if (bc_x != DG_BC_PERIODIC || bc_y != DG_BC_PERIODIC)
+        return fail(DG_E_INVAL, "unknown boundary condition");
+    dg_grid* g = new (std::nothrow) dg_grid;
+    if (!g) return fail(DG_E_NOMEM, "host allocation failed");
+    g->n = n; g->nx = nx; g->ny = ny;
+    g->x0 = x0; g->x1 = x1; g->y0 = y0; g->y1 = y1;
+    g->hx = (x1 - x0) / nx;
+    g->hy = (y1 - y0) / ny;
+    g->area = (x1 - x0) * (y1 - y0);
+    if (!build_tables(n, &g->t)) { delete g; return fail(DG_E_INVAL, "table build failed"); }
+    fill_const(*g, g->k64);
+    fill_const(*g, g->k32);
+    g->geom = Geom{n, nx, ny};
+    g->elems = (size_t)nx * ny * n * n;
+    *out = g;
+    return DG_OK;
+}
+
+void dg_grid_destroy(dg_grid* g) { delete g; }
+
+size_t dg_field_elems(const dg_grid* g) { return g ? g->elems : 0; }
+
+int dg_grid_tables(const dg_grid* g, double* out, int len) {
+    if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
+    const int n = g->n;
+    const int need = 2 * n + 2 * (n * n + 4 * n);
+    if (len < need) return fail(DG_E_INVAL, "need %d doubles", need);
+    int o = 0;
+    auto put = [&](const double* a, int m) { for (int i = 0; i < m; ++i) out[o++] = a[i]; };
+    put(g->t.xi, n); put(g->t.w, n);
+    put(g->t.C0, n * n); put(g->t.cR, n); put(g->t.sR, n); put(g->t.cL, n); put(g->t.sL, n);
+    put(g->t.L0, n * n); put(g->t.eR, n); put(g->t.lR, n); put(g->t.eL, n); put(g->t.lL, n);
+    return o;
+}
+
+int dg_workspace_bytes(const dg_grid* g, int mode, size_t* bytes) {
+    if (!g || !bytes) return fail(DG_E_INVAL, "NULL argument");
+    if (mode != DG_PREC_FP64 && mode != DG_PREC_MIXED) return fail(DG_E_INVAL, "bad mode");
+    *bytes = ws_bytes(g, mode);
+    return DG_OK;
+}
+
+void dg_workspace_destroy(dg_workspace* ws) {
+    if (!ws) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ws->device);
+    void* bufs[] = {ws->r, ws->p0, ws->p1, ws->s1, ws->s2, ws->r32, ws->e32,
+                    ws->q0, ws->q1, ws->d.sc, ws->d.counters, ws->d.partials,
+                    ws->d.out3, ws->inner};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (ws->host) (void)hipHostFree(ws->host);
+    for (auto& e : ws->ev) if (e) (void)hipEventDestroy(e);
+    for (auto& e : ws->tev) if (e) (void)hipEventDestroy(e);
+    for (auto& row : ws->pev)
+        for (auto& e : row) if (e) (void)hipEventDestroy(e);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete ws;
+}
+
+int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
+    if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (mode != DG_PREC_FP64 && mode != DG_PREC_MIXED) return fail(DG_E_INVAL, "bad mode");
+    dg_workspace* ws = new (std::nothrow) dg_workspace;
+    if (!ws) return fail(DG_E_NOMEM, "host allocation failed");
+    std::memset(ws, 0, sizeof *ws);
+    ws->n = g->n; ws->nx = g->nx; ws->ny = g->ny; ws->mode = mode;
+    ws->elems = g->elems;
+    hipError_t e = hipGetDevice(&ws->device);
+    if (e != hipSuccess) { delete ws; return hip_fail(e, "hipGetDevice"); }
+    const size_t F = g->elems * sizeof(double);
+    int blocks = stencil_blocks(g->geom);
+    if (blocks < pointwise_block_cap()) blocks = pointwise_block_cap();
+    ws->d.max_blocks = blocks;
+    auto alloc = [&](void** p, size_t b) -> bool {
+        return hipMalloc(p, b) == hipSuccess;
+    };
+    bool ok = alloc((void**)&ws->r, F) && alloc((void**)&ws->p0, F) &&
+              alloc((void**)&ws->p1, F) && alloc((void**)&ws->s1, F) &&
+              alloc((void**)&ws->s2, F) &&
+              alloc((void**)&ws->d.sc, sizeof(CgScalars)) &&
+              alloc((void**)&ws->inner, sizeof(CgScalars)) &&
+              alloc((void**)&ws->d.counters, kCntCount * sizeof(unsigned)) &&
+              alloc((void**)&ws->d.partials, (size_t)blocks * 4 * sizeof(double)) &&
+              alloc((void**)&ws->d.out3, 4 * sizeof(double));
+    if (ok && mode == DG_PREC_MIXED) {
+        const size_t f32 = g->elems * sizeof(float);
+        ok = alloc((void**)&ws->r32, f32) && alloc((void**)&ws->e32, f32) &&
+             alloc((void**)&ws->q0, f32) && alloc((void**)&ws->q1, f32);
+    }
+    if (ok) ok = hipHostMalloc((void**)&ws->host, 4 * sizeof(CgScalars)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        dg_workspace_destroy(ws);
+        return fail(DG_E_NOMEM, "workspace allocation of %zu bytes failed", ws_bytes(g, mode));
+    }
+    for (auto& ev : ws->ev) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            dg_workspace_destroy(ws);
+            return fail(DG_E_HIP, "event creation failed");
+        }
+    }
+    for (auto& ev : ws->tev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            dg_workspace_destroy(ws);
+            return fail(DG_E_HIP, "event creation failed");
+        }
+    }
+    for (auto& row : ws->pev)
+        for (auto& ev : row)
+            if (hipEventCreate(&ev) != hipSuccess) {
+                dg_workspace_destroy(ws);
+                return fail(DG_E_HIP, "event creation failed");
+            }
+    ws->pev_iter[0] = ws->pev_iter[1] = -1;
+    // counters must start at zero (each reduction resets its own)
+    e = hipMemset(ws->d.counters, 0, kCntCount * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(ws->d.sc, 0, sizeof(CgScalars));
+    if (e == hipSuccess) e = hipMemset(ws->inner, 0, sizeof(CgScalars));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { dg_workspace_destroy(ws); return hip_fail(e, "workspace init"); }
+    ws->bytes = ws_bytes(g, mode);
+    *out = ws;
+    return DG_OK;
+}
+
+int dg_profile_enable(dg_workspace* ws, int on) {
+    if (!ws) return fail(DG_E_INVAL, "workspace is NULL");
+    ws->prof_on = on ? 1 : 0;
+    return DG_OK;
+}
+
+int dg_profile_read(dg_workspace* ws, double* out4) {
+    if (!ws || !out4) return fail(DG_E_INVAL, "NULL argument");
+    out4[0] = ws->prof_ms[0];
+    out4[1] = ws->prof_n[0];
+    out4[2] = ws->prof_ms[1];
+    out4[3] = ws->prof_n[1];
+    ws->prof_ms[0] = ws->prof_ms[1] = ws->prof_n[0] = ws->prof_n[1] = 0.0;
+    return DG_OK;
+}
+
+int dg_poisson_bracket(const dg_grid* g, const double* f, const double* gg,
+                       double* out, void* stream) {
+    return dg_bracket_form(g, f, gg, out, DG_FORM_ARAKAWA, stream);
+}
+
+int dg_bracket_form(const dg_grid* g, const double* f, const double* gg,
+                    double* out, int form, void* stream) {
+    if (!g || !f || !gg || !out) return fail(DG_E_INVAL, "NULL argument");
+    const size_t B = g->elems * sizeof(double);
+    if (ranges_overlap(out, f, B) || ranges_overlap(out, gg, B))
+        return fail(DG_E_ALIAS, "out aliases an input");
+    RhsParams p{};
+    switch (form) {
+        case DG_FORM_ARAKAWA: p.c0 = p.c1 = p.c2 = 1.0; p.scale = 1.0 / 3.0; break;
+        case DG_FORM_PP: p.c0 = 1.0; p.scale = 1.0; break;
+        case DG_FORM_PX: p.c1 = 1.0; p.scale = 1.0; break;
+        case DG_FORM_XP: p.c2 = 1.0; p.scale = 1.0; break;
+        default: return fail(DG_E_INVAL, "unknown bracket form %d", form);
+    }
+    hipError_t e = launch_rhs(g->geom, g->k64, f, gg, nullptr, out, p, false,
+                              as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "bracket launch");
+    return DG_OK;
+}
+
+int dg_laplace_apply(const dg_grid* g, const double* f, double* out, void* stream) {
+    if (!g || !f || !out) return fail(DG_E_INVAL, "NULL argument");
+    if (ranges_overlap(out, f, g->elems * sizeof(double)))
+        return fail(DG_E_ALIAS, "out aliases f");
+    hipError_t e = launch_laplace(g->geom, g->k64, f, out, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "laplace launch");
+    return DG_OK;
+}
+
+int dg_cg_solve_poisson(const dg_grid* g, const double* omega, double* psi,
+                        const dg_cg_opts* opts, dg_cg_stats* st, dg_workspace* ws,
+                        void* stream) {
+    if (!g || !omega || !psi) return fail(DG_E_INVAL, "NULL argument");
+    int rc = check_ws(g, ws);
+    if (rc != DG_OK) return rc;
+    const size_t B = g->elems * sizeof(double);
+    if (ranges_overlap(psi, omega, B)) return fail(DG_E_ALIAS, "psi aliases omega");
+    hipStream_t s = as_stream(stream);
+    // the guess is read with halos while x is written: copy it first
+    HIP_TRY(hipMemcpyAsync(ws->s1, psi, B, hipMemcpyDeviceToDevice, s));
+    return cg_dispatch(g, omega, psi, ws->s1, 1.0, nullptr, 0.0, opts, st, ws, s);
+}
+
+int dg_state_create(const dg_grid* g, double t0, dg_state** out) {
+    if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
+    *out = nullptr;
+    dg_state* st = new (std::nothrow) dg_state;
+    if (!st) return fail(DG_E_NOMEM, "host allocation failed");
+    std::memset(st, 0, sizeof *st);
+    st->n = g->n; st->nx = g->nx; st->ny = g->ny; st->elems = g->elems;
+    st->ia = st->ib = -1;
+    st->t = t0;
+    for (auto& b : st->buf) {
+        if (hipMalloc((void**)&b, g->elems * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            dg_state_destroy(st);
+            return fail(DG_E_NOMEM, "state allocation failed");
+        }
+    }
+    *out = st;
+    return DG_OK;
+}
+
+void dg_state_destroy(dg_state* st) {
+    if (!st) return;
+    for (auto b : st->buf) if (b) (void)hipFree(b);
+    delete st;
+}
+
+const double* dg_state_psi(const dg_state* st) {
+    return (st && st->ia >= 0) ? st->buf[st->ia] : nullptr;
+}
+
+double dg_state_time(const dg_state* st) { return st ? st->t : 0.0; }
+
+int dg_state_copy_psi(const dg_state* st, double* out, void* stream) {
+    if (!st || !out) return fail(DG_E_INVAL, "NULL argument");
+    if (st->ia < 0) return fail(DG_E_INVAL, "no Poisson solve yet");
+    HIP_TRY(hipMemcpyAsync(out, st->buf[st->ia], st->elems * sizeof(double),
+                           hipMemcpyDeviceToDevice, as_stream(stream)));
+    return DG_OK;
+}
+
+int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
+               const dg_step_opts* opts, dg_step_stats* stats, dg_workspace* ws,
+               void* stream) {
+    if (!g || !omega || !st || !opts) return fail(DG_E_INVAL, "NULL argument");
+    int rc = check_ws(g, ws);
+    if (rc != DG_OK) return rc;
+    if (st->n != g->n || st->nx != g->nx || st->ny != g->ny)
+        return fail(DG_E_INVAL, "state was made for another grid");
+    if (!std::isfinite(opts->dt) || !std::isfinite(opts->D))
+        return fail(DG_E_INVAL, "dt and D must be finite");
+    hipStream_t s = as_stream(stream);
+    const double dt = opts->dt, t = st->t;
+    const double ts[3] = {t, t + dt, t + 0.5 * dt};
+    const double ra[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double rb[3] = {1.0, 0.25, 2.0 / 3.0};
+    double* win[3] = {omega, ws->s1, ws->s2};
+    double* wout[3] = {ws->s1, ws->s2, omega};
+    const bool timing = opts->record_times != 0;
+    int result = DG_OK;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    bool all_conv = true;
+    if (timing) HIP_TRY(hipEventRecord(ws->tev[0], s));
+    for (int k = 0; k < 3; ++k) {
+        // guess: linear extrapolation in time through the two newest solves
+        const double* pa = nullptr;
+        const double* pb = nullptr;
+        double ca = 0.0, cb = 0.0;
+        if (st->count >= 1) {
+            pa = st->buf[st->ia];
+            ca = 1.0;
+            if (st->count >= 2 && st->ta != st->tb) {
+                const double th = (ts[k] - st->ta) / (st->ta - st->tb);
+                pb = st->buf[st->ib];
+                ca = 1.0 + th;
+                cb = -th;
+            }
+        }
+        int fr = 0;
+        while (fr == st->ia || fr == st->ib) ++fr;
+        double* x = st->buf[fr];
+        dg_cg_stats cs{};
+        rc = cg_dispatch(g, win[k], x, pa, ca, pb, cb, &opts->cg, &cs, ws, s);
+        if (rc == DG_E_NOCONV) { result = DG_E_NOCONV; all_conv = false; }
+        else if (rc != DG_OK) return rc;
+        st->ib = st->ia;
+        st->ia = fr;
+        st->tb = st->ta;
+        st->ta = ts[k];
+        st->count += 1;
+        RhsParams p{1.0, 1.0, 1.0, 1.0 / 3.0, opts->D, dt, ra[k], rb[k]};
+        hipError_t e = launch_rhs(g->geom, g->k64, x, win[k], k ? omega : nullptr,
+                                  wout[k], p, true, s);
+        if (e != hipSuccess) return hip_fail(e, "rhs launch");
+        if (timing) HIP_TRY(hipEventRecord(ws->tev[k + 1], s));
+        if (stats) stats->cg_iters[k] = cs.iters;
+    }
+    st->t = t + dt;
+    if (timing) {
+        HIP_TRY(hipEventSynchronize(ws->tev[3]));
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ws->tev[k], ws->tev[k + 1]));
+            if (stats) stats->stage_ms[k] = ms;
+        }
+    }
+    if (stats) stats->converged = all_conv ? 1 : 0;
+    if (result != DG_OK) return fail(result, "a stage solve did not converge");
+    return DG_OK;
+}
+
+int dg_invariants_dev(const dg_grid* g, const double* omega, const double* psi,
+                      double* out_dev3, dg_workspace* ws, void* stream) {
+    if (!g || !omega || !psi || !out_dev3) return fail(DG_E_INVAL, "NULL argument");
+    int rc = check_ws(g, ws);
+    if (rc != DG_OK) return rc;
+    hipError_t e = launch_invariants(g->geom, g->k64, omega, psi, out_dev3, ws->d,
+                                     as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "invariants launch");
+    return DG_OK;
+}
+
+int dg_invariants(const dg_grid* g, const double* omega, const double* psi,
+                  double* out_host3, dg_workspace* ws, void* stream) {
+    if (!out_host3) return fail(DG_E_INVAL, "NULL argument");
+    int rc = dg_invariants_dev(g, omega, psi, ws ? ws->d.out3 : nullptr, ws, stream);
+    if (rc != DG_OK) return rc;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(hipMemcpyAsync(out_host3, ws->d.out3, 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Internal declarations shared by the host tables, the C ABI layer and the
+// HIP kernels of libdgark.  Not part of the public interface.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dgk {
+
+constexpr int kMaxN = 5;
+
+// 1D operators on one cell and its two neighbours along one axis, unit cell
+// size (h = 1), in X-space (nodal values at Gauss-Legendre points).
+//   centred derivative (Sec. 4.2 eqs. discrete_der, matrix_xspace):
+//     (D u)_m = C0 u_m + cR (sR . u_{m+1}) + cL (sL . u_{m-1})
+//   LDG second derivative D_backward D_forward (Sec. 6):
+//     (L u)_m = L0 u_m + eR (lR . u_{m+1}) + eL (lL . u_{m-1})
+// The neighbour couplings are rank one: one scalar per node row.
+struct HostTables {
+    int n;
+    double xi[kMaxN], w[kMaxN];
+    double C0[kMaxN * kMaxN], cR[kMaxN], sR[kMaxN], cL[kMaxN], sL[kMaxN];
+    double L0[kMaxN * kMaxN], eR[kMaxN], lR[kMaxN], eL[kMaxN], lL[kMaxN];
+};
+
+// Builds the tables for n in [1, 5]; returns false on bad n.
+bool build_tables(int n, HostTables* t);
+
+// Operator constants passed to kernels by value (kernel-argument segment).
+template <class T>
+struct OpConst {
+    T C0[kMaxN * kMaxN], cR[kMaxN], sR[kMaxN], cL[kMaxN], sL[kMaxN];
+    T L0[kMaxN * kMaxN], eR[kMaxN], lR[kMaxN], eL[kMaxN], lL[kMaxN];
+    T w[kMaxN];
+    T ihx, ihy, ihx2, ihy2;   // 1/hx, 1/hy, 1/hx^2, 1/hy^2
+    double wq;                // hx * hy / 4: node weight = wq * w_i * w_j
+};
+
+// Geometry of one launch.
+struct Geom {
+    int n, nx, ny;
+};
+
+// Device-side scalars of one CG solve (lives in the workspace).
+struct CgScalars {
+    double rr;        // <r, r>_W of the current residual
+    double bb;        // <b, b>_W
+    double pq;        // <p, A p>_W
+    double alpha, beta;
+    double tol2;      // rtol^2
+    double mean_omega, mean_guess, mean_x;
+    double ca, cb;    // guess = ca * psi_a + cb * psi_b (device copies)
+    int iter, max_iter;
+    int done, converged, pending, first, zero, breakdown;
+};
+
+// Counters for the last-block-done reductions, one per kernel kind.
+enum CounterId { kCntMean = 0, kCntInit, kCntDir, kCntRes, kCntFinish,
+                 kCntInv, kCntDot, kCntCount };
+
+struct DevScratch {
+    CgScalars* sc;          // device scalars
+    unsigned* counters;     // kCntCount counters, zero between launches
+    double* partials;       // per-block partial sums (capacity max_blocks * 4)
+    double* out3;           // 3 doubles (invariants / generic reductions)
+    int max_blocks;
+};
+
+}  // namespace dgk

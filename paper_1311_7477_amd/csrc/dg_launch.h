@@ -1,0 +1,64 @@
+// Kernel launchers of libdgark (implemented in kernels.hip).  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+
+namespace dgk {
+
+struct RhsParams {
+    double c0, c1, c2, scale;   // bracket form coefficients
+    double D, dt, a, b;         // viscosity and RK-stage combination
+};
+
+// Blocks of one stencil launch on this grid (the reduction partials buffer
+// must hold at least this many entries, and pointwise_block_cap()).
+int stencil_blocks(const Geom& g);
+int pointwise_block_cap();
+
+hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,
+                          const double* u, double* out, hipStream_t s);
+hipError_t launch_rhs(const Geom& g, const OpConst<double>& k, const double* f,
+                      const double* gg, const double* wn, double* out,
+                      const RhsParams& p, bool visc, hipStream_t s);
+hipError_t launch_cg_mean(const Geom& g, const OpConst<double>& k,
+                          const double* omega, const double* pa,
+                          const double* pb, double ca, double cb, double area,
+                          double tol2, int max_iter, const DevScratch& d,
+                          hipStream_t s);
+hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
+                          const double* omega, const double* pa,
+                          const double* pb, double ca, double cb, double* x,
+                          double* r, const DevScratch& d, hipStream_t s);
+template <class T>
+hipError_t launch_cg_dir(const Geom& g, const OpConst<T>& k, T* x, T* r, T* p0,
+                         T* p1, int parity, CgScalars* sc, const DevScratch& d,
+                         hipStream_t s);
+template <class T>
+hipError_t launch_cg_res(const Geom& g, const OpConst<T>& k, T* r, T* p0, T* p1,
+                         int parity, CgScalars* sc, const DevScratch& d,
+                         hipStream_t s);
+template <class T>
+hipError_t launch_cg_iter(const Geom& g, const OpConst<T>& k, T* x, T* r,
+                          T* p0, T* p1, int parity, CgScalars* sc,
+                          const DevScratch& d, hipStream_t s);
+hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k, double* x,
+                            const double* p0, const double* p1, double area,
+                            const DevScratch& d, hipStream_t s);
+hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
+                             const double* omega, const double* psi,
+                             double* out3, const DevScratch& d, hipStream_t s);
+hipError_t launch_mixed_residual(const Geom& g, const OpConst<double>& k,
+                                 const double* omega, const double* psi,
+                                 float* r32, float* e32, double inner_tol2,
+                                 int inner_max, CgScalars* outer,
+                                 CgScalars* inner, const DevScratch& d,
+                                 hipStream_t s);
+hipError_t launch_mixed_update(const Geom& g, double* psi, const float* e,
+                               const float* p0, const float* p1,
+                               const CgScalars* inner, hipStream_t s);
+hipError_t launch_guess(long elems, double* x, const double* pa,
+                        const double* pb, double ca, double cb, hipStream_t s);
+
+}  // namespace dgk
