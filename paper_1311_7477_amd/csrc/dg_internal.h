@@ -49,6 +49,8 @@ struct CgScalars {
     double alpha, beta;
     double tol2;      // rtol^2
     double mean_omega, mean_guess, mean_x;
+    double ww;        // <omega, omega>_W
+    double zero_tol2; // b counts as zero when <b,b>_W <= zero_tol2 * ww
     double ca, cb;    // guess = ca * psi_a + cb * psi_b (device copies)
     int iter, max_iter;
     int done, converged, pending, first, zero, breakdown;

