@@ -29,7 +29,7 @@ METRIC = ("DG cell-updates/s per RHS (bracket+CG) at n=4, 512², 1 GPU; "
           "p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_dir_traffic_n4_512.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1311_7477_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1311_7477_amd", "csrc", "cg_kernels.hip")
 
 
 def kernel_source_hash():
@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--D", type=float, default=1e-4)
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 3 plain 256 MiB device copies (torch copy_) whose "
+                         "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the single-instance RHS is not "
@@ -106,6 +109,13 @@ def main():
 
     n, N = args.n, args.N
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     omega0, umax = inputs.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
     dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
     grid = dg.Grid(n, N, N)

@@ -30,8 +30,9 @@ struct dg_grid {
 struct dg_workspace {
     int n, nx, ny, mode, device;
     size_t elems;
-    double *r, *p0, *p1, *s1, *s2;
-    float *r32, *e32, *q0, *q1;
+    double *x, *r, *p0, *p1;   // CG vectors, lane-interleaved layout
+    double *s1, *s2;           // RK stage fields, canonical layout
+    float *r32, *e32, *q0, *q1;  // mixed-precision inner CG vectors
     DevScratch d;
     CgScalars* inner;          // device scalars of the mixed inner solve
     CgScalars* host;           // pinned, 4 slots (2 poll slots x {outer, inner})
@@ -114,16 +115,15 @@ int check_ws(const dg_grid* g, const dg_workspace* ws) {
     return DG_OK;
 }
 
-size_t mixed_extra(size_t elems) { return 4 * elems * sizeof(float); }
-
 size_t ws_bytes(const dg_grid* g, int mode) {
     const size_t F = g->elems * sizeof(double);
+    const size_t L = l64_elems(g->geom);
     int blocks = stencil_blocks(g->geom);
     if (blocks < pointwise_block_cap()) blocks = pointwise_block_cap();
-    size_t b = 5 * F;                                   // r, p0, p1, s1, s2
+    size_t b = 4 * L * sizeof(double) + 2 * F;          // x, r, p0, p1; s1, s2
     b += (size_t)blocks * 4 * sizeof(double);           // partials
     b += 2 * sizeof(CgScalars) + kCntCount * sizeof(unsigned) + 4 * sizeof(double);
-    if (mode == DG_PREC_MIXED) b += mixed_extra(g->elems);
+    if (mode == DG_PREC_MIXED) b += 4 * L * sizeof(float);
     return b;
 }
 
@@ -226,13 +226,13 @@ int cg_fp64(const dg_grid* g, const double* omega, double* x, const double* pa,
     hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
                                   tol2, o.max_iter, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg mean launch");
-    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, x, ws->r, ws->d, s);
+    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, ws->x, ws->r, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg init launch");
     CgScalars fin;
-    int rc = cg_loop<double>(g->geom, g->k64, x, ws->r, ws->p0, ws->p1, ws->d.sc,
+    int rc = cg_loop<double>(g->geom, g->k64, ws->x, ws->r, ws->p0, ws->p1, ws->d.sc,
                              o.max_iter, o.check_every, ws, s, &fin);
     if (rc != DG_OK) return rc;
-    e = launch_cg_finish(g->geom, g->k64, x, ws->p0, ws->p1, g->area, ws->d, s);
+    e = launch_cg_finish(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg finish launch");
     rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
     if (rc != DG_OK) return rc;
@@ -260,10 +260,10 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
     hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
                                   tol2, o.max_iter, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg mean launch");
-    // x = guess - mean(guess): reuse the finish kernel's mean subtraction
+    // x = guess - mean(guess)
     e = launch_guess((long)g->elems, x, pa, pb, ca, cb, s);
     if (e != hipSuccess) return hip_fail(e, "guess launch");
-    e = launch_cg_finish(g->geom, g->k64, x, ws->p0, ws->p1, g->area, ws->d, s);
+    e = launch_mean_sub(g->geom, g->k64, x, g->area, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "mean launch");
     int total_inner = 0, outer = 0;
     CgScalars oh, ih;
@@ -294,9 +294,13 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
             break;
         }
     }
-    // final W-mean removal of psi (pending = 0 in the outer scalars)
-    e = launch_cg_finish(g->geom, g->k64, x, ws->p0, ws->p1, g->area, ws->d, s);
-    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
+    // final W-mean removal of psi; b = 0 gives psi = 0
+    if (oh.zero) {
+        HIP_TRY(hipMemsetAsync(x, 0, g->elems * sizeof(double), s));
+    } else {
+        e = launch_mean_sub(g->geom, g->k64, x, g->area, ws->d, s);
+        if (e != hipSuccess) return hip_fail(e, "mean launch");
+    }
     HIP_TRY(hipStreamSynchronize(s));
     if (st) {
         st->iters = total_inner;
@@ -394,7 +398,7 @@ void dg_workspace_destroy(dg_workspace* ws) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ws->device);
-    void* bufs[] = {ws->r, ws->p0, ws->p1, ws->s1, ws->s2, ws->r32, ws->e32,
+    void* bufs[] = {ws->x, ws->r, ws->p0, ws->p1, ws->s1, ws->s2, ws->r32, ws->e32,
                     ws->q0, ws->q1, ws->d.sc, ws->d.counters, ws->d.partials,
                     ws->d.out3, ws->inner};
     for (void* b : bufs)
@@ -426,16 +430,19 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     auto alloc = [&](void** p, size_t b) -> bool {
         return hipMalloc(p, b) == hipSuccess;
     };
-    bool ok = alloc((void**)&ws->r, F) && alloc((void**)&ws->p0, F) &&
-              alloc((void**)&ws->p1, F) && alloc((void**)&ws->s1, F) &&
-              alloc((void**)&ws->s2, F) &&
+    const size_t L = l64_elems(g->geom);
+    bool ok = alloc((void**)&ws->x, L * sizeof(double)) &&
+              alloc((void**)&ws->r, L * sizeof(double)) &&
+              alloc((void**)&ws->p0, L * sizeof(double)) &&
+              alloc((void**)&ws->p1, L * sizeof(double)) &&
+              alloc((void**)&ws->s1, F) && alloc((void**)&ws->s2, F) &&
               alloc((void**)&ws->d.sc, sizeof(CgScalars)) &&
               alloc((void**)&ws->inner, sizeof(CgScalars)) &&
               alloc((void**)&ws->d.counters, kCntCount * sizeof(unsigned)) &&
               alloc((void**)&ws->d.partials, (size_t)blocks * 4 * sizeof(double)) &&
               alloc((void**)&ws->d.out3, 4 * sizeof(double));
     if (ok && mode == DG_PREC_MIXED) {
-        const size_t f32 = g->elems * sizeof(float);
+        const size_t f32 = L * sizeof(float);
         ok = alloc((void**)&ws->r32, f32) && alloc((void**)&ws->e32, f32) &&
              alloc((void**)&ws->q0, f32) && alloc((void**)&ws->q1, f32);
     }
@@ -533,10 +540,10 @@ int dg_cg_solve_poisson(const dg_grid* g, const double* omega, double* psi,
     if (rc != DG_OK) return rc;
     const size_t B = g->elems * sizeof(double);
     if (ranges_overlap(psi, omega, B)) return fail(DG_E_ALIAS, "psi aliases omega");
-    hipStream_t s = as_stream(stream);
-    // the guess is read with halos while x is written: copy it first
-    HIP_TRY(hipMemcpyAsync(ws->s1, psi, B, hipMemcpyDeviceToDevice, s));
-    return cg_dispatch(g, omega, psi, ws->s1, 1.0, nullptr, 0.0, opts, st, ws, s);
+    // psi is read (the guess) only by the setup kernels and written only by
+    // the final conversion out of the workspace vectors
+    return cg_dispatch(g, omega, psi, psi, 1.0, nullptr, 0.0, opts, st, ws,
+                       as_stream(stream));
 }
 
 int dg_state_create(const dg_grid* g, double t0, dg_state** out) {

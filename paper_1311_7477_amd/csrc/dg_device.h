@@ -1,0 +1,123 @@
+// Device helpers shared by the HIP kernels of libdgark: XCD-aware tile
+// order, vector loads/stores and the deterministic grid reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+
+namespace dgk {
+
+constexpr int kPwThreads = 256;
+
+// Block index -> tile index such that the blocks the dispatcher sends to one
+// XCD (block b goes to XCD b mod 8) get a contiguous run of tiles: halo
+// reads of neighbouring tiles then hit the same L2.
+__device__ __forceinline__ int xcd_tile(int nblocks) {
+    const int b = blockIdx.x;
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = nblocks >> 3, r = nblocks & 7;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+template <int M, class T>
+__device__ __forceinline__ void load_vec(const T* __restrict__ f, long off,
+                                         T (&u)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) u[i] = f[off + i];
+}
+
+template <int M, class T>
+__device__ __forceinline__ void store_vec(T* __restrict__ f, long off,
+                                          const T (&u)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) f[off + i] = u[i];
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction + last-block-done final sum.
+//
+// Partials are published with agent-scope atomic stores (coherent across
+// the XCDs' L2 caches), the publishing wave waits for their completion, then
+// takes a ticket with an agent-scope atomic add.  The block that draws the
+// last ticket reads all partials with agent-scope atomic loads.  No L2
+// write-back or invalidate is needed because only atomics carry data
+// between blocks; results for the next kernel are ordinary stores made
+// visible by the kernel boundary.
+// Returns true in the last block, where tot[] holds the grid-wide sums.
+// ---------------------------------------------------------------------------
+template <int NV, int NT>
+__device__ bool reduce_last(double (&v)[NV], double* partials,
+                            unsigned* counter, int nblocks, double (&tot)[NV]) {
+    __shared__ double red[(NT / 64) * NV];
+    __shared__ int is_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
+            __hip_atomic_store(&partials[(long)blockIdx.x * NV + k], s,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // partials performed before the ticket
+        const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (t == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += NT)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            acc[k] += __hip_atomic_load(&partials[(long)b * NV + k],
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
+        tot[k] = s;
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+#define DG_DISPATCH_N(n, ...) \
+    switch (n) {              \
+        case 1: { constexpr int NN = 1; __VA_ARGS__; } break; \
+        case 2: { constexpr int NN = 2; __VA_ARGS__; } break; \
+        case 3: { constexpr int NN = 3; __VA_ARGS__; } break; \
+        case 4: { constexpr int NN = 4; __VA_ARGS__; } break; \
+        case 5: { constexpr int NN = 5; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+inline int pw_blocks(long rows, int cap) {
+    long b = (rows + kPwThreads - 1) / kPwThreads;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace dgk

@@ -1,4 +1,5 @@
-// Kernel launchers of libdgark (implemented in kernels.hip).  Internal.
+// Kernel launchers of libdgark (cg_kernels.hip, rhs_kernels.hip,
+// pointwise.hip).  Internal.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,10 +13,18 @@ struct RhsParams {
     double D, dt, a, b;         // viscosity and RK-stage combination
 };
 
-// Blocks of one stencil launch on this grid (the reduction partials buffer
-// must hold at least this many entries, and pointwise_block_cap()).
+// Blocks of one launch of each stencil family; the reduction partials
+// buffer holds at least max(stencil_blocks, pointwise_block_cap) entries.
+int row_blocks(const Geom& g);
+int cell_blocks(const Geom& g);
 int stencil_blocks(const Geom& g);
 int pointwise_block_cap();
+
+// Elements of one CG vector in the lane-interleaved layout (cells grouped by
+// 64 along x, node-major inside a group): ny * ceil(nx/64) * n*n * 64.
+inline size_t l64_elems(const Geom& g) {
+    return (size_t)g.ny * (size_t)((g.nx + 63) / 64) * (size_t)(g.n * g.n) * 64;
+}
 
 hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,
                           const double* u, double* out, hipStream_t s);
@@ -27,6 +36,7 @@ hipError_t launch_cg_mean(const Geom& g, const OpConst<double>& k,
                           const double* pb, double ca, double cb, double area,
                           double tol2, int max_iter, const DevScratch& d,
                           hipStream_t s);
+// x, r: lane-interleaved; omega, pa, pb: canonical
 hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                           const double* omega, const double* pa,
                           const double* pb, double ca, double cb, double* x,
@@ -43,9 +53,14 @@ template <class T>
 hipError_t launch_cg_iter(const Geom& g, const OpConst<T>& k, T* x, T* r,
                           T* p0, T* p1, int parity, CgScalars* sc,
                           const DevScratch& d, hipStream_t s);
-hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k, double* x,
-                            const double* p0, const double* p1, double area,
-                            const DevScratch& d, hipStream_t s);
+// psi (canonical) = x + pending alpha p (lane-interleaved), minus its W-mean
+hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
+                            const double* x, const double* p0, const double* p1,
+                            double* psi, double area, const DevScratch& d,
+                            hipStream_t s);
+// x (canonical) -= its W-mean
+hipError_t launch_mean_sub(const Geom& g, const OpConst<double>& k, double* x,
+                           double area, const DevScratch& d, hipStream_t s);
 hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
                              const double* omega, const double* psi,
                              double* out3, const DevScratch& d, hipStream_t s);

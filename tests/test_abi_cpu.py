@@ -99,9 +99,15 @@ def test_workspace_bytes_and_field_size():
     g = dg.Grid(4, 512, 512)
     assert g.elems == 512 * 512 * 16
     F = g.elems * 8
+    # CG vectors x, r, p0, p1 (lane-interleaved, no padding when 64 | nx),
+    # RK stage fields s1, s2, reduction scratch
     b64, bmx = g.workspace_bytes(dg.DG_PREC_FP64), g.workspace_bytes(dg.DG_PREC_MIXED)
-    assert 5 * F <= b64 < 5 * F + 2 ** 20
+    assert 6 * F <= b64 < 6 * F + 2 ** 20
     assert bmx == b64 + 4 * g.elems * 4
+    # ragged nx: the interleaved vectors are padded to whole groups of 64 cells
+    h = dg.Grid(3, 100, 7)
+    L = 7 * 2 * 9 * 64
+    assert h.workspace_bytes(dg.DG_PREC_FP64) >= 4 * L * 8 + 2 * h.elems * 8
 
 
 def test_null_arguments_are_rejected():
