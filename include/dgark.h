@@ -206,6 +206,45 @@ int  dg_invariants_dev(const dg_grid* grid, const double* omega,
                        const double* psi, double* out_dev3, dg_workspace* ws,
                        void* stream);
 
+/* ------------------------------------------------------------- batches --- */
+/* Many independent instances (any n, any grid) advanced together: each
+ * kernel kind runs as one persistent launch per polynomial order over a
+ * device-resident (instance, block) work list, and the setup, CG-chunk and
+ * finish/RHS sequences of an RK stage are replayed as HIP graphs.  Every
+ * instance is cut into the same blocks and uses the same device code as
+ * dg_rk_step, so its result is bitwise the same alone or in any batch.
+ * Instances can be attached and detached between steps (continuous
+ * batching).  A batch lives on the current device and serves one stream at
+ * a time. */
+typedef struct dg_batch dg_batch;
+/* capacity in [1, 4096] slots.  Errors: DG_E_INVAL, DG_E_NOMEM. */
+int  dg_batch_create(int capacity, dg_batch** out);
+void dg_batch_destroy(dg_batch* b);                  /* NULL-safe; synchronises */
+/* Put an instance into a free slot.  grid must outlive the membership;
+ * omega (device, canonical, caller-owned) is advanced in place by each step.
+ * The batch allocates the instance's workspace and state
+ * (dg_batch_member_bytes).  Returns the slot in *slot.  DG_E_INVAL when
+ * the batch is full. */
+int  dg_batch_attach(dg_batch* b, const dg_grid* grid, double* omega, double dt,
+                     double D, double t0, int* slot);
+/* Free a slot and its device memory (synchronises the device). */
+int  dg_batch_detach(dg_batch* b, int slot);
+/* Device bytes one member holds (workspace + state + record): the figure
+ * an admission controller budgets. */
+int  dg_batch_member_bytes(const dg_grid* grid, size_t* bytes);
+/* 1 (default): replay captured HIP graphs; 0: launch kernels directly. */
+int  dg_batch_use_graphs(dg_batch* b, int on);
+/* One SSP-RK3 step of every attached instance (FP64 CG, opts->precision
+ * must be DG_PREC_FP64).  iters_out, if not NULL, receives the CG
+ * iterations of slot i's stage k at [3 i + k] (capacity * 3 ints).
+ * Synchronises the stream.  DG_E_NOCONV if some solve hit max_iter. */
+int  dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
+                      void* stream);
+/* Copy slot's most recent psi to out (device); asynchronous. */
+int  dg_batch_copy_psi(const dg_batch* b, int slot, double* out, void* stream);
+/* Simulation time of a slot (0 for an empty slot). */
+double dg_batch_time(const dg_batch* b, int slot);
+
 #ifdef __cplusplus
 }
 #endif

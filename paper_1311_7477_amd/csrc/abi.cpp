@@ -11,54 +11,16 @@
 #include <new>
 #include <string>
 
-#include "../../include/dgark.h"
-#include "dg_internal.h"
+#include "abi_types.h"
 #include "dg_launch.h"
 
 using namespace dgk;
 
-struct dg_grid {
-    int n, nx, ny;
-    double x0, x1, y0, y1, hx, hy, area;
-    HostTables t;
-    OpConst<double> k64;
-    OpConst<float> k32;
-    Geom geom;
-    size_t elems;
-};
-
-struct dg_workspace {
-    int n, nx, ny, mode, device;
-    size_t elems;
-    double *x, *r, *p0, *p1;   // CG vectors, lane-interleaved layout
-    double *s1, *s2;           // RK stage fields, canonical layout
-    float *r32, *e32, *q0, *q1;  // mixed-precision inner CG vectors
-    DevScratch d;
-    CgScalars* inner;          // device scalars of the mixed inner solve
-    CgScalars* host;           // pinned, 4 slots (2 poll slots x {outer, inner})
-    hipEvent_t ev[2];
-    hipEvent_t tev[4];
-    size_t bytes;
-    // live kernel timing (measurement support)
-    int prof_on;
-    hipEvent_t pev[2][4];
-    int pev_iter[2];           // iteration index sampled in that poll slot (-1: none)
-    double prof_ms[2];         // summed ms of sampled direction / residual launches
-    double prof_n[2];
-};
-
-struct dg_state {
-    int n, nx, ny;
-    size_t elems;
-    double* buf[3];
-    int ia, ib;                // indices of the newest / previous solution (-1 none)
-    double ta, tb, t;
-    int count;
-};
+namespace dgk {
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -74,11 +36,41 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(DG_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(call)                                 \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
+const char* last_error() { return g_err.c_str(); }
+
+void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
+                 const double** pb, double* cb, double** x, int* xi) {
+    *pa = nullptr;
+    *pb = nullptr;
+    *ca = 0.0;
+    *cb = 0.0;
+    if (st->count >= 1) {
+        *pa = st->buf[st->ia];
+        *ca = 1.0;
+        if (st->count >= 2 && st->ta != st->tb) {
+            const double th = (ts - st->ta) / (st->ta - st->tb);
+            *pb = st->buf[st->ib];
+            *ca = 1.0 + th;
+            *cb = -th;
+        }
+    }
+    int fr = 0;
+    while (fr == st->ia || fr == st->ib) ++fr;
+    *x = st->buf[fr];
+    *xi = fr;
+}
+
+void state_push(dg_state* st, int xi, double ts) {
+    st->ib = st->ia;
+    st->ia = xi;
+    st->tb = st->ta;
+    st->ta = ts;
+    st->count += 1;
+}
+
+}  // namespace dgk
+
+namespace {
 
 template <class T>
 void fill_const(const dg_grid& g, OpConst<T>& k) {
@@ -610,31 +602,17 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
     if (timing) HIP_TRY(hipEventRecord(ws->tev[0], s));
     for (int k = 0; k < 3; ++k) {
         // guess: linear extrapolation in time through the two newest solves
-        const double* pa = nullptr;
-        const double* pb = nullptr;
-        double ca = 0.0, cb = 0.0;
-        if (st->count >= 1) {
-            pa = st->buf[st->ia];
-            ca = 1.0;
-            if (st->count >= 2 && st->ta != st->tb) {
-                const double th = (ts[k] - st->ta) / (st->ta - st->tb);
-                pb = st->buf[st->ib];
-                ca = 1.0 + th;
-                cb = -th;
-            }
-        }
-        int fr = 0;
-        while (fr == st->ia || fr == st->ib) ++fr;
-        double* x = st->buf[fr];
+        const double* pa;
+        const double* pb;
+        double ca, cb;
+        double* x;
+        int fr;
+        state_guess(st, ts[k], &pa, &ca, &pb, &cb, &x, &fr);
         dg_cg_stats cs{};
         rc = cg_dispatch(g, win[k], x, pa, ca, pb, cb, &opts->cg, &cs, ws, s);
         if (rc == DG_E_NOCONV) { result = DG_E_NOCONV; all_conv = false; }
         else if (rc != DG_OK) return rc;
-        st->ib = st->ia;
-        st->ia = fr;
-        st->tb = st->ta;
-        st->ta = ts[k];
-        st->count += 1;
+        state_push(st, fr, ts[k]);
         RhsParams p{1.0, 1.0, 1.0, 1.0 / 3.0, opts->D, dt, ra[k], rb[k]};
         hipError_t e = launch_rhs(g->geom, g->k64, x, win[k], k ? omega : nullptr,
                                   wout[k], p, true, s);

@@ -1,0 +1,69 @@
+// Definitions of the opaque C-ABI objects and the error helpers shared by
+// the ABI translation units (abi.cpp, batch.cpp).  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/dgark.h"
+#include "dg_internal.h"
+
+using dgk::HostTables; using dgk::OpConst; using dgk::Geom; using dgk::DevScratch; using dgk::CgScalars;
+
+struct dg_grid {
+    int n, nx, ny;
+    double x0, x1, y0, y1, hx, hy, area;
+    HostTables t;
+    OpConst<double> k64;
+    OpConst<float> k32;
+    Geom geom;
+    size_t elems;
+};
+
+struct dg_workspace {
+    int n, nx, ny, mode, device;
+    size_t elems;
+    double *x, *r, *p0, *p1;   // CG vectors, lane-interleaved layout
+    double *s1, *s2;           // RK stage fields, canonical layout
+    float *r32, *e32, *q0, *q1;  // mixed-precision inner CG vectors
+    DevScratch d;
+    CgScalars* inner;          // device scalars of the mixed inner solve
+    CgScalars* host;           // pinned, 4 slots (2 poll slots x {outer, inner})
+    hipEvent_t ev[2];
+    hipEvent_t tev[4];
+    size_t bytes;
+    // live kernel timing (measurement support)
+    int prof_on;
+    hipEvent_t pev[2][4];
+    int pev_iter[2];           // iteration index sampled in that poll slot (-1: none)
+    double prof_ms[2];         // summed ms of sampled direction / residual launches
+    double prof_n[2];
+};
+
+struct dg_state {
+    int n, nx, ny;
+    size_t elems;
+    double* buf[3];
+    int ia, ib;                // indices of the newest / previous solution (-1 none)
+    double ta, tb, t;
+    int count;
+};
+
+namespace dgk {
+// Record a failure (thread-local message) and return its code.
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+// The guess of the next solve from the state's history (linear-in-time
+// extrapolation through the two newest solves), and the free buffer x.
+void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
+                 const double** pb, double* cb, double** x, int* xi);
+// Record that buffer xi now holds the solve at time ts.
+void state_push(dg_state* st, int xi, double ts);
+}  // namespace dgk
+
+#define HIP_TRY(call)                                          \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return dgk::hip_fail(e_, #call); \
+    } while (0)

@@ -1,0 +1,438 @@
+// C ABI of batches: independent instances that advance together, one
+// persistent launch per kernel kind and polynomial order, captured in HIP
+// graphs.  Instances can be attached and detached between steps (the
+// serving loop's continuous batching); each keeps its own workspace, state
+// and device CG scalars, and its arithmetic is that of dg_rk_step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "abi_types.h"
+#include "batch.h"
+#include "dg_launch.h"
+
+using namespace dgk;
+
+namespace {
+
+enum ListKind { kCell = 0, kRow, kPwRows, kPwCells, kPwElems, kListCount };
+
+struct Slot {
+    bool used = false;
+    const dg_grid* grid = nullptr;
+    double* omega = nullptr;
+    double dt = 0.0, D = 0.0;
+    dg_workspace* ws = nullptr;
+    dg_state* st = nullptr;
+};
+
+struct DevList {
+    BatchItem* items = nullptr;
+    int cap = 0;
+    int count = 0;
+};
+
+}  // namespace
+
+struct dg_batch {
+    int capacity = 0;
+    int device = 0;
+    std::vector<Slot> slots;
+    BatchInst* d_inst = nullptr;   // device records
+    BatchInst* h_inst = nullptr;   // pinned host records
+    CgScalars* d_sc = nullptr;     // device CG scalars, one per slot
+    CgScalars* h_sc = nullptr;     // pinned: 3 x capacity (2 poll slots + final)
+    int* d_counts = nullptr;       // device item counts [n-1][kind]
+    int* h_counts = nullptr;       // pinned
+    DevList lists[kMaxN][kListCount];
+    bool lists_dirty = true;
+    unsigned group_mask = 0;       // bit n-1 set if some slot has order n
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t cap = nullptr;     // capture stream
+    bool use_graphs = true;
+    bool graphs_valid = false;
+    int chunk = 16;                // CG iterations per captured chunk (even)
+    hipGraphExec_t g_setup = nullptr, g_chunk = nullptr, g_finish = nullptr;
+};
+
+namespace {
+
+void destroy_graphs(dg_batch* b) {
+    for (hipGraphExec_t* g : {&b->g_setup, &b->g_chunk, &b->g_finish})
+        if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+    b->graphs_valid = false;
+}
+
+ItemList list_of(const dg_batch* b, int n, int kind) {
+    return ItemList{b->lists[n - 1][kind].items, b->d_counts + (n - 1) * kListCount + kind};
+}
+
+int grid_of(const dg_batch* b, int n, int kind) {
+    const int c = b->lists[n - 1][kind].count;
+    return c < 1 ? 1 : (c > 65535 ? 65535 : c);
+}
+
+// Rebuild the per-order work lists (instance, local block) on the host and
+// upload them.
+int rebuild_lists(dg_batch* b, hipStream_t s) {
+    std::vector<BatchItem> h[kMaxN][kListCount];
+    unsigned mask = 0;
+    for (int i = 0; i < b->capacity; ++i) {
+        const Slot& sl = b->slots[i];
+        if (!sl.used) continue;
+        const BatchInst& r = b->h_inst[i];
+        const int n = r.g.n;
+        mask |= 1u << (n - 1);
+        const int counts[kListCount] = {r.cell_nblocks, r.row_nblocks, r.nb_rows,
+                                        r.nb_cells, r.nb_elems};
+        for (int k = 0; k < kListCount; ++k)
+            for (int q = 0; q < counts[k]; ++q) h[n - 1][k].push_back(BatchItem{i, q});
+    }
+    bool realloc_any = false;
+    for (int n = 0; n < kMaxN; ++n)
+        for (int k = 0; k < kListCount; ++k) {
+            DevList& L = b->lists[n][k];
+            const int need = (int)h[n][k].size();
+            if (need > L.cap) {
+                if (L.items) (void)hipFree(L.items);
+                L.items = nullptr;
+                int cap = L.cap ? L.cap : 256;
+                while (cap < need) cap *= 2;
+                if (hipMalloc((void**)&L.items, (size_t)cap * sizeof(BatchItem)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    L.cap = 0;
+                    return fail(DG_E_NOMEM, "batch work list allocation failed");
+                }
+                L.cap = cap;
+                realloc_any = true;
+            }
+            L.count = need;
+            b->h_counts[n * kListCount + k] = need;
+            if (need)
+                HIP_TRY(hipMemcpyAsync(L.items, h[n][k].data(), need * sizeof(BatchItem),
+                                       hipMemcpyHostToDevice, s));
+        }
+    HIP_TRY(hipMemcpyAsync(b->d_counts, b->h_counts, kMaxN * kListCount * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    // the host vectors above are pageable: make the copies complete
+    HIP_TRY(hipStreamSynchronize(s));
+    // launch grids follow the item counts: recapture the graphs
+    (void)realloc_any;
+    destroy_graphs(b);
+    b->group_mask = mask;
+    b->lists_dirty = false;
+    return DG_OK;
+}
+
+int enqueue_setup(dg_batch* b, hipStream_t s) {
+    for (int n = 1; n <= kMaxN; ++n) {
+        if (!(b->group_mask & (1u << (n - 1)))) continue;
+        hipError_t e = launch_batch(n, BatchKernel::Mean, b->d_inst, list_of(b, n, kPwRows),
+                                    grid_of(b, n, kPwRows), 0, s);
+        if (e == hipSuccess)
+            e = launch_batch(n, BatchKernel::Init, b->d_inst, list_of(b, n, kCell),
+                             grid_of(b, n, kCell), 0, s);
+        if (e != hipSuccess) return hip_fail(e, "batch setup launch");
+    }
+    return DG_OK;
+}
+
+int enqueue_chunk(dg_batch* b, hipStream_t s) {
+    for (int i = 0; i < b->chunk; ++i)
+        for (int n = 1; n <= kMaxN; ++n) {
+            if (!(b->group_mask & (1u << (n - 1)))) continue;
+            hipError_t e = launch_batch(n, BatchKernel::Dir, b->d_inst, list_of(b, n, kCell),
+                                        grid_of(b, n, kCell), i & 1, s);
+            if (e == hipSuccess)
+                e = launch_batch(n, BatchKernel::Res, b->d_inst, list_of(b, n, kCell),
+                                 grid_of(b, n, kCell), i & 1, s);
+            if (e != hipSuccess) return hip_fail(e, "batch CG launch");
+        }
+    return DG_OK;
+}
+
+int enqueue_finish(dg_batch* b, hipStream_t s) {
+    for (int n = 1; n <= kMaxN; ++n) {
+        if (!(b->group_mask & (1u << (n - 1)))) continue;
+        hipError_t e = launch_batch(n, BatchKernel::Finish, b->d_inst,
+                                    list_of(b, n, kPwCells), grid_of(b, n, kPwCells), 0, s);
+        if (e == hipSuccess)
+            e = launch_batch(n, BatchKernel::SubMean, b->d_inst, list_of(b, n, kPwElems),
+                             grid_of(b, n, kPwElems), 0, s);
+        if (e == hipSuccess)
+            e = launch_batch(n, BatchKernel::Rhs, b->d_inst, list_of(b, n, kRow),
+                             grid_of(b, n, kRow), 0, s);
+        if (e != hipSuccess) return hip_fail(e, "batch finish launch");
+    }
+    return DG_OK;
+}
+
+int capture(dg_batch* b, int (*fn)(dg_batch*, hipStream_t), hipGraphExec_t* out) {
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = fn(b, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc != DG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return DG_OK;
+}
+
+int ensure_graphs(dg_batch* b) {
+    if (b->graphs_valid) return DG_OK;
+    destroy_graphs(b);
+    int rc = capture(b, enqueue_setup, &b->g_setup);
+    if (rc == DG_OK) rc = capture(b, enqueue_chunk, &b->g_chunk);
+    if (rc == DG_OK) rc = capture(b, enqueue_finish, &b->g_finish);
+    if (rc != DG_OK) { destroy_graphs(b); return rc; }
+    b->graphs_valid = true;
+    return DG_OK;
+}
+
+int run(dg_batch* b, int (*fn)(dg_batch*, hipStream_t), hipGraphExec_t g, hipStream_t s) {
+    if (b->use_graphs) {
+        HIP_TRY(hipGraphLaunch(g, s));
+        return DG_OK;
+    }
+    return fn(b, s);
+}
+
+bool all_done(const dg_batch* b, const CgScalars* h) {
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->slots[i].used && !h[i].done) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_batch_create(int capacity, dg_batch** out) {
+    if (!out || capacity < 1 || capacity > 4096)
+        return fail(DG_E_INVAL, "capacity must be in [1, 4096]");
+    *out = nullptr;
+    dg_batch* b = new (std::nothrow) dg_batch;
+    if (!b) return fail(DG_E_NOMEM, "host allocation failed");
+    b->capacity = capacity;
+    b->slots.resize(capacity);
+    bool ok = hipGetDevice(&b->device) == hipSuccess &&
+              hipMalloc((void**)&b->d_inst, capacity * sizeof(BatchInst)) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_inst, capacity * sizeof(BatchInst)) == hipSuccess &&
+              hipMalloc((void**)&b->d_sc, capacity * sizeof(CgScalars)) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_sc, 3 * capacity * sizeof(CgScalars)) == hipSuccess &&
+              hipMalloc((void**)&b->d_counts, kMaxN * kListCount * sizeof(int)) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_counts, kMaxN * kListCount * sizeof(int)) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        std::memset(b->h_inst, 0, capacity * sizeof(BatchInst));
+        std::memset(b->h_counts, 0, kMaxN * kListCount * sizeof(int));
+        ok = hipMemset(b->d_sc, 0, capacity * sizeof(CgScalars)) == hipSuccess &&
+             hipMemset(b->d_counts, 0, kMaxN * kListCount * sizeof(int)) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        dg_batch_destroy(b);
+        return fail(DG_E_NOMEM, "batch allocation failed");
+    }
+    *out = b;
+    return DG_OK;
+}
+
+void dg_batch_destroy(dg_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    destroy_graphs(b);
+    for (Slot& s : b->slots) {
+        dg_workspace_destroy(s.ws);
+        dg_state_destroy(s.st);
+    }
+    for (auto& row : b->lists)
+        for (DevList& L : row)
+            if (L.items) (void)hipFree(L.items);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->h_inst) (void)hipHostFree(b->h_inst);
+    if (b->d_sc) (void)hipFree(b->d_sc);
+    if (b->h_sc) (void)hipHostFree(b->h_sc);
+    if (b->d_counts) (void)hipFree(b->d_counts);
+    if (b->h_counts) (void)hipHostFree(b->h_counts);
+    for (hipEvent_t e : b->ev) if (e) (void)hipEventDestroy(e);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+int dg_batch_attach(dg_batch* b, const dg_grid* g, double* omega, double dt,
+                    double D, double t0, int* slot) {
+    if (!b || !g || !omega || !slot) return fail(DG_E_INVAL, "NULL argument");
+    if (!std::isfinite(dt) || !std::isfinite(D)) return fail(DG_E_INVAL, "dt, D must be finite");
+    int i = 0;
+    while (i < b->capacity && b->slots[i].used) ++i;
+    if (i == b->capacity) return fail(DG_E_INVAL, "batch is full (%d slots)", b->capacity);
+    Slot& sl = b->slots[i];
+    int rc = dg_workspace_create(g, DG_PREC_FP64, &sl.ws);
+    if (rc != DG_OK) return rc;
+    rc = dg_state_create(g, t0, &sl.st);
+    if (rc != DG_OK) { dg_workspace_destroy(sl.ws); sl.ws = nullptr; return rc; }
+    sl.used = true;
+    sl.grid = g;
+    sl.omega = omega;
+    sl.dt = dt;
+    sl.D = D;
+    BatchInst& r = b->h_inst[i];
+    std::memset(&r, 0, sizeof r);
+    r.g = g->geom;
+    fill_batch_geometry(r);
+    r.area = g->area;
+    r.k = g->k64;
+    r.active = 1;
+    r.x = sl.ws->x;
+    r.r = sl.ws->r;
+    r.p0 = sl.ws->p0;
+    r.p1 = sl.ws->p1;
+    r.sc = b->d_sc + i;
+    r.counters = sl.ws->d.counters;
+    r.partials = sl.ws->d.partials;
+    b->lists_dirty = true;
+    *slot = i;
+    return DG_OK;
+}
+
+int dg_batch_detach(dg_batch* b, int slot) {
+    if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].used)
+        return fail(DG_E_INVAL, "no instance in slot %d", slot);
+    HIP_TRY(hipDeviceSynchronize());
+    Slot& sl = b->slots[slot];
+    dg_workspace_destroy(sl.ws);
+    dg_state_destroy(sl.st);
+    sl = Slot{};
+    b->h_inst[slot].active = 0;
+    b->lists_dirty = true;
+    return DG_OK;
+}
+
+int dg_batch_use_graphs(dg_batch* b, int on) {
+    if (!b) return fail(DG_E_INVAL, "NULL argument");
+    b->use_graphs = on != 0;
+    return DG_OK;
+}
+
+int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
+                     void* stream) {
+    if (!b) return fail(DG_E_INVAL, "NULL argument");
+    dg_cg_opts o;
+    if (opts) o = *opts;
+    else { o.rtol = 1e-12; o.max_iter = 100000; o.precision = DG_PREC_FP64;
+           o.inner_rtol = 1e-5; o.check_every = 0; }
+    if (o.precision != DG_PREC_FP64)
+        return fail(DG_E_UNSUPPORTED, "batches run the FP64 CG only");
+    if (!(o.rtol > 0) || o.max_iter < 0) return fail(DG_E_INVAL, "bad CG options");
+    hipStream_t s = (hipStream_t)stream;
+    int used = 0;
+    for (const Slot& sl : b->slots) used += sl.used;
+    if (used == 0) return DG_OK;
+    if (b->lists_dirty) {
+        int rc = rebuild_lists(b, s);
+        if (rc != DG_OK) return rc;
+    }
+    if (b->use_graphs) {
+        int rc = ensure_graphs(b);
+        if (rc != DG_OK) return rc;
+    }
+    const double ra_a[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double ra_b[3] = {1.0, 0.25, 2.0 / 3.0};
+    bool all_conv = true;
+    for (int k = 0; k < 3; ++k) {
+        std::vector<int> xi(b->capacity, -1);
+        std::vector<double> ts(b->capacity, 0.0);
+        for (int i = 0; i < b->capacity; ++i) {
+            Slot& sl = b->slots[i];
+            if (!sl.used) continue;
+            BatchInst& r = b->h_inst[i];
+            const double t = sl.st->t;
+            ts[i] = (k == 0) ? t : (k == 1 ? t + sl.dt : t + 0.5 * sl.dt);
+            double* x;
+            state_guess(sl.st, ts[i], &r.pa, &r.ca, &r.pb, &r.cb, &x, &xi[i]);
+            r.psi = x;
+            double* win[3] = {sl.omega, sl.ws->s1, sl.ws->s2};
+            double* wout[3] = {sl.ws->s1, sl.ws->s2, sl.omega};
+            r.w_in = win[k];
+            r.w_out = wout[k];
+            r.w_n = k ? sl.omega : nullptr;
+            r.ra = RhsArgs{1.0, 1.0, 1.0, 1.0 / 3.0, sl.D, sl.dt, ra_a[k], ra_b[k]};
+            r.tol2 = o.rtol * o.rtol;
+            r.max_iter = o.max_iter;
+        }
+        HIP_TRY(hipMemcpyAsync(b->d_inst, b->h_inst, b->capacity * sizeof(BatchInst),
+                               hipMemcpyHostToDevice, s));
+        int rc = run(b, enqueue_setup, b->g_setup, s);
+        if (rc != DG_OK) return rc;
+        // CG chunks, polled one chunk behind
+        int issued = 0, round = 0, prev = -1;
+        for (;;) {
+            rc = run(b, enqueue_chunk, b->g_chunk, s);
+            if (rc != DG_OK) return rc;
+            issued += b->chunk;
+            const int slot = round & 1;
+            HIP_TRY(hipMemcpyAsync(b->h_sc + slot * b->capacity, b->d_sc,
+                                   b->capacity * sizeof(CgScalars),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(b->ev[slot], s));
+            if (issued >= o.max_iter + b->chunk) {
+                HIP_TRY(hipEventSynchronize(b->ev[slot]));
+                break;
+            }
+            if (prev >= 0) {
+                HIP_TRY(hipEventSynchronize(b->ev[prev]));
+                if (all_done(b, b->h_sc + prev * b->capacity)) break;
+            }
+            prev = slot;
+            ++round;
+        }
+        rc = run(b, enqueue_finish, b->g_finish, s);
+        if (rc != DG_OK) return rc;
+        CgScalars* fin = b->h_sc + 2 * b->capacity;
+        HIP_TRY(hipMemcpyAsync(fin, b->d_sc, b->capacity * sizeof(CgScalars),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < b->capacity; ++i) {
+            Slot& sl = b->slots[i];
+            if (!sl.used) continue;
+            state_push(sl.st, xi[i], ts[i]);
+            if (!fin[i].converged) all_conv = false;
+            if (iters_out) iters_out[3 * i + k] = fin[i].iter;
+        }
+    }
+    for (Slot& sl : b->slots)
+        if (sl.used) sl.st->t += sl.dt;
+    if (!all_conv) return fail(DG_E_NOCONV, "a batched solve did not converge");
+    return DG_OK;
+}
+
+int dg_batch_copy_psi(const dg_batch* b, int slot, double* out, void* stream) {
+    if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].used)
+        return fail(DG_E_INVAL, "no instance in slot %d", slot);
+    return dg_state_copy_psi(b->slots[slot].st, out, stream);
+}
+
+double dg_batch_time(const dg_batch* b, int slot) {
+    if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].used) return 0.0;
+    return b->slots[slot].st->t;
+}
+
+int dg_batch_member_bytes(const dg_grid* g, size_t* bytes) {
+    if (!g || !bytes) return fail(DG_E_INVAL, "NULL argument");
+    size_t w = 0;
+    int rc = dg_workspace_bytes(g, DG_PREC_FP64, &w);
+    if (rc != DG_OK) return rc;
+    *bytes = w + 3 * g->elems * sizeof(double) + sizeof(BatchInst);
+    return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Batched launches: many independent instances (any grid sizes, one
+// polynomial order per launch) in one persistent grid-stride launch per
+// kernel kind.  Every instance is described by a BatchInst record in device
+// memory and cut into the same blocks as its single-instance launch; the
+// work list holds (instance, local block index) items.  Each item runs the
+// very same device body as the single-instance kernel with the same local
+// block index, so an instance's arithmetic and reduction order -- and hence
+// its result, bit for bit -- do not depend on what else is in the batch.
+// Parameters that change between RK stages live in the records, so one
+// captured graph serves every stage.
+#include "batch.h"
+#include "dg_launch.h"
+#include "cg_body.h"
+#include "pw_body.h"
+#include "rhs_body.h"
+
+namespace dgk {
+
+// Loop over this launch's items; the per-item early exits of the bodies are
+// uniform per block, and the barrier at the end of each item protects the
+// block's LDS before the next item reuses it.
+#define DG_FOR_ITEMS(list)                                                   \
+    for (int it_ = blockIdx.x; it_ < *(list).count; it_ += gridDim.x)        \
+        if (const BatchItem item_ = (list).items[it_]; true)                 \
+            if (const BatchInst& B = inst[item_.inst]; B.active)
+
+template <int N>
+__global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* inst,
+                                                         ItemList list) {
+    DG_FOR_ITEMS(list) {
+        cg_mean_body<N>(item_.b, B.nb_rows, B.rows, B.k, B.w_in, B.pa, B.pb,
+                        B.ca, B.cb, B.area, B.tol2, B.max_iter, B.sc,
+                        B.counters + kCntMean, B.partials);
+        __syncthreads();
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * kCellWaves) void kb_cg_init(const BatchInst* inst,
+                                                              ItemList list) {
+    __shared__ YFaces<N, double> lds;
+    DG_FOR_ITEMS(list) {
+        cg_init_body<N>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k, B.w_in,
+                        B.pa, B.pb, B.ca, B.cb, B.x, B.r, B.sc,
+                        B.counters + kCntInit, B.partials, lds);
+        __syncthreads();
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * kCellWaves) void kb_cg_dir(const BatchInst* inst,
+                                                             ItemList list,
+                                                             int parity) {
+    __shared__ YFaces<N, double> lds;
+    DG_FOR_ITEMS(list) {
+        cg_dir_body<N, double>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
+                               B.r, parity ? B.p1 : B.p0, parity ? B.p0 : B.p1,
+                               B.x, B.sc, B.counters + kCntDir, B.partials, lds);
+        __syncthreads();
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * kCellWaves) void kb_cg_res(const BatchInst* inst,
+                                                             ItemList list,
+                                                             int parity) {
+    __shared__ YFaces<N, double> lds;
+    DG_FOR_ITEMS(list) {
+        cg_res_body<N, double>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
+                               parity ? B.p0 : B.p1, B.r, B.sc,
+                               B.counters + kCntRes, B.partials, lds);
+        __syncthreads();
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kPwThreads) void kb_cg_finish(const BatchInst* inst,
+                                                           ItemList list) {
+    DG_FOR_ITEMS(list) {
+        cg_finish_body<N>(item_.b, B.nb_cells, B.g, B.k, B.x, B.p0, B.p1, B.psi,
+                          B.area, B.sc, B.counters + kCntFinish, B.partials);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kPwThreads) void kb_sub_mean(const BatchInst* inst,
+                                                          ItemList list) {
+    DG_FOR_ITEMS(list) {
+        sub_mean_body(item_.b, B.nb_elems, B.elems, B.psi, B.sc);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * kRowWaves) void kb_rhs(const BatchInst* inst,
+                                                         ItemList list) {
+    __shared__ RhsLds<N, kRowWaves, true> lds;
+    DG_FOR_ITEMS(list) {
+        rhs_body<N, kRowWaves, true>(item_.b, B.g, B.row_tilesX, B.row_nblocks,
+                                     B.k, B.psi, B.w_in, B.w_n, B.w_out, B.ra, lds);
+        __syncthreads();
+    }
+}
+
+#undef DG_FOR_ITEMS
+
+// ---------------------------------------------------------------------------
+// Host-side helpers
+// ---------------------------------------------------------------------------
+void fill_batch_geometry(BatchInst& b) {
+    const Geom& g = b.g;
+    CellLaunch cl(g);
+    b.cell_tilesX = cl.tilesX;
+    b.cell_nblocks = cl.nblocks;
+    switch (g.n) {
+        case 1: { RowLaunch<1, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
+        case 2: { RowLaunch<2, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
+        case 3: { RowLaunch<3, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
+        case 4: { RowLaunch<4, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
+        default: { RowLaunch<5, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
+    }
+    b.cells = (long)g.nx * g.ny;
+    b.rows = b.cells * g.n;
+    b.elems = b.rows * g.n;
+    b.nb_rows = pw_blocks(b.rows, pointwise_block_cap());
+    b.nb_cells = pw_blocks(b.cells, pointwise_block_cap());
+    b.nb_elems = pw_blocks(b.elems, pointwise_block_cap());
+}
+
+hipError_t launch_batch(int n, BatchKernel kind, const BatchInst* inst,
+                        const ItemList& list, int grid, int parity,
+                        hipStream_t s) {
+    const dim3 cell(64 * kCellWaves), row(64 * kRowWaves), pw(kPwThreads);
+    DG_DISPATCH_N(n, {
+        switch (kind) {
+            case BatchKernel::Mean:
+                hipLaunchKernelGGL((kb_cg_mean<NN>), dim3(grid), pw, 0, s, inst, list);
+                break;
+            case BatchKernel::Init:
+                hipLaunchKernelGGL((kb_cg_init<NN>), dim3(grid), cell, 0, s, inst, list);
+                break;
+            case BatchKernel::Dir:
+                hipLaunchKernelGGL((kb_cg_dir<NN>), dim3(grid), cell, 0, s, inst, list,
+                                   parity);
+                break;
+            case BatchKernel::Res:
+                hipLaunchKernelGGL((kb_cg_res<NN>), dim3(grid), cell, 0, s, inst, list,
+                                   parity);
+                break;
+            case BatchKernel::Finish:
+                hipLaunchKernelGGL((kb_cg_finish<NN>), dim3(grid), pw, 0, s, inst, list);
+                break;
+            case BatchKernel::SubMean:
+                hipLaunchKernelGGL(kb_sub_mean, dim3(grid), pw, 0, s, inst, list);
+                break;
+            case BatchKernel::Rhs:
+                hipLaunchKernelGGL((kb_rhs<NN>), dim3(grid), row, 0, s, inst, list);
+                break;
+        }
+    });
+    return hipGetLastError();
+}
+
+}  // namespace dgk

@@ -1,293 +1,19 @@
-// LDG Laplacian and conjugate-gradient kernels (cell per lane).
-//
-// A lane holds all n*n nodal values of one cell in registers; a wave holds
-// 64 consecutive cells of one cell row, a workgroup kCellWaves consecutive
-// rows (a 64 x kCellWaves tile).  Each 1D operator couples a cell to its
-// neighbours only through one scalar per node row (x) or column (y) -- the
-// rank-one face blocks of the LDG second derivative (Sec. 6, built from the
-// one-sided variants of Sec. 3 eq. discrete_derivative) -- so:
-//   * x face scalars come from lanes +-1 by cross-lane shuffles,
-//   * y face scalars come from waves +-1 through LDS (one barrier),
-//   * only the edge lanes / edge waves of a tile load a halo cell.
-//
-// The CG vectors x, r, p live in a lane-interleaved layout ("L64"): cells
-// are grouped by 64 along x and stored node-major inside a group,
-//   element (cy, cx, node e) at ((cy * G + cx / 64) * n*n + e) * 64 + cx % 64,
-// G = ceil(nx / 64), so every wave-wide load or store of one node touches
-// 512 contiguous bytes.  Fields that cross the library boundary (omega, the
-// guess, psi) keep the canonical [cy][cx][j][i] layout and are converted at
-// the start and the end of a solve.
-#include "dg_device.h"
+// Single-instance launches of the LDG Laplacian and CG kernels (cell per
+// lane; the device code and its layout conventions are in cg_body.h).  One
+// block per 64 x kCellWaves tile; block b processes tile xcd_tile(b).
+#include "cg_body.h"
 #include "dg_launch.h"
 
 namespace dgk {
 
-constexpr int kCellWaves = 8;   // tile = 64 x 8 cells, 512 threads
-
-struct CellRef {
-    long canon;   // canonical offset of node 0 (node e at +e)
-    long l64;     // L64 offset of node 0 (node e at +64 e)
-};
-
-struct CellCtx {
-    int lane, wave;
-    bool active;                   // this lane's cell lies in the grid
-    bool xin_r, xin_l;             // x neighbour held by lane +-1
-    bool yin_u, yin_d;             // y neighbour row held by wave +-1 (uniform)
-    CellRef self, r, l, u, d;
-};
-
-template <int N>
-__device__ __forceinline__ CellRef cell_ref(const Geom& g, int G, int cx, int cy) {
-    CellRef c;
-    c.canon = ((long)cy * g.nx + cx) * (N * N);
-    c.l64 = ((long)cy * G + (cx >> 6)) * (N * N * 64) + (cx & 63);
-    return c;
-}
-
-template <int N>
-__device__ __forceinline__ CellCtx make_cell_ctx(const Geom& g, int tilesX,
-                                                 int nblocks) {
-    CellCtx c;
-    c.lane = threadIdx.x & 63;
-    c.wave = threadIdx.x >> 6;
-    const int t = xcd_tile(nblocks);
-    const int ty = t / tilesX, tx = t - ty * tilesX;
-    const int cx = tx * 64 + c.lane;
-    const int cy = ty * kCellWaves + c.wave;
-    c.active = cx < g.nx && cy < g.ny;
-    const int cxa = c.active ? cx : 0, cya = c.active ? cy : 0;
-    const int cxr = (cxa + 1 < g.nx) ? cxa + 1 : 0;
-    const int cxl = (cxa > 0) ? cxa - 1 : g.nx - 1;
-    const int cyu = (cya + 1 < g.ny) ? cya + 1 : 0;
-    const int cyd = (cya > 0) ? cya - 1 : g.ny - 1;
-    c.xin_r = c.lane < 63 && cx + 1 < g.nx;
-    c.xin_l = c.lane > 0;
-    c.yin_u = c.wave + 1 < kCellWaves && cy + 1 < g.ny;
-    c.yin_d = c.wave > 0;
-    const int G = tilesX;
-    c.self = cell_ref<N>(g, G, cxa, cya);
-    c.r = cell_ref<N>(g, G, cxr, cya);
-    c.l = cell_ref<N>(g, G, cxl, cya);
-    c.u = cell_ref<N>(g, G, cxa, cyu);
-    c.d = cell_ref<N>(g, G, cxa, cyd);
-    return c;
-}
-
-template <int N, class T>
-__device__ __forceinline__ void ld_canon(const T* __restrict__ f, const CellRef& c,
-                                         T (&u)[N * N]) {
-#pragma unroll
-    for (int e = 0; e < N * N; ++e) u[e] = f[c.canon + e];
-}
-
-template <int N, class T>
-__device__ __forceinline__ void st_canon(T* __restrict__ f, const CellRef& c,
-                                         const T (&u)[N * N]) {
-#pragma unroll
-    for (int e = 0; e < N * N; ++e) f[c.canon + e] = u[e];
-}
-
-template <int N, class T>
-__device__ __forceinline__ void ld_l64(const T* __restrict__ f, const CellRef& c,
-                                       T (&u)[N * N]) {
-#pragma unroll
-    for (int e = 0; e < N * N; ++e) u[e] = f[c.l64 + 64 * e];
-}
-
-template <int N, class T>
-__device__ __forceinline__ void st_l64(T* __restrict__ f, const CellRef& c,
-                                       const T (&u)[N * N]) {
-#pragma unroll
-    for (int e = 0; e < N * N; ++e) f[c.l64 + 64 * e] = u[e];
-}
-
-// Face scalars of a cell u (n x n, [j][i]) along x for node row j and along
-// y for node column i, with weights w.
-template <int N, class T>
-__device__ __forceinline__ T xdot(const T (&u)[N * N], int j, const T* w) {
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) s += w[i] * u[j * N + i];
-    return s;
-}
-
-template <int N, class T>
-__device__ __forceinline__ T ydot(const T (&u)[N * N], int i, const T* w) {
-    T s = 0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) s += w[k] * u[k * N + i];
-    return s;
-}
-
-// LDS for the y face scalars of one tile: [wave][face][i][lane]
-template <int N, class T>
-struct YFaces {
-    T v[kCellWaves * 2 * N * 64];
-};
-
-// Lap_h u for this lane's cell.  `src(ref, out)` evaluates the field on a
-// halo cell; the own cell's values are passed in u.  Every thread of the
-// block must call it (one barrier).
-template <int N, class T, class Src>
-__device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
-                                         const Src& src, const T (&u)[N * N],
-                                         YFaces<N, T>& lds, T (&out)[N * N]) {
-    T hR[N], hL[N], hU[N], hD[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) hR[m] = hL[m] = hU[m] = hD[m] = 0;
-    if (c.active && !c.yin_u) {
-        T h[N * N];
-        src(c.u, h);
-#pragma unroll
-        for (int i = 0; i < N; ++i) hU[i] = ydot<N>(h, i, k.lR);
-    }
-    if (c.active && !c.yin_d) {
-        T h[N * N];
-        src(c.d, h);
-#pragma unroll
-        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, k.lL);
-    }
-    if (c.active && !c.xin_r) {
-        T h[N * N];
-        src(c.r, h);
-#pragma unroll
-        for (int j = 0; j < N; ++j) hR[j] = xdot<N>(h, j, k.lR);
-    }
-    if (c.active && !c.xin_l) {
-        T h[N * N];
-        src(c.l, h);
-#pragma unroll
-        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lL);
-    }
-    // publish this cell's y face scalars
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        lds.v[((c.wave * 2 + 0) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lR);
-        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lL);
-    }
-    // x face scalars from the neighbouring lanes
-    T fR[N], fL[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const T a = __shfl(xdot<N>(u, j, k.lR), c.lane + 1);
-        const T b = __shfl(xdot<N>(u, j, k.lL), c.lane - 1);
-        fR[j] = c.xin_r ? a : hR[j];
-        fL[j] = c.xin_l ? b : hL[j];
-    }
-    __syncthreads();
-    T fU[N], fD[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        fU[i] = c.yin_u ? lds.v[(((c.wave + 1) * 2 + 0) * N + i) * 64 + c.lane] : hU[i];
-        fD[i] = c.yin_d ? lds.v[(((c.wave - 1) * 2 + 1) * N + i) * 64 + c.lane] : hD[i];
-    }
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T lx = k.eR[i] * fR[j] + k.eL[i] * fL[j];
-            T ly = k.eR[j] * fU[i] + k.eL[j] * fD[i];
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                lx += k.L0[i * N + m] * u[j * N + m];
-                ly += k.L0[j * N + m] * u[m * N + i];
-            }
-            out[j * N + i] = lx * k.ihx2 + ly * k.ihy2;
-        }
-}
-
-// <a, b>_W over one cell, accumulated in FP64
-template <int N, class T>
-__device__ __forceinline__ double wdot_cell(const OpConst<T>& k, const T (&a)[N * N],
-                                            const T (&b)[N * N]) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        double r = 0.0;
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            r += (double)k.w[i] * ((double)a[j * N + i] * (double)b[j * N + i]);
-        s += r * (double)k.w[j];
-    }
-    return s * k.wq;
-}
-
-template <int N, class T>
-struct SrcCanon {                       // u = f (canonical layout)
-    const T* f;
-    __device__ void operator()(const CellRef& c, T (&u)[N * N]) const { ld_canon<N>(f, c, u); }
-};
-
-template <int N, class T>
-struct SrcL64 {                         // u = f (L64 layout)
-    const T* f;
-    __device__ void operator()(const CellRef& c, T (&u)[N * N]) const { ld_l64<N>(f, c, u); }
-};
-
-template <int N, class T>
-struct SrcDirection {                   // p = r (first) or r + beta p_old, L64
-    const T* r;
-    const T* p;
-    T beta;
-    bool first;
-    __device__ void operator()(const CellRef& c, T (&u)[N * N]) const {
-        ld_l64<N>(r, c, u);
-        if (!first) {
-            T q[N * N];
-            ld_l64<N>(p, c, q);
-#pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] += beta * q[e];
-        }
-    }
-};
-
-template <int N>
-struct SrcGuess {                       // x0 = ca pa + cb pb - mean, canonical
-    const double* pa;
-    const double* pb;
-    double ca, cb, m;
-    __device__ void operator()(const CellRef& c, double (&u)[N * N]) const {
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) u[e] = -m;
-        if (ca != 0.0) {
-            double a[N * N];
-            ld_canon<N>(pa, c, a);
-#pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] += ca * a[e];
-        }
-        if (cb != 0.0) {
-            double b[N * N];
-            ld_canon<N>(pb, c, b);
-#pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] += cb * b[e];
-        }
-    }
-};
-
-template <int N, class T>
-__device__ __forceinline__ void zero_cell(T (&u)[N * N]) {
-#pragma unroll
-    for (int e = 0; e < N * N; ++e) u[e] = 0;
-}
-
-// out = Lap_h u (canonical layout in and out)
 template <int N>
 __global__ __launch_bounds__(64 * kCellWaves) void k_laplace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ u, double* __restrict__ out) {
     __shared__ YFaces<N, double> lds;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks);
-    SrcCanon<N, double> src{u};
-    double v[N * N], lap[N * N];
-    if (c.active) src(c.self, v);
-    else zero_cell<N>(v);
-    lap_cell<N>(c, k, src, v, lds, lap);
-    if (c.active) st_canon<N>(out, c.self, lap);
+    laplace_body<N>(blockIdx.x, g, tilesX, nblocks, k, u, out, lds);
 }
 
-// CG setup (stencil part): x0 = guess - mean(guess) (to L64);
-// r0 = (omega - mean(omega)) + Lap_h x0 (to L64); partials <r0,r0>_W, <b,b>_W.
 template <int N>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_init(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
@@ -296,155 +22,29 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cg_init(
     double* __restrict__ x, double* __restrict__ r, CgScalars* sc,
     unsigned* counter, double* partials) {
     __shared__ YFaces<N, double> lds;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks);
-    SrcGuess<N> src{pa, pb, ca, cb, sc->mean_guess};
-    const double mo = sc->mean_omega;
-    double x0[N * N], lap[N * N];
-    if (c.active) src(c.self, x0);
-    else zero_cell<N>(x0);
-    lap_cell<N>(c, k, src, x0, lds, lap);
-    double part[2] = {0.0, 0.0};
-    if (c.active) {
-        double b[N * N];
-        ld_canon<N>(omega, c.self, b);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) {
-            b[e] -= mo;
-            lap[e] += b[e];          // r0
-        }
-        st_l64<N>(x, c.self, x0);
-        st_l64<N>(r, c.self, lap);
-        part[0] = wdot_cell<N>(k, lap, lap);
-        part[1] = wdot_cell<N>(k, b, b);
-    }
-    double tot[2];
-    if (reduce_last<2, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        sc->rr = tot[0];
-        sc->bb = tot[1];
-        sc->first = 1;
-        sc->iter = 0;
-        sc->pending = 0;
-        sc->breakdown = 0;
-        // b at the rounding level of the mean removal counts as zero
-        if (tot[1] <= sc->zero_tol2 * sc->ww) {
-            sc->zero = 1;
-            sc->done = 1;
-            sc->converged = 1;
-        } else if (tot[0] <= sc->tol2 * tot[1]) {
-            sc->done = 1;
-            sc->converged = 1;
-        } else if (sc->max_iter <= 0) {
-            sc->done = 1;
-        }
-    }
+    cg_init_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, pa, pb, ca, cb, x,
+                    r, sc, counter, partials, lds);
 }
 
-// CG iteration, first half (L64 vectors):
-//   x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};  q = A p_k;
-//   alpha_k = <r,r>_W / <p_k, q>_W.
-// p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
-// neighbouring tiles while p_k is written.
 template <int N, class T>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_dir(
     Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ r,
     const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ x,
     CgScalars* sc, unsigned* counter, double* partials) {
-    if (sc->done) return;
     __shared__ YFaces<N, T> lds;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks);
-    const bool first = sc->first != 0;
-    const T alpha = (T)sc->alpha;
-    SrcDirection<N, T> src{r, pin, (T)sc->beta, first};
-    T p[N * N], q[N * N];
-    if (c.active) {
-        ld_l64<N>(r, c.self, p);
-        if (!first) {
-            T po[N * N], xv[N * N];
-            ld_l64<N>(pin, c.self, po);
-            ld_l64<N>(x, c.self, xv);
-#pragma unroll
-            for (int e = 0; e < N * N; ++e) {
-                xv[e] += alpha * po[e];
-                p[e] += src.beta * po[e];
-            }
-            st_l64<N>(x, c.self, xv);
-        }
-    } else {
-        zero_cell<N>(p);
-    }
-    lap_cell<N>(c, k, src, p, lds, q);
-    double part[1] = {0.0};
-    if (c.active) {
-        st_l64<N>(pout, c.self, p);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) q[e] = -q[e];
-        part[0] = wdot_cell<N>(k, p, q);
-    }
-    double tot[1];
-    if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        sc->pq = tot[0];
-        sc->first = 0;
-        if (tot[0] > 0.0 && tot[0] == tot[0]) {
-            sc->alpha = sc->rr / tot[0];
-        } else {  // breakdown (or non-finite data): stop, x is current
-            sc->done = 1;
-            sc->breakdown = 1;
-            sc->pending = 0;
-        }
-    }
+    cg_dir_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, r, pin, pout, x, sc,
+                      counter, partials, lds);
 }
 
-// CG iteration, second half: q = A p_k; r -= alpha q; beta = <r,r>new/<r,r>;
-// convergence test ||r||_W^2 <= tol^2 ||b||_W^2.
 template <int N, class T>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_res(
     Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ p,
     T* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
-    if (sc->done) return;
     __shared__ YFaces<N, T> lds;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks);
-    const T alpha = (T)sc->alpha;
-    SrcL64<N, T> src{p};
-    T pv[N * N], q[N * N], rv[N * N];
-    if (c.active) {
-        src(c.self, pv);
-        ld_l64<N>(r, c.self, rv);
-    } else {
-        zero_cell<N>(pv);
-    }
-    lap_cell<N>(c, k, src, pv, lds, q);   // q = Lap p = -A p
-    double part[1] = {0.0};
-    if (c.active) {
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) rv[e] += alpha * q[e];
-        st_l64<N>(r, c.self, rv);
-        part[0] = wdot_cell<N>(k, rv, rv);
-    }
-    double tot[1];
-    if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        const double rrn = tot[0];
-        sc->beta = rrn / sc->rr;
-        sc->rr = rrn;
-        sc->iter += 1;
-        if (rrn <= sc->tol2 * sc->bb) {
-            sc->done = 1;
-            sc->converged = 1;
-            sc->pending = 1;
-        } else if (sc->iter >= sc->max_iter || !(rrn == rrn)) {
-            sc->done = 1;
-            sc->pending = 1;
-            if (!(rrn == rrn)) sc->breakdown = 1;
-        }
-    }
+    cg_res_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, p, r, sc, counter,
+                      partials, lds);
 }
 
-// Mixed precision, outer step: r64 = (omega - mean(omega)) + Lap_h psi in
-// FP64 (psi, omega canonical); stores r32 = float(r64) and e32 = 0 (L64) for
-// the inner solve; partials <r64,r64>, <b,b>, <r32,r32>.  The last block
-// decides outer convergence and initialises the inner CG scalars.
 template <int N>
 __global__ __launch_bounds__(64 * kCellWaves) void k_mixed_residual(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
@@ -453,72 +53,14 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_mixed_residual(
     int inner_max, CgScalars* outer, CgScalars* inner, unsigned* counter,
     double* partials) {
     __shared__ YFaces<N, double> lds;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks);
-    SrcCanon<N, double> src{psi};
-    const double mo = outer->mean_omega;
-    double v[N * N], lap[N * N];
-    if (c.active) src(c.self, v);
-    else zero_cell<N>(v);
-    lap_cell<N>(c, k, src, v, lds, lap);
-    double part[3] = {0.0, 0.0, 0.0};
-    if (c.active) {
-        double b[N * N], rd[N * N];
-        float rf[N * N], zf[N * N];
-        ld_canon<N>(omega, c.self, b);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) {
-            b[e] -= mo;
-            lap[e] += b[e];
-            rf[e] = (float)lap[e];
-            rd[e] = (double)rf[e];
-            zf[e] = 0.0f;
-        }
-        st_l64<N>(r32, c.self, rf);
-        st_l64<N>(e32, c.self, zf);
-        part[0] = wdot_cell<N>(k, lap, lap);
-        part[1] = wdot_cell<N>(k, b, b);
-        part[2] = wdot_cell<N>(k, rd, rd);
-    }
-    double tot[3];
-    if (reduce_last<3, 64 * kCellWaves>(part, partials, counter, nblocks, tot) &&
-        threadIdx.x == 0) {
-        outer->rr = tot[0];
-        outer->bb = tot[1];
-        outer->iter += 1;
-        const bool zero = tot[1] <= outer->zero_tol2 * outer->ww;
-        const bool ok = zero || tot[0] <= outer->tol2 * tot[1];
-        outer->converged = ok ? 1 : 0;
-        outer->zero = zero ? 1 : 0;
-        inner->rr = tot[2];
-        inner->bb = tot[2];
-        inner->tol2 = inner_tol2;
-        inner->max_iter = inner_max;
-        inner->alpha = 0.0;
-        inner->beta = 0.0;
-        inner->first = 1;
-        inner->iter = 0;
-        inner->pending = 0;
-        inner->zero = 0;
-        inner->breakdown = 0;
-        inner->converged = 0;
-        inner->done = (ok || tot[2] == 0.0 || inner_max <= 0) ? 1 : 0;
-    }
+    mixed_residual_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, psi, r32,
+                           e32, inner_tol2, inner_max, outer, inner, counter,
+                           partials, lds);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-namespace {
-struct CellLaunch {
-    int tilesX, tilesY, nblocks;
-    explicit CellLaunch(const Geom& g) {
-        tilesX = (g.nx + 63) / 64;
-        tilesY = (g.ny + kCellWaves - 1) / kCellWaves;
-        nblocks = tilesX * tilesY;
-    }
-};
-}  // namespace
-
 int cell_blocks(const Geom& g) { return CellLaunch(g).nblocks; }
 
 hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,

@@ -13,8 +13,7 @@ constexpr int kPwThreads = 256;
 // Block index -> tile index such that the blocks the dispatcher sends to one
 // XCD (block b goes to XCD b mod 8) get a contiguous run of tiles: halo
 // reads of neighbouring tiles then hit the same L2.
-__device__ __forceinline__ int xcd_tile(int nblocks) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
     const int xcd = b & 7, idx = b >> 3;
     const int q = nblocks >> 3, r = nblocks & 7;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
@@ -44,11 +43,13 @@ __device__ __forceinline__ void store_vec(T* __restrict__ f, long off,
 // write-back or invalidate is needed because only atomics carry data
 // between blocks; results for the next kernel are ordinary stores made
 // visible by the kernel boundary.
-// Returns true in the last block, where tot[] holds the grid-wide sums.
+// b is the block's index among the nblocks blocks of this reduction (its
+// partial slot).  Returns true in the last block, where tot[] holds the sums.
 // ---------------------------------------------------------------------------
 template <int NV, int NT>
 __device__ bool reduce_last(double (&v)[NV], double* partials,
-                            unsigned* counter, int nblocks, double (&tot)[NV]) {
+                            unsigned* counter, int nblocks, int b,
+                            double (&tot)[NV]) {
     __shared__ double red[(NT / 64) * NV];
     __shared__ int is_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -65,7 +66,7 @@ __device__ bool reduce_last(double (&v)[NV], double* partials,
         for (int k = 0; k < NV; ++k) {
             double s = 0.0;
             for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
-            __hip_atomic_store(&partials[(long)blockIdx.x * NV + k], s,
+            __hip_atomic_store(&partials[(long)b * NV + k], s,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __builtin_amdgcn_s_waitcnt(0);   // partials performed before the ticket
@@ -78,10 +79,10 @@ __device__ bool reduce_last(double (&v)[NV], double* partials,
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += NT)
+    for (int q = threadIdx.x; q < nblocks; q += NT)
 #pragma unroll
         for (int k = 0; k < NV; ++k)
-            acc[k] += __hip_atomic_load(&partials[(long)b * NV + k],
+            acc[k] += __hip_atomic_load(&partials[(long)q * NV + k],
                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int k = 0; k < NV; ++k)

@@ -1,0 +1,253 @@
+// Fused bracket / right-hand-side kernel (row per lane).
+//
+// A lane holds one node row (cell, j) of a field; a wave covers S = 64/n
+// consecutive cells of one cell row (lane = slot * n + j) and a workgroup
+// WAVES consecutive cell rows.  The outer ring of slots and waves is halo:
+// halo lanes load and compute like the others but never store, so every
+// interior cell sees its full 3 x 3 cell neighbourhood (the bracket needs
+// the x neighbours' y derivatives and vice versa).  Tiles of (S-2) x
+// (WAVES-2) interior cells cover the grid; indices wrap periodically
+// (Sec. 3 periodic closure).  x operators use one cross-lane shuffle per
+// neighbour (rank-one face blocks of Sec. 4.2 eq. discrete_der); y
+// operators stage rows in LDS, evaluate columns, and transpose back.
+#pragma once
+
+#include "dg_device.h"
+
+namespace dgk {
+
+template <int N, int WAVES>
+struct Tile {
+    static constexpr int S = 64 / N;          // cell slots per wave
+    static constexpr int TX = S - 2;          // interior cells per tile in x
+    static constexpr int TY = WAVES - 2;      // interior cells per tile in y
+    // LDS stride of one cell: odd for even n so that lanes of different
+    // cells fall into different banks
+    static constexpr int CS = (N % 2 == 0) ? N * N + 1 : N * N;
+    static constexpr int LDS_FIELD = WAVES * S * CS;
+};
+
+constexpr int kRowWaves = 8;
+
+template <int N, int WAVES>
+struct Ctx {
+    int lane, wave, s, j;
+    bool active;      // lane holds a node row
+    bool interior;    // lane's cell is inside the tile and the grid: stores
+    long row;         // element index of this thread's row start
+    int slot;         // wave * S + s (LDS cell slot)
+};
+
+template <int N, int WAVES>
+__device__ __forceinline__ Ctx<N, WAVES> make_ctx(const Geom& g, int tilesX,
+                                                  int nblocks, int b) {
+    using TL = Tile<N, WAVES>;
+    Ctx<N, WAVES> c;
+    c.lane = threadIdx.x & 63;
+    c.wave = threadIdx.x >> 6;
+    c.s = c.lane / N;
+    c.j = c.lane - c.s * N;
+    c.active = c.s < TL::S;
+    const int t = xcd_tile(b, nblocks);
+    const int ty = t / tilesX, tx = t - ty * tilesX;
+    const int cx = tx * TL::TX + c.s - 1;
+    const int cy = ty * TL::TY + c.wave - 1;
+    c.interior = c.active && c.s >= 1 && c.s <= TL::TX && c.wave >= 1 &&
+                 c.wave <= TL::TY && cx < g.nx && cy < g.ny;
+    int gx = cx % g.nx;
+    if (gx < 0) gx += g.nx;
+    int gy = cy % g.ny;
+    if (gy < 0) gy += g.ny;
+    const long cell = c.active ? (long)gy * g.nx + gx : 0;
+    c.row = (cell * N + c.j) * N;
+    c.slot = c.wave * TL::S + (c.active ? c.s : TL::S - 1);
+    return c;
+}
+
+// One 1D operator along x on this thread's row:
+//   res = scale * (A0 u + eR (tR . u_right) + eL (tL . u_left))
+template <int N, class T>
+__device__ __forceinline__ void row_op(const T (&u)[N], int lane,
+                                       const T* A0, const T* eR, const T* tR,
+                                       const T* eL, const T* tL, T scale,
+                                       T (&res)[N]) {
+    T dR = 0, dL = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        dR += tR[k] * u[k];
+        dL += tL[k] * u[k];
+    }
+    // the right neighbour cell is N lanes up, the left one N lanes down;
+    // lanes of the edge slots receive wrapped values but are halo
+    const T fromR = __shfl(dR, lane + N);
+    const T fromL = __shfl(dL, lane - N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        T a = eR[i] * fromR + eL[i] * fromL;
+#pragma unroll
+        for (int k = 0; k < N; ++k) a += A0[i * N + k] * u[k];
+        res[i] = a * scale;
+    }
+}
+
+// One 1D operator along y evaluated on column j of this thread's cell from
+// rows staged in LDS; res[k] is the value at node (k, j).  The halo waves
+// read clamped (wrong but in-bounds) neighbours and are never stored.
+template <int N, int WAVES, class T>
+__device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
+                                       const T* A0, const T* eR, const T* tR,
+                                       const T* eL, const T* tL, T scale,
+                                       T (&res)[N]) {
+    using TL = Tile<N, WAVES>;
+    const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
+    const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
+    const T* c0 = lds + c.slot * TL::CS + c.j;
+    const T* cu = lds + up * TL::CS + c.j;
+    const T* cd = lds + dn * TL::CS + c.j;
+    T col[N];
+    T du = 0, dd = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        col[k] = c0[k * N];
+        du += tR[k] * cu[k * N];
+        dd += tL[k] * cd[k * N];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        T a = eR[k] * du + eL[k] * dd;
+#pragma unroll
+        for (int m = 0; m < N; ++m) a += A0[k * N + m] * col[m];
+        res[k] = a * scale;
+    }
+}
+
+template <int N, int WAVES, class T>
+__device__ __forceinline__ void lds_put_row(T* lds, const Ctx<N, WAVES>& c,
+                                            const T (&u)[N]) {
+    if (c.active) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[c.slot * Tile<N, WAVES>::CS + c.j * N + i] = u[i];
+    }
+}
+
+template <int N, int WAVES, class T>
+__device__ __forceinline__ void lds_put_col(T* lds, const Ctx<N, WAVES>& c,
+                                            const T (&v)[N]) {
+    if (c.active) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[c.slot * Tile<N, WAVES>::CS + k * N + c.j] = v[k];
+    }
+}
+
+template <int N, int WAVES, class T>
+__device__ __forceinline__ void lds_get_row(const T* lds, const Ctx<N, WAVES>& c,
+                                            T (&u)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = lds[c.slot * Tile<N, WAVES>::CS + c.j * N + i];
+}
+
+// Bracket and right-hand side.
+//   J = scale * (c0 J++ + Dx(c1 f Dy g - c2 Dy f g) + Dy(c2 Dx f g - c1 f Dx g))
+// (c0, c1, c2, scale) = (1, 1, 1, 1/3) gives (J++ + J+x + Jx+)/3 (Sec. 2
+// eq. J); one of them alone gives a single form.  With VISC the kernel
+// forms R = -J(f, g) + D Lap_h g and stores a * wn + b * (g + dt R)
+// (SSP-RK3 stage combination; wn may be null when a == 0).
+
+template <int N, int WAVES, bool VISC>
+struct RhsLds {
+    double A[Tile<N, WAVES>::LDS_FIELD];
+    double B[Tile<N, WAVES>::LDS_FIELD];
+    double C[VISC ? Tile<N, WAVES>::LDS_FIELD : 1];
+};
+
+template <int N, int WAVES, bool VISC>
+__device__ __forceinline__ void rhs_body(
+    int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
+    const double* __restrict__ f, const double* __restrict__ gg,
+    const double* __restrict__ wn, double* __restrict__ out, const RhsArgs& ra,
+    RhsLds<N, WAVES, VISC>& L) {
+    double* lA = L.A;
+    double* lB = L.B;
+    double* lC = L.C;
+    const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks, b);
+
+    double F[N], G[N];
+    load_vec(f, c.row, F);
+    load_vec(gg, c.row, G);
+
+    double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
+    row_op(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF);
+    row_op(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG);
+    if (VISC) row_op(G, c.lane, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihx2, LxG);
+
+    lds_put_row(lA, c, F);
+    lds_put_row(lB, c, G);
+    __syncthreads();
+    {
+        double cF[N], cG[N], cL[N];
+        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
+        col_op(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
+        if (VISC) col_op(lB, c, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihy2, cL);
+        __syncthreads();
+        lds_put_col(lA, c, cF);
+        lds_put_col(lB, c, cG);
+        if (VISC) lds_put_col(lC, c, cL);
+    }
+    __syncthreads();
+    lds_get_row(lA, c, DyF);
+    lds_get_row(lB, c, DyG);
+    if (VISC) lds_get_row(lC, c, LyG);
+    __syncthreads();
+
+    double J[N], A[N], B[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        J[i] = ra.c0 * (DxF[i] * DyG[i] - DyF[i] * DxG[i]);
+        A[i] = ra.c1 * (F[i] * DyG[i]) - ra.c2 * (DyF[i] * G[i]);
+        B[i] = ra.c2 * (DxF[i] * G[i]) - ra.c1 * (F[i] * DxG[i]);
+    }
+    double DxA[N], DyB[N];
+    row_op(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA);
+    lds_put_row(lA, c, B);
+    __syncthreads();
+    {
+        double cb[N];
+        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cb);
+        __syncthreads();
+        lds_put_col(lA, c, cb);
+    }
+    __syncthreads();
+    lds_get_row(lA, c, DyB);
+
+    if (!c.interior) return;
+    double o[N];
+    if (VISC) {
+        double wnr[N];
+        if (ra.a != 0.0) load_vec(wn, c.row, wnr);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double Jv = ra.scale * (J[i] + DxA[i] + DyB[i]);
+            const double R = ra.D * (LxG[i] + LyG[i]) - Jv;
+            const double s = ra.b * (G[i] + ra.dt * R);
+            o[i] = (ra.a != 0.0) ? ra.a * wnr[i] + s : s;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] = ra.scale * (J[i] + DxA[i] + DyB[i]);
+    }
+    store_vec(out, c.row, o);
+}
+
+
+template <int N, int WAVES>
+struct RowLaunch {
+    using TL = Tile<N, WAVES>;
+    int tilesX, tilesY, nblocks;
+    __host__ __device__ explicit RowLaunch(const Geom& g) {
+        tilesX = (g.nx + TL::TX - 1) / TL::TX;
+        tilesY = (g.ny + TL::TY - 1) / TL::TY;
+        nblocks = tilesX * tilesY;
+    }
+};
+
+}  // namespace dgk

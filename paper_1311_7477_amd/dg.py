@@ -92,6 +92,18 @@ def lib():
         "dg_invariants_dev": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "dg_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
         "dg_profile_read": (ctypes.c_int, [_vp, _dp]),
+        "dg_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+        "dg_batch_destroy": (None, [_vp]),
+        "dg_batch_attach": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_int)]),
+        "dg_batch_detach": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "dg_batch_member_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "dg_batch_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "dg_batch_rk_step": (ctypes.c_int, [_vp, ctypes.POINTER(CgOpts),
+                                            ctypes.POINTER(ctypes.c_int), _vp]),
+        "dg_batch_copy_psi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+        "dg_batch_time": (ctypes.c_double, [_vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -294,3 +306,56 @@ def invariants(grid: Grid, omega, psi, ws: Workspace):
     _check(lib().dg_invariants(grid.handle, _field(omega, grid, "omega"),
                                _field(psi, grid, "psi"), out, ws.handle, _stream()))
     return tuple(out)
+
+
+class Batch:
+    """Instances advanced together by batched persistent launches (see
+    dg_batch_* in include/dgark.h).  Members keep references to their grid
+    and omega tensor while attached."""
+
+    def __init__(self, capacity: int, use_graphs: bool = True):
+        h = _vp()
+        _check(lib().dg_batch_create(capacity, ctypes.byref(h)))
+        self._h, self.capacity = h, capacity
+        self.members = {}
+        _check(lib().dg_batch_use_graphs(h, 1 if use_graphs else 0))
+
+    def attach(self, grid: Grid, omega, dt: float, D: float, t0: float = 0.0) -> int:
+        slot = ctypes.c_int()
+        _check(lib().dg_batch_attach(self._h, grid.handle, _field(omega, grid, "omega"),
+                                     dt, D, t0, ctypes.byref(slot)))
+        self.members[slot.value] = (grid, omega)
+        return slot.value
+
+    def detach(self, slot: int):
+        _check(lib().dg_batch_detach(self._h, slot))
+        self.members.pop(slot, None)
+
+    def rk_step(self, opts: CgOpts = None):
+        """One SSP-RK3 step of every member; returns {slot: (iters stage 1..3)}
+        and whether every solve converged."""
+        it = (ctypes.c_int * (3 * self.capacity))()
+        rc = _check(lib().dg_batch_rk_step(self._h, ctypes.byref(cg_opts() if opts is None else opts),
+                                           it, _stream()), allow=(DG_E_NOCONV,))
+        return {s: tuple(it[3 * s:3 * s + 3]) for s in self.members}, rc == DG_OK
+
+    def psi(self, slot: int):
+        import torch
+        grid = self.members[slot][0]
+        out = torch.empty(grid.shape, dtype=torch.float64, device="cuda")
+        _check(lib().dg_batch_copy_psi(self._h, slot, _vp(out.data_ptr()), _stream()))
+        return out
+
+    def time(self, slot: int) -> float:
+        return lib().dg_batch_time(self._h, slot)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dg_batch_destroy(self._h)
+            self._h = None
+
+
+def batch_member_bytes(grid: Grid) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().dg_batch_member_bytes(grid.handle, ctypes.byref(b)))
+    return b.value
