@@ -109,7 +109,7 @@ template <int N, class T>
 __device__ __forceinline__ T xdot(const T (&u)[N * N], int j, const T* w) {
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) s += w[i] * u[j * N + i];
+    for (int i = 0; i < N; ++i) s = fmx(w[i], u[j * N + i], s);
     return s;
 }
 
@@ -117,7 +117,7 @@ template <int N, class T>
 __device__ __forceinline__ T ydot(const T (&u)[N * N], int i, const T* w) {
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) s += w[k] * u[k * N + i];
+    for (int k = 0; k < N; ++k) s = fmx(w[k], u[k * N + i], s);
     return s;
 }
 
@@ -187,14 +187,14 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     for (int j = 0; j < N; ++j)
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T lx = k.eR[i] * fR[j] + k.eL[i] * fL[j];
-            T ly = k.eR[j] * fU[i] + k.eL[j] * fD[i];
+            T lx = fmx(k.eR[i], fR[j], k.eL[i] * fL[j]);
+            T ly = fmx(k.eR[j], fU[i], k.eL[j] * fD[i]);
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                lx += k.L0[i * N + m] * u[j * N + m];
-                ly += k.L0[j * N + m] * u[m * N + i];
+                lx = fmx(k.L0[i * N + m], u[j * N + m], lx);
+                ly = fmx(k.L0[j * N + m], u[m * N + i], ly);
             }
-            out[j * N + i] = lx * k.ihx2 + ly * k.ihy2;
+            out[j * N + i] = fmx(lx, k.ihx2, ly * k.ihy2);
         }
 }
 
@@ -208,8 +208,8 @@ __device__ __forceinline__ double wdot_cell(const OpConst<T>& k, const T (&a)[N 
         double r = 0.0;
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            r += (double)k.w[i] * ((double)a[j * N + i] * (double)b[j * N + i]);
-        s += r * (double)k.w[j];
+            r = fmx((double)k.w[i], (double)a[j * N + i] * (double)b[j * N + i], r);
+        s = fmx(r, (double)k.w[j], s);
     }
     return s * k.wq;
 }
@@ -238,7 +238,7 @@ struct SrcDirection {                   // p = r (first) or r + beta p_old, L64
             T q[N * N];
             ld_l64<N>(p, c, q);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] += beta * q[e];
+            for (int e = 0; e < N * N; ++e) u[e] = fmx(beta, q[e], u[e]);
         }
     }
 };
@@ -255,13 +255,13 @@ struct SrcGuess {                       // x0 = ca pa + cb pb - mean, canonical
             double a[N * N];
             ld_canon<N>(pa, c, a);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] += ca * a[e];
+            for (int e = 0; e < N * N; ++e) u[e] = fmx(ca, a[e], u[e]);
         }
         if (cb != 0.0) {
             double b[N * N];
             ld_canon<N>(pb, c, b);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] += cb * b[e];
+            for (int e = 0; e < N * N; ++e) u[e] = fmx(cb, b[e], u[e]);
         }
     }
 };
@@ -366,8 +366,8 @@ __device__ __forceinline__ void cg_dir_body(
             ld_l64<N>(x, c.self, xv);
 #pragma unroll
             for (int e = 0; e < N * N; ++e) {
-                xv[e] += alpha * po[e];
-                p[e] += src.beta * po[e];
+                xv[e] = fmx(alpha, po[e], xv[e]);
+                p[e] = fmx(src.beta, po[e], p[e]);
             }
             st_l64<N>(x, c.self, xv);
         }
@@ -419,7 +419,7 @@ __device__ __forceinline__ void cg_res_body(
     double part[1] = {0.0};
     if (c.active) {
 #pragma unroll
-        for (int e = 0; e < N * N; ++e) rv[e] += alpha * q[e];
+        for (int e = 0; e < N * N; ++e) rv[e] = fmx(alpha, q[e], rv[e]);
         st_l64<N>(r, c.self, rv);
         part[0] = wdot_cell<N>(k, rv, rv);
     }

@@ -10,6 +10,16 @@ namespace dgk {
 
 constexpr int kPwThreads = 256;
 
+// Fused multiply-add written out: the library is compiled with
+// -ffp-contract=off, so every rounding is the one the source states and a
+// body computes bit-identical results in every kernel that inlines it.
+__device__ __forceinline__ double fmx(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fmx(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+
 // Block index -> tile index such that the blocks the dispatcher sends to one
 // XCD (block b goes to XCD b mod 8) get a contiguous run of tiles: halo
 // reads of neighbouring tiles then hit the same L2.

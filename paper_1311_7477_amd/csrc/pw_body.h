@@ -14,7 +14,7 @@ template <int N, class T>
 __device__ __forceinline__ double wrow(const OpConst<T>& k, int j, const double (&v)[N]) {
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) s += (double)k.w[i] * v[i];
+    for (int i = 0; i < N; ++i) s = fmx((double)k.w[i], v[i], s);
     return s * (double)k.w[j] * k.wq;
 }
 
@@ -98,7 +98,7 @@ __device__ __forceinline__ void cg_finish_body(int b, int nb, Geom g, const OpCo
             double a = 0.0;
             if (!zero) {
                 a = x[l64 + 64 * e];
-                if (pending) a += alpha * pl[l64 + 64 * e];
+                if (pending) a = fmx(alpha, pl[l64 + 64 * e], a);
             }
             v[e] = a;
         }
@@ -195,7 +195,7 @@ __device__ __forceinline__ void mixed_update_body(int b, int nb, Geom g, double*
 #pragma unroll
         for (int e = 0; e < N * N; ++e) {
             float c = e32[l64 + 64 * e];
-            if (pending) c += alpha * pl[l64 + 64 * e];
+            if (pending) c = fmx(alpha, pl[l64 + 64 * e], c);
             v[e] += (double)c;
         }
         store_vec(psi, cell * (N * N), v);

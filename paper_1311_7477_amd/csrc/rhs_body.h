@@ -74,8 +74,8 @@ __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
     T dR = 0, dL = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        dR += tR[k] * u[k];
-        dL += tL[k] * u[k];
+        dR = fmx(tR[k], u[k], dR);
+        dL = fmx(tL[k], u[k], dL);
     }
     // the right neighbour cell is N lanes up, the left one N lanes down;
     // lanes of the edge slots receive wrapped values but are halo
@@ -83,9 +83,9 @@ __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
     const T fromL = __shfl(dL, lane - N);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        T a = eR[i] * fromR + eL[i] * fromL;
+        T a = fmx(eR[i], fromR, eL[i] * fromL);
 #pragma unroll
-        for (int k = 0; k < N; ++k) a += A0[i * N + k] * u[k];
+        for (int k = 0; k < N; ++k) a = fmx(A0[i * N + k], u[k], a);
         res[i] = a * scale;
     }
 }
@@ -109,14 +109,14 @@ __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         col[k] = c0[k * N];
-        du += tR[k] * cu[k * N];
-        dd += tL[k] * cd[k * N];
+        du = fmx(tR[k], cu[k * N], du);
+        dd = fmx(tL[k], cd[k * N], dd);
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        T a = eR[k] * du + eL[k] * dd;
+        T a = fmx(eR[k], du, eL[k] * dd);
 #pragma unroll
-        for (int m = 0; m < N; ++m) a += A0[k * N + m] * col[m];
+        for (int m = 0; m < N; ++m) a = fmx(A0[k * N + m], col[m], a);
         res[k] = a * scale;
     }
 }
