@@ -82,6 +82,168 @@ def cpu_baseline(n, N, omega0, psi0, D, dt, iters_per_rhs):
     }
 
 
+def form_batch(args):
+    """Batched form: 64 instances with n uniform over {2..5}, N log-uniform
+    over [64, N_max], random spectra with peak k0 uniform over [4, 16]; the
+    same members stepped one by one with dg_rk_step and together in one
+    batch (persistent launches, graph replay).  Reports aggregate
+    cell-updates/s per RHS of both and checks bitwise equality."""
+    import numpy as np
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    rng = np.random.default_rng(2)
+    members = []
+    for _ in range(args.members):
+        n = int(rng.integers(2, 6))
+        N = int(round(math.exp(rng.uniform(math.log(64), math.log(args.N_max)))))
+        k0 = float(rng.uniform(4.0, 16.0))
+        w0, umax = inputs.random_spectrum(n, N, k0=k0, seed=int(rng.integers(1 << 30)),
+                                          return_umax=True)
+        members.append((n, N, w0, inputs.cfl_dt(n, N, umax, cfl=0.1)))
+    opts = dg.cg_opts(rtol=args.rtol)
+    cells = sum(N * N for (_, N, _, _) in members)
+    steps = args.steps
+
+    # one by one
+    singles = []
+    for (n, N, w0, dt) in members:
+        g = dg.Grid(n, N, N)
+        singles.append((g, dg.Workspace(g), dg.State(g), torch.from_numpy(w0).cuda(), dt))
+    for (g, ws, st, w, dt) in singles:            # warm-up step
+        dg.rk_step(g, w, st, ws, dt, args.D, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for (g, ws, st, w, dt) in singles:
+            dg.rk_step(g, w, st, ws, dt, args.D, opts)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+
+    # batched
+    batch = dg.Batch(len(members))
+    bw = []
+    for (n, N, w0, dt) in members:
+        g = dg.Grid(n, N, N)
+        w = torch.from_numpy(w0).cuda()
+        batch.attach(g, w, dt, args.D)
+        bw.append((g, w))
+    batch.rk_step(opts)                            # warm-up step (+ capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.rk_step(opts)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(bool(torch.equal(w, s[3])) for (g, w), s in zip(bw, singles))
+    rhs = 3 * steps
+    print(json.dumps({
+        "metric": "batched DG cell-updates/s per RHS (64 uneven instances)",
+        "value": cells * rhs / t_batch, "unit": "cell-updates/s",
+        "one_by_one_value": cells * rhs / t_single, "speedup": t_single / t_batch,
+        "bitwise_equal_to_one_by_one": same, "steps": steps, "warmup": 1,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.members} instances, n~U{{2..5}}, N log-uniform "
+                               f"[64,{args.N_max}], k0~U[4,16], D={args.D}, CFL 0.1, "
+                               f"CG rtol {args.rtol}, seed 2",
+                   "total_cells": cells, "graphs": True},
+    }), flush=True)
+
+
+def form_mixed(args):
+    """Mixed precision (FP32 inner CG, FP64 refinement) against the FP64 CG
+    on the double shear layer at n = 5: time per RHS and the difference of
+    the resulting vorticity and streamfunction."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    n, N = 5, args.N
+    w0, umax = inputs.double_shear_layer(n, N)
+    dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
+    res = {}
+    for name, prec in (("fp64", dg.DG_PREC_FP64), ("mixed", dg.DG_PREC_MIXED)):
+        g = dg.Grid(n, N, N)
+        ws, st = dg.Workspace(g, dg.DG_PREC_MIXED), dg.State(g)
+        w = torch.from_numpy(w0).cuda()
+        opts = dg.cg_opts(rtol=1e-10, precision=prec)
+        dg.rk_step(g, w, st, ws, dt, 5e-5, opts)           # warm-up step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for _ in range(args.steps):
+            its += dg.rk_step(g, w, st, ws, dt, 5e-5, opts).cg_iters
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) / (3 * args.steps), w, st.psi(), its)
+    e_w = ((res["mixed"][1] - res["fp64"][1]).norm() / res["fp64"][1].norm()).item()
+    e_p = ((res["mixed"][2] - res["fp64"][2]).norm() / res["fp64"][2].norm()).item()
+    print(json.dumps({
+        "metric": "mixed-precision CG: DG cell-updates/s per RHS",
+        "value": N * N / res["mixed"][0], "unit": "cell-updates/s",
+        "fp64_value": N * N / res["fp64"][0], "speedup": res["fp64"][0] / res["mixed"][0],
+        "rel_err_omega_vs_fp64": e_w, "rel_err_psi_vs_fp64": e_p,
+        "inner_iters_per_rhs_mixed": statistics.mean(res["mixed"][3]),
+        "iters_per_rhs_fp64": statistics.mean(res["fp64"][3]),
+        "steps": args.steps, "warmup": 1, "dtype": "f32 inner / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": f"double shear layer, n=5, {N}x{N}, D=5e-5, CFL 0.1, "
+                               "outer rtol 1e-10, inner relative 1e-5"},
+    }), flush=True)
+
+
+def form_serve(args):
+    """Serving: a seeded Poisson stream of requests (n uniform over {2..5},
+    N log-uniform, random spectra), continuous batching under an HBM budget;
+    latency percentiles, aggregate throughput and an alone-vs-mix check."""
+    import numpy as np
+    from paper_1311_7477_amd import dg, serve
+    reqs = serve.draw_requests(args.requests, seed=4, rate=args.rate,
+                               N_range=(32, args.N_max), steps=args.req_steps)
+    srv = serve.Server(capacity=64, opts=dg.cg_opts(rtol=1e-10))
+    t0 = time.perf_counter()
+    done = srv.run(reqs, log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
+    makespan = time.perf_counter() - t0
+    s = serve.summarize(done, makespan)
+    same = [bool(np.array_equal(r.result, serve.run_alone(r, srv.opts)))
+            for r in done[:4]]
+    s.update({
+        "metric": "served DG cell-updates/s (aggregate) with p50/p99 request latency",
+        "value": s["aggregate_cell_updates_per_s"], "unit": "cell-updates/s",
+        "max_concurrent": srv.max_active, "ticks": srv.ticks,
+        "alone_equals_mix_first4": same, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.requests} requests, Poisson rate {args.rate}/s, "
+                               f"n~U{{2..5}}, N log-uniform [32,{args.N_max}], "
+                               f"{args.req_steps} RK3 steps each, k0~U[4,16], CG rtol 1e-10, "
+                               "HBM budget 80% of free memory, seed 4"},
+    })
+    print(json.dumps(s), flush=True)
+
+
+def form_paper(args):
+    """The paper's timing shape (Table 1): one bracket evaluation, N = 100,
+    P = 1..4, FP64, beside the printed GTX 570 times (context only)."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    printed = {1: 0.05, 2: 0.26, 3: 0.71, 4: 1.47}
+    rows = []
+    for n in (1, 2, 3, 4):
+        g = dg.Grid(n, 100, 100)
+        f = torch.from_numpy(inputs.white_noise(n, 100, 100, 1)).cuda()
+        h = torch.from_numpy(inputs.white_noise(n, 100, 100, 2)).cuda()
+        out = torch.empty_like(f)
+        for _ in range(10):
+            dg.poisson_bracket(g, f, h, out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(200):
+            dg.poisson_bracket(g, f, h, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 200
+        rows.append({"P": n, "ms": ms, "paper_gtx570_ms": printed[n],
+                     "ratio": printed[n] / ms})
+    print(json.dumps({"metric": "bracket time, N=100 (Table 1 shape)", "unit": "ms",
+                      "rows": rows, "higher_is_better": False, "dtype": "f64",
+                      "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +257,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 plain 256 MiB device copies (torch copy_) whose "
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
+    ap.add_argument("--form", default="rhs",
+                    choices=["rhs", "batch", "mixed", "serve", "paper"],
+                    help="rhs: the headline metric (default); the others measure "
+                         "the batched, mixed-precision and served forms and the "
+                         "paper's bracket-timing shape")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--N-max", dest="N_max", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=16)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--req-steps", dest="req_steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the single-instance RHS is not "
@@ -102,13 +274,16 @@ def main():
               "domain-decomposition plan).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1311_7477_amd import dg, inputs
 
-    n, N = args.n, args.N
     torch.cuda.set_device(0)
+    if args.form != "rhs":
+        {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
+         "paper": form_paper}[args.form](args)
+        return
+    n, N = args.n, args.N
     if args.copy_calibration:
         src = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")   # 256 MiB
         dst = torch.empty_like(src)

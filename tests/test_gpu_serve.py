@@ -1,0 +1,66 @@
+"""Serving loop: requests that arrive while others run are admitted between
+steps (continuous batching), every result equals the same request run
+alone (bitwise, since a batch runs each instance with the stand-alone
+device code), and a small HBM budget forces queueing instead of failure."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def serve():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1311_7477_amd import dg, serve as _serve
+    dg.lib()
+    return _serve
+
+
+def _stream(serve, count=6, rate=50.0):
+    return serve.draw_requests(count, seed=4, rate=rate, N_range=(16, 48),
+                               k0_range=(2.0, 5.0), steps=3)
+
+
+def test_mixed_stream_equals_alone(serve):
+    from paper_1311_7477_amd import dg
+    opts = dg.cg_opts(rtol=1e-10)
+    reqs = _stream(serve)
+    srv = serve.Server(capacity=8, opts=opts)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert srv.max_active > 1            # requests overlapped on the device
+    for r in done:
+        alone = serve.run_alone(r, opts)
+        same = bool(np.array_equal(r.result, alone))
+        assert same, f"request {r.rid}: differs by {np.abs(r.result - alone).max():.3e}"
+        assert r.latency > 0 and r.admitted >= r.arrival
+    s = serve.summarize(done, max(r.finished for r in done))
+    assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+    assert s["aggregate_cell_updates_per_s"] > 0
+
+
+def test_small_budget_queues_requests(serve):
+    from paper_1311_7477_amd import dg
+    reqs = _stream(serve, count=4, rate=1000.0)
+    biggest = max(serve.member_bytes(r.n, r.N) for r in reqs)
+    srv = serve.Server(capacity=8, hbm_budget=biggest, opts=dg.cg_opts(rtol=1e-8))
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert srv.peak_used <= biggest      # the budget was never exceeded
+    assert srv.max_active < len(reqs)    # so some requests had to wait
+    # FIFO order under queueing
+    order = [r.rid for r in sorted(done, key=lambda r: r.admitted)]
+    assert order == sorted(order)
+
+
+def test_oversized_request_is_rejected(serve):
+    from paper_1311_7477_amd import dg
+    reqs = _stream(serve, count=2)
+    srv = serve.Server(capacity=2, hbm_budget=1024, opts=dg.cg_opts(rtol=1e-8))
+    done = srv.run(reqs)
+    assert done == [] and len(srv.rejected) == 2
+    assert all(math.isnan(r.finished) for r in reqs)
