@@ -164,20 +164,19 @@ int cg_loop(const Geom& geom, const OpConst<T>& k, T* x, T* r, T* p0, T* p1,
         if (m > chunk) m = chunk;
         const int slot = round & 1;
         for (int i = 0; i < m; ++i) {
-            const int par = (issued + i) & 1;
             hipError_t e;
             if (ws->prof_on && i == 0) {
                 HIP_TRY(hipEventRecord(ws->pev[slot][0], s));
-                e = launch_cg_dir<T>(geom, k, x, r, p0, p1, par, sc, ws->d, s);
+                e = launch_cg_dir<T>(geom, k, x, r, p0, p1, sc, ws->d, s);
                 if (e != hipSuccess) return hip_fail(e, "cg direction launch");
                 HIP_TRY(hipEventRecord(ws->pev[slot][1], s));
                 HIP_TRY(hipEventRecord(ws->pev[slot][2], s));
-                e = launch_cg_res<T>(geom, k, r, p0, p1, par, sc, ws->d, s);
+                e = launch_cg_res<T>(geom, k, r, p0, p1, sc, ws->d, s);
                 if (e != hipSuccess) return hip_fail(e, "cg residual launch");
                 HIP_TRY(hipEventRecord(ws->pev[slot][3], s));
                 ws->pev_iter[slot] = issued;
             } else {
-                e = launch_cg_iter<T>(geom, k, x, r, p0, p1, par, sc, ws->d, s);
+                e = launch_cg_iter<T>(geom, k, x, r, p0, p1, sc, ws->d, s);
                 if (e != hipSuccess) return hip_fail(e, "cg iteration launch");
             }
         }
@@ -242,68 +241,62 @@ int cg_fp64(const dg_grid* g, const double* omega, double* x, const double* pa,
     return DG_OK;
 }
 
-// Mixed precision: FP64 residual r = b - A psi, FP32 CG on A e = r, psi += e,
-// repeated until ||r||_W <= rtol ||b||_W.
+// Mixed precision: the CG recurrences run in FP32 (lane-interleaved x32,
+// r32, p), the solution accumulates in FP64 (x64 = ws->x).  After every
+// segment of iterations, and whenever the FP32 recursive residual meets the
+// tolerance, the true residual of x64 + x32 is recomputed in FP64 and
+// replaces r32 while the recurrence continues (no restart), and x32 is
+// folded into x64.  Stops when ||r64||_W <= rtol ||b||_W.
 int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
              double ca, const double* pb, double cb, const dg_cg_opts& o,
              dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
     const double tol2 = o.rtol * o.rtol;
-    const double itol = o.inner_rtol > 0 ? o.inner_rtol : 1e-5;
+    const int segment = o.check_every > 0 ? o.check_every : 32;
     hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
                                   tol2, o.max_iter, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg mean launch");
-    // x = guess - mean(guess)
-    e = launch_guess((long)g->elems, x, pa, pb, ca, cb, s);
-    if (e != hipSuccess) return hip_fail(e, "guess launch");
-    e = launch_mean_sub(g->geom, g->k64, x, g->area, ws->d, s);
-    if (e != hipSuccess) return hip_fail(e, "mean launch");
-    int total_inner = 0, outer = 0;
-    CgScalars oh, ih;
-    for (;;) {
-        e = launch_mixed_residual(g->geom, g->k64, omega, x, ws->r32, ws->e32,
-                                  itol * itol, o.max_iter, ws->d.sc, ws->inner,
-                                  ws->d, s);
-        if (e != hipSuccess) return hip_fail(e, "mixed residual launch");
-        int rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
-        if (rc != DG_OK) return rc;
-        oh = ws->host[2];
-        if (oh.converged || total_inner >= o.max_iter || outer >= 100) break;
-        rc = cg_loop<float>(g->geom, g->k32, ws->e32, ws->r32, ws->q0, ws->q1,
-                            ws->inner, o.max_iter - total_inner, o.check_every, ws,
-                            s, &ih);
-        if (rc != DG_OK) return rc;
-        total_inner += ih.iter;
-        e = launch_mixed_update(g->geom, x, ws->e32, ws->q0, ws->q1, ws->inner, s);
-        if (e != hipSuccess) return hip_fail(e, "mixed update launch");
-        ++outer;
-        if (ih.iter == 0) {  // inner solve could not move: stagnation
-            e = launch_mixed_residual(g->geom, g->k64, omega, x, ws->r32, ws->e32,
-                                      itol * itol, 0, ws->d.sc, ws->inner, ws->d, s);
-            if (e != hipSuccess) return hip_fail(e, "mixed residual launch");
+    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, ws->x, ws->r, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg init launch");
+    int rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+    if (rc != DG_OK) return rc;
+    CgScalars h = ws->host[2];
+    if (!h.done) {
+        e = launch_mixed_start(g->geom, g->k64, ws->r, ws->r32, ws->e32, ws->d, s);
+        if (e != hipSuccess) return hip_fail(e, "mixed start launch");
+        for (;;) {
+            for (int i = 0; i < segment; ++i) {
+                e = launch_cg_iter<float>(g->geom, g->k32, ws->e32, ws->r32, ws->q0,
+                                          ws->q1, ws->d.sc, ws->d, s);
+                if (e != hipSuccess) return hip_fail(e, "mixed CG launch");
+            }
+            e = launch_mixed_replace(g->geom, g->k64, omega, ws->x, ws->e32, ws->q0,
+                                     ws->q1, ws->r32, ws->d, s);
+            if (e == hipSuccess)
+                e = launch_mixed_accum(g->geom, ws->x, ws->e32, ws->q0, ws->q1, ws->d, s);
+            if (e != hipSuccess) return hip_fail(e, "mixed replacement launch");
             rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
             if (rc != DG_OK) return rc;
-            oh = ws->host[2];
-            break;
+            h = ws->host[2];
+            if (h.done) break;
         }
-    }
-    // final W-mean removal of psi; b = 0 gives psi = 0
-    if (oh.zero) {
-        HIP_TRY(hipMemsetAsync(x, 0, g->elems * sizeof(double), s));
     } else {
-        e = launch_mean_sub(g->geom, g->k64, x, g->area, ws->d, s);
-        if (e != hipSuccess) return hip_fail(e, "mean launch");
+        h.rr_true = h.rr;
     }
+    // psi (canonical) = x64 (every pending update already folded in), minus
+    // its W-mean; b = 0 gives psi = 0
+    e = launch_cg_finish(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
     HIP_TRY(hipStreamSynchronize(s));
+    const double rel = h.bb > 0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
     if (st) {
-        st->iters = total_inner;
-        st->outer_iters = outer;
-        st->rel_residual = oh.bb > 0 ? std::sqrt(oh.rr / oh.bb) : 0.0;
-        st->converged = oh.converged;
+        st->iters = h.iter;
+        st->outer_iters = h.outer;
+        st->rel_residual = rel;
+        st->converged = h.converged;
     }
-    if (!oh.converged)
-        return fail(DG_E_NOCONV, "mixed CG stopped: %d inner, %d outer iterations, "
-                    "relative residual %.3e", total_inner, outer,
-                    oh.bb > 0 ? std::sqrt(oh.rr / oh.bb) : 0.0);
+    if (!h.converged)
+        return fail(DG_E_NOCONV, "mixed CG stopped after %d iterations (%d residual "
+                    "replacements), relative residual %.3e", h.iter, h.outer, rel);
     return DG_OK;
 }
 

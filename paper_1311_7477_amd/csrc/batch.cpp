@@ -131,10 +131,10 @@ int enqueue_setup(dg_batch* b, hipStream_t s) {
     for (int n = 1; n <= kMaxN; ++n) {
         if (!(b->group_mask & (1u << (n - 1)))) continue;
         hipError_t e = launch_batch(n, BatchKernel::Mean, b->d_inst, list_of(b, n, kPwRows),
-                                    grid_of(b, n, kPwRows), 0, s);
+                                    grid_of(b, n, kPwRows), s);
         if (e == hipSuccess)
             e = launch_batch(n, BatchKernel::Init, b->d_inst, list_of(b, n, kCell),
-                             grid_of(b, n, kCell), 0, s);
+                             grid_of(b, n, kCell), s);
         if (e != hipSuccess) return hip_fail(e, "batch setup launch");
     }
     return DG_OK;
@@ -145,10 +145,10 @@ int enqueue_chunk(dg_batch* b, hipStream_t s) {
         for (int n = 1; n <= kMaxN; ++n) {
             if (!(b->group_mask & (1u << (n - 1)))) continue;
             hipError_t e = launch_batch(n, BatchKernel::Dir, b->d_inst, list_of(b, n, kCell),
-                                        grid_of(b, n, kCell), i & 1, s);
+                                        grid_of(b, n, kCell), s);
             if (e == hipSuccess)
                 e = launch_batch(n, BatchKernel::Res, b->d_inst, list_of(b, n, kCell),
-                                 grid_of(b, n, kCell), i & 1, s);
+                                 grid_of(b, n, kCell), s);
             if (e != hipSuccess) return hip_fail(e, "batch CG launch");
         }
     return DG_OK;
@@ -158,13 +158,13 @@ int enqueue_finish(dg_batch* b, hipStream_t s) {
     for (int n = 1; n <= kMaxN; ++n) {
         if (!(b->group_mask & (1u << (n - 1)))) continue;
         hipError_t e = launch_batch(n, BatchKernel::Finish, b->d_inst,
-                                    list_of(b, n, kPwCells), grid_of(b, n, kPwCells), 0, s);
+                                    list_of(b, n, kPwCells), grid_of(b, n, kPwCells), s);
         if (e == hipSuccess)
             e = launch_batch(n, BatchKernel::SubMean, b->d_inst, list_of(b, n, kPwElems),
-                             grid_of(b, n, kPwElems), 0, s);
+                             grid_of(b, n, kPwElems), s);
         if (e == hipSuccess)
             e = launch_batch(n, BatchKernel::Rhs, b->d_inst, list_of(b, n, kRow),
-                             grid_of(b, n, kRow), 0, s);
+                             grid_of(b, n, kRow), s);
         if (e != hipSuccess) return hip_fail(e, "batch finish launch");
     }
     return DG_OK;

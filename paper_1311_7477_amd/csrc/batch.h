@@ -47,6 +47,6 @@ enum class BatchKernel { Mean, Init, Dir, Res, Finish, SubMean, Rhs };
 
 void fill_batch_geometry(BatchInst& b);
 hipError_t launch_batch(int n, BatchKernel kind, const BatchInst* inst,
-                        const ItemList& list, int grid, int parity, hipStream_t s);
+                        const ItemList& list, int grid, hipStream_t s);
 
 }  // namespace dgk

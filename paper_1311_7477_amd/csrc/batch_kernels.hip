@@ -49,25 +49,22 @@ __global__ __launch_bounds__(64 * kCellWaves) void kb_cg_init(const BatchInst* i
 
 template <int N>
 __global__ __launch_bounds__(64 * kCellWaves) void kb_cg_dir(const BatchInst* inst,
-                                                             ItemList list,
-                                                             int parity) {
+                                                             ItemList list) {
     __shared__ YFaces<N, double> lds;
     DG_FOR_ITEMS(list) {
         cg_dir_body<N, double>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
-                               B.r, parity ? B.p1 : B.p0, parity ? B.p0 : B.p1,
-                               B.x, B.sc, B.counters + kCntDir, B.partials, lds);
+                               B.r, B.p0, B.p1, B.x, B.sc, B.counters + kCntDir, B.partials, lds);
         __syncthreads();
     }
 }
 
 template <int N>
 __global__ __launch_bounds__(64 * kCellWaves) void kb_cg_res(const BatchInst* inst,
-                                                             ItemList list,
-                                                             int parity) {
+                                                             ItemList list) {
     __shared__ YFaces<N, double> lds;
     DG_FOR_ITEMS(list) {
         cg_res_body<N, double>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
-                               parity ? B.p0 : B.p1, B.r, B.sc,
+                               B.p0, B.p1, B.r, B.sc,
                                B.counters + kCntRes, B.partials, lds);
         __syncthreads();
     }
@@ -127,8 +124,7 @@ void fill_batch_geometry(BatchInst& b) {
 }
 
 hipError_t launch_batch(int n, BatchKernel kind, const BatchInst* inst,
-                        const ItemList& list, int grid, int parity,
-                        hipStream_t s) {
+                        const ItemList& list, int grid, hipStream_t s) {
     const dim3 cell(64 * kCellWaves), row(64 * kRowWaves), pw(kPwThreads);
     DG_DISPATCH_N(n, {
         switch (kind) {
@@ -139,12 +135,10 @@ hipError_t launch_batch(int n, BatchKernel kind, const BatchInst* inst,
                 hipLaunchKernelGGL((kb_cg_init<NN>), dim3(grid), cell, 0, s, inst, list);
                 break;
             case BatchKernel::Dir:
-                hipLaunchKernelGGL((kb_cg_dir<NN>), dim3(grid), cell, 0, s, inst, list,
-                                   parity);
+                hipLaunchKernelGGL((kb_cg_dir<NN>), dim3(grid), cell, 0, s, inst, list);
                 break;
             case BatchKernel::Res:
-                hipLaunchKernelGGL((kb_cg_res<NN>), dim3(grid), cell, 0, s, inst, list,
-                                   parity);
+                hipLaunchKernelGGL((kb_cg_res<NN>), dim3(grid), cell, 0, s, inst, list);
                 break;
             case BatchKernel::Finish:
                 hipLaunchKernelGGL((kb_cg_finish<NN>), dim3(grid), pw, 0, s, inst, list);

@@ -349,27 +349,35 @@ __device__ __forceinline__ void cg_init_body(
 template <int N, class T>
 __device__ __forceinline__ void cg_dir_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<T>& k, const T* __restrict__ r,
-    const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ x,
+    T* p0, T* p1, T* __restrict__ x,
     CgScalars* sc, unsigned* counter, double* partials,
     YFaces<N, T>& lds) {
     if (sc->done) return;
+    // iteration k reads p_{k-1} from buffer k mod 2 and writes p_k to the other
+    const T* pin = (sc->iter & 1) ? p1 : p0;
+    T* pout = (sc->iter & 1) ? p0 : p1;
     const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
-    const bool first = sc->first != 0;
+    // first = 1: p = r; 0: x += alpha p_old, p = r + beta p_old;
+    // 2 (after a residual replacement that already applied alpha p_old):
+    // p = r + beta p_old only
+    const int first = sc->first;
     const T alpha = (T)sc->alpha;
-    SrcDirection<N, T> src{r, pin, (T)sc->beta, first};
+    SrcDirection<N, T> src{r, pin, (T)sc->beta, first == 1};
     T p[N * N], q[N * N];
     if (c.active) {
         ld_l64<N>(r, c.self, p);
-        if (!first) {
-            T po[N * N], xv[N * N];
+        if (first != 1) {
+            T po[N * N];
             ld_l64<N>(pin, c.self, po);
-            ld_l64<N>(x, c.self, xv);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) {
-                xv[e] = fmx(alpha, po[e], xv[e]);
-                p[e] = fmx(src.beta, po[e], p[e]);
+            for (int e = 0; e < N * N; ++e) p[e] = fmx(src.beta, po[e], p[e]);
+            if (first == 0) {
+                T xv[N * N];
+                ld_l64<N>(x, c.self, xv);
+#pragma unroll
+                for (int e = 0; e < N * N; ++e) xv[e] = fmx(alpha, po[e], xv[e]);
+                st_l64<N>(x, c.self, xv);
             }
-            st_l64<N>(x, c.self, xv);
         }
     } else {
         zero_cell<N>(p);
@@ -401,10 +409,11 @@ __device__ __forceinline__ void cg_dir_body(
 // convergence test ||r||_W^2 <= tol^2 ||b||_W^2.
 template <int N, class T>
 __device__ __forceinline__ void cg_res_body(
-    int b, Geom g, int tilesX, int nblocks, const OpConst<T>& k, const T* __restrict__ p,
-    T* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials,
-    YFaces<N, T>& lds) {
+    int b, Geom g, int tilesX, int nblocks, const OpConst<T>& k, const T* p0,
+    const T* p1, T* __restrict__ r, CgScalars* sc, unsigned* counter,
+    double* partials, YFaces<N, T>& lds) {
     if (sc->done) return;
+    const T* p = (sc->iter & 1) ? p0 : p1;   // p_k written by this iteration's direction update
     const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
     const T alpha = (T)sc->alpha;
     SrcL64<N, T> src{p};
@@ -442,67 +451,92 @@ __device__ __forceinline__ void cg_res_body(
     }
 }
 
-// Mixed precision, outer step: r64 = (omega - mean(omega)) + Lap_h psi in
-// FP64 (psi, omega canonical); stores r32 = float(r64) and e32 = 0 (L64) for
-// the inner solve; partials <r64,r64>, <b,b>, <r32,r32>.  The last block
-// decides outer convergence and initialises the inner CG scalars.
+// Mixed precision, residual replacement: with the FP64 solution
+// x = x64 + x32 + alpha p_last (the FP32 accumulator and the direction
+// update the next iteration would apply), the true residual
+// r64 = (omega - mean(omega)) + Lap_h x is computed in FP64 and replaces the
+// FP32 recursive residual (r32 = float(r64)).  Partials <r64,r64>, <r32,r32>.
+// The last block tests convergence on the FP64 residual; otherwise the CG
+// recurrence continues: beta is rescaled to the replaced residual and the
+// next direction update must not apply alpha p_last again (first = 2),
+// because the accumulation kernel that follows folds it into x64.
 template <int N>
-__device__ __forceinline__ void mixed_residual_body(
+struct SrcMixedX {
+    const double* x64;
+    const float* x32;
+    const float* pl;
+    double alpha;
+    bool pending;
+    __device__ void operator()(const CellRef& c, double (&u)[N * N]) const {
+        float a[N * N];
+        ld_l64<N>(x64, c, u);
+        ld_l64<N>(x32, c, a);
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) u[e] += (double)a[e];
+        if (pending) {
+            float q[N * N];
+            ld_l64<N>(pl, c, q);
+#pragma unroll
+            for (int e = 0; e < N * N; ++e) u[e] = fmx(alpha, (double)q[e], u[e]);
+        }
+    }
+};
+
+template <int N>
+__device__ __forceinline__ void mixed_replace_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
-    const double* __restrict__ omega, const double* __restrict__ psi,
-    float* __restrict__ r32, float* __restrict__ e32, double inner_tol2,
-    int inner_max, CgScalars* outer, CgScalars* inner, unsigned* counter,
-    double* partials,
-    YFaces<N, double>& lds) {
+    const double* __restrict__ omega, const double* __restrict__ x64,
+    const float* __restrict__ x32, const float* __restrict__ q0,
+    const float* __restrict__ q1, float* __restrict__ r32, CgScalars* sc,
+    unsigned* counter, double* partials, YFaces<N, double>& lds) {
     const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
-    SrcCanon<N, double> src{psi};
-    const double mo = outer->mean_omega;
+    // alpha p_last is still owed to x when an iteration ran since the last
+    // replacement, unless the direction update broke down (it had applied
+    // the previous alpha p itself)
+    const bool pending = sc->iter > sc->iter_repl && !sc->breakdown;
+    SrcMixedX<N> src{x64, x32, (sc->iter & 1) ? q1 : q0, sc->alpha, pending};
+    const double mo = sc->mean_omega;
     double v[N * N], lap[N * N];
     if (c.active) src(c.self, v);
     else zero_cell<N>(v);
     lap_cell<N>(c, k, src, v, lds, lap);
-    double part[3] = {0.0, 0.0, 0.0};
+    double part[2] = {0.0, 0.0};
     if (c.active) {
-        double b[N * N], rd[N * N];
-        float rf[N * N], zf[N * N];
-        ld_canon<N>(omega, c.self, b);
+        double w[N * N], rd[N * N];
+        float rf[N * N];
+        ld_canon<N>(omega, c.self, w);
 #pragma unroll
         for (int e = 0; e < N * N; ++e) {
-            b[e] -= mo;
-            lap[e] += b[e];
+            lap[e] += w[e] - mo;
             rf[e] = (float)lap[e];
             rd[e] = (double)rf[e];
-            zf[e] = 0.0f;
         }
         st_l64<N>(r32, c.self, rf);
-        st_l64<N>(e32, c.self, zf);
         part[0] = wdot_cell<N>(k, lap, lap);
-        part[1] = wdot_cell<N>(k, b, b);
-        part[2] = wdot_cell<N>(k, rd, rd);
+        part[1] = wdot_cell<N>(k, rd, rd);
     }
-    double tot[3];
-    if (reduce_last<3, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    double tot[2];
+    if (reduce_last<2, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
-        outer->rr = tot[0];
-        outer->bb = tot[1];
-        outer->iter += 1;
-        const bool zero = tot[1] <= outer->zero_tol2 * outer->ww;
-        const bool ok = zero || tot[0] <= outer->tol2 * tot[1];
-        outer->converged = ok ? 1 : 0;
-        outer->zero = zero ? 1 : 0;
-        inner->rr = tot[2];
-        inner->bb = tot[2];
-        inner->tol2 = inner_tol2;
-        inner->max_iter = inner_max;
-        inner->alpha = 0.0;
-        inner->beta = 0.0;
-        inner->first = 1;
-        inner->iter = 0;
-        inner->pending = 0;
-        inner->zero = 0;
-        inner->breakdown = 0;
-        inner->converged = 0;
-        inner->done = (ok || tot[2] == 0.0 || inner_max <= 0) ? 1 : 0;
+        sc->rr_true = tot[0];
+        sc->accum_pending = pending ? 1 : 0;
+        sc->accum_alpha = sc->alpha;
+        sc->iter_repl = sc->iter;
+        sc->pending = 0;
+        sc->outer += 1;
+        if (tot[0] <= sc->tol2 * sc->bb) {
+            sc->done = 1;
+            sc->converged = 1;
+        } else if (sc->iter >= sc->max_iter || sc->breakdown || !(tot[0] == tot[0])) {
+            sc->done = 1;
+            sc->converged = 0;
+        } else {
+            if (sc->first != 1) sc->beta *= tot[1] / sc->rr;
+            sc->rr = tot[1];
+            sc->first = (sc->first == 1) ? 1 : 2;
+            sc->done = 0;
+            sc->converged = 0;
+        }
     }
 }
 

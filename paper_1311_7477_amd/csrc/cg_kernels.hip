@@ -29,33 +29,32 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cg_init(
 template <int N, class T>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_dir(
     Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ r,
-    const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ x,
-    CgScalars* sc, unsigned* counter, double* partials) {
+    T* p0, T* p1, T* __restrict__ x, CgScalars* sc, unsigned* counter,
+    double* partials) {
     __shared__ YFaces<N, T> lds;
-    cg_dir_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, r, pin, pout, x, sc,
+    cg_dir_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
                       counter, partials, lds);
 }
 
 template <int N, class T>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_res(
-    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ p,
+    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* p0, const T* p1,
     T* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
     __shared__ YFaces<N, T> lds;
-    cg_res_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, p, r, sc, counter,
+    cg_res_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
                       partials, lds);
 }
 
 template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void k_mixed_residual(
+__global__ __launch_bounds__(64 * kCellWaves) void k_mixed_replace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
-    const double* __restrict__ omega, const double* __restrict__ psi,
-    float* __restrict__ r32, float* __restrict__ e32, double inner_tol2,
-    int inner_max, CgScalars* outer, CgScalars* inner, unsigned* counter,
-    double* partials) {
+    const double* __restrict__ omega, const double* __restrict__ x64,
+    const float* __restrict__ x32, const float* __restrict__ q0,
+    const float* __restrict__ q1, float* __restrict__ r32, CgScalars* sc,
+    unsigned* counter, double* partials) {
     __shared__ YFaces<N, double> lds;
-    mixed_residual_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, psi, r32,
-                           e32, inner_tol2, inner_max, outer, inner, counter,
-                           partials, lds);
+    mixed_replace_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, x64, x32, q0,
+                          q1, r32, sc, counter, partials, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -86,66 +85,59 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
 
 template <class T>
 hipError_t launch_cg_dir(const Geom& g, const OpConst<T>& k, T* x, T* r, T* p0,
-                         T* p1, int parity, CgScalars* sc, const DevScratch& d,
-                         hipStream_t s) {
-    T* pin = parity ? p1 : p0;
-    T* pout = parity ? p0 : p1;
+                         T* p1, CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, T>), dim3(L.nblocks),
                                           dim3(64 * kCellWaves), 0, s, g, L.tilesX,
-                                          L.nblocks, k, r, pin, pout, x, sc,
+                                          L.nblocks, k, r, p0, p1, x, sc,
                                           d.counters + kCntDir, d.partials));
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_cg_res(const Geom& g, const OpConst<T>& k, T* r, T* p0, T* p1,
-                         int parity, CgScalars* sc, const DevScratch& d,
-                         hipStream_t s) {
-    T* pout = parity ? p0 : p1;
+                         CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, T>), dim3(L.nblocks),
                                           dim3(64 * kCellWaves), 0, s, g, L.tilesX,
-                                          L.nblocks, k, pout, r, sc,
+                                          L.nblocks, k, p0, p1, r, sc,
                                           d.counters + kCntRes, d.partials));
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_cg_iter(const Geom& g, const OpConst<T>& k, T* x, T* r,
-                          T* p0, T* p1, int parity, CgScalars* sc,
-                          const DevScratch& d, hipStream_t s) {
-    hipError_t e = launch_cg_dir<T>(g, k, x, r, p0, p1, parity, sc, d, s);
+                          T* p0, T* p1, CgScalars* sc, const DevScratch& d,
+                          hipStream_t s) {
+    hipError_t e = launch_cg_dir<T>(g, k, x, r, p0, p1, sc, d, s);
     if (e != hipSuccess) return e;
-    return launch_cg_res<T>(g, k, r, p0, p1, parity, sc, d, s);
+    return launch_cg_res<T>(g, k, r, p0, p1, sc, d, s);
 }
 
 #define DG_INST(T)                                                             \
     template hipError_t launch_cg_dir<T>(const Geom&, const OpConst<T>&, T*, T*, \
-                                         T*, T*, int, CgScalars*,               \
-                                         const DevScratch&, hipStream_t);       \
+                                         T*, T*, CgScalars*, const DevScratch&,  \
+                                         hipStream_t);                          \
     template hipError_t launch_cg_res<T>(const Geom&, const OpConst<T>&, T*, T*, \
-                                         T*, int, CgScalars*, const DevScratch&, \
+                                         T*, CgScalars*, const DevScratch&,     \
                                          hipStream_t);                          \
     template hipError_t launch_cg_iter<T>(const Geom&, const OpConst<T>&, T*,   \
-                                          T*, T*, T*, int, CgScalars*,          \
+                                          T*, T*, T*, CgScalars*,               \
                                           const DevScratch&, hipStream_t);
 DG_INST(double)
 DG_INST(float)
 #undef DG_INST
 
-hipError_t launch_mixed_residual(const Geom& g, const OpConst<double>& k,
-                                 const double* omega, const double* psi,
-                                 float* r32, float* e32, double inner_tol2,
-                                 int inner_max, CgScalars* outer,
-                                 CgScalars* inner, const DevScratch& d,
-                                 hipStream_t s) {
+hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
+                                const double* omega, const double* x64,
+                                const float* x32, const float* q0,
+                                const float* q1, float* r32, const DevScratch& d,
+                                hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_residual<NN>), dim3(L.nblocks),
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_replace<NN>), dim3(L.nblocks),
                                           dim3(64 * kCellWaves), 0, s, g, L.tilesX,
-                                          L.nblocks, k, omega, psi, r32, e32,
-                                          inner_tol2, inner_max, outer, inner,
-                                          d.counters + kCntDot, d.partials));
+                                          L.nblocks, k, omega, x64, x32, q0, q1, r32,
+                                          d.sc, d.counters + kCntDot, d.partials));
     return hipGetLastError();
 }
 

@@ -60,6 +60,10 @@ struct CgScalars {
     double ww;        // <omega, omega>_W
     double zero_tol2; // b counts as zero when <b,b>_W <= zero_tol2 * ww
     double ca, cb;    // guess = ca * psi_a + cb * psi_b (device copies)
+    // mixed precision: FP64 residual of the last replacement, the direction
+    // update it folded into the FP64 solution, and the iteration it ran at
+    double rr_true, accum_alpha;
+    int iter_repl, accum_pending, outer;
     int iter, max_iter;
     int done, converged, pending, first, zero, breakdown;
 };

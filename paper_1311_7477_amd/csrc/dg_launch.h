@@ -41,18 +41,19 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                           const double* omega, const double* pa,
                           const double* pb, double ca, double cb, double* x,
                           double* r, const DevScratch& d, hipStream_t s);
+// CG iterations; the direction buffers p0/p1 alternate by the device
+// iteration count (sc->iter), so any number of queued no-op iterations
+// keeps them consistent.
 template <class T>
 hipError_t launch_cg_dir(const Geom& g, const OpConst<T>& k, T* x, T* r, T* p0,
-                         T* p1, int parity, CgScalars* sc, const DevScratch& d,
-                         hipStream_t s);
+                         T* p1, CgScalars* sc, const DevScratch& d, hipStream_t s);
 template <class T>
 hipError_t launch_cg_res(const Geom& g, const OpConst<T>& k, T* r, T* p0, T* p1,
-                         int parity, CgScalars* sc, const DevScratch& d,
-                         hipStream_t s);
+                         CgScalars* sc, const DevScratch& d, hipStream_t s);
 template <class T>
 hipError_t launch_cg_iter(const Geom& g, const OpConst<T>& k, T* x, T* r,
-                          T* p0, T* p1, int parity, CgScalars* sc,
-                          const DevScratch& d, hipStream_t s);
+                          T* p0, T* p1, CgScalars* sc, const DevScratch& d,
+                          hipStream_t s);
 // psi (canonical) = x + pending alpha p (lane-interleaved), minus its W-mean
 hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
                             const double* x, const double* p0, const double* p1,
@@ -64,15 +65,20 @@ hipError_t launch_mean_sub(const Geom& g, const OpConst<double>& k, double* x,
 hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
                              const double* omega, const double* psi,
                              double* out3, const DevScratch& d, hipStream_t s);
-hipError_t launch_mixed_residual(const Geom& g, const OpConst<double>& k,
-                                 const double* omega, const double* psi,
-                                 float* r32, float* e32, double inner_tol2,
-                                 int inner_max, CgScalars* outer,
-                                 CgScalars* inner, const DevScratch& d,
-                                 hipStream_t s);
-hipError_t launch_mixed_update(const Geom& g, double* psi, const float* e,
-                               const float* p0, const float* p1,
-                               const CgScalars* inner, hipStream_t s);
+// Mixed precision (FP32 CG recurrences, FP64 residual replacement; all
+// vectors lane-interleaved): r32 = float(r64), x32 = 0; true residual of
+// x64 + x32 + alpha p_last into r32; x64 += x32 (+ alpha p_last), x32 = 0.
+hipError_t launch_mixed_start(const Geom& g, const OpConst<double>& k,
+                              const double* r64, float* r32, float* x32,
+                              const DevScratch& d, hipStream_t s);
+hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
+                                const double* omega, const double* x64,
+                                const float* x32, const float* q0,
+                                const float* q1, float* r32, const DevScratch& d,
+                                hipStream_t s);
+hipError_t launch_mixed_accum(const Geom& g, double* x64, float* x32,
+                              const float* q0, const float* q1, const DevScratch& d,
+                              hipStream_t s);
 hipError_t launch_guess(long elems, double* x, const double* pa,
                         const double* pb, double ca, double cb, hipStream_t s);
 

@@ -49,11 +49,20 @@ __global__ __launch_bounds__(kPwThreads) void k_invariants(
 }
 
 template <int N>
-__global__ __launch_bounds__(kPwThreads) void k_mixed_update(
-    Geom g, double* __restrict__ psi, const float* __restrict__ e32,
-    const float* __restrict__ p0, const float* __restrict__ p1,
-    const CgScalars* inner) {
-    mixed_update_body<N>(blockIdx.x, gridDim.x, g, psi, e32, p0, p1, inner);
+__global__ __launch_bounds__(kPwThreads) void k_mixed_start(
+    Geom g, OpConst<double> k, const double* __restrict__ r64,
+    float* __restrict__ r32, float* __restrict__ x32, CgScalars* sc,
+    unsigned* counter, double* partials) {
+    mixed_start_body<N>(blockIdx.x, gridDim.x, g, k, r64, r32, x32, sc, counter,
+                        partials);
+}
+
+template <int N>
+__global__ __launch_bounds__(kPwThreads) void k_mixed_accum(
+    Geom g, double* __restrict__ x64, float* __restrict__ x32,
+    const float* __restrict__ q0, const float* __restrict__ q1,
+    const CgScalars* sc) {
+    mixed_accum_body<N>(blockIdx.x, gridDim.x, g, x64, x32, q0, q1, sc);
 }
 
 __global__ __launch_bounds__(kPwThreads) void k_guess(long elems,
@@ -133,14 +142,25 @@ hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
     return hipGetLastError();
 }
 
-hipError_t launch_mixed_update(const Geom& g, double* psi, const float* e,
-                               const float* p0, const float* p1,
-                               const CgScalars* inner, hipStream_t s) {
+hipError_t launch_mixed_start(const Geom& g, const OpConst<double>& k,
+                              const double* r64, float* r32, float* x32,
+                              const DevScratch& d, hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_update<NN>), dim3(nb),
-                                          dim3(kPwThreads), 0, s, g, psi, e, p0, p1,
-                                          inner));
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_start<NN>), dim3(nb),
+                                          dim3(kPwThreads), 0, s, g, k, r64, r32, x32,
+                                          d.sc, d.counters + kCntMean, d.partials));
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_accum(const Geom& g, double* x64, float* x32,
+                              const float* q0, const float* q1, const DevScratch& d,
+                              hipStream_t s) {
+    const long cells = (long)g.nx * g.ny;
+    const int nb = pw_blocks(cells, pointwise_block_cap());
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_accum<NN>), dim3(nb),
+                                          dim3(kPwThreads), 0, s, g, x64, x32, q0, q1,
+                                          d.sc));
     return hipGetLastError();
 }
 

@@ -175,33 +175,6 @@ __device__ __forceinline__ void invariants_body(int b, int nb, long rows, const 
     }
 }
 
-// psi (canonical, FP64) += e + alpha p_last (lane-interleaved, FP32): the
-// FP64 accumulation of one inner FP32 solve.
-template <int N>
-__device__ __forceinline__ void mixed_update_body(int b, int nb, Geom g, double* __restrict__ psi, const float* __restrict__ e32,
-    const float* __restrict__ p0, const float* __restrict__ p1,
-    const CgScalars* inner) {
-    const int pending = inner->pending;
-    const float alpha = (float)inner->alpha;
-    const float* pl = (inner->iter & 1) ? p1 : p0;
-    const long cells = (long)g.nx * g.ny;
-    const int G = (g.nx + 63) / 64;
-    for (long cell = b * (long)kPwThreads + threadIdx.x; cell < cells;
-         cell += (long)nb * kPwThreads) {
-        const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
-        const long l64 = ((long)cy * G + (cx >> 6)) * (N * N * 64) + (cx & 63);
-        double v[N * N];
-        load_vec(psi, cell * (N * N), v);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) {
-            float c = e32[l64 + 64 * e];
-            if (pending) c = fmx(alpha, pl[l64 + 64 * e], c);
-            v[e] += (double)c;
-        }
-        store_vec(psi, cell * (N * N), v);
-    }
-}
-
 // x = ca pa + cb pb (pointwise; in place allowed)
 __device__ __forceinline__ void guess_body(int b, int nb, long elems,
                                                       double* __restrict__ x,
@@ -217,5 +190,74 @@ __device__ __forceinline__ void guess_body(int b, int nb, long elems,
     }
 }
 
+
+// Mixed precision, after a residual replacement: x64 += x32 (+ the pending
+// alpha p_last the replacement used), x32 = 0; all lane-interleaved.
+template <int N>
+__device__ __forceinline__ void mixed_accum_body(int b, int nb, Geom g,
+                                                 double* __restrict__ x64,
+                                                 float* __restrict__ x32,
+                                                 const float* __restrict__ q0,
+                                                 const float* __restrict__ q1,
+                                                 const CgScalars* sc) {
+    const bool pending = sc->accum_pending != 0;
+    const double alpha = sc->accum_alpha;
+    const float* pl = (sc->iter & 1) ? q1 : q0;
+    const long cells = (long)g.nx * g.ny;
+    const int G = (g.nx + 63) / 64;
+    for (long cell = b * (long)kPwThreads + threadIdx.x; cell < cells;
+         cell += (long)nb * kPwThreads) {
+        const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
+        const long l64 = ((long)cy * G + (cx >> 6)) * (N * N * 64) + (cx & 63);
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) {
+            double v = x64[l64 + 64 * e] + (double)x32[l64 + 64 * e];
+            if (pending) v = fmx(alpha, (double)pl[l64 + 64 * e], v);
+            x64[l64 + 64 * e] = v;
+            x32[l64 + 64 * e] = 0.0f;
+        }
+    }
+}
+
+// Mixed precision, start: r32 = float(r64), x32 = 0 (lane-interleaved);
+// <r32, r32>_W becomes the CG recurrence's residual norm.
+template <int N>
+__device__ __forceinline__ void mixed_start_body(int b, int nb, Geom g,
+                                                 const OpConst<double>& k,
+                                                 const double* __restrict__ r64,
+                                                 float* __restrict__ r32,
+                                                 float* __restrict__ x32,
+                                                 CgScalars* sc, unsigned* counter,
+                                                 double* partials) {
+    const long cells = (long)g.nx * g.ny;
+    const int G = (g.nx + 63) / 64;
+    double part[1] = {0.0};
+    for (long cell = b * (long)kPwThreads + threadIdx.x; cell < cells;
+         cell += (long)nb * kPwThreads) {
+        const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
+        const long l64 = ((long)cy * G + (cx >> 6)) * (N * N * 64) + (cx & 63);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double row[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int e = j * N + i;
+                const float f = (float)r64[l64 + 64 * e];
+                r32[l64 + 64 * e] = f;
+                x32[l64 + 64 * e] = 0.0f;
+                row[i] = (double)f * (double)f;
+            }
+            part[0] += wrow<N>(k, j, row);
+        }
+    }
+    double tot[1];
+    if (reduce_last<1, kPwThreads>(part, partials, counter, nb, b, tot) &&
+        threadIdx.x == 0) {
+        sc->rr_true = sc->rr;
+        sc->rr = tot[0];
+        sc->iter_repl = 0;
+        sc->outer = 0;
+    }
+}
 
 }  // namespace dgk
