@@ -29,7 +29,8 @@ __all__ = [
     "legendre_values", "ReferenceElement", "Grid1D", "Grid2D",
     "to_image", "from_image", "dx", "dy", "dx_form", "dy_form",
     "bracket_forms", "bracket", "laplacian", "inner", "wmean",
-    "cg_poisson", "rhs", "rk3_step", "PsiHistory", "invariants",
+    "cg_poisson", "pcg_poisson", "FastDiagonalisation", "rhs", "rk3_step",
+    "PsiHistory", "invariants",
     "dense_operators", "dense_poisson_solve", "arakawa_fd_jacobian",
     "five_point_laplacian",
 ]
@@ -351,6 +352,97 @@ def cg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
             break
         p = r + (rr_new / rr) * p
         rr = rr_new
+    x = x - wmean(g, x)
+    return CGResult(x, it, converged, math.sqrt(rr) / bnorm)
+
+
+# --------------------------------------------------------------------------
+# Preconditioned CG (beyond the paper, which uses plain CG in Sec. 6): the
+# preconditioner is the exact inverse of -Delta_h on W-mean-free fields
+# built from separable 1D eigenbases ("fast diagonalisation").
+# --------------------------------------------------------------------------
+class FastDiagonalisation:
+    """Exact inverse of -Delta_h on W-mean-free fields.
+
+    The 1D LDG second derivative L of each axis is self-adjoint in the 1D
+    Gauss inner product (W L is symmetric, W = diag of Grid1D.weights), so
+    W^(1/2) L W^(-1/2) = Q diag(lam) Q^T with Q orthogonal (numpy eigh) and
+    V = W^(-1/2) Q satisfies V^T W V = I and L V = V diag(lam).  Since
+    Delta_h = Ly (x) I + I (x) Lx on the image layout (Sec. 4.3, Kronecker
+    products), its eigenvectors are V_y[:, b] (x) V_x[:, a] with eigenvalues
+    lam_y[b] + lam_x[a] <= 0, and
+        (-Delta_h)^+ R = V_y [ (V_y^T W_y R W_x V_x) / -(lam_y + lam_x) ] V_x^T
+    with the single zero eigenvalue (the constant mode, lam_x = lam_y = 0)
+    dropped.  Dense eigh: meant for grids up to a few thousand nodes per
+    axis."""
+
+    def __init__(self, g: Grid2D):
+        self.g = g
+        self.Vx, self.lx, self.wx = self._axis(g.gx)
+        self.Vy, self.ly, self.wy = self._axis(g.gy)
+        mu = -(self.ly[:, None] + self.lx[None, :])
+        inv = np.zeros_like(mu)
+        nz = np.ones_like(mu, dtype=bool)
+        nz[int(np.argmax(self.ly)), int(np.argmax(self.lx))] = False
+        inv[nz] = 1.0 / mu[nz]
+        self.inv_mu = inv
+
+    @staticmethod
+    def _axis(g1: Grid1D):
+        L = g1.laplacian().toarray()
+        w = g1.weights()
+        sw = np.sqrt(w)
+        S = sw[:, None] * L / sw[None, :]
+        lam, Q = np.linalg.eigh(0.5 * (S + S.T))
+        return Q / sw[:, None], lam, w
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """z = (-Delta_h)^+ r for a canonical-layout field r."""
+        R = to_image(r)
+        Rt = self.Vy.T @ (self.wy[:, None] * R * self.wx[None, :]) @ self.Vx
+        Z = self.Vy @ (Rt * self.inv_mu) @ self.Vx.T
+        return from_image(Z, self.g.n)
+
+
+def pcg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
+                max_iter=100000, precond=None) -> CGResult:
+    """Preconditioned CG in the W inner product on -Delta_h psi = b, with
+    the same b, initial guess, stopping rule (on ||r||_W, tested on r_0 and
+    after every update), iteration count and zero-mean result as
+    cg_poisson.  precond(r) returns z = M r for a W-self-adjoint positive
+    M; None means M = I, which reproduces cg_poisson's iterates exactly."""
+    W = g.weights()
+
+    def dot(u, v):
+        return float(np.sum(W * u * v))
+
+    apply_m = (lambda u: u.copy()) if precond is None else precond
+    b = omega - wmean(g, omega)
+    bnorm = math.sqrt(dot(b, b))
+    if bnorm == 0.0:
+        return CGResult(np.zeros_like(omega), 0, True, 0.0)
+    x = np.zeros_like(omega) if guess is None else guess - wmean(g, guess)
+    r = b + laplacian(g, x)
+    rr = dot(r, r)
+    it = 0
+    converged = math.sqrt(rr) <= rtol * bnorm
+    z = apply_m(r)
+    rz = dot(r, z)
+    p = z
+    while not converged and it < max_iter:
+        q = -laplacian(g, p)
+        alpha = rz / dot(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        rr = dot(r, r)
+        if math.sqrt(rr) <= rtol * bnorm:
+            converged = True
+            break
+        z = apply_m(r)
+        rz_new = dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
     x = x - wmean(g, x)
     return CGResult(x, it, converged, math.sqrt(rr) / bnorm)
 
