@@ -55,9 +55,17 @@ extern "C" {
 #define DG_BC_PERIODIC   0
 #define DG_BC_DIRICHLET  1      /* returns DG_E_UNSUPPORTED */
 
-/* CG precision modes */
+/* CG precision modes (also the workspace mode) */
 #define DG_PREC_FP64   0
-#define DG_PREC_MIXED  1        /* FP32 inner CG, FP64 residual refinement */
+#define DG_PREC_MIXED  1        /* r, p stored in FP32, FP64 arithmetic and solution,
+                                   periodic FP64 residual replacement */
+/* workspace option, OR-ed into the mode: also hold the fast-diagonalisation
+   preconditioner (dense separable eigenbases of the 1D LDG operators) */
+#define DG_WS_FD       0x10
+
+/* CG preconditioners (dg_cg_opts.precond) */
+#define DG_PRECOND_NONE 0       /* plain CG, as in Sec. 6 */
+#define DG_PRECOND_FD   1       /* exact inverse of -Lap_h by fast diagonalisation */
 
 /* single Jacobian forms for dg_bracket_form (Sec. 2 eq. J) */
 #define DG_FORM_ARAKAWA 0       /* (J++ + J+x + Jx+)/3 */
@@ -70,20 +78,25 @@ typedef struct dg_workspace dg_workspace;
 typedef struct dg_state dg_state;
 
 typedef struct {
-    double rtol;        /* stop when ||r||_W <= rtol ||b||_W (FP64 mode), or
-                           the outer FP64 residual meets it (mixed mode) */
-    int    max_iter;    /* operator applications allowed (inner ones in mixed mode) */
+    double rtol;        /* stop when ||r||_W <= rtol ||b||_W (in mixed mode: the
+                           FP64 residual recomputed at a replacement) */
+    int    max_iter;    /* CG iterations allowed */
     int    precision;   /* DG_PREC_FP64 or DG_PREC_MIXED */
-    double inner_rtol;  /* mixed mode: relative reduction of each FP32 inner solve */
-    int    check_every; /* iterations between host polls of the device
-                           convergence flag (0 = library default) */
+    int    precond;     /* DG_PRECOND_NONE or DG_PRECOND_FD (FP64 only) */
+    int    check_every; /* FP64: iterations between host polls of the device
+                           convergence flag; mixed: iterations between FP64
+                           residual replacements (0 = library default, 32) */
 } dg_cg_opts;
 
 typedef struct {
-    int    iters;         /* operator applications after r_0 (all inner ones in mixed mode) */
-    int    outer_iters;   /* mixed mode: FP64 refinement steps; FP64 mode: 0 */
+    int    iters;         /* CG iterations (operator applications after r_0) */
+    int    outer_iters;   /* mixed mode: FP64 residual replacements; otherwise 0 */
     double rel_residual;  /* final ||r||_W / ||b||_W (FP64 residual) */
-    int    converged;     /* 1 if the tolerance was met */
+    int    converged;     /* 1 if the tolerance was met; 2 (mixed mode only):
+                             the recursive residual met it and the FP64
+                             residual stopped decreasing above it, i.e. the
+                             solve reached the attainable FP64 accuracy
+                             (~ eps |Lap_h| |psi|); 0 otherwise */
 } dg_cg_stats;
 
 typedef struct {
@@ -124,9 +137,13 @@ size_t dg_field_elems(const dg_grid* grid);
 int  dg_grid_tables(const dg_grid* grid, double* out, int len);
 
 /* ----------------------------------------------------------- workspace --- */
-/* Device bytes a workspace for (grid, mode) holds: CG vectors r and p, the
- * two RK stage fields, reduction partials and scalars, plus FP32 copies in
- * DG_PREC_MIXED mode.  This is the figure that admission control budgets. */
+/* Device bytes a workspace for (grid, mode) holds: CG vectors x, r, p, the
+ * two RK stage fields, reduction partials and scalars, plus FP32 r and p in
+ * DG_PREC_MIXED mode, plus (DG_WS_FD) the preconditioner's z vector, two
+ * image-layout fields and the eigenbases (2 (nx n)^2 + 2 (ny n)^2 doubles,
+ * half that when the axes agree; rocBLAS keeps its own small workspace on
+ * top).  This is the figure that admission control budgets.  mode =
+ * DG_PREC_FP64 or DG_PREC_MIXED, optionally | DG_WS_FD. */
 int  dg_workspace_bytes(const dg_grid* grid, int mode, size_t* bytes);
 /* Allocate a workspace on the current device (hipMalloc + pinned host
  * scalars).  Errors: DG_E_INVAL, DG_E_NOMEM, DG_E_HIP. */
@@ -165,12 +182,32 @@ int  dg_laplace_apply(const dg_grid* grid, const double* f, double* out,
  * Gauss inner product (Sec. 6: symmetric system, CG; Sec. 4.1 eq. def_norm).
  * On entry psi holds the initial guess (its W-mean is removed); on exit the
  * zero-mean solution.  ||omega - mean|| = 0 gives psi = 0.  ws must be made
- * for this grid and, for DG_PREC_MIXED, in mixed mode.  Synchronises the
- * stream (convergence polling).  Returns DG_E_NOCONV when max_iter was hit
- * (psi holds the last iterate).  psi must not alias omega. */
+ * for this grid, in mixed mode for DG_PREC_MIXED and with DG_WS_FD for
+ * DG_PRECOND_FD (else DG_E_WORKSPACE).  Synchronises the stream
+ * (convergence polling).  Returns DG_E_NOCONV when max_iter was hit or the
+ * iteration broke down (psi holds the last iterate).  psi must not alias
+ * omega. */
 int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
                          const dg_cg_opts* opts, dg_cg_stats* stats,
                          dg_workspace* ws, void* stream);
+/* z = (-Lap_h)^+ r: the exact solution of -Lap_h z = r - mean_W(r) with
+ * W-mean zero, by fast diagonalisation -- the preconditioner DG_PRECOND_FD
+ * applies (beyond the paper, whose CG of Sec. 6 is unpreconditioned).  The
+ * 1D LDG operator of each axis is block circulant, so Bloch waves reduce it
+ * to n x n Hermitian (in the Gauss weights) symbols whose eigenvectors give
+ * a real W-orthonormal basis V with L V = V diag(lambda); then
+ * z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T on the image
+ * layout, the constant mode dropped.  r, z: canonical fields, z must not
+ * alias r.  ws must hold DG_WS_FD.  Asynchronous. */
+int  dg_precond_apply(const dg_grid* grid, const double* r, double* z,
+                      dg_workspace* ws, void* stream);
+/* The eigenbasis dg_precond_apply uses along one axis (axis 0: x, 1: y),
+ * built on the host from the Bloch symbols: V (host, (N n)^2 doubles,
+ * column-major, row = c n + i for cell c and node i, column = mode) with
+ * L V = V diag(lam) and V^T W V = I for the 1D LDG second derivative L and
+ * Gauss weights W of that axis; lam (host, N n doubles); *zero = the column
+ * of the constant mode.  Touches no GPU. */
+int  dg_grid_fd_basis(const dg_grid* grid, int axis, double* V, double* lam, int* zero);
 
 /* ------------------------------------------------------------ stepping --- */
 /* History of Poisson solutions used for the CG initial guess: the
@@ -235,7 +272,7 @@ int  dg_batch_member_bytes(const dg_grid* grid, size_t* bytes);
 /* 1 (default): replay captured HIP graphs; 0: launch kernels directly. */
 int  dg_batch_use_graphs(dg_batch* b, int on);
 /* One SSP-RK3 step of every attached instance (FP64 CG, opts->precision
- * must be DG_PREC_FP64).  iters_out, if not NULL, receives the CG
+ * must be DG_PREC_FP64 and opts->precond DG_PRECOND_NONE).  iters_out, if not NULL, receives the CG
  * iterations of slot i's stage k at [3 i + k] (capacity * 3 ints).
  * Synchronises the stream.  DG_E_NOCONV if some solve hit max_iter. */
 int  dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,

@@ -107,6 +107,11 @@ int check_ws(const dg_grid* g, const dg_workspace* ws) {
     return DG_OK;
 }
 
+bool valid_mode(int mode) {
+    const int prec = mode & ~DG_WS_FD;
+    return prec == DG_PREC_FP64 || prec == DG_PREC_MIXED;
+}
+
 size_t ws_bytes(const dg_grid* g, int mode) {
     const size_t F = g->elems * sizeof(double);
     const size_t L = l64_elems(g->geom);
@@ -114,8 +119,9 @@ size_t ws_bytes(const dg_grid* g, int mode) {
     if (blocks < pointwise_block_cap()) blocks = pointwise_block_cap();
     size_t b = 4 * L * sizeof(double) + 2 * F;          // x, r, p0, p1; s1, s2
     b += (size_t)blocks * 4 * sizeof(double);           // partials
-    b += 2 * sizeof(CgScalars) + kCntCount * sizeof(unsigned) + 4 * sizeof(double);
-    if (mode == DG_PREC_MIXED) b += 4 * L * sizeof(float);
+    b += sizeof(CgScalars) + kCntCount * sizeof(unsigned) + 4 * sizeof(double);
+    if ((mode & ~DG_WS_FD) == DG_PREC_MIXED) b += 3 * L * sizeof(float);
+    if (mode & DG_WS_FD) b += L * sizeof(double) + fd_bytes(g);
     return b;
 }
 
@@ -153,7 +159,7 @@ int harvest_profile(dg_workspace* ws, int slot, int device_iter) {
 }
 
 template <class T>
-int cg_loop(const Geom& geom, const OpConst<T>& k, T* x, T* r, T* p0, T* p1,
+int cg_loop(const Geom& geom, const OpConst<double>& k, T* x, T* r, T* p0, T* p1,
             CgScalars* sc, int max_iter, int check_every, dg_workspace* ws,
             hipStream_t s, CgScalars* final_host) {
     const int chunk = check_every > 0 ? check_every : 32;
@@ -223,7 +229,8 @@ int cg_fp64(const dg_grid* g, const double* omega, double* x, const double* pa,
     int rc = cg_loop<double>(g->geom, g->k64, ws->x, ws->r, ws->p0, ws->p1, ws->d.sc,
                              o.max_iter, o.check_every, ws, s, &fin);
     if (rc != DG_OK) return rc;
-    e = launch_cg_finish(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area, ws->d, s);
+    e = launch_cg_finish<double>(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area,
+                                 ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg finish launch");
     rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
     if (rc != DG_OK) return rc;
@@ -241,12 +248,13 @@ int cg_fp64(const dg_grid* g, const double* omega, double* x, const double* pa,
     return DG_OK;
 }
 
-// Mixed precision: the CG recurrences run in FP32 (lane-interleaved x32,
-// r32, p), the solution accumulates in FP64 (x64 = ws->x).  After every
-// segment of iterations, and whenever the FP32 recursive residual meets the
-// tolerance, the true residual of x64 + x32 is recomputed in FP64 and
-// replaces r32 while the recurrence continues (no restart), and x32 is
-// folded into x64.  Stops when ||r64||_W <= rtol ||b||_W.
+// Mixed precision: r and the directions p are stored in FP32 (lane-
+// interleaved r32, q0, q1), the solution x in FP64; every operator, update
+// and dot product is computed in FP64 (only the stores round).  After every
+// segment of check_every iterations (and whenever the recursive residual
+// meets the tolerance) the true residual of the FP64 solution is recomputed
+// in FP64 and replaces r32 while the recurrence continues (no restart).
+// Stops when that FP64 residual has ||r||_W <= rtol ||b||_W.
 int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
              double ca, const double* pb, double cb, const dg_cg_opts& o,
              dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
@@ -261,18 +269,16 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
     if (rc != DG_OK) return rc;
     CgScalars h = ws->host[2];
     if (!h.done) {
-        e = launch_mixed_start(g->geom, g->k64, ws->r, ws->r32, ws->e32, ws->d, s);
+        e = launch_mixed_start(g->geom, g->k64, ws->r, ws->r32, ws->d, s);
         if (e != hipSuccess) return hip_fail(e, "mixed start launch");
         for (;;) {
             for (int i = 0; i < segment; ++i) {
-                e = launch_cg_iter<float>(g->geom, g->k32, ws->e32, ws->r32, ws->q0,
+                e = launch_cg_iter<float>(g->geom, g->k64, ws->x, ws->r32, ws->q0,
                                           ws->q1, ws->d.sc, ws->d, s);
                 if (e != hipSuccess) return hip_fail(e, "mixed CG launch");
             }
-            e = launch_mixed_replace(g->geom, g->k64, omega, ws->x, ws->e32, ws->q0,
-                                     ws->q1, ws->r32, ws->d, s);
-            if (e == hipSuccess)
-                e = launch_mixed_accum(g->geom, ws->x, ws->e32, ws->q0, ws->q1, ws->d, s);
+            e = launch_mixed_replace(g->geom, g->k64, omega, ws->x, ws->q0, ws->q1,
+                                     ws->r32, ws->d, s);
             if (e != hipSuccess) return hip_fail(e, "mixed replacement launch");
             rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
             if (rc != DG_OK) return rc;
@@ -282,9 +288,10 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
     } else {
         h.rr_true = h.rr;
     }
-    // psi (canonical) = x64 (every pending update already folded in), minus
-    // its W-mean; b = 0 gives psi = 0
-    e = launch_cg_finish(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area, ws->d, s);
+    // psi (canonical) = x + the pending alpha p_last (FP32 directions),
+    // minus its W-mean; b = 0 gives psi = 0
+    e = launch_cg_finish<float>(g->geom, g->k64, ws->x, ws->q0, ws->q1, x, g->area,
+                                ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "cg finish launch");
     HIP_TRY(hipStreamSynchronize(s));
     const double rel = h.bb > 0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
@@ -300,17 +307,77 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
     return DG_OK;
 }
 
+// FP64 CG preconditioned by the fast-diagonalisation inverse of -Lap_h:
+// z = M r on the image layout (dense basis products), then the usual
+// direction / residual kernels with p built from z.  The host polls after
+// every iteration (an exact preconditioner converges in one or two).
+int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
+           double ca, const double* pb, double cb, const dg_cg_opts& o,
+           dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+    const double tol2 = o.rtol * o.rtol;
+    hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
+                                  tol2, o.max_iter, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg mean launch");
+    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, ws->x, ws->r, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg init launch");
+    int rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+    if (rc != DG_OK) return rc;
+    CgScalars h = ws->host[2];
+    while (!h.done) {
+        e = launch_to_image(g->geom, ws->r, true, ws->fd->img0, s);
+        if (e != hipSuccess) return hip_fail(e, "image conversion launch");
+        rc = fd_apply_image(ws->fd, s);
+        if (rc != DG_OK) return rc;
+        e = launch_from_image_dot(g->geom, g->k64, ws->fd->img0, ws->z, ws->r, ws->d, s);
+        if (e == hipSuccess)
+            e = launch_cg_dir<double>(g->geom, g->k64, ws->x, ws->z, ws->p0, ws->p1,
+                                      ws->d.sc, ws->d, s);
+        if (e == hipSuccess)
+            e = launch_cg_res<double>(g->geom, g->k64, ws->r, ws->p0, ws->p1, ws->d.sc,
+                                      ws->d, s);
+        if (e != hipSuccess) return hip_fail(e, "pcg iteration launch");
+        rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+        if (rc != DG_OK) return rc;
+        h = ws->host[2];
+    }
+    e = launch_cg_finish<double>(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area,
+                                 ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
+    HIP_TRY(hipStreamSynchronize(s));
+    const double rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    if (st) {
+        st->iters = h.iter;
+        st->outer_iters = 0;
+        st->rel_residual = rel;
+        st->converged = h.converged;
+    }
+    if (!h.converged)
+        return fail(DG_E_NOCONV, "preconditioned CG stopped after %d iterations, "
+                    "relative residual %.3e%s", h.iter, rel,
+                    h.breakdown ? " (breakdown or non-finite data)" : "");
+    return DG_OK;
+}
+
 int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* pa,
                 double ca, const double* pb, double cb, const dg_cg_opts* opts,
                 dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
     dg_cg_opts o;
     if (opts) o = *opts;
     else { o.rtol = 1e-12; o.max_iter = 100000; o.precision = DG_PREC_FP64;
-           o.inner_rtol = 1e-5; o.check_every = 0; }
+           o.precond = DG_PRECOND_NONE; o.check_every = 0; }
     if (!(o.rtol > 0) || o.max_iter < 0)
         return fail(DG_E_INVAL, "rtol must be > 0 and max_iter >= 0");
+    if (o.precond != DG_PRECOND_NONE && o.precond != DG_PRECOND_FD)
+        return fail(DG_E_INVAL, "unknown preconditioner %d", o.precond);
+    if (o.precond == DG_PRECOND_FD) {
+        if (o.precision != DG_PREC_FP64)
+            return fail(DG_E_UNSUPPORTED, "the preconditioned solve is FP64 only");
+        if (!ws->fd)
+            return fail(DG_E_WORKSPACE, "preconditioning needs a DG_WS_FD workspace");
+        return cg_pcg(g, omega, x, pa, ca, pb, cb, o, st, ws, s);
+    }
     if (o.precision == DG_PREC_MIXED) {
-        if (ws->mode != DG_PREC_MIXED)
+        if ((ws->mode & ~DG_WS_FD) != DG_PREC_MIXED)
             return fail(DG_E_WORKSPACE, "mixed precision needs a DG_PREC_MIXED workspace");
         return cg_mixed(g, omega, x, pa, ca, pb, cb, o, st, ws, s);
     }
@@ -347,7 +414,6 @@ int dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
     g->area = (x1 - x0) * (y1 - y0);
     if (!build_tables(n, &g->t)) { delete g; return fail(DG_E_INVAL, "table build failed"); }
     fill_const(*g, g->k64);
-    fill_const(*g, g->k32);
     g->geom = Geom{n, nx, ny};
     g->elems = (size_t)nx * ny * n * n;
     *out = g;
@@ -373,7 +439,7 @@ int dg_grid_tables(const dg_grid* g, double* out, int len) {
 
 int dg_workspace_bytes(const dg_grid* g, int mode, size_t* bytes) {
     if (!g || !bytes) return fail(DG_E_INVAL, "NULL argument");
-    if (mode != DG_PREC_FP64 && mode != DG_PREC_MIXED) return fail(DG_E_INVAL, "bad mode");
+    if (!valid_mode(mode)) return fail(DG_E_INVAL, "bad mode %d", mode);
     *bytes = ws_bytes(g, mode);
     return DG_OK;
 }
@@ -383,11 +449,12 @@ void dg_workspace_destroy(dg_workspace* ws) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ws->device);
-    void* bufs[] = {ws->x, ws->r, ws->p0, ws->p1, ws->s1, ws->s2, ws->r32, ws->e32,
-                    ws->q0, ws->q1, ws->d.sc, ws->d.counters, ws->d.partials,
-                    ws->d.out3, ws->inner};
+    void* bufs[] = {ws->x, ws->r, ws->p0, ws->p1, ws->s1, ws->s2, ws->r32,
+                    ws->q0, ws->q1, ws->z, ws->d.sc, ws->d.counters, ws->d.partials,
+                    ws->d.out3};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    fd_destroy(ws->fd);
     if (ws->host) (void)hipHostFree(ws->host);
     for (auto& e : ws->ev) if (e) (void)hipEventDestroy(e);
     for (auto& e : ws->tev) if (e) (void)hipEventDestroy(e);
@@ -400,7 +467,7 @@ void dg_workspace_destroy(dg_workspace* ws) {
 int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
     *out = nullptr;
-    if (mode != DG_PREC_FP64 && mode != DG_PREC_MIXED) return fail(DG_E_INVAL, "bad mode");
+    if (!valid_mode(mode)) return fail(DG_E_INVAL, "bad mode %d", mode);
     dg_workspace* ws = new (std::nothrow) dg_workspace;
     if (!ws) return fail(DG_E_NOMEM, "host allocation failed");
     std::memset(ws, 0, sizeof *ws);
@@ -422,15 +489,15 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
               alloc((void**)&ws->p1, L * sizeof(double)) &&
               alloc((void**)&ws->s1, F) && alloc((void**)&ws->s2, F) &&
               alloc((void**)&ws->d.sc, sizeof(CgScalars)) &&
-              alloc((void**)&ws->inner, sizeof(CgScalars)) &&
               alloc((void**)&ws->d.counters, kCntCount * sizeof(unsigned)) &&
               alloc((void**)&ws->d.partials, (size_t)blocks * 4 * sizeof(double)) &&
               alloc((void**)&ws->d.out3, 4 * sizeof(double));
-    if (ok && mode == DG_PREC_MIXED) {
+    if (ok && (mode & ~DG_WS_FD) == DG_PREC_MIXED) {
         const size_t f32 = L * sizeof(float);
-        ok = alloc((void**)&ws->r32, f32) && alloc((void**)&ws->e32, f32) &&
-             alloc((void**)&ws->q0, f32) && alloc((void**)&ws->q1, f32);
+        ok = alloc((void**)&ws->r32, f32) && alloc((void**)&ws->q0, f32) &&
+             alloc((void**)&ws->q1, f32);
     }
+    if (ok && (mode & DG_WS_FD)) ok = alloc((void**)&ws->z, L * sizeof(double));
     if (ok) ok = hipHostMalloc((void**)&ws->host, 4 * sizeof(CgScalars)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -459,9 +526,12 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     // counters must start at zero (each reduction resets its own)
     e = hipMemset(ws->d.counters, 0, kCntCount * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(ws->d.sc, 0, sizeof(CgScalars));
-    if (e == hipSuccess) e = hipMemset(ws->inner, 0, sizeof(CgScalars));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { dg_workspace_destroy(ws); return hip_fail(e, "workspace init"); }
+    if (mode & DG_WS_FD) {
+        const int rc = fd_create(g, &ws->fd);
+        if (rc != DG_OK) { dg_workspace_destroy(ws); return rc; }
+    }
     ws->bytes = ws_bytes(g, mode);
     *out = ws;
     return DG_OK;
@@ -514,6 +584,38 @@ int dg_laplace_apply(const dg_grid* g, const double* f, double* out, void* strea
         return fail(DG_E_ALIAS, "out aliases f");
     hipError_t e = launch_laplace(g->geom, g->k64, f, out, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "laplace launch");
+    return DG_OK;
+}
+
+int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* zero) {
+    if (!g || !V || !lam || !zero) return fail(DG_E_INVAL, "NULL argument");
+    if (axis != 0 && axis != 1) return fail(DG_E_INVAL, "axis must be 0 (x) or 1 (y)");
+    FdAxis a;
+    double err = 0.0;
+    const bool ok = axis == 0 ? fd_axis_basis(g->t, g->nx, g->hx, &a, &err)
+                              : fd_axis_basis(g->t, g->ny, g->hy, &a, &err);
+    if (!ok || err > 1e-10) return fail(DG_E_INVAL, "eigenbasis construction failed (defect %.3e)", err);
+    std::memcpy(V, a.V.data(), a.V.size() * sizeof(double));
+    std::memcpy(lam, a.lam.data(), a.lam.size() * sizeof(double));
+    *zero = a.zero;
+    return DG_OK;
+}
+
+int dg_precond_apply(const dg_grid* g, const double* r, double* z, dg_workspace* ws,
+                     void* stream) {
+    if (!g || !r || !z) return fail(DG_E_INVAL, "NULL argument");
+    int rc = check_ws(g, ws);
+    if (rc != DG_OK) return rc;
+    if (!ws->fd) return fail(DG_E_WORKSPACE, "the workspace has no DG_WS_FD preconditioner");
+    if (ranges_overlap(z, r, g->elems * sizeof(double)))
+        return fail(DG_E_ALIAS, "z aliases r");
+    const hipStream_t s = as_stream(stream);
+    hipError_t e = launch_to_image(g->geom, r, false, ws->fd->img0, s);
+    if (e != hipSuccess) return hip_fail(e, "image conversion launch");
+    rc = fd_apply_image(ws->fd, s);
+    if (rc != DG_OK) return rc;
+    e = launch_from_image(g->geom, ws->fd->img0, z, s);
+    if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }
 

@@ -8,6 +8,7 @@
 
 #include "../../include/dgark.h"
 #include "dg_internal.h"
+#include "fd_basis.h"
 
 using dgk::HostTables; using dgk::OpConst; using dgk::Geom; using dgk::DevScratch; using dgk::CgScalars;
 
@@ -16,7 +17,6 @@ struct dg_grid {
     double x0, x1, y0, y1, hx, hy, area;
     HostTables t;
     OpConst<double> k64;
-    OpConst<float> k32;
     Geom geom;
     size_t elems;
 };
@@ -26,10 +26,11 @@ struct dg_workspace {
     size_t elems;
     double *x, *r, *p0, *p1;   // CG vectors, lane-interleaved layout
     double *s1, *s2;           // RK stage fields, canonical layout
-    float *r32, *e32, *q0, *q1;  // mixed-precision inner CG vectors
+    float *r32, *q0, *q1;      // mixed precision: FP32 residual and directions
+    double* z;                 // preconditioned residual (DG_WS_FD workspaces)
+    dgk::FdDevice* fd;         // fast-diagonalisation preconditioner, or NULL
     DevScratch d;
-    CgScalars* inner;          // device scalars of the mixed inner solve
-    CgScalars* host;           // pinned, 4 slots (2 poll slots x {outer, inner})
+    CgScalars* host;           // pinned, 4 slots (2 poll slots + 2 spare)
     hipEvent_t ev[2];
     hipEvent_t tev[4];
     size_t bytes;
@@ -60,6 +61,12 @@ void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
                  const double** pb, double* cb, double** x, int* xi);
 // Record that buffer xi now holds the solve at time ts.
 void state_push(dg_state* st, int xi, double ts);
+// Fast-diagonalisation preconditioner resources (fd_apply.cpp): device bytes,
+// creation / destruction, and z = M r on the image buffer img0 in place.
+size_t fd_bytes(const dg_grid* g);
+int fd_create(const dg_grid* g, FdDevice** out);
+void fd_destroy(FdDevice* fd);
+int fd_apply_image(const FdDevice* fd, hipStream_t s);
 }  // namespace dgk
 
 #define HIP_TRY(call)                                          \

@@ -329,9 +329,9 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
     dg_cg_opts o;
     if (opts) o = *opts;
     else { o.rtol = 1e-12; o.max_iter = 100000; o.precision = DG_PREC_FP64;
-           o.inner_rtol = 1e-5; o.check_every = 0; }
-    if (o.precision != DG_PREC_FP64)
-        return fail(DG_E_UNSUPPORTED, "batches run the FP64 CG only");
+           o.precond = DG_PRECOND_NONE; o.check_every = 0; }
+    if (o.precision != DG_PREC_FP64 || o.precond != DG_PRECOND_NONE)
+        return fail(DG_E_UNSUPPORTED, "batches run the unpreconditioned FP64 CG only");
     if (!(o.rtol > 0) || o.max_iter < 0) return fail(DG_E_INVAL, "bad CG options");
     hipStream_t s = (hipStream_t)stream;
     int used = 0;

@@ -89,19 +89,27 @@ __device__ __forceinline__ void st_canon(T* __restrict__ f, const CellRef& c,
     for (int e = 0; e < N * N; ++e) f[c.canon + e] = u[e];
 }
 
-template <int N, class T>
-__device__ __forceinline__ void ld_l64(const T* __restrict__ f, const CellRef& c,
-                                       T (&u)[N * N]) {
+// L64 loads and stores convert between the storage type S of a CG vector
+// and the FP64 arithmetic of the kernels.
+template <int N, class S, class C>
+__device__ __forceinline__ void ld_l64(const S* __restrict__ f, const CellRef& c,
+                                       C (&u)[N * N]) {
 #pragma unroll
-    for (int e = 0; e < N * N; ++e) u[e] = f[c.l64 + 64 * e];
+    for (int e = 0; e < N * N; ++e) u[e] = (C)f[c.l64 + 64 * e];
 }
 
-template <int N, class T>
-__device__ __forceinline__ void st_l64(T* __restrict__ f, const CellRef& c,
-                                       const T (&u)[N * N]) {
+template <int N, class S, class C>
+__device__ __forceinline__ void st_l64(S* __restrict__ f, const CellRef& c,
+                                       const C (&u)[N * N]) {
 #pragma unroll
-    for (int e = 0; e < N * N; ++e) f[c.l64 + 64 * e] = u[e];
+    for (int e = 0; e < N * N; ++e) f[c.l64 + 64 * e] = (S)u[e];
 }
+
+// Round a value to the storage type S and back: the value a stored vector
+// will hold, so that an operator applied in registers sees exactly the
+// stored vector.  The identity for S = double.
+template <class S>
+__device__ __forceinline__ double as_stored(double v) { return (double)(S)v; }
 
 // Face scalars of a cell u (n x n, [j][i]) along x for node row j and along
 // y for node column i, with weights w.
@@ -220,25 +228,38 @@ struct SrcCanon {                       // u = f (canonical layout)
     __device__ void operator()(const CellRef& c, T (&u)[N * N]) const { ld_canon<N>(f, c, u); }
 };
 
-template <int N, class T>
-struct SrcL64 {                         // u = f (L64 layout)
-    const T* f;
-    __device__ void operator()(const CellRef& c, T (&u)[N * N]) const { ld_l64<N>(f, c, u); }
+template <int N, class S>
+struct SrcL64 {                         // u = f (L64 layout, stored as S)
+    const S* f;
+    __device__ void operator()(const CellRef& c, double (&u)[N * N]) const {
+        ld_l64<N>(f, c, u);
+    }
 };
 
-template <int N, class T>
-struct SrcDirection {                   // p = r (first) or r + beta p_old, L64
-    const T* r;
-    const T* p;
-    T beta;
+// FP32-stored recurrences (mixed precision) take the exact line-search step
+// alpha = <r,p>/<p,Ap> (equal to <r,r>/<p,Ap> without rounding, and still a
+// descent step once rounding has cost r its orthogonality to p_old), and,
+// right after a residual replacement, the direction p = cr r + beta p_old
+// (mixed_replace_body).
+template <class S>
+constexpr bool kStoredLow = sizeof(S) < sizeof(double);
+
+template <int N, class S>
+struct SrcDirection {                   // p = r (first) or cr r + beta p_old, L64
+    const S* r;
+    const S* p;
+    double beta, cr;
     bool first;
-    __device__ void operator()(const CellRef& c, T (&u)[N * N]) const {
+    __device__ void operator()(const CellRef& c, double (&u)[N * N]) const {
         ld_l64<N>(r, c, u);
         if (!first) {
-            T q[N * N];
+            double q[N * N];
             ld_l64<N>(p, c, q);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] = fmx(beta, q[e], u[e]);
+            for (int e = 0; e < N * N; ++e) {
+                const double ru = kStoredLow<S> ? cr * u[e] : u[e];
+                u[e] = as_stored<S>(fmx(beta, q[e], ru));
+            }
         }
     }
 };
@@ -322,6 +343,7 @@ __device__ __forceinline__ void cg_init_body(
     if (reduce_last<2, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         sc->rr = tot[0];
+        sc->rz = tot[0];
         sc->bb = tot[1];
         sc->first = 1;
         sc->iter = 0;
@@ -341,62 +363,69 @@ __device__ __forceinline__ void cg_init_body(
     }
 }
 
-// CG iteration, first half (L64 vectors):
+// CG iteration, first half (L64 vectors r, p stored as S, x in FP64, FP64
+// arithmetic):
 //   x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};  q = A p_k;
 //   alpha_k = <r,r>_W / <p_k, q>_W.
 // p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
-// neighbouring tiles while p_k is written.
-template <int N, class T>
+// neighbouring tiles while p_k is written.  q is applied to p_k as stored.
+template <int N, class S>
 __device__ __forceinline__ void cg_dir_body(
-    int b, Geom g, int tilesX, int nblocks, const OpConst<T>& k, const T* __restrict__ r,
-    T* p0, T* p1, T* __restrict__ x,
+    int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
+    const S* __restrict__ r, S* p0, S* p1, double* __restrict__ x,
     CgScalars* sc, unsigned* counter, double* partials,
-    YFaces<N, T>& lds) {
+    YFaces<N, double>& lds) {
     if (sc->done) return;
     // iteration k reads p_{k-1} from buffer k mod 2 and writes p_k to the other
-    const T* pin = (sc->iter & 1) ? p1 : p0;
-    T* pout = (sc->iter & 1) ? p0 : p1;
+    const S* pin = (sc->iter & 1) ? p1 : p0;
+    S* pout = (sc->iter & 1) ? p0 : p1;
     const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
-    // first = 1: p = r; 0: x += alpha p_old, p = r + beta p_old;
-    // 2 (after a residual replacement that already applied alpha p_old):
-    // p = r + beta p_old only
+    // first = 1: p = r; otherwise x += alpha p_old, p = r + beta p_old
     const int first = sc->first;
-    const T alpha = (T)sc->alpha;
-    SrcDirection<N, T> src{r, pin, (T)sc->beta, first == 1};
-    T p[N * N], q[N * N];
+    const double alpha = sc->alpha;
+    SrcDirection<N, S> src{r, pin, sc->beta, sc->cr, first == 1};
+    double p[N * N], q[N * N], rv[N * N];
     if (c.active) {
         ld_l64<N>(r, c.self, p);
+#pragma unroll
+        for (int e = 0; e < N * N; ++e) rv[e] = p[e];
         if (first != 1) {
-            T po[N * N];
+            double po[N * N];
             ld_l64<N>(pin, c.self, po);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) p[e] = fmx(src.beta, po[e], p[e]);
-            if (first == 0) {
-                T xv[N * N];
-                ld_l64<N>(x, c.self, xv);
-#pragma unroll
-                for (int e = 0; e < N * N; ++e) xv[e] = fmx(alpha, po[e], xv[e]);
-                st_l64<N>(x, c.self, xv);
+            for (int e = 0; e < N * N; ++e) {
+                const double ru = kStoredLow<S> ? src.cr * p[e] : p[e];
+                p[e] = as_stored<S>(fmx(src.beta, po[e], ru));
             }
+            double xv[N * N];
+            ld_l64<N>(x, c.self, xv);
+#pragma unroll
+            for (int e = 0; e < N * N; ++e) xv[e] = fmx(alpha, po[e], xv[e]);
+            st_l64<N>(x, c.self, xv);
         }
     } else {
         zero_cell<N>(p);
     }
     lap_cell<N>(c, k, src, p, lds, q);
-    double part[1] = {0.0};
+    constexpr int NV = kStoredLow<S> ? 2 : 1;
+    double part[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) part[v] = 0.0;
     if (c.active) {
         st_l64<N>(pout, c.self, p);
 #pragma unroll
         for (int e = 0; e < N * N; ++e) q[e] = -q[e];
         part[0] = wdot_cell<N>(k, p, q);
+        if (kStoredLow<S>) part[NV - 1] = wdot_cell<N>(k, rv, p);
     }
-    double tot[1];
-    if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    double tot[NV];
+    if (reduce_last<NV, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         sc->pq = tot[0];
         sc->first = 0;
+        sc->cr = 1.0;
         if (tot[0] > 0.0 && tot[0] == tot[0]) {
-            sc->alpha = sc->rr / tot[0];
+            sc->alpha = (kStoredLow<S> ? tot[NV - 1] : sc->rz) / tot[0];
         } else {  // breakdown (or non-finite data): stop, x is current
             sc->done = 1;
             sc->breakdown = 1;
@@ -406,18 +435,18 @@ __device__ __forceinline__ void cg_dir_body(
 }
 
 // CG iteration, second half: q = A p_k; r -= alpha q; beta = <r,r>new/<r,r>;
-// convergence test ||r||_W^2 <= tol^2 ||b||_W^2.
-template <int N, class T>
+// convergence test ||r||_W^2 <= tol^2 ||b||_W^2 on r as stored.
+template <int N, class S>
 __device__ __forceinline__ void cg_res_body(
-    int b, Geom g, int tilesX, int nblocks, const OpConst<T>& k, const T* p0,
-    const T* p1, T* __restrict__ r, CgScalars* sc, unsigned* counter,
-    double* partials, YFaces<N, T>& lds) {
+    int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k, const S* p0,
+    const S* p1, S* __restrict__ r, CgScalars* sc, unsigned* counter,
+    double* partials, YFaces<N, double>& lds) {
     if (sc->done) return;
-    const T* p = (sc->iter & 1) ? p0 : p1;   // p_k written by this iteration's direction update
+    const S* p = (sc->iter & 1) ? p0 : p1;   // p_k written by this iteration's direction update
     const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
-    const T alpha = (T)sc->alpha;
-    SrcL64<N, T> src{p};
-    T pv[N * N], q[N * N], rv[N * N];
+    const double alpha = sc->alpha;
+    SrcL64<N, S> src{p};
+    double pv[N * N], q[N * N], rv[N * N];
     if (c.active) {
         src(c.self, pv);
         ld_l64<N>(r, c.self, rv);
@@ -428,7 +457,7 @@ __device__ __forceinline__ void cg_res_body(
     double part[1] = {0.0};
     if (c.active) {
 #pragma unroll
-        for (int e = 0; e < N * N; ++e) rv[e] = fmx(alpha, q[e], rv[e]);
+        for (int e = 0; e < N * N; ++e) rv[e] = as_stored<S>(fmx(alpha, q[e], rv[e]));
         st_l64<N>(r, c.self, rv);
         part[0] = wdot_cell<N>(k, rv, rv);
     }
@@ -436,8 +465,12 @@ __device__ __forceinline__ void cg_res_body(
     if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         const double rrn = tot[0];
-        sc->beta = rrn / sc->rr;
+        if (!sc->precond) {           // plain CG: z = r
+            sc->beta = rrn / sc->rz;
+            sc->rz = rrn;
+        }
         sc->rr = rrn;
+        if (kStoredLow<S> && rrn > sc->rr_max) sc->rr_max = rrn;
         sc->iter += 1;
         if (rrn <= sc->tol2 * sc->bb) {
             sc->done = 1;
@@ -451,91 +484,107 @@ __device__ __forceinline__ void cg_res_body(
     }
 }
 
-// Mixed precision, residual replacement: with the FP64 solution
-// x = x64 + x32 + alpha p_last (the FP32 accumulator and the direction
-// update the next iteration would apply), the true residual
-// r64 = (omega - mean(omega)) + Lap_h x is computed in FP64 and replaces the
-// FP32 recursive residual (r32 = float(r64)).  Partials <r64,r64>, <r32,r32>.
-// The last block tests convergence on the FP64 residual; otherwise the CG
-// recurrence continues: beta is rescaled to the replaced residual and the
-// next direction update must not apply alpha p_last again (first = 2),
-// because the accumulation kernel that follows folds it into x64.
+// Mixed precision, residual replacement.  r and p are stored in FP32, the
+// solution x in FP64; x lags by the update alpha p_last that the next
+// direction kernel applies (after any iteration, unless the direction
+// update broke down, having applied it itself).  A replacement is made when
+// the recursive residual has dropped by delta^2 = 1e-2 in <r,r> below its
+// largest value since the last replacement, or the recurrence stopped
+// (tolerance met by the recursive residual, max_iter, breakdown); otherwise
+// the kernel exits at once.  It computes the true residual of x +
+// alpha p_last in FP64, r64 = (omega - mean(omega)) + Lap_h (x + alpha p_last),
+// stores r32 = float(r64), and tests convergence on r64.  An FP64 residual
+// cannot be evaluated more accurately than ~ eps_64 |Lap_h| |x|, which for
+// stiff grids exceeds small tolerances; so the solve also ends (converged =
+// 2, "at the attainable accuracy") when the recursive residual had met the
+// tolerance but the true one fell by less than 2x since the previous
+// replacement.  If the solve goes
+// on, the next direction is p = cr r32 + beta p_last with beta rescaled to
+// the replaced residual and cr = 1 - beta <r32, p_last> / <r32, r32>, so that
+// p_last's component along the new residual is removed first (it would be
+// zero without rounding).  Partials <r64,r64>_W, <r32,r32>_W, <r32,p_last>_W.
 template <int N>
 struct SrcMixedX {
-    const double* x64;
-    const float* x32;
+    const double* x;
     const float* pl;
     double alpha;
     bool pending;
     __device__ void operator()(const CellRef& c, double (&u)[N * N]) const {
-        float a[N * N];
-        ld_l64<N>(x64, c, u);
-        ld_l64<N>(x32, c, a);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) u[e] += (double)a[e];
+        ld_l64<N>(x, c, u);
         if (pending) {
-            float q[N * N];
+            double q[N * N];
             ld_l64<N>(pl, c, q);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) u[e] = fmx(alpha, (double)q[e], u[e]);
+            for (int e = 0; e < N * N; ++e) u[e] = fmx(alpha, q[e], u[e]);
         }
     }
 };
 
+constexpr double kReplaceDrop2 = 1e-2;
+
 template <int N>
 __device__ __forceinline__ void mixed_replace_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
-    const double* __restrict__ omega, const double* __restrict__ x64,
-    const float* __restrict__ x32, const float* __restrict__ q0,
-    const float* __restrict__ q1, float* __restrict__ r32, CgScalars* sc,
-    unsigned* counter, double* partials, YFaces<N, double>& lds) {
+    const double* __restrict__ omega, const double* __restrict__ x,
+    const float* __restrict__ q0, const float* __restrict__ q1,
+    float* __restrict__ r32, CgScalars* sc, unsigned* counter, double* partials,
+    YFaces<N, double>& lds) {
+    if (!sc->done && !(sc->rr <= kReplaceDrop2 * sc->rr_max)) return;
     const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
-    // alpha p_last is still owed to x when an iteration ran since the last
-    // replacement, unless the direction update broke down (it had applied
-    // the previous alpha p itself)
-    const bool pending = sc->iter > sc->iter_repl && !sc->breakdown;
-    SrcMixedX<N> src{x64, x32, (sc->iter & 1) ? q1 : q0, sc->alpha, pending};
+    const bool pending = sc->first != 1 && !sc->breakdown;
+    const float* pl = (sc->iter & 1) ? q1 : q0;
+    SrcMixedX<N> src{x, pl, sc->alpha, pending};
     const double mo = sc->mean_omega;
     double v[N * N], lap[N * N];
     if (c.active) src(c.self, v);
     else zero_cell<N>(v);
     lap_cell<N>(c, k, src, v, lds, lap);
-    double part[2] = {0.0, 0.0};
+    double part[3] = {0.0, 0.0, 0.0};
     if (c.active) {
-        double w[N * N], rd[N * N];
-        float rf[N * N];
+        double w[N * N], rd[N * N], pv[N * N];
         ld_canon<N>(omega, c.self, w);
+        ld_l64<N>(pl, c.self, pv);
 #pragma unroll
         for (int e = 0; e < N * N; ++e) {
             lap[e] += w[e] - mo;
-            rf[e] = (float)lap[e];
-            rd[e] = (double)rf[e];
+            rd[e] = as_stored<float>(lap[e]);
         }
-        st_l64<N>(r32, c.self, rf);
+        st_l64<N>(r32, c.self, rd);
         part[0] = wdot_cell<N>(k, lap, lap);
         part[1] = wdot_cell<N>(k, rd, rd);
+        part[2] = wdot_cell<N>(k, rd, pv);
     }
-    double tot[2];
-    if (reduce_last<2, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    double tot[3];
+    if (reduce_last<3, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
+        const bool rec_met = sc->rr <= sc->tol2 * sc->bb;
+        const double prev = sc->rr_true_prev;
         sc->rr_true = tot[0];
-        sc->accum_pending = pending ? 1 : 0;
-        sc->accum_alpha = sc->alpha;
-        sc->iter_repl = sc->iter;
-        sc->pending = 0;
+        sc->rr_true_prev = tot[0];
         sc->outer += 1;
         if (tot[0] <= sc->tol2 * sc->bb) {
             sc->done = 1;
             sc->converged = 1;
+            sc->pending = pending ? 1 : 0;
         } else if (sc->iter >= sc->max_iter || sc->breakdown || !(tot[0] == tot[0])) {
             sc->done = 1;
             sc->converged = 0;
+            sc->pending = pending ? 1 : 0;
+        } else if (rec_met && tot[0] > 0.25 * prev) {
+            sc->done = 1;
+            sc->converged = 2;
+            sc->pending = pending ? 1 : 0;
         } else {
-            if (sc->first != 1) sc->beta *= tot[1] / sc->rr;
+            if (sc->first != 1) {
+                sc->beta *= tot[1] / sc->rz;
+                sc->cr = 1.0 - sc->beta * tot[2] / tot[1];
+            }
             sc->rr = tot[1];
-            sc->first = (sc->first == 1) ? 1 : 2;
+            sc->rz = tot[1];
+            sc->rr_max = tot[1];
             sc->done = 0;
             sc->converged = 0;
+            sc->pending = 0;
         }
     }
 }

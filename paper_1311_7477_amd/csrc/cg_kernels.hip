@@ -26,35 +26,34 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cg_init(
                     r, sc, counter, partials, lds);
 }
 
-template <int N, class T>
+template <int N, class S>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_dir(
-    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* __restrict__ r,
-    T* p0, T* p1, T* __restrict__ x, CgScalars* sc, unsigned* counter,
+    Geom g, int tilesX, int nblocks, OpConst<double> k, const S* __restrict__ r,
+    S* p0, S* p1, double* __restrict__ x, CgScalars* sc, unsigned* counter,
     double* partials) {
-    __shared__ YFaces<N, T> lds;
-    cg_dir_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
+    __shared__ YFaces<N, double> lds;
+    cg_dir_body<N, S>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
                       counter, partials, lds);
 }
 
-template <int N, class T>
+template <int N, class S>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cg_res(
-    Geom g, int tilesX, int nblocks, OpConst<T> k, const T* p0, const T* p1,
-    T* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
-    __shared__ YFaces<N, T> lds;
-    cg_res_body<N, T>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
+    Geom g, int tilesX, int nblocks, OpConst<double> k, const S* p0, const S* p1,
+    S* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
+    __shared__ YFaces<N, double> lds;
+    cg_res_body<N, S>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
                       partials, lds);
 }
 
 template <int N>
 __global__ __launch_bounds__(64 * kCellWaves) void k_mixed_replace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
-    const double* __restrict__ omega, const double* __restrict__ x64,
-    const float* __restrict__ x32, const float* __restrict__ q0,
-    const float* __restrict__ q1, float* __restrict__ r32, CgScalars* sc,
-    unsigned* counter, double* partials) {
+    const double* __restrict__ omega, const double* __restrict__ x,
+    const float* __restrict__ q0, const float* __restrict__ q1,
+    float* __restrict__ r32, CgScalars* sc, unsigned* counter, double* partials) {
     __shared__ YFaces<N, double> lds;
-    mixed_replace_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, x64, x32, q0,
-                          q1, r32, sc, counter, partials, lds);
+    mixed_replace_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, x, q0, q1, r32,
+                          sc, counter, partials, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -83,60 +82,59 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_cg_dir(const Geom& g, const OpConst<T>& k, T* x, T* r, T* p0,
-                         T* p1, CgScalars* sc, const DevScratch& d, hipStream_t s) {
+template <class S>
+hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* r, S* p0,
+                         S* p1, CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, T>), dim3(L.nblocks),
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S>), dim3(L.nblocks),
                                           dim3(64 * kCellWaves), 0, s, g, L.tilesX,
                                           L.nblocks, k, r, p0, p1, x, sc,
                                           d.counters + kCntDir, d.partials));
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_cg_res(const Geom& g, const OpConst<T>& k, T* r, T* p0, T* p1,
+template <class S>
+hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
                          CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, T>), dim3(L.nblocks),
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S>), dim3(L.nblocks),
                                           dim3(64 * kCellWaves), 0, s, g, L.tilesX,
                                           L.nblocks, k, p0, p1, r, sc,
                                           d.counters + kCntRes, d.partials));
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_cg_iter(const Geom& g, const OpConst<T>& k, T* x, T* r,
-                          T* p0, T* p1, CgScalars* sc, const DevScratch& d,
+template <class S>
+hipError_t launch_cg_iter(const Geom& g, const OpConst<double>& k, double* x, S* r,
+                          S* p0, S* p1, CgScalars* sc, const DevScratch& d,
                           hipStream_t s) {
-    hipError_t e = launch_cg_dir<T>(g, k, x, r, p0, p1, sc, d, s);
+    hipError_t e = launch_cg_dir<S>(g, k, x, r, p0, p1, sc, d, s);
     if (e != hipSuccess) return e;
-    return launch_cg_res<T>(g, k, r, p0, p1, sc, d, s);
+    return launch_cg_res<S>(g, k, r, p0, p1, sc, d, s);
 }
 
-#define DG_INST(T)                                                             \
-    template hipError_t launch_cg_dir<T>(const Geom&, const OpConst<T>&, T*, T*, \
-                                         T*, T*, CgScalars*, const DevScratch&,  \
+#define DG_INST(S)                                                             \
+    template hipError_t launch_cg_dir<S>(const Geom&, const OpConst<double>&,   \
+                                         double*, S*, S*, S*, CgScalars*,       \
+                                         const DevScratch&, hipStream_t);       \
+    template hipError_t launch_cg_res<S>(const Geom&, const OpConst<double>&, S*, \
+                                         S*, S*, CgScalars*, const DevScratch&, \
                                          hipStream_t);                          \
-    template hipError_t launch_cg_res<T>(const Geom&, const OpConst<T>&, T*, T*, \
-                                         T*, CgScalars*, const DevScratch&,     \
-                                         hipStream_t);                          \
-    template hipError_t launch_cg_iter<T>(const Geom&, const OpConst<T>&, T*,   \
-                                          T*, T*, T*, CgScalars*,               \
+    template hipError_t launch_cg_iter<S>(const Geom&, const OpConst<double>&,  \
+                                          double*, S*, S*, S*, CgScalars*,      \
                                           const DevScratch&, hipStream_t);
 DG_INST(double)
 DG_INST(float)
 #undef DG_INST
 
 hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
-                                const double* omega, const double* x64,
-                                const float* x32, const float* q0,
+                                const double* omega, const double* x, const float* q0,
                                 const float* q1, float* r32, const DevScratch& d,
                                 hipStream_t s) {
     CellLaunch L(g);
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_replace<NN>), dim3(L.nblocks),
                                           dim3(64 * kCellWaves), 0, s, g, L.tilesX,
-                                          L.nblocks, k, omega, x64, x32, q0, q1, r32,
+                                          L.nblocks, k, omega, x, q0, q1, r32,
                                           d.sc, d.counters + kCntDot, d.partials));
     return hipGetLastError();
 }

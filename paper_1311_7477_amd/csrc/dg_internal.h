@@ -52,6 +52,7 @@ struct RhsArgs {
 // Device-side scalars of one CG solve (lives in the workspace).
 struct CgScalars {
     double rr;        // <r, r>_W of the current residual
+    double rz;        // <r, z>_W with z = M r (preconditioned); = rr for plain CG
     double bb;        // <b, b>_W
     double pq;        // <p, A p>_W
     double alpha, beta;
@@ -60,12 +61,16 @@ struct CgScalars {
     double ww;        // <omega, omega>_W
     double zero_tol2; // b counts as zero when <b,b>_W <= zero_tol2 * ww
     double ca, cb;    // guess = ca * psi_a + cb * psi_b (device copies)
-    // mixed precision: FP64 residual of the last replacement, the direction
-    // update it folded into the FP64 solution, and the iteration it ran at
-    double rr_true, accum_alpha;
-    int iter_repl, accum_pending, outer;
+    // mixed precision: <r,r>_W of the FP64 residual at the last replacement,
+    // and the number of replacements
+    double rr_true, rr_true_prev;
+    double rr_max;    // largest recursive <r,r>_W since the last replacement
+    double cr;        // coefficient of r in the next direction (1 but right
+                      // after a replacement)
+    int outer;
     int iter, max_iter;
     int done, converged, pending, first, zero, breakdown;
+    int precond;      // 1: beta and rz come from the preconditioned dot kernel
 };
 
 // Counters for the last-block-done reductions, one per kernel kind.

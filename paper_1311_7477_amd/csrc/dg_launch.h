@@ -41,22 +41,25 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                           const double* omega, const double* pa,
                           const double* pb, double ca, double cb, double* x,
                           double* r, const DevScratch& d, hipStream_t s);
-// CG iterations; the direction buffers p0/p1 alternate by the device
+// CG iterations on vectors stored as S (double or float; the arithmetic is
+// FP64 either way); the direction buffers p0/p1 alternate by the device
 // iteration count (sc->iter), so any number of queued no-op iterations
 // keeps them consistent.
-template <class T>
-hipError_t launch_cg_dir(const Geom& g, const OpConst<T>& k, T* x, T* r, T* p0,
-                         T* p1, CgScalars* sc, const DevScratch& d, hipStream_t s);
-template <class T>
-hipError_t launch_cg_res(const Geom& g, const OpConst<T>& k, T* r, T* p0, T* p1,
+template <class S>
+hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* r, S* p0,
+                         S* p1, CgScalars* sc, const DevScratch& d, hipStream_t s);
+template <class S>
+hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
                          CgScalars* sc, const DevScratch& d, hipStream_t s);
-template <class T>
-hipError_t launch_cg_iter(const Geom& g, const OpConst<T>& k, T* x, T* r,
-                          T* p0, T* p1, CgScalars* sc, const DevScratch& d,
+template <class S>
+hipError_t launch_cg_iter(const Geom& g, const OpConst<double>& k, double* x, S* r,
+                          S* p0, S* p1, CgScalars* sc, const DevScratch& d,
                           hipStream_t s);
-// psi (canonical) = x + pending alpha p (lane-interleaved), minus its W-mean
+// psi (canonical) = x + pending alpha p (lane-interleaved; p stored as P =
+// double or float), minus its W-mean
+template <class P>
 hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
-                            const double* x, const double* p0, const double* p1,
+                            const double* x, const P* p0, const P* p1,
                             double* psi, double area, const DevScratch& d,
                             hipStream_t s);
 // x (canonical) -= its W-mean
@@ -65,20 +68,28 @@ hipError_t launch_mean_sub(const Geom& g, const OpConst<double>& k, double* x,
 hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
                              const double* omega, const double* psi,
                              double* out3, const DevScratch& d, hipStream_t s);
-// Mixed precision (FP32 CG recurrences, FP64 residual replacement; all
-// vectors lane-interleaved): r32 = float(r64), x32 = 0; true residual of
-// x64 + x32 + alpha p_last into r32; x64 += x32 (+ alpha p_last), x32 = 0.
+// Mixed precision (r, p stored in FP32, x in FP64, FP64 residual
+// replacement; all vectors lane-interleaved): r32 = float(r64); the true
+// residual of x + alpha p_last replaces r32.
 hipError_t launch_mixed_start(const Geom& g, const OpConst<double>& k,
-                              const double* r64, float* r32, float* x32,
-                              const DevScratch& d, hipStream_t s);
+                              const double* r64, float* r32, const DevScratch& d,
+                              hipStream_t s);
 hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
-                                const double* omega, const double* x64,
-                                const float* x32, const float* q0,
+                                const double* omega, const double* x, const float* q0,
                                 const float* q1, float* r32, const DevScratch& d,
                                 hipStream_t s);
-hipError_t launch_mixed_accum(const Geom& g, double* x64, float* x32,
-                              const float* q0, const float* q1, const DevScratch& d,
-                              hipStream_t s);
+// Fast-diagonalisation preconditioner support (fd_kernels.hip): field ->
+// image layout (from canonical or lane-interleaved), image -> canonical,
+// image -> z (lane-interleaved) with <r, z>_W closing the PCG step, and the
+// spectral scaling U[r][c] /= -(ly[r] + lx[c]) with the constant mode zeroed.
+hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, double* img,
+                           hipStream_t s);
+hipError_t launch_from_image(const Geom& g, const double* img, double* dst, hipStream_t s);
+hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const double* img,
+                                 double* z, const double* r, const DevScratch& d,
+                                 hipStream_t s);
+hipError_t launch_fd_scale(int NX, int NY, double* img, const double* lx, const double* ly,
+                           int zx, int zy, hipStream_t s);
 hipError_t launch_guess(long elems, double* x, const double* pa,
                         const double* pb, double ca, double cb, hipStream_t s);
 

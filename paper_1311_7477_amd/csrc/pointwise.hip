@@ -15,13 +15,13 @@ __global__ __launch_bounds__(kPwThreads) void k_cg_mean(
                     tol2, max_iter, sc, counter, partials);
 }
 
-template <int N>
+template <int N, class P>
 __global__ __launch_bounds__(kPwThreads) void k_cg_finish(
     Geom g, OpConst<double> k, const double* __restrict__ x,
-    const double* __restrict__ p0, const double* __restrict__ p1,
+    const P* __restrict__ p0, const P* __restrict__ p1,
     double* __restrict__ psi, double area, CgScalars* sc, unsigned* counter,
     double* partials) {
-    cg_finish_body<N>(blockIdx.x, gridDim.x, g, k, x, p0, p1, psi, area, sc,
+    cg_finish_body<N, P>(blockIdx.x, gridDim.x, g, k, x, p0, p1, psi, area, sc,
                       counter, partials);
 }
 
@@ -51,18 +51,8 @@ __global__ __launch_bounds__(kPwThreads) void k_invariants(
 template <int N>
 __global__ __launch_bounds__(kPwThreads) void k_mixed_start(
     Geom g, OpConst<double> k, const double* __restrict__ r64,
-    float* __restrict__ r32, float* __restrict__ x32, CgScalars* sc,
-    unsigned* counter, double* partials) {
-    mixed_start_body<N>(blockIdx.x, gridDim.x, g, k, r64, r32, x32, sc, counter,
-                        partials);
-}
-
-template <int N>
-__global__ __launch_bounds__(kPwThreads) void k_mixed_accum(
-    Geom g, double* __restrict__ x64, float* __restrict__ x32,
-    const float* __restrict__ q0, const float* __restrict__ q1,
-    const CgScalars* sc) {
-    mixed_accum_body<N>(blockIdx.x, gridDim.x, g, x64, x32, q0, q1, sc);
+    float* __restrict__ r32, CgScalars* sc, unsigned* counter, double* partials) {
+    mixed_start_body<N>(blockIdx.x, gridDim.x, g, k, r64, r32, sc, counter, partials);
 }
 
 __global__ __launch_bounds__(kPwThreads) void k_guess(long elems,
@@ -97,13 +87,14 @@ hipError_t launch_cg_mean(const Geom& g, const OpConst<double>& k,
     return hipGetLastError();
 }
 
+template <class P>
 hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
-                            const double* x, const double* p0, const double* p1,
+                            const double* x, const P* p0, const P* p1,
                             double* psi, double area, const DevScratch& d,
                             hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_finish<NN>), dim3(nb),
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_finish<NN, P>), dim3(nb),
                                           dim3(kPwThreads), 0, s, g, k, x, p0, p1,
                                           psi, area, d.sc, d.counters + kCntFinish,
                                           d.partials));
@@ -114,6 +105,12 @@ hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
                        dim3(kPwThreads), 0, s, elems, psi, d.sc);
     return hipGetLastError();
 }
+template hipError_t launch_cg_finish<double>(const Geom&, const OpConst<double>&,
+                                             const double*, const double*, const double*,
+                                             double*, double, const DevScratch&, hipStream_t);
+template hipError_t launch_cg_finish<float>(const Geom&, const OpConst<double>&,
+                                            const double*, const float*, const float*,
+                                            double*, double, const DevScratch&, hipStream_t);
 
 hipError_t launch_mean_sub(const Geom& g, const OpConst<double>& k, double* x,
                            double area, const DevScratch& d, hipStream_t s) {
@@ -143,24 +140,13 @@ hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
 }
 
 hipError_t launch_mixed_start(const Geom& g, const OpConst<double>& k,
-                              const double* r64, float* r32, float* x32,
-                              const DevScratch& d, hipStream_t s) {
-    const long cells = (long)g.nx * g.ny;
-    const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_start<NN>), dim3(nb),
-                                          dim3(kPwThreads), 0, s, g, k, r64, r32, x32,
-                                          d.sc, d.counters + kCntMean, d.partials));
-    return hipGetLastError();
-}
-
-hipError_t launch_mixed_accum(const Geom& g, double* x64, float* x32,
-                              const float* q0, const float* q1, const DevScratch& d,
+                              const double* r64, float* r32, const DevScratch& d,
                               hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_accum<NN>), dim3(nb),
-                                          dim3(kPwThreads), 0, s, g, x64, x32, q0, q1,
-                                          d.sc));
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_start<NN>), dim3(nb),
+                                          dim3(kPwThreads), 0, s, g, k, r64, r32,
+                                          d.sc, d.counters + kCntMean, d.partials));
     return hipGetLastError();
 }
 

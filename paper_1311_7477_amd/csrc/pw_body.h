@@ -71,20 +71,23 @@ __device__ __forceinline__ void cg_mean_body(int b, int nb, long rows, const OpC
         sc->pending = 0;
         sc->iter = 0;
         sc->breakdown = 0;
+        sc->precond = 0;
+        sc->rz = 0.0;
+        sc->cr = 1.0;
     }
 }
 
 // End of a solve: psi = x + alpha p_last (pending update; p_last = the
 // buffer written by the last direction update) or psi = 0 when b = 0,
 // converted from the lane-interleaved layout to canonical; partial W-mean.
-template <int N>
+template <int N, class P>
 __device__ __forceinline__ void cg_finish_body(int b, int nb, Geom g, const OpConst<double>& k, const double* __restrict__ x,
-    const double* __restrict__ p0, const double* __restrict__ p1,
+    const P* __restrict__ p0, const P* __restrict__ p1,
     double* __restrict__ psi, double area, CgScalars* sc, unsigned* counter,
     double* partials) {
     const int pending = sc->pending, zero = sc->zero;
     const double alpha = sc->alpha;
-    const double* pl = (sc->iter & 1) ? p1 : p0;
+    const P* pl = (sc->iter & 1) ? p1 : p0;
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
     double part[1] = {0.0};
@@ -98,7 +101,7 @@ __device__ __forceinline__ void cg_finish_body(int b, int nb, Geom g, const OpCo
             double a = 0.0;
             if (!zero) {
                 a = x[l64 + 64 * e];
-                if (pending) a = fmx(alpha, pl[l64 + 64 * e], a);
+                if (pending) a = fmx(alpha, (double)pl[l64 + 64 * e], a);
             }
             v[e] = a;
         }
@@ -191,42 +194,13 @@ __device__ __forceinline__ void guess_body(int b, int nb, long elems,
 }
 
 
-// Mixed precision, after a residual replacement: x64 += x32 (+ the pending
-// alpha p_last the replacement used), x32 = 0; all lane-interleaved.
-template <int N>
-__device__ __forceinline__ void mixed_accum_body(int b, int nb, Geom g,
-                                                 double* __restrict__ x64,
-                                                 float* __restrict__ x32,
-                                                 const float* __restrict__ q0,
-                                                 const float* __restrict__ q1,
-                                                 const CgScalars* sc) {
-    const bool pending = sc->accum_pending != 0;
-    const double alpha = sc->accum_alpha;
-    const float* pl = (sc->iter & 1) ? q1 : q0;
-    const long cells = (long)g.nx * g.ny;
-    const int G = (g.nx + 63) / 64;
-    for (long cell = b * (long)kPwThreads + threadIdx.x; cell < cells;
-         cell += (long)nb * kPwThreads) {
-        const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
-        const long l64 = ((long)cy * G + (cx >> 6)) * (N * N * 64) + (cx & 63);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) {
-            double v = x64[l64 + 64 * e] + (double)x32[l64 + 64 * e];
-            if (pending) v = fmx(alpha, (double)pl[l64 + 64 * e], v);
-            x64[l64 + 64 * e] = v;
-            x32[l64 + 64 * e] = 0.0f;
-        }
-    }
-}
-
-// Mixed precision, start: r32 = float(r64), x32 = 0 (lane-interleaved);
+// Mixed precision, start: r32 = float(r64) (lane-interleaved);
 // <r32, r32>_W becomes the CG recurrence's residual norm.
 template <int N>
 __device__ __forceinline__ void mixed_start_body(int b, int nb, Geom g,
                                                  const OpConst<double>& k,
                                                  const double* __restrict__ r64,
                                                  float* __restrict__ r32,
-                                                 float* __restrict__ x32,
                                                  CgScalars* sc, unsigned* counter,
                                                  double* partials) {
     const long cells = (long)g.nx * g.ny;
@@ -244,7 +218,6 @@ __device__ __forceinline__ void mixed_start_body(int b, int nb, Geom g,
                 const int e = j * N + i;
                 const float f = (float)r64[l64 + 64 * e];
                 r32[l64 + 64 * e] = f;
-                x32[l64 + 64 * e] = 0.0f;
                 row[i] = (double)f * (double)f;
             }
             part[0] += wrow<N>(k, j, row);
@@ -255,7 +228,9 @@ __device__ __forceinline__ void mixed_start_body(int b, int nb, Geom g,
         threadIdx.x == 0) {
         sc->rr_true = sc->rr;
         sc->rr = tot[0];
-        sc->iter_repl = 0;
+        sc->rz = tot[0];
+        sc->rr_max = tot[0];
+        sc->rr_true_prev = __builtin_inf();
         sc->outer = 0;
     }
 }

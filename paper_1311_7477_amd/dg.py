@@ -20,6 +20,8 @@ DG_E_INVAL, DG_E_ALIAS, DG_E_NOMEM, DG_E_HIP = -1, -2, -3, -4
 DG_E_NOCONV, DG_E_UNSUPPORTED, DG_E_WORKSPACE = -5, -6, -7
 DG_BC_PERIODIC, DG_BC_DIRICHLET = 0, 1
 DG_PREC_FP64, DG_PREC_MIXED = 0, 1
+DG_WS_FD = 0x10
+DG_PRECOND_NONE, DG_PRECOND_FD = 0, 1
 DG_FORM_ARAKAWA, DG_FORM_PP, DG_FORM_PX, DG_FORM_XP = 0, 1, 2, 3
 
 _vp = ctypes.c_void_p
@@ -28,7 +30,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class CgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double),
+                ("precision", ctypes.c_int), ("precond", ctypes.c_int),
                 ("check_every", ctypes.c_int)]
 
 
@@ -81,6 +83,9 @@ def lib():
         "dg_laplace_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
         "dg_cg_solve_poisson": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(CgOpts),
                                                ctypes.POINTER(CgStats), _vp, _vp]),
+        "dg_precond_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+        "dg_grid_fd_basis": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp,
+                                            ctypes.POINTER(ctypes.c_int)]),
         "dg_state_create": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(_vp)]),
         "dg_state_destroy": (None, [_vp]),
         "dg_state_psi": (_vp, [_vp]),
@@ -149,6 +154,19 @@ class Grid:
         out = (ctypes.c_double * 256)()
         k = _check_count(lib().dg_grid_tables(self._h, out, 256))
         return [out[i] for i in range(k)]
+
+    def fd_basis(self, axis=0):
+        """(V, lam, zero) of the fast-diagonalisation basis along one axis
+        (host numpy arrays; V[:, k] is mode k)."""
+        import numpy as np
+        N = self.nx if axis == 0 else self.ny
+        NN = N * self.n
+        V = np.empty(NN * NN)
+        lam = np.empty(NN)
+        z = ctypes.c_int()
+        _check(lib().dg_grid_fd_basis(self._h, axis, V.ctypes.data_as(_dp),
+                                      lam.ctypes.data_as(_dp), ctypes.byref(z)))
+        return V.reshape(NN, NN).T.copy(), lam, z.value
 
     def workspace_bytes(self, mode=DG_PREC_FP64):
         b = ctypes.c_size_t()
@@ -261,8 +279,17 @@ def laplace_apply(grid: Grid, f, out=None):
 
 
 def cg_opts(rtol=1e-12, max_iter=100000, precision=DG_PREC_FP64,
-            inner_rtol=1e-5, check_every=0):
-    return CgOpts(rtol, max_iter, precision, inner_rtol, check_every)
+            precond=DG_PRECOND_NONE, check_every=0):
+    return CgOpts(rtol, max_iter, precision, precond, check_every)
+
+
+def precond_apply(grid: Grid, r, ws: Workspace, out=None):
+    """z = (-Lap_h)^+ r by fast diagonalisation (ws made with DG_WS_FD)."""
+    import torch
+    out = torch.empty_like(r) if out is None else out
+    _check(lib().dg_precond_apply(grid.handle, _field(r, grid, "r"),
+                                  _field(out, grid, "z"), ws.handle, _stream()))
+    return out
 
 
 @dataclass
@@ -271,6 +298,7 @@ class SolveResult:
     outer_iters: int
     rel_residual: float
     converged: bool
+    stalled: bool = False     # mixed mode: stopped at the attainable FP64 accuracy
 
 
 def cg_solve_poisson(grid: Grid, omega, psi, ws: Workspace, opts: CgOpts = None):
@@ -281,7 +309,8 @@ def cg_solve_poisson(grid: Grid, omega, psi, ws: Workspace, opts: CgOpts = None)
                                      _field(psi, grid, "psi"), ctypes.byref(opts),
                                      ctypes.byref(st), ws.handle, _stream()),
            allow=(DG_E_NOCONV,))
-    return SolveResult(st.iters, st.outer_iters, st.rel_residual, bool(st.converged))
+    return SolveResult(st.iters, st.outer_iters, st.rel_residual, bool(st.converged),
+                       st.converged == 2)
 
 
 @dataclass

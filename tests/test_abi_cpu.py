@@ -103,11 +103,23 @@ def test_workspace_bytes_and_field_size():
     # RK stage fields s1, s2, reduction scratch
     b64, bmx = g.workspace_bytes(dg.DG_PREC_FP64), g.workspace_bytes(dg.DG_PREC_MIXED)
     assert 6 * F <= b64 < 6 * F + 2 ** 20
-    assert bmx == b64 + 4 * g.elems * 4
+    assert bmx == b64 + 3 * g.elems * 4          # FP32 r, p0, p1
+    # fast-diagonalisation option: z, two image fields, and V, W V of one
+    # axis (square grid: the y basis is the x basis) plus the eigenvalues
+    NX = 512 * 4
+    bfd = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    assert bfd == b64 + 3 * F + (2 * NX * NX + 2 * NX) * 8
+    # unequal axes keep both bases
+    r = dg.Grid(2, 6, 5)
+    extra = r.workspace_bytes(dg.DG_WS_FD) - r.workspace_bytes(dg.DG_PREC_FP64)
+    L6 = 5 * 1 * 4 * 64
+    assert extra == (L6 + 2 * r.elems + 2 * 12 * 12 + 2 * 10 * 10 + 12 + 10) * 8
     # ragged nx: the interleaved vectors are padded to whole groups of 64 cells
     h = dg.Grid(3, 100, 7)
     L = 7 * 2 * 9 * 64
     assert h.workspace_bytes(dg.DG_PREC_FP64) >= 4 * L * 8 + 2 * h.elems * 8
+    with pytest.raises(dg.DgError):
+        g.workspace_bytes(7)
 
 
 def test_null_arguments_are_rejected():
@@ -124,3 +136,25 @@ def test_null_arguments_are_rejected():
     assert L.dg_poisson_bracket(g.handle, x, ctypes.c_void_p(0x100000), x, None) == dg.DG_E_ALIAS
     assert L.dg_bracket_form(g.handle, ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000),
                              ctypes.c_void_p(0x30000), 9, None) == dg.DG_E_INVAL
+
+
+@pytest.mark.parametrize("n,N,length", [(1, 7, 1.0), (2, 6, 2.0), (3, 5, 6.283185307179586),
+                                        (4, 8, 0.5), (5, 9, 3.0), (4, 1, 1.0), (2, 2, 1.0)])
+def test_fd_basis_diagonalises_the_oracle_operator(n, N, length):
+    # The host-built Bloch eigenbasis against the oracle's sparse 1D LDG
+    # operator and Gauss weights: L V = V diag(lam), V^T W V = I, the
+    # constant mode, and the spectrum of the oracle's dense eigh.
+    from paper_1311_7477_amd import dg
+    g = dg.Grid(n, N, 3, 0.0, length, 0.0, 1.0)
+    V, lam, zero = g.fd_basis(0)
+    g1 = O.Grid1D(n, N, 0.0, length)
+    L = g1.laplacian().toarray()
+    W = np.diag(g1.weights())
+    scale = np.abs(lam).max()
+    assert np.abs(L @ V - V * lam[None, :]).max() <= 1e-11 * scale * np.abs(V).max()
+    assert np.abs(V.T @ W @ V - np.eye(N * n)).max() <= 1e-12
+    assert abs(lam[zero]) <= 1e-11 * scale
+    c = V[:, zero]
+    assert np.ptp(c) <= 1e-12 * np.abs(c).max()
+    ref = np.sort(np.linalg.eigvals(L).real)
+    np.testing.assert_allclose(np.sort(lam), ref, atol=1e-10 * scale)

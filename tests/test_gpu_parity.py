@@ -179,6 +179,38 @@ def test_mixed_precision_solve(dg):
     assert math.sqrt(O.inner(g, e, e)) <= 1e-7 * math.sqrt(O.inner(g, p64, p64))
 
 
+def _true_rel_residual(g, w, psi):
+    b = w - O.wmean(g, w)
+    r = b + O.laplacian(g, psi)
+    return math.sqrt(O.inner(g, r, r) / O.inner(g, b, b))
+
+
+@pytest.mark.parametrize("N", [128, 256])
+def test_mixed_precision_large_grid(dg, N):
+    # n = 5 double shear layer.  An FP64 residual is attainable only to
+    # ~ eps |Lap_h| |psi| (~1.4e-10 of ||b|| at 128^2, growing ~6x per
+    # doubling of N), so rtol = 1e-10 lies below what any FP64 evaluation
+    # can confirm here: the FP64 CG stops on its recursive residual, the
+    # mixed CG on its FP64 one or at the attainable accuracy (converged =
+    # 2).  Bars: both stop, the mixed iterations stay within 12x the FP64
+    # ones, and the mixed solution's true residual (oracle operator) is
+    # within 1.5 x rtol or within 64x the FP64 solution's own.
+    n = 5
+    print(f"mixed n=5 N={N}", flush=True)
+    g = O.Grid2D(n, N, N)
+    w, _ = I.double_shear_layer(n, N)
+    rtol = 1e-10
+    r64, p64 = _solve(dg, n, N, N, w, rtol)
+    rmx, pmx = _solve(dg, n, N, N, w, rtol, mixed=True)
+    assert r64.converged and rmx.converged, (r64, rmx)
+    assert rmx.iters <= 12 * r64.iters, (rmx.iters, r64.iters)
+    t64, tmx = _true_rel_residual(g, w, p64), _true_rel_residual(g, w, pmx)
+    assert tmx <= max(1.5 * rtol, 64 * t64), (tmx, t64)
+    assert abs(tmx - rmx.rel_residual) <= 0.5 * tmx + 1e-11
+    e = pmx - p64
+    assert math.sqrt(O.inner(g, e, e)) <= 1e-5 * math.sqrt(O.inner(g, p64, p64))
+
+
 def test_rk3_config1_trajectory(dg):
     # 10 SSP-RK3 steps, n = 3, 32 x 32, D = 1e-3, dt = 1e-3 (Taylor-Green +
     # 1e-3 noise); both sides solve to rtol 1e-14
