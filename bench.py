@@ -110,10 +110,18 @@ def form_batch(args):
     cells = sum(N * N for (_, N, _, _) in members)
     steps = args.steps
 
+    # tile shapes from the tuner, once per (n, N), shared by both runs
+    shapes = {}
+    for (n, N, w0, dt) in members:
+        if (n, N) not in shapes:
+            g = dg.Grid(n, N, N)
+            shapes[(n, N)] = g.tune(torch.from_numpy(w0).cuda(), reps=5)[0]
+
     # one by one
     singles = []
     for (n, N, w0, dt) in members:
         g = dg.Grid(n, N, N)
+        g.set_tiles(*shapes[(n, N)])
         singles.append((g, dg.Workspace(g), dg.State(g), torch.from_numpy(w0).cuda(), dt))
     for (g, ws, st, w, dt) in singles:            # warm-up step
         dg.rk_step(g, w, st, ws, dt, args.D, opts)
@@ -130,6 +138,7 @@ def form_batch(args):
     bw = []
     for (n, N, w0, dt) in members:
         g = dg.Grid(n, N, N)
+        g.set_tiles(*shapes[(n, N)])
         w = torch.from_numpy(w0).cuda()
         batch.attach(g, w, dt, args.D)
         bw.append((g, w))
@@ -250,7 +259,8 @@ def form_serve(args):
     done = srv.run(reqs, log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
     makespan = time.perf_counter() - t0
     s = serve.summarize(done, makespan)
-    same = [bool(np.array_equal(r.result, serve.run_alone(r, srv.opts)))
+    same = [bool(np.array_equal(r.result, serve.run_alone(r, srv.opts,
+                                                          srv.tiles.get((r.n, r.N)))))
             for r in done[:4]]
     s.update({
         "metric": "served DG cell-updates/s (aggregate) with p50/p99 request latency",
@@ -293,7 +303,7 @@ def form_paper(args):
                       "data": "synthetic"}), flush=True)
 
 
-def precond_leg(args, omega0, dt):
+def precond_leg(args, omega0, dt, tiles):
     """The same workload (fresh from omega0) with CG preconditioned by the
     exact fast-diagonalisation inverse of -Lap_h: W warm-up steps, then K
     timed steps; per-RHS latency from HIP events around each stage."""
@@ -301,6 +311,7 @@ def precond_leg(args, omega0, dt):
     from paper_1311_7477_amd import dg
     n, N = args.n, args.N
     grid = dg.Grid(n, N, N)
+    grid.set_tiles(*tiles)
     ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
     st = dg.State(grid)
     w = torch.from_numpy(omega0).cuda()
@@ -343,6 +354,8 @@ def main():
     ap.add_argument("--D", type=float, default=1e-4)
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tile shapes instead of running the tuner")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the fast-diagonalisation preconditioned leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,12 +398,13 @@ def main():
     omega0, umax = inputs.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
     dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
     grid = dg.Grid(n, N, N)
+    w = torch.from_numpy(omega0).cuda()
+    tiles, tune_ms = (grid.tiles(), None) if args.no_tune else grid.tune(w)
     ws = dg.Workspace(grid)
     st = dg.State(grid)
-    w = torch.from_numpy(omega0).cuda()
     opts = dg.cg_opts(rtol=args.rtol)
     print(f"[bench] n={n} N={N} D={args.D} dt={dt:.3e} warmup={args.warmup} "
-          f"steps={args.steps}", file=sys.stderr, flush=True)
+          f"steps={args.steps} tiles={tiles} tune_ms={tune_ms}", file=sys.stderr, flush=True)
 
     for k in range(args.warmup):
         r = dg.rk_step(grid, w, st, ws, dt, args.D, opts, record_times=True)
@@ -459,6 +473,8 @@ def main():
                          f"D={args.D}, dt={dt:.4e} (CFL 0.1), SSP-RK3, CG rtol "
                          f"{args.rtol}, extrapolated guess; step = 1 RK3 step = 3 RHS"),
             "n": n, "Nx": N, "Ny": N, "rhs_per_step": 3,
+            "tiles": {"cell_tile": [64, tiles[0]], "bracket_tile_rows": tiles[1],
+                      "tuner_ms": tune_ms},
         },
         "latency_ms_per_rhs": {"p50": pct(0.50), "p99": pct(0.99),
                                "mean": statistics.mean(stage_ms)},
@@ -480,7 +496,7 @@ def main():
         },
     }
     if not args.no_precond:
-        out["preconditioned"] = precond_leg(args, omega0, dt)
+        out["preconditioned"] = precond_leg(args, omega0, dt, tiles)
     if not args.no_cpu_baseline:
         psi0 = st.psi().cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(n, N, w.cpu().numpy(), psi0, args.D, dt,

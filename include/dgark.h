@@ -136,6 +136,25 @@ size_t dg_field_elems(const dg_grid* grid);
  * negative status (DG_E_INVAL if len is too small). */
 int  dg_grid_tables(const dg_grid* grid, double* out, int len);
 
+/* Tile shapes of the grid's stencil launches: the cell-per-lane kernels
+ * (Laplacian, CG) use tiles of 64 x cw cells, cw in {4, 8, 16}; the fused
+ * bracket kernel tiles of rw rows, rw in {8, 16} (default 8 and 8).  Taller
+ * tiles re-read fewer halo rows but hold more registers and LDS per
+ * workgroup.  The shapes change the reduction order and hence the last bits
+ * of CG results; set them before using the grid (a batch copies them when an
+ * instance is attached).  DG_E_INVAL for other values. */
+int  dg_grid_set_tiles(dg_grid* grid, int cw, int rw);
+int  dg_grid_tiles(const dg_grid* grid, int* cw, int* rw);
+/* Tile autotuner: on the current device, time `reps` CG iterations for each
+ * cell tile height and `reps` fused bracket evaluations for each bracket tile
+ * height on this grid, from the caller's field omega (device, canonical; its
+ * mean-free part must be nonzero), and set the fastest shapes in the grid.
+ * ms_out5 (host, optional): mean ms per CG iteration for cw = 4, 8, 16 and
+ * per bracket for rw = 8, 16.  Allocates and frees a temporary workspace;
+ * synchronises the stream.  Not thread-safe with other users of the grid. */
+int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
+                  void* stream);
+
 /* ----------------------------------------------------------- workspace --- */
 /* Device bytes a workspace for (grid, mode) holds: CG vectors x, r, p, the
  * two RK stage fields, reduction partials and scalars, plus FP32 r and p in

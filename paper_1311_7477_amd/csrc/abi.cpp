@@ -414,7 +414,7 @@ int dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
     g->area = (x1 - x0) * (y1 - y0);
     if (!build_tables(n, &g->t)) { delete g; return fail(DG_E_INVAL, "table build failed"); }
     fill_const(*g, g->k64);
-    g->geom = Geom{n, nx, ny};
+    g->geom = Geom{n, nx, ny, kCellWavesDefault, kRowWavesDefault};
     g->elems = (size_t)nx * ny * n * n;
     *out = g;
     return DG_OK;

@@ -20,6 +20,29 @@ namespace {
 
 enum ListKind { kCell = 0, kRow, kPwRows, kPwCells, kPwElems, kListCount };
 
+// Launch groups: one per (polynomial order, cell tile height, bracket tile
+// height); every kernel kind of a group is one persistent launch.
+constexpr int kCellShapes[3] = {4, 8, 16};
+constexpr int kRowShapes[2] = {8, 16};
+constexpr int kShapes = 6;
+constexpr int kGroups = kMaxN * kShapes;
+static_assert(kGroups <= 32, "group_mask holds one bit per launch group");
+
+int group_of(const Geom& g) {
+    const int ci = g.cw == 4 ? 0 : (g.cw == 8 ? 1 : 2);
+    const int ri = g.rw == 8 ? 0 : 1;
+    return (g.n - 1) * kShapes + ci * 2 + ri;
+}
+
+struct GroupShape {
+    int n, cw, rw;
+};
+
+GroupShape shape_of(int gi) {
+    const int n = gi / kShapes + 1, s = gi % kShapes;
+    return GroupShape{n, kCellShapes[s / 2], kRowShapes[s % 2]};
+}
+
 struct Slot {
     bool used = false;
     const dg_grid* grid = nullptr;
@@ -47,9 +70,9 @@ struct dg_batch {
     CgScalars* h_sc = nullptr;     // pinned: 3 x capacity (2 poll slots + final)
     int* d_counts = nullptr;       // device item counts [n-1][kind]
     int* h_counts = nullptr;       // pinned
-    DevList lists[kMaxN][kListCount];
+    DevList lists[kGroups][kListCount];
     bool lists_dirty = true;
-    unsigned group_mask = 0;       // bit n-1 set if some slot has order n
+    unsigned group_mask = 0;       // bit gi set if some slot is in launch group gi
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipStream_t cap = nullptr;     // capture stream
     bool use_graphs = true;
@@ -66,33 +89,33 @@ void destroy_graphs(dg_batch* b) {
     b->graphs_valid = false;
 }
 
-ItemList list_of(const dg_batch* b, int n, int kind) {
-    return ItemList{b->lists[n - 1][kind].items, b->d_counts + (n - 1) * kListCount + kind};
+ItemList list_of(const dg_batch* b, int gi, int kind) {
+    return ItemList{b->lists[gi][kind].items, b->d_counts + gi * kListCount + kind};
 }
 
-int grid_of(const dg_batch* b, int n, int kind) {
-    const int c = b->lists[n - 1][kind].count;
+int grid_of(const dg_batch* b, int gi, int kind) {
+    const int c = b->lists[gi][kind].count;
     return c < 1 ? 1 : (c > 65535 ? 65535 : c);
 }
 
 // Rebuild the per-order work lists (instance, local block) on the host and
 // upload them.
 int rebuild_lists(dg_batch* b, hipStream_t s) {
-    std::vector<BatchItem> h[kMaxN][kListCount];
+    std::vector<BatchItem> h[kGroups][kListCount];
     unsigned mask = 0;
     for (int i = 0; i < b->capacity; ++i) {
         const Slot& sl = b->slots[i];
         if (!sl.used) continue;
         const BatchInst& r = b->h_inst[i];
-        const int n = r.g.n;
-        mask |= 1u << (n - 1);
+        const int gi = group_of(r.g);
+        mask |= 1u << gi;
         const int counts[kListCount] = {r.cell_nblocks, r.row_nblocks, r.nb_rows,
                                         r.nb_cells, r.nb_elems};
         for (int k = 0; k < kListCount; ++k)
-            for (int q = 0; q < counts[k]; ++q) h[n - 1][k].push_back(BatchItem{i, q});
+            for (int q = 0; q < counts[k]; ++q) h[gi][k].push_back(BatchItem{i, q});
     }
     bool realloc_any = false;
-    for (int n = 0; n < kMaxN; ++n)
+    for (int n = 0; n < kGroups; ++n)
         for (int k = 0; k < kListCount; ++k) {
             DevList& L = b->lists[n][k];
             const int need = (int)h[n][k].size();
@@ -115,7 +138,7 @@ int rebuild_lists(dg_batch* b, hipStream_t s) {
                 HIP_TRY(hipMemcpyAsync(L.items, h[n][k].data(), need * sizeof(BatchItem),
                                        hipMemcpyHostToDevice, s));
         }
-    HIP_TRY(hipMemcpyAsync(b->d_counts, b->h_counts, kMaxN * kListCount * sizeof(int),
+    HIP_TRY(hipMemcpyAsync(b->d_counts, b->h_counts, kGroups * kListCount * sizeof(int),
                            hipMemcpyHostToDevice, s));
     // the host vectors above are pageable: make the copies complete
     HIP_TRY(hipStreamSynchronize(s));
@@ -128,13 +151,14 @@ int rebuild_lists(dg_batch* b, hipStream_t s) {
 }
 
 int enqueue_setup(dg_batch* b, hipStream_t s) {
-    for (int n = 1; n <= kMaxN; ++n) {
-        if (!(b->group_mask & (1u << (n - 1)))) continue;
-        hipError_t e = launch_batch(n, BatchKernel::Mean, b->d_inst, list_of(b, n, kPwRows),
-                                    grid_of(b, n, kPwRows), s);
+    for (int gi = 0; gi < kGroups; ++gi) {
+        if (!(b->group_mask & (1u << gi))) continue;
+        const GroupShape q = shape_of(gi);
+        hipError_t e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Mean, b->d_inst,
+                                    list_of(b, gi, kPwRows), grid_of(b, gi, kPwRows), s);
         if (e == hipSuccess)
-            e = launch_batch(n, BatchKernel::Init, b->d_inst, list_of(b, n, kCell),
-                             grid_of(b, n, kCell), s);
+            e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Init, b->d_inst,
+                             list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
         if (e != hipSuccess) return hip_fail(e, "batch setup launch");
     }
     return DG_OK;
@@ -142,29 +166,31 @@ int enqueue_setup(dg_batch* b, hipStream_t s) {
 
 int enqueue_chunk(dg_batch* b, hipStream_t s) {
     for (int i = 0; i < b->chunk; ++i)
-        for (int n = 1; n <= kMaxN; ++n) {
-            if (!(b->group_mask & (1u << (n - 1)))) continue;
-            hipError_t e = launch_batch(n, BatchKernel::Dir, b->d_inst, list_of(b, n, kCell),
-                                        grid_of(b, n, kCell), s);
+        for (int gi = 0; gi < kGroups; ++gi) {
+            if (!(b->group_mask & (1u << gi))) continue;
+            const GroupShape q = shape_of(gi);
+            hipError_t e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Dir, b->d_inst,
+                                        list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
             if (e == hipSuccess)
-                e = launch_batch(n, BatchKernel::Res, b->d_inst, list_of(b, n, kCell),
-                                 grid_of(b, n, kCell), s);
+                e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Res, b->d_inst,
+                                 list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
             if (e != hipSuccess) return hip_fail(e, "batch CG launch");
         }
     return DG_OK;
 }
 
 int enqueue_finish(dg_batch* b, hipStream_t s) {
-    for (int n = 1; n <= kMaxN; ++n) {
-        if (!(b->group_mask & (1u << (n - 1)))) continue;
-        hipError_t e = launch_batch(n, BatchKernel::Finish, b->d_inst,
-                                    list_of(b, n, kPwCells), grid_of(b, n, kPwCells), s);
+    for (int gi = 0; gi < kGroups; ++gi) {
+        if (!(b->group_mask & (1u << gi))) continue;
+        const GroupShape q = shape_of(gi);
+        hipError_t e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Finish, b->d_inst,
+                                    list_of(b, gi, kPwCells), grid_of(b, gi, kPwCells), s);
         if (e == hipSuccess)
-            e = launch_batch(n, BatchKernel::SubMean, b->d_inst, list_of(b, n, kPwElems),
-                             grid_of(b, n, kPwElems), s);
+            e = launch_batch(q.n, q.cw, q.rw, BatchKernel::SubMean, b->d_inst,
+                             list_of(b, gi, kPwElems), grid_of(b, gi, kPwElems), s);
         if (e == hipSuccess)
-            e = launch_batch(n, BatchKernel::Rhs, b->d_inst, list_of(b, n, kRow),
-                             grid_of(b, n, kRow), s);
+            e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Rhs, b->d_inst,
+                             list_of(b, gi, kRow), grid_of(b, gi, kRow), s);
         if (e != hipSuccess) return hip_fail(e, "batch finish launch");
     }
     return DG_OK;
@@ -225,16 +251,16 @@ int dg_batch_create(int capacity, dg_batch** out) {
               hipHostMalloc((void**)&b->h_inst, capacity * sizeof(BatchInst)) == hipSuccess &&
               hipMalloc((void**)&b->d_sc, capacity * sizeof(CgScalars)) == hipSuccess &&
               hipHostMalloc((void**)&b->h_sc, 3 * capacity * sizeof(CgScalars)) == hipSuccess &&
-              hipMalloc((void**)&b->d_counts, kMaxN * kListCount * sizeof(int)) == hipSuccess &&
-              hipHostMalloc((void**)&b->h_counts, kMaxN * kListCount * sizeof(int)) == hipSuccess &&
+              hipMalloc((void**)&b->d_counts, kGroups * kListCount * sizeof(int)) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_counts, kGroups * kListCount * sizeof(int)) == hipSuccess &&
               hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) == hipSuccess &&
               hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
     if (ok) {
         std::memset(b->h_inst, 0, capacity * sizeof(BatchInst));
-        std::memset(b->h_counts, 0, kMaxN * kListCount * sizeof(int));
+        std::memset(b->h_counts, 0, kGroups * kListCount * sizeof(int));
         ok = hipMemset(b->d_sc, 0, capacity * sizeof(CgScalars)) == hipSuccess &&
-             hipMemset(b->d_counts, 0, kMaxN * kListCount * sizeof(int)) == hipSuccess &&
+             hipMemset(b->d_counts, 0, kGroups * kListCount * sizeof(int)) == hipSuccess &&
              hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {

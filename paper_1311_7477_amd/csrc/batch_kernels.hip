@@ -1,6 +1,6 @@
-// Batched launches: many independent instances (any grid sizes, one
-// polynomial order per launch) in one persistent grid-stride launch per
-// kernel kind.  Every instance is described by a BatchInst record in device
+// Batched launches: many independent instances (any grid sizes; one
+// polynomial order and one tile shape per launch) in one persistent
+// grid-stride launch per kernel kind.  Every instance is described by a BatchInst record in device
 // memory and cut into the same blocks as its single-instance launch; the
 // work list holds (instance, local block index) items.  Each item runs the
 // very same device body as the single-instance kernel with the same local
@@ -35,35 +35,32 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* inst,
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void kb_cg_init(const BatchInst* inst,
-                                                              ItemList list) {
-    __shared__ YFaces<N, double> lds;
+template <int N, int WV>
+__global__ __launch_bounds__(64 * WV) void kb_cg_init(const BatchInst* inst, ItemList list) {
+    __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
-        cg_init_body<N>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k, B.w_in,
+        cg_init_body<N, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k, B.w_in,
                         B.pa, B.pb, B.ca, B.cb, B.x, B.r, B.sc,
                         B.counters + kCntInit, B.partials, lds);
         __syncthreads();
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void kb_cg_dir(const BatchInst* inst,
-                                                             ItemList list) {
-    __shared__ YFaces<N, double> lds;
+template <int N, int WV>
+__global__ __launch_bounds__(64 * WV) void kb_cg_dir(const BatchInst* inst, ItemList list) {
+    __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
-        cg_dir_body<N, double>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
+        cg_dir_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
                                B.r, B.p0, B.p1, B.x, B.sc, B.counters + kCntDir, B.partials, lds);
         __syncthreads();
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void kb_cg_res(const BatchInst* inst,
-                                                             ItemList list) {
-    __shared__ YFaces<N, double> lds;
+template <int N, int WV>
+__global__ __launch_bounds__(64 * WV) void kb_cg_res(const BatchInst* inst, ItemList list) {
+    __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
-        cg_res_body<N, double>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
+        cg_res_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
                                B.p0, B.p1, B.r, B.sc,
                                B.counters + kCntRes, B.partials, lds);
         __syncthreads();
@@ -87,12 +84,11 @@ __global__ __launch_bounds__(kPwThreads) void kb_sub_mean(const BatchInst* inst,
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * kRowWaves) void kb_rhs(const BatchInst* inst,
-                                                         ItemList list) {
-    __shared__ RhsLds<N, kRowWaves, true> lds;
+template <int N, int W>
+__global__ __launch_bounds__(64 * W) void kb_rhs(const BatchInst* inst, ItemList list) {
+    __shared__ RhsLds<N, W, true> lds;
     DG_FOR_ITEMS(list) {
-        rhs_body<N, kRowWaves, true>(item_.b, B.g, B.row_tilesX, B.row_nblocks,
+        rhs_body<N, W, true>(item_.b, B.g, B.row_tilesX, B.row_nblocks,
                                      B.k, B.psi, B.w_in, B.w_n, B.w_out, B.ra, lds);
         __syncthreads();
     }
@@ -108,13 +104,9 @@ void fill_batch_geometry(BatchInst& b) {
     CellLaunch cl(g);
     b.cell_tilesX = cl.tilesX;
     b.cell_nblocks = cl.nblocks;
-    switch (g.n) {
-        case 1: { RowLaunch<1, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
-        case 2: { RowLaunch<2, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
-        case 3: { RowLaunch<3, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
-        case 4: { RowLaunch<4, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
-        default: { RowLaunch<5, kRowWaves> r(g); b.row_tilesX = r.tilesX; b.row_nblocks = r.nblocks; } break;
-    }
+    RowLaunch rl(g);
+    b.row_tilesX = rl.tilesX;
+    b.row_nblocks = rl.nblocks;
     b.cells = (long)g.nx * g.ny;
     b.rows = b.cells * g.n;
     b.elems = b.rows * g.n;
@@ -123,34 +115,37 @@ void fill_batch_geometry(BatchInst& b) {
     b.nb_elems = pw_blocks(b.elems, pointwise_block_cap());
 }
 
-hipError_t launch_batch(int n, BatchKernel kind, const BatchInst* inst,
+hipError_t launch_batch(int n, int cw, int rw, BatchKernel kind, const BatchInst* inst,
                         const ItemList& list, int grid, hipStream_t s) {
-    const dim3 cell(64 * kCellWaves), row(64 * kRowWaves), pw(kPwThreads);
-    DG_DISPATCH_N(n, {
-        switch (kind) {
-            case BatchKernel::Mean:
-                hipLaunchKernelGGL((kb_cg_mean<NN>), dim3(grid), pw, 0, s, inst, list);
-                break;
-            case BatchKernel::Init:
-                hipLaunchKernelGGL((kb_cg_init<NN>), dim3(grid), cell, 0, s, inst, list);
-                break;
-            case BatchKernel::Dir:
-                hipLaunchKernelGGL((kb_cg_dir<NN>), dim3(grid), cell, 0, s, inst, list);
-                break;
-            case BatchKernel::Res:
-                hipLaunchKernelGGL((kb_cg_res<NN>), dim3(grid), cell, 0, s, inst, list);
-                break;
-            case BatchKernel::Finish:
-                hipLaunchKernelGGL((kb_cg_finish<NN>), dim3(grid), pw, 0, s, inst, list);
-                break;
-            case BatchKernel::SubMean:
-                hipLaunchKernelGGL(kb_sub_mean, dim3(grid), pw, 0, s, inst, list);
-                break;
-            case BatchKernel::Rhs:
-                hipLaunchKernelGGL((kb_rhs<NN>), dim3(grid), row, 0, s, inst, list);
-                break;
-        }
-    });
+    const dim3 pw(kPwThreads);
+    switch (kind) {
+        case BatchKernel::Mean:
+            DG_DISPATCH_N(n, hipLaunchKernelGGL((kb_cg_mean<NN>), dim3(grid), pw, 0, s, inst, list));
+            break;
+        case BatchKernel::Init:
+            DG_DISPATCH_NW(n, cw, hipLaunchKernelGGL((kb_cg_init<NN, WW>), dim3(grid),
+                                                     dim3(64 * WW), 0, s, inst, list));
+            break;
+        case BatchKernel::Dir:
+            DG_DISPATCH_NW(n, cw, hipLaunchKernelGGL((kb_cg_dir<NN, WW>), dim3(grid),
+                                                     dim3(64 * WW), 0, s, inst, list));
+            break;
+        case BatchKernel::Res:
+            DG_DISPATCH_NW(n, cw, hipLaunchKernelGGL((kb_cg_res<NN, WW>), dim3(grid),
+                                                     dim3(64 * WW), 0, s, inst, list));
+            break;
+        case BatchKernel::Finish:
+            DG_DISPATCH_N(n, hipLaunchKernelGGL((kb_cg_finish<NN>), dim3(grid), pw, 0, s, inst,
+                                                list));
+            break;
+        case BatchKernel::SubMean:
+            hipLaunchKernelGGL(kb_sub_mean, dim3(grid), pw, 0, s, inst, list);
+            break;
+        case BatchKernel::Rhs:
+            DG_DISPATCH_NR(n, rw, hipLaunchKernelGGL((kb_rhs<NN, WW>), dim3(grid), dim3(64 * WW),
+                                                     0, s, inst, list));
+            break;
+    }
     return hipGetLastError();
 }
 

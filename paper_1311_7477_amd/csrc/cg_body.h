@@ -1,8 +1,9 @@
 // LDG Laplacian and conjugate-gradient kernels (cell per lane).
 //
 // A lane holds all n*n nodal values of one cell in registers; a wave holds
-// 64 consecutive cells of one cell row, a workgroup kCellWaves consecutive
-// rows (a 64 x kCellWaves tile).  Each 1D operator couples a cell to its
+// 64 consecutive cells of one cell row, a workgroup WV consecutive rows (a
+// 64 x WV tile; WV in {4, 8, 16} is a template parameter chosen per grid by
+// the tile autotuner).  Each 1D operator couples a cell to its
 // neighbours only through one scalar per node row (x) or column (y) -- the
 // rank-one face blocks of the LDG second derivative (Sec. 6, built from the
 // one-sided variants of Sec. 3 eq. discrete_derivative) -- so:
@@ -23,7 +24,6 @@
 
 namespace dgk {
 
-constexpr int kCellWaves = 8;   // tile = 64 x 8 cells, 512 threads
 
 struct CellRef {
     long canon;   // canonical offset of node 0 (node e at +e)
@@ -46,7 +46,7 @@ __device__ __forceinline__ CellRef cell_ref(const Geom& g, int G, int cx, int cy
     return c;
 }
 
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ CellCtx make_cell_ctx(const Geom& g, int tilesX,
                                                  int nblocks, int b) {
     CellCtx c;
@@ -55,7 +55,7 @@ __device__ __forceinline__ CellCtx make_cell_ctx(const Geom& g, int tilesX,
     const int t = xcd_tile(b, nblocks);
     const int ty = t / tilesX, tx = t - ty * tilesX;
     const int cx = tx * 64 + c.lane;
-    const int cy = ty * kCellWaves + c.wave;
+    const int cy = ty * WV + c.wave;
     c.active = cx < g.nx && cy < g.ny;
     const int cxa = c.active ? cx : 0, cya = c.active ? cy : 0;
     const int cxr = (cxa + 1 < g.nx) ? cxa + 1 : 0;
@@ -64,7 +64,7 @@ __device__ __forceinline__ CellCtx make_cell_ctx(const Geom& g, int tilesX,
     const int cyd = (cya > 0) ? cya - 1 : g.ny - 1;
     c.xin_r = c.lane < 63 && cx + 1 < g.nx;
     c.xin_l = c.lane > 0;
-    c.yin_u = c.wave + 1 < kCellWaves && cy + 1 < g.ny;
+    c.yin_u = c.wave + 1 < WV && cy + 1 < g.ny;
     c.yin_d = c.wave > 0;
     const int G = tilesX;
     c.self = cell_ref<N>(g, G, cxa, cya);
@@ -130,18 +130,18 @@ __device__ __forceinline__ T ydot(const T (&u)[N * N], int i, const T* w) {
 }
 
 // LDS for the y face scalars of one tile: [wave][face][i][lane]
-template <int N, class T>
+template <int N, class T, int WV>
 struct YFaces {
-    T v[kCellWaves * 2 * N * 64];
+    T v[WV * 2 * N * 64];
 };
 
 // Lap_h u for this lane's cell.  `src(ref, out)` evaluates the field on a
 // halo cell; the own cell's values are passed in u.  Every thread of the
 // block must call it (one barrier).
-template <int N, class T, class Src>
+template <int N, int WV, class T, class Src>
 __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
                                          const Src& src, const T (&u)[N * N],
-                                         YFaces<N, T>& lds, T (&out)[N * N]) {
+                                         YFaces<N, T, WV>& lds, T (&out)[N * N]) {
     T hR[N], hL[N], hU[N], hD[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) hR[m] = hL[m] = hU[m] = hD[m] = 0;
@@ -294,37 +294,37 @@ __device__ __forceinline__ void zero_cell(T (&u)[N * N]) {
 }
 
 // out = Lap_h u (canonical layout in and out)
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void laplace_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ u, double* __restrict__ out,
-    YFaces<N, double>& lds) {
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
+    YFaces<N, double, WV>& lds) {
+    const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
     SrcCanon<N, double> src{u};
     double v[N * N], lap[N * N];
     if (c.active) src(c.self, v);
     else zero_cell<N>(v);
-    lap_cell<N>(c, k, src, v, lds, lap);
+    lap_cell<N, WV>(c, k, src, v, lds, lap);
     if (c.active) st_canon<N>(out, c.self, lap);
 }
 
 // CG setup (stencil part): x0 = guess - mean(guess) (to L64);
 // r0 = (omega - mean(omega)) + Lap_h x0 (to L64); partials <r0,r0>_W, <b,b>_W.
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void cg_init_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ omega, const double* __restrict__ pa,
     const double* __restrict__ pb, double ca, double cb,
     double* __restrict__ x, double* __restrict__ r, CgScalars* sc,
     unsigned* counter, double* partials,
-    YFaces<N, double>& lds) {
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
+    YFaces<N, double, WV>& lds) {
+    const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
     SrcGuess<N> src{pa, pb, ca, cb, sc->mean_guess};
     const double mo = sc->mean_omega;
     double x0[N * N], lap[N * N];
     if (c.active) src(c.self, x0);
     else zero_cell<N>(x0);
-    lap_cell<N>(c, k, src, x0, lds, lap);
+    lap_cell<N, WV>(c, k, src, x0, lds, lap);
     double part[2] = {0.0, 0.0};
     if (c.active) {
         double b[N * N];
@@ -340,7 +340,7 @@ __device__ __forceinline__ void cg_init_body(
         part[1] = wdot_cell<N>(k, b, b);
     }
     double tot[2];
-    if (reduce_last<2, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    if (reduce_last<2, 64 * WV>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         sc->rr = tot[0];
         sc->rz = tot[0];
@@ -369,17 +369,17 @@ __device__ __forceinline__ void cg_init_body(
 //   alpha_k = <r,r>_W / <p_k, q>_W.
 // p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
 // neighbouring tiles while p_k is written.  q is applied to p_k as stored.
-template <int N, class S>
+template <int N, class S, int WV>
 __device__ __forceinline__ void cg_dir_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const S* __restrict__ r, S* p0, S* p1, double* __restrict__ x,
     CgScalars* sc, unsigned* counter, double* partials,
-    YFaces<N, double>& lds) {
+    YFaces<N, double, WV>& lds) {
     if (sc->done) return;
     // iteration k reads p_{k-1} from buffer k mod 2 and writes p_k to the other
     const S* pin = (sc->iter & 1) ? p1 : p0;
     S* pout = (sc->iter & 1) ? p0 : p1;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
+    const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
     // first = 1: p = r; otherwise x += alpha p_old, p = r + beta p_old
     const int first = sc->first;
     const double alpha = sc->alpha;
@@ -406,7 +406,7 @@ __device__ __forceinline__ void cg_dir_body(
     } else {
         zero_cell<N>(p);
     }
-    lap_cell<N>(c, k, src, p, lds, q);
+    lap_cell<N, WV>(c, k, src, p, lds, q);
     constexpr int NV = kStoredLow<S> ? 2 : 1;
     double part[NV];
 #pragma unroll
@@ -419,7 +419,7 @@ __device__ __forceinline__ void cg_dir_body(
         if (kStoredLow<S>) part[NV - 1] = wdot_cell<N>(k, rv, p);
     }
     double tot[NV];
-    if (reduce_last<NV, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    if (reduce_last<NV, 64 * WV>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         sc->pq = tot[0];
         sc->first = 0;
@@ -436,14 +436,14 @@ __device__ __forceinline__ void cg_dir_body(
 
 // CG iteration, second half: q = A p_k; r -= alpha q; beta = <r,r>new/<r,r>;
 // convergence test ||r||_W^2 <= tol^2 ||b||_W^2 on r as stored.
-template <int N, class S>
+template <int N, class S, int WV>
 __device__ __forceinline__ void cg_res_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k, const S* p0,
     const S* p1, S* __restrict__ r, CgScalars* sc, unsigned* counter,
-    double* partials, YFaces<N, double>& lds) {
+    double* partials, YFaces<N, double, WV>& lds) {
     if (sc->done) return;
     const S* p = (sc->iter & 1) ? p0 : p1;   // p_k written by this iteration's direction update
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
+    const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
     const double alpha = sc->alpha;
     SrcL64<N, S> src{p};
     double pv[N * N], q[N * N], rv[N * N];
@@ -453,7 +453,7 @@ __device__ __forceinline__ void cg_res_body(
     } else {
         zero_cell<N>(pv);
     }
-    lap_cell<N>(c, k, src, pv, lds, q);   // q = Lap p = -A p
+    lap_cell<N, WV>(c, k, src, pv, lds, q);   // q = Lap p = -A p
     double part[1] = {0.0};
     if (c.active) {
 #pragma unroll
@@ -462,7 +462,7 @@ __device__ __forceinline__ void cg_res_body(
         part[0] = wdot_cell<N>(k, rv, rv);
     }
     double tot[1];
-    if (reduce_last<1, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    if (reduce_last<1, 64 * WV>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         const double rrn = tot[0];
         if (!sc->precond) {           // plain CG: z = r
@@ -522,15 +522,15 @@ struct SrcMixedX {
 
 constexpr double kReplaceDrop2 = 1e-2;
 
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void mixed_replace_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ omega, const double* __restrict__ x,
     const float* __restrict__ q0, const float* __restrict__ q1,
     float* __restrict__ r32, CgScalars* sc, unsigned* counter, double* partials,
-    YFaces<N, double>& lds) {
+    YFaces<N, double, WV>& lds) {
     if (!sc->done && !(sc->rr <= kReplaceDrop2 * sc->rr_max)) return;
-    const CellCtx c = make_cell_ctx<N>(g, tilesX, nblocks, b);
+    const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
     const bool pending = sc->first != 1 && !sc->breakdown;
     const float* pl = (sc->iter & 1) ? q1 : q0;
     SrcMixedX<N> src{x, pl, sc->alpha, pending};
@@ -538,7 +538,7 @@ __device__ __forceinline__ void mixed_replace_body(
     double v[N * N], lap[N * N];
     if (c.active) src(c.self, v);
     else zero_cell<N>(v);
-    lap_cell<N>(c, k, src, v, lds, lap);
+    lap_cell<N, WV>(c, k, src, v, lds, lap);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.active) {
         double w[N * N], rd[N * N], pv[N * N];
@@ -555,7 +555,7 @@ __device__ __forceinline__ void mixed_replace_body(
         part[2] = wdot_cell<N>(k, rd, pv);
     }
     double tot[3];
-    if (reduce_last<3, 64 * kCellWaves>(part, partials, counter, nblocks, b, tot) &&
+    if (reduce_last<3, 64 * WV>(part, partials, counter, nblocks, b, tot) &&
         threadIdx.x == 0) {
         const bool rec_met = sc->rr <= sc->tol2 * sc->bb;
         const double prev = sc->rr_true_prev;
@@ -594,7 +594,7 @@ struct CellLaunch {
     int tilesX, tilesY, nblocks;
     __host__ __device__ explicit CellLaunch(const Geom& g) {
         tilesX = (g.nx + 63) / 64;
-        tilesY = (g.ny + kCellWaves - 1) / kCellWaves;
+        tilesY = (g.ny + g.cw - 1) / g.cw;
         nblocks = tilesX * tilesY;
     }
 };

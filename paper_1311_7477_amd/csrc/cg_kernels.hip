@@ -1,58 +1,59 @@
 // Single-instance launches of the LDG Laplacian and CG kernels (cell per
 // lane; the device code and its layout conventions are in cg_body.h).  One
-// block per 64 x kCellWaves tile; block b processes tile xcd_tile(b).
+// block per 64 x WV tile (WV = the grid's cell tile height g.cw, one of 4, 8,
+// 16); block b processes tile xcd_tile(b).
 #include "cg_body.h"
 #include "dg_launch.h"
 
 namespace dgk {
 
-template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void k_laplace(
+template <int N, int WV>
+__global__ __launch_bounds__(64 * WV) void k_laplace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ u, double* __restrict__ out) {
-    __shared__ YFaces<N, double> lds;
-    laplace_body<N>(blockIdx.x, g, tilesX, nblocks, k, u, out, lds);
+    __shared__ YFaces<N, double, WV> lds;
+    laplace_body<N, WV>(blockIdx.x, g, tilesX, nblocks, k, u, out, lds);
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void k_cg_init(
+template <int N, int WV>
+__global__ __launch_bounds__(64 * WV) void k_cg_init(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ omega, const double* __restrict__ pa,
     const double* __restrict__ pb, double ca, double cb,
     double* __restrict__ x, double* __restrict__ r, CgScalars* sc,
     unsigned* counter, double* partials) {
-    __shared__ YFaces<N, double> lds;
-    cg_init_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, pa, pb, ca, cb, x,
+    __shared__ YFaces<N, double, WV> lds;
+    cg_init_body<N, WV>(blockIdx.x, g, tilesX, nblocks, k, omega, pa, pb, ca, cb, x,
                     r, sc, counter, partials, lds);
 }
 
-template <int N, class S>
-__global__ __launch_bounds__(64 * kCellWaves) void k_cg_dir(
+template <int N, class S, int WV>
+__global__ __launch_bounds__(64 * WV) void k_cg_dir(
     Geom g, int tilesX, int nblocks, OpConst<double> k, const S* __restrict__ r,
     S* p0, S* p1, double* __restrict__ x, CgScalars* sc, unsigned* counter,
     double* partials) {
-    __shared__ YFaces<N, double> lds;
-    cg_dir_body<N, S>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
+    __shared__ YFaces<N, double, WV> lds;
+    cg_dir_body<N, S, WV>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
                       counter, partials, lds);
 }
 
-template <int N, class S>
-__global__ __launch_bounds__(64 * kCellWaves) void k_cg_res(
+template <int N, class S, int WV>
+__global__ __launch_bounds__(64 * WV) void k_cg_res(
     Geom g, int tilesX, int nblocks, OpConst<double> k, const S* p0, const S* p1,
     S* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
-    __shared__ YFaces<N, double> lds;
-    cg_res_body<N, S>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
+    __shared__ YFaces<N, double, WV> lds;
+    cg_res_body<N, S, WV>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
                       partials, lds);
 }
 
-template <int N>
-__global__ __launch_bounds__(64 * kCellWaves) void k_mixed_replace(
+template <int N, int WV>
+__global__ __launch_bounds__(64 * WV) void k_mixed_replace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ omega, const double* __restrict__ x,
     const float* __restrict__ q0, const float* __restrict__ q1,
     float* __restrict__ r32, CgScalars* sc, unsigned* counter, double* partials) {
-    __shared__ YFaces<N, double> lds;
-    mixed_replace_body<N>(blockIdx.x, g, tilesX, nblocks, k, omega, x, q0, q1, r32,
+    __shared__ YFaces<N, double, WV> lds;
+    mixed_replace_body<N, WV>(blockIdx.x, g, tilesX, nblocks, k, omega, x, q0, q1, r32,
                           sc, counter, partials, lds);
 }
 
@@ -64,8 +65,8 @@ int cell_blocks(const Geom& g) { return CellLaunch(g).nblocks; }
 hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,
                           const double* u, double* out, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_laplace<NN>), dim3(L.nblocks),
-                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_laplace<NN, WW>), dim3(L.nblocks),
+                                          dim3(64 * WW), 0, s, g, L.tilesX,
                                           L.nblocks, k, u, out));
     return hipGetLastError();
 }
@@ -75,8 +76,8 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                           const double* pb, double ca, double cb, double* x,
                           double* r, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN>), dim3(L.nblocks),
-                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_init<NN, WW>), dim3(L.nblocks),
+                                          dim3(64 * WW), 0, s, g, L.tilesX,
                                           L.nblocks, k, omega, pa, pb, ca, cb, x, r,
                                           d.sc, d.counters + kCntInit, d.partials));
     return hipGetLastError();
@@ -86,8 +87,8 @@ template <class S>
 hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* r, S* p0,
                          S* p1, CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S>), dim3(L.nblocks),
-                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_dir<NN, S, WW>), dim3(L.nblocks),
+                                          dim3(64 * WW), 0, s, g, L.tilesX,
                                           L.nblocks, k, r, p0, p1, x, sc,
                                           d.counters + kCntDir, d.partials));
     return hipGetLastError();
@@ -97,8 +98,8 @@ template <class S>
 hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
                          CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S>), dim3(L.nblocks),
-                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_res<NN, S, WW>), dim3(L.nblocks),
+                                          dim3(64 * WW), 0, s, g, L.tilesX,
                                           L.nblocks, k, p0, p1, r, sc,
                                           d.counters + kCntRes, d.partials));
     return hipGetLastError();
@@ -132,8 +133,8 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
                                 const float* q1, float* r32, const DevScratch& d,
                                 hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_replace<NN>), dim3(L.nblocks),
-                                          dim3(64 * kCellWaves), 0, s, g, L.tilesX,
+    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_mixed_replace<NN, WW>), dim3(L.nblocks),
+                                          dim3(64 * WW), 0, s, g, L.tilesX,
                                           L.nblocks, k, omega, x, q0, q1, r32,
                                           d.sc, d.counters + kCntDot, d.partials));
     return hipGetLastError();

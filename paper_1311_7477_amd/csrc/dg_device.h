@@ -124,6 +124,24 @@ __device__ bool reduce_last(double (&v)[NV], double* partials,
         default: return hipErrorInvalidValue; \
     }
 
+// Dispatch on the polynomial order n (NN) and the tile height w in waves
+// (WW, one of 4, 8, 16) of a cell-per-lane or row-per-lane kernel.
+#define DG_DISPATCH_NW(n, w, ...)                                          \
+    switch (w) {                                                           \
+        case 4: { constexpr int WW = 4; DG_DISPATCH_N(n, __VA_ARGS__); } break;   \
+        case 8: { constexpr int WW = 8; DG_DISPATCH_N(n, __VA_ARGS__); } break;   \
+        case 16: { constexpr int WW = 16; DG_DISPATCH_N(n, __VA_ARGS__); } break; \
+        default: return hipErrorInvalidValue;                              \
+    }
+
+// Dispatch on n (NN) and the bracket kernel's tile height (WW, 8 or 16).
+#define DG_DISPATCH_NR(n, w, ...)                                          \
+    switch (w) {                                                           \
+        case 8: { constexpr int WW = 8; DG_DISPATCH_N(n, __VA_ARGS__); } break;   \
+        case 16: { constexpr int WW = 16; DG_DISPATCH_N(n, __VA_ARGS__); } break; \
+        default: return hipErrorInvalidValue;                              \
+    }
+
 inline int pw_blocks(long rows, int cap) {
     long b = (rows + kPwThreads - 1) / kPwThreads;
     if (b > cap) b = cap;

@@ -36,9 +36,16 @@ struct OpConst {
     double wq;                // hx * hy / 4: node weight = wq * w_i * w_j
 };
 
-// Geometry of one launch.
+// Default tile heights in waves: cell-per-lane tiles of 64 x 8 cells,
+// bracket tiles of 8 rows (the tuner may pick 4 / 16 and 16).
+constexpr int kCellWavesDefault = 8;
+constexpr int kRowWavesDefault = 8;
+
+// Geometry of one launch, with the grid's tile shapes: cw waves (cell rows)
+// per cell-per-lane tile, rw waves per row-per-lane bracket tile.
 struct Geom {
     int n, nx, ny;
+    int cw, rw;
 };
 
 // Bracket / right-hand-side kernel parameters:

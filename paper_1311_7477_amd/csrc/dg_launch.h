@@ -13,8 +13,10 @@ struct RhsParams {
     double D, dt, a, b;         // viscosity and RK-stage combination
 };
 
-// Blocks of one launch of each stencil family; the reduction partials
-// buffer holds at least max(stencil_blocks, pointwise_block_cap) entries.
+// Blocks of one launch of each stencil family for the grid's tile shapes;
+// stencil_blocks is the maximum over every tile shape.  The reduction
+// partials buffer holds at least max(stencil_blocks, pointwise_block_cap)
+// entries.
 int row_blocks(const Geom& g);
 int cell_blocks(const Geom& g);
 int stencil_blocks(const Geom& g);

@@ -69,7 +69,13 @@ __global__ __launch_bounds__(kPwThreads) void k_guess(long elems,
 int pointwise_block_cap() { return 1024; }
 
 int stencil_blocks(const Geom& g) {
-    const int a = row_blocks(g), b = cell_blocks(g);
+    // the most blocks any tile shape of this grid can launch (cell tiles of
+    // 4 waves, bracket tiles of 8), so a workspace sized once serves every
+    // shape the tuner may choose later
+    Geom w = g;
+    w.cw = 4;
+    w.rw = 8;
+    const int a = row_blocks(w), b = cell_blocks(w);
     return a > b ? a : b;
 }
 

@@ -27,7 +27,6 @@ struct Tile {
     static constexpr int LDS_FIELD = WAVES * S * CS;
 };
 
-constexpr int kRowWaves = 8;
 
 template <int N, int WAVES>
 struct Ctx {
@@ -239,13 +238,13 @@ __device__ __forceinline__ void rhs_body(
 }
 
 
-template <int N, int WAVES>
 struct RowLaunch {
-    using TL = Tile<N, WAVES>;
     int tilesX, tilesY, nblocks;
+    // interior cells per tile: (64 / n - 2) along x, rw - 2 along y (Tile)
     __host__ __device__ explicit RowLaunch(const Geom& g) {
-        tilesX = (g.nx + TL::TX - 1) / TL::TX;
-        tilesY = (g.ny + TL::TY - 1) / TL::TY;
+        const int tx = 64 / g.n - 2, ty = g.rw - 2;
+        tilesX = (g.nx + tx - 1) / tx;
+        tilesY = (g.ny + ty - 1) / ty;
         nblocks = tilesX * tilesY;
     }
 };

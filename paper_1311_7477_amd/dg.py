@@ -84,6 +84,10 @@ def lib():
         "dg_cg_solve_poisson": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(CgOpts),
                                                ctypes.POINTER(CgStats), _vp, _vp]),
         "dg_precond_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+        "dg_grid_set_tiles": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+        "dg_grid_tiles": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int)]),
+        "dg_grid_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
         "dg_grid_fd_basis": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp,
                                             ctypes.POINTER(ctypes.c_int)]),
         "dg_state_create": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(_vp)]),
@@ -154,6 +158,23 @@ class Grid:
         out = (ctypes.c_double * 256)()
         k = _check_count(lib().dg_grid_tables(self._h, out, 256))
         return [out[i] for i in range(k)]
+
+    def set_tiles(self, cw, rw):
+        """Cell tile height cw in {4, 8, 16}, bracket tile height rw in {8, 16}."""
+        _check(lib().dg_grid_set_tiles(self._h, cw, rw))
+
+    def tiles(self):
+        cw, rw = ctypes.c_int(), ctypes.c_int()
+        _check(lib().dg_grid_tiles(self._h, ctypes.byref(cw), ctypes.byref(rw)))
+        return cw.value, rw.value
+
+    def tune(self, omega, reps=20):
+        """Time every tile shape on this grid (omega: a device field with a
+        nonzero mean-free part), keep the fastest; returns ((cw, rw), ms) with
+        ms = per-iteration / per-bracket times of cw = 4, 8, 16 and rw = 8, 16."""
+        ms = (ctypes.c_double * 5)()
+        _check(lib().dg_grid_tune(self._h, _field(omega, self, "omega"), reps, ms, _stream()))
+        return self.tiles(), list(ms)
 
     def fd_basis(self, axis=0):
         """(V, lam, zero) of the fast-diagonalisation basis along one axis

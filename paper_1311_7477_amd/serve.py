@@ -89,7 +89,11 @@ def prepare(req: Request):
 
 
 class Server:
-    def __init__(self, capacity=64, hbm_budget=None, opts=None):
+    """Continuous-batching request loop.  With tune=True the tile shapes of
+    each (n, N) are chosen once by the library's tile autotuner (on the first
+    admitted request of that shape) and reused for later ones."""
+
+    def __init__(self, capacity=64, hbm_budget=None, opts=None, tune=True):
         import torch
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info()
@@ -104,6 +108,8 @@ class Server:
         self.max_active = 0
         self.peak_used = 0
         self.rejected = []
+        self.tune = tune
+        self.tiles = {}           # (n, N) -> (cell tile height, bracket tile height)
 
     def fits(self, req: Request) -> bool:
         return (len(self.active) < self.capacity and
@@ -114,6 +120,11 @@ class Server:
         w0 = prepare(req)
         req.grid = dg.Grid(req.n, req.N, req.N)
         req.omega = torch.from_numpy(w0).cuda()
+        key = (req.n, req.N)
+        if self.tune and key not in self.tiles:
+            self.tiles[key] = req.grid.tune(req.omega, reps=5)[0]
+        if key in self.tiles:
+            req.grid.set_tiles(*self.tiles[key])
         req.slot = self.batch.attach(req.grid, req.omega, req.dt, req.D)
         req.admitted = now
         self.used += req.bytes
@@ -183,12 +194,15 @@ def summarize(done, makespan):
     }
 
 
-def run_alone(req: Request, opts=None):
+def run_alone(req: Request, opts=None, tiles=None):
     """The same request stepped alone with dg_rk_step (for the alone-vs-mix
-    check): returns the final omega on the host."""
+    check), with the tile shapes the server used: returns the final omega on
+    the host."""
     import torch
     w0 = prepare(req)
     grid = dg.Grid(req.n, req.N, req.N)
+    if tiles is not None:
+        grid.set_tiles(*tiles)
     ws, st = dg.Workspace(grid), dg.State(grid)
     w = torch.from_numpy(w0).cuda()
     for _ in range(req.steps):

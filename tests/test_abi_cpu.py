@@ -158,3 +158,21 @@ def test_fd_basis_diagonalises_the_oracle_operator(n, N, length):
     assert np.ptp(c) <= 1e-12 * np.abs(c).max()
     ref = np.sort(np.linalg.eigvals(L).real)
     np.testing.assert_allclose(np.sort(lam), ref, atol=1e-10 * scale)
+
+
+def test_tile_shapes_default_and_validation():
+    from paper_1311_7477_amd import dg
+    g = dg.Grid(3, 10, 12)
+    assert g.tiles() == (8, 8)
+    for cw, rw in [(4, 8), (16, 16), (8, 16)]:
+        g.set_tiles(cw, rw)
+        assert g.tiles() == (cw, rw)
+    for cw, rw in [(2, 8), (8, 4), (32, 8), (8, 32), (0, 0)]:
+        with pytest.raises(dg.DgError) as e:
+            g.set_tiles(cw, rw)
+        assert e.value.code == dg.DG_E_INVAL
+    assert g.tiles() == (8, 16)
+    # workspaces are sized for every tile shape: the same bytes whatever the shape
+    b = g.workspace_bytes()
+    g.set_tiles(4, 8)
+    assert g.workspace_bytes() == b

@@ -33,8 +33,9 @@ def test_mixed_stream_equals_alone(serve):
     done = srv.run(reqs)
     assert len(done) == len(reqs)
     assert srv.max_active > 1            # requests overlapped on the device
+    assert all(v[0] in (4, 8, 16) and v[1] in (8, 16) for v in srv.tiles.values())
     for r in done:
-        alone = serve.run_alone(r, opts)
+        alone = serve.run_alone(r, opts, srv.tiles.get((r.n, r.N)))
         same = bool(np.array_equal(r.result, alone))
         assert same, f"request {r.rid}: differs by {np.abs(r.result - alone).max():.3e}"
         assert r.latency > 0 and r.admitted >= r.arrival
