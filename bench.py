@@ -246,6 +246,28 @@ def form_mixed(args):
     }), flush=True)
 
 
+def form_tune(args):
+    """Tile autotuner sweep: for n in {2,3,4,5} and N in {64, 256, 512, 1024},
+    dg_grid_tune on a random-spectrum field; prints one line per case with
+    the chosen shapes and the per-shape times (CG iteration, bracket)."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    rows = []
+    for n in (2, 3, 4, 5):
+        for N in (64, 256, 512, 1024):
+            w0 = inputs.random_spectrum(n, N, k0=8.0, seed=1)
+            g = dg.Grid(n, N, N)
+            (cw, rw), ms = g.tune(torch.from_numpy(w0).cuda(), reps=10)
+            F = 8 * N * N * n * n
+            rows.append({"n": n, "N": N, "cw": cw, "rw": rw,
+                         "cg_iter_ms": dict(zip(("cw4", "cw8", "cw16"), ms[:3])),
+                         "bracket_ms": dict(zip(("rw8", "rw16"), ms[3:])),
+                         "cg_GBps_at_8F": 8 * F / (ms[(4, 8, 16).index(cw)] * 1e-3) / 1e9})
+            print(f"[tune] {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "tile autotuner sweep", "cases": rows,
+                      "data": "synthetic", "dtype": "f64"}), flush=True)
+
+
 def form_serve(args):
     """Serving: a seeded Poisson stream of requests (n uniform over {2..5},
     N log-uniform, random spectra), continuous batching under an HBM budget;
@@ -362,7 +384,7 @@ def main():
                     help="also run 3 plain 256 MiB device copies (torch copy_) whose "
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     ap.add_argument("--form", default="rhs",
-                    choices=["rhs", "batch", "mixed", "serve", "paper"],
+                    choices=["rhs", "batch", "mixed", "serve", "paper", "tune"],
                     help="rhs: the headline metric (default); the others measure "
                          "the batched, mixed-precision and served forms and the "
                          "paper's bracket-timing shape")
@@ -385,7 +407,7 @@ def main():
     torch.cuda.set_device(0)
     if args.form != "rhs":
         {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
-         "paper": form_paper}[args.form](args)
+         "paper": form_paper, "tune": form_tune}[args.form](args)
         return
     n, N = args.n, args.N
     if args.copy_calibration:
