@@ -246,6 +246,50 @@ def form_mixed(args):
     }), flush=True)
 
 
+def form_lamb(args):
+    """Table 4 of the paper on the GPU: the Lamb dipole (P = 1, N = 200, box
+    1 x 1, U = 1, R = 0.1, D = 0) integrated to t = 0.01 with the K-step
+    Adams-Bashforth method, K = 1..4, 10/20/40/80 steps (PCG, rtol 1e-14);
+    relative enstrophy and energy errors, their orders, and the time."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    n, N = 1, 200
+    grid = dg.Grid(n, N, N, 0.0, 1.0, 0.0, 1.0)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    opts = dg.cg_opts(rtol=1e-14, precond=dg.DG_PRECOND_FD)
+    w0 = torch.from_numpy(inputs.lamb_dipole(n, N)).cuda()
+    p0 = torch.zeros_like(w0)
+    dg.cg_solve_poisson(grid, w0, p0, ws, opts)
+    V0, E0, Om0 = dg.invariants(grid, w0, p0, ws)
+    rows = []
+    for K in (1, 2, 3, 4):
+        prev = None
+        for steps in (10, 20, 40, 80):
+            ab = dg.AbState(grid, K)
+            w = w0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                dg.ab_step(grid, w, ab, ws, 0.01 / steps, 0.0, opts)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            psi = ab.psi()
+            dg.cg_solve_poisson(grid, w, psi, ws, opts)
+            V, E, Om = dg.invariants(grid, w, psi, ws)
+            eo, ee = abs((Om - Om0) / Om0), abs((E - E0) / E0)
+            row = {"K": K, "steps": steps, "eps_V": abs(V), "eps_Omega": eo, "eps_E": ee,
+                   "order_Omega": math.log2(prev[0] / eo) if prev else None,
+                   "order_E": math.log2(prev[1] / ee) if prev else None,
+                   "ms_per_step": t / steps * 1e3}
+            prev = (eo, ee)
+            rows.append(row)
+            print(f"[lamb] {row}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "Table 4: Lamb dipole conservation errors, K-step Adams-Bashforth",
+                      "rows": rows, "data": "synthetic (analytic Lamb dipole)", "dtype": "f64",
+                      "config": {"workload": "P=1, 200x200 cells, [0,1]^2, U=1, R=0.1, D=0, "
+                                             "t in [0, 0.01], PCG rtol 1e-14"}}), flush=True)
+
+
 def form_tune(args):
     """Tile autotuner sweep: for n in {2,3,4,5} and N in {64, 256, 512, 1024},
     dg_grid_tune on a random-spectrum field; prints one line per case with
@@ -384,7 +428,7 @@ def main():
                     help="also run 3 plain 256 MiB device copies (torch copy_) whose "
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     ap.add_argument("--form", default="rhs",
-                    choices=["rhs", "batch", "mixed", "serve", "paper", "tune"],
+                    choices=["rhs", "batch", "mixed", "serve", "paper", "tune", "lamb"],
                     help="rhs: the headline metric (default); the others measure "
                          "the batched, mixed-precision and served forms and the "
                          "paper's bracket-timing shape")
@@ -407,7 +451,7 @@ def main():
     torch.cuda.set_device(0)
     if args.form != "rhs":
         {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
-         "paper": form_paper, "tune": form_tune}[args.form](args)
+         "paper": form_paper, "tune": form_tune, "lamb": form_lamb}[args.form](args)
         return
     n, N = args.n, args.N
     if args.copy_calibration:

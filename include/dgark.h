@@ -250,6 +250,31 @@ int  dg_rk_step(const dg_grid* grid, double* omega, dg_state* state,
                 const dg_step_opts* opts, dg_step_stats* stats,
                 dg_workspace* ws, void* stream);
 
+/* K-step Adams-Bashforth stepping, the paper's integrator (Sec. 6 uses three
+ * steps; Sec. 6.2, Table 4 runs K = 1..4):
+ *     omega_{n+1} = omega_n + dt sum_{j<K} b_j R(omega_{n-j}),
+ *     b = (1), (3/2, -1/2), (23, -16, 5)/12, (55, -59, 37, -9)/24,
+ * R = -J(psi, omega) + D Lap_h omega, psi from one Poisson solve per step
+ * (opts->cg, initial guess extrapolated from the last two solves).  The
+ * state owns K right-hand-side fields and a dg_state (psi history, time).
+ * While fewer than K-1 earlier right-hand sides are known the step is an
+ * SSP-RK3 step (the paper does not state the start-up; this reading makes
+ * the start third-order accurate).  K outside [1, 4]: DG_E_INVAL. */
+typedef struct dg_ab_state dg_ab_state;
+int  dg_ab_state_create(const dg_grid* grid, int K, double t0, dg_ab_state** out);
+void dg_ab_state_destroy(dg_ab_state* ab);           /* NULL-safe */
+double dg_ab_time(const dg_ab_state* ab);
+/* The psi history inside (for dg_state_psi / dg_state_copy_psi). */
+const dg_state* dg_ab_psi_state(const dg_ab_state* ab);
+/* One step; omega (device, canonical) is updated in place, the state's time
+ * advances by opts->dt.  stats->cg_iters[0]: the solve of this step;
+ * [1]: the start-up RK3 stages' solves (0 once the multistep method runs).
+ * Synchronises the stream.  DG_E_NOCONV if a solve hit max_iter (the step
+ * is still completed). */
+int  dg_ab_step(const dg_grid* grid, double* omega, dg_ab_state* ab,
+                const dg_step_opts* opts, dg_step_stats* stats, dg_workspace* ws,
+                void* stream);
+
 /* --------------------------------------------------------- invariants --- */
 /* out[0..2] = (V, E, Omega) = (int omega, 1/2 int psi omega, 1/2 int omega^2)
  * (Sec. 2 eq. quantities, E by the Green identity) with Gauss quadrature

@@ -30,7 +30,7 @@ __all__ = [
     "to_image", "from_image", "dx", "dy", "dx_form", "dy_form",
     "bracket_forms", "bracket", "laplacian", "inner", "wmean",
     "cg_poisson", "pcg_poisson", "FastDiagonalisation", "rhs", "rk3_step",
-    "PsiHistory", "invariants",
+    "PsiHistory", "invariants", "AB_COEFFS", "ab_step",
     "dense_operators", "dense_poisson_solve", "arakawa_fd_jacobian",
     "five_point_laplacian",
 ]
@@ -487,6 +487,62 @@ def rk3_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float,
 
     def stage_rhs(w, ts):
         res = cg_poisson(g, w, hist.guess(ts), rtol, max_iter)
+        hist.push(ts, res.x)
+        iters.append(res.iters)
+        return rhs(g, w, res.x, D)
+
+    u1 = omega + dt * stage_rhs(omega, t)
+    u2 = 0.75 * omega + 0.25 * (u1 + dt * stage_rhs(u1, t + dt))
+    u3 = omega / 3.0 + (2.0 / 3.0) * (u2 + dt * stage_rhs(u2, t + 0.5 * dt))
+    return u3, iters
+
+
+# --------------------------------------------------------------------------
+# K-step Adams-Bashforth (Sec. 6: the paper's stepper, three steps; Sec. 6.2
+# and Table 4: K = 1..4)
+# --------------------------------------------------------------------------
+# omega_{n+1} = omega_n + dt sum_j b_j R(omega_{n-j}), j = 0..K-1: the
+# explicit Adams-Bashforth weights of order K (integrals of the Lagrange
+# polynomials through the last K right-hand sides).
+AB_COEFFS = {
+    1: (1.0,),
+    2: (3.0 / 2.0, -1.0 / 2.0),
+    3: (23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0),
+    4: (55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0),
+}
+
+
+def ab_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float, K: int,
+            rhs_hist: list, hist: PsiHistory, rtol=1e-12, max_iter=100000,
+            precond=None):
+    """One step of the K-step Adams-Bashforth method.  rhs_hist holds the
+    right-hand sides of the previous steps, most recent first, and is
+    updated in place.  While fewer than K-1 are known the step is an SSP-RK3
+    step instead (the paper does not state how the multistep method starts;
+    this reading starts it with a third-order one-step method), after
+    recording R(omega_n).  Each R needs the Poisson solve of its omega, from
+    the extrapolated guess.  Returns (omega_new, [cg iteration counts])."""
+    res = pcg_poisson(g, omega, hist.guess(t), rtol, max_iter, precond)
+    hist.push(t, res.x)
+    r_n = rhs(g, omega, res.x, D)
+    if len(rhs_hist) < K - 1:
+        rhs_hist.insert(0, r_n)
+        w, its = _rk3_precond(g, omega, t, dt, D, hist, rtol, max_iter, precond)
+        return w, [res.iters] + its
+    rs = [r_n] + rhs_hist[:K - 1]
+    w = omega.copy()
+    for b, r in zip(AB_COEFFS[K], rs):
+        w = w + (dt * b) * r
+    rhs_hist[:] = rs[:K - 1]
+    return w, [res.iters]
+
+
+def _rk3_precond(g, omega, t, dt, D, hist, rtol, max_iter, precond):
+    """rk3_step with an optional CG preconditioner (same stages)."""
+    iters = []
+
+    def stage_rhs(w, ts):
+        res = pcg_poisson(g, w, hist.guess(ts), rtol, max_iter, precond)
         hist.push(ts, res.x)
         iters.append(res.iters)
         return rhs(g, w, res.x, D)

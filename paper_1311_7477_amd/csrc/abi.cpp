@@ -387,6 +387,14 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
 
 }  // namespace
 
+namespace dgk {
+int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,
+                  double ca, const double* pb, double cb, const dg_cg_opts* opts,
+                  dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+    return cg_dispatch(g, omega, x, pa, ca, pb, cb, opts, st, ws, s);
+}
+}  // namespace dgk
+
 extern "C" {
 
 const char* dg_last_error(void) { return g_err.c_str(); }

@@ -61,6 +61,11 @@ void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
                  const double** pb, double* cb, double** x, int* xi);
 // Record that buffer xi now holds the solve at time ts.
 void state_push(dg_state* st, int xi, double ts);
+// The Poisson solve behind dg_cg_solve_poisson and the steppers: guess
+// ca pa + cb pb (canonical), result in x (canonical, must not alias pa, pb).
+int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,
+                  double ca, const double* pb, double cb, const dg_cg_opts* opts,
+                  dg_cg_stats* st, dg_workspace* ws, hipStream_t s);
 // Fast-diagonalisation preconditioner resources (fd_apply.cpp): device bytes,
 // creation / destruction, and z = M r on the image buffer img0 in place.
 size_t fd_bytes(const dg_grid* g);

@@ -391,7 +391,7 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
             r.w_in = win[k];
             r.w_out = wout[k];
             r.w_n = k ? sl.omega : nullptr;
-            r.ra = RhsArgs{1.0, 1.0, 1.0, 1.0 / 3.0, sl.D, sl.dt, ra_a[k], ra_b[k]};
+            r.ra = RhsArgs{1.0, 1.0, 1.0, 1.0 / 3.0, sl.D, sl.dt, ra_a[k], ra_b[k], 0};
             r.tol2 = o.rtol * o.rtol;
             r.max_iter = o.max_iter;
         }

@@ -50,10 +50,12 @@ struct Geom {
 
 // Bracket / right-hand-side kernel parameters:
 //   J = scale * (c0 J++ + Dx(c1 f Dy g - c2 Dy f g) + Dy(c2 Dx f g - c1 f Dx g))
-// and, for an RK stage, out = a * w_n + b * (g + dt * (-J + D Lap_h g)).
+// and, for an RK stage, out = a * w_n + b * (g + dt * (-J + D Lap_h g)), or
+// with only_r set the right-hand side itself, out = -J + D Lap_h g.
 struct RhsArgs {
     double c0, c1, c2, scale;
     double D, dt, a, b;
+    int only_r;
 };
 
 // Device-side scalars of one CG solve (lives in the workspace).

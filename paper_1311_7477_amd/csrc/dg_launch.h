@@ -11,6 +11,7 @@ namespace dgk {
 struct RhsParams {
     double c0, c1, c2, scale;   // bracket form coefficients
     double D, dt, a, b;         // viscosity and RK-stage combination
+    int only_r;                 // 1: out = -J + D Lap_h g (no stage combination)
 };
 
 // Blocks of one launch of each stencil family for the grid's tile shapes;
@@ -94,5 +95,9 @@ hipError_t launch_fd_scale(int NX, int NY, double* img, const double* lx, const 
                            int zx, int zy, hipStream_t s);
 hipError_t launch_guess(long elems, double* x, const double* pa,
                         const double* pb, double ca, double cb, hipStream_t s);
+// Adams-Bashforth update omega += sum_{j<K} c[j] R[j] (element-wise, in the
+// order j = 0..K-1), K in [1, 4].
+hipError_t launch_ab_combine(long elems, double* omega, const double* const* R,
+                             const double* c, int K, hipStream_t s);
 
 }  // namespace dgk

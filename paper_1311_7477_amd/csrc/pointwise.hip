@@ -55,6 +55,13 @@ __global__ __launch_bounds__(kPwThreads) void k_mixed_start(
     mixed_start_body<N>(blockIdx.x, gridDim.x, g, k, r64, r32, sc, counter, partials);
 }
 
+__global__ __launch_bounds__(kPwThreads) void k_ab_combine(
+    long elems, double* __restrict__ omega, const double* r0, const double* r1,
+    const double* r2, const double* r3, double c0, double c1, double c2, double c3,
+    int K) {
+    ab_combine_body(blockIdx.x, gridDim.x, elems, omega, r0, r1, r2, r3, c0, c1, c2, c3, K);
+}
+
 __global__ __launch_bounds__(kPwThreads) void k_guess(long elems,
                                                       double* __restrict__ x,
                                                       const double* pa,
@@ -153,6 +160,16 @@ hipError_t launch_mixed_start(const Geom& g, const OpConst<double>& k,
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_start<NN>), dim3(nb),
                                           dim3(kPwThreads), 0, s, g, k, r64, r32,
                                           d.sc, d.counters + kCntMean, d.partials));
+    return hipGetLastError();
+}
+
+hipError_t launch_ab_combine(long elems, double* omega, const double* const* R,
+                             const double* c, int K, hipStream_t s) {
+    if (K < 1 || K > 4) return hipErrorInvalidValue;
+    const int nb = pw_blocks(elems, pointwise_block_cap());
+    hipLaunchKernelGGL(k_ab_combine, dim3(nb), dim3(kPwThreads), 0, s, elems, omega, R[0],
+                       K > 1 ? R[1] : R[0], K > 2 ? R[2] : R[0], K > 3 ? R[3] : R[0], c[0],
+                       K > 1 ? c[1] : 0.0, K > 2 ? c[2] : 0.0, K > 3 ? c[3] : 0.0, K);
     return hipGetLastError();
 }
 

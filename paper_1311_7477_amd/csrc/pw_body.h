@@ -235,4 +235,21 @@ __device__ __forceinline__ void mixed_start_body(int b, int nb, Geom g,
     }
 }
 
+// Adams-Bashforth update: omega += c0 R0 + c1 R1 + ... (K terms, in order).
+__device__ __forceinline__ void ab_combine_body(int b, int nb, long elems,
+                                                double* __restrict__ omega,
+                                                const double* r0, const double* r1,
+                                                const double* r2, const double* r3,
+                                                double c0, double c1, double c2, double c3,
+                                                int K) {
+    for (long e = b * (long)kPwThreads + threadIdx.x; e < elems; e += (long)nb * kPwThreads) {
+        double w = omega[e];
+        w = fmx(c0, r0[e], w);
+        if (K > 1) w = fmx(c1, r1[e], w);
+        if (K > 2) w = fmx(c2, r2[e], w);
+        if (K > 3) w = fmx(c3, r3[e], w);
+        omega[e] = w;
+    }
+}
+
 }  // namespace dgk

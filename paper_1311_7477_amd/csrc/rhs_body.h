@@ -228,7 +228,7 @@ __device__ __forceinline__ void rhs_body(
             const double Jv = ra.scale * (J[i] + DxA[i] + DyB[i]);
             const double R = ra.D * (LxG[i] + LyG[i]) - Jv;
             const double s = ra.b * (G[i] + ra.dt * R);
-            o[i] = (ra.a != 0.0) ? ra.a * wnr[i] + s : s;
+            o[i] = ra.only_r ? R : ((ra.a != 0.0) ? ra.a * wnr[i] + s : s);
         }
     } else {
 #pragma unroll

@@ -20,7 +20,7 @@ int row_blocks(const Geom& g) { return RowLaunch(g).nblocks; }
 hipError_t launch_rhs(const Geom& g, const OpConst<double>& k, const double* f,
                       const double* gg, const double* wn, double* out,
                       const RhsParams& p, bool visc, hipStream_t s) {
-    RhsArgs ra{p.c0, p.c1, p.c2, p.scale, p.D, p.dt, p.a, p.b};
+    RhsArgs ra{p.c0, p.c1, p.c2, p.scale, p.D, p.dt, p.a, p.b, p.only_r};
     DG_DISPATCH_NR(g.n, g.rw, {
         RowLaunch L(g);
         if (visc)

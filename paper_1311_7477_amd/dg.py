@@ -84,6 +84,13 @@ def lib():
         "dg_cg_solve_poisson": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(CgOpts),
                                                ctypes.POINTER(CgStats), _vp, _vp]),
         "dg_precond_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+        "dg_ab_state_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double,
+                                              ctypes.POINTER(_vp)]),
+        "dg_ab_state_destroy": (None, [_vp]),
+        "dg_ab_time": (ctypes.c_double, [_vp]),
+        "dg_ab_psi_state": (_vp, [_vp]),
+        "dg_ab_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(StepOpts),
+                                      ctypes.POINTER(StepStats), _vp, _vp]),
         "dg_grid_set_tiles": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "dg_grid_tiles": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
@@ -346,6 +353,48 @@ def rk_step(grid: Grid, omega, state: State, ws: Workspace, dt, D,
     so = StepOpts(dt, D, cg_opts() if opts is None else opts, 1 if record_times else 0)
     st = StepStats()
     _check(lib().dg_rk_step(grid.handle, _field(omega, grid, "omega"), state.handle,
+                            ctypes.byref(so), ctypes.byref(st), ws.handle, _stream()),
+           allow=(DG_E_NOCONV,))
+    return StepResult(tuple(st.cg_iters), tuple(st.stage_ms), bool(st.converged))
+
+
+class AbState:
+    """K-step Adams-Bashforth state (dg_ab_*): K right-hand sides and the
+    psi history."""
+
+    def __init__(self, grid: Grid, K: int, t0=0.0):
+        h = _vp()
+        _check(lib().dg_ab_state_create(grid.handle, K, t0, ctypes.byref(h)))
+        self._h, self.grid, self.K = h, grid, K
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def t(self):
+        return lib().dg_ab_time(self._h)
+
+    def psi(self):
+        """The most recent Poisson solution as a new tensor (a copy)."""
+        import torch
+        st = lib().dg_ab_psi_state(self._h)
+        if not lib().dg_state_psi(st):
+            return None
+        out = torch.empty(self.grid.shape, dtype=torch.float64, device="cuda")
+        _check(lib().dg_state_copy_psi(st, _vp(out.data_ptr()), _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dg_ab_state_destroy(self._h)
+            self._h = None
+
+
+def ab_step(grid: Grid, omega, ab: AbState, ws: Workspace, dt, D, opts: CgOpts = None):
+    so = StepOpts(dt, D, cg_opts() if opts is None else opts, 0)
+    st = StepStats()
+    _check(lib().dg_ab_step(grid.handle, _field(omega, grid, "omega"), ab.handle,
                             ctypes.byref(so), ctypes.byref(st), ws.handle, _stream()),
            allow=(DG_E_NOCONV,))
     return StepResult(tuple(st.cg_iters), tuple(st.stage_ms), bool(st.converged))

@@ -20,6 +20,10 @@ Recipes (no dataset is involved; the paper's own workloads are analytic):
   -Lap psi = omega and u = (-psi_y, psi_x).
 * ``decay_taylor_green``: omega = 2 sin x sin y (Sec. 6.1 initial value).
 * ``conservation_pair``: f = sin x cos y, g = exp(0.1 (x + y)) (Sec. 5.2).
+* ``lamb_dipole``: the Lamb dipole of Sec. 6.2, omega = 2 lam U / J0(lam R)
+  J1(lam r) cos(theta) inside r < R, zero outside, lam R the first zero of J1;
+  centred in the box, theta measured from the x axis (the paper states
+  neither the centre nor the reference axis); Bessel functions from scipy.
 """
 from __future__ import annotations
 
@@ -141,3 +145,22 @@ def double_shear_layer(n, N, rho=math.pi / 15, delta=0.05):
 def cfl_dt(n, N, umax, cfl=0.1, length=2 * math.pi):
     """dt = cfl * h / ((2n - 1) * umax), h = length / N."""
     return cfl * (length / N) / ((2 * n - 1) * umax)
+
+
+LAMB_LAM_R = 3.83170597020751231561     # first zero of J1 (Sec. 6.2)
+
+
+def lamb_dipole(n, N, L=1.0, U=1.0, R=0.1, centre=None):
+    """Lamb dipole vorticity on the periodic box [0, L]^2 with N x N cells:
+    omega = 2 lam U / J0(lam R) J1(lam r) cos(theta) for r < R, 0 outside
+    (Sec. 6.2), sampled at the nodes."""
+    from scipy.special import j0, j1
+    X, Y = node_coords(n, N, N, 0.0, L, 0.0, L)
+    cx, cy = (0.5 * L, 0.5 * L) if centre is None else centre
+    dx, dy = X - cx, Y - cy
+    r = np.hypot(dx, dy)
+    lam = LAMB_LAM_R / R
+    with np.errstate(invalid="ignore", divide="ignore"):
+        cos_t = np.where(r > 0, dx / np.where(r > 0, r, 1.0), 0.0)
+    w = 2.0 * lam * U / j0(lam * R) * j1(lam * r) * cos_t
+    return np.where(r < R, w, 0.0)
