@@ -105,22 +105,30 @@ class ReferenceElement:
 # 1D grid and derivative matrices (Sec. 3 eq. discrete_derivative,
 # Sec. 4.2 eqs. discrete_der, matrix_xspace)
 # --------------------------------------------------------------------------
-def _shift(N: int, offset: int) -> sp.csr_matrix:
-    """Periodic shift 1^+ (offset=+1: (1^+ f)^m = f^{m+1}) or 1^- (offset=-1)
-    (Sec. 4.2, eq. operator_one; periodic wrap as in the periodic closure of
-    Sec. 3)."""
+def _shift(N: int, offset: int, periodic: bool = True) -> sp.csr_matrix:
+    """Shift 1^+ (offset=+1: (1^+ f)^m = f^{m+1}) or 1^- (offset=-1)
+    (Sec. 4.2, eq. operator_one); periodic wrap as in the periodic closure of
+    Sec. 3, or no coupling across the ends (homogeneous Dirichlet)."""
     rows = np.arange(N)
-    cols = (rows + offset) % N
-    return sp.csr_matrix((np.ones(N), (rows, cols)), shape=(N, N))
+    cols = rows + offset
+    if periodic:
+        cols = cols % N
+    keep = (cols >= 0) & (cols < N)
+    return sp.csr_matrix((np.ones(int(keep.sum())), (rows[keep], cols[keep])), shape=(N, N))
 
 
 class Grid1D:
-    """Equidistant periodic 1D grid on [a, b] with N cells of size h
-    (Sec. 4.1) and n polynomials per cell."""
+    """Equidistant 1D grid on [a, b] with N cells of size h (Sec. 4.1) and n
+    polynomials per cell; bc = "periodic" or "dirichlet" (homogeneous, Sec. 3
+    boundary closures; read as a zero numerical flux on the two boundary
+    faces, see lspace_operator)."""
 
-    def __init__(self, n: int, N: int, a: float, b: float):
+    def __init__(self, n: int, N: int, a: float, b: float, bc: str = "periodic"):
+        if bc not in ("periodic", "dirichlet"):
+            raise ValueError(bc)
         self.el = ReferenceElement(n)
         self.n, self.N, self.a, self.b = n, N, float(a), float(b)
+        self.bc = bc
         self.h = (self.b - self.a) / N
         self._cache = {}
 
@@ -145,13 +153,26 @@ class Grid1D:
         gives  Mbar = 1^+ (x) theta RL + 1 (x) (-theta L + (1-theta) R - D^T)
                       - 1^- (x) (1-theta) LR.
         theta = 1/2 is the standard (centred) flux of eq. standard-flux;
-        theta = 1 / 0 are the one-sided fluxes used by the LDG Laplacian."""
+        theta = 1 / 0 are the one-sided fluxes used by the LDG Laplacian.
+
+        Homogeneous Dirichlet: the numerical flux on the two boundary faces
+        is zero (the reading that reproduces Table 2's Dirichlet row; the
+        alternative of a zero outside value, fhat = f_inside / 2, keeps the
+        operator skew and would conserve int f J and int g J, which Table 2
+        says it does not).  So the boundary cells lose both the neighbour
+        coupling and their own share of the boundary-face flux."""
         e = self.el
         N = self.N
+        per = self.bc == "periodic"
         self_block = -theta * e.L + (1.0 - theta) * e.R - e.D.T
-        M = (sp.kron(_shift(N, +1), theta * e.RL)
+        M = (sp.kron(_shift(N, +1, per), theta * e.RL)
              + sp.kron(sp.identity(N), self_block)
-             - sp.kron(_shift(N, -1), (1.0 - theta) * e.LR))
+             - sp.kron(_shift(N, -1, per), (1.0 - theta) * e.LR))
+        if not per:
+            n = self.n
+            M = M.tolil()
+            M[(N - 1) * n:, (N - 1) * n:] = M[(N - 1) * n:, (N - 1) * n:] - (1.0 - theta) * e.R
+            M[:n, :n] = M[:n, :n] + theta * e.L
         return M.tocsr()
 
     def derivative(self, kind: str = "centred") -> sp.csr_matrix:
@@ -174,7 +195,9 @@ class Grid1D:
 
     def laplacian(self) -> sp.csr_matrix:
         """1D LDG second derivative D_backward D_forward (alternating fluxes,
-        no penalty; the reading of Sec. 6's LDG Laplacian)."""
+        no penalty; the reading of Sec. 6's LDG Laplacian).  Periodic only."""
+        if self.bc != "periodic":
+            raise NotImplementedError("the LDG Laplacian is built for periodic grids only")
         if "lap" not in self._cache:
             self._cache["lap"] = (self.derivative("backward")
                                   @ self.derivative("forward")).tocsr()
@@ -186,10 +209,10 @@ class Grid2D:
     polynomials per cell and direction (Sec. 4.3, two dimensions)."""
 
     def __init__(self, n: int, Nx: int, Ny: int, x0=0.0, x1=2 * math.pi,
-                 y0=0.0, y1=2 * math.pi):
+                 y0=0.0, y1=2 * math.pi, bc_x="periodic", bc_y="periodic"):
         self.n, self.Nx, self.Ny = n, Nx, Ny
-        self.gx = Grid1D(n, Nx, x0, x1)
-        self.gy = Grid1D(n, Ny, y0, y1)
+        self.gx = Grid1D(n, Nx, x0, x1, bc_x)
+        self.gy = Grid1D(n, Ny, y0, y1, bc_y)
         self.hx, self.hy = self.gx.h, self.gy.h
 
     @property

@@ -40,6 +40,45 @@ def test_table2_periodic_rows():
                 assert round(v, 3) == p, (name, v, p)
 
 
+def test_table2_dirichlet_row():
+    # homogeneous Dirichlet closure read as a zero numerical flux on the
+    # boundary faces: all three integrals are nonzero (Sec. 5.2 text after
+    # Table 2) with the printed values
+    printed = _read_table2()["Jdir"]
+    g = O.Grid2D(3, 112, 112, 0.0, math.pi, 0.0, math.pi, "dirichlet", "dirichlet")
+    f, h = I.conservation_pair(3, 112)
+    J = O.bracket(g, f, h)
+    got = [O.inner(g, np.ones_like(f), J), O.inner(g, f, J), O.inner(g, h, J)]
+    for v, p in zip(got, printed):
+        digits = 2 - int(math.floor(math.log10(abs(p)))) - 1
+        assert round(v, digits) == p, (v, p)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_dirichlet_derivative(n):
+    # zero boundary flux: exact on continuous piecewise polynomials of degree
+    # <= n-1 that vanish at both ends, and the integral of any derivative is
+    # zero (the face fluxes telescope to the two zero boundary fluxes)
+    a, b, N = 0.3, 2.1, 7
+    g1 = O.Grid1D(n, N, a, b, "dirichlet")
+    D = g1.derivative("centred")
+    x = g1.nodes()
+    if n >= 3:        # global quadratic vanishing at both ends
+        u, du = (x - a) * (b - x), a + b - 2 * x
+    else:             # hat function on the face between cells 2 and 3
+        xf, h = a + 3 * g1.h, g1.h
+        u = np.maximum(0.0, 1.0 - np.abs(x - xf) / h)
+        du = np.where(np.abs(x - xf) < h, -np.sign(x - xf) / h, 0.0)
+    np.testing.assert_allclose(D @ u, du, atol=1e-11 * np.abs(du).max())
+    r = np.random.default_rng(n).standard_normal(x.shape)
+    assert abs(np.sum(g1.weights() * (D @ r))) < 1e-12 * np.sum(np.abs(r))
+    # the periodic operator of the same grid conserves as well; the two
+    # differ exactly in the boundary cells
+    P = O.Grid1D(n, N, a, b).derivative("centred").toarray()
+    diff = np.abs(P - D.toarray()).sum(axis=1)
+    assert np.all(diff[n:-n] == 0) and diff[:n].max() > 0 and diff[-n:].max() > 0
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
 def test_conservation_identities_random_fields(n):
     # eqs. average1-3 hold to roundoff for arbitrary (discontinuous) fields
