@@ -53,7 +53,7 @@ extern "C" {
 
 /* boundary conditions */
 #define DG_BC_PERIODIC   0
-#define DG_BC_DIRICHLET  1      /* returns DG_E_UNSUPPORTED */
+#define DG_BC_DIRICHLET  1      /* homogeneous; bracket only (others: DG_E_UNSUPPORTED) */
 
 /* CG precision modes (also the workspace mode) */
 #define DG_PREC_FP64   0
@@ -120,8 +120,13 @@ const char* dg_last_error(void);
  * weights (Sec. 4.1), the X-space centred derivative blocks (Sec. 4.2 eqs.
  * discrete_der, matrix_xspace) and the LDG Laplacian blocks (Sec. 6).
  * n in [1, 5] polynomials per cell and direction, nx, ny >= 1 cells, finite
- * x0 < x1 and y0 < y1, bc_x = bc_y = DG_BC_PERIODIC.  Touches no GPU.
- * Errors: DG_E_INVAL, DG_E_UNSUPPORTED (Dirichlet), DG_E_NOMEM. */
+ * x0 < x1 and y0 < y1.  bc_x, bc_y: DG_BC_PERIODIC (Sec. 3 periodic closure)
+ * or DG_BC_DIRICHLET (homogeneous, Sec. 3: read as a zero numerical flux on
+ * the boundary faces of that axis, the closure that gives Table 2's
+ * Dirichlet row).  A grid with a Dirichlet axis supports dg_poisson_bracket,
+ * dg_bracket_form and dg_invariants; the Laplacian, the Poisson solve, the
+ * steppers, batches, the preconditioner and the tuner return
+ * DG_E_UNSUPPORTED for it.  Touches no GPU.  Errors: DG_E_INVAL, DG_E_NOMEM. */
 int  dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
                     double y1, int bc_x, int bc_y, dg_grid** out);
 void dg_grid_destroy(dg_grid* grid);                 /* NULL-safe */

@@ -388,6 +388,11 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
 }  // namespace
 
 namespace dgk {
+int periodic_only(const char* what) {
+    return fail(DG_E_UNSUPPORTED, "%s is implemented for periodic grids only "
+                "(Dirichlet grids support the bracket)", what);
+}
+
 int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,
                   double ca, const double* pb, double cb, const dg_cg_opts* opts,
                   dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
@@ -409,9 +414,8 @@ int dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
     if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(y0) ||
         !std::isfinite(y1) || !(x1 > x0) || !(y1 > y0))
         return fail(DG_E_INVAL, "domain bounds must be finite with x0 < x1, y0 < y1");
-    if (bc_x == DG_BC_DIRICHLET || bc_y == DG_BC_DIRICHLET)
-        return fail(DG_E_UNSUPPORTED, "Dirichlet boundaries are not implemented");
-    if (bc_x != DG_BC_PERIODIC || bc_y != DG_BC_PERIODIC)
+    if ((bc_x != DG_BC_PERIODIC && bc_x != DG_BC_DIRICHLET) ||
+        (bc_y != DG_BC_PERIODIC && bc_y != DG_BC_DIRICHLET))
         return fail(DG_E_INVAL, "unknown boundary condition");
     dg_grid* g = new (std::nothrow) dg_grid;
     if (!g) return fail(DG_E_NOMEM, "host allocation failed");
@@ -422,7 +426,8 @@ int dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
     g->area = (x1 - x0) * (y1 - y0);
     if (!build_tables(n, &g->t)) { delete g; return fail(DG_E_INVAL, "table build failed"); }
     fill_const(*g, g->k64);
-    g->geom = Geom{n, nx, ny, kCellWavesDefault, kRowWavesDefault};
+    g->geom = Geom{n, nx, ny, kCellWavesDefault, kRowWavesDefault,
+                   bc_x == DG_BC_DIRICHLET ? 1 : 0, bc_y == DG_BC_DIRICHLET ? 1 : 0};
     g->elems = (size_t)nx * ny * n * n;
     *out = g;
     return DG_OK;
@@ -588,6 +593,7 @@ int dg_bracket_form(const dg_grid* g, const double* f, const double* gg,
 
 int dg_laplace_apply(const dg_grid* g, const double* f, double* out, void* stream) {
     if (!g || !f || !out) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("the LDG Laplacian");
     if (ranges_overlap(out, f, g->elems * sizeof(double)))
         return fail(DG_E_ALIAS, "out aliases f");
     hipError_t e = launch_laplace(g->geom, g->k64, f, out, as_stream(stream));
@@ -597,6 +603,7 @@ int dg_laplace_apply(const dg_grid* g, const double* f, double* out, void* strea
 
 int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* zero) {
     if (!g || !V || !lam || !zero) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("the preconditioner");
     if (axis != 0 && axis != 1) return fail(DG_E_INVAL, "axis must be 0 (x) or 1 (y)");
     FdAxis a;
     double err = 0.0;
@@ -612,6 +619,7 @@ int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* ze
 int dg_precond_apply(const dg_grid* g, const double* r, double* z, dg_workspace* ws,
                      void* stream) {
     if (!g || !r || !z) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("the preconditioner");
     int rc = check_ws(g, ws);
     if (rc != DG_OK) return rc;
     if (!ws->fd) return fail(DG_E_WORKSPACE, "the workspace has no DG_WS_FD preconditioner");
@@ -631,6 +639,7 @@ int dg_cg_solve_poisson(const dg_grid* g, const double* omega, double* psi,
                         const dg_cg_opts* opts, dg_cg_stats* st, dg_workspace* ws,
                         void* stream) {
     if (!g || !omega || !psi) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("the Poisson solve");
     int rc = check_ws(g, ws);
     if (rc != DG_OK) return rc;
     const size_t B = g->elems * sizeof(double);
@@ -685,6 +694,7 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
                const dg_step_opts* opts, dg_step_stats* stats, dg_workspace* ws,
                void* stream) {
     if (!g || !omega || !st || !opts) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("time stepping");
     int rc = check_ws(g, ws);
     if (rc != DG_OK) return rc;
     if (st->n != g->n || st->nx != g->nx || st->ny != g->ny)

@@ -61,6 +61,8 @@ void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
                  const double** pb, double* cb, double** x, int* xi);
 // Record that buffer xi now holds the solve at time ts.
 void state_push(dg_state* st, int xi, double ts);
+// DG_E_UNSUPPORTED for an operation that needs a periodic grid.
+int periodic_only(const char* what);
 // The Poisson solve behind dg_cg_solve_poisson and the steppers: guess
 // ca pa + cb pb (canonical), result in x (canonical, must not alias pa, pb).
 int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,

@@ -297,6 +297,7 @@ void dg_batch_destroy(dg_batch* b) {
 int dg_batch_attach(dg_batch* b, const dg_grid* g, double* omega, double dt,
                     double D, double t0, int* slot) {
     if (!b || !g || !omega || !slot) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("time stepping");
     if (!std::isfinite(dt) || !std::isfinite(D)) return fail(DG_E_INVAL, "dt, D must be finite");
     int i = 0;
     while (i < b->capacity && b->slots[i].used) ++i;

@@ -46,6 +46,7 @@ constexpr int kRowWavesDefault = 8;
 struct Geom {
     int n, nx, ny;
     int cw, rw;
+    int bcx, bcy;     // 1: homogeneous Dirichlet along x / y (bracket only)
 };
 
 // Bracket / right-hand-side kernel parameters:

@@ -33,6 +33,7 @@ struct Ctx {
     int lane, wave, s, j;
     bool active;      // lane holds a node row
     bool interior;    // lane's cell is inside the tile and the grid: stores
+    bool at_l, at_r, at_d, at_u;   // cell on a Dirichlet boundary of the grid
     long row;         // element index of this thread's row start
     int slot;         // wave * S + s (LDS cell slot)
 };
@@ -53,6 +54,10 @@ __device__ __forceinline__ Ctx<N, WAVES> make_ctx(const Geom& g, int tilesX,
     const int cy = ty * TL::TY + c.wave - 1;
     c.interior = c.active && c.s >= 1 && c.s <= TL::TX && c.wave >= 1 &&
                  c.wave <= TL::TY && cx < g.nx && cy < g.ny;
+    c.at_l = g.bcx && cx == 0;
+    c.at_r = g.bcx && cx == g.nx - 1;
+    c.at_d = g.bcy && cy == 0;
+    c.at_u = g.bcy && cy == g.ny - 1;
     int gx = cx % g.nx;
     if (gx < 0) gx += g.nx;
     int gy = cy % g.ny;
@@ -65,11 +70,17 @@ __device__ __forceinline__ Ctx<N, WAVES> make_ctx(const Geom& g, int tilesX,
 
 // One 1D operator along x on this thread's row:
 //   res = scale * (A0 u + eR (tR . u_right) + eL (tL . u_left))
+// For the centred derivative (A0 = C0 with both faces' self terms, tR / tL
+// the left / right trace functionals) a homogeneous Dirichlet boundary face
+// carries zero flux (at_hi: right face, at_lo: left face): the neighbour
+// trace is replaced by minus the cell's own trace at that face, which
+// cancels the face's self term in C0 and drops the coupling.
 template <int N, class T>
 __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
                                        const T* A0, const T* eR, const T* tR,
                                        const T* eL, const T* tL, T scale,
-                                       T (&res)[N]) {
+                                       T (&res)[N], bool at_lo = false,
+                                       bool at_hi = false) {
     T dR = 0, dL = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -78,8 +89,12 @@ __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
     }
     // the right neighbour cell is N lanes up, the left one N lanes down;
     // lanes of the edge slots receive wrapped values but are halo
-    const T fromR = __shfl(dR, lane + N);
-    const T fromL = __shfl(dL, lane - N);
+    // the shuffles run on every lane (a lane that skipped one would not
+    // provide its value); the boundary replacement is a select afterwards
+    const T nbR = __shfl(dR, lane + N);
+    const T nbL = __shfl(dL, lane - N);
+    const T fromR = at_hi ? -dL : nbR;
+    const T fromL = at_lo ? -dR : nbL;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         T a = fmx(eR[i], fromR, eL[i] * fromL);
@@ -96,7 +111,7 @@ template <int N, int WAVES, class T>
 __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
                                        const T* A0, const T* eR, const T* tR,
                                        const T* eL, const T* tL, T scale,
-                                       T (&res)[N]) {
+                                       T (&res)[N], bool dirichlet = false) {
     using TL = Tile<N, WAVES>;
     const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
     const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
@@ -104,13 +119,18 @@ __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
     const T* cu = lds + up * TL::CS + c.j;
     const T* cd = lds + dn * TL::CS + c.j;
     T col[N];
-    T du = 0, dd = 0;
+    T du = 0, dd = 0, sb = 0, st = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         col[k] = c0[k * N];
         du = fmx(tR[k], cu[k * N], du);
         dd = fmx(tL[k], cd[k * N], dd);
+        sb = fmx(tR[k], col[k], sb);
+        st = fmx(tL[k], col[k], st);
     }
+    // zero flux on a Dirichlet boundary face (see row_op)
+    if (dirichlet && c.at_u) du = -st;
+    if (dirichlet && c.at_d) dd = -sb;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         T a = fmx(eR[k], du, eL[k] * dd);
@@ -175,8 +195,8 @@ __device__ __forceinline__ void rhs_body(
     load_vec(gg, c.row, G);
 
     double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
-    row_op(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF);
-    row_op(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG);
+    row_op(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
+    row_op(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
     if (VISC) row_op(G, c.lane, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihx2, LxG);
 
     lds_put_row(lA, c, F);
@@ -184,8 +204,8 @@ __device__ __forceinline__ void rhs_body(
     __syncthreads();
     {
         double cF[N], cG[N], cL[N];
-        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
-        col_op(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
+        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF, true);
+        col_op(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG, true);
         if (VISC) col_op(lB, c, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihy2, cL);
         __syncthreads();
         lds_put_col(lA, c, cF);
@@ -206,12 +226,12 @@ __device__ __forceinline__ void rhs_body(
         B[i] = ra.c2 * (DxF[i] * G[i]) - ra.c1 * (F[i] * DxG[i]);
     }
     double DxA[N], DyB[N];
-    row_op(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA);
+    row_op(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA, c.at_l, c.at_r);
     lds_put_row(lA, c, B);
     __syncthreads();
     {
         double cb[N];
-        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cb);
+        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cb, true);
         __syncthreads();
         lds_put_col(lA, c, cb);
     }

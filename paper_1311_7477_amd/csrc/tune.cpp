@@ -95,6 +95,7 @@ int dg_grid_tiles(const dg_grid* g, int* cw, int* rw) {
 
 int dg_grid_tune(dg_grid* g, const double* omega, int reps, double* ms_out5, void* stream) {
     if (!g || !omega) return fail(DG_E_INVAL, "NULL argument");
+    if (g->geom.bcx || g->geom.bcy) return periodic_only("the tile tuner");
     if (reps < 1) return fail(DG_E_INVAL, "reps must be >= 1");
     const hipStream_t s = (hipStream_t)stream;
     dg_workspace* ws = nullptr;

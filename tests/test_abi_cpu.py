@@ -90,7 +90,17 @@ def test_grid_create_validation():
             dg.Grid(args["n"], args["nx"], args["ny"], 0.0, args["x1"], 0.0, args["y1"])
         assert ei.value.code == dg.DG_E_INVAL
     with pytest.raises(dg.DgError) as ei:
-        dg.Grid(2, 4, 4, bc_x=dg.DG_BC_DIRICHLET)
+        dg.Grid(2, 4, 4, bc_x=7)
+    assert ei.value.code == dg.DG_E_INVAL
+    # a Dirichlet axis: the bracket only; host-side rejections need no GPU
+    d = dg.Grid(2, 4, 4, bc_x=dg.DG_BC_DIRICHLET)
+    L = dg.lib()
+    for rc in (L.dg_laplace_apply(d.handle, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), None),
+               L.dg_cg_solve_poisson(d.handle, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x9000),
+                                     None, None, None, None)):
+        assert rc == dg.DG_E_UNSUPPORTED
+    with pytest.raises(dg.DgError) as ei:
+        d.fd_basis(0)
     assert ei.value.code == dg.DG_E_UNSUPPORTED
 
 
