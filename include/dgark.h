@@ -175,9 +175,10 @@ int  dg_workspace_create(const dg_grid* grid, int mode, dg_workspace** out);
 void dg_workspace_destroy(dg_workspace* ws);         /* NULL-safe */
 
 /* Measurement support.  While enabled, every CG polling chunk of a solve on
- * this workspace brackets one direction-update kernel launch and one
- * residual-update kernel launch with HIP events on the solve's stream (only
- * iterations the device really executed are counted).  dg_profile_read
+ * this workspace times one direction-update kernel launch and one
+ * residual-update kernel launch with HIP events recorded by those dispatches
+ * on the solve's stream (only iterations the device really executed are
+ * counted).  dg_profile_read
  * stores {sum_ms_direction, launches, sum_ms_residual, launches} accumulated
  * since the previous read and resets them.  Host-only bookkeeping. */
 int  dg_profile_enable(dg_workspace* ws, int on);

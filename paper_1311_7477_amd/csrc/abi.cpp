@@ -172,14 +172,12 @@ int cg_loop(const Geom& geom, const OpConst<double>& k, T* x, T* r, T* p0, T* p1
         for (int i = 0; i < m; ++i) {
             hipError_t e;
             if (ws->prof_on && i == 0) {
-                HIP_TRY(hipEventRecord(ws->pev[slot][0], s));
-                e = launch_cg_dir<T>(geom, k, x, r, p0, p1, sc, ws->d, s);
+                e = launch_cg_dir_timed<T>(geom, k, x, r, p0, p1, sc, ws->d, s,
+                                           ws->pev[slot][0], ws->pev[slot][1]);
                 if (e != hipSuccess) return hip_fail(e, "cg direction launch");
-                HIP_TRY(hipEventRecord(ws->pev[slot][1], s));
-                HIP_TRY(hipEventRecord(ws->pev[slot][2], s));
-                e = launch_cg_res<T>(geom, k, r, p0, p1, sc, ws->d, s);
+                e = launch_cg_res_timed<T>(geom, k, r, p0, p1, sc, ws->d, s,
+                                           ws->pev[slot][2], ws->pev[slot][3]);
                 if (e != hipSuccess) return hip_fail(e, "cg residual launch");
-                HIP_TRY(hipEventRecord(ws->pev[slot][3], s));
                 ws->pev_iter[slot] = issued;
             } else {
                 e = launch_cg_iter<T>(geom, k, x, r, p0, p1, sc, ws->d, s);

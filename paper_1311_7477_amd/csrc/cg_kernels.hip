@@ -2,6 +2,8 @@
 // lane; the device code and its layout conventions are in cg_body.h).  One
 // block per 64 x WV tile (WV = the grid's cell tile height g.cw, one of 4, 8,
 // 16); block b processes tile xcd_tile(b).
+#include <hip/hip_ext.h>
+
 #include "cg_body.h"
 #include "dg_launch.h"
 
@@ -104,6 +106,43 @@ hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S
                                           d.counters + kCntRes, d.partials));
     return hipGetLastError();
 }
+
+// The same launches with the dispatch's own start / stop timestamps
+// (hipExtLaunchKernel): the events bracket exactly this kernel, without the
+// cost of separate marker packets around it.
+template <class S>
+hipError_t launch_cg_dir_timed(const Geom& g, const OpConst<double>& k, double* x, S* r,
+                               S* p0, S* p1, CgScalars* sc, const DevScratch& d,
+                               hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+    CellLaunch L(g);
+    DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_dir<NN, S, WW>), dim3(L.nblocks),
+                                                    dim3(64 * WW), 0, s, start, stop, 0, g,
+                                                    L.tilesX, L.nblocks, k, (const S*)r, p0,
+                                                    p1, x, sc, d.counters + kCntDir,
+                                                    d.partials));
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_cg_res_timed(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
+                               CgScalars* sc, const DevScratch& d, hipStream_t s,
+                               hipEvent_t start, hipEvent_t stop) {
+    CellLaunch L(g);
+    DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_res<NN, S, WW>), dim3(L.nblocks),
+                                                    dim3(64 * WW), 0, s, start, stop, 0, g,
+                                                    L.tilesX, L.nblocks, k, (const S*)p0,
+                                                    (const S*)p1, r, sc, d.counters + kCntRes,
+                                                    d.partials));
+    return hipGetLastError();
+}
+template hipError_t launch_cg_dir_timed<double>(const Geom&, const OpConst<double>&, double*,
+                                                double*, double*, double*, CgScalars*,
+                                                const DevScratch&, hipStream_t, hipEvent_t,
+                                                hipEvent_t);
+template hipError_t launch_cg_res_timed<double>(const Geom&, const OpConst<double>&, double*,
+                                                double*, double*, CgScalars*,
+                                                const DevScratch&, hipStream_t, hipEvent_t,
+                                                hipEvent_t);
 
 template <class S>
 hipError_t launch_cg_iter(const Geom& g, const OpConst<double>& k, double* x, S* r,

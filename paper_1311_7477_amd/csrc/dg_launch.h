@@ -54,6 +54,15 @@ hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* 
 template <class S>
 hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
                          CgScalars* sc, const DevScratch& d, hipStream_t s);
+// Timed variants: start / stop events record the dispatch's own timestamps.
+template <class S>
+hipError_t launch_cg_dir_timed(const Geom& g, const OpConst<double>& k, double* x, S* r,
+                               S* p0, S* p1, CgScalars* sc, const DevScratch& d,
+                               hipStream_t s, hipEvent_t start, hipEvent_t stop);
+template <class S>
+hipError_t launch_cg_res_timed(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
+                               CgScalars* sc, const DevScratch& d, hipStream_t s,
+                               hipEvent_t start, hipEvent_t stop);
 template <class S>
 hipError_t launch_cg_iter(const Geom& g, const OpConst<double>& k, double* x, S* r,
                           S* p0, S* p1, CgScalars* sc, const DevScratch& d,
