@@ -75,7 +75,7 @@ __device__ __forceinline__ Ctx<N, WAVES> make_ctx(const Geom& g, int tilesX,
 // carries zero flux (at_hi: right face, at_lo: left face): the neighbour
 // trace is replaced by minus the cell's own trace at that face, which
 // cancels the face's self term in C0 and drops the coupling.
-template <int N, class T>
+template <int N, class T, bool DIR = false>
 __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
                                        const T* A0, const T* eR, const T* tR,
                                        const T* eL, const T* tL, T scale,
@@ -93,8 +93,8 @@ __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
     // provide its value); the boundary replacement is a select afterwards
     const T nbR = __shfl(dR, lane + N);
     const T nbL = __shfl(dL, lane - N);
-    const T fromR = at_hi ? -dL : nbR;
-    const T fromL = at_lo ? -dR : nbL;
+    const T fromR = (DIR && at_hi) ? -dL : nbR;
+    const T fromL = (DIR && at_lo) ? -dR : nbL;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         T a = fmx(eR[i], fromR, eL[i] * fromL);
@@ -107,11 +107,11 @@ __device__ __forceinline__ void row_op(const T (&u)[N], int lane,
 // One 1D operator along y evaluated on column j of this thread's cell from
 // rows staged in LDS; res[k] is the value at node (k, j).  The halo waves
 // read clamped (wrong but in-bounds) neighbours and are never stored.
-template <int N, int WAVES, class T>
+template <int N, int WAVES, class T, bool DIR = false>
 __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
                                        const T* A0, const T* eR, const T* tR,
                                        const T* eL, const T* tL, T scale,
-                                       T (&res)[N], bool dirichlet = false) {
+                                       T (&res)[N]) {
     using TL = Tile<N, WAVES>;
     const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
     const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
@@ -119,18 +119,23 @@ __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
     const T* cu = lds + up * TL::CS + c.j;
     const T* cd = lds + dn * TL::CS + c.j;
     T col[N];
-    T du = 0, dd = 0, sb = 0, st = 0;
+    T du = 0, dd = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         col[k] = c0[k * N];
         du = fmx(tR[k], cu[k * N], du);
         dd = fmx(tL[k], cd[k * N], dd);
-        sb = fmx(tR[k], col[k], sb);
-        st = fmx(tL[k], col[k], st);
     }
-    // zero flux on a Dirichlet boundary face (see row_op)
-    if (dirichlet && c.at_u) du = -st;
-    if (dirichlet && c.at_d) dd = -sb;
+    if (DIR) {   // zero flux on a Dirichlet boundary face (see row_op)
+        T sb = 0, st = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            sb = fmx(tR[k], col[k], sb);
+            st = fmx(tL[k], col[k], st);
+        }
+        if (c.at_u) du = -st;
+        if (c.at_d) dd = -sb;
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         T a = fmx(eR[k], du, eL[k] * dd);
@@ -179,7 +184,7 @@ struct RhsLds {
     double C[VISC ? Tile<N, WAVES>::LDS_FIELD : 1];
 };
 
-template <int N, int WAVES, bool VISC>
+template <int N, int WAVES, bool VISC, bool DIR = false>
 __device__ __forceinline__ void rhs_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ f, const double* __restrict__ gg,
@@ -195,8 +200,8 @@ __device__ __forceinline__ void rhs_body(
     load_vec(gg, c.row, G);
 
     double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
-    row_op(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
-    row_op(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
+    row_op<N, double, DIR>(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
+    row_op<N, double, DIR>(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
     if (VISC) row_op(G, c.lane, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihx2, LxG);
 
     lds_put_row(lA, c, F);
@@ -204,8 +209,8 @@ __device__ __forceinline__ void rhs_body(
     __syncthreads();
     {
         double cF[N], cG[N], cL[N];
-        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF, true);
-        col_op(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG, true);
+        col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
+        col_op<N, WAVES, double, DIR>(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
         if (VISC) col_op(lB, c, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihy2, cL);
         __syncthreads();
         lds_put_col(lA, c, cF);
@@ -226,12 +231,12 @@ __device__ __forceinline__ void rhs_body(
         B[i] = ra.c2 * (DxF[i] * G[i]) - ra.c1 * (F[i] * DxG[i]);
     }
     double DxA[N], DyB[N];
-    row_op(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA, c.at_l, c.at_r);
+    row_op<N, double, DIR>(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA, c.at_l, c.at_r);
     lds_put_row(lA, c, B);
     __syncthreads();
     {
         double cb[N];
-        col_op(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cb, true);
+        col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cb);
         __syncthreads();
         lds_put_col(lA, c, cb);
     }
