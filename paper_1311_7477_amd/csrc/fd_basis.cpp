@@ -73,95 +73,161 @@ void herm_eig(int n, cplx* H, double* lam, cplx* U) {
     for (int a = 0; a < n; ++a) lam[a] = H[a * n + a].real();
 }
 
+// Eigenpairs of the Bloch symbol of wave number k: lam[e] and v[:, e]
+// (v[i * n + e]) with v^H Wc v = 1.  Accumulates the largest relative defect
+// (Hermitian symmetry, eigen-residual) into *err.
+void bloch_eig(const HostTables& t, int N, double h, int k, double* lam, cplx* v, double* err) {
+    const int n = t.n;
+    const double ih2 = 1.0 / (h * h);
+    const double two_pi = 6.283185307179586476925286766559;
+    std::vector<cplx> S(n * n), H(n * n), U(n * n);
+    const double th = two_pi * k / N;
+    // e^{i theta}, exact at theta = 0 and pi so those symbols stay real
+    const cplx ep = (k == 0) ? cplx(1.0, 0.0)
+                  : (2 * k == N) ? cplx(-1.0, 0.0) : cplx(std::cos(th), std::sin(th));
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            S[a * n + b] = ih2 * (t.L0[a * n + b] + ep * (t.eR[a] * t.lR[b]) +
+                                  std::conj(ep) * (t.eL[a] * t.lL[b]));
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            H[a * n + b] = std::sqrt(t.w[a]) * S[a * n + b] / std::sqrt(t.w[b]);
+    // symmetrise the rounding of the Hermitian form; record its defect
+    double scale = 0.0;
+    for (int a = 0; a < n * n; ++a) scale = std::fmax(scale, std::abs(H[a]));
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            const cplx m = 0.5 * (H[a * n + b] + std::conj(H[b * n + a]));
+            *err = std::fmax(*err, std::abs(H[a * n + b] - std::conj(H[b * n + a])) / scale);
+            H[a * n + b] = m;
+            H[b * n + a] = std::conj(m);
+        }
+    herm_eig(n, H.data(), lam, U.data());
+    // v = Wc^{-1/2} u; check S v = lambda v
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) v[a * n + b] = U[a * n + b] / std::sqrt(t.w[a]);
+    for (int e = 0; e < n; ++e) {
+        double r = 0.0, vn = 0.0;
+        for (int a = 0; a < n; ++a) {
+            cplx sv = 0.0;
+            for (int b = 0; b < n; ++b) sv += S[a * n + b] * v[b * n + e];
+            r = std::fmax(r, std::abs(sv - lam[e] * v[a * n + e]));
+            vn = std::fmax(vn, std::abs(v[a * n + e]));
+        }
+        *err = std::fmax(*err, r / (scale * vn));
+    }
+}
+
 }  // namespace
 
-bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err) {
+bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, double* max_err) {
     const int n = t.n;
-    const long NN = (long)N * n;
-    out->NN = (int)NN;
-    out->V.assign((size_t)(NN * NN), 0.0);
-    out->lam.assign((size_t)NN, 0.0);
-    out->zero = -1;
-    const double ih2 = 1.0 / (h * h);
-    const double norm = 1.0 / std::sqrt(N * 0.5 * h);
     const double two_pi = 6.283185307179586476925286766559;
-    double err = 0.0;
-    std::vector<cplx> S(n * n), H(n * n), U(n * n), v(n * n);
-    std::vector<double> lam(n);
-    long col = 0;
-    double zero_abs = 0.0;
-    for (int k = 0; 2 * k <= N; ++k) {
-        const double th = two_pi * k / N;
-        // e^{i theta}, exact at theta = 0 and pi so those symbols stay real
-        const cplx ep = (k == 0) ? cplx(1.0, 0.0)
-                      : (2 * k == N) ? cplx(-1.0, 0.0) : cplx(std::cos(th), std::sin(th));
-        for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b)
-                S[a * n + b] = ih2 * (t.L0[a * n + b] + ep * (t.eR[a] * t.lR[b]) +
-                                      std::conj(ep) * (t.eL[a] * t.lL[b]));
-        for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b)
-                H[a * n + b] = std::sqrt(t.w[a]) * S[a * n + b] / std::sqrt(t.w[b]);
-        // symmetrise the rounding of the Hermitian form; record its defect
-        double scale = 0.0;
-        for (int a = 0; a < n * n; ++a) scale = std::fmax(scale, std::abs(H[a]));
-        for (int a = 0; a < n; ++a)
-            for (int b = a; b < n; ++b) {
-                const cplx m = 0.5 * (H[a * n + b] + std::conj(H[b * n + a]));
-                err = std::fmax(err, std::abs(H[a * n + b] - std::conj(H[b * n + a])) / scale);
-                H[a * n + b] = m;
-                H[b * n + a] = std::conj(m);
-            }
-        herm_eig(n, H.data(), lam.data(), U.data());
-        // v = Wc^{-1/2} u; check S v = lambda v
-        for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b) v[a * n + b] = U[a * n + b] / std::sqrt(t.w[a]);
-        for (int e = 0; e < n; ++e) {
-            double r = 0.0, vn = 0.0;
-            for (int a = 0; a < n; ++a) {
-                cplx sv = 0.0;
-                for (int b = 0; b < n; ++b) sv += S[a * n + b] * v[b * n + e];
-                r = std::fmax(r, std::abs(sv - lam[e] * v[a * n + e]));
-                vn = std::fmax(vn, std::abs(v[a * n + e]));
-            }
-            err = std::fmax(err, r / (scale * vn));
-        }
-        const bool real_pair = (k == 0) || (2 * k == N);
-        for (int e = 0; e < n; ++e) {
-            if (real_pair) {
-                for (int cx = 0; cx < N; ++cx) {
-                    const double sgn = (k == 0 || (cx % 2 == 0)) ? 1.0 : -1.0;
-                    for (int i = 0; i < n; ++i)
-                        out->V[(size_t)(col * NN + (long)cx * n + i)] =
-                            norm * sgn * v[i * n + e].real();
-                }
-                out->lam[col] = lam[e];
-                if (k == 0 && (out->zero < 0 || std::fabs(lam[e]) < zero_abs)) {
-                    out->zero = (int)col;
-                    zero_abs = std::fabs(lam[e]);
-                }
-                ++col;
+    const int K = N / 2 + 1;                 // wave numbers 0 .. floor(N/2)
+    const int s = 2 * n;
+    out->N = N;
+    out->n = n;
+    out->K = K;
+    out->phi.assign((size_t)N * N, 0.0);
+    out->ccos.assign(K, -1);
+    out->csin.assign(K, -1);
+    out->mf.assign((size_t)K * s * s, 0.0);
+    out->mi.assign((size_t)K * s * s, 0.0);
+    out->lam.assign((size_t)N * n, 0.0);
+    out->zero = -1;
+    // real orthonormal Fourier basis over the cells: column 0 = constant,
+    // columns 2k-1 / 2k = cos / sin of wave number k, and for even N the
+    // last column the alternating (-1)^c
+    const double c0 = 1.0 / std::sqrt((double)N), c1 = std::sqrt(2.0 / N);
+    for (int k = 0; k < K; ++k) {
+        const bool real = (k == 0) || (2 * k == N);
+        const int cc = (k == 0) ? 0 : (real ? N - 1 : 2 * k - 1);
+        out->ccos[k] = cc;
+        if (!real) out->csin[k] = 2 * k;
+        for (int cx = 0; cx < N; ++cx) {
+            if (real) {
+                out->phi[(size_t)cc * N + cx] = (k == 0 || cx % 2 == 0) ? c0 : -c0;
             } else {
-                const double r2 = std::sqrt(2.0) * norm;
-                for (int cx = 0; cx < N; ++cx) {
-                    // angle reduced exactly: theta * cx = 2 pi (k cx mod N) / N
-                    const long m = ((long)k * cx) % N;
-                    const double ang = two_pi * (double)m / N;
-                    const cplx e_ = cplx(std::cos(ang), std::sin(ang));
-                    for (int i = 0; i < n; ++i) {
-                        const cplx z = v[i * n + e] * e_;
-                        out->V[(size_t)(col * NN + (long)cx * n + i)] = r2 * z.real();
-                        out->V[(size_t)((col + 1) * NN + (long)cx * n + i)] = r2 * z.imag();
+                const long m = ((long)k * cx) % N;   // angle reduced exactly
+                const double ang = two_pi * (double)m / N;
+                out->phi[(size_t)cc * N + cx] = c1 * std::cos(ang);
+                out->phi[(size_t)(cc + 1) * N + cx] = c1 * std::sin(ang);
+            }
+        }
+    }
+    // mixing blocks: slot p = (i, cos) -> i, (i, sin) -> n + i on the input
+    // side, q = (a, re) -> a, (a, im) -> n + a on the mode side.  With
+    // sc = 1 / sqrt(h / 2) the basis is V = (Phi (x) I) B with
+    //   B[(cos,i),(re,a)] = sc Re v,  B[(sin,i),(re,a)] = -sc Im v,
+    //   B[(cos,i),(im,a)] = sc Im v,  B[(sin,i),(im,a)] =  sc Re v
+    // (v = v_a[i]); forward mf[q][p] = B[p][q] (h/2) w_i, inverse mi[p][q] = B[p][q].
+    const double sc = 1.0 / std::sqrt(0.5 * h);
+    double err = 0.0, zero_abs = 0.0;
+    std::vector<cplx> v(n * n);
+    std::vector<double> lam(n);
+    for (int k = 0; k < K; ++k) {
+        bloch_eig(t, N, h, k, lam.data(), v.data(), &err);
+        const bool real = out->csin[k] < 0;
+        double* mf = &out->mf[(size_t)k * s * s];
+        double* mi = &out->mi[(size_t)k * s * s];
+        for (int a = 0; a < n; ++a) {
+            for (int i = 0; i < n; ++i) {
+                const cplx va = v[i * n + a];
+                const double wi = 0.5 * h * t.w[i];
+                double Bv[2][2];   // [cos/sin][re/im]
+                Bv[0][0] = sc * va.real();
+                Bv[1][0] = -sc * va.imag();
+                Bv[0][1] = sc * va.imag();
+                Bv[1][1] = sc * va.real();
+                const int nc = real ? 1 : 2;
+                for (int cs = 0; cs < nc; ++cs)
+                    for (int ri = 0; ri < nc; ++ri) {
+                        const int p = cs * n + i, q = ri * n + a;
+                        mf[q * s + p] = Bv[cs][ri] * wi;
+                        mi[p * s + q] = Bv[cs][ri];
                     }
-                }
-                out->lam[col] = lam[e];
-                out->lam[col + 1] = lam[e];
-                col += 2;
+            }
+            out->lam[(size_t)a * N + out->ccos[k]] = lam[a];
+            if (!real) out->lam[(size_t)a * N + out->csin[k]] = lam[a];
+            if (k == 0 && (out->zero < 0 || std::fabs(lam[a]) < zero_abs)) {
+                out->zero = a * N;
+                zero_abs = std::fabs(lam[a]);
             }
         }
     }
     *max_err = err;
-    return col == NN && out->zero >= 0;
+    return out->zero >= 0;
+}
+
+bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err) {
+    FdFactors f;
+    if (!fd_axis_factors(t, N, h, &f, max_err)) return false;
+    const int n = t.n, s = 2 * n;
+    const long NN = (long)N * n;
+    out->NN = (int)NN;
+    out->V.assign((size_t)(NN * NN), 0.0);
+    out->lam = f.lam;
+    out->zero = f.zero;
+    // V[(cx, i), slot (a, c')] = sum over the block's basis columns c of
+    // Phi[cx, c] B[(c, i), (a, c')]
+    for (int k = 0; k < f.K; ++k) {
+        const int cols[2] = {f.ccos[k], f.csin[k]};
+        const int nc = cols[1] < 0 ? 1 : 2;
+        const double* mi = &f.mi[(size_t)k * s * s];
+        for (int ri = 0; ri < nc; ++ri)
+            for (int a = 0; a < n; ++a) {
+                const long col = (long)a * N + cols[ri];
+                for (int cx = 0; cx < N; ++cx)
+                    for (int i = 0; i < n; ++i) {
+                        double acc = 0.0;
+                        for (int cs = 0; cs < nc; ++cs)
+                            acc += f.phi[(size_t)cols[cs] * N + cx] *
+                                   mi[(cs * n + i) * s + ri * n + a];
+                        out->V[(size_t)(col * NN + (long)cx * n + i)] = acc;
+                    }
+            }
+    }
+    return true;
 }
 
 }  // namespace dgk

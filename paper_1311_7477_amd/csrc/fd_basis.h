@@ -19,9 +19,32 @@ struct FdAxis {
     int zero = -1;
 };
 
+// The same basis in factored form V = (Phi (x) I_n) B: Phi (N x N,
+// column-major) is the real orthonormal Fourier basis over the cells
+// (column 0 constant, 2k-1 / 2k cos / sin of wave number k, N-1 the
+// alternating one for even N), B block diagonal over the K = N/2 + 1 wave
+// numbers.  Block k couples the basis columns ccos[k] (and csin[k], -1 for
+// k = 0 and N/2) of every node i with the modes of that k: slot p = (i, cos)
+// -> i, (i, sin) -> n + i; mode q = (a, re) -> a, (a, im) -> n + a, both
+// stored at index a * N + ccos / csin.  mf[k] (2n x 2n, row q) = B^T scaled
+// by the Gauss weights (h/2) w_i (forward, V^T W); mi[k] (row p) = B
+// (inverse).  lam[a * N + c] is the eigenvalue of that mode, `zero` the
+// index of the constant one.
+struct FdFactors {
+    int N = 0, n = 0, K = 0;
+    std::vector<double> phi;
+    std::vector<int> ccos, csin;
+    std::vector<double> mf, mi;
+    std::vector<double> lam;
+    int zero = -1;
+};
+
 // Builds the basis for N cells of size h from the LDG tables (h = 1 form).
 // *max_err receives the largest relative defect seen (Hermitian symmetry of
 // the symbols, eigen-residuals).  Returns false if the basis is incomplete.
+bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, double* max_err);
+// Dense assembly of the same basis (host checks): column a * N + c is the
+// mode of slot (a, c), rows cx * n + i.
 bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err);
 
 // Device resources of the preconditioner, owned by a workspace.
