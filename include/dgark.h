@@ -221,8 +221,10 @@ int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
  * 1D LDG operator of each axis is block circulant, so Bloch waves reduce it
  * to n x n Hermitian (in the Gauss weights) symbols whose eigenvectors give
  * a real W-orthonormal basis V with L V = V diag(lambda); then
- * z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T on the image
- * layout, the constant mode dropped.  r, z: canonical fields, z must not
+ * z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T, the
+ * constant mode dropped.  V is applied in factored form (the cell Fourier
+ * transform as an FP64 matrix product, then 2n x 2n mixing per wave number),
+ * 4 n^2 Nx Ny (Nx + Ny) flops per call.  r, z: canonical fields, z must not
  * alias r.  ws must hold DG_WS_FD.  Asynchronous. */
 int  dg_precond_apply(const dg_grid* grid, const double* r, double* z,
                       dg_workspace* ws, void* stream);

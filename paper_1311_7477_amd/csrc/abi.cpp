@@ -306,8 +306,8 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
 }
 
 // FP64 CG preconditioned by the fast-diagonalisation inverse of -Lap_h:
-// z = M r on the image layout (dense basis products), then the usual
-// direction / residual kernels with p built from z.  The host polls after
+// z = M r on node planes (cell Fourier transforms + per-wave-number mixing),
+// then the usual direction / residual kernels with p built from z.  The host polls after
 // every iteration (an exact preconditioner converges in one or two).
 int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
            double ca, const double* pb, double cb, const dg_cg_opts& o,

@@ -91,17 +91,22 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
                                 const float* q1, float* r32, const DevScratch& d,
                                 hipStream_t s);
 // Fast-diagonalisation preconditioner support (fd_kernels.hip): field ->
-// image layout (from canonical or lane-interleaved), image -> canonical,
-// image -> z (lane-interleaved) with <r, z>_W closing the PCG step, and the
-// spectral scaling U[r][c] /= -(ly[r] + lx[c]) with the constant mode zeroed.
+// node planes U[cell + nx ny q] (from canonical or lane-interleaved), planes
+// -> canonical, planes -> z (lane-interleaved) with <r, z>_W closing the PCG
+// step, the per-wave-number mixing of the x cell transform (K blocks, M
+// row-major 2n x 2n each, cols[2k] / cols[2k+1] the cos / sin columns), and
+// the y mixing + spectral scaling + unmixing.
 hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, double* img,
                            hipStream_t s);
 hipError_t launch_from_image(const Geom& g, const double* img, double* dst, hipStream_t s);
 hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const double* img,
                                  double* z, const double* r, const DevScratch& d,
                                  hipStream_t s);
-hipError_t launch_fd_scale(int NX, int NY, double* img, const double* lx, const double* ly,
-                           int zx, int zy, hipStream_t s);
+hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const double* M,
+                           double* u, hipStream_t s);
+hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const double* Mf,
+                           const double* Mi, const double* lx, const double* ly, int zx, int zy,
+                           double* u, hipStream_t s);
 hipError_t launch_guess(long elems, double* x, const double* pa,
                         const double* pb, double ca, double cb, hipStream_t s);
 // Adams-Bashforth update omega += sum_{j<K} c[j] R[j] (element-wise, in the

@@ -1,9 +1,18 @@
 // Device side of the fast-diagonalisation preconditioner: upload of the
-// separable eigenbases (fd_basis.cpp) and the application
-//     z = V_y [ (V_y^T W_y R W_x V_x) / -(lam_y + lam_x) ] V_x^T
-// on the image layout (R[(cy n + j)][(cx n + i)], NY x NX row-major, which
-// is the NX x NY column-major matrix R^T) as four dense FP64 products
-// (rocBLAS dgemm) and one scaling kernel.  P = W V is stored next to V.
+// factored separable eigenbases (fd_basis.cpp) and the application
+//     z = V_y [ (V_y^T W_y R W_x V_x) / -(lam_y + lam_x) ] V_x^T,
+// with V = (Phi (x) I_n) B per axis, on node planes U[cx + Nx (cy + Ny q)]
+// (q = i + n j).  The cell Fourier transforms Phi are FP64 matrix products
+// (rocBLAS), each chosen so that its output puts the next step's axis first:
+//   U  --(x transform, batched over j)-->  U1[cy + Ny (i + n kx + n Nx j)]
+//   U1 --(x mixing B_x^T W_x, in place)
+//   U1 --(y transform)-->                   U2[i + n kx + n Nx (j + n ky)]
+//   U2 --(y mixing, scaling, unmixing, in place)
+//   U2 --(inverse y transform)-->           U1
+//   U1 --(x unmixing B_x, in place)
+//   U1 --(inverse x transform, batched)-->  U
+// The transforms cost 4 n^2 Nx Ny (Nx + Ny) flops in all, n times fewer
+// than dense products with V.
 #include <rocblas/rocblas.h>
 
 #include <cstring>
@@ -24,25 +33,52 @@ int blas_fail(rocblas_status st, const char* what) {
                 rocblas_status_to_string(st));
 }
 
+size_t axis_bytes(int N, int n) {
+    const size_t K = (size_t)N / 2 + 1, S = 2 * (size_t)n;
+    return ((size_t)N * N + 2 * K * S * S + (size_t)N * n) * sizeof(double) + 2 * K * sizeof(int);
+}
+
+void free_axis(FdAxisDevice* a) {
+    void* bufs[] = {a->phi, a->mf, a->mi, a->lam, a->cols};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    *a = FdAxisDevice{};
+}
+
+template <class T>
+bool upload(T** dst, const std::vector<T>& src) {
+    const size_t b = src.size() * sizeof(T);
+    if (hipMalloc((void**)dst, b) != hipSuccess) return false;
+    return hipMemcpy(*dst, src.data(), b, hipMemcpyHostToDevice) == hipSuccess;
+}
+
+bool upload_axis(const FdFactors& f, FdAxisDevice* a) {
+    a->N = f.N;
+    a->K = f.K;
+    a->zero = f.zero;
+    std::vector<int> cols(2 * (size_t)f.K);
+    for (int k = 0; k < f.K; ++k) {
+        cols[2 * k] = f.ccos[k];
+        cols[2 * k + 1] = f.csin[k];
+    }
+    return upload(&a->phi, f.phi) && upload(&a->mf, f.mf) && upload(&a->mi, f.mi) &&
+           upload(&a->lam, f.lam) && upload(&a->cols, cols);
+}
+
 }  // namespace
 
 size_t fd_bytes(const dg_grid* g) {
-    const size_t NX = (size_t)g->nx * g->n, NY = (size_t)g->ny * g->n;
-    size_t mats = 2 * NX * NX + (same_axis(g) ? 0 : 2 * NY * NY);
-    return (mats + NX + NY + 2 * NX * NY) * sizeof(double);
+    const size_t planes = 2 * (size_t)g->nx * g->ny * g->n * g->n * sizeof(double);
+    return planes + axis_bytes(g->nx, g->n) + (same_axis(g) ? 0 : axis_bytes(g->ny, g->n));
 }
 
 void fd_destroy(FdDevice* fd) {
     if (!fd) return;
     if (fd->blas) (void)rocblas_destroy_handle((rocblas_handle)fd->blas);
-    double* bufs[] = {fd->Vx, fd->Px, fd->lx, fd->img0, fd->img1};
-    for (double* b : bufs)
-        if (b) (void)hipFree(b);
-    if (!fd->shared) {
-        if (fd->Vy) (void)hipFree(fd->Vy);
-        if (fd->Py) (void)hipFree(fd->Py);
-        if (fd->ly) (void)hipFree(fd->ly);
-    }
+    if (fd->img0) (void)hipFree(fd->img0);
+    if (fd->img1) (void)hipFree(fd->img1);
+    free_axis(&fd->x);
+    if (!fd->shared) free_axis(&fd->y);
     delete fd;
 }
 
@@ -50,13 +86,12 @@ int fd_create(const dg_grid* g, FdDevice** out) {
     *out = nullptr;
     FdDevice* fd = new (std::nothrow) FdDevice;
     if (!fd) return fail(DG_E_NOMEM, "host allocation failed");
-    fd->NX = g->nx * g->n;
-    fd->NY = g->ny * g->n;
+    fd->n = g->n;
     fd->shared = same_axis(g);
-    FdAxis ax, ay;
+    FdFactors fx, fy;
     double ex = 0.0, ey = 0.0;
-    if (!fd_axis_basis(g->t, g->nx, g->hx, &ax, &ex) ||
-        (!fd->shared && !fd_axis_basis(g->t, g->ny, g->hy, &ay, &ey))) {
+    if (!fd_axis_factors(g->t, g->nx, g->hx, &fx, &ex) ||
+        (!fd->shared && !fd_axis_factors(g->t, g->ny, g->hy, &fy, &ey))) {
         delete fd;
         return fail(DG_E_INVAL, "eigenbasis construction failed");
     }
@@ -64,34 +99,10 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         delete fd;
         return fail(DG_E_INVAL, "eigenbasis defect %.3e too large", ex > ey ? ex : ey);
     }
-    const FdAxis& by = fd->shared ? ax : ay;
-    fd->zx = ax.zero;
-    fd->zy = by.zero;
-    // P = W V: row (cx, i) of V scaled by the Gauss weight (h / 2) w_i
-    auto weighted = [&](const FdAxis& a, double h) {
-        std::vector<double> P(a.V.size());
-        const int n = g->n;
-        for (long c = 0; c < a.NN; ++c)
-            for (long r = 0; r < a.NN; ++r)
-                P[(size_t)(c * a.NN + r)] = 0.5 * h * g->t.w[r % n] * a.V[(size_t)(c * a.NN + r)];
-        return P;
-    };
-    auto upload = [&](double** dst, const std::vector<double>& src) -> bool {
-        const size_t b = src.size() * sizeof(double);
-        if (hipMalloc((void**)dst, b) != hipSuccess) return false;
-        return hipMemcpy(*dst, src.data(), b, hipMemcpyHostToDevice) == hipSuccess;
-    };
-    bool ok = upload(&fd->Vx, ax.V) && upload(&fd->Px, weighted(ax, g->hx)) &&
-              upload(&fd->lx, ax.lam);
-    if (ok && fd->shared) {
-        fd->Vy = fd->Vx;
-        fd->Py = fd->Px;
-        fd->ly = fd->lx;
-    } else if (ok) {
-        ok = upload(&fd->Vy, ay.V) && upload(&fd->Py, weighted(ay, g->hy)) &&
-             upload(&fd->ly, ay.lam);
-    }
-    const size_t img = (size_t)fd->NX * fd->NY * sizeof(double);
+    bool ok = upload_axis(fx, &fd->x);
+    if (ok && fd->shared) fd->y = fd->x;
+    else if (ok) ok = upload_axis(fy, &fd->y);
+    const size_t img = (size_t)g->nx * g->ny * g->n * g->n * sizeof(double);
     if (ok) ok = hipMalloc((void**)&fd->img0, img) == hipSuccess &&
                  hipMalloc((void**)&fd->img1, img) == hipSuccess;
     if (!ok) {
@@ -111,32 +122,40 @@ int fd_create(const dg_grid* g, FdDevice** out) {
     return DG_OK;
 }
 
-// img0 holds the image of r on entry and the image of z = M r on exit.
+// img0 holds the node planes of r on entry and those of z = M r on exit.
 int fd_apply_image(const FdDevice* fd, hipStream_t s) {
     rocblas_handle h = (rocblas_handle)fd->blas;
     rocblas_status st = rocblas_set_stream(h, s);
     if (st != rocblas_status_success) return blas_fail(st, "rocblas_set_stream");
-    const rocblas_int NX = fd->NX, NY = fd->NY;
+    const FdAxisDevice& X = fd->x;
+    const FdAxisDevice& Y = fd->y;
+    const rocblas_int n = fd->n, Nx = X.N, Ny = Y.N;
+    const rocblas_stride plane_j = (rocblas_stride)Nx * Ny * n;   // one j of U / U1
     const double one = 1.0, zero = 0.0;
     const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
-    // B = R^T P_y  (NX x NY)
-    st = rocblas_dgemm(h, N_, N_, NX, NY, NY, &one, fd->img0, NX, fd->Py, NY, &zero,
-                       fd->img1, NX);
-    if (st != rocblas_status_success) return blas_fail(st, "dgemm 1");
-    // A = P_x^T B = (P_y^T R P_x)^T
-    st = rocblas_dgemm(h, T_, N_, NX, NY, NX, &one, fd->Px, NX, fd->img1, NX, &zero,
-                       fd->img0, NX);
-    if (st != rocblas_status_success) return blas_fail(st, "dgemm 2");
-    hipError_t e = launch_fd_scale(NX, NY, fd->img0, fd->lx, fd->ly, fd->zx, fd->zy, s);
-    if (e != hipSuccess) return hip_fail(e, "spectral scaling launch");
-    // B = V_x A
-    st = rocblas_dgemm(h, N_, N_, NX, NY, NX, &one, fd->Vx, NX, fd->img0, NX, &zero,
-                       fd->img1, NX);
-    if (st != rocblas_status_success) return blas_fail(st, "dgemm 3");
-    // A = B V_y^T = (V_y Z~ V_x^T)^T
-    st = rocblas_dgemm(h, N_, T_, NX, NY, NY, &one, fd->img1, NX, fd->Vy, NY, &zero,
-                       fd->img0, NX);
-    if (st != rocblas_status_success) return blas_fail(st, "dgemm 4");
+    // U1_j = U_j^T Phi_x: U_j is Nx x (Ny n), U1_j is (Ny n) x Nx
+    st = rocblas_dgemm_strided_batched(h, T_, N_, Ny * n, Nx, Nx, &one, fd->img0, Nx, plane_j,
+                                       X.phi, Nx, 0, &zero, fd->img1, Ny * n, plane_j, n);
+    if (st != rocblas_status_success) return blas_fail(st, "x transform");
+    hipError_t e = launch_fd_mix_x(n, Nx, Ny, X.K, X.cols, X.mf, fd->img1, s);
+    if (e != hipSuccess) return hip_fail(e, "x mixing launch");
+    // U2 = U1^T Phi_y: U1 is Ny x (n^2 Nx), U2 is (n^2 Nx) x Ny
+    st = rocblas_dgemm(h, T_, N_, n * n * Nx, Ny, Ny, &one, fd->img1, Ny, Y.phi, Ny, &zero,
+                       fd->img0, n * n * Nx);
+    if (st != rocblas_status_success) return blas_fail(st, "y transform");
+    e = launch_fd_mix_y(n, Nx, Ny, Y.K, Y.cols, Y.mf, Y.mi, X.lam, Y.lam, X.zero, Y.zero,
+                        fd->img0, s);
+    if (e != hipSuccess) return hip_fail(e, "y mixing launch");
+    // U1 = Phi_y U2^T
+    st = rocblas_dgemm(h, N_, T_, Ny, n * n * Nx, Ny, &one, Y.phi, Ny, fd->img0, n * n * Nx,
+                       &zero, fd->img1, Ny);
+    if (st != rocblas_status_success) return blas_fail(st, "inverse y transform");
+    e = launch_fd_mix_x(n, Nx, Ny, X.K, X.cols, X.mi, fd->img1, s);
+    if (e != hipSuccess) return hip_fail(e, "x unmixing launch");
+    // U_j = Phi_x U1_j^T
+    st = rocblas_dgemm_strided_batched(h, N_, T_, Nx, Ny * n, Nx, &one, X.phi, Nx, 0, fd->img1,
+                                       Ny * n, plane_j, &zero, fd->img0, Nx, plane_j, n);
+    if (st != rocblas_status_success) return blas_fail(st, "inverse x transform");
     return DG_OK;
 }
 

@@ -1,6 +1,6 @@
 // Separable eigenbases of the periodic 1D LDG second derivative for the
 // fast-diagonalisation preconditioner (host construction in fd_basis.cpp,
-// device application in fd_kernels.hip and abi.cpp).  Internal.
+// device application in fd_apply.cpp and fd_kernels.hip).  Internal.
 #pragma once
 
 #include <vector>
@@ -47,13 +47,20 @@ bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, doubl
 // mode of slot (a, c), rows cx * n + i.
 bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err);
 
+// Device copy of one axis's factors: phi (N x N), cols[2k] / cols[2k+1]
+// (ccos / csin), mf / mi (K blocks of 2n x 2n), lam (n N).
+struct FdAxisDevice {
+    int N = 0, K = 0, zero = -1;
+    double *phi = nullptr, *mf = nullptr, *mi = nullptr, *lam = nullptr;
+    int* cols = nullptr;
+};
+
 // Device resources of the preconditioner, owned by a workspace.
 struct FdDevice {
-    int NX = 0, NY = 0, zx = -1, zy = -1;
-    double *Vx = nullptr, *Px = nullptr, *Vy = nullptr, *Py = nullptr;  // Py/Vy may alias
-    double *lx = nullptr, *ly = nullptr;
-    double *img0 = nullptr, *img1 = nullptr;   // image-layout work fields
-    bool shared = false;                       // y basis aliases the x basis
+    int n = 0;
+    FdAxisDevice x, y;                         // y aliases x when `shared`
+    bool shared = false;
+    double *img0 = nullptr, *img1 = nullptr;   // node-plane work fields
     void* blas = nullptr;                      // rocblas_handle
     size_t bytes = 0;
 };

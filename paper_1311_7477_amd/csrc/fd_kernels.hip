@@ -1,7 +1,10 @@
-// Device kernels of the fast-diagonalisation preconditioner: conversions
-// between the CG layouts and the image layout U[(cy n + j) * NX + cx n + i]
-// (NX = nx n) that the dense basis products act on, the spectral scaling,
-// and the preconditioned dot product <r, z>_W that closes the PCG step.
+// Device kernels of the fast-diagonalisation preconditioner.  Its fields
+// live in node planes: U[cell + nx ny (i + n j)] (cell = cy nx + cx), so the
+// cell Fourier transforms along x and y are plain matrix products over whole
+// planes.  Here: the conversions between the CG layouts and the planes, the
+// per-wave-number mixing of the x transform, the mixing + spectral scaling +
+// unmixing of the y transform, and the preconditioned dot product <r, z>_W
+// that closes the PCG step.
 #include "cg_body.h"
 #include "dg_launch.h"
 
@@ -9,17 +12,11 @@ namespace dgk {
 
 namespace {
 
-// Image offset of node (j, i) = 0 of cell (cx, cy).
-__device__ __forceinline__ long img_base(int n, long NX, int cx, int cy) {
-    return (long)cy * n * NX + (long)cx * n;
-}
-
 template <int N, bool FromL64>
 __global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, const double* __restrict__ src,
                                                          double* __restrict__ img) {
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
-    const long NX = (long)g.nx * N;
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
          cell += (long)gridDim.x * kPwThreads) {
         const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
@@ -27,11 +24,8 @@ __global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, const double* _
         double u[N * N];
         if (FromL64) ld_l64<N>(src, c, u);
         else ld_canon<N>(src, c, u);
-        const long o = img_base(N, NX, cx, cy);
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-#pragma unroll
-            for (int i = 0; i < N; ++i) img[o + j * NX + i] = u[j * N + i];
+        for (int q = 0; q < N * N; ++q) img[cell + cells * q] = u[q];
     }
 }
 
@@ -40,17 +34,13 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const double*
                                                            double* __restrict__ dst) {
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
-    const long NX = (long)g.nx * N;
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
          cell += (long)gridDim.x * kPwThreads) {
         const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
         const CellRef c = cell_ref<N>(g, G, cx, cy);
-        const long o = img_base(N, NX, cx, cy);
         double u[N * N];
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-#pragma unroll
-            for (int i = 0; i < N; ++i) u[j * N + i] = img[o + j * NX + i];
+        for (int q = 0; q < N * N; ++q) u[q] = img[cell + cells * q];
         st_canon<N>(dst, c, u);
     }
 }
@@ -65,18 +55,14 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
     if (sc->done) return;
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
-    const long NX = (long)g.nx * N;
     double part[1] = {0.0};
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
          cell += (long)gridDim.x * kPwThreads) {
         const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
         const CellRef c = cell_ref<N>(g, G, cx, cy);
-        const long o = img_base(N, NX, cx, cy);
         double u[N * N], rv[N * N];
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-#pragma unroll
-            for (int i = 0; i < N; ++i) u[j * N + i] = img[o + j * NX + i];
+        for (int q = 0; q < N * N; ++q) u[q] = img[cell + cells * q];
         st_l64<N>(z, c, u);
         ld_l64<N>(r, c, rv);
         part[0] += wdot_cell<N>(k, rv, u);
@@ -99,17 +85,114 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
     }
 }
 
-// U[r][c] /= -(ly[r] + lx[c]); the constant mode (zy, zx) is set to zero.
-__global__ __launch_bounds__(kPwThreads) void k_fd_scale(int NX, int NY, double* __restrict__ img,
-                                                         const double* __restrict__ lx,
-                                                         const double* __restrict__ ly, int zx,
-                                                         int zy) {
-    const long total = (long)NX * NY;
-    for (long e = blockIdx.x * (long)kPwThreads + threadIdx.x; e < total;
-         e += (long)gridDim.x * kPwThreads) {
-        const int r = (int)(e / NX), c = (int)(e - (long)r * NX);
-        const double mu = -(ly[r] + lx[c]);
-        img[e] = (r == zy && c == zx) ? 0.0 : img[e] / mu;
+// out = M v for one 2n-vector (M row-major, S = 2n, row = output index);
+// `pair` false: only the leading n x n block (wave numbers 0 and N/2).
+template <int N>
+__device__ __forceinline__ void mix_vec(const double* __restrict__ M, bool pair,
+                                        const double* v, double* out) {
+    constexpr int S = 2 * N;
+    if (pair) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int p = 0; p < S; ++p) acc = fma(M[q * S + p], v[p], acc);
+            out[q] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int p = 0; p < N; ++p) acc = fma(M[q * S + p], v[p], acc);
+            out[q] = acc;
+        }
+    }
+}
+
+// Mixing of the x transform, U1[cy + Ny (i + n c + n Nx j)] (c: cell
+// Fourier column along x).  Block row k = blockIdx.y is one wave number:
+// for every (cy, j) the values at columns cols[2k] (cos) and cols[2k+1]
+// (sin, -1 if none) of all nodes i form the 2n-vector (h, i) -> h n + i,
+// which is replaced by M_k times it, in place.  One lane per cy, so each
+// access is contiguous across the wave; M_k is the same for the block.
+template <int N>
+__global__ __launch_bounds__(kPwThreads) void k_fd_mix_x(int Nx, int Ny,
+                                                         const int* __restrict__ cols,
+                                                         const double* __restrict__ M,
+                                                         double* __restrict__ u) {
+    constexpr int S = 2 * N;
+    const int k = blockIdx.y;
+    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+    const bool pair = c1 >= 0;
+    const double* Mk = M + (size_t)k * S * S;
+    const long per = (long)Ny * N;
+    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
+         t += (long)gridDim.x * kPwThreads) {
+        const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
+        const long base = cy + (long)Ny * N * Nx * j;
+        const long o0 = base + (long)Ny * N * c0;
+        const long o1 = base + (long)Ny * N * (pair ? c1 : c0);
+        double v[S], w[S];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            v[i] = u[o0 + (long)Ny * i];
+            v[N + i] = pair ? u[o1 + (long)Ny * i] : 0.0;
+        }
+        mix_vec<N>(Mk, pair, v, w);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            u[o0 + (long)Ny * i] = w[i];
+            if (pair) u[o1 + (long)Ny * i] = w[N + i];
+        }
+    }
+}
+
+// Mixing of the y transform, spectral scaling and unmixing, on
+// U2[m + n Nx (j + n c)] with m = i + n kx the x mode (a = i, column kx,
+// eigenvalue lx[i Nx + kx]) and c the cell Fourier column along y.  Block
+// row k = blockIdx.y is one y wave number: per x mode, the 2n-vector at
+// columns cols[2k], cols[2k+1] over the nodes j goes to y modes by Mf_k,
+// each y mode (b, column c) is divided by -(lx + ly[b Ny + c]) (the constant
+// mode, x slot zx and y slot zy, is set to zero), and Mi_k maps back.
+template <int N>
+__global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
+    int Nx, const int* __restrict__ cols, const double* __restrict__ Mf,
+    const double* __restrict__ Mi, const double* __restrict__ lx, const double* __restrict__ ly,
+    int Ny, int zx, int zy, double* __restrict__ u) {
+    constexpr int S = 2 * N;
+    const int k = blockIdx.y;
+    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+    const bool pair = c1 >= 0;
+    const double* Mfk = Mf + (size_t)k * S * S;
+    const double* Mik = Mi + (size_t)k * S * S;
+    const long NXn = (long)N * Nx;
+    for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
+         m += (long)gridDim.x * kPwThreads) {
+        const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
+        const int xs = i * Nx + kx;
+        const double lam_x = lx[xs];
+        const long o0 = m + NXn * N * c0;
+        const long o1 = m + NXn * N * (pair ? c1 : c0);
+        double v[S], w[S];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            v[j] = u[o0 + NXn * j];
+            v[N + j] = pair ? u[o1 + NXn * j] : 0.0;
+        }
+        mix_vec<N>(Mfk, pair, v, w);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (q >= N && !pair) break;
+            const int ys = (q % N) * Ny + (q < N ? c0 : c1);
+            w[q] = (xs == zx && ys == zy) ? 0.0 : w[q] / -(lam_x + ly[ys]);
+        }
+        mix_vec<N>(Mik, pair, w, v);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            u[o0 + NXn * j] = v[j];
+            if (pair) u[o1 + NXn * j] = v[N + j];
+        }
     }
 }
 
@@ -147,11 +230,20 @@ hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const 
     return hipGetLastError();
 }
 
-hipError_t launch_fd_scale(int NX, int NY, double* img, const double* lx, const double* ly,
-                           int zx, int zy, hipStream_t s) {
-    const long total = (long)NX * NY;
-    const int nb = pw_blocks(total, pointwise_block_cap());
-    hipLaunchKernelGGL(k_fd_scale, dim3(nb), dim3(kPwThreads), 0, s, NX, NY, img, lx, ly, zx, zy);
+hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const double* M,
+                           double* u, hipStream_t s) {
+    const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_x<NN>), dim3(nb, K), dim3(kPwThreads), 0, s,
+                                        Nx, Ny, cols, M, u));
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const double* Mf,
+                           const double* Mi, const double* lx, const double* ly, int zx, int zy,
+                           double* u, hipStream_t s) {
+    const int nb = pw_blocks((long)Nx * n, pointwise_block_cap());
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_y<NN>), dim3(nb, K), dim3(kPwThreads), 0, s,
+                                        Nx, cols, Mf, Mi, lx, ly, Ny, zx, zy, u));
     return hipGetLastError();
 }
 

@@ -114,16 +114,20 @@ def test_workspace_bytes_and_field_size():
     b64, bmx = g.workspace_bytes(dg.DG_PREC_FP64), g.workspace_bytes(dg.DG_PREC_MIXED)
     assert 6 * F <= b64 < 6 * F + 2 ** 20
     assert bmx == b64 + 3 * g.elems * 4          # FP32 r, p0, p1
-    # fast-diagonalisation option: z, two image fields, and V, W V of one
-    # axis (square grid: the y basis is the x basis) plus the eigenvalues
-    NX = 512 * 4
+    # fast-diagonalisation option: z, two node-plane fields, and per axis
+    # (square grid: the y factors are the x factors) the cell Fourier basis
+    # (N x N), the forward and inverse mixing blocks (K = N/2 + 1 blocks of
+    # 2n x 2n), the eigenvalues (n N) and the K cos / sin column pairs
+    def axis(N, n):
+        K = N // 2 + 1
+        return (N * N + 2 * K * (2 * n) ** 2 + N * n) * 8 + 2 * K * 4
     bfd = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
-    assert bfd == b64 + 3 * F + (2 * NX * NX + 2 * NX) * 8
-    # unequal axes keep both bases
+    assert bfd == b64 + 3 * F + axis(512, 4)
+    # unequal axes keep both factor sets
     r = dg.Grid(2, 6, 5)
     extra = r.workspace_bytes(dg.DG_WS_FD) - r.workspace_bytes(dg.DG_PREC_FP64)
     L6 = 5 * 1 * 4 * 64
-    assert extra == (L6 + 2 * r.elems + 2 * 12 * 12 + 2 * 10 * 10 + 12 + 10) * 8
+    assert extra == L6 * 8 + 2 * r.elems * 8 + axis(6, 2) + axis(5, 2)
     # ragged nx: the interleaved vectors are padded to whole groups of 64 cells
     h = dg.Grid(3, 100, 7)
     L = 7 * 2 * 9 * 64
