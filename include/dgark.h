@@ -60,7 +60,8 @@ extern "C" {
 #define DG_PREC_MIXED  1        /* r, p stored in FP32, FP64 arithmetic and solution,
                                    periodic FP64 residual replacement */
 /* workspace option, OR-ed into the mode: also hold the fast-diagonalisation
-   preconditioner (dense separable eigenbases of the 1D LDG operators) */
+   preconditioner (factored separable eigenbases of the 1D LDG operators, in
+   FP64 and FP32, and two node-plane work fields) */
 #define DG_WS_FD       0x10
 
 /* CG preconditioners (dg_cg_opts.precond) */
@@ -81,8 +82,10 @@ typedef struct {
     double rtol;        /* stop when ||r||_W <= rtol ||b||_W (in mixed mode: the
                            FP64 residual recomputed at a replacement) */
     int    max_iter;    /* CG iterations allowed */
-    int    precision;   /* DG_PREC_FP64 or DG_PREC_MIXED */
-    int    precond;     /* DG_PRECOND_NONE or DG_PRECOND_FD (FP64 only) */
+    int    precision;   /* DG_PREC_FP64 or DG_PREC_MIXED; with DG_PRECOND_FD,
+                           DG_PREC_MIXED applies the preconditioner in FP32
+                           (the iteration itself stays FP64) */
+    int    precond;     /* DG_PRECOND_NONE or DG_PRECOND_FD */
     int    check_every; /* FP64: iterations between host polls of the device
                            convergence flag; mixed: iterations between FP64
                            residual replacements (0 = library default, 32) */
@@ -207,8 +210,8 @@ int  dg_laplace_apply(const dg_grid* grid, const double* f, double* out,
  * Gauss inner product (Sec. 6: symmetric system, CG; Sec. 4.1 eq. def_norm).
  * On entry psi holds the initial guess (its W-mean is removed); on exit the
  * zero-mean solution.  ||omega - mean|| = 0 gives psi = 0.  ws must be made
- * for this grid, in mixed mode for DG_PREC_MIXED and with DG_WS_FD for
- * DG_PRECOND_FD (else DG_E_WORKSPACE).  Synchronises the stream
+ * for this grid, with DG_WS_FD for DG_PRECOND_FD (any precision mode), else
+ * in mixed mode for DG_PREC_MIXED (else DG_E_WORKSPACE).  Synchronises the stream
  * (convergence polling).  Returns DG_E_NOCONV when max_iter was hit or the
  * iteration broke down (psi holds the last iterate).  psi must not alias
  * omega. */

@@ -305,12 +305,28 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
     return DG_OK;
 }
 
+// z = M r on node planes in the precision T, then z and <r, z>_W in FP64.
+template <class T>
+int precond_step(const dg_grid* g, dg_workspace* ws, hipStream_t s) {
+    T* planes = reinterpret_cast<T*>(ws->fd->img0);
+    hipError_t e = launch_to_image<T>(g->geom, ws->r, true, planes, s);
+    if (e != hipSuccess) return hip_fail(e, "image conversion launch");
+    int rc = fd_apply_image(ws->fd, sizeof(T) == sizeof(float), s);
+    if (rc != DG_OK) return rc;
+    e = launch_from_image_dot<T>(g->geom, g->k64, planes, ws->z, ws->r, ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "image conversion launch");
+    return DG_OK;
+}
+
 // FP64 CG preconditioned by the fast-diagonalisation inverse of -Lap_h:
 // z = M r on node planes (cell Fourier transforms + per-wave-number mixing),
-// then the usual direction / residual kernels with p built from z.  The host polls after
-// every iteration (an exact preconditioner converges in one or two).
+// then the usual direction / residual kernels with p built from z.  The host
+// polls after every iteration (an exact preconditioner converges in one or
+// two).  fp32: M is applied in FP32 (the mixed-precision form: the solve's
+// bulk work in FP32, every residual, solution and step length in FP64, so
+// the FP64 iteration refines the FP32 solves; about one extra iteration).
 int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
-           double ca, const double* pb, double cb, const dg_cg_opts& o,
+           double ca, const double* pb, double cb, const dg_cg_opts& o, bool fp32,
            dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
     const double tol2 = o.rtol * o.rtol;
     hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
@@ -322,13 +338,9 @@ int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
     if (rc != DG_OK) return rc;
     CgScalars h = ws->host[2];
     while (!h.done) {
-        e = launch_to_image(g->geom, ws->r, true, ws->fd->img0, s);
-        if (e != hipSuccess) return hip_fail(e, "image conversion launch");
-        rc = fd_apply_image(ws->fd, s);
+        rc = fp32 ? precond_step<float>(g, ws, s) : precond_step<double>(g, ws, s);
         if (rc != DG_OK) return rc;
-        e = launch_from_image_dot(g->geom, g->k64, ws->fd->img0, ws->z, ws->r, ws->d, s);
-        if (e == hipSuccess)
-            e = launch_cg_dir<double>(g->geom, g->k64, ws->x, ws->z, ws->p0, ws->p1,
+        e = launch_cg_dir<double>(g->geom, g->k64, ws->x, ws->z, ws->p0, ws->p1,
                                       ws->d.sc, ws->d, s);
         if (e == hipSuccess)
             e = launch_cg_res<double>(g->geom, g->k64, ws->r, ws->p0, ws->p1, ws->d.sc,
@@ -368,11 +380,11 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
     if (o.precond != DG_PRECOND_NONE && o.precond != DG_PRECOND_FD)
         return fail(DG_E_INVAL, "unknown preconditioner %d", o.precond);
     if (o.precond == DG_PRECOND_FD) {
-        if (o.precision != DG_PREC_FP64)
-            return fail(DG_E_UNSUPPORTED, "the preconditioned solve is FP64 only");
+        if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_MIXED)
+            return fail(DG_E_INVAL, "unknown precision %d", o.precision);
         if (!ws->fd)
             return fail(DG_E_WORKSPACE, "preconditioning needs a DG_WS_FD workspace");
-        return cg_pcg(g, omega, x, pa, ca, pb, cb, o, st, ws, s);
+        return cg_pcg(g, omega, x, pa, ca, pb, cb, o, o.precision == DG_PREC_MIXED, st, ws, s);
     }
     if (o.precision == DG_PREC_MIXED) {
         if ((ws->mode & ~DG_WS_FD) != DG_PREC_MIXED)
@@ -624,11 +636,11 @@ int dg_precond_apply(const dg_grid* g, const double* r, double* z, dg_workspace*
     if (ranges_overlap(z, r, g->elems * sizeof(double)))
         return fail(DG_E_ALIAS, "z aliases r");
     const hipStream_t s = as_stream(stream);
-    hipError_t e = launch_to_image(g->geom, r, false, ws->fd->img0, s);
+    hipError_t e = launch_to_image<double>(g->geom, r, false, ws->fd->img0, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
-    rc = fd_apply_image(ws->fd, s);
+    rc = fd_apply_image(ws->fd, false, s);
     if (rc != DG_OK) return rc;
-    e = launch_from_image(g->geom, ws->fd->img0, z, s);
+    e = launch_from_image<double>(g->geom, ws->fd->img0, z, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }

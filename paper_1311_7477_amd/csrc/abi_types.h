@@ -73,7 +73,7 @@ int solve_poisson(const dg_grid* g, const double* omega, double* x, const double
 size_t fd_bytes(const dg_grid* g);
 int fd_create(const dg_grid* g, FdDevice** out);
 void fd_destroy(FdDevice* fd);
-int fd_apply_image(const FdDevice* fd, hipStream_t s);
+int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s);
 }  // namespace dgk
 
 #define HIP_TRY(call)                                          \

@@ -96,17 +96,23 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
 // step, the per-wave-number mixing of the x cell transform (K blocks, M
 // row-major 2n x 2n each, cols[2k] / cols[2k+1] the cos / sin columns), and
 // the y mixing + spectral scaling + unmixing.
-hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, double* img,
+// T = double, or float for the FP32 apply of the mixed-precision PCG.
+template <class T>
+hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, T* img,
                            hipStream_t s);
-hipError_t launch_from_image(const Geom& g, const double* img, double* dst, hipStream_t s);
-hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const double* img,
+template <class T>
+hipError_t launch_from_image(const Geom& g, const T* img, double* dst, hipStream_t s);
+template <class T>
+hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const T* img,
                                  double* z, const double* r, const DevScratch& d,
                                  hipStream_t s);
-hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const double* M,
-                           double* u, hipStream_t s);
-hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const double* Mf,
-                           const double* Mi, const double* lx, const double* ly, int zx, int zy,
-                           double* u, hipStream_t s);
+template <class T>
+hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const T* M, T* u,
+                           hipStream_t s);
+template <class T>
+hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+                           const T* Mi, const T* lx, const T* ly, int zx, int zy, T* u,
+                           hipStream_t s);
 hipError_t launch_guess(long elems, double* x, const double* pa,
                         const double* pb, double ca, double cb, hipStream_t s);
 // Adams-Bashforth update omega += sum_{j<K} c[j] R[j] (element-wise, in the

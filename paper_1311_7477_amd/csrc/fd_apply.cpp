@@ -12,7 +12,9 @@
 //   U1 --(x unmixing B_x, in place)
 //   U1 --(inverse x transform, batched)-->  U
 // The transforms cost 4 n^2 Nx Ny (Nx + Ny) flops in all, n times fewer
-// than dense products with V.
+// than dense products with V.  The same steps run in FP64 or, for the mixed-
+// precision PCG, in FP32 (factors rounded once at setup; the planes then take
+// the first half of the FP64 work fields).
 #include <rocblas/rocblas.h>
 
 #include <cstring>
@@ -35,11 +37,13 @@ int blas_fail(rocblas_status st, const char* what) {
 
 size_t axis_bytes(int N, int n) {
     const size_t K = (size_t)N / 2 + 1, S = 2 * (size_t)n;
-    return ((size_t)N * N + 2 * K * S * S + (size_t)N * n) * sizeof(double) + 2 * K * sizeof(int);
+    const size_t vals = (size_t)N * N + 2 * K * S * S + (size_t)N * n;
+    return vals * (sizeof(double) + sizeof(float)) + 2 * K * sizeof(int);
 }
 
 void free_axis(FdAxisDevice* a) {
-    void* bufs[] = {a->phi, a->mf, a->mi, a->lam, a->cols};
+    void* bufs[] = {a->f64.phi, a->f64.mf, a->f64.mi, a->f64.lam,
+                    a->f32.phi, a->f32.mf, a->f32.mi, a->f32.lam, a->cols};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     *a = FdAxisDevice{};
@@ -52,6 +56,10 @@ bool upload(T** dst, const std::vector<T>& src) {
     return hipMemcpy(*dst, src.data(), b, hipMemcpyHostToDevice) == hipSuccess;
 }
 
+std::vector<float> rounded(const std::vector<double>& v) {
+    return std::vector<float>(v.begin(), v.end());
+}
+
 bool upload_axis(const FdFactors& f, FdAxisDevice* a) {
     a->N = f.N;
     a->K = f.K;
@@ -61,8 +69,68 @@ bool upload_axis(const FdFactors& f, FdAxisDevice* a) {
         cols[2 * k] = f.ccos[k];
         cols[2 * k + 1] = f.csin[k];
     }
-    return upload(&a->phi, f.phi) && upload(&a->mf, f.mf) && upload(&a->mi, f.mi) &&
-           upload(&a->lam, f.lam) && upload(&a->cols, cols);
+    return upload(&a->f64.phi, f.phi) && upload(&a->f64.mf, f.mf) &&
+           upload(&a->f64.mi, f.mi) && upload(&a->f64.lam, f.lam) &&
+           upload(&a->f32.phi, rounded(f.phi)) && upload(&a->f32.mf, rounded(f.mf)) &&
+           upload(&a->f32.mi, rounded(f.mi)) && upload(&a->f32.lam, rounded(f.lam)) &&
+           upload(&a->cols, cols);
+}
+
+// C_b = op(A_b) op(B_b), b < batch (alpha 1, beta 0), in the precision of T.
+rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                    rocblas_int m, rocblas_int n, rocblas_int k, const double* A,
+                    rocblas_int lda, rocblas_stride sa, const double* B, rocblas_int ldb,
+                    rocblas_stride sb, double* C, rocblas_int ldc, rocblas_stride sc,
+                    rocblas_int batch) {
+    const double one = 1.0, zero = 0.0;
+    return rocblas_dgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sa, B, ldb, sb,
+                                         &zero, C, ldc, sc, batch);
+}
+
+rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                    rocblas_int m, rocblas_int n, rocblas_int k, const float* A,
+                    rocblas_int lda, rocblas_stride sa, const float* B, rocblas_int ldb,
+                    rocblas_stride sb, float* C, rocblas_int ldc, rocblas_stride sc,
+                    rocblas_int batch) {
+    const float one = 1.0f, zero = 0.0f;
+    return rocblas_sgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sa, B, ldb, sb,
+                                         &zero, C, ldc, sc, batch);
+}
+
+template <class T>
+int apply_planes(const FdDevice* fd, hipStream_t s) {
+    rocblas_handle h = (rocblas_handle)fd->blas;
+    rocblas_status st = rocblas_set_stream(h, s);
+    if (st != rocblas_status_success) return blas_fail(st, "rocblas_set_stream");
+    const FdAxisDevice& X = fd->x;
+    const FdAxisDevice& Y = fd->y;
+    const FdFactorsDevice<T>& fx = X.get<T>();
+    const FdFactorsDevice<T>& fy = Y.get<T>();
+    T* u0 = reinterpret_cast<T*>(fd->img0);
+    T* u1 = reinterpret_cast<T*>(fd->img1);
+    const rocblas_int n = fd->n, Nx = X.N, Ny = Y.N, M2 = n * n * Nx;
+    const rocblas_stride plane_j = (rocblas_stride)Nx * Ny * n;   // one j of U / U1
+    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+    // U1_j = U_j^T Phi_x: U_j is Nx x (Ny n), U1_j is (Ny n) x Nx
+    st = gemm(h, T_, N_, Ny * n, Nx, Nx, u0, Nx, plane_j, fx.phi, Nx, 0, u1, Ny * n, plane_j, n);
+    if (st != rocblas_status_success) return blas_fail(st, "x transform");
+    hipError_t e = launch_fd_mix_x<T>(n, Nx, Ny, X.K, X.cols, fx.mf, u1, s);
+    if (e != hipSuccess) return hip_fail(e, "x mixing launch");
+    // U2 = U1^T Phi_y: U1 is Ny x (n^2 Nx), U2 is (n^2 Nx) x Ny
+    st = gemm(h, T_, N_, M2, Ny, Ny, u1, Ny, 0, fy.phi, Ny, 0, u0, M2, 0, 1);
+    if (st != rocblas_status_success) return blas_fail(st, "y transform");
+    e = launch_fd_mix_y<T>(n, Nx, Ny, Y.K, Y.cols, fy.mf, fy.mi, fx.lam, fy.lam, X.zero, Y.zero,
+                           u0, s);
+    if (e != hipSuccess) return hip_fail(e, "y mixing launch");
+    // U1 = Phi_y U2^T
+    st = gemm(h, N_, T_, Ny, M2, Ny, fy.phi, Ny, 0, u0, M2, 0, u1, Ny, 0, 1);
+    if (st != rocblas_status_success) return blas_fail(st, "inverse y transform");
+    e = launch_fd_mix_x<T>(n, Nx, Ny, X.K, X.cols, fx.mi, u1, s);
+    if (e != hipSuccess) return hip_fail(e, "x unmixing launch");
+    // U_j = Phi_x U1_j^T
+    st = gemm(h, N_, T_, Nx, Ny * n, Nx, fx.phi, Nx, 0, u1, Ny * n, plane_j, u0, Nx, plane_j, n);
+    if (st != rocblas_status_success) return blas_fail(st, "inverse x transform");
+    return DG_OK;
 }
 
 }  // namespace
@@ -122,41 +190,10 @@ int fd_create(const dg_grid* g, FdDevice** out) {
     return DG_OK;
 }
 
-// img0 holds the node planes of r on entry and those of z = M r on exit.
-int fd_apply_image(const FdDevice* fd, hipStream_t s) {
-    rocblas_handle h = (rocblas_handle)fd->blas;
-    rocblas_status st = rocblas_set_stream(h, s);
-    if (st != rocblas_status_success) return blas_fail(st, "rocblas_set_stream");
-    const FdAxisDevice& X = fd->x;
-    const FdAxisDevice& Y = fd->y;
-    const rocblas_int n = fd->n, Nx = X.N, Ny = Y.N;
-    const rocblas_stride plane_j = (rocblas_stride)Nx * Ny * n;   // one j of U / U1
-    const double one = 1.0, zero = 0.0;
-    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
-    // U1_j = U_j^T Phi_x: U_j is Nx x (Ny n), U1_j is (Ny n) x Nx
-    st = rocblas_dgemm_strided_batched(h, T_, N_, Ny * n, Nx, Nx, &one, fd->img0, Nx, plane_j,
-                                       X.phi, Nx, 0, &zero, fd->img1, Ny * n, plane_j, n);
-    if (st != rocblas_status_success) return blas_fail(st, "x transform");
-    hipError_t e = launch_fd_mix_x(n, Nx, Ny, X.K, X.cols, X.mf, fd->img1, s);
-    if (e != hipSuccess) return hip_fail(e, "x mixing launch");
-    // U2 = U1^T Phi_y: U1 is Ny x (n^2 Nx), U2 is (n^2 Nx) x Ny
-    st = rocblas_dgemm(h, T_, N_, n * n * Nx, Ny, Ny, &one, fd->img1, Ny, Y.phi, Ny, &zero,
-                       fd->img0, n * n * Nx);
-    if (st != rocblas_status_success) return blas_fail(st, "y transform");
-    e = launch_fd_mix_y(n, Nx, Ny, Y.K, Y.cols, Y.mf, Y.mi, X.lam, Y.lam, X.zero, Y.zero,
-                        fd->img0, s);
-    if (e != hipSuccess) return hip_fail(e, "y mixing launch");
-    // U1 = Phi_y U2^T
-    st = rocblas_dgemm(h, N_, T_, Ny, n * n * Nx, Ny, &one, Y.phi, Ny, fd->img0, n * n * Nx,
-                       &zero, fd->img1, Ny);
-    if (st != rocblas_status_success) return blas_fail(st, "inverse y transform");
-    e = launch_fd_mix_x(n, Nx, Ny, X.K, X.cols, X.mi, fd->img1, s);
-    if (e != hipSuccess) return hip_fail(e, "x unmixing launch");
-    // U_j = Phi_x U1_j^T
-    st = rocblas_dgemm_strided_batched(h, N_, T_, Nx, Ny * n, Nx, &one, X.phi, Nx, 0, fd->img1,
-                                       Ny * n, plane_j, &zero, fd->img0, Nx, plane_j, n);
-    if (st != rocblas_status_success) return blas_fail(st, "inverse x transform");
-    return DG_OK;
+// img0 holds the node planes of r on entry and those of z = M r on exit
+// (FP32 planes when fp32).
+int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s) {
+    return fp32 ? apply_planes<float>(fd, s) : apply_planes<double>(fd, s);
 }
 
 }  // namespace dgk

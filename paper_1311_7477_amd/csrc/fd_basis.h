@@ -47,20 +47,32 @@ bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, doubl
 // mode of slot (a, c), rows cx * n + i.
 bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err);
 
-// Device copy of one axis's factors: phi (N x N), cols[2k] / cols[2k+1]
-// (ccos / csin), mf / mi (K blocks of 2n x 2n), lam (n N).
+// Device copy of one axis's factors in one precision: phi (N x N),
+// mf / mi (K blocks of 2n x 2n), lam (n N).
+template <class T>
+struct FdFactorsDevice {
+    T *phi = nullptr, *mf = nullptr, *mi = nullptr, *lam = nullptr;
+};
+
+// One axis: the factors in FP64 and rounded to FP32 (the FP32 apply), and
+// cols[2k] / cols[2k+1] (ccos / csin).
 struct FdAxisDevice {
     int N = 0, K = 0, zero = -1;
-    double *phi = nullptr, *mf = nullptr, *mi = nullptr, *lam = nullptr;
+    FdFactorsDevice<double> f64;
+    FdFactorsDevice<float> f32;
     int* cols = nullptr;
+    template <class T> const FdFactorsDevice<T>& get() const;
 };
+template <> inline const FdFactorsDevice<double>& FdAxisDevice::get<double>() const { return f64; }
+template <> inline const FdFactorsDevice<float>& FdAxisDevice::get<float>() const { return f32; }
 
 // Device resources of the preconditioner, owned by a workspace.
 struct FdDevice {
     int n = 0;
     FdAxisDevice x, y;                         // y aliases x when `shared`
     bool shared = false;
-    double *img0 = nullptr, *img1 = nullptr;   // node-plane work fields
+    double *img0 = nullptr, *img1 = nullptr;   // node-plane work fields (FP64,
+                                               // or FP32 in their first half)
     void* blas = nullptr;                      // rocblas_handle
     size_t bytes = 0;
 };

@@ -12,9 +12,9 @@ namespace dgk {
 
 namespace {
 
-template <int N, bool FromL64>
+template <int N, bool FromL64, class T>
 __global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, const double* __restrict__ src,
-                                                         double* __restrict__ img) {
+                                                         T* __restrict__ img) {
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
@@ -25,12 +25,12 @@ __global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, const double* _
         if (FromL64) ld_l64<N>(src, c, u);
         else ld_canon<N>(src, c, u);
 #pragma unroll
-        for (int q = 0; q < N * N; ++q) img[cell + cells * q] = u[q];
+        for (int q = 0; q < N * N; ++q) img[cell + cells * q] = (T)u[q];
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const double* __restrict__ img,
+template <int N, class T>
+__global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const T* __restrict__ img,
                                                            double* __restrict__ dst) {
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const double*
         const CellRef c = cell_ref<N>(g, G, cx, cy);
         double u[N * N];
 #pragma unroll
-        for (int q = 0; q < N * N; ++q) u[q] = img[cell + cells * q];
+        for (int q = 0; q < N * N; ++q) u[q] = (double)img[cell + cells * q];
         st_canon<N>(dst, c, u);
     }
 }
@@ -48,9 +48,9 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const double*
 // z = image (to L64) and <r, z>_W; the last block sets rz and, past the
 // first iteration, beta = <r,z>_new / <r,z>_old (no-op once the solve is
 // done; a non-positive or non-finite <r,z> ends the solve as a breakdown).
-template <int N>
+template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
-    Geom g, OpConst<double> k, const double* __restrict__ img, double* __restrict__ z,
+    Geom g, OpConst<double> k, const T* __restrict__ img, double* __restrict__ z,
     const double* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
     if (sc->done) return;
     const long cells = (long)g.nx * g.ny;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
         const CellRef c = cell_ref<N>(g, G, cx, cy);
         double u[N * N], rv[N * N];
 #pragma unroll
-        for (int q = 0; q < N * N; ++q) u[q] = img[cell + cells * q];
+        for (int q = 0; q < N * N; ++q) u[q] = (double)img[cell + cells * q];
         st_l64<N>(z, c, u);
         ld_l64<N>(r, c, rv);
         part[0] += wdot_cell<N>(k, rv, u);
@@ -87,14 +87,13 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
 
 // out = M v for one 2n-vector (M row-major, S = 2n, row = output index);
 // `pair` false: only the leading n x n block (wave numbers 0 and N/2).
-template <int N>
-__device__ __forceinline__ void mix_vec(const double* __restrict__ M, bool pair,
-                                        const double* v, double* out) {
+template <int N, class T>
+__device__ __forceinline__ void mix_vec(const T* __restrict__ M, bool pair, const T* v, T* out) {
     constexpr int S = 2 * N;
     if (pair) {
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            double acc = 0.0;
+            T acc = 0;
 #pragma unroll
             for (int p = 0; p < S; ++p) acc = fma(M[q * S + p], v[p], acc);
             out[q] = acc;
@@ -102,7 +101,7 @@ __device__ __forceinline__ void mix_vec(const double* __restrict__ M, bool pair,
     } else {
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-            double acc = 0.0;
+            T acc = 0;
 #pragma unroll
             for (int p = 0; p < N; ++p) acc = fma(M[q * S + p], v[p], acc);
             out[q] = acc;
@@ -116,16 +115,16 @@ __device__ __forceinline__ void mix_vec(const double* __restrict__ M, bool pair,
 // (sin, -1 if none) of all nodes i form the 2n-vector (h, i) -> h n + i,
 // which is replaced by M_k times it, in place.  One lane per cy, so each
 // access is contiguous across the wave; M_k is the same for the block.
-template <int N>
+template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fd_mix_x(int Nx, int Ny,
                                                          const int* __restrict__ cols,
-                                                         const double* __restrict__ M,
-                                                         double* __restrict__ u) {
+                                                         const T* __restrict__ M,
+                                                         T* __restrict__ u) {
     constexpr int S = 2 * N;
     const int k = blockIdx.y;
     const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
     const bool pair = c1 >= 0;
-    const double* Mk = M + (size_t)k * S * S;
+    const T* Mk = M + (size_t)k * S * S;
     const long per = (long)Ny * N;
     for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
          t += (long)gridDim.x * kPwThreads) {
@@ -133,13 +132,13 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_x(int Nx, int Ny,
         const long base = cy + (long)Ny * N * Nx * j;
         const long o0 = base + (long)Ny * N * c0;
         const long o1 = base + (long)Ny * N * (pair ? c1 : c0);
-        double v[S], w[S];
+        T v[S], w[S];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             v[i] = u[o0 + (long)Ny * i];
-            v[N + i] = pair ? u[o1 + (long)Ny * i] : 0.0;
+            v[N + i] = pair ? u[o1 + (long)Ny * i] : T(0);
         }
-        mix_vec<N>(Mk, pair, v, w);
+        mix_vec<N, T>(Mk, pair, v, w);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             u[o0 + (long)Ny * i] = w[i];
@@ -155,39 +154,39 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_x(int Nx, int Ny,
 // columns cols[2k], cols[2k+1] over the nodes j goes to y modes by Mf_k,
 // each y mode (b, column c) is divided by -(lx + ly[b Ny + c]) (the constant
 // mode, x slot zx and y slot zy, is set to zero), and Mi_k maps back.
-template <int N>
+template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
-    int Nx, const int* __restrict__ cols, const double* __restrict__ Mf,
-    const double* __restrict__ Mi, const double* __restrict__ lx, const double* __restrict__ ly,
-    int Ny, int zx, int zy, double* __restrict__ u) {
+    int Nx, const int* __restrict__ cols, const T* __restrict__ Mf, const T* __restrict__ Mi,
+    const T* __restrict__ lx, const T* __restrict__ ly, int Ny, int zx, int zy,
+    T* __restrict__ u) {
     constexpr int S = 2 * N;
     const int k = blockIdx.y;
     const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
     const bool pair = c1 >= 0;
-    const double* Mfk = Mf + (size_t)k * S * S;
-    const double* Mik = Mi + (size_t)k * S * S;
+    const T* Mfk = Mf + (size_t)k * S * S;
+    const T* Mik = Mi + (size_t)k * S * S;
     const long NXn = (long)N * Nx;
     for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
          m += (long)gridDim.x * kPwThreads) {
         const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
         const int xs = i * Nx + kx;
-        const double lam_x = lx[xs];
+        const T lam_x = lx[xs];
         const long o0 = m + NXn * N * c0;
         const long o1 = m + NXn * N * (pair ? c1 : c0);
-        double v[S], w[S];
+        T v[S], w[S];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             v[j] = u[o0 + NXn * j];
-            v[N + j] = pair ? u[o1 + NXn * j] : 0.0;
+            v[N + j] = pair ? u[o1 + NXn * j] : T(0);
         }
-        mix_vec<N>(Mfk, pair, v, w);
+        mix_vec<N, T>(Mfk, pair, v, w);
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             if (q >= N && !pair) break;
             const int ys = (q % N) * Ny + (q < N ? c0 : c1);
-            w[q] = (xs == zx && ys == zy) ? 0.0 : w[q] / -(lam_x + ly[ys]);
+            w[q] = (xs == zx && ys == zy) ? T(0) : w[q] / -(lam_x + ly[ys]);
         }
-        mix_vec<N>(Mik, pair, w, v);
+        mix_vec<N, T>(Mik, pair, w, v);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             u[o0 + NXn * j] = v[j];
@@ -198,53 +197,72 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
 
 }  // namespace
 
-hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, double* img,
+template <class T>
+hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, T* img,
                            hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
     if (from_l64) {
-        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, true>), dim3(nb), dim3(kPwThreads),
-                                              0, s, g, src, img));
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, true, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, src, img));
     } else {
-        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, false>), dim3(nb), dim3(kPwThreads),
-                                              0, s, g, src, img));
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, false, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, src, img));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_from_image(const Geom& g, const double* img, double* dst, hipStream_t s) {
+template <class T>
+hipError_t launch_from_image(const Geom& g, const T* img, double* dst, hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image<NN>), dim3(nb), dim3(kPwThreads), 0, s, g,
-                                          img, dst));
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image<NN, T>), dim3(nb), dim3(kPwThreads), 0,
+                                          s, g, img, dst));
     return hipGetLastError();
 }
 
-hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const double* img,
+template <class T>
+hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const T* img,
                                  double* z, const double* r, const DevScratch& d, hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN>), dim3(nb), dim3(kPwThreads), 0,
-                                          s, g, k, img, z, r, d.sc, d.counters + kCntDot,
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN, T>), dim3(nb), dim3(kPwThreads),
+                                          0, s, g, k, img, z, r, d.sc, d.counters + kCntDot,
                                           d.partials));
     return hipGetLastError();
 }
 
-hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const double* M,
-                           double* u, hipStream_t s) {
+template <class T>
+hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const T* M, T* u,
+                           hipStream_t s) {
     const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_x<NN>), dim3(nb, K), dim3(kPwThreads), 0, s,
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_x<NN, T>), dim3(nb, K), dim3(kPwThreads), 0, s,
                                         Nx, Ny, cols, M, u));
     return hipGetLastError();
 }
 
-hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const double* Mf,
-                           const double* Mi, const double* lx, const double* ly, int zx, int zy,
-                           double* u, hipStream_t s) {
+template <class T>
+hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+                           const T* Mi, const T* lx, const T* ly, int zx, int zy, T* u,
+                           hipStream_t s) {
     const int nb = pw_blocks((long)Nx * n, pointwise_block_cap());
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_y<NN>), dim3(nb, K), dim3(kPwThreads), 0, s,
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_y<NN, T>), dim3(nb, K), dim3(kPwThreads), 0, s,
                                         Nx, cols, Mf, Mi, lx, ly, Ny, zx, zy, u));
     return hipGetLastError();
 }
+
+#define DG_FD_INSTANTIATE(T)                                                                  \
+    template hipError_t launch_to_image<T>(const Geom&, const double*, bool, T*, hipStream_t); \
+    template hipError_t launch_from_image<T>(const Geom&, const T*, double*, hipStream_t);    \
+    template hipError_t launch_from_image_dot<T>(const Geom&, const OpConst<double>&,          \
+                                                 const T*, double*, const double*,             \
+                                                 const DevScratch&, hipStream_t);              \
+    template hipError_t launch_fd_mix_x<T>(int, int, int, int, const int*, const T*, T*,      \
+                                           hipStream_t);                                       \
+    template hipError_t launch_fd_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \
+                                           const T*, const T*, int, int, T*, hipStream_t);
+DG_FD_INSTANTIATE(double)
+DG_FD_INSTANTIATE(float)
+#undef DG_FD_INSTANTIATE
 
 }  // namespace dgk

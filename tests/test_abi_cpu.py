@@ -117,10 +117,11 @@ def test_workspace_bytes_and_field_size():
     # fast-diagonalisation option: z, two node-plane fields, and per axis
     # (square grid: the y factors are the x factors) the cell Fourier basis
     # (N x N), the forward and inverse mixing blocks (K = N/2 + 1 blocks of
-    # 2n x 2n), the eigenvalues (n N) and the K cos / sin column pairs
+    # 2n x 2n) and the eigenvalues (n N), each in FP64 and FP32, plus the K
+    # cos / sin column pairs
     def axis(N, n):
         K = N // 2 + 1
-        return (N * N + 2 * K * (2 * n) ** 2 + N * n) * 8 + 2 * K * 4
+        return (N * N + 2 * K * (2 * n) ** 2 + N * n) * (8 + 4) + 2 * K * 4
     bfd = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
     assert bfd == b64 + 3 * F + axis(512, 4)
     # unequal axes keep both factor sets
