@@ -141,7 +141,7 @@ class Grid1D:
         """Diagonal of 1 (x) W, W = diag(h w_j / 2) (Sec. 4.1, eq. diagonal)."""
         return np.tile(0.5 * self.h * self.el.w, self.N)
 
-    def lspace_operator(self, theta: float) -> sp.csr_matrix:
+    def lspace_operator(self, theta: float, boundary: str = "zero") -> sp.csr_matrix:
         """L-space matrix Mbar_theta of the weak dG derivative with numerical
         flux fhat = theta f^+ + (1 - theta) f^- at every face
         (Sec. 3, eq. discrete_derivative):
@@ -155,12 +155,15 @@ class Grid1D:
         theta = 1/2 is the standard (centred) flux of eq. standard-flux;
         theta = 1 / 0 are the one-sided fluxes used by the LDG Laplacian.
 
-        Homogeneous Dirichlet: the numerical flux on the two boundary faces
-        is zero (the reading that reproduces Table 2's Dirichlet row; the
-        alternative of a zero outside value, fhat = f_inside / 2, keeps the
-        operator skew and would conserve int f J and int g J, which Table 2
-        says it does not).  So the boundary cells lose both the neighbour
-        coupling and their own share of the boundary-face flux."""
+        Homogeneous Dirichlet, boundary = "zero": the numerical flux on the
+        two boundary faces is zero (the reading that reproduces Table 2's
+        Dirichlet row; the alternative of a zero outside value, fhat =
+        f_inside / 2, keeps the operator skew and would conserve int f J and
+        int g J, which Table 2 says it does not).  So the boundary cells lose
+        both the neighbour coupling and their own share of the boundary-face
+        flux.  boundary = "inside": the flux on a boundary face is the
+        cell's own trace there (the LDG flux of the gradient variable on a
+        Dirichlet boundary, see laplacian)."""
         e = self.el
         N = self.N
         per = self.bc == "periodic"
@@ -171,42 +174,92 @@ class Grid1D:
         if not per:
             n = self.n
             M = M.tolil()
-            M[(N - 1) * n:, (N - 1) * n:] = M[(N - 1) * n:, (N - 1) * n:] - (1.0 - theta) * e.R
-            M[:n, :n] = M[:n, :n] + theta * e.L
+            if boundary == "zero":
+                M[(N - 1) * n:, (N - 1) * n:] = M[(N - 1) * n:, (N - 1) * n:] - (1.0 - theta) * e.R
+                M[:n, :n] = M[:n, :n] + theta * e.L
+            elif boundary == "inside":
+                M[(N - 1) * n:, (N - 1) * n:] = M[(N - 1) * n:, (N - 1) * n:] + theta * e.R
+                M[:n, :n] = M[:n, :n] - (1.0 - theta) * e.L
+            else:
+                raise ValueError(boundary)
         return M.tocsr()
 
-    def derivative(self, kind: str = "centred") -> sp.csr_matrix:
+    def derivative(self, kind: str = "centred", boundary: str = "zero") -> sp.csr_matrix:
         """X-space derivative f_x = (1 (x) V) M f with
         M = (1 (x) F^T) Mbar (1 (x) F) and the mass-matrix inverse T = That/h
         folded in (Sec. 4.2, eq. matrix_xspace):
             f_x = (1 (x) V F^T) Mbar (1 (x) F) f .
-        kind: 'centred' (theta=1/2), 'forward' (theta=1), 'backward' (0)."""
-        if kind in self._cache:
-            return self._cache[kind]
+        kind: 'centred' (theta=1/2), 'forward' (theta=1), 'backward' (0);
+        boundary: the Dirichlet boundary-face flux (see lspace_operator)."""
+        key = (kind, boundary)
+        if key in self._cache:
+            return self._cache[key]
         theta = {"centred": 0.5, "forward": 1.0, "backward": 0.0}[kind]
         e = self.el
         N = self.N
         V = np.diag(2.0 / (self.h * e.w))
         left = sp.kron(sp.identity(N), V @ e.F.T)
         right = sp.kron(sp.identity(N), e.F)
-        op = (left @ self.lspace_operator(theta) @ right).tocsr()
-        self._cache[kind] = op
+        op = (left @ self.lspace_operator(theta, boundary) @ right).tocsr()
+        self._cache[key] = op
         return op
 
+    def jumps(self) -> sp.csr_matrix:
+        """Jump operator J (faces x nodes): [u]_f = u(right side) - u(left
+        side) at every face, the traces taken from the cell polynomials
+        (u(+-1) = sum_k ubar_k p_k(+-1), ubar = F u).  Periodic: the N faces
+        m - 1/2, m = 0..N-1 (face 0 joins cell N-1 to cell 0).  Dirichlet:
+        the N + 1 faces, the two boundary faces against the outside value 0."""
+        e = self.el
+        n, N = self.n, self.N
+        k = np.arange(n)
+        tr_r = np.ones(n) @ e.F                  # u(+1) as a functional of u
+        tr_l = ((-1.0) ** k) @ e.F               # u(-1)
+        per = self.bc == "periodic"
+        faces = N if per else N + 1
+        J = sp.lil_matrix((faces, N * n))
+        for f in range(faces):
+            right, left = f, f - 1               # cells on either side of face f
+            if per:
+                left %= N
+            if right < N:
+                J[f, right * n:(right + 1) * n] = J[f, right * n:(right + 1) * n].toarray() + tr_l
+            if left >= 0:
+                J[f, left * n:(left + 1) * n] = J[f, left * n:(left + 1) * n].toarray() - tr_r
+        return J.tocsr()
+
+    def penalty(self) -> float:
+        """C11 of the LDG jump penalty: 1 (in the units of the domain), except
+        n = 1 on a periodic grid, where the paper falls back to the plain
+        finite-difference Laplacian (Sec. 6.1, the P = 1 remark): 0."""
+        return 0.0 if (self.n == 1 and self.bc == "periodic") else 1.0
+
     def laplacian(self) -> sp.csr_matrix:
-        """1D LDG second derivative D_backward D_forward (alternating fluxes,
-        no penalty; the reading of Sec. 6's LDG Laplacian).  Periodic only."""
-        if self.bc != "periodic":
-            raise NotImplementedError("the LDG Laplacian is built for periodic grids only")
+        """1D LDG second derivative (Sec. 6: the local dG method of Cockburn
+        and Shu; its fluxes are not printed, this is the reading whose Table 3
+        errors match the printed ones):
+            L = D_backward D_forward - C11 W^-1 J^T J,
+        alternating fluxes (u-hat from the right, q-hat from the left of each
+        face) plus the jump penalty C11 sum_f [u][v] with C11 = penalty().
+        Homogeneous Dirichlet (Cockburn-Shu's boundary fluxes): u-hat = 0 and
+        q-hat = the inside trace of q on the boundary faces, and the penalty
+        acts on the jump against the outside value 0.  W L is symmetric;
+        negative semi-definite with the constants as null space (periodic),
+        negative definite (Dirichlet)."""
         if "lap" not in self._cache:
-            self._cache["lap"] = (self.derivative("backward")
-                                  @ self.derivative("forward")).tocsr()
+            L = self.derivative("backward", "inside") @ self.derivative("forward", "zero")
+            c11 = self.penalty()
+            if c11 != 0.0:
+                J = self.jumps()
+                L = L - c11 * sp.diags(1.0 / self.weights()) @ (J.T @ J)
+            self._cache["lap"] = L.tocsr()
         return self._cache["lap"]
 
 
 class Grid2D:
-    """Tensor-product periodic grid [x0,x1] x [y0,y1], Nx x Ny cells, n
-    polynomials per cell and direction (Sec. 4.3, two dimensions)."""
+    """Tensor-product grid [x0,x1] x [y0,y1], Nx x Ny cells, n polynomials
+    per cell and direction (Sec. 4.3, two dimensions); each axis periodic or
+    homogeneous Dirichlet."""
 
     def __init__(self, n: int, Nx: int, Ny: int, x0=0.0, x1=2 * math.pi,
                  y0=0.0, y1=2 * math.pi, bc_x="periodic", bc_y="periodic"):
@@ -218,6 +271,12 @@ class Grid2D:
     @property
     def shape(self):
         return (self.Ny, self.Nx, self.n, self.n)
+
+    @property
+    def periodic(self) -> bool:
+        """Both axes periodic: -Delta_h then has the constants as null space
+        and the Poisson problem is solved for W-mean-free data."""
+        return self.gx.bc == "periodic" and self.gy.bc == "periodic"
 
     def node_coords(self):
         """(X, Y) of every node in the canonical layout (Sec. 4.1 nodes)."""
@@ -304,15 +363,11 @@ def bracket(g: Grid2D, f: np.ndarray, h: np.ndarray) -> np.ndarray:
 
 
 def laplacian(g: Grid2D, u: np.ndarray) -> np.ndarray:
-    """LDG Laplacian with alternating fluxes:
-    Delta_h u = Dx_b(Dx_f u) + Dy_b(Dy_f u) (Sec. 6 first paragraph; the
-    fluxes are the reading stated in the design notes)."""
+    """LDG Laplacian Delta_h u = Lx u + Ly u with the 1D operators of
+    Grid1D.laplacian along each axis (Sec. 6 first paragraph; Sec. 4.3,
+    Kronecker products)."""
     U = to_image(u)
-    Lx = _apply_x(g.gx.derivative("backward"),
-                  _apply_x(g.gx.derivative("forward"), U))
-    Ly = _apply_y(g.gy.derivative("backward"),
-                  _apply_y(g.gy.derivative("forward"), U))
-    return from_image(Lx + Ly, g.n)
+    return from_image(_apply_x(g.gx.laplacian(), U) + _apply_y(g.gy.laplacian(), U), g.n)
 
 
 # --------------------------------------------------------------------------
@@ -342,21 +397,21 @@ class CGResult:
 def cg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
                max_iter=100000) -> CGResult:
     """Plain conjugate gradient on -Delta_h psi = b in the W inner product
-    (A = -Delta_h is W-self-adjoint), b = omega minus its W-mean (periodic
-    problem: constants span the null space).  The initial guess has its
-    W-mean removed; iteration stops when ||r||_W <= rtol ||b||_W, tested on
-    r_0 and after every update; iters counts operator applications after r_0.
-    The returned psi has zero W-mean.  ||b||_W = 0 returns psi = 0."""
+    (A = -Delta_h is W-self-adjoint).  Periodic grid: b = omega minus its
+    W-mean (constants span the null space), the initial guess has its W-mean
+    removed and so has the returned psi.  Dirichlet on an axis: A is
+    definite, b = omega.  Iteration stops when ||r||_W <= rtol ||b||_W,
+    tested on r_0 and after every update; iters counts operator
+    applications after r_0.  ||b||_W = 0 returns psi = 0."""
     W = g.weights()
 
     def dot(u, v):
         return float(np.sum(W * u * v))
 
-    b = omega - wmean(g, omega)
+    b, x = _poisson_start(g, omega, guess)
     bnorm = math.sqrt(dot(b, b))
     if bnorm == 0.0:
         return CGResult(np.zeros_like(omega), 0, True, 0.0)
-    x = np.zeros_like(omega) if guess is None else guess - wmean(g, guess)
     r = b + laplacian(g, x)                      # r = b - A x
     rr = dot(r, r)
     it = 0
@@ -375,8 +430,20 @@ def cg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
             break
         p = r + (rr_new / rr) * p
         rr = rr_new
-    x = x - wmean(g, x)
+    if g.periodic:
+        x = x - wmean(g, x)
     return CGResult(x, it, converged, math.sqrt(rr) / bnorm)
+
+
+def _poisson_start(g: Grid2D, omega: np.ndarray, guess):
+    """(b, x0) of the Poisson solves: on a periodic grid both W-mean-free."""
+    if g.periodic:
+        b = omega - wmean(g, omega)
+        x = np.zeros_like(omega) if guess is None else guess - wmean(g, guess)
+    else:
+        b = omega.copy()
+        x = np.zeros_like(omega) if guess is None else guess.copy()
+    return b, x
 
 
 # --------------------------------------------------------------------------
@@ -385,7 +452,8 @@ def cg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
 # built from separable 1D eigenbases ("fast diagonalisation").
 # --------------------------------------------------------------------------
 class FastDiagonalisation:
-    """Exact inverse of -Delta_h on W-mean-free fields.
+    """Exact inverse of -Delta_h on W-mean-free fields (periodic grid; with a
+    Dirichlet axis, of the definite -Delta_h on all fields).
 
     The 1D LDG second derivative L of each axis is self-adjoint in the 1D
     Gauss inner product (W L is symmetric, W = diag of Grid1D.weights), so
@@ -396,7 +464,7 @@ class FastDiagonalisation:
     lam_y[b] + lam_x[a] <= 0, and
         (-Delta_h)^+ R = V_y [ (V_y^T W_y R W_x V_x) / -(lam_y + lam_x) ] V_x^T
     with the single zero eigenvalue (the constant mode, lam_x = lam_y = 0)
-    dropped.  Dense eigh: meant for grids up to a few thousand nodes per
+    dropped on a periodic grid.  Dense eigh: meant for grids up to a few thousand nodes per
     axis."""
 
     def __init__(self, g: Grid2D):
@@ -406,7 +474,8 @@ class FastDiagonalisation:
         mu = -(self.ly[:, None] + self.lx[None, :])
         inv = np.zeros_like(mu)
         nz = np.ones_like(mu, dtype=bool)
-        nz[int(np.argmax(self.ly)), int(np.argmax(self.lx))] = False
+        if g.periodic:
+            nz[int(np.argmax(self.ly)), int(np.argmax(self.lx))] = False
         inv[nz] = 1.0 / mu[nz]
         self.inv_mu = inv
 
@@ -440,11 +509,10 @@ def pcg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
         return float(np.sum(W * u * v))
 
     apply_m = (lambda u: u.copy()) if precond is None else precond
-    b = omega - wmean(g, omega)
+    b, x = _poisson_start(g, omega, guess)
     bnorm = math.sqrt(dot(b, b))
     if bnorm == 0.0:
         return CGResult(np.zeros_like(omega), 0, True, 0.0)
-    x = np.zeros_like(omega) if guess is None else guess - wmean(g, guess)
     r = b + laplacian(g, x)
     rr = dot(r, r)
     it = 0
@@ -466,7 +534,8 @@ def pcg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
         rz_new = dot(r, z)
         p = z + (rz_new / rz) * p
         rz = rz_new
-    x = x - wmean(g, x)
+    if g.periodic:
+        x = x - wmean(g, x)
     return CGResult(x, it, converged, math.sqrt(rr) / bnorm)
 
 
@@ -606,12 +675,14 @@ def dense_operators(g: Grid2D):
 
 def dense_poisson_solve(g: Grid2D, omega: np.ndarray) -> np.ndarray:
     """Minimum-norm least-squares solution of -Lap psi = omega - mean, then
-    the W-mean removed: the exact zero-mean solution on a tiny grid."""
+    the W-mean removed: the exact zero-mean solution on a tiny periodic
+    grid (Dirichlet axis: the solution of -Lap psi = omega)."""
     _, _, Lap = dense_operators(g)
-    b = to_image(omega - wmean(g, omega)).ravel()
+    rhs = omega - wmean(g, omega) if g.periodic else omega
+    b = to_image(rhs).ravel()
     psi, *_ = np.linalg.lstsq(-Lap, b, rcond=None)
     psi = from_image(psi.reshape(g.Ny * g.n, g.Nx * g.n), g.n)
-    return psi - wmean(g, psi)
+    return psi - wmean(g, psi) if g.periodic else psi
 
 
 # --------------------------------------------------------------------------

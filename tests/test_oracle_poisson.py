@@ -67,3 +67,43 @@ def test_poisson_order_matches_table3(n):
         errs.append(math.sqrt(O.inner(g, e, e)))
     order = math.log2(errs[0] / errs[1])
     assert abs(order - np.mean(printed)) < 0.3
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_ldg_laplacian_is_symmetric_and_signed(n, bc):
+    # W L symmetric; negative semi-definite with the constants as null space
+    # (periodic) or negative definite (Dirichlet)
+    g1 = O.Grid1D(n, 7, 0.0, 1.3, bc)
+    L = g1.laplacian().toarray()
+    W = np.diag(g1.weights())
+    S = W @ L
+    assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    ev = np.linalg.eigvalsh(0.5 * (S + S.T))
+    scale = np.abs(ev).max()
+    if bc == "periodic":
+        assert ev[-1] <= 1e-12 * scale and abs(ev[-1]) <= 1e-12 * scale
+        assert ev[-2] < -1e-8 * scale
+        assert np.abs(L @ np.ones(L.shape[0])).max() <= 1e-12 * scale
+    else:
+        assert ev[-1] < -1e-8 * scale
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_ldg_laplacian_exact_on_polynomials_away_from_the_ends(n):
+    # a global polynomial of degree <= n - 1 has no jumps on interior faces
+    # and its LDG derivatives are exact there, so L q = q'' on every cell not
+    # next to an end (Dirichlet) or the wrap (periodic)
+    N = 8
+    for bc in ("periodic", "dirichlet"):
+        g1 = O.Grid1D(n, N, -0.4, 1.1, bc)
+        x = g1.nodes()
+        c = np.arange(1, n + 1) * 0.37
+        q = np.polynomial.polynomial.polyval(x, c)
+        d2 = np.polynomial.polynomial.polyval(x, np.polynomial.polynomial.polyder(c, 2))
+        Lq = g1.laplacian() @ q
+        inner_cells = slice(2 * n, (N - 2) * n)
+        assert np.abs(Lq[inner_cells] - d2[inner_cells]).max() <= 1e-9 * max(1.0, np.abs(d2).max())
+        J = g1.jumps() @ q
+        interior = slice(1, N)                  # faces between two cells
+        assert np.abs(J[interior]).max() <= 1e-12 * np.abs(q).max()
