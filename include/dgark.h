@@ -137,11 +137,13 @@ void dg_grid_destroy(dg_grid* grid);                 /* NULL-safe */
 size_t dg_field_elems(const dg_grid* grid);
 /* Copy the grid's host tables into `out` (capacity `len` doubles), in the
  * order: xi[n], w[n], C0[n*n], cR[n], sR[n], cL[n], sL[n] (centred, h = 1),
- * L0[n*n], eR[n], lR[n], eL[n], lL[n] (LDG second derivative, h = 1).
- * A 1D centred derivative is (1/h)[C0 u_m + cR (sR.u_{m+1}) + cL (sL.u_{m-1})],
- * the 1D LDG part (1/h^2)[L0 u_m + eR (lR.u_{m+1}) + eL (lL.u_{m-1})], all
- * n x n blocks row-major.  Returns the number of doubles written, or a
- * negative status (DG_E_INVAL if len is too small). */
+ * then for x and for y: L0[n*n], eR[n], lR[n], eL[n], lL[n] (the LDG second
+ * derivative of that axis).  A 1D centred derivative is
+ * (1/h)[C0 u_m + cR (sR.u_{m+1}) + cL (sL.u_{m-1})], the 1D LDG operator on
+ * interior cells (1/h^2)[L0 u_m + eR (lR.u_{m+1}) + eL (lL.u_{m-1})] with
+ * the axis' own h (its jump penalty is folded in, so these blocks depend on
+ * h), all n x n blocks row-major.  Returns the number of doubles written, or
+ * a negative status (DG_E_INVAL if len is too small). */
 int  dg_grid_tables(const dg_grid* grid, double* out, int len);
 
 /* Tile shapes of the grid's stencil launches: the cell-per-lane kernels

@@ -76,15 +76,20 @@ template <class T>
 void fill_const(const dg_grid& g, OpConst<T>& k) {
     std::memset(&k, 0, sizeof k);
     const int n = g.n;
+    AxisLdg ax, ay;
+    ldg_axis(g.t, g.hx, g.geom.bcx == 0, &ax);
+    ldg_axis(g.t, g.hy, g.geom.bcy == 0, &ay);
     for (int i = 0; i < n * n; ++i) {
         k.C0[i] = (T)g.t.C0[i];
-        k.L0[i] = (T)g.t.L0[i];
+        k.L0x[i] = (T)ax.L0[i];
+        k.L0y[i] = (T)ay.L0[i];
     }
     for (int i = 0; i < n; ++i) {
         k.cR[i] = (T)g.t.cR[i]; k.sR[i] = (T)g.t.sR[i];
         k.cL[i] = (T)g.t.cL[i]; k.sL[i] = (T)g.t.sL[i];
-        k.eR[i] = (T)g.t.eR[i]; k.lR[i] = (T)g.t.lR[i];
-        k.eL[i] = (T)g.t.eL[i]; k.lL[i] = (T)g.t.lL[i];
+        k.eRx[i] = (T)ax.eR[i]; k.eRy[i] = (T)ay.eR[i];
+        k.lLx[i] = (T)ax.lL[i]; k.lLy[i] = (T)ay.lL[i];
+        k.lR[i] = (T)g.t.lR[i]; k.eL[i] = (T)g.t.eL[i];
         k.w[i] = (T)g.t.w[i];
     }
     k.ihx = (T)(1.0 / g.hx);
@@ -435,9 +440,9 @@ int dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
     g->hy = (y1 - y0) / ny;
     g->area = (x1 - x0) * (y1 - y0);
     if (!build_tables(n, &g->t)) { delete g; return fail(DG_E_INVAL, "table build failed"); }
-    fill_const(*g, g->k64);
     g->geom = Geom{n, nx, ny, kCellWavesDefault, kRowWavesDefault,
                    bc_x == DG_BC_DIRICHLET ? 1 : 0, bc_y == DG_BC_DIRICHLET ? 1 : 0};
+    fill_const(*g, g->k64);
     g->elems = (size_t)nx * ny * n * n;
     *out = g;
     return DG_OK;
@@ -450,13 +455,18 @@ size_t dg_field_elems(const dg_grid* g) { return g ? g->elems : 0; }
 int dg_grid_tables(const dg_grid* g, double* out, int len) {
     if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
     const int n = g->n;
-    const int need = 2 * n + 2 * (n * n + 4 * n);
+    const int need = 2 * n + 3 * (n * n + 4 * n);
     if (len < need) return fail(DG_E_INVAL, "need %d doubles", need);
     int o = 0;
     auto put = [&](const double* a, int m) { for (int i = 0; i < m; ++i) out[o++] = a[i]; };
     put(g->t.xi, n); put(g->t.w, n);
     put(g->t.C0, n * n); put(g->t.cR, n); put(g->t.sR, n); put(g->t.cL, n); put(g->t.sL, n);
-    put(g->t.L0, n * n); put(g->t.eR, n); put(g->t.lR, n); put(g->t.eL, n); put(g->t.lL, n);
+    AxisLdg ax, ay;
+    ldg_axis(g->t, g->hx, g->geom.bcx == 0, &ax);
+    ldg_axis(g->t, g->hy, g->geom.bcy == 0, &ay);
+    for (const AxisLdg* a : {&ax, &ay}) {
+        put(a->L0, n * n); put(a->eR, n); put(g->t.lR, n); put(g->t.eL, n); put(a->lL, n);
+    }
     return o;
 }
 

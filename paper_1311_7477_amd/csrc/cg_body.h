@@ -155,7 +155,7 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
         T h[N * N];
         src(c.d, h);
 #pragma unroll
-        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, k.lL);
+        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, k.lLy);
     }
     if (c.active && !c.xin_r) {
         T h[N * N];
@@ -167,20 +167,20 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
         T h[N * N];
         src(c.l, h);
 #pragma unroll
-        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lL);
+        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lLx);
     }
     // publish this cell's y face scalars
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         lds.v[((c.wave * 2 + 0) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lR);
-        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lL);
+        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lLy);
     }
     // x face scalars from the neighbouring lanes
     T fR[N], fL[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const T a = __shfl(xdot<N>(u, j, k.lR), c.lane + 1);
-        const T b = __shfl(xdot<N>(u, j, k.lL), c.lane - 1);
+        const T b = __shfl(xdot<N>(u, j, k.lLx), c.lane - 1);
         fR[j] = c.xin_r ? a : hR[j];
         fL[j] = c.xin_l ? b : hL[j];
     }
@@ -195,12 +195,12 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     for (int j = 0; j < N; ++j)
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T lx = fmx(k.eR[i], fR[j], k.eL[i] * fL[j]);
-            T ly = fmx(k.eR[j], fU[i], k.eL[j] * fD[i]);
+            T lx = fmx(k.eRx[i], fR[j], k.eL[i] * fL[j]);
+            T ly = fmx(k.eRy[j], fU[i], k.eL[j] * fD[i]);
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                lx = fmx(k.L0[i * N + m], u[j * N + m], lx);
-                ly = fmx(k.L0[j * N + m], u[m * N + i], ly);
+                lx = fmx(k.L0x[i * N + m], u[j * N + m], lx);
+                ly = fmx(k.L0y[j * N + m], u[m * N + i], ly);
             }
             out[j * N + i] = fmx(lx, k.ihx2, ly * k.ihy2);
         }

@@ -15,22 +15,44 @@ constexpr int kMaxN = 5;
 //     (D u)_m = C0 u_m + cR (sR . u_{m+1}) + cL (sL . u_{m-1})
 //   LDG second derivative D_backward D_forward (Sec. 6):
 //     (L u)_m = L0 u_m + eR (lR . u_{m+1}) + eL (lL . u_{m-1})
-// The neighbour couplings are rank one: one scalar per node row.
+// The neighbour couplings are rank one: one scalar per node row.  tR / tL
+// are the end-value functionals u(+1) = tR . u, u(-1) = tL . u, and pR / pL
+// = h W^-1 tR, h W^-1 tL (W = (h/2) diag(w)); they build the LDG jump
+// penalty (ldg_axis).
 struct HostTables {
     int n;
     double xi[kMaxN], w[kMaxN];
     double C0[kMaxN * kMaxN], cR[kMaxN], sR[kMaxN], cL[kMaxN], sL[kMaxN];
     double L0[kMaxN * kMaxN], eR[kMaxN], lR[kMaxN], eL[kMaxN], lL[kMaxN];
+    double tR[kMaxN], tL[kMaxN], pR[kMaxN], pL[kMaxN];
 };
 
 // Builds the tables for n in [1, 5]; returns false on bad n.
 bool build_tables(int n, HostTables* t);
 
+// The LDG second derivative of one periodic axis with cell size h, in the
+// same h = 1 form (the operator is these blocks times h^-2):
+//     L = D_backward D_forward - C11 W^-1 J^T J,
+// the jump penalty C11 sum_faces [u][v] added to the alternating-flux
+// operator.  Its couplings stay rank one with the same lR and eL:
+//     L0' = L0 - C11 h (pR tR^T + pL tL^T),  eR' = eR + C11 h pR,
+//     lL' = lL - C11 h tR.
+// C11 = ldg_penalty(n, periodic): 1 in the units of the domain, 0 for n = 1
+// on a periodic axis (the plain finite-difference Laplacian there).
+struct AxisLdg {
+    double L0[kMaxN * kMaxN], eR[kMaxN], lL[kMaxN];
+};
+double ldg_penalty(int n, bool periodic);
+void ldg_axis(const HostTables& t, double h, bool periodic, AxisLdg* out);
+
 // Operator constants passed to kernels by value (kernel-argument segment).
+// The LDG blocks depend on the cell size through the jump penalty, so x and
+// y have their own L0 / eR / lL (lR and eL are shared).
 template <class T>
 struct OpConst {
     T C0[kMaxN * kMaxN], cR[kMaxN], sR[kMaxN], cL[kMaxN], sL[kMaxN];
-    T L0[kMaxN * kMaxN], eR[kMaxN], lR[kMaxN], eL[kMaxN], lL[kMaxN];
+    T L0x[kMaxN * kMaxN], L0y[kMaxN * kMaxN];
+    T eRx[kMaxN], eRy[kMaxN], lLx[kMaxN], lLy[kMaxN], lR[kMaxN], eL[kMaxN];
     T w[kMaxN];
     T ihx, ihy, ihx2, ihy2;   // 1/hx, 1/hy, 1/hx^2, 1/hy^2
     double wq;                // hx * hy / 4: node weight = wq * w_i * w_j

@@ -3,7 +3,8 @@
 // fields (a preconditioner for the CG of Sec. 6, which itself is plain CG).
 //
 // Along one periodic axis with N cells of size h the LDG second derivative
-// (Sec. 6, D_backward D_forward) is block circulant,
+// (Sec. 6, D_backward D_forward plus the jump penalty; the blocks of
+// ldg_axis) is block circulant,
 //     (L u)_m = h^-2 [L0 u_m + eR (lR . u_{m+1}) + eL (lL . u_{m-1})],
 // so Bloch waves u_m = v e^{i theta m}, theta = 2 pi k / N, reduce it to the
 // n x n symbols S(theta) = h^-2 [L0 + e^{i theta} eR lR^T + e^{-i theta} eL lL^T].
@@ -81,14 +82,16 @@ void bloch_eig(const HostTables& t, int N, double h, int k, double* lam, cplx* v
     const double ih2 = 1.0 / (h * h);
     const double two_pi = 6.283185307179586476925286766559;
     std::vector<cplx> S(n * n), H(n * n), U(n * n);
+    AxisLdg ax;
+    ldg_axis(t, h, true, &ax);
     const double th = two_pi * k / N;
     // e^{i theta}, exact at theta = 0 and pi so those symbols stay real
     const cplx ep = (k == 0) ? cplx(1.0, 0.0)
                   : (2 * k == N) ? cplx(-1.0, 0.0) : cplx(std::cos(th), std::sin(th));
-    for (int a = 0; a < n; ++a)
+    for (int r = 0; r < n; ++r)
         for (int b = 0; b < n; ++b)
-            S[a * n + b] = ih2 * (t.L0[a * n + b] + ep * (t.eR[a] * t.lR[b]) +
-                                  std::conj(ep) * (t.eL[a] * t.lL[b]));
+            S[r * n + b] = ih2 * (ax.L0[r * n + b] + ep * (ax.eR[r] * t.lR[b]) +
+                                  std::conj(ep) * (t.eL[r] * ax.lL[b]));
     for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b)
             H[a * n + b] = std::sqrt(t.w[a]) * S[a * n + b] / std::sqrt(t.w[b]);

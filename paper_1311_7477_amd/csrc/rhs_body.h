@@ -202,7 +202,7 @@ __device__ __forceinline__ void rhs_body(
     double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
     row_op<N, double, DIR>(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
     row_op<N, double, DIR>(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
-    if (VISC) row_op(G, c.lane, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihx2, LxG);
+    if (VISC) row_op(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.ihx2, LxG);
 
     lds_put_row(lA, c, F);
     lds_put_row(lB, c, G);
@@ -211,7 +211,7 @@ __device__ __forceinline__ void rhs_body(
         double cF[N], cG[N], cL[N];
         col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
         col_op<N, WAVES, double, DIR>(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
-        if (VISC) col_op(lB, c, k.L0, k.eR, k.lR, k.eL, k.lL, k.ihy2, cL);
+        if (VISC) col_op(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.ihy2, cL);
         __syncthreads();
         lds_put_col(lA, c, cF);
         lds_put_col(lB, c, cG);

@@ -142,9 +142,29 @@ bool build_tables(int n, HostTables* t) {
         double q = 0.0;
         for (int k = 0; k < n; ++k) q += F0[k * n + i] * trR[k];
         t->lL[i] = q;
+        // end values and their W^-1 images: W^-1 tR^T = (B T r) / h
+        t->tR[i] = trR[i];
+        t->tL[i] = trL[i];
+        t->pR[i] = BTr[i];
+        t->pL[i] = BTl[i];
     }
     (void)nn;
     return true;
+}
+
+double ldg_penalty(int n, bool periodic) { return (n == 1 && periodic) ? 0.0 : 1.0; }
+
+void ldg_axis(const HostTables& t, double h, bool periodic, AxisLdg* out) {
+    const int n = t.n;
+    const double c = ldg_penalty(n, periodic) * h;
+    // penalty on face m+1/2: -C11 W^-1 (-tR)^T [u], [u] = tL.u_{m+1} - tR.u_m;
+    // on face m-1/2: -C11 W^-1 tL^T [u], [u] = tL.u_m - tR.u_{m-1}
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j)
+            out->L0[i * n + j] = t.L0[i * n + j] - c * (t.pR[i] * t.tR[j] + t.pL[i] * t.tL[j]);
+        out->eR[i] = t.eR[i] + c * t.pR[i];
+        out->lL[i] = t.lL[i] - c * t.tR[i];
+    }
 }
 
 }  // namespace dgk

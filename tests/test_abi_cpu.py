@@ -33,9 +33,9 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def _tables(n):
+def _tables(n, N=3, x1=1.0, y1=1.0):
     from paper_1311_7477_amd import dg
-    t = np.array(dg.Grid(n, 3, 3).tables())
+    t = np.array(dg.Grid(n, N, N, 0.0, x1, 0.0, y1).tables())
     o = 0
 
     def take(m):
@@ -47,8 +47,10 @@ def _tables(n):
     d["xi"], d["w"] = take(n), take(n)
     d["C0"] = take(n * n).reshape(n, n)
     d["cR"], d["sR"], d["cL"], d["sL"] = take(n), take(n), take(n), take(n)
-    d["L0"] = take(n * n).reshape(n, n)
-    d["eR"], d["lR"], d["eL"], d["lL"] = take(n), take(n), take(n), take(n)
+    for ax in ("x", "y"):
+        d["L0" + ax] = take(n * n).reshape(n, n)
+        for k in ("eR", "lR", "eL", "lL"):
+            d[k + ax] = take(n)
     assert o == len(t)
     return d
 
@@ -67,17 +69,24 @@ def _assemble(n, N, A0, eR, tR, eL, tL):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
 def test_host_tables_reproduce_oracle_operators(n):
-    d = _tables(n)
-    N, a, b = 6, 0.0, 1.7
-    g = O.Grid1D(n, N, a, b)
-    np.testing.assert_allclose(d["xi"], g.el.xi, atol=1e-15)
-    np.testing.assert_allclose(d["w"], g.el.w, atol=1e-15)
-    Dc = _assemble(n, N, d["C0"], d["cR"], d["sR"], d["cL"], d["sL"]) / g.h
-    ref = g.derivative("centred").toarray()
-    np.testing.assert_allclose(Dc, ref, atol=1e-13 * np.abs(ref).max())
-    Lp = _assemble(n, N, d["L0"], d["eR"], d["lR"], d["eL"], d["lL"]) / g.h ** 2
-    ref = g.laplacian().toarray()
-    np.testing.assert_allclose(Lp, ref, atol=1e-13 * np.abs(ref).max())
+    # the C++ tables (built from the Legendre recursion and the block
+    # algebra of the fluxes) against the oracle's sparse operators (built
+    # from lspace_operator and the explicit jump operator); x and y with
+    # different cell sizes, since the jump penalty makes the LDG blocks
+    # depend on h
+    N, lx, ly = 6, 1.7, 5.0
+    d = _tables(n, N, lx, ly)
+    for ax, length in (("x", lx), ("y", ly)):
+        g = O.Grid1D(n, N, 0.0, length)
+        np.testing.assert_allclose(d["xi"], g.el.xi, atol=1e-15)
+        np.testing.assert_allclose(d["w"], g.el.w, atol=1e-15)
+        Dc = _assemble(n, N, d["C0"], d["cR"], d["sR"], d["cL"], d["sL"]) / g.h
+        ref = g.derivative("centred").toarray()
+        np.testing.assert_allclose(Dc, ref, atol=1e-13 * np.abs(ref).max())
+        Lp = _assemble(n, N, d["L0" + ax], d["eR" + ax], d["lR" + ax], d["eL" + ax],
+                       d["lL" + ax]) / g.h ** 2
+        ref = g.laplacian().toarray()
+        np.testing.assert_allclose(Lp, ref, atol=1e-13 * np.abs(ref).max())
 
 
 def test_grid_create_validation():

@@ -213,7 +213,8 @@ def test_mixed_precision_large_grid(dg, N):
 
 def test_rk3_config1_trajectory(dg):
     # 10 SSP-RK3 steps, n = 3, 32 x 32, D = 1e-3, dt = 1e-3 (Taylor-Green +
-    # 1e-3 noise); both sides solve to rtol 1e-14
+    # 1e-3 noise); both sides solve to rtol 1e-13 (1e-14 lies below the
+    # attainable FP64 residual of this operator: the oracle's CG stalls there)
     n, N, D, dt, steps = 3, 32, 1e-3, 1e-3, 10
     print("rk3 config1", flush=True)
     g = O.Grid2D(n, N, N)
@@ -223,14 +224,14 @@ def test_rk3_config1_trajectory(dg):
     st = dg.State(grid)
     w = _dev(w0)
     wr, t, hist = w0.copy(), 0.0, O.PsiHistory()
-    opts = dg.cg_opts(rtol=1e-14)
+    opts = dg.cg_opts(rtol=1e-13)
     for k in range(steps):
         res = dg.rk_step(grid, w, st, ws, dt, D, opts)
-        wr, its = O.rk3_step(g, wr, t, dt, D, hist, rtol=1e-14)
+        wr, its = O.rk3_step(g, wr, t, dt, D, hist, rtol=1e-13, max_iter=5000)
         t += dt
         assert res.converged
-        # at rtol 1e-14 CG runs at its rounding floor, where the last few
-        # residual reductions depend on the summation order
+        # near the rounding floor the last few residual reductions depend on
+        # the summation order
         assert all(abs(a - b) <= max(2, 0.03 * b) for a, b in zip(res.cg_iters, its)), \
             (res.cg_iters, its)
     got = w.cpu().numpy()
