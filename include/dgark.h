@@ -53,7 +53,7 @@ extern "C" {
 
 /* boundary conditions */
 #define DG_BC_PERIODIC   0
-#define DG_BC_DIRICHLET  1      /* homogeneous; bracket only (others: DG_E_UNSUPPORTED) */
+#define DG_BC_DIRICHLET  1      /* homogeneous (see dg_grid_create for what it supports) */
 
 /* CG precision modes (also the workspace mode) */
 #define DG_PREC_FP64   0
@@ -124,12 +124,16 @@ const char* dg_last_error(void);
  * discrete_der, matrix_xspace) and the LDG Laplacian blocks (Sec. 6).
  * n in [1, 5] polynomials per cell and direction, nx, ny >= 1 cells, finite
  * x0 < x1 and y0 < y1.  bc_x, bc_y: DG_BC_PERIODIC (Sec. 3 periodic closure)
- * or DG_BC_DIRICHLET (homogeneous, Sec. 3: read as a zero numerical flux on
- * the boundary faces of that axis, the closure that gives Table 2's
- * Dirichlet row).  A grid with a Dirichlet axis supports dg_poisson_bracket,
- * dg_bracket_form and dg_invariants; the Laplacian, the Poisson solve, the
- * steppers, batches, the preconditioner and the tuner return
- * DG_E_UNSUPPORTED for it.  Touches no GPU.  Errors: DG_E_INVAL, DG_E_NOMEM. */
+ * or DG_BC_DIRICHLET (homogeneous: for the bracket, Sec. 3, read as a zero
+ * numerical flux on the boundary faces of that axis, the closure that gives
+ * Table 2's Dirichlet row; for the LDG Laplacian u-hat = 0 and q-hat = the
+ * inside trace with the jump penalty against 0, the closure that gives
+ * Table 3's Dirichlet columns).  A grid with a Dirichlet axis supports the
+ * bracket, the Laplacian, the plain FP64 Poisson solve (no mean is removed:
+ * -Lap_h is definite), dg_rk_step, dg_ab_step and dg_invariants, with cell
+ * tiles of 64 x 8; mixed precision, the preconditioner, batches and the
+ * tuner return DG_E_UNSUPPORTED for it.  Touches no GPU.  Errors:
+ * DG_E_INVAL, DG_E_NOMEM. */
 int  dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
                     double y1, int bc_x, int bc_y, dg_grid** out);
 void dg_grid_destroy(dg_grid* grid);                 /* NULL-safe */
@@ -137,13 +141,16 @@ void dg_grid_destroy(dg_grid* grid);                 /* NULL-safe */
 size_t dg_field_elems(const dg_grid* grid);
 /* Copy the grid's host tables into `out` (capacity `len` doubles), in the
  * order: xi[n], w[n], C0[n*n], cR[n], sR[n], cL[n], sL[n] (centred, h = 1),
- * then for x and for y: L0[n*n], eR[n], lR[n], eL[n], lL[n] (the LDG second
- * derivative of that axis).  A 1D centred derivative is
- * (1/h)[C0 u_m + cR (sR.u_{m+1}) + cL (sL.u_{m-1})], the 1D LDG operator on
- * interior cells (1/h^2)[L0 u_m + eR (lR.u_{m+1}) + eL (lL.u_{m-1})] with
- * the axis' own h (its jump penalty is folded in, so these blocks depend on
- * h), all n x n blocks row-major.  Returns the number of doubles written, or
- * a negative status (DG_E_INVAL if len is too small). */
+ * then for x and for y: L0[n*n], eR[n], lR[n], eL[n], lL[n], L0B[n*n],
+ * eRB[n], lLB[n] (the LDG second derivative of that axis).  A 1D centred derivative
+ * is (1/h)[C0 u_m + cR (sR.u_{m+1}) + cL (sL.u_{m-1})], the 1D LDG operator
+ * (1/h^2)[L0 u_m + eR (lR.u_{m+1}) + eL (lL.u_{m-1})] with the axis' own h
+ * (its jump penalty is folded in, so these blocks depend on h); on a
+ * homogeneous Dirichlet axis the last cell drops the right coupling, the
+ * first cell is (1/h^2)[L0B u_0 + eRB (lR.u_1)] and the second one sees the
+ * first through eL (lLB.u_0).  All n x n blocks row-major.  Returns the
+ * number of doubles written, or a negative status (DG_E_INVAL if len is too
+ * small). */
 int  dg_grid_tables(const dg_grid* grid, double* out, int len);
 
 /* Tile shapes of the grid's stencil launches: the cell-per-lane kernels
@@ -152,7 +159,8 @@ int  dg_grid_tables(const dg_grid* grid, double* out, int len);
  * tiles re-read fewer halo rows but hold more registers and LDS per
  * workgroup.  The shapes change the reduction order and hence the last bits
  * of CG results; set them before using the grid (a batch copies them when an
- * instance is attached).  DG_E_INVAL for other values. */
+ * instance is attached).  DG_E_INVAL for other values, and for cw != 8 on a
+ * grid with a Dirichlet axis. */
 int  dg_grid_set_tiles(dg_grid* grid, int cw, int rw);
 int  dg_grid_tiles(const dg_grid* grid, int* cw, int* rw);
 /* Tile autotuner: on the current device, time `reps` CG iterations for each
@@ -169,13 +177,15 @@ int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
 /* Device bytes a workspace for (grid, mode) holds: CG vectors x, r, p, the
  * two RK stage fields, reduction partials and scalars, plus FP32 r and p in
  * DG_PREC_MIXED mode, plus (DG_WS_FD) the preconditioner's z vector, two
- * image-layout fields and the eigenbases (2 (nx n)^2 + 2 (ny n)^2 doubles,
- * half that when the axes agree; rocBLAS keeps its own small workspace on
- * top).  This is the figure that admission control budgets.  mode =
- * DG_PREC_FP64 or DG_PREC_MIXED, optionally | DG_WS_FD. */
+ * node-plane fields and per axis the factored eigenbasis in FP64 and FP32
+ * (the N x N cell Fourier basis, 2 (N/2 + 1) mixing blocks of 2n x 2n and
+ * n N eigenvalues; one set when the axes agree; rocBLAS keeps its own small
+ * workspace on top).  This is the figure that admission control budgets.
+ * mode = DG_PREC_FP64 or DG_PREC_MIXED, optionally | DG_WS_FD. */
 int  dg_workspace_bytes(const dg_grid* grid, int mode, size_t* bytes);
 /* Allocate a workspace on the current device (hipMalloc + pinned host
- * scalars).  Errors: DG_E_INVAL, DG_E_NOMEM, DG_E_HIP. */
+ * scalars).  Errors: DG_E_INVAL, DG_E_NOMEM, DG_E_HIP; DG_E_UNSUPPORTED for
+ * DG_WS_FD on a grid with a Dirichlet axis. */
 int  dg_workspace_create(const dg_grid* grid, int mode, dg_workspace** out);
 void dg_workspace_destroy(dg_workspace* ws);         /* NULL-safe */
 
@@ -200,10 +210,13 @@ int  dg_poisson_bracket(const dg_grid* grid, const double* f, const double* g,
  * (form = DG_FORM_*), Sec. 2 eq. J.  Same rules as dg_poisson_bracket. */
 int  dg_bracket_form(const dg_grid* grid, const double* f, const double* g,
                      double* out, int form, void* stream);
-/* out = Lap_h f, the LDG Laplacian with alternating fluxes,
- * Dx_backward Dx_forward + Dy_backward Dy_forward (Sec. 6; the flux choice is
- * the reading stated with the design).  -W Lap_h is symmetric positive
- * semi-definite with the constants as null space.  out != f.  Asynchronous. */
+/* out = Lap_h f, the LDG Laplacian of Sec. 6 (local dG of Cockburn and Shu,
+ * fluxes unprinted; read as): per axis Dx_backward Dx_forward minus the jump
+ * penalty C11 sum_faces [u][v] with C11 = 1, the reading whose Table 3
+ * errors match the printed ones (n = 1 on a periodic axis: no penalty, the
+ * 5-point Laplacian the paper falls back to).  -W Lap_h is symmetric
+ * positive semi-definite with the constants as null space (periodic) or
+ * definite (a Dirichlet axis).  out != f.  Asynchronous. */
 int  dg_laplace_apply(const dg_grid* grid, const double* f, double* out,
                       void* stream);
 
@@ -211,9 +224,11 @@ int  dg_laplace_apply(const dg_grid* grid, const double* f, double* out,
 /* Solve -Lap_h psi = omega - mean_W(omega) by conjugate gradients in the
  * Gauss inner product (Sec. 6: symmetric system, CG; Sec. 4.1 eq. def_norm).
  * On entry psi holds the initial guess (its W-mean is removed); on exit the
- * zero-mean solution.  ||omega - mean|| = 0 gives psi = 0.  ws must be made
- * for this grid, with DG_WS_FD for DG_PRECOND_FD (any precision mode), else
- * in mixed mode for DG_PREC_MIXED (else DG_E_WORKSPACE).  Synchronises the stream
+ * zero-mean solution.  ||omega - mean|| = 0 gives psi = 0.  On a grid with a
+ * Dirichlet axis -Lap_h is definite: -Lap_h psi = omega, no mean removed.
+ * ws must be made for this grid, with DG_WS_FD for DG_PRECOND_FD (any
+ * precision mode), else in mixed mode for DG_PREC_MIXED (else
+ * DG_E_WORKSPACE).  Synchronises the stream
  * (convergence polling).  Returns DG_E_NOCONV when max_iter was hit or the
  * iteration broke down (psi holds the last iterate).  psi must not alias
  * omega. */

@@ -75,7 +75,6 @@ const dg_state* dg_ab_psi_state(const dg_ab_state* ab) { return ab ? ab->st : nu
 int dg_ab_step(const dg_grid* g, double* omega, dg_ab_state* ab, const dg_step_opts* opts,
                dg_step_stats* stats, dg_workspace* ws, void* stream) {
     if (!g || !omega || !ab || !opts) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("time stepping");
     if (!ws) return fail(DG_E_INVAL, "workspace is NULL");
     if (ab->n != g->n || ab->nx != g->nx || ab->ny != g->ny)
         return fail(DG_E_INVAL, "Adams-Bashforth state was made for another grid");

@@ -83,6 +83,8 @@ void fill_const(const dg_grid& g, OpConst<T>& k) {
         k.C0[i] = (T)g.t.C0[i];
         k.L0x[i] = (T)ax.L0[i];
         k.L0y[i] = (T)ay.L0[i];
+        k.L0Bx[i] = (T)ax.L0B[i];
+        k.L0By[i] = (T)ay.L0B[i];
     }
     for (int i = 0; i < n; ++i) {
         k.cR[i] = (T)g.t.cR[i]; k.sR[i] = (T)g.t.sR[i];
@@ -90,6 +92,8 @@ void fill_const(const dg_grid& g, OpConst<T>& k) {
         k.eRx[i] = (T)ax.eR[i]; k.eRy[i] = (T)ay.eR[i];
         k.lLx[i] = (T)ax.lL[i]; k.lLy[i] = (T)ay.lL[i];
         k.lR[i] = (T)g.t.lR[i]; k.eL[i] = (T)g.t.eL[i];
+        k.eRBx[i] = (T)ax.eRB[i]; k.eRBy[i] = (T)ay.eRB[i];
+        k.lLBx[i] = (T)ax.lLB[i]; k.lLBy[i] = (T)ay.lLB[i];
         k.w[i] = (T)g.t.w[i];
     }
     k.ihx = (T)(1.0 / g.hx);
@@ -384,6 +388,9 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
         return fail(DG_E_INVAL, "rtol must be > 0 and max_iter >= 0");
     if (o.precond != DG_PRECOND_NONE && o.precond != DG_PRECOND_FD)
         return fail(DG_E_INVAL, "unknown preconditioner %d", o.precond);
+    if ((g->geom.bcx || g->geom.bcy) &&
+        (o.precond != DG_PRECOND_NONE || o.precision != DG_PREC_FP64))
+        return periodic_only("the preconditioned and the mixed-precision solve");
     if (o.precond == DG_PRECOND_FD) {
         if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_MIXED)
             return fail(DG_E_INVAL, "unknown precision %d", o.precision);
@@ -405,7 +412,8 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
 namespace dgk {
 int periodic_only(const char* what) {
     return fail(DG_E_UNSUPPORTED, "%s is implemented for periodic grids only "
-                "(Dirichlet grids support the bracket)", what);
+                "(Dirichlet grids support the bracket, the Laplacian, the plain FP64 "
+                "CG and time stepping)", what);
 }
 
 int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,
@@ -455,7 +463,7 @@ size_t dg_field_elems(const dg_grid* g) { return g ? g->elems : 0; }
 int dg_grid_tables(const dg_grid* g, double* out, int len) {
     if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
     const int n = g->n;
-    const int need = 2 * n + 3 * (n * n + 4 * n);
+    const int need = 2 * n + (n * n + 4 * n) + 2 * (2 * n * n + 6 * n);
     if (len < need) return fail(DG_E_INVAL, "need %d doubles", need);
     int o = 0;
     auto put = [&](const double* a, int m) { for (int i = 0; i < m; ++i) out[o++] = a[i]; };
@@ -466,6 +474,7 @@ int dg_grid_tables(const dg_grid* g, double* out, int len) {
     ldg_axis(g->t, g->hy, g->geom.bcy == 0, &ay);
     for (const AxisLdg* a : {&ax, &ay}) {
         put(a->L0, n * n); put(a->eR, n); put(g->t.lR, n); put(g->t.eL, n); put(a->lL, n);
+        put(a->L0B, n * n); put(a->eRB, n); put(a->lLB, n);
     }
     return o;
 }
@@ -501,6 +510,8 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
     *out = nullptr;
     if (!valid_mode(mode)) return fail(DG_E_INVAL, "bad mode %d", mode);
+    if ((mode & DG_WS_FD) && (g->geom.bcx || g->geom.bcy))
+        return periodic_only("the preconditioner");
     dg_workspace* ws = new (std::nothrow) dg_workspace;
     if (!ws) return fail(DG_E_NOMEM, "host allocation failed");
     std::memset(ws, 0, sizeof *ws);
@@ -613,7 +624,6 @@ int dg_bracket_form(const dg_grid* g, const double* f, const double* gg,
 
 int dg_laplace_apply(const dg_grid* g, const double* f, double* out, void* stream) {
     if (!g || !f || !out) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("the LDG Laplacian");
     if (ranges_overlap(out, f, g->elems * sizeof(double)))
         return fail(DG_E_ALIAS, "out aliases f");
     hipError_t e = launch_laplace(g->geom, g->k64, f, out, as_stream(stream));
@@ -659,7 +669,6 @@ int dg_cg_solve_poisson(const dg_grid* g, const double* omega, double* psi,
                         const dg_cg_opts* opts, dg_cg_stats* st, dg_workspace* ws,
                         void* stream) {
     if (!g || !omega || !psi) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("the Poisson solve");
     int rc = check_ws(g, ws);
     if (rc != DG_OK) return rc;
     const size_t B = g->elems * sizeof(double);
@@ -714,7 +723,6 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
                const dg_step_opts* opts, dg_step_stats* stats, dg_workspace* ws,
                void* stream) {
     if (!g || !omega || !st || !opts) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("time stepping");
     int rc = check_ws(g, ws);
     if (rc != DG_OK) return rc;
     if (st->n != g->n || st->nx != g->nx || st->ny != g->ny)

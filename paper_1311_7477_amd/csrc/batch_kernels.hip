@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* inst,
                                                          ItemList list) {
     DG_FOR_ITEMS(list) {
         cg_mean_body<N>(item_.b, B.nb_rows, B.rows, B.k, B.w_in, B.pa, B.pb,
-                        B.ca, B.cb, B.area, B.tol2, B.max_iter, B.sc,
+                        B.ca, B.cb, B.area, B.tol2, B.max_iter, 0, B.sc,
                         B.counters + kCntMean, B.partials);
         __syncthreads();
     }

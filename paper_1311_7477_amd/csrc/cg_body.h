@@ -35,6 +35,8 @@ struct CellCtx {
     bool active;                   // this lane's cell lies in the grid
     bool xin_r, xin_l;             // x neighbour held by lane +-1
     bool yin_u, yin_d;             // y neighbour row held by wave +-1 (uniform)
+    // homogeneous Dirichlet axes: first / second / last cell along x and y
+    bool lo_x, sec_x, hi_x, lo_y, sec_y, hi_y;
     CellRef self, r, l, u, d;
 };
 
@@ -66,6 +68,12 @@ __device__ __forceinline__ CellCtx make_cell_ctx(const Geom& g, int tilesX,
     c.xin_l = c.lane > 0;
     c.yin_u = c.wave + 1 < WV && cy + 1 < g.ny;
     c.yin_d = c.wave > 0;
+    c.lo_x = g.bcx && cx == 0;
+    c.sec_x = g.bcx && cx == 1;
+    c.hi_x = g.bcx && cx == g.nx - 1;
+    c.lo_y = g.bcy && cy == 0;
+    c.sec_y = g.bcy && cy == 1;
+    c.hi_y = g.bcy && cy == g.ny - 1;
     const int G = tilesX;
     c.self = cell_ref<N>(g, G, cxa, cya);
     c.r = cell_ref<N>(g, G, cxr, cya);
@@ -137,8 +145,13 @@ struct YFaces {
 
 // Lap_h u for this lane's cell.  `src(ref, out)` evaluates the field on a
 // halo cell; the own cell's values are passed in u.  Every thread of the
-// block must call it (one barrier).
-template <int N, int WV, class T, class Src>
+// block must call it (one barrier).  DIR: the homogeneous Dirichlet closure
+// on the axes the grid marks (the last cell drops its outer coupling, the
+// first cell uses L0B / eRB and drops its outer coupling, and it is seen by
+// the second cell through lLB); the periodic kernels do not carry it.
+// ISO: square cells on two periodic axes, whose x and y blocks coincide --
+// the y operator reads the x tables (half the constants held in registers).
+template <int N, int WV, bool DIR = false, bool ISO = false, class T, class Src>
 __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
                                          const Src& src, const T (&u)[N * N],
                                          YFaces<N, T, WV>& lds, T (&out)[N * N]) {
@@ -154,8 +167,9 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     if (c.active && !c.yin_d) {
         T h[N * N];
         src(c.d, h);
+        const T* lf = (DIR && c.sec_y) ? k.lLBy : (ISO ? k.lLx : k.lLy);
 #pragma unroll
-        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, k.lLy);
+        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, lf);
     }
     if (c.active && !c.xin_r) {
         T h[N * N];
@@ -166,23 +180,30 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     if (c.active && !c.xin_l) {
         T h[N * N];
         src(c.l, h);
+        const T* lf = (DIR && c.sec_x) ? k.lLBx : k.lLx;
 #pragma unroll
-        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lLx);
+        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, lf);
     }
     // publish this cell's y face scalars
+    const T* lfy = (DIR && c.lo_y) ? k.lLBy : (ISO ? k.lLx : k.lLy);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         lds.v[((c.wave * 2 + 0) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lR);
-        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lLy);
+        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, lfy);
     }
     // x face scalars from the neighbouring lanes
+    const T* lfx = (DIR && c.lo_x) ? k.lLBx : k.lLx;
     T fR[N], fL[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const T a = __shfl(xdot<N>(u, j, k.lR), c.lane + 1);
-        const T b = __shfl(xdot<N>(u, j, k.lLx), c.lane - 1);
+        const T b = __shfl(xdot<N>(u, j, lfx), c.lane - 1);
         fR[j] = c.xin_r ? a : hR[j];
         fL[j] = c.xin_l ? b : hL[j];
+        if (DIR) {
+            if (c.hi_x) fR[j] = 0;
+            if (c.lo_x) fL[j] = 0;
+        }
     }
     __syncthreads();
     T fU[N], fD[N];
@@ -190,17 +211,25 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     for (int i = 0; i < N; ++i) {
         fU[i] = c.yin_u ? lds.v[(((c.wave + 1) * 2 + 0) * N + i) * 64 + c.lane] : hU[i];
         fD[i] = c.yin_d ? lds.v[(((c.wave - 1) * 2 + 1) * N + i) * 64 + c.lane] : hD[i];
+        if (DIR) {
+            if (c.hi_y) fU[i] = 0;
+            if (c.lo_y) fD[i] = 0;
+        }
     }
+    const T* L0x = (DIR && c.lo_x) ? k.L0Bx : k.L0x;
+    const T* L0y = (DIR && c.lo_y) ? k.L0By : (ISO ? k.L0x : k.L0y);
+    const T* eRx = (DIR && c.lo_x) ? k.eRBx : k.eRx;
+    const T* eRy = (DIR && c.lo_y) ? k.eRBy : (ISO ? k.eRx : k.eRy);
 #pragma unroll
     for (int j = 0; j < N; ++j)
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T lx = fmx(k.eRx[i], fR[j], k.eL[i] * fL[j]);
-            T ly = fmx(k.eRy[j], fU[i], k.eL[j] * fD[i]);
+            T lx = fmx(eRx[i], fR[j], k.eL[i] * fL[j]);
+            T ly = fmx(eRy[j], fU[i], k.eL[j] * fD[i]);
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                lx = fmx(k.L0x[i * N + m], u[j * N + m], lx);
-                ly = fmx(k.L0y[j * N + m], u[m * N + i], ly);
+                lx = fmx(L0x[i * N + m], u[j * N + m], lx);
+                ly = fmx(L0y[j * N + m], u[m * N + i], ly);
             }
             out[j * N + i] = fmx(lx, k.ihx2, ly * k.ihy2);
         }
@@ -294,7 +323,7 @@ __device__ __forceinline__ void zero_cell(T (&u)[N * N]) {
 }
 
 // out = Lap_h u (canonical layout in and out)
-template <int N, int WV>
+template <int N, int WV, bool DIR = false, bool ISO = false>
 __device__ __forceinline__ void laplace_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ u, double* __restrict__ out,
@@ -304,13 +333,13 @@ __device__ __forceinline__ void laplace_body(
     double v[N * N], lap[N * N];
     if (c.active) src(c.self, v);
     else zero_cell<N>(v);
-    lap_cell<N, WV>(c, k, src, v, lds, lap);
+    lap_cell<N, WV, DIR, ISO>(c, k, src, v, lds, lap);
     if (c.active) st_canon<N>(out, c.self, lap);
 }
 
 // CG setup (stencil part): x0 = guess - mean(guess) (to L64);
 // r0 = (omega - mean(omega)) + Lap_h x0 (to L64); partials <r0,r0>_W, <b,b>_W.
-template <int N, int WV>
+template <int N, int WV, bool DIR = false, bool ISO = false>
 __device__ __forceinline__ void cg_init_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ omega, const double* __restrict__ pa,
@@ -324,7 +353,7 @@ __device__ __forceinline__ void cg_init_body(
     double x0[N * N], lap[N * N];
     if (c.active) src(c.self, x0);
     else zero_cell<N>(x0);
-    lap_cell<N, WV>(c, k, src, x0, lds, lap);
+    lap_cell<N, WV, DIR, ISO>(c, k, src, x0, lds, lap);
     double part[2] = {0.0, 0.0};
     if (c.active) {
         double b[N * N];
@@ -369,7 +398,7 @@ __device__ __forceinline__ void cg_init_body(
 //   alpha_k = <r,r>_W / <p_k, q>_W.
 // p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
 // neighbouring tiles while p_k is written.  q is applied to p_k as stored.
-template <int N, class S, int WV>
+template <int N, class S, int WV, bool DIR = false, bool ISO = false>
 __device__ __forceinline__ void cg_dir_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const S* __restrict__ r, S* p0, S* p1, double* __restrict__ x,
@@ -406,7 +435,7 @@ __device__ __forceinline__ void cg_dir_body(
     } else {
         zero_cell<N>(p);
     }
-    lap_cell<N, WV>(c, k, src, p, lds, q);
+    lap_cell<N, WV, DIR, ISO>(c, k, src, p, lds, q);
     constexpr int NV = kStoredLow<S> ? 2 : 1;
     double part[NV];
 #pragma unroll
@@ -436,7 +465,7 @@ __device__ __forceinline__ void cg_dir_body(
 
 // CG iteration, second half: q = A p_k; r -= alpha q; beta = <r,r>new/<r,r>;
 // convergence test ||r||_W^2 <= tol^2 ||b||_W^2 on r as stored.
-template <int N, class S, int WV>
+template <int N, class S, int WV, bool DIR = false, bool ISO = false>
 __device__ __forceinline__ void cg_res_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k, const S* p0,
     const S* p1, S* __restrict__ r, CgScalars* sc, unsigned* counter,
@@ -453,7 +482,7 @@ __device__ __forceinline__ void cg_res_body(
     } else {
         zero_cell<N>(pv);
     }
-    lap_cell<N, WV>(c, k, src, pv, lds, q);   // q = Lap p = -A p
+    lap_cell<N, WV, DIR, ISO>(c, k, src, pv, lds, q);   // q = Lap p = -A p
     double part[1] = {0.0};
     if (c.active) {
 #pragma unroll
@@ -522,7 +551,7 @@ struct SrcMixedX {
 
 constexpr double kReplaceDrop2 = 1e-2;
 
-template <int N, int WV>
+template <int N, int WV, bool ISO = false>
 __device__ __forceinline__ void mixed_replace_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
     const double* __restrict__ omega, const double* __restrict__ x,
@@ -538,7 +567,7 @@ __device__ __forceinline__ void mixed_replace_body(
     double v[N * N], lap[N * N];
     if (c.active) src(c.self, v);
     else zero_cell<N>(v);
-    lap_cell<N, WV>(c, k, src, v, lds, lap);
+    lap_cell<N, WV, false, ISO>(c, k, src, v, lds, lap);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.active) {
         double w[N * N], rd[N * N], pv[N * N];

@@ -4,20 +4,22 @@
 // 16); block b processes tile xcd_tile(b).
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "cg_body.h"
 #include "dg_launch.h"
 
 namespace dgk {
 
-template <int N, int WV>
+template <int N, int WV, bool DIR, bool ISO>
 __global__ __launch_bounds__(64 * WV) void k_laplace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ u, double* __restrict__ out) {
     __shared__ YFaces<N, double, WV> lds;
-    laplace_body<N, WV>(blockIdx.x, g, tilesX, nblocks, k, u, out, lds);
+    laplace_body<N, WV, DIR, ISO>(blockIdx.x, g, tilesX, nblocks, k, u, out, lds);
 }
 
-template <int N, int WV>
+template <int N, int WV, bool DIR, bool ISO>
 __global__ __launch_bounds__(64 * WV) void k_cg_init(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ omega, const double* __restrict__ pa,
@@ -25,37 +27,37 @@ __global__ __launch_bounds__(64 * WV) void k_cg_init(
     double* __restrict__ x, double* __restrict__ r, CgScalars* sc,
     unsigned* counter, double* partials) {
     __shared__ YFaces<N, double, WV> lds;
-    cg_init_body<N, WV>(blockIdx.x, g, tilesX, nblocks, k, omega, pa, pb, ca, cb, x,
-                    r, sc, counter, partials, lds);
+    cg_init_body<N, WV, DIR, ISO>(blockIdx.x, g, tilesX, nblocks, k, omega, pa, pb, ca, cb, x,
+                             r, sc, counter, partials, lds);
 }
 
-template <int N, class S, int WV>
+template <int N, class S, int WV, bool DIR, bool ISO>
 __global__ __launch_bounds__(64 * WV) void k_cg_dir(
     Geom g, int tilesX, int nblocks, OpConst<double> k, const S* __restrict__ r,
     S* p0, S* p1, double* __restrict__ x, CgScalars* sc, unsigned* counter,
     double* partials) {
     __shared__ YFaces<N, double, WV> lds;
-    cg_dir_body<N, S, WV>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
-                      counter, partials, lds);
+    cg_dir_body<N, S, WV, DIR, ISO>(blockIdx.x, g, tilesX, nblocks, k, r, p0, p1, x, sc,
+                               counter, partials, lds);
 }
 
-template <int N, class S, int WV>
+template <int N, class S, int WV, bool DIR, bool ISO>
 __global__ __launch_bounds__(64 * WV) void k_cg_res(
     Geom g, int tilesX, int nblocks, OpConst<double> k, const S* p0, const S* p1,
     S* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
     __shared__ YFaces<N, double, WV> lds;
-    cg_res_body<N, S, WV>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
-                      partials, lds);
+    cg_res_body<N, S, WV, DIR, ISO>(blockIdx.x, g, tilesX, nblocks, k, p0, p1, r, sc, counter,
+                               partials, lds);
 }
 
-template <int N, int WV>
+template <int N, int WV, bool ISO>
 __global__ __launch_bounds__(64 * WV) void k_mixed_replace(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ omega, const double* __restrict__ x,
     const float* __restrict__ q0, const float* __restrict__ q1,
     float* __restrict__ r32, CgScalars* sc, unsigned* counter, double* partials) {
     __shared__ YFaces<N, double, WV> lds;
-    mixed_replace_body<N, WV>(blockIdx.x, g, tilesX, nblocks, k, omega, x, q0, q1, r32,
+    mixed_replace_body<N, WV, ISO>(blockIdx.x, g, tilesX, nblocks, k, omega, x, q0, q1, r32,
                           sc, counter, partials, lds);
 }
 
@@ -64,12 +66,33 @@ __global__ __launch_bounds__(64 * WV) void k_mixed_replace(
 // ---------------------------------------------------------------------------
 int cell_blocks(const Geom& g) { return CellLaunch(g).nblocks; }
 
+// A grid with a homogeneous Dirichlet axis runs the DIR variants, built for
+// 64 x 8 cell tiles only; a periodic grid of square cells the ISO variants
+// (identical x and y blocks).
+bool dirichlet(const Geom& g) { return g.bcx || g.bcy; }
+bool iso(const Geom& g, const OpConst<double>& k) { return !dirichlet(g) && k.ihx == k.ihy; }
+
 hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,
                           const double* u, double* out, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_laplace<NN, WW>), dim3(L.nblocks),
-                                          dim3(64 * WW), 0, s, g, L.tilesX,
-                                          L.nblocks, k, u, out));
+    if (dirichlet(g)) {
+        if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_laplace<NN, kDirichletCellWaves, true, false>),
+                                              dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
+                                              0, s, g, L.tilesX, L.nblocks, k, u, out));
+        return hipGetLastError();
+    }
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_laplace<NN, WW, false, true>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, u, out));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_laplace<NN, WW, false, false>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, u, out));
+    }
     return hipGetLastError();
 }
 
@@ -78,10 +101,28 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                           const double* pb, double ca, double cb, double* x,
                           double* r, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_init<NN, WW>), dim3(L.nblocks),
-                                          dim3(64 * WW), 0, s, g, L.tilesX,
-                                          L.nblocks, k, omega, pa, pb, ca, cb, x, r,
-                                          d.sc, d.counters + kCntInit, d.partials));
+    if (dirichlet(g)) {
+        if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN, kDirichletCellWaves, true, false>),
+                                              dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
+                                              0, s, g, L.tilesX, L.nblocks, k, omega, pa, pb,
+                                              ca, cb, x, r, d.sc, d.counters + kCntInit,
+                                              d.partials));
+        return hipGetLastError();
+    }
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_init<NN, WW, false, true>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, omega, pa, pb, ca, cb, x, r,
+                                              d.sc, d.counters + kCntInit, d.partials));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_init<NN, WW, false, false>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, omega, pa, pb, ca, cb, x, r,
+                                              d.sc, d.counters + kCntInit, d.partials));
+    }
     return hipGetLastError();
 }
 
@@ -89,10 +130,31 @@ template <class S>
 hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* r, S* p0,
                          S* p1, CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_dir<NN, S, WW>), dim3(L.nblocks),
-                                          dim3(64 * WW), 0, s, g, L.tilesX,
-                                          L.nblocks, k, r, p0, p1, x, sc,
-                                          d.counters + kCntDir, d.partials));
+    if (dirichlet(g)) {
+        if constexpr (std::is_same<S, double>::value) {
+            if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
+            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S, kDirichletCellWaves, true, false>),
+                                                  dim3(L.nblocks),
+                                                  dim3(64 * kDirichletCellWaves), 0, s, g,
+                                                  L.tilesX, L.nblocks, k, r, p0, p1, x, sc,
+                                                  d.counters + kCntDir, d.partials));
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_dir<NN, S, WW, false, true>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, r, p0, p1, x, sc,
+                                              d.counters + kCntDir, d.partials));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_dir<NN, S, WW, false, false>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, r, p0, p1, x, sc,
+                                              d.counters + kCntDir, d.partials));
+    }
     return hipGetLastError();
 }
 
@@ -100,10 +162,31 @@ template <class S>
 hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S* p1,
                          CgScalars* sc, const DevScratch& d, hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_res<NN, S, WW>), dim3(L.nblocks),
-                                          dim3(64 * WW), 0, s, g, L.tilesX,
-                                          L.nblocks, k, p0, p1, r, sc,
-                                          d.counters + kCntRes, d.partials));
+    if (dirichlet(g)) {
+        if constexpr (std::is_same<S, double>::value) {
+            if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
+            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S, kDirichletCellWaves, true, false>),
+                                                  dim3(L.nblocks),
+                                                  dim3(64 * kDirichletCellWaves), 0, s, g,
+                                                  L.tilesX, L.nblocks, k, p0, p1, r, sc,
+                                                  d.counters + kCntRes, d.partials));
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_res<NN, S, WW, false, true>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, p0, p1, r, sc,
+                                              d.counters + kCntRes, d.partials));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_res<NN, S, WW, false, false>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, p0, p1, r, sc,
+                                              d.counters + kCntRes, d.partials));
+    }
     return hipGetLastError();
 }
 
@@ -115,11 +198,22 @@ hipError_t launch_cg_dir_timed(const Geom& g, const OpConst<double>& k, double* 
                                S* p0, S* p1, CgScalars* sc, const DevScratch& d,
                                hipStream_t s, hipEvent_t start, hipEvent_t stop) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_dir<NN, S, WW>), dim3(L.nblocks),
-                                                    dim3(64 * WW), 0, s, start, stop, 0, g,
-                                                    L.tilesX, L.nblocks, k, (const S*)r, p0,
-                                                    p1, x, sc, d.counters + kCntDir,
-                                                    d.partials));
+    if (dirichlet(g)) return hipErrorInvalidValue;
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_dir<NN, S, WW, false, true>),
+                                                        dim3(L.nblocks),
+                                                        dim3(64 * WW), 0, s, start, stop, 0, g,
+                                                        L.tilesX, L.nblocks, k, (const S*)r, p0,
+                                                        p1, x, sc, d.counters + kCntDir,
+                                                        d.partials));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_dir<NN, S, WW, false, false>),
+                                                        dim3(L.nblocks),
+                                                        dim3(64 * WW), 0, s, start, stop, 0, g,
+                                                        L.tilesX, L.nblocks, k, (const S*)r, p0,
+                                                        p1, x, sc, d.counters + kCntDir,
+                                                        d.partials));
+    }
     return hipGetLastError();
 }
 
@@ -128,11 +222,22 @@ hipError_t launch_cg_res_timed(const Geom& g, const OpConst<double>& k, S* r, S*
                                CgScalars* sc, const DevScratch& d, hipStream_t s,
                                hipEvent_t start, hipEvent_t stop) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_res<NN, S, WW>), dim3(L.nblocks),
-                                                    dim3(64 * WW), 0, s, start, stop, 0, g,
-                                                    L.tilesX, L.nblocks, k, (const S*)p0,
-                                                    (const S*)p1, r, sc, d.counters + kCntRes,
-                                                    d.partials));
+    if (dirichlet(g)) return hipErrorInvalidValue;
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_res<NN, S, WW, false, true>),
+                                                        dim3(L.nblocks),
+                                                        dim3(64 * WW), 0, s, start, stop, 0, g,
+                                                        L.tilesX, L.nblocks, k, (const S*)p0,
+                                                        (const S*)p1, r, sc, d.counters + kCntRes,
+                                                        d.partials));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_res<NN, S, WW, false, false>),
+                                                        dim3(L.nblocks),
+                                                        dim3(64 * WW), 0, s, start, stop, 0, g,
+                                                        L.tilesX, L.nblocks, k, (const S*)p0,
+                                                        (const S*)p1, r, sc, d.counters + kCntRes,
+                                                        d.partials));
+    }
     return hipGetLastError();
 }
 template hipError_t launch_cg_dir_timed<double>(const Geom&, const OpConst<double>&, double*,
@@ -172,10 +277,20 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
                                 const float* q1, float* r32, const DevScratch& d,
                                 hipStream_t s) {
     CellLaunch L(g);
-    DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_mixed_replace<NN, WW>), dim3(L.nblocks),
-                                          dim3(64 * WW), 0, s, g, L.tilesX,
-                                          L.nblocks, k, omega, x, q0, q1, r32,
-                                          d.sc, d.counters + kCntDot, d.partials));
+    if (dirichlet(g)) return hipErrorInvalidValue;
+    if (iso(g, k)) {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_mixed_replace<NN, WW, true>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, omega, x, q0, q1, r32,
+                                              d.sc, d.counters + kCntDot, d.partials));
+    } else {
+        DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_mixed_replace<NN, WW, false>),
+                                                     dim3(L.nblocks),
+                                              dim3(64 * WW), 0, s, g, L.tilesX,
+                                              L.nblocks, k, omega, x, q0, q1, r32,
+                                              d.sc, d.counters + kCntDot, d.partials));
+    }
     return hipGetLastError();
 }
 

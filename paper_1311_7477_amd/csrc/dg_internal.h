@@ -25,6 +25,10 @@ struct HostTables {
     double C0[kMaxN * kMaxN], cR[kMaxN], sR[kMaxN], cL[kMaxN], sL[kMaxN];
     double L0[kMaxN * kMaxN], eR[kMaxN], lR[kMaxN], eL[kMaxN], lL[kMaxN];
     double tR[kMaxN], tL[kMaxN], pR[kMaxN], pL[kMaxN];
+    // first cell of a homogeneous Dirichlet axis (u-hat = 0 and q-hat = the
+    // inside trace on its boundary face): self block and right coupling, and
+    // the functional lLB through which the second cell sees it
+    double L0B[kMaxN * kMaxN], eRB[kMaxN], lLB[kMaxN];
 };
 
 // Builds the tables for n in [1, 5]; returns false on bad n.
@@ -39,8 +43,14 @@ bool build_tables(int n, HostTables* t);
 //     lL' = lL - C11 h tR.
 // C11 = ldg_penalty(n, periodic): 1 in the units of the domain, 0 for n = 1
 // on a periodic axis (the plain finite-difference Laplacian there).
+// On a homogeneous Dirichlet axis the last cell drops its right coupling
+// (and keeps L0', its boundary face adds the same self penalty an inside
+// face would), the first cell drops its left coupling and uses
+//     L0B' = L0B - C11 h (pR tR^T + pL tL^T),  eRB' = eRB + C11 h pR,
+// and the second cell couples to the first through lLB' = lLB - C11 h tR.
 struct AxisLdg {
     double L0[kMaxN * kMaxN], eR[kMaxN], lL[kMaxN];
+    double L0B[kMaxN * kMaxN], eRB[kMaxN], lLB[kMaxN];
 };
 double ldg_penalty(int n, bool periodic);
 void ldg_axis(const HostTables& t, double h, bool periodic, AxisLdg* out);
@@ -53,6 +63,8 @@ struct OpConst {
     T C0[kMaxN * kMaxN], cR[kMaxN], sR[kMaxN], cL[kMaxN], sL[kMaxN];
     T L0x[kMaxN * kMaxN], L0y[kMaxN * kMaxN];
     T eRx[kMaxN], eRy[kMaxN], lLx[kMaxN], lLy[kMaxN], lR[kMaxN], eL[kMaxN];
+    T L0Bx[kMaxN * kMaxN], L0By[kMaxN * kMaxN], eRBx[kMaxN], eRBy[kMaxN];
+    T lLBx[kMaxN], lLBy[kMaxN];
     T w[kMaxN];
     T ihx, ihy, ihx2, ihy2;   // 1/hx, 1/hy, 1/hx^2, 1/hy^2
     double wq;                // hx * hy / 4: node weight = wq * w_i * w_j
@@ -62,13 +74,16 @@ struct OpConst {
 // bracket tiles of 8 rows (the tuner may pick 4 / 16 and 16).
 constexpr int kCellWavesDefault = 8;
 constexpr int kRowWavesDefault = 8;
+// the cell tile of grids with a homogeneous Dirichlet axis (the only one
+// their Laplacian / CG kernels are built for)
+constexpr int kDirichletCellWaves = 8;
 
 // Geometry of one launch, with the grid's tile shapes: cw waves (cell rows)
 // per cell-per-lane tile, rw waves per row-per-lane bracket tile.
 struct Geom {
     int n, nx, ny;
     int cw, rw;
-    int bcx, bcy;     // 1: homogeneous Dirichlet along x / y (bracket only)
+    int bcx, bcy;     // 1: homogeneous Dirichlet along x / y
 };
 
 // Bracket / right-hand-side kernel parameters:

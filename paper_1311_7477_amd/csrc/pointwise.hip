@@ -9,10 +9,10 @@ template <int N>
 __global__ __launch_bounds__(kPwThreads) void k_cg_mean(
     long rows, OpConst<double> k, const double* __restrict__ omega,
     const double* __restrict__ pa, const double* __restrict__ pb, double ca,
-    double cb, double area, double tol2, int max_iter, CgScalars* sc,
+    double cb, double area, double tol2, int max_iter, int dir, CgScalars* sc,
     unsigned* counter, double* partials) {
     cg_mean_body<N>(blockIdx.x, gridDim.x, rows, k, omega, pa, pb, ca, cb, area,
-                    tol2, max_iter, sc, counter, partials);
+                    tol2, max_iter, dir, sc, counter, partials);
 }
 
 template <int N, class P>
@@ -96,7 +96,8 @@ hipError_t launch_cg_mean(const Geom& g, const OpConst<double>& k,
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_mean<NN>), dim3(nb),
                                           dim3(kPwThreads), 0, s, rows, k, omega,
                                           pa, pb, ca, cb, area, tol2, max_iter,
-                                          d.sc, d.counters + kCntMean, d.partials));
+                                          (g.bcx || g.bcy) ? 1 : 0, d.sc,
+                                          d.counters + kCntMean, d.partials));
     return hipGetLastError();
 }
 
@@ -113,6 +114,7 @@ hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
                                           d.partials));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (g.bcx || g.bcy) return hipSuccess;   // definite operator: psi keeps its mean
     const long elems = cells * g.n * g.n;
     hipLaunchKernelGGL(k_sub_mean, dim3(pw_blocks(elems, pointwise_block_cap())),
                        dim3(kPwThreads), 0, s, elems, psi, d.sc);

@@ -20,10 +20,12 @@ __device__ __forceinline__ double wrow(const OpConst<T>& k, int j, const double 
 
 // Means of omega and of the guess ca psi_a + cb psi_b, and <omega, omega>_W;
 // the last block also initialises every CG scalar for the coming solve.
+// With a Dirichlet axis (dir != 0) -Lap_h is definite and nothing is
+// subtracted: the means the later kernels remove are stored as zero.
 template <int N>
 __device__ __forceinline__ void cg_mean_body(int b, int nb, long rows, const OpConst<double>& k, const double* __restrict__ omega,
     const double* __restrict__ pa, const double* __restrict__ pb, double ca,
-    double cb, double area, double tol2, int max_iter, CgScalars* sc,
+    double cb, double area, double tol2, int max_iter, int dir, CgScalars* sc,
     unsigned* counter, double* partials) {
     double part[3] = {0.0, 0.0, 0.0};
     for (long row = b * (long)kPwThreads + threadIdx.x; row < rows;
@@ -54,8 +56,8 @@ __device__ __forceinline__ void cg_mean_body(int b, int nb, long rows, const OpC
     double tot[3];
     if (reduce_last<3, kPwThreads>(part, partials, counter, nb, b, tot) &&
         threadIdx.x == 0) {
-        sc->mean_omega = tot[0] / area;
-        sc->mean_guess = tot[1] / area;
+        sc->mean_omega = dir ? 0.0 : tot[0] / area;
+        sc->mean_guess = dir ? 0.0 : tot[1] / area;
         sc->ww = tot[2];
         sc->zero_tol2 = 1e-28;   // (1e-14)^2: b below the mean-removal rounding
         sc->tol2 = tol2;

@@ -34,6 +34,7 @@ struct Ctx {
     bool active;      // lane holds a node row
     bool interior;    // lane's cell is inside the tile and the grid: stores
     bool at_l, at_r, at_d, at_u;   // cell on a Dirichlet boundary of the grid
+    bool sec_d;                    // second cell row above a Dirichlet y boundary
     long row;         // element index of this thread's row start
     int slot;         // wave * S + s (LDS cell slot)
 };
@@ -58,6 +59,7 @@ __device__ __forceinline__ Ctx<N, WAVES> make_ctx(const Geom& g, int tilesX,
     c.at_r = g.bcx && cx == g.nx - 1;
     c.at_d = g.bcy && cy == 0;
     c.at_u = g.bcy && cy == g.ny - 1;
+    c.sec_d = g.bcy && cy == 1;
     int gx = cx % g.nx;
     if (gx < 0) gx += g.nx;
     int gy = cy % g.ny;
@@ -145,6 +147,72 @@ __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
     }
 }
 
+// The LDG second derivative along x on this thread's row with the
+// homogeneous Dirichlet closure of the viscous term (u-hat = 0 and q-hat =
+// the inside trace on a boundary face, jump penalty against 0): the last
+// cell (at_hi) drops its right coupling; the first (at_lo) uses A0B / eRB,
+// drops its left coupling and gives its right neighbour tLB . u in place of
+// tL . u.
+template <int N, class T>
+__device__ __forceinline__ void row_ldg(const T (&u)[N], int lane, const T* A0, const T* eR,
+                                        const T* tR, const T* eL, const T* tL, const T* A0B,
+                                        const T* eRB, const T* tLB, T scale, T (&res)[N],
+                                        bool at_lo, bool at_hi) {
+    T dR = 0, dL = 0, dB = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        dR = fmx(tR[k], u[k], dR);
+        dL = fmx(tL[k], u[k], dL);
+        dB = fmx(tLB[k], u[k], dB);
+    }
+    const T nbR = __shfl(dR, lane + N);
+    const T nbL = __shfl(at_lo ? dB : dL, lane - N);
+    const T fromR = at_hi ? T(0) : nbR;
+    const T fromL = at_lo ? T(0) : nbL;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        T a = fmx(at_lo ? eRB[i] : eR[i], fromR, eL[i] * fromL);
+#pragma unroll
+        for (int k = 0; k < N; ++k) a = fmx(at_lo ? A0B[i * N + k] : A0[i * N + k], u[k], a);
+        res[i] = a * scale;
+    }
+}
+
+// The same along y (column j of this thread's cell from rows staged in LDS):
+// the top cell (at_u) drops its upper coupling, the bottom one (at_d) uses
+// A0B / eRB and drops its lower coupling, and the second row (sec_d) reads
+// the bottom cell through tLB.
+template <int N, int WAVES, class T>
+__device__ __forceinline__ void col_ldg(const T* lds, const Ctx<N, WAVES>& c, const T* A0,
+                                        const T* eR, const T* tR, const T* eL, const T* tL,
+                                        const T* A0B, const T* eRB, const T* tLB, T scale,
+                                        T (&res)[N]) {
+    using TL = Tile<N, WAVES>;
+    const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
+    const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
+    const T* c0 = lds + c.slot * TL::CS + c.j;
+    const T* cu = lds + up * TL::CS + c.j;
+    const T* cd = lds + dn * TL::CS + c.j;
+    const T* tl = c.sec_d ? tLB : tL;
+    T col[N];
+    T du = 0, dd = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        col[k] = c0[k * N];
+        du = fmx(tR[k], cu[k * N], du);
+        dd = fmx(tl[k], cd[k * N], dd);
+    }
+    if (c.at_u) du = 0;
+    if (c.at_d) dd = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        T a = fmx(c.at_d ? eRB[k] : eR[k], du, eL[k] * dd);
+#pragma unroll
+        for (int m = 0; m < N; ++m) a = fmx(c.at_d ? A0B[k * N + m] : A0[k * N + m], col[m], a);
+        res[k] = a * scale;
+    }
+}
+
 template <int N, int WAVES, class T>
 __device__ __forceinline__ void lds_put_row(T* lds, const Ctx<N, WAVES>& c,
                                             const T (&u)[N]) {
@@ -202,7 +270,10 @@ __device__ __forceinline__ void rhs_body(
     double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
     row_op<N, double, DIR>(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
     row_op<N, double, DIR>(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
-    if (VISC) row_op(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.ihx2, LxG);
+    if (VISC && !DIR) row_op(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.ihx2, LxG);
+    if (VISC && DIR)
+        row_ldg(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.L0Bx, k.eRBx, k.lLBx, k.ihx2,
+                LxG, c.at_l, c.at_r);
 
     lds_put_row(lA, c, F);
     lds_put_row(lB, c, G);
@@ -211,7 +282,9 @@ __device__ __forceinline__ void rhs_body(
         double cF[N], cG[N], cL[N];
         col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
         col_op<N, WAVES, double, DIR>(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
-        if (VISC) col_op(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.ihy2, cL);
+        if (VISC && !DIR) col_op(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.ihy2, cL);
+        if (VISC && DIR)
+            col_ldg(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.L0By, k.eRBy, k.lLBy, k.ihy2, cL);
         __syncthreads();
         lds_put_col(lA, c, cF);
         lds_put_col(lB, c, cG);

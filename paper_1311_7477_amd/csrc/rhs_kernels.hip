@@ -21,12 +21,14 @@ hipError_t launch_rhs(const Geom& g, const OpConst<double>& k, const double* f,
                       const double* gg, const double* wn, double* out,
                       const RhsParams& p, bool visc, hipStream_t s) {
     RhsArgs ra{p.c0, p.c1, p.c2, p.scale, p.D, p.dt, p.a, p.b, p.only_r};
-    if (visc && (g.bcx || g.bcy)) return hipErrorInvalidValue;
     DG_DISPATCH_NR(g.n, g.rw, {
         RowLaunch L(g);
-        // the viscous / stage path is periodic only; a Dirichlet axis takes
-        // the bracket-only kernel with the boundary faces compiled in
-        if (visc)
+        // a Dirichlet axis takes the variants with the boundary faces
+        // compiled in (the bracket's zero flux, the viscous term's LDG closure)
+        if (visc && (g.bcx || g.bcy))
+            hipLaunchKernelGGL((k_rhs<NN, WW, true, true>), dim3(L.nblocks), dim3(64 * WW), 0,
+                               s, g, L.tilesX, L.nblocks, k, f, gg, wn, out, ra);
+        else if (visc)
             hipLaunchKernelGGL((k_rhs<NN, WW, true, false>), dim3(L.nblocks), dim3(64 * WW), 0,
                                s, g, L.tilesX, L.nblocks, k, f, gg, wn, out, ra);
         else if (g.bcx || g.bcy)

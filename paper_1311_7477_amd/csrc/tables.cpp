@@ -148,6 +148,26 @@ bool build_tables(int n, HostTables* t) {
         t->pR[i] = BTr[i];
         t->pL[i] = BTl[i];
     }
+    // first cell of a Dirichlet axis: Df with u-hat = 0 on the left face,
+    // F0' = F0 + (B T l) trL^T; Db with q-hat = its own left trace there and
+    // no left neighbour, G0' = G0 - (B T l) trL^T.  (Db Df u)_0 = G0' F0' u_0
+    // + G0' fp (trL . u_1).
+    double F0b[kMaxN * kMaxN], G0b[kMaxN * kMaxN];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            F0b[i * n + j] = F0[i * n + j] + BTl[i] * trL[j];
+            G0b[i * n + j] = G0[i * n + j] - BTl[i] * trL[j];
+        }
+    matmul(n, G0b, F0b, t->L0B);
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0, q = 0.0;
+        for (int k = 0; k < n; ++k) {
+            s += G0b[i * n + k] * BTr[k];
+            q += F0b[k * n + i] * trR[k];
+        }
+        t->eRB[i] = s;
+        t->lLB[i] = q;   // the second cell's Db reads trR . q_0, q_0 = F0' u_0 + ..
+    }
     (void)nn;
     return true;
 }
@@ -160,10 +180,15 @@ void ldg_axis(const HostTables& t, double h, bool periodic, AxisLdg* out) {
     // penalty on face m+1/2: -C11 W^-1 (-tR)^T [u], [u] = tL.u_{m+1} - tR.u_m;
     // on face m-1/2: -C11 W^-1 tL^T [u], [u] = tL.u_m - tR.u_{m-1}
     for (int i = 0; i < n; ++i) {
-        for (int j = 0; j < n; ++j)
-            out->L0[i * n + j] = t.L0[i * n + j] - c * (t.pR[i] * t.tR[j] + t.pL[i] * t.tL[j]);
+        for (int j = 0; j < n; ++j) {
+            const double pen = c * (t.pR[i] * t.tR[j] + t.pL[i] * t.tL[j]);
+            out->L0[i * n + j] = t.L0[i * n + j] - pen;
+            out->L0B[i * n + j] = t.L0B[i * n + j] - pen;
+        }
         out->eR[i] = t.eR[i] + c * t.pR[i];
+        out->eRB[i] = t.eRB[i] + c * t.pR[i];
         out->lL[i] = t.lL[i] - c * t.tR[i];
+        out->lLB[i] = t.lLB[i] - c * t.tR[i];
     }
 }
 

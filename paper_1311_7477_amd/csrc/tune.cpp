@@ -81,6 +81,9 @@ int dg_grid_set_tiles(dg_grid* g, int cw, int rw) {
     if (!g) return fail(DG_E_INVAL, "grid is NULL");
     if (!valid_cw(cw) || !valid_rw(rw))
         return fail(DG_E_INVAL, "tile heights must be cw in {4, 8, 16} and rw in {8, 16}");
+    if ((g->geom.bcx || g->geom.bcy) && cw != kDirichletCellWaves)
+        return fail(DG_E_INVAL, "a grid with a Dirichlet axis uses cell tiles of %d waves",
+                    kDirichletCellWaves);
     g->geom.cw = cw;
     g->geom.rw = rw;
     return DG_OK;

@@ -33,9 +33,9 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def _tables(n, N=3, x1=1.0, y1=1.0):
+def _tables(n, N=3, x1=1.0, y1=1.0, bc=0):
     from paper_1311_7477_amd import dg
-    t = np.array(dg.Grid(n, N, N, 0.0, x1, 0.0, y1).tables())
+    t = np.array(dg.Grid(n, N, N, 0.0, x1, 0.0, y1, bc_x=bc, bc_y=bc).tables())
     o = 0
 
     def take(m):
@@ -51,6 +51,9 @@ def _tables(n, N=3, x1=1.0, y1=1.0):
         d["L0" + ax] = take(n * n).reshape(n, n)
         for k in ("eR", "lR", "eL", "lL"):
             d[k + ax] = take(n)
+        d["L0B" + ax] = take(n * n).reshape(n, n)
+        d["eRB" + ax] = take(n)
+        d["lLB" + ax] = take(n)
     assert o == len(t)
     return d
 
@@ -89,6 +92,34 @@ def test_host_tables_reproduce_oracle_operators(n):
         np.testing.assert_allclose(Lp, ref, atol=1e-13 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("N", [1, 2, 6])
+def test_host_tables_reproduce_oracle_dirichlet_laplacian(n, N):
+    # homogeneous Dirichlet axis: interior blocks, the last cell without its
+    # right coupling, the first cell with L0B / eRB and no left coupling, the
+    # second one coupled to the first through lLB,
+    # against the oracle's operator built from the boundary fluxes and the
+    # jump operator with its two boundary faces
+    lx, ly = 1.3, 2.9
+    d = _tables(n, N, lx, ly, bc=1)
+    for ax, length in (("x", lx), ("y", ly)):
+        g = O.Grid1D(n, N, 0.0, length, "dirichlet")
+        M = np.zeros((N * n, N * n))
+        for m in range(N):
+            b = slice(m * n, (m + 1) * n)
+            first = m == 0
+            M[b, b] += d["L0B" + ax] if first else d["L0" + ax]
+            if m + 1 < N:
+                eR = d["eRB" + ax] if first else d["eR" + ax]
+                M[b, (m + 1) * n:(m + 2) * n] += np.outer(eR, d["lR" + ax])
+            if m > 0:
+                lL = d["lLB" + ax] if m == 1 else d["lL" + ax]
+                M[b, (m - 1) * n:m * n] += np.outer(d["eL" + ax], lL)
+        M /= g.h ** 2
+        ref = g.laplacian().toarray()
+        np.testing.assert_allclose(M, ref, atol=1e-13 * np.abs(ref).max())
+
+
 def test_grid_create_validation():
     from paper_1311_7477_amd import dg
     for bad in [dict(n=0), dict(n=6), dict(nx=0), dict(ny=-1), dict(x1=-1.0),
@@ -101,16 +132,17 @@ def test_grid_create_validation():
     with pytest.raises(dg.DgError) as ei:
         dg.Grid(2, 4, 4, bc_x=7)
     assert ei.value.code == dg.DG_E_INVAL
-    # a Dirichlet axis: the bracket only; host-side rejections need no GPU
+    # a Dirichlet axis: no preconditioner basis, no tuner, cell tiles of 8
+    # waves only; host-side rejections need no GPU
     d = dg.Grid(2, 4, 4, bc_x=dg.DG_BC_DIRICHLET)
-    L = dg.lib()
-    for rc in (L.dg_laplace_apply(d.handle, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), None),
-               L.dg_cg_solve_poisson(d.handle, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x9000),
-                                     None, None, None, None)):
-        assert rc == dg.DG_E_UNSUPPORTED
     with pytest.raises(dg.DgError) as ei:
         d.fd_basis(0)
     assert ei.value.code == dg.DG_E_UNSUPPORTED
+    with pytest.raises(dg.DgError) as ei:
+        d.set_tiles(16, 8)
+    assert ei.value.code == dg.DG_E_INVAL
+    d.set_tiles(8, 16)
+    assert d.tiles() == (8, 16)
 
 
 def test_workspace_bytes_and_field_size():
