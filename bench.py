@@ -300,6 +300,94 @@ def form_lamb(args):
                                              "t in [0, 0.01], PCG rtol 1e-14"}}), flush=True)
 
 
+# Table 3 of the paper: printed L2 errors at t = 2 (columns: D = 0 periodic,
+# D = 0 Dirichlet, D = 0.01 periodic, D = 0.01 Dirichlet), P = 1..4,
+# N = 16, 32, 64, 128.
+TABLE3_PRINTED = {
+    1: [(0.0, 4.00e-01, 2.63e-03, 3.79e-01), (0.0, 3.30e-01, 6.59e-04, 3.07e-01),
+        (0.0, 2.00e-01, 1.79e-04, 1.90e-01), (0.0, 1.10e-01, 4.48e-05, 1.00e-01)],
+    2: [(5.96e-02, 5.46e-02, 5.63e-02, 5.71e-02), (1.48e-02, 1.38e-02, 1.49e-02, 1.51e-02),
+        (3.74e-03, 3.60e-03, 3.83e-03, 3.87e-03), (9.44e-04, 9.20e-04, 9.74e-04, 9.80e-04)],
+    3: [(2.59e-03, 2.47e-03, 1.80e-03, 1.69e-03), (3.36e-04, 3.27e-04, 2.32e-04, 2.25e-04),
+        (4.34e-05, 4.28e-05, 2.95e-05, 2.91e-05), (5.51e-06, 5.47e-06, 3.73e-06, 3.70e-06)],
+    4: [(3.16e-05, 3.33e-05, 4.33e-05, 4.49e-05), (1.84e-06, 1.91e-06, 2.78e-06, 2.84e-06),
+        (1.11e-07, 1.13e-07, 1.76e-07, 1.78e-07), (6.79e-09, 6.84e-09, 1.11e-08, 1.12e-08)],
+}
+
+
+def _lap_max(dg, grid, ws_like, iters=80):
+    """Largest |eigenvalue| of Lap_h by power iteration on the device (a
+    lower estimate; the caller keeps a margin)."""
+    import torch
+    v = torch.randn(grid.shape, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(5))
+    lam = 0.0
+    for _ in range(iters):
+        u = dg.laplace_apply(grid, v)
+        lam = float(u.norm() / v.norm())
+        v = u / u.norm()
+    return lam
+
+
+def form_table3(args):
+    """Table 3 of the paper on the GPU: omega = 2 sin x sin y on [0, 2 pi]^2
+    (exact: 2 sin x sin y exp(-2 D t) for periodic and homogeneous Dirichlet
+    boundaries) integrated to t = 2 with the three-step Adams-Bashforth
+    method (SSP-RK3 start), dt = min(0.1 h / P, 0.3 / (D |lambda_max|));
+    L2 error against the exact solution at the Gauss nodes, for every entry
+    of the printed table.  Poisson solves: CG preconditioned by fast
+    diagonalisation on periodic grids, plain CG on Dirichlet grids (rtol
+    1e-12; the errors are those of the spatial discretisation)."""
+    import numpy as np
+    import torch
+    from numpy.polynomial.legendre import leggauss
+    from paper_1311_7477_amd import dg, inputs
+    rows, t_all = [], time.perf_counter()
+    Ns = (16, 32, 64, 128)
+    for P in (1, 2, 3, 4):
+        for i, N in enumerate(Ns):
+            for col, (D, bc) in enumerate(((0.0, 0), (0.0, 1), (0.01, 0), (0.01, 1))):
+                t0 = time.perf_counter()
+                grid = dg.Grid(P, N, N, bc_x=bc, bc_y=bc)
+                ws = dg.Workspace(grid, dg.DG_PREC_FP64 | (0 if bc else dg.DG_WS_FD))
+                X, Y = inputs.node_coords(P, N, N)
+                w0 = 2.0 * np.sin(X) * np.sin(Y)
+                h = 2.0 * math.pi / N
+                dt = 0.1 * h / P
+                if D > 0:
+                    dt = min(dt, 0.3 / (D * 1.25 * _lap_max(dg, grid, ws)))
+                steps = int(math.ceil(2.0 / dt))
+                dt = 2.0 / steps
+                opts = dg.cg_opts(rtol=1e-12,
+                                  precond=dg.DG_PRECOND_NONE if bc else dg.DG_PRECOND_FD)
+                ab, w = dg.AbState(grid, 3), torch.from_numpy(w0).cuda()
+                iters, t_print = 0, time.perf_counter()
+                for k in range(steps):
+                    r = dg.ab_step(grid, w, ab, ws, dt, D, opts)
+                    iters += sum(r.cg_iters)
+                    if time.perf_counter() - t_print > 30.0:
+                        t_print = time.perf_counter()
+                        print(f"[table3] P={P} N={N} D={D} bc={bc}: step {k + 1}/{steps}",
+                              file=sys.stderr, flush=True)
+                d = w.cpu().numpy() - w0 * math.exp(-2.0 * D * 2.0)
+                wg = 0.5 * h * leggauss(P)[1]           # Gauss weights of one cell
+                wq = (wg[:, None] * wg[None, :])[None, None]
+                err = math.sqrt(float(np.sum(wq * d * d)))
+                printed = TABLE3_PRINTED[P][i][col]
+                rows.append({"P": P, "N": N, "D": D, "bc": "dirichlet" if bc else "periodic",
+                             "error": err, "printed": printed,
+                             "ratio": err / printed if printed else None,
+                             "steps": steps, "cg_iters": iters,
+                             "seconds": time.perf_counter() - t0})
+                print(f"[table3] {rows[-1]}", file=sys.stderr, flush=True)
+    dev = [abs(r["ratio"] - 1.0) for r in rows
+           if r["ratio"] is not None and (r["P"] > 1 or r["bc"] == "dirichlet")]
+    print(json.dumps({"metric": "Table 3: L2 errors at t = 2 vs the printed ones",
+                      "rows": rows, "max_rel_deviation_P2to4_and_P1_dirichlet": max(dev),
+                      "seconds": time.perf_counter() - t_all, "dtype": "f64",
+                      "data": "analytic (2 sin x sin y)"}), flush=True)
+
+
 def form_tune(args):
     """Tile autotuner sweep: for n in {2,3,4,5} and N in {64, 256, 512, 1024},
     dg_grid_tune on a random-spectrum field; prints one line per case with
@@ -438,7 +526,8 @@ def main():
                     help="also run 3 plain 256 MiB device copies (torch copy_) whose "
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     ap.add_argument("--form", default="rhs",
-                    choices=["rhs", "batch", "mixed", "serve", "paper", "tune", "lamb"],
+                    choices=["rhs", "batch", "mixed", "serve", "paper", "tune", "lamb",
+                             "table3"],
                     help="rhs: the headline metric (default); the others measure "
                          "the batched, mixed-precision and served forms and the "
                          "paper's bracket-timing shape")
@@ -465,7 +554,8 @@ def main():
     torch.cuda.set_device(0)
     if args.form != "rhs":
         {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
-         "paper": form_paper, "tune": form_tune, "lamb": form_lamb}[args.form](args)
+         "paper": form_paper, "tune": form_tune, "lamb": form_lamb,
+         "table3": form_table3}[args.form](args)
         return
     n, N = args.n, args.N
     if args.copy_calibration:
