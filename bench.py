@@ -43,10 +43,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(F_bytes):
-    """HBM bytes per launch of the direction kernel from committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE counters, or None when they are missing or were
-    taken on a different kernel source."""
+def measured_traffic(F_bytes, cw):
+    """HBM bytes per launch of the direction kernel with cell tiles of cw
+    waves, from committed rocprofv3 FETCH_SIZE/WRITE_SIZE counters, or None
+    when they are missing or were taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -54,7 +54,7 @@ def measured_traffic(F_bytes):
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch_by_cw", {}).get(str(cw))
 
 
 def cpu_baseline(n, N, omega0, psi0, D, dt, iters_per_rhs):
@@ -618,7 +618,7 @@ def main():
     # write x, p  (5 fields)
     alg_bytes = 5 * F
     achieved = alg_bytes / (ms_dir * 1e-3) / 1e9
-    traffic = measured_traffic(F)
+    traffic = measured_traffic(F, tiles[0])
     srt = sorted(stage_ms)
 
     def pct(q):

@@ -25,7 +25,7 @@ namespace dgk {
             if (const BatchInst& B = inst[item_.inst]; B.active)
 
 template <int N>
-__global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* inst,
+__global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* __restrict__ inst,
                                                          ItemList list) {
     DG_FOR_ITEMS(list) {
         cg_mean_body<N>(item_.b, B.nb_rows, B.rows, B.k, B.w_in, B.pa, B.pb,
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* inst,
 }
 
 template <int N, int WV>
-__global__ __launch_bounds__(64 * WV) void kb_cg_init(const BatchInst* inst, ItemList list) {
+__global__ __launch_bounds__(64 * WV) void kb_cg_init(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_init_body<N, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k, B.w_in,
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(64 * WV) void kb_cg_init(const BatchInst* inst, Ite
 }
 
 template <int N, int WV>
-__global__ __launch_bounds__(64 * WV) void kb_cg_dir(const BatchInst* inst, ItemList list) {
+__global__ __launch_bounds__(64 * WV) void kb_cg_dir(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_dir_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64 * WV) void kb_cg_dir(const BatchInst* inst, Item
 }
 
 template <int N, int WV>
-__global__ __launch_bounds__(64 * WV) void kb_cg_res(const BatchInst* inst, ItemList list) {
+__global__ __launch_bounds__(64 * WV) void kb_cg_res(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_res_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(64 * WV) void kb_cg_res(const BatchInst* inst, Item
 }
 
 template <int N>
-__global__ __launch_bounds__(kPwThreads) void kb_cg_finish(const BatchInst* inst,
+__global__ __launch_bounds__(kPwThreads) void kb_cg_finish(const BatchInst* __restrict__ inst,
                                                            ItemList list) {
     DG_FOR_ITEMS(list) {
         cg_finish_body<N>(item_.b, B.nb_cells, B.g, B.k, B.x, B.p0, B.p1, B.psi,
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_finish(const BatchInst* inst
     }
 }
 
-__global__ __launch_bounds__(kPwThreads) void kb_sub_mean(const BatchInst* inst,
+__global__ __launch_bounds__(kPwThreads) void kb_sub_mean(const BatchInst* __restrict__ inst,
                                                           ItemList list) {
     DG_FOR_ITEMS(list) {
         sub_mean_body(item_.b, B.nb_elems, B.elems, B.psi, B.sc);
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_sub_mean(const BatchInst* inst,
 }
 
 template <int N, int W>
-__global__ __launch_bounds__(64 * W) void kb_rhs(const BatchInst* inst, ItemList list) {
+__global__ __launch_bounds__(64 * W) void kb_rhs(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ RhsLds<N, W, true> lds;
     DG_FOR_ITEMS(list) {
         rhs_body<N, W, true>(item_.b, B.g, B.row_tilesX, B.row_nblocks,
