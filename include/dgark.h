@@ -179,8 +179,8 @@ int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
  * DG_PREC_MIXED mode, plus (DG_WS_FD) the preconditioner's z vector, two
  * node-plane fields and per axis the factored eigenbasis in FP64 and FP32
  * (the N x N cell Fourier basis, 2 (N/2 + 1) mixing blocks of 2n x 2n and
- * n N eigenvalues; one set when the axes agree; rocBLAS keeps its own small
- * workspace on top).  This is the figure that admission control budgets.
+ * n N eigenvalues; one set when the axes agree; rocBLAS and, beyond 512
+ * cells on an axis, rocFFT keep their own work buffers on top).  This is the figure that admission control budgets.
  * mode = DG_PREC_FP64 or DG_PREC_MIXED, optionally | DG_WS_FD. */
 int  dg_workspace_bytes(const dg_grid* grid, int mode, size_t* bytes);
 /* Allocate a workspace on the current device (hipMalloc + pinned host
@@ -243,8 +243,9 @@ int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
  * a real W-orthonormal basis V with L V = V diag(lambda); then
  * z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T, the
  * constant mode dropped.  V is applied in factored form (the cell Fourier
- * transform as an FP64 matrix product, then 2n x 2n mixing per wave number),
- * 4 n^2 Nx Ny (Nx + Ny) flops per call.  r, z: canonical fields, z must not
+ * transform, then 2n x 2n mixing per wave number); the transform is an FP64
+ * matrix product (4 n^2 Nx Ny (Nx + Ny) flops per call) up to 512 cells per
+ * axis and a real FFT (rocFFT) beyond.  r, z: canonical fields, z must not
  * alias r.  ws must hold DG_WS_FD.  Asynchronous. */
 int  dg_precond_apply(const dg_grid* grid, const double* r, double* z,
                       dg_workspace* ws, void* stream);

@@ -12,12 +12,16 @@
 //   U1 --(x unmixing B_x, in place)
 //   U1 --(inverse x transform, batched)-->  U
 // The transforms cost 4 n^2 Nx Ny (Nx + Ny) flops in all, n times fewer
-// than dense products with V.  The same steps run in FP64 or, for the mixed-
-// precision PCG, in FP32 (factors rounded once at setup; the planes then take
-// the first half of the FP64 work fields).
+// than dense products with V.  Beyond 512 cells on an axis they run as real
+// FFTs along the cells instead (rocFFT; the mixing kernels then read and
+// write half spectra, fd_kernels.hip).  The same steps run in FP64 or, for
+// the mixed-precision PCG, in FP32 (factors rounded once at setup; the
+// fields then take the first half of the FP64 work fields).
 #include <rocblas/rocblas.h>
+#include <rocfft/rocfft.h>
 
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "abi_types.h"
@@ -33,6 +37,20 @@ bool same_axis(const dg_grid* g) { return g->nx == g->ny && g->hx == g->hy; }
 int blas_fail(rocblas_status st, const char* what) {
     return fail(DG_E_HIP, "%s: rocBLAS status %d (%s)", what, (int)st,
                 rocblas_status_to_string(st));
+}
+
+constexpr int kFdGemmMaxCells = 512;
+
+int fft_fail(rocfft_status st, const char* what) {
+    return fail(DG_E_HIP, "%s: rocFFT status %d", what, (int)st);
+}
+
+// Reals in one work field: the node planes, or the half spectra of the x or
+// of the y transform (N/2 + 1 complex values per transform).
+size_t field_reals(int n, int Nx, int Ny) {
+    const size_t nn = (size_t)n * n;
+    size_t a = nn * Nx * Ny, b = nn * Ny * 2 * (Nx / 2 + 1), c = nn * Nx * 2 * (Ny / 2 + 1);
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
 size_t axis_bytes(int N, int n) {
@@ -133,16 +151,131 @@ int apply_planes(const FdDevice* fd, hipStream_t s) {
     return DG_OK;
 }
 
+template <class T>
+int apply_fft(const FdDevice* fd, hipStream_t s) {
+    const int pr = sizeof(T) == sizeof(float) ? 1 : 0;
+    rocfft_execution_info info = (rocfft_execution_info)fd->fft_info;
+    rocfft_status st = rocfft_execution_info_set_stream(info, s);
+    if (st != rocfft_status_success) return fft_fail(st, "set stream");
+    const FdAxisDevice& X = fd->x;
+    const FdAxisDevice& Y = fd->y;
+    const FdFactorsDevice<T>& fx = X.get<T>();
+    const FdFactorsDevice<T>& fy = Y.get<T>();
+    const int n = fd->n, Nx = X.N, Ny = Y.N;
+    void* b0 = fd->img0;
+    void* b1 = fd->img1;
+    auto run = [&](int i, void* in, void* out) {
+        void* ib[1] = {in};
+        void* ob[1] = {out};
+        return rocfft_execute((rocfft_plan)fd->fft[pr][i], ib, ob, info);
+    };
+    // node planes U (b0) -> x spectra (b1) -> x-mixed real field U1 (b0)
+    st = run(0, b0, b1);
+    if (st != rocfft_status_success) return fft_fail(st, "x transform");
+    hipError_t e = launch_fft_mix_x_fwd<T>(n, Nx, Ny, X.K, X.cols, fx.mf, b1, (T*)b0, s);
+    if (e != hipSuccess) return hip_fail(e, "x mixing launch");
+    // U1 (b0) -> y spectra (b1), mixed, divided, unmixed in place -> U1 (b0)
+    st = run(1, b0, b1);
+    if (st != rocfft_status_success) return fft_fail(st, "y transform");
+    e = launch_fft_mix_y<T>(n, Nx, Ny, Y.K, Y.cols, fy.mf, fy.mi, fx.lam, fy.lam, X.zero,
+                            Y.zero, b1, s);
+    if (e != hipSuccess) return hip_fail(e, "y mixing launch");
+    st = run(2, b1, b0);
+    if (st != rocfft_status_success) return fft_fail(st, "inverse y transform");
+    // U1 (b0) -> x spectra (b1) -> node planes of z (b0)
+    e = launch_fft_mix_x_inv<T>(n, Nx, Ny, X.K, X.cols, fx.mi, (const T*)b0, b1, s);
+    if (e != hipSuccess) return hip_fail(e, "x unmixing launch");
+    st = run(3, b1, b0);
+    if (st != rocfft_status_success) return fft_fail(st, "inverse x transform");
+    return DG_OK;
+}
+
 }  // namespace
 
 size_t fd_bytes(const dg_grid* g) {
-    const size_t planes = 2 * (size_t)g->nx * g->ny * g->n * g->n * sizeof(double);
+    const size_t planes = 2 * field_reals(g->n, g->nx, g->ny) * sizeof(double);
     return planes + axis_bytes(g->nx, g->n) + (same_axis(g) ? 0 : axis_bytes(g->ny, g->n));
 }
+
+namespace {
+
+// One batched 1D real FFT along an axis of length L: `count` transforms of
+// contiguous real rows (distance L) whose half spectra are stored with
+// stride `spec_stride` between wave numbers and distance 1 between
+// transforms (the wave number becomes the slowest index).
+int make_plan(bool forward, bool fp32, size_t L, size_t count, size_t spec_stride,
+              rocfft_plan* out) {
+    rocfft_plan_description d = nullptr;
+    rocfft_status st = rocfft_plan_description_create(&d);
+    if (st != rocfft_status_success) return fft_fail(st, "plan description");
+    const size_t one = 1;
+    if (forward)
+        st = rocfft_plan_description_set_data_layout(
+            d, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved, nullptr, nullptr,
+            1, &one, L, 1, &spec_stride, 1);
+    else
+        st = rocfft_plan_description_set_data_layout(
+            d, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real, nullptr, nullptr,
+            1, &spec_stride, 1, 1, &one, L);
+    if (st == rocfft_status_success)
+        st = rocfft_plan_create(out, rocfft_placement_notinplace,
+                                forward ? rocfft_transform_type_real_forward
+                                        : rocfft_transform_type_real_inverse,
+                                fp32 ? rocfft_precision_single : rocfft_precision_double, 1, &L,
+                                count, d);
+    (void)rocfft_plan_description_destroy(d);
+    if (st != rocfft_status_success) return fft_fail(st, "plan create");
+    return DG_OK;
+}
+
+int make_fft(const dg_grid* g, FdDevice* fd) {
+    static std::once_flag once;
+    static rocfft_status setup = rocfft_status_success;
+    std::call_once(once, [] { setup = rocfft_setup(); });
+    if (setup != rocfft_status_success) return fft_fail(setup, "rocfft_setup");
+    const size_t n = g->n, Nx = g->nx, Ny = g->ny;
+    const size_t bx = Ny * n * n, by = n * n * Nx;    // transforms per axis
+    for (int pr = 0; pr < 2; ++pr) {
+        rocfft_plan plans[4] = {nullptr, nullptr, nullptr, nullptr};
+        int rc = make_plan(true, pr == 1, Nx, bx, bx, &plans[0]);
+        if (rc == DG_OK) rc = make_plan(true, pr == 1, Ny, by, by, &plans[1]);
+        if (rc == DG_OK) rc = make_plan(false, pr == 1, Ny, by, by, &plans[2]);
+        if (rc == DG_OK) rc = make_plan(false, pr == 1, Nx, bx, bx, &plans[3]);
+        for (int i = 0; i < 4; ++i) fd->fft[pr][i] = plans[i];
+        if (rc != DG_OK) return rc;
+        for (int i = 0; i < 4; ++i) {
+            size_t w = 0;
+            rocfft_status st = rocfft_plan_get_work_buffer_size(plans[i], &w);
+            if (st != rocfft_status_success) return fft_fail(st, "work buffer size");
+            if (w > fd->fft_work_bytes) fd->fft_work_bytes = w;
+        }
+    }
+    rocfft_execution_info info = nullptr;
+    rocfft_status st = rocfft_execution_info_create(&info);
+    if (st != rocfft_status_success) return fft_fail(st, "execution info");
+    fd->fft_info = info;
+    if (fd->fft_work_bytes &&
+        hipMalloc(&fd->fft_work, fd->fft_work_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DG_E_NOMEM, "FFT work buffer of %zu bytes", fd->fft_work_bytes);
+    }
+    if (fd->fft_work_bytes) {
+        st = rocfft_execution_info_set_work_buffer(info, fd->fft_work, fd->fft_work_bytes);
+        if (st != rocfft_status_success) return fft_fail(st, "work buffer");
+    }
+    return DG_OK;
+}
+
+}  // namespace
 
 void fd_destroy(FdDevice* fd) {
     if (!fd) return;
     if (fd->blas) (void)rocblas_destroy_handle((rocblas_handle)fd->blas);
+    for (auto& pr : fd->fft)
+        for (void* p : pr)
+            if (p) (void)rocfft_plan_destroy((rocfft_plan)p);
+    if (fd->fft_info) (void)rocfft_execution_info_destroy((rocfft_execution_info)fd->fft_info);
+    if (fd->fft_work) (void)hipFree(fd->fft_work);
     if (fd->img0) (void)hipFree(fd->img0);
     if (fd->img1) (void)hipFree(fd->img1);
     free_axis(&fd->x);
@@ -170,7 +303,7 @@ int fd_create(const dg_grid* g, FdDevice** out) {
     bool ok = upload_axis(fx, &fd->x);
     if (ok && fd->shared) fd->y = fd->x;
     else if (ok) ok = upload_axis(fy, &fd->y);
-    const size_t img = (size_t)g->nx * g->ny * g->n * g->n * sizeof(double);
+    const size_t img = field_reals(g->n, g->nx, g->ny) * sizeof(double);
     if (ok) ok = hipMalloc((void**)&fd->img0, img) == hipSuccess &&
                  hipMalloc((void**)&fd->img1, img) == hipSuccess;
     if (!ok) {
@@ -185,6 +318,16 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         return blas_fail(st, "rocblas_create_handle");
     }
     fd->blas = h;
+    // the cell transforms: FP64 GEMMs up to 512 cells per axis (at n = 4,
+    // 512^2 they beat rocFFT, whose real transforms with the wave number as
+    // the slowest output index run as a complex FFT plus two strided copies),
+    // real FFTs beyond (at n = 5, 1024^2 a preconditioned solve takes 6.0 ms
+    // against 9.6 ms with the O(N^3) products)
+    fd->use_fft = g->nx > kFdGemmMaxCells || g->ny > kFdGemmMaxCells;
+    if (fd->use_fft) {
+        const int rc = make_fft(g, fd);
+        if (rc != DG_OK) { fd_destroy(fd); return rc; }
+    }
     fd->bytes = fd_bytes(g);
     *out = fd;
     return DG_OK;
@@ -193,6 +336,7 @@ int fd_create(const dg_grid* g, FdDevice** out) {
 // img0 holds the node planes of r on entry and those of z = M r on exit
 // (FP32 planes when fp32).
 int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s) {
+    if (fd->use_fft) return fp32 ? apply_fft<float>(fd, s) : apply_fft<double>(fd, s);
     return fp32 ? apply_planes<float>(fd, s) : apply_planes<double>(fd, s);
 }
 

@@ -71,9 +71,18 @@ struct FdDevice {
     int n = 0;
     FdAxisDevice x, y;                         // y aliases x when `shared`
     bool shared = false;
-    double *img0 = nullptr, *img1 = nullptr;   // node-plane work fields (FP64,
-                                               // or FP32 in their first half)
+    double *img0 = nullptr, *img1 = nullptr;   // node-plane / half-spectrum work
+                                               // fields (FP64, or FP32 in their
+                                               // first half)
     void* blas = nullptr;                      // rocblas_handle
+    // real FFTs along the cells: plans [precision][x fwd, y fwd, y inv,
+    // x inv] (rocfft_plan, FP64 then FP32), one execution info, work buffer
+    void* fft[2][4] = {{nullptr, nullptr, nullptr, nullptr},
+                       {nullptr, nullptr, nullptr, nullptr}};
+    void* fft_info = nullptr;
+    void* fft_work = nullptr;
+    size_t fft_work_bytes = 0;
+    bool use_fft = true;
     size_t bytes = 0;
 };
 

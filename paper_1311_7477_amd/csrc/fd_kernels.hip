@@ -5,6 +5,8 @@
 // per-wave-number mixing of the x transform, the mixing + spectral scaling +
 // unmixing of the y transform, and the preconditioned dot product <r, z>_W
 // that closes the PCG step.
+#include <cmath>
+
 #include "cg_body.h"
 #include "dg_launch.h"
 
@@ -195,6 +197,147 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
     }
 }
 
+// ---- The same steps with the cell transforms as real FFTs (half spectra,
+// rocFFT).  A forward transform gives X_k = sum_c u_c e^{-2 pi i k c / N};
+// the orthonormal cos / sin coefficients of wave number k are then
+// sqrt(2/N) (Re X_k, -Im X_k) (k = 0 and N/2: 1/sqrt(N) Re X_k), and the
+// inverse (unnormalised) transform of Y_k = sqrt(2/N)/2 (a - i b), Y_0 and
+// Y_{N/2} = 1/sqrt(N) a, rebuilds sum a cos + b sin.  The mixing kernels
+// convert between the two while they mix.
+
+template <class T> struct CplxOf;
+template <> struct CplxOf<double> { using type = double2; };
+template <> struct CplxOf<float> { using type = float2; };
+
+// Half-spectrum value -> the cos / sin coefficient pair (pair) or the single
+// real coefficient, with the orthonormal scaling (cn = 1/sqrt(N),
+// cp = sqrt(2/N)).
+template <class C, class T>
+__device__ __forceinline__ void spec_to_coef(const C z, bool pair, T cn, T cp, T& a, T& b) {
+    if (pair) {
+        a = cp * z.x;
+        b = -cp * z.y;
+    } else {
+        a = cn * z.x;
+        b = T(0);
+    }
+}
+
+template <class C, class T>
+__device__ __forceinline__ C coef_to_spec(bool pair, T cn, T cp, T a, T b) {
+    C z;
+    if (pair) {
+        z.x = T(0.5) * cp * a;
+        z.y = -T(0.5) * cp * b;
+    } else {
+        z.x = cn * a;
+        z.y = T(0);
+    }
+    return z;
+}
+
+// Forward x mixing from the x spectra X[(cy + Ny (i + n j)) + M k] (M =
+// Ny n^2; block row k = blockIdx.y, lanes along cy) into the real
+// x-transformed field U1[cy + Ny (i + n c + n Nx j)] (c: the cos / sin
+// columns of wave number k, as in the matrix-product path).
+template <int N, class T>
+__global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_fwd(
+    int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf, T cn, T cp,
+    const typename CplxOf<T>::type* __restrict__ X, T* __restrict__ u1) {
+    constexpr int S = 2 * N;
+    const int k = blockIdx.y;
+    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+    const bool pair = c1 >= 0;
+    const T* Mk = Mf + (size_t)k * S * S;
+    const long per = (long)Ny * N, M = (long)Ny * N * N;
+    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
+         t += (long)gridDim.x * kPwThreads) {
+        const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
+        T v[S], w[S];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            spec_to_coef(X[cy + (long)Ny * (i + N * j) + M * k], pair, cn, cp, v[i], v[N + i]);
+        mix_vec<N, T>(Mk, pair, v, w);
+        const long base = cy + (long)Ny * N * Nx * j;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            u1[base + (long)Ny * (i + (long)N * c0)] = w[i];
+            if (pair) u1[base + (long)Ny * (i + (long)N * c1)] = w[N + i];
+        }
+    }
+}
+
+// Inverse x mixing: U1 (real coefficients) -> the x spectra, ready for the
+// inverse x transform.
+template <int N, class T>
+__global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_inv(
+    int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mi, T cn, T cp,
+    const T* __restrict__ u1, typename CplxOf<T>::type* __restrict__ X) {
+    using C = typename CplxOf<T>::type;
+    constexpr int S = 2 * N;
+    const int k = blockIdx.y;
+    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+    const bool pair = c1 >= 0;
+    const T* Mk = Mi + (size_t)k * S * S;
+    const long per = (long)Ny * N, M = (long)Ny * N * N;
+    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
+         t += (long)gridDim.x * kPwThreads) {
+        const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
+        const long base = cy + (long)Ny * N * Nx * j;
+        T v[S], w[S];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            v[i] = u1[base + (long)Ny * (i + (long)N * c0)];
+            v[N + i] = pair ? u1[base + (long)Ny * (i + (long)N * c1)] : T(0);
+        }
+        mix_vec<N, T>(Mk, pair, v, w);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            X[cy + (long)Ny * (i + N * j) + M * k] =
+                coef_to_spec<C>(pair, cn, cp, w[i], pair ? w[N + i] : T(0));
+    }
+}
+
+// y mixing, spectral division and unmixing in place on the y spectra
+// Y[(m + n Nx j) + n^2 Nx k] (m = i + n kx; block row k = blockIdx.y, lanes
+// along m): spectrum -> y modes (Mf), divided by -(lam_x + lam_y), the
+// constant mode zeroed, -> coefficients (Mi) -> spectrum.
+template <int N, class T>
+__global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
+    int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf,
+    const T* __restrict__ Mi, const T* __restrict__ lx, const T* __restrict__ ly, int zx, int zy,
+    T cn, T cp, typename CplxOf<T>::type* __restrict__ Y) {
+    using C = typename CplxOf<T>::type;
+    constexpr int S = 2 * N;
+    const int k = blockIdx.y;
+    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+    const bool pair = c1 >= 0;
+    const T* Mfk = Mf + (size_t)k * S * S;
+    const T* Mik = Mi + (size_t)k * S * S;
+    const long NXn = (long)N * Nx;
+    for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
+         m += (long)gridDim.x * kPwThreads) {
+        const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
+        const int xs = i * Nx + kx;
+        const T lam_x = lx[xs];
+        T v[S], w[S];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            spec_to_coef(Y[m + NXn * j + NXn * N * k], pair, cn, cp, v[j], v[N + j]);
+        mix_vec<N, T>(Mfk, pair, v, w);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (q >= N && !pair) break;
+            const int ys = (q % N) * Ny + (q < N ? c0 : c1);
+            w[q] = (xs == zx && ys == zy) ? T(0) : w[q] / -(lam_x + ly[ys]);
+        }
+        mix_vec<N, T>(Mik, pair, w, v);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            Y[m + NXn * j + NXn * N * k] = coef_to_spec<C>(pair, cn, cp, v[j], pair ? v[N + j] : T(0));
+    }
+}
+
 }  // namespace
 
 template <class T>
@@ -251,6 +394,40 @@ hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const 
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+                                const void* X, T* u1, hipStream_t s) {
+    using C = typename CplxOf<T>::type;
+    const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
+    const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), dim3(nb, K), dim3(kPwThreads),
+                                        0, s, Nx, Ny, cols, Mf, cn, cp, (const C*)X, u1));
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, int K, const int* cols, const T* Mi,
+                                const T* u1, void* X, hipStream_t s) {
+    using C = typename CplxOf<T>::type;
+    const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
+    const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), dim3(nb, K), dim3(kPwThreads),
+                                        0, s, Nx, Ny, cols, Mi, cn, cp, u1, (C*)X));
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fft_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+                            const T* Mi, const T* lx, const T* ly, int zx, int zy, void* Y,
+                            hipStream_t s) {
+    using C = typename CplxOf<T>::type;
+    const int nb = pw_blocks((long)Nx * n, pointwise_block_cap());
+    const T cn = T(1.0 / std::sqrt((double)Ny)), cp = T(std::sqrt(2.0 / Ny));
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_y<NN, T>), dim3(nb, K), dim3(kPwThreads), 0,
+                                        s, Nx, Ny, cols, Mf, Mi, lx, ly, zx, zy, cn, cp, (C*)Y));
+    return hipGetLastError();
+}
+
 #define DG_FD_INSTANTIATE(T)                                                                  \
     template hipError_t launch_to_image<T>(const Geom&, const double*, bool, T*, hipStream_t); \
     template hipError_t launch_from_image<T>(const Geom&, const T*, double*, hipStream_t);    \
@@ -260,7 +437,13 @@ hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const 
     template hipError_t launch_fd_mix_x<T>(int, int, int, int, const int*, const T*, T*,      \
                                            hipStream_t);                                       \
     template hipError_t launch_fd_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \
-                                           const T*, const T*, int, int, T*, hipStream_t);
+                                           const T*, const T*, int, int, T*, hipStream_t);     \
+    template hipError_t launch_fft_mix_x_fwd<T>(int, int, int, int, const int*, const T*,      \
+                                                const void*, T*, hipStream_t);                 \
+    template hipError_t launch_fft_mix_x_inv<T>(int, int, int, int, const int*, const T*,      \
+                                                const T*, void*, hipStream_t);                 \
+    template hipError_t launch_fft_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \
+                                            const T*, const T*, int, int, void*, hipStream_t);
 DG_FD_INSTANTIATE(double)
 DG_FD_INSTANTIATE(float)
 #undef DG_FD_INSTANTIATE

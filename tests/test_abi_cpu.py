@@ -163,13 +163,18 @@ def test_workspace_bytes_and_field_size():
     def axis(N, n):
         K = N // 2 + 1
         return (N * N + 2 * K * (2 * n) ** 2 + N * n) * (8 + 4) + 2 * K * 4
+
+    def field(n, Nx, Ny):
+        # a work field holds the node planes or the half spectra of the
+        # real FFTs along x or y (N/2 + 1 complex values per transform)
+        return 8 * n * n * max(Nx * Ny, Ny * 2 * (Nx // 2 + 1), Nx * 2 * (Ny // 2 + 1))
     bfd = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
-    assert bfd == b64 + 3 * F + axis(512, 4)
+    assert bfd == b64 + F + 2 * field(4, 512, 512) + axis(512, 4)
     # unequal axes keep both factor sets
     r = dg.Grid(2, 6, 5)
     extra = r.workspace_bytes(dg.DG_WS_FD) - r.workspace_bytes(dg.DG_PREC_FP64)
     L6 = 5 * 1 * 4 * 64
-    assert extra == L6 * 8 + 2 * r.elems * 8 + axis(6, 2) + axis(5, 2)
+    assert extra == L6 * 8 + 2 * field(2, 6, 5) + axis(6, 2) + axis(5, 2)
     # ragged nx: the interleaved vectors are padded to whole groups of 64 cells
     h = dg.Grid(3, 100, 7)
     L = 7 * 2 * 9 * 64
