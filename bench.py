@@ -123,14 +123,19 @@ def form_batch(args):
         g = dg.Grid(n, N, N)
         g.set_tiles(*shapes[(n, N)])
         singles.append((g, dg.Workspace(g), dg.State(g), torch.from_numpy(w0).cuda(), dt))
+    print(f"[batch] {len(members)} members, {cells} cells, {len(shapes)} tuned shapes",
+          file=sys.stderr, flush=True)
     for (g, ws, st, w, dt) in singles:            # warm-up step
         dg.rk_step(g, w, st, ws, dt, args.D, opts)
     torch.cuda.synchronize()
+    print("[batch] one-by-one warm-up done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         for (g, ws, st, w, dt) in singles:
             dg.rk_step(g, w, st, ws, dt, args.D, opts)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"[batch] one-by-one step {k} at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t_single = time.perf_counter() - t0
 
     # batched
@@ -144,10 +149,13 @@ def form_batch(args):
         bw.append((g, w))
     batch.rk_step(opts)                            # warm-up step (+ capture)
     torch.cuda.synchronize()
+    print("[batch] batched warm-up done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         batch.rk_step(opts)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"[batch] batched step {k} at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t_batch = time.perf_counter() - t0
     same = all(bool(torch.equal(w, s[3])) for (g, w), s in zip(bw, singles))
     rhs = 3 * steps
@@ -336,8 +344,9 @@ def form_table3(args):
     method (SSP-RK3 start), dt = min(0.1 h / P, 0.3 / (D |lambda_max|));
     L2 error against the exact solution at the Gauss nodes, for every entry
     of the printed table.  Poisson solves: CG preconditioned by fast
-    diagonalisation on periodic grids, plain CG on Dirichlet grids (rtol
-    1e-12; the errors are those of the spatial discretisation)."""
+    diagonalisation (factored Bloch bases on periodic grids, dense
+    eigenbases on Dirichlet grids; rtol 1e-12, the errors are those of the
+    spatial discretisation)."""
     import numpy as np
     import torch
     from numpy.polynomial.legendre import leggauss
@@ -349,7 +358,7 @@ def form_table3(args):
             for col, (D, bc) in enumerate(((0.0, 0), (0.0, 1), (0.01, 0), (0.01, 1))):
                 t0 = time.perf_counter()
                 grid = dg.Grid(P, N, N, bc_x=bc, bc_y=bc)
-                ws = dg.Workspace(grid, dg.DG_PREC_FP64 | (0 if bc else dg.DG_WS_FD))
+                ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
                 X, Y = inputs.node_coords(P, N, N)
                 w0 = 2.0 * np.sin(X) * np.sin(Y)
                 h = 2.0 * math.pi / N
@@ -358,8 +367,7 @@ def form_table3(args):
                     dt = min(dt, 0.3 / (D * 1.25 * _lap_max(dg, grid, ws)))
                 steps = int(math.ceil(2.0 / dt))
                 dt = 2.0 / steps
-                opts = dg.cg_opts(rtol=1e-12,
-                                  precond=dg.DG_PRECOND_NONE if bc else dg.DG_PRECOND_FD)
+                opts = dg.cg_opts(rtol=1e-12, precond=dg.DG_PRECOND_FD)
                 ab, w = dg.AbState(grid, 3), torch.from_numpy(w0).cuda()
                 iters, t_print = 0, time.perf_counter()
                 for k in range(steps):
@@ -467,6 +475,80 @@ def form_paper(args):
                       "data": "synthetic"}), flush=True)
 
 
+def form_turbulence(args):
+    """The full decaying-turbulence run: n = 4, 512^2 periodic cells,
+    random-spectrum omega0 (k0 = 10, seed 1), CFL 0.1, `--run-steps` SSP-RK3
+    steps (default 2000) for D = 0 and D = 1e-4 after 50 warm-up steps, CG
+    preconditioned by the exact fast-diagonalisation inverse (rtol 1e-12,
+    extrapolated guess); per-RHS device times over every RHS of the run.
+    Reports the invariants V = int omega, E = 1/2 int psi omega and
+    Omega = 1/2 int omega^2 along the run: with D = 0 the scheme conserves E
+    and Omega up to the RK3 time error and the CG tolerance, with D > 0 they
+    decay."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    n, N = args.n, args.N
+    omega0, umax = inputs.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
+    dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
+    grid = dg.Grid(n, N, N)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    opts = dg.cg_opts(rtol=args.rtol, precond=dg.DG_PRECOND_FD)
+    every = max(1, args.run_steps // 8)
+    runs = []
+    for D in (0.0, 1e-4):
+        # 50 warm-up steps on a copy, then the run from omega0
+        st = dg.State(grid)
+        w = torch.from_numpy(omega0).cuda()
+        for _ in range(50):
+            dg.rk_step(grid, w, st, ws, dt, D, opts)
+        st = dg.State(grid)
+        w = torch.from_numpy(omega0).cuda()
+        psi = torch.zeros_like(w)
+        dg.cg_solve_poisson(grid, w, psi, ws, opts)
+        V0, E0, Om0 = dg.invariants(grid, w, psi, ws)
+        track = [{"step": 0, "t": 0.0, "V": V0, "E": E0, "Omega": Om0}]
+        iters, stage_ms, busy, last = [], [], 0.0, time.perf_counter()
+        for k in range(1, args.run_steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = dg.rk_step(grid, w, st, ws, dt, D, opts, record_times=True)
+            torch.cuda.synchronize()
+            busy += time.perf_counter() - t0
+            if not r.converged:
+                raise RuntimeError(f"CG did not converge at step {k} (D={D})")
+            iters.extend(r.cg_iters)
+            stage_ms.extend(r.stage_ms)
+            if k % every == 0 or k == args.run_steps:
+                psi = torch.zeros_like(w)
+                dg.cg_solve_poisson(grid, w, psi, ws, opts)
+                V, E, Om = dg.invariants(grid, w, psi, ws)
+                track.append({"step": k, "t": k * dt, "V": V, "E": E, "Omega": Om,
+                              "dE_rel": (E - E0) / E0, "dOmega_rel": (Om - Om0) / Om0})
+            if time.perf_counter() - last > 20 or k == args.run_steps:
+                last = time.perf_counter()
+                print(f"[turbulence] D={D} step {k}/{args.run_steps} "
+                      f"{track[-1]}", file=sys.stderr, flush=True)
+        srt = sorted(stage_ms)
+        runs.append({"D": D, "steps": args.run_steps, "t_end": args.run_steps * dt,
+                     "value": N * N * 3 * args.run_steps / busy,
+                     "ms_per_step": busy / args.run_steps * 1e3,
+                     "latency_ms_per_rhs": {
+                         "p50": srt[len(srt) // 2],
+                         "p99": srt[min(len(srt) - 1, int(math.ceil(0.99 * len(srt))) - 1)],
+                         "mean": statistics.mean(stage_ms)},
+                     "cg_iters_per_rhs": {"mean": statistics.mean(iters), "max": max(iters)},
+                     "invariants": track})
+    print(json.dumps({
+        "metric": "decaying turbulence run: invariants and throughput",
+        "unit": "cell-updates/s", "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"decaying 2D turbulence, periodic [0,2pi]^2, n={n}, "
+                                f"{N}x{N} cells, random-spectrum omega0 (k0=10, seed 1), "
+                                f"dt={dt:.4e} (CFL 0.1), SSP-RK3, PCG (fast "
+                                f"diagonalisation) rtol {args.rtol}, extrapolated guess"),
+                   "n": n, "Nx": N, "Ny": N},
+        "runs": runs}), flush=True)
+
+
 def precond_leg(args, omega0, dt, tiles):
     """The same workload (fresh from omega0) with CG preconditioned by the
     exact fast-diagonalisation inverse of -Lap_h: W warm-up steps, then K
@@ -527,7 +609,7 @@ def main():
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     ap.add_argument("--form", default="rhs",
                     choices=["rhs", "batch", "mixed", "serve", "paper", "tune", "lamb",
-                             "table3"],
+                             "table3", "turbulence"],
                     help="rhs: the headline metric (default); the others measure "
                          "the batched, mixed-precision and served forms and the "
                          "paper's bracket-timing shape")
@@ -535,6 +617,8 @@ def main():
                     help="--form mixed: the solver variants to run (fp64 is always run); "
                          "the plain mixed form does not reach rtol 1e-10 beyond 128^2 "
                          "cells at n = 5")
+    ap.add_argument("--run-steps", dest="run_steps", type=int, default=2000,
+                    help="--form turbulence: RK3 steps per run")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--N-max", dest="N_max", type=int, default=256)
     ap.add_argument("--requests", type=int, default=16)
@@ -555,7 +639,7 @@ def main():
     if args.form != "rhs":
         {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
          "paper": form_paper, "tune": form_tune, "lamb": form_lamb,
-         "table3": form_table3}[args.form](args)
+         "table3": form_table3, "turbulence": form_turbulence}[args.form](args)
         return
     n, N = args.n, args.N
     if args.copy_calibration:

@@ -129,11 +129,12 @@ const char* dg_last_error(void);
  * Table 2's Dirichlet row; for the LDG Laplacian u-hat = 0 and q-hat = the
  * inside trace with the jump penalty against 0, the closure that gives
  * Table 3's Dirichlet columns).  A grid with a Dirichlet axis supports the
- * bracket, the Laplacian, the plain FP64 Poisson solve (no mean is removed:
- * -Lap_h is definite), dg_rk_step, dg_ab_step and dg_invariants, with cell
- * tiles of 64 x 8; mixed precision, the preconditioner, batches and the
- * tuner return DG_E_UNSUPPORTED for it.  Touches no GPU.  Errors:
- * DG_E_INVAL, DG_E_NOMEM. */
+ * bracket, the Laplacian, the FP64 Poisson solve (no mean is removed:
+ * -Lap_h is definite) plain or preconditioned, the mixed-precision
+ * preconditioned solve, dg_rk_step, dg_ab_step and dg_invariants, with cell
+ * tiles of 64 x 8; the mixed-precision solve without a preconditioner,
+ * batches and the tuner return DG_E_UNSUPPORTED for it.  Touches no GPU.
+ * Errors: DG_E_INVAL, DG_E_NOMEM. */
 int  dg_grid_create(int n, int nx, int ny, double x0, double x1, double y0,
                     double y1, int bc_x, int bc_y, dg_grid** out);
 void dg_grid_destroy(dg_grid* grid);                 /* NULL-safe */
@@ -180,12 +181,18 @@ int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
  * node-plane fields and per axis the factored eigenbasis in FP64 and FP32
  * (the N x N cell Fourier basis, 2 (N/2 + 1) mixing blocks of 2n x 2n and
  * n N eigenvalues; one set when the axes agree; rocBLAS and, beyond 512
- * cells on an axis, rocFFT keep their own work buffers on top).  This is the figure that admission control budgets.
+ * cells on an axis, rocFFT keep their own work buffers on top).  On a grid
+ * with a Dirichlet axis the preconditioner holds instead two dense work
+ * images of n^2 Nx Ny doubles and per axis the dense (n N)^2 eigenbasis and
+ * n N eigenvalues in FP64 and FP32.  This is the figure that admission
+ * control budgets.
  * mode = DG_PREC_FP64 or DG_PREC_MIXED, optionally | DG_WS_FD. */
 int  dg_workspace_bytes(const dg_grid* grid, int mode, size_t* bytes);
 /* Allocate a workspace on the current device (hipMalloc + pinned host
- * scalars).  Errors: DG_E_INVAL, DG_E_NOMEM, DG_E_HIP; DG_E_UNSUPPORTED for
- * DG_WS_FD on a grid with a Dirichlet axis. */
+ * scalars).  With DG_WS_FD on a grid with a Dirichlet axis this runs the
+ * dense eigensolver (rocSOLVER) on the device, synchronously.  Errors:
+ * DG_E_INVAL, DG_E_NOMEM, DG_E_HIP; DG_E_UNSUPPORTED for DG_WS_FD on a grid
+ * with a Dirichlet axis of more than 8192 nodes (n * cells). */
 int  dg_workspace_create(const dg_grid* grid, int mode, dg_workspace** out);
 void dg_workspace_destroy(dg_workspace* ws);         /* NULL-safe */
 
@@ -238,24 +245,35 @@ int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
 /* z = (-Lap_h)^+ r: the exact solution of -Lap_h z = r - mean_W(r) with
  * W-mean zero, by fast diagonalisation -- the preconditioner DG_PRECOND_FD
  * applies (beyond the paper, whose CG of Sec. 6 is unpreconditioned).  The
- * 1D LDG operator of each axis is block circulant, so Bloch waves reduce it
- * to n x n Hermitian (in the Gauss weights) symbols whose eigenvectors give
- * a real W-orthonormal basis V with L V = V diag(lambda); then
- * z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T, the
+ * 1D LDG operator of each periodic axis is block circulant, so Bloch waves
+ * reduce it to n x n Hermitian (in the Gauss weights) symbols whose
+ * eigenvectors give a real W-orthonormal basis V with L V = V diag(lambda);
+ * then z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T, the
  * constant mode dropped.  V is applied in factored form (the cell Fourier
  * transform, then 2n x 2n mixing per wave number); the transform is an FP64
  * matrix product (4 n^2 Nx Ny (Nx + Ny) flops per call) up to 512 cells per
- * axis and a real FFT (rocFFT) beyond.  r, z: canonical fields, z must not
- * alias r.  ws must hold DG_WS_FD.  Asynchronous. */
+ * axis and a real FFT (rocFFT) beyond.  On a grid with a homogeneous
+ * Dirichlet axis (-Lap_h definite, z = (-Lap_h)^-1 r) both axes use dense
+ * eigenbases (the Dirichlet one from rocSOLVER's symmetric eigensolver) and
+ * the apply is four dense matrix products, 2 (n Nx)(n Ny)(n Nx + n Ny)
+ * flops.  r, z: canonical fields, z must not alias r.  ws must hold
+ * DG_WS_FD.  Asynchronous. */
 int  dg_precond_apply(const dg_grid* grid, const double* r, double* z,
                       dg_workspace* ws, void* stream);
-/* The eigenbasis dg_precond_apply uses along one axis (axis 0: x, 1: y),
- * built on the host from the Bloch symbols: V (host, (N n)^2 doubles,
+/* The eigenbasis dg_precond_apply uses along one periodic axis (axis 0: x,
+ * 1: y), built on the host from the Bloch symbols: V (host, (N n)^2 doubles,
  * column-major, row = c n + i for cell c and node i, column = mode) with
  * L V = V diag(lam) and V^T W V = I for the 1D LDG second derivative L and
  * Gauss weights W of that axis; lam (host, N n doubles); *zero = the column
- * of the constant mode.  Touches no GPU. */
+ * of the constant mode.  DG_E_UNSUPPORTED for a Dirichlet axis (its basis
+ * is computed on the device).  Touches no GPU. */
 int  dg_grid_fd_basis(const dg_grid* grid, int axis, double* V, double* lam, int* zero);
+/* The 1D LDG second derivative of one axis (axis 0: x, 1: y; Sec. 6 as read
+ * for dg_laplace_apply, with the Dirichlet closure on a Dirichlet axis), the
+ * operator the preconditioner diagonalises: L (host, (N n)^2 doubles,
+ * column-major, row and column = c n + i).  Lap_h is L_x along x plus L_y
+ * along y.  Touches no GPU. */
+int  dg_grid_axis_operator(const dg_grid* grid, int axis, double* L);
 
 /* ------------------------------------------------------------ stepping --- */
 /* History of Poisson solutions used for the CG initial guess: the

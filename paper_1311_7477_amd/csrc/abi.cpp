@@ -318,11 +318,12 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
 template <class T>
 int precond_step(const dg_grid* g, dg_workspace* ws, hipStream_t s) {
     T* planes = reinterpret_cast<T*>(ws->fd->img0);
-    hipError_t e = launch_to_image<T>(g->geom, ws->r, true, planes, s);
+    const bool dense = ws->fd->dense;
+    hipError_t e = launch_to_image<T>(g->geom, g->k64, ws->r, true, dense, planes, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     int rc = fd_apply_image(ws->fd, sizeof(T) == sizeof(float), s);
     if (rc != DG_OK) return rc;
-    e = launch_from_image_dot<T>(g->geom, g->k64, planes, ws->z, ws->r, ws->d, s);
+    e = launch_from_image_dot<T>(g->geom, g->k64, planes, dense, ws->z, ws->r, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }
@@ -388,9 +389,9 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
         return fail(DG_E_INVAL, "rtol must be > 0 and max_iter >= 0");
     if (o.precond != DG_PRECOND_NONE && o.precond != DG_PRECOND_FD)
         return fail(DG_E_INVAL, "unknown preconditioner %d", o.precond);
-    if ((g->geom.bcx || g->geom.bcy) &&
-        (o.precond != DG_PRECOND_NONE || o.precision != DG_PREC_FP64))
-        return periodic_only("the preconditioned and the mixed-precision solve");
+    if ((g->geom.bcx || g->geom.bcy) && o.precond == DG_PRECOND_NONE &&
+        o.precision != DG_PREC_FP64)
+        return periodic_only("the mixed-precision solve without a preconditioner");
     if (o.precond == DG_PRECOND_FD) {
         if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_MIXED)
             return fail(DG_E_INVAL, "unknown precision %d", o.precision);
@@ -412,8 +413,8 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
 namespace dgk {
 int periodic_only(const char* what) {
     return fail(DG_E_UNSUPPORTED, "%s is implemented for periodic grids only "
-                "(Dirichlet grids support the bracket, the Laplacian, the plain FP64 "
-                "CG and time stepping)", what);
+                "(Dirichlet grids support the bracket, the Laplacian, the FP64 CG plain "
+                "or preconditioned, the mixed-precision PCG and time stepping)", what);
 }
 
 int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,
@@ -510,8 +511,10 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
     *out = nullptr;
     if (!valid_mode(mode)) return fail(DG_E_INVAL, "bad mode %d", mode);
-    if ((mode & DG_WS_FD) && (g->geom.bcx || g->geom.bcy))
-        return periodic_only("the preconditioner");
+    if (mode & DG_WS_FD) {
+        const int rc = fd_supported(g);
+        if (rc != DG_OK) return rc;
+    }
     dg_workspace* ws = new (std::nothrow) dg_workspace;
     if (!ws) return fail(DG_E_NOMEM, "host allocation failed");
     std::memset(ws, 0, sizeof *ws);
@@ -633,8 +636,9 @@ int dg_laplace_apply(const dg_grid* g, const double* f, double* out, void* strea
 
 int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* zero) {
     if (!g || !V || !lam || !zero) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("the preconditioner");
     if (axis != 0 && axis != 1) return fail(DG_E_INVAL, "axis must be 0 (x) or 1 (y)");
+    if (axis == 0 ? g->geom.bcx : g->geom.bcy)
+        return periodic_only("the Bloch eigenbasis");
     FdAxis a;
     double err = 0.0;
     const bool ok = axis == 0 ? fd_axis_basis(g->t, g->nx, g->hx, &a, &err)
@@ -646,21 +650,31 @@ int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* ze
     return DG_OK;
 }
 
+int dg_grid_axis_operator(const dg_grid* g, int axis, double* L) {
+    if (!g || !L) return fail(DG_E_INVAL, "NULL argument");
+    if (axis != 0 && axis != 1) return fail(DG_E_INVAL, "axis must be 0 (x) or 1 (y)");
+    std::vector<double> M;
+    if (axis == 0) fd_axis_operator(g->t, g->nx, g->hx, !g->geom.bcx, &M);
+    else fd_axis_operator(g->t, g->ny, g->hy, !g->geom.bcy, &M);
+    std::memcpy(L, M.data(), M.size() * sizeof(double));
+    return DG_OK;
+}
+
 int dg_precond_apply(const dg_grid* g, const double* r, double* z, dg_workspace* ws,
                      void* stream) {
     if (!g || !r || !z) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("the preconditioner");
     int rc = check_ws(g, ws);
     if (rc != DG_OK) return rc;
     if (!ws->fd) return fail(DG_E_WORKSPACE, "the workspace has no DG_WS_FD preconditioner");
     if (ranges_overlap(z, r, g->elems * sizeof(double)))
         return fail(DG_E_ALIAS, "z aliases r");
     const hipStream_t s = as_stream(stream);
-    hipError_t e = launch_to_image<double>(g->geom, r, false, ws->fd->img0, s);
+    const bool dense = ws->fd->dense;
+    hipError_t e = launch_to_image<double>(g->geom, g->k64, r, false, dense, ws->fd->img0, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     rc = fd_apply_image(ws->fd, false, s);
     if (rc != DG_OK) return rc;
-    e = launch_from_image<double>(g->geom, ws->fd->img0, z, s);
+    e = launch_from_image<double>(g->geom, g->k64, ws->fd->img0, dense, z, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }

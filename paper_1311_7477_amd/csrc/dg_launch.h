@@ -95,17 +95,23 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
 // -> canonical, planes -> z (lane-interleaved) with <r, z>_W closing the PCG
 // step, the per-wave-number mixing of the x cell transform (K blocks, M
 // row-major 2n x 2n each, cols[2k] / cols[2k+1] the cos / sin columns), and
-// the y mixing + spectral scaling + unmixing.
+// the y mixing + spectral scaling + unmixing.  `dense`: the conversions
+// use the dense image of the eigenbasis path instead of node planes (rows
+// along x, values scaled by sqrt(W) on the way in and by its inverse on the
+// way out), and launch_dense_divide is that path's spectral division.
 // T = double, or float for the FP32 apply of the mixed-precision PCG.
 template <class T>
-hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, T* img,
-                           hipStream_t s);
+hipError_t launch_to_image(const Geom& g, const OpConst<double>& k, const double* src,
+                           bool from_l64, bool dense, T* img, hipStream_t s);
 template <class T>
-hipError_t launch_from_image(const Geom& g, const T* img, double* dst, hipStream_t s);
+hipError_t launch_from_image(const Geom& g, const OpConst<double>& k, const T* img, bool dense,
+                             double* dst, hipStream_t s);
 template <class T>
 hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const T* img,
-                                 double* z, const double* r, const DevScratch& d,
+                                 bool dense, double* z, const double* r, const DevScratch& d,
                                  hipStream_t s);
+template <class T>
+hipError_t launch_dense_divide(int mx, int my, const T* lx, const T* ly, T* c, hipStream_t s);
 template <class T>
 hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const T* M, T* u,
                            hipStream_t s);

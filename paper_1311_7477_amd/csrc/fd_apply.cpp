@@ -17,9 +17,21 @@
 // write half spectra, fd_kernels.hip).  The same steps run in FP64 or, for
 // the mixed-precision PCG, in FP32 (factors rounded once at setup; the
 // fields then take the first half of the FP64 work fields).
+//
+// A grid with a homogeneous Dirichlet axis has no circulant structure along
+// that axis, so it takes the dense path: per axis the orthogonal Q = W^{1/2} V
+// (V the W-orthonormal eigenbasis of the 1D operator; rocSOLVER's symmetric
+// eigensolver on W^{1/2} (-L) W^{-1/2} for a Dirichlet axis, the Bloch basis
+// assembled densely for a periodic one), and on the dense image A of
+// sqrt(W) r (rows along x)
+//     z = W^{-1/2} Q_x [ (Q_x^T A Q_y) / -(lam_x + lam_y) ] Q_y^T,
+// four GEMMs of 2 m_x m_y (m_x + m_y) flops in all (m = n N per axis).
 #include <rocblas/rocblas.h>
 #include <rocfft/rocfft.h>
+#include <rocsolver/rocsolver.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -32,7 +44,19 @@ namespace dgk {
 
 namespace {
 
-bool same_axis(const dg_grid* g) { return g->nx == g->ny && g->hx == g->hy; }
+bool same_axis(const dg_grid* g) {
+    return g->nx == g->ny && g->hx == g->hy && g->geom.bcx == g->geom.bcy;
+}
+
+bool has_dirichlet(const dg_grid* g) { return g->geom.bcx || g->geom.bcy; }
+
+// the dense path's limit: 8192 nodes per axis (Q in FP64 and FP32: 805 MB)
+constexpr int kFdDenseMaxNodes = 8192;
+
+size_t dense_axis_bytes(int N, int n) {
+    const size_t m = (size_t)N * n;
+    return (m * m + m) * (sizeof(double) + sizeof(float));
+}
 
 int blas_fail(rocblas_status st, const char* what) {
     return fail(DG_E_HIP, "%s: rocBLAS status %d (%s)", what, (int)st,
@@ -193,11 +217,173 @@ int apply_fft(const FdDevice* fd, hipStream_t s) {
 }  // namespace
 
 size_t fd_bytes(const dg_grid* g) {
+    if (has_dirichlet(g)) {
+        const size_t img = 2 * (size_t)g->n * g->n * g->nx * g->ny * sizeof(double);
+        return img + dense_axis_bytes(g->nx, g->n) +
+               (same_axis(g) ? 0 : dense_axis_bytes(g->ny, g->n));
+    }
     const size_t planes = 2 * field_reals(g->n, g->nx, g->ny) * sizeof(double);
     return planes + axis_bytes(g->nx, g->n) + (same_axis(g) ? 0 : axis_bytes(g->ny, g->n));
 }
 
+int fd_supported(const dg_grid* g) {
+    if (!has_dirichlet(g)) return DG_OK;
+    const long mx = (long)g->n * g->nx, my = (long)g->n * g->ny;
+    if (mx > kFdDenseMaxNodes || my > kFdDenseMaxNodes)
+        return fail(DG_E_UNSUPPORTED, "the preconditioner of a grid with a Dirichlet axis uses "
+                    "dense eigenbases, limited to %d nodes per axis (n * cells: %ld x %ld)",
+                    kFdDenseMaxNodes, mx, my);
+    return DG_OK;
+}
+
 namespace {
+
+void free_dense(FdDenseAxis* a) {
+    void* bufs[] = {a->q64, a->lam64, a->q32, a->lam32};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    *a = FdDenseAxis{};
+}
+
+// Q (rows c * n + i on entry) reordered to rows c + N i and uploaded in
+// FP64 and FP32 with the eigenvalues.
+bool upload_dense(int n, int N, const std::vector<double>& Q, const std::vector<double>& lam,
+                  FdDenseAxis* out) {
+    const size_t m = (size_t)N * n;
+    std::vector<double> R(m * m);
+    for (size_t col = 0; col < m; ++col)
+        for (int c = 0; c < N; ++c)
+            for (int i = 0; i < n; ++i)
+                R[col * m + c + (size_t)N * i] = Q[col * m + (size_t)c * n + i];
+    out->m = (int)m;
+    return upload(&out->q64, R) && upload(&out->lam64, lam) &&
+           upload(&out->q32, rounded(R)) && upload(&out->lam32, rounded(lam));
+}
+
+// The dense eigenbasis of one axis (0: x, 1: y).  A periodic axis assembles
+// its Bloch basis; a Dirichlet axis diagonalises S = W^{1/2} (-L) W^{-1/2}
+// (symmetric: L is self-adjoint in the Gauss inner product) with rocSOLVER.
+// Every eigenpair is then checked against the sparse operator on the host.
+int dense_axis(const dg_grid* g, int axis, rocblas_handle h, FdDenseAxis* out) {
+    const HostTables& t = g->t;
+    const int n = g->n, N = axis ? g->ny : g->nx;
+    const double hh = axis ? g->hy : g->hx;
+    const bool periodic = !(axis ? g->geom.bcy : g->geom.bcx);
+    const size_t m = (size_t)N * n;
+    std::vector<double> sw(m);
+    for (int c = 0; c < N; ++c)
+        for (int i = 0; i < n; ++i) sw[(size_t)c * n + i] = std::sqrt(0.5 * hh * t.w[i]);
+    std::vector<double> Q, lam(m);
+    double err = 0.0;
+    if (periodic) {
+        FdAxis a;
+        if (!fd_axis_basis(t, N, hh, &a, &err) || err > 1e-10)
+            return fail(DG_E_INVAL, "eigenbasis construction failed (defect %.3e)", err);
+        Q.swap(a.V);
+        for (size_t col = 0; col < m; ++col)
+            for (size_t row = 0; row < m; ++row) Q[col * m + row] *= sw[row];
+        lam = a.lam;
+    } else {
+        fd_axis_operator(t, N, hh, false, &Q);
+        double scale = 0.0;
+        for (size_t col = 0; col < m; ++col)
+            for (size_t row = 0; row < m; ++row) {
+                double& v = Q[col * m + row];
+                v = -v * sw[row] / sw[col];
+                scale = std::max(scale, std::fabs(v));
+            }
+        for (size_t col = 0; col < m; ++col)
+            for (size_t row = col + 1; row < m; ++row) {
+                double& a = Q[col * m + row];
+                double& b = Q[row * m + col];
+                err = std::max(err, std::fabs(a - b) / scale);
+                a = b = 0.5 * (a + b);
+            }
+        double *dS = nullptr, *dD = nullptr, *dE = nullptr;
+        rocblas_int* dinfo = nullptr;
+        rocblas_int info = -1;
+        bool ok = hipMalloc((void**)&dS, m * m * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void**)&dD, m * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void**)&dE, m * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void**)&dinfo, sizeof(rocblas_int)) == hipSuccess;
+        rocblas_status st = rocblas_status_success;
+        if (ok) ok = hipMemcpy(dS, Q.data(), m * m * sizeof(double), hipMemcpyHostToDevice) ==
+                     hipSuccess;
+        if (ok) {
+            st = rocblas_set_stream(h, nullptr);
+            if (st == rocblas_status_success)
+                st = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper,
+                                      (rocblas_int)m, dS, (rocblas_int)m, dD, dE, dinfo);
+            if (st == rocblas_status_success) {
+                ok = hipMemcpy(Q.data(), dS, m * m * sizeof(double), hipMemcpyDeviceToHost) ==
+                         hipSuccess &&
+                     hipMemcpy(lam.data(), dD, m * sizeof(double), hipMemcpyDeviceToHost) ==
+                         hipSuccess &&
+                     hipMemcpy(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost) == hipSuccess;
+            }
+        }
+        void* bufs[] = {dS, dD, dE, dinfo};
+        for (void* b : bufs)
+            if (b) (void)hipFree(b);
+        if (st != rocblas_status_success) return blas_fail(st, "rocsolver_dsyevd");
+        if (!ok) {
+            (void)hipGetLastError();
+            return fail(DG_E_NOMEM, "eigensolver buffers for %zu x %zu failed", m, m);
+        }
+        if (info != 0)
+            return fail(DG_E_INVAL, "rocsolver_dsyevd did not converge (info %d)", (int)info);
+        for (double& l : lam) l = -l;
+    }
+    // eigen-residuals |L v - lam v| with v = W^{-1/2} q, against the sparse
+    // operator, relative to max |lam| |v|
+    double lmax = 0.0;
+    for (double l : lam) lmax = std::max(lmax, std::fabs(l));
+    std::vector<double> v(m), Lv(m);
+    for (size_t col = 0; col < m; ++col) {
+        double vmax = 0.0;
+        for (size_t row = 0; row < m; ++row) {
+            v[row] = Q[col * m + row] / sw[row];
+            vmax = std::max(vmax, std::fabs(v[row]));
+        }
+        fd_axis_apply(t, N, hh, periodic, v.data(), Lv.data());
+        for (size_t row = 0; row < m; ++row)
+            err = std::max(err, std::fabs(Lv[row] - lam[col] * v[row]) / (lmax * vmax));
+    }
+    if (!(err <= 1e-9))
+        return fail(DG_E_INVAL, "dense eigenbasis defect %.3e too large", err);
+    if (!upload_dense(n, N, Q, lam, out)) {
+        (void)hipGetLastError();
+        return fail(DG_E_NOMEM, "dense eigenbasis upload (%zu bytes) failed",
+                    dense_axis_bytes(N, n));
+    }
+    return DG_OK;
+}
+
+template <class T>
+int apply_dense(const FdDevice* fd, hipStream_t s) {
+    rocblas_handle h = (rocblas_handle)fd->blas;
+    rocblas_status st = rocblas_set_stream(h, s);
+    if (st != rocblas_status_success) return blas_fail(st, "rocblas_set_stream");
+    const FdDenseAxis& X = fd->dx;
+    const FdDenseAxis& Y = fd->dy;
+    const rocblas_int mx = X.m, my = Y.m;
+    T* a = reinterpret_cast<T*>(fd->img0);
+    T* b = reinterpret_cast<T*>(fd->img1);
+    const T* qx = X.q<T>();
+    const T* qy = Y.q<T>();
+    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+    st = gemm(h, T_, N_, mx, my, mx, qx, mx, 0, a, mx, 0, b, mx, 0, 1);          // B = Qx^T A
+    if (st == rocblas_status_success)
+        st = gemm(h, N_, N_, mx, my, my, b, mx, 0, qy, my, 0, a, mx, 0, 1);      // A = B Qy
+    if (st != rocblas_status_success) return blas_fail(st, "dense forward transform");
+    hipError_t e = launch_dense_divide<T>(mx, my, X.lam<T>(), Y.lam<T>(), a, s);
+    if (e != hipSuccess) return hip_fail(e, "dense spectral division launch");
+    st = gemm(h, N_, N_, mx, my, mx, qx, mx, 0, a, mx, 0, b, mx, 0, 1);          // B = Qx A
+    if (st == rocblas_status_success)
+        st = gemm(h, N_, T_, mx, my, my, b, mx, 0, qy, my, 0, a, mx, 0, 1);      // A = B Qy^T
+    if (st != rocblas_status_success) return blas_fail(st, "dense inverse transform");
+    return DG_OK;
+}
 
 // One batched 1D real FFT along an axis of length L: `count` transforms of
 // contiguous real rows (distance L) whose half spectra are stored with
@@ -280,15 +466,59 @@ void fd_destroy(FdDevice* fd) {
     if (fd->img1) (void)hipFree(fd->img1);
     free_axis(&fd->x);
     if (!fd->shared) free_axis(&fd->y);
+    free_dense(&fd->dx);
+    if (!fd->shared) free_dense(&fd->dy);
     delete fd;
 }
 
+namespace {
+
+int fd_create_dense(const dg_grid* g, FdDevice* fd) {
+    const size_t img = (size_t)g->n * g->n * g->nx * g->ny * sizeof(double);
+    if (hipMalloc((void**)&fd->img0, img) != hipSuccess ||
+        hipMalloc((void**)&fd->img1, img) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DG_E_NOMEM, "preconditioner allocation of %zu bytes failed", fd_bytes(g));
+    }
+    rocblas_handle h = (rocblas_handle)fd->blas;
+    int rc = dense_axis(g, 0, h, &fd->dx);
+    if (rc != DG_OK) return rc;
+    if (fd->shared) {
+        fd->dy = fd->dx;
+        return DG_OK;
+    }
+    return dense_axis(g, 1, h, &fd->dy);
+}
+
+}  // namespace
+
 int fd_create(const dg_grid* g, FdDevice** out) {
     *out = nullptr;
+    int rc0 = fd_supported(g);
+    if (rc0 != DG_OK) return rc0;
     FdDevice* fd = new (std::nothrow) FdDevice;
     if (!fd) return fail(DG_E_NOMEM, "host allocation failed");
     fd->n = g->n;
     fd->shared = same_axis(g);
+    if (has_dirichlet(g)) {
+        fd->dense = true;
+        fd->use_fft = false;
+        rocblas_handle h = nullptr;
+        rocblas_status st = rocblas_create_handle(&h);
+        if (st != rocblas_status_success) {
+            delete fd;
+            return blas_fail(st, "rocblas_create_handle");
+        }
+        fd->blas = h;
+        rc0 = fd_create_dense(g, fd);
+        if (rc0 != DG_OK) {
+            fd_destroy(fd);
+            return rc0;
+        }
+        fd->bytes = fd_bytes(g);
+        *out = fd;
+        return DG_OK;
+    }
     FdFactors fx, fy;
     double ex = 0.0, ey = 0.0;
     if (!fd_axis_factors(g->t, g->nx, g->hx, &fx, &ex) ||
@@ -336,6 +566,7 @@ int fd_create(const dg_grid* g, FdDevice** out) {
 // img0 holds the node planes of r on entry and those of z = M r on exit
 // (FP32 planes when fp32).
 int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s) {
+    if (fd->dense) return fp32 ? apply_dense<float>(fd, s) : apply_dense<double>(fd, s);
     if (fd->use_fft) return fp32 ? apply_fft<float>(fd, s) : apply_fft<double>(fd, s);
     return fp32 ? apply_planes<float>(fd, s) : apply_planes<double>(fd, s);
 }

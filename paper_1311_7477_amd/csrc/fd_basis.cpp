@@ -233,4 +233,73 @@ bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* ma
     return true;
 }
 
+// Row c of the axis operator in the h = 1 blocks: self block, the right
+// coupling vector (times lR . u_{c+1}) and the left functional (eL times it
+// applied to u_{c-1}); null where the coupling is absent (the Dirichlet ends).
+struct AxisRow {
+    const double *L0, *eR, *lL;
+};
+
+static AxisRow axis_row(const AxisLdg& ax, int N, bool periodic, int c) {
+    if (periodic) return {ax.L0, ax.eR, ax.lL};
+    AxisRow r{c == 0 ? ax.L0B : ax.L0, c == 0 ? ax.eRB : ax.eR, c == 1 ? ax.lLB : ax.lL};
+    if (c == N - 1) r.eR = nullptr;
+    if (c == 0) r.lL = nullptr;
+    return r;
+}
+
+void fd_axis_apply(const HostTables& t, int N, double h, bool periodic, const double* u,
+                   double* out) {
+    const int n = t.n;
+    AxisLdg ax;
+    ldg_axis(t, h, periodic, &ax);
+    const double ih2 = 1.0 / (h * h);
+    for (int c = 0; c < N; ++c) {
+        const AxisRow r = axis_row(ax, N, periodic, c);
+        const double* uc = u + (size_t)c * n;
+        double fr = 0.0, fl = 0.0;
+        if (r.eR) {
+            const double* up = u + (size_t)((c + 1) % N) * n;
+            for (int m = 0; m < n; ++m) fr += t.lR[m] * up[m];
+        }
+        if (r.lL) {
+            const double* um = u + (size_t)((c + N - 1) % N) * n;
+            for (int m = 0; m < n; ++m) fl += r.lL[m] * um[m];
+        }
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int m = 0; m < n; ++m) acc += r.L0[i * n + m] * uc[m];
+            if (r.eR) acc += r.eR[i] * fr;
+            if (r.lL) acc += t.eL[i] * fl;
+            out[(size_t)c * n + i] = ih2 * acc;
+        }
+    }
+}
+
+void fd_axis_operator(const HostTables& t, int N, double h, bool periodic,
+                      std::vector<double>* L) {
+    const int n = t.n;
+    const size_t m = (size_t)N * n;
+    AxisLdg ax;
+    ldg_axis(t, h, periodic, &ax);
+    const double ih2 = 1.0 / (h * h);
+    L->assign(m * m, 0.0);
+    auto at = [&](size_t row, size_t col) -> double& { return (*L)[col * m + row]; };
+    for (int c = 0; c < N; ++c) {
+        const AxisRow r = axis_row(ax, N, periodic, c);
+        const size_t rc = (size_t)c * n;
+        for (int i = 0; i < n; ++i) {
+            for (int b = 0; b < n; ++b) at(rc + i, rc + b) += ih2 * r.L0[i * n + b];
+            if (r.eR) {
+                const size_t cp = (size_t)((c + 1) % N) * n;
+                for (int b = 0; b < n; ++b) at(rc + i, cp + b) += ih2 * r.eR[i] * t.lR[b];
+            }
+            if (r.lL) {
+                const size_t cm = (size_t)((c + N - 1) % N) * n;
+                for (int b = 0; b < n; ++b) at(rc + i, cm + b) += ih2 * t.eL[i] * r.lL[b];
+            }
+        }
+    }
+}
+
 }  // namespace dgk

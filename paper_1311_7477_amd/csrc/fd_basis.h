@@ -47,6 +47,15 @@ bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, doubl
 // mode of slot (a, c), rows cx * n + i.
 bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err);
 
+// The 1D LDG second derivative of one axis (the blocks of ldg_axis times
+// h^-2; the homogeneous Dirichlet closure when !periodic): fd_axis_apply
+// computes out = L u, fd_axis_operator assembles L densely (m x m with
+// m = n N, column-major, row and column index c * n + i).
+void fd_axis_apply(const HostTables& t, int N, double h, bool periodic, const double* u,
+                   double* out);
+void fd_axis_operator(const HostTables& t, int N, double h, bool periodic,
+                      std::vector<double>* L);
+
 // Device copy of one axis's factors in one precision: phi (N x N),
 // mf / mi (K blocks of 2n x 2n), lam (n N).
 template <class T>
@@ -66,9 +75,29 @@ struct FdAxisDevice {
 template <> inline const FdFactorsDevice<double>& FdAxisDevice::get<double>() const { return f64; }
 template <> inline const FdFactorsDevice<float>& FdAxisDevice::get<float>() const { return f32; }
 
+// Dense eigenbasis of one axis, the path of grids with a homogeneous
+// Dirichlet axis (whose operator is not circulant): Q = W^{1/2} V, with V the
+// W-orthonormal eigenbasis of the 1D operator, is orthogonal; m x m
+// column-major with rows c + N i (the axis index of the dense work image),
+// in FP64 and rounded to FP32, and lam the eigenvalues of L (m of them).
+struct FdDenseAxis {
+    int m = 0;
+    double *q64 = nullptr, *lam64 = nullptr;
+    float *q32 = nullptr, *lam32 = nullptr;
+    template <class T> const T* q() const;
+    template <class T> const T* lam() const;
+};
+template <> inline const double* FdDenseAxis::q<double>() const { return q64; }
+template <> inline const float* FdDenseAxis::q<float>() const { return q32; }
+template <> inline const double* FdDenseAxis::lam<double>() const { return lam64; }
+template <> inline const float* FdDenseAxis::lam<float>() const { return lam32; }
+
 // Device resources of the preconditioner, owned by a workspace.
 struct FdDevice {
     int n = 0;
+    // dense path (a Dirichlet axis): dy aliases dx when `shared`
+    bool dense = false;
+    FdDenseAxis dx, dy;
     FdAxisDevice x, y;                         // y aliases x when `shared`
     bool shared = false;
     double *img0 = nullptr, *img1 = nullptr;   // node-plane / half-spectrum work

@@ -14,11 +14,37 @@ namespace dgk {
 
 namespace {
 
-template <int N, bool FromL64, class T>
-__global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, const double* __restrict__ src,
+// Where node q = i + n j of cell (cx, cy) sits in the work field: node
+// planes [cell + nx ny q], or (Dense, the eigenbasis path of grids with a
+// Dirichlet axis) the image [(cx + nx i) + n nx (cy + ny j)], a column-major
+// (n nx) x (n ny) matrix whose rows run along x.  Consecutive cells along x
+// stay consecutive either way.
+template <int N, bool Dense>
+__device__ __forceinline__ long fd_at(const Geom& g, long cell, int cx, int cy, int q) {
+    if (!Dense) return cell + (long)g.nx * g.ny * q;
+    const int i = q % N, j = q / N;
+    return cx + (long)g.nx * i + (long)N * g.nx * (cy + (long)g.ny * j);
+}
+
+// sqrt(W) at the nodes of one cell (the dense path works with the
+// orthogonal Q = W^{1/2} V, so fields enter scaled by sqrt(W) and leave
+// scaled by its inverse)
+template <int N>
+__device__ __forceinline__ void sqrt_w(const OpConst<double>& k, double (&sw)[N * N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) sw[j * N + i] = sqrt(k.w[i] * k.w[j] * k.wq);
+}
+
+template <int N, bool FromL64, bool Dense, class T>
+__global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, OpConst<double> k,
+                                                         const double* __restrict__ src,
                                                          T* __restrict__ img) {
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
+    double sw[N * N];
+    if (Dense) sqrt_w<N>(k, sw);
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
          cell += (long)gridDim.x * kPwThreads) {
         const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
@@ -27,22 +53,29 @@ __global__ __launch_bounds__(kPwThreads) void k_to_image(Geom g, const double* _
         if (FromL64) ld_l64<N>(src, c, u);
         else ld_canon<N>(src, c, u);
 #pragma unroll
-        for (int q = 0; q < N * N; ++q) img[cell + cells * q] = (T)u[q];
+        for (int q = 0; q < N * N; ++q)
+            img[fd_at<N, Dense>(g, cell, cx, cy, q)] = (T)(Dense ? u[q] * sw[q] : u[q]);
     }
 }
 
-template <int N, class T>
-__global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const T* __restrict__ img,
+template <int N, bool Dense, class T>
+__global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, OpConst<double> k,
+                                                           const T* __restrict__ img,
                                                            double* __restrict__ dst) {
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
+    double sw[N * N];
+    if (Dense) sqrt_w<N>(k, sw);
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
          cell += (long)gridDim.x * kPwThreads) {
         const int cy = (int)(cell / g.nx), cx = (int)(cell - (long)cy * g.nx);
         const CellRef c = cell_ref<N>(g, G, cx, cy);
         double u[N * N];
 #pragma unroll
-        for (int q = 0; q < N * N; ++q) u[q] = (double)img[cell + cells * q];
+        for (int q = 0; q < N * N; ++q) {
+            u[q] = (double)img[fd_at<N, Dense>(g, cell, cx, cy, q)];
+            if (Dense) u[q] /= sw[q];
+        }
         st_canon<N>(dst, c, u);
     }
 }
@@ -50,13 +83,15 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, const T* __re
 // z = image (to L64) and <r, z>_W; the last block sets rz and, past the
 // first iteration, beta = <r,z>_new / <r,z>_old (no-op once the solve is
 // done; a non-positive or non-finite <r,z> ends the solve as a breakdown).
-template <int N, class T>
+template <int N, bool Dense, class T>
 __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
     Geom g, OpConst<double> k, const T* __restrict__ img, double* __restrict__ z,
     const double* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
     if (sc->done) return;
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
+    double sw[N * N];
+    if (Dense) sqrt_w<N>(k, sw);
     double part[1] = {0.0};
     for (long cell = blockIdx.x * (long)kPwThreads + threadIdx.x; cell < cells;
          cell += (long)gridDim.x * kPwThreads) {
@@ -64,7 +99,10 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
         const CellRef c = cell_ref<N>(g, G, cx, cy);
         double u[N * N], rv[N * N];
 #pragma unroll
-        for (int q = 0; q < N * N; ++q) u[q] = (double)img[cell + cells * q];
+        for (int q = 0; q < N * N; ++q) {
+            u[q] = (double)img[fd_at<N, Dense>(g, cell, cx, cy, q)];
+            if (Dense) u[q] /= sw[q];
+        }
         st_l64<N>(z, c, u);
         ld_l64<N>(r, c, rv);
         part[0] += wdot_cell<N>(k, rv, u);
@@ -338,40 +376,81 @@ __global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
     }
 }
 
+// Spectral division of the dense path: C[a + mx b] /= -(lam_x[a] + lam_y[b])
+// (a Dirichlet axis keeps every sum negative).
+template <class T>
+__global__ __launch_bounds__(kPwThreads) void k_dense_divide(int mx, int my,
+                                                             const T* __restrict__ lx,
+                                                             const T* __restrict__ ly,
+                                                             T* __restrict__ c) {
+    const long total = (long)mx * my;
+    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < total;
+         t += (long)gridDim.x * kPwThreads) {
+        const int b = (int)(t / mx), a = (int)(t - (long)b * mx);
+        c[t] = c[t] / -(lx[a] + ly[b]);
+    }
+}
+
 }  // namespace
 
 template <class T>
-hipError_t launch_to_image(const Geom& g, const double* src, bool from_l64, T* img,
-                           hipStream_t s) {
+hipError_t launch_to_image(const Geom& g, const OpConst<double>& k, const double* src,
+                           bool from_l64, bool dense, T* img, hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    if (from_l64) {
-        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, true, T>), dim3(nb),
-                                              dim3(kPwThreads), 0, s, g, src, img));
+#define DG_TO_IMAGE(L64, DN)                                                                 \
+    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, L64, DN, T>), dim3(nb),            \
+                                          dim3(kPwThreads), 0, s, g, k, src, img))
+    if (from_l64 && dense) {
+        DG_TO_IMAGE(true, true);
+    } else if (from_l64) {
+        DG_TO_IMAGE(true, false);
+    } else if (dense) {
+        DG_TO_IMAGE(false, true);
     } else {
-        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_image<NN, false, T>), dim3(nb),
-                                              dim3(kPwThreads), 0, s, g, src, img));
+        DG_TO_IMAGE(false, false);
+    }
+#undef DG_TO_IMAGE
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_from_image(const Geom& g, const OpConst<double>& k, const T* img, bool dense,
+                             double* dst, hipStream_t s) {
+    const long cells = (long)g.nx * g.ny;
+    const int nb = pw_blocks(cells, pointwise_block_cap());
+    if (dense) {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image<NN, true, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, k, img, dst));
+    } else {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image<NN, false, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, k, img, dst));
     }
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_from_image(const Geom& g, const T* img, double* dst, hipStream_t s) {
+hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const T* img,
+                                 bool dense, double* z, const double* r, const DevScratch& d,
+                                 hipStream_t s) {
     const long cells = (long)g.nx * g.ny;
     const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image<NN, T>), dim3(nb), dim3(kPwThreads), 0,
-                                          s, g, img, dst));
+    if (dense) {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN, true, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, k, img, z, r, d.sc,
+                                              d.counters + kCntDot, d.partials));
+    } else {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN, false, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, k, img, z, r, d.sc,
+                                              d.counters + kCntDot, d.partials));
+    }
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const T* img,
-                                 double* z, const double* r, const DevScratch& d, hipStream_t s) {
-    const long cells = (long)g.nx * g.ny;
-    const int nb = pw_blocks(cells, pointwise_block_cap());
-    DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN, T>), dim3(nb), dim3(kPwThreads),
-                                          0, s, g, k, img, z, r, d.sc, d.counters + kCntDot,
-                                          d.partials));
+hipError_t launch_dense_divide(int mx, int my, const T* lx, const T* ly, T* c, hipStream_t s) {
+    const int nb = pw_blocks((long)mx * my, pointwise_block_cap());
+    hipLaunchKernelGGL((k_dense_divide<T>), dim3(nb), dim3(kPwThreads), 0, s, mx, my, lx, ly, c);
     return hipGetLastError();
 }
 
@@ -429,11 +508,14 @@ hipError_t launch_fft_mix_y(int n, int Nx, int Ny, int K, const int* cols, const
 }
 
 #define DG_FD_INSTANTIATE(T)                                                                  \
-    template hipError_t launch_to_image<T>(const Geom&, const double*, bool, T*, hipStream_t); \
-    template hipError_t launch_from_image<T>(const Geom&, const T*, double*, hipStream_t);    \
+    template hipError_t launch_to_image<T>(const Geom&, const OpConst<double>&, const double*, \
+                                           bool, bool, T*, hipStream_t);                       \
+    template hipError_t launch_from_image<T>(const Geom&, const OpConst<double>&, const T*,    \
+                                             bool, double*, hipStream_t);                      \
     template hipError_t launch_from_image_dot<T>(const Geom&, const OpConst<double>&,          \
-                                                 const T*, double*, const double*,             \
+                                                 const T*, bool, double*, const double*,       \
                                                  const DevScratch&, hipStream_t);              \
+    template hipError_t launch_dense_divide<T>(int, int, const T*, const T*, T*, hipStream_t); \
     template hipError_t launch_fd_mix_x<T>(int, int, int, int, const int*, const T*, T*,      \
                                            hipStream_t);                                       \
     template hipError_t launch_fd_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \

@@ -97,6 +97,7 @@ def lib():
         "dg_grid_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
         "dg_grid_fd_basis": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp,
                                             ctypes.POINTER(ctypes.c_int)]),
+        "dg_grid_axis_operator": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
         "dg_state_create": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(_vp)]),
         "dg_state_destroy": (None, [_vp]),
         "dg_state_psi": (_vp, [_vp]),
@@ -195,6 +196,16 @@ class Grid:
         _check(lib().dg_grid_fd_basis(self._h, axis, V.ctypes.data_as(_dp),
                                       lam.ctypes.data_as(_dp), ctypes.byref(z)))
         return V.reshape(NN, NN).T.copy(), lam, z.value
+
+    def axis_operator(self, axis=0):
+        """The 1D LDG second derivative of one axis as a dense host numpy
+        array (rows and columns c * n + i)."""
+        import numpy as np
+        N = self.nx if axis == 0 else self.ny
+        NN = N * self.n
+        L = np.empty(NN * NN)
+        _check(lib().dg_grid_axis_operator(self._h, axis, L.ctypes.data_as(_dp)))
+        return L.reshape(NN, NN).T.copy()
 
     def workspace_bytes(self, mode=DG_PREC_FP64):
         b = ctypes.c_size_t()

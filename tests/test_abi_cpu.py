@@ -132,12 +132,14 @@ def test_grid_create_validation():
     with pytest.raises(dg.DgError) as ei:
         dg.Grid(2, 4, 4, bc_x=7)
     assert ei.value.code == dg.DG_E_INVAL
-    # a Dirichlet axis: no preconditioner basis, no tuner, cell tiles of 8
-    # waves only; host-side rejections need no GPU
+    # a Dirichlet axis: no host-built Bloch basis (the periodic axis of the
+    # same grid has one), cell tiles of 8 waves only; host-side rejections
+    # need no GPU
     d = dg.Grid(2, 4, 4, bc_x=dg.DG_BC_DIRICHLET)
     with pytest.raises(dg.DgError) as ei:
         d.fd_basis(0)
     assert ei.value.code == dg.DG_E_UNSUPPORTED
+    assert d.fd_basis(1)[0].shape == (8, 8)
     with pytest.raises(dg.DgError) as ei:
         d.set_tiles(16, 8)
     assert ei.value.code == dg.DG_E_INVAL
@@ -181,6 +183,19 @@ def test_workspace_bytes_and_field_size():
     assert h.workspace_bytes(dg.DG_PREC_FP64) >= 4 * L * 8 + 2 * h.elems * 8
     with pytest.raises(dg.DgError):
         g.workspace_bytes(7)
+    # a Dirichlet axis: two dense work images and per axis the dense
+    # (n N)^2 eigenbasis and n N eigenvalues in FP64 and FP32
+    def dense(N, n):
+        m = N * n
+        return (m * m + m) * (8 + 4)
+    d = dg.Grid(3, 40, 24, bc_y=dg.DG_BC_DIRICHLET)
+    Ld = 24 * 1 * 9 * 64
+    extra = d.workspace_bytes(dg.DG_WS_FD) - d.workspace_bytes(dg.DG_PREC_FP64)
+    assert extra == Ld * 8 + 2 * 8 * 9 * 40 * 24 + dense(40, 3) + dense(24, 3)
+    sq = dg.Grid(2, 16, 16, bc_x=dg.DG_BC_DIRICHLET, bc_y=dg.DG_BC_DIRICHLET)
+    Ls = 16 * 1 * 4 * 64
+    extra = sq.workspace_bytes(dg.DG_WS_FD) - sq.workspace_bytes(dg.DG_PREC_FP64)
+    assert extra == Ls * 8 + 2 * 8 * 4 * 16 * 16 + dense(16, 2)
 
 
 def test_null_arguments_are_rejected():
@@ -219,6 +234,24 @@ def test_fd_basis_diagonalises_the_oracle_operator(n, N, length):
     assert np.ptp(c) <= 1e-12 * np.abs(c).max()
     ref = np.sort(np.linalg.eigvals(L).real)
     np.testing.assert_allclose(np.sort(lam), ref, atol=1e-10 * scale)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("N", [1, 2, 3, 7])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_axis_operator_is_the_oracle_operator(n, N, bc):
+    # The host assembly of the 1D LDG second derivative (the operator the
+    # preconditioner diagonalises, densely on a Dirichlet axis) against the
+    # oracle's sparse 1D operator, built independently from the flux
+    # definitions (Sec. 6 with the jump penalty and the boundary closure)
+    from paper_1311_7477_amd import dg
+    code = {"periodic": dg.DG_BC_PERIODIC, "dirichlet": dg.DG_BC_DIRICHLET}
+    g = dg.Grid(n, N, N + 2, 0.0, 1.7, -1.0, 4.0, code[bc], code[bc])
+    for axis, (Nc, a, b) in enumerate([(N, 0.0, 1.7), (N + 2, -1.0, 4.0)]):
+        ref = O.Grid1D(n, Nc, a, b, bc).laplacian().toarray()
+        got = g.axis_operator(axis)
+        assert got.shape == ref.shape
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
 def test_tile_shapes_default_and_validation():

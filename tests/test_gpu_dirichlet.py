@@ -7,8 +7,12 @@ and Table 3's Dirichlet columns (Sec. 6.1).
 Tolerances: the bracket and the Laplacian element-wise within 1e-12 of
 max |oracle|; the Poisson solve's residual, recomputed with the oracle's
 operator, within 1.5 x rtol, and its solution within 1e-9 of the oracle's
-exact (fast-diagonalisation) one; trajectories within 1e-11 (relative,
-max norm); Table 3's printed errors within 1% (three printed digits)."""
+exact (fast-diagonalisation) one; the preconditioner's apply within
+2e-14 x kappa of the oracle's exact inverse (max norm, relative), with a
+residual at the oracle's own level; the preconditioned solve in at most two
+iterations (four with the FP32 preconditioner); trajectories within 1e-11
+(relative, max norm); Table 3's printed errors within 1% (three printed
+digits)."""
 import math
 
 import numpy as np
@@ -139,9 +143,117 @@ def test_dirichlet_rk3_trajectory(dg, bcs):
     assert np.max(np.abs(got - wr)) <= 1e-11 * np.max(np.abs(wr))
 
 
+PC_CASES = [(1, 9, 7), (2, 16, 16), (3, 37, 23), (4, 13, 29), (5, 24, 24), (3, 1, 5),
+            (2, 2, 2), (4, 64, 40)]
+
+
+def _wn(g, u):
+    return math.sqrt(O.inner(g, u, u))
+
+
+@pytest.mark.parametrize("n,nx,ny", PC_CASES)
+@pytest.mark.parametrize("bcs", BCS)
+def test_dirichlet_precond_apply_parity(dg, n, nx, ny, bcs):
+    # z = (-Lap_h)^-1 r by the dense eigenbases against the oracle's
+    # fast diagonalisation (numpy eigh per axis)
+    print(f"dirichlet precond apply n={n} {nx}x{ny} {bcs}", flush=True)
+    bx, by = bcs
+    g = O.Grid2D(n, nx, ny, 0.0, 2.0, -1.0, 1.5, bx, by)
+    r = I.white_noise(n, nx, ny, seed=5 * n + nx) + 0.7      # the mean stays
+    grid = dg.Grid(n, nx, ny, 0.0, 2.0, -1.0, 1.5, CODE[bx], CODE[by])
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    got = dg.precond_apply(grid, _dev(r), ws).cpu().numpy()
+    fd = O.FastDiagonalisation(g)
+    ref = fd.apply(r)
+    inv = np.abs(fd.inv_mu)
+    kappa = inv.max() / inv.min()
+    assert np.max(np.abs(got - ref)) <= 2e-14 * kappa * np.max(np.abs(ref))
+    # a residual at the level the oracle's own exact inverse reaches
+    floor = _wn(g, r + O.laplacian(g, ref))
+    assert _wn(g, r + O.laplacian(g, got)) <= max(1e-11 * _wn(g, r), 4.0 * floor)
+
+
+@pytest.mark.parametrize("n,nx,ny", PC_CASES)
+@pytest.mark.parametrize("bcs", BCS)
+@pytest.mark.parametrize("mixed", [False, True])
+def test_dirichlet_pcg_parity(dg, n, nx, ny, bcs, mixed):
+    # the preconditioned solve (FP64, or its FP32 preconditioner under the
+    # FP64 iteration) against the oracle's PCG with its exact inverse
+    print(f"dirichlet pcg n={n} {nx}x{ny} {bcs} mixed={mixed}", flush=True)
+    bx, by = bcs
+    g = O.Grid2D(n, nx, ny, 0.0, 2.0, -1.0, 1.5, bx, by)
+    w = I.white_noise(n, nx, ny, seed=n + nx + 1) + 0.5
+    grid = dg.Grid(n, nx, ny, 0.0, 2.0, -1.0, 1.5, CODE[bx], CODE[by])
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    psi = torch.zeros(grid.shape, dtype=torch.float64, device="cuda")
+    rtol = 1e-12
+    opts = dg.cg_opts(rtol=rtol, precond=dg.DG_PRECOND_FD,
+                      precision=dg.DG_PREC_MIXED if mixed else dg.DG_PREC_FP64)
+    res = dg.cg_solve_poisson(grid, _dev(w), psi, ws, opts)
+    fd = O.FastDiagonalisation(g)
+    ref = O.pcg_poisson(g, w, rtol=rtol, precond=fd.apply)
+    assert res.converged and ref.converged
+    if mixed:
+        assert 1 <= res.iters <= 4
+    else:
+        assert res.iters <= 2 and abs(res.iters - ref.iters) <= 1
+    p = psi.cpu().numpy()
+    exact = fd.apply(w)
+    floor = _wn(g, w + O.laplacian(g, exact))
+    assert _wn(g, w + O.laplacian(g, p)) <= max(1.5 * rtol * _wn(g, w), 4.0 * floor)
+    assert _wn(g, p - exact) <= 1e-9 * _wn(g, exact)
+
+
+@pytest.mark.parametrize("bcs", BCS)
+def test_dirichlet_rk3_preconditioned_matches_plain(dg, bcs):
+    # the same SSP-RK3 steps with the plain and the preconditioned solve
+    n, nx, ny, D, dt = 4, 48, 40, 1e-3, 2e-3
+    bx, by = bcs
+    print(f"dirichlet rk3 pcg {bcs}", flush=True)
+    g = O.Grid2D(n, nx, ny, bc_x=bx, bc_y=by)
+    X, Y = g.node_coords()
+    w0 = np.sin(X) * np.sin(Y) + 0.3 * np.sin(2 * X) * np.sin(3 * Y) + 0.1 * np.cos(5 * X)
+    out = {}
+    for pc in (dg.DG_PRECOND_NONE, dg.DG_PRECOND_FD):
+        grid = dg.Grid(n, nx, ny, bc_x=CODE[bx], bc_y=CODE[by])
+        ws, st, w = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD), dg.State(grid), _dev(w0)
+        its = []
+        for _ in range(3):
+            r = dg.rk_step(grid, w, st, ws, dt, D, dg.cg_opts(rtol=1e-13, precond=pc))
+            assert r.converged
+            its += r.cg_iters
+        out[pc] = (w.cpu().numpy(), its)
+    a, b = out[dg.DG_PRECOND_NONE][0], out[dg.DG_PRECOND_FD][0]
+    assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(a))
+    assert max(out[dg.DG_PRECOND_FD][1]) <= 2 < min(out[dg.DG_PRECOND_NONE][1])
+
+
+def test_dirichlet_pcg_full_size(dg):
+    # n = 4, 512^2 cells, both axes Dirichlet: 2048 nodes per axis, the
+    # dense bases from rocSOLVER; sampled against the plain FP64 CG
+    n, N = 4, 512
+    print("dirichlet pcg 512^2", flush=True)
+    w0 = I.random_spectrum(n, N, k0=10.0, seed=1)
+    grid = dg.Grid(n, N, N, bc_x=1, bc_y=1)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    w = _dev(w0)
+    psi = torch.zeros_like(w)
+    rtol = 1e-10
+    res = dg.cg_solve_poisson(grid, w, psi, ws, dg.cg_opts(rtol=rtol, precond=dg.DG_PRECOND_FD))
+    assert res.converged and res.iters <= 2
+    r = w + dg.laplace_apply(grid, psi)
+    wn = lambda u: float(torch.sqrt((u * u).sum()))
+    assert wn(r) <= 1e-9 * wn(w)
+    p0 = torch.zeros_like(w)
+    plain = dg.cg_solve_poisson(grid, w, p0, ws, dg.cg_opts(rtol=rtol))
+    assert plain.converged and plain.iters > 100
+    assert wn(psi - p0) <= 1e-8 * wn(p0)
+
+
 def _table3_gpu(dg, P, N, D):
     # Table 3's experiment (see tests/test_oracle_table3.py) with the GPU
-    # stepper: AB3 started by SSP-RK3, plain CG
+    # stepper: AB3 started by SSP-RK3, CG preconditioned by the dense
+    # eigenbases
     g = O.Grid2D(P, N, N, bc_x="dirichlet", bc_y="dirichlet")
     X, Y = g.node_coords()
     w0 = 2.0 * np.sin(X) * np.sin(Y)
@@ -154,9 +266,11 @@ def _table3_gpu(dg, P, N, D):
     steps = int(math.ceil(2.0 / dt))
     dt = 2.0 / steps
     grid = dg.Grid(P, N, N, bc_x=1, bc_y=1)
-    ws, ab, w = dg.Workspace(grid), dg.AbState(grid, 3), _dev(w0)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    ab, w = dg.AbState(grid, 3), _dev(w0)
+    opts = dg.cg_opts(rtol=1e-12, precond=dg.DG_PRECOND_FD)
     for _ in range(steps):
-        assert dg.ab_step(grid, w, ab, ws, dt, D, dg.cg_opts(rtol=1e-12)).converged
+        assert dg.ab_step(grid, w, ab, ws, dt, D, opts).converged
     d = w.cpu().numpy() - w0 * math.exp(-2.0 * D * 2.0)
     return math.sqrt(O.inner(g, d, d))
 
@@ -181,6 +295,9 @@ def test_dirichlet_grid_rejects_other_paths(dg):
         with pytest.raises(dg.DgError) as e:
             call()
         assert e.value.code == dg.DG_E_UNSUPPORTED
+    # the dense eigenbases stop at 8192 nodes per axis (checked before any
+    # allocation)
+    big = dg.Grid(5, 2000, 8, bc_x=dg.DG_BC_DIRICHLET)
     with pytest.raises(dg.DgError) as e:
-        dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        dg.Workspace(big, dg.DG_PREC_FP64 | dg.DG_WS_FD)
     assert e.value.code == dg.DG_E_UNSUPPORTED
