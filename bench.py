@@ -420,17 +420,42 @@ def form_tune(args):
 
 def form_serve(args):
     """Serving: a seeded Poisson stream of requests (n uniform over {2..5},
-    N log-uniform, random spectra), continuous batching under an HBM budget;
-    latency percentiles, aggregate throughput and an alone-vs-mix check."""
+    N log-uniform over [N_min, N_max], random spectra), continuous batching
+    under an HBM budget; latency percentiles, aggregate throughput and an
+    alone-vs-mix check.  --serve-solver batch: the persistent batched launches
+    with the plain FP64 CG; pcg: a stream per request with the CG
+    preconditioned by fast diagonalisation, its preconditioner in FP32 under
+    the FP64 iteration.  --rate 0 sets the arrival rate to 0.7 x the
+    measured capacity (cell-updates/s of the first four requests run alone,
+    divided by the mean request size)."""
     import numpy as np
     from paper_1311_7477_amd import dg, serve
-    reqs = serve.draw_requests(args.requests, seed=4, rate=args.rate,
-                               N_range=(32, args.N_max), steps=args.req_steps)
-    srv = serve.Server(capacity=64, opts=dg.cg_opts(rtol=1e-10))
+    reqs = serve.draw_requests(args.requests, seed=4, rate=1.0,
+                               N_range=(args.N_min, args.N_max), steps=args.req_steps)
+    if args.serve_solver == "pcg":
+        srv = serve.StreamServer(capacity=64)
+    else:
+        srv = serve.Server(capacity=64, opts=dg.cg_opts(rtol=1e-10))
+    # capacity estimate: the first four requests run alone, one after another
+    t_alone = 0.0
+    serve.run_alone(reqs[0], srv.opts, None)                 # warm-up
+    for r in reqs[:4]:
+        t0 = time.perf_counter()
+        serve.run_alone(r, srv.opts, None)
+        t_alone += time.perf_counter() - t0
+        print(f"[serve] alone: request {r.rid} n={r.n} N={r.N} done", file=sys.stderr,
+              flush=True)
+    capacity = sum(r.cell_updates for r in reqs[:4]) / t_alone
+    mean_size = float(np.mean([r.cell_updates for r in reqs]))
+    rate = args.rate if args.rate > 0 else 0.7 * capacity / mean_size
+    for r in reqs:
+        r.arrival /= rate
     t0 = time.perf_counter()
     done = srv.run(reqs, log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
     makespan = time.perf_counter() - t0
     s = serve.summarize(done, makespan)
+    # alone vs in the mix: the first four finished requests again, alone,
+    # with the tile shapes the server used
     same = [bool(np.array_equal(r.result, serve.run_alone(r, srv.opts,
                                                           srv.tiles.get((r.n, r.N)))))
             for r in done[:4]]
@@ -438,11 +463,18 @@ def form_serve(args):
         "metric": "served DG cell-updates/s (aggregate) with p50/p99 request latency",
         "value": s["aggregate_cell_updates_per_s"], "unit": "cell-updates/s",
         "max_concurrent": srv.max_active, "ticks": srv.ticks,
-        "alone_equals_mix_first4": same, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.requests} requests, Poisson rate {args.rate}/s, "
-                               f"n~U{{2..5}}, N log-uniform [32,{args.N_max}], "
-                               f"{args.req_steps} RK3 steps each, k0~U[4,16], CG rtol 1e-10, "
-                               "HBM budget 80% of free memory, seed 4"},
+        "peak_budgeted_bytes": srv.peak_used, "budget_bytes": srv.budget,
+        "alone_equals_mix_first4": same, "arrival_rate_per_s": rate,
+        "capacity_cell_updates_per_s_alone": capacity,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.requests} requests, Poisson arrivals at {rate:.3g}/s, "
+                               f"n~U{{2..5}}, N log-uniform [{args.N_min},{args.N_max}], "
+                               f"{args.req_steps} RK3 steps each, k0~U[4,16], D=1e-4, "
+                               f"rtol 1e-10, HBM budget 80% of free memory, seed 4",
+                   "solver": ("stream per request, CG preconditioned by fast "
+                              "diagonalisation (FP32 preconditioner, FP64 iteration)"
+                              if args.serve_solver == "pcg" else
+                              "batched persistent launches, plain FP64 CG")},
     })
     print(json.dumps(s), flush=True)
 
@@ -473,6 +505,74 @@ def form_paper(args):
     print(json.dumps({"metric": "bracket time, N=100 (Table 1 shape)", "unit": "ms",
                       "rows": rows, "higher_is_better": False, "dtype": "f64",
                       "data": "synthetic"}), flush=True)
+
+
+def form_dirichlet(args):
+    """The Poisson solve on a grid with homogeneous Dirichlet boundaries on
+    both axes (n = 4, 512^2 cells by default, [0, 2 pi]^2, random-spectrum
+    right-hand side): the preconditioner's setup (dense eigenbases, one
+    rocSOLVER eigensolve per distinct axis), single solves from a zero guess
+    with plain CG, PCG and the FP32-preconditioned PCG (rtol 1e-10), and
+    SSP-RK3 steps with each solver."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    n, N = args.n, args.N
+    omega0, umax = inputs.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
+    dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
+    grid = dg.Grid(n, N, N, bc_x=dg.DG_BC_DIRICHLET, bc_y=dg.DG_BC_DIRICHLET)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    setup_s = time.perf_counter() - t0
+    print(f"[dirichlet] workspace with dense eigenbases: {setup_s:.2f} s", file=sys.stderr,
+          flush=True)
+    w = torch.from_numpy(omega0).cuda()
+    variants = {"plain_fp64": dg.cg_opts(rtol=1e-10),
+                "precond_fp64": dg.cg_opts(rtol=1e-10, precond=dg.DG_PRECOND_FD),
+                "precond_mixed": dg.cg_opts(rtol=1e-10, precond=dg.DG_PRECOND_FD,
+                                            precision=dg.DG_PREC_MIXED)}
+    solves, ref = {}, None
+    for name, opts in variants.items():
+        best = None
+        for _ in range(3):
+            psi = torch.zeros_like(w)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = dg.cg_solve_poisson(grid, w, psi, ws, opts)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        if ref is None:
+            ref = psi
+        solves[name] = {"ms": best * 1e3, "iters": res.iters, "converged": res.converged,
+                        "rel_diff_vs_plain": float((psi - ref).norm() / ref.norm())}
+        print(f"[dirichlet] solve {name}: {solves[name]}", file=sys.stderr, flush=True)
+    steps = {}
+    for name in ("plain_fp64", "precond_fp64", "precond_mixed"):
+        st, wk = dg.State(grid), torch.from_numpy(omega0).cuda()
+        k_steps = 2 if name == "plain_fp64" else 50
+        dg.rk_step(grid, wk, st, ws, dt, 1e-4, variants[name])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for _ in range(k_steps):
+            r = dg.rk_step(grid, wk, st, ws, dt, 1e-4, variants[name])
+            its += r.cg_iters
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        steps[name] = {"value": N * N * 3 * k_steps / T, "unit": "cell-updates/s",
+                       "steps": k_steps, "cg_iters_per_rhs": statistics.mean(its)}
+        print(f"[dirichlet] rk3 {name}: {steps[name]}", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "Poisson solve and RK3 steps on a Dirichlet grid", "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"n={n}, {N}x{N} cells, [0,2pi]^2, homogeneous Dirichlet on "
+                                f"both axes, random-spectrum omega0 (k0=10, seed 1), rtol "
+                                f"1e-10, D=1e-4, dt={dt:.4e}")},
+        "setup_seconds": setup_s,
+        "workspace_bytes": grid.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD),
+        "precond_flops_per_apply": 2 * (n * N) ** 2 * (2 * n * N) * 2,
+        "solves": solves, "rk3": steps}), flush=True)
 
 
 def form_turbulence(args):
@@ -609,7 +709,7 @@ def main():
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     ap.add_argument("--form", default="rhs",
                     choices=["rhs", "batch", "mixed", "serve", "paper", "tune", "lamb",
-                             "table3", "turbulence"],
+                             "table3", "turbulence", "dirichlet"],
                     help="rhs: the headline metric (default); the others measure "
                          "the batched, mixed-precision and served forms and the "
                          "paper's bracket-timing shape")
@@ -621,8 +721,15 @@ def main():
                     help="--form turbulence: RK3 steps per run")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--N-max", dest="N_max", type=int, default=256)
+    ap.add_argument("--N-min", dest="N_min", type=int, default=32,
+                    help="--form serve: smallest grid of the request stream")
+    ap.add_argument("--serve-solver", dest="serve_solver", default="batch",
+                    choices=["batch", "pcg"],
+                    help="--form serve: batched plain CG, or a stream per request with "
+                         "the FP32-preconditioned CG")
     ap.add_argument("--requests", type=int, default=16)
-    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--rate", type=float, default=20.0,
+                    help="--form serve: arrivals per second (0: 0.7 x measured capacity)")
     ap.add_argument("--req-steps", dest="req_steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -639,7 +746,8 @@ def main():
     if args.form != "rhs":
         {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
          "paper": form_paper, "tune": form_tune, "lamb": form_lamb,
-         "table3": form_table3, "turbulence": form_turbulence}[args.form](args)
+         "table3": form_table3, "turbulence": form_turbulence,
+         "dirichlet": form_dirichlet}[args.form](args)
         return
     n, N = args.n, args.N
     if args.copy_calibration:

@@ -12,14 +12,23 @@ batching.  Finished requests leave the batch at once and free their memory.
 
 Because a batch runs every instance with the same device code and block
 decomposition as a stand-alone run, a request's result is bitwise the same
-whatever else was in flight.  All scheduling is host logic here; every
-computation runs in the HIP library.
+whatever else was in flight.
+
+StreamServer runs the same loop with another engine: every admitted request
+owns a workspace with the fast-diagonalisation preconditioner and a HIP
+stream, and a tick issues one dg_rk_step per active request from a pool of
+host threads, so the requests' kernels overlap on the device; the solve is
+the preconditioned CG with its preconditioner applied in FP32 under the FP64
+iteration (rtol 1e-10 by default).  A request again gets the result of the
+same steps run alone.  All scheduling is host logic here; every computation
+runs in the HIP library.
 """
 from __future__ import annotations
 
 import collections
 import math
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -48,6 +57,9 @@ class Request:
     grid: object = None
     slot: int = -1
     done_steps: int = 0
+    ws: object = None         # StreamServer: workspace, state and stream
+    state: object = None
+    stream: object = None
 
     @property
     def latency(self) -> float:
@@ -101,7 +113,7 @@ class Server:
         self.budget = hbm_budget
         self.capacity = capacity
         self.opts = opts if opts is not None else dg.cg_opts(rtol=1e-10)
-        self.batch = dg.Batch(capacity)
+        self.batch = self._engine()
         self.used = 0
         self.active = {}
         self.ticks = 0
@@ -110,6 +122,12 @@ class Server:
         self.rejected = []
         self.tune = tune
         self.tiles = {}           # (n, N) -> (cell tile height, bracket tile height)
+
+    def _engine(self):
+        return dg.Batch(self.capacity)
+
+    def request_bytes(self, req: Request) -> int:
+        return member_bytes(req.n, req.N)
 
     def fits(self, req: Request) -> bool:
         return (len(self.active) < self.capacity and
@@ -153,7 +171,7 @@ class Server:
         """Serve an arrival stream in real time; returns the finished
         requests.  Requests larger than the whole budget are rejected."""
         for r in requests:
-            r.bytes = member_bytes(r.n, r.N)
+            r.bytes = self.request_bytes(r)
         reqs = sorted(requests, key=lambda r: r.arrival)
         rejected = [r for r in reqs if r.bytes > self.budget]
         todo = collections.deque(r for r in reqs if r.bytes <= self.budget)
@@ -176,6 +194,82 @@ class Server:
                 time.sleep(max(0.0, min(todo[0].arrival - now(), 0.05)))
         self.rejected = rejected
         return [r for r in reqs if not math.isnan(r.finished)]
+
+
+class StreamServer(Server):
+    """The request loop of Server with one stream per request: admission
+    creates the request's grid, a DG_WS_FD workspace (the preconditioner's
+    bases and plans), its state and a HIP stream; a tick runs one
+    dg_rk_step of every active request, each issued from a worker thread
+    on that request's stream (the library's calls release the GIL, and each
+    one waits only for its own stream).  Default solve: CG preconditioned by
+    fast diagonalisation, the preconditioner in FP32 under the FP64
+    iteration, rtol 1e-10."""
+
+    def __init__(self, capacity=64, hbm_budget=None, opts=None, tune=False, workers=16):
+        if opts is None:
+            opts = dg.cg_opts(rtol=1e-10, precond=dg.DG_PRECOND_FD,
+                              precision=dg.DG_PREC_MIXED)
+        self.workers = workers
+        super().__init__(capacity, hbm_budget, opts, tune)
+
+    def _engine(self):
+        return ThreadPoolExecutor(self.workers)
+
+    def request_bytes(self, req: Request) -> int:
+        """Workspace (with the preconditioner), state (three fields) and
+        omega; rocBLAS and rocFFT keep their work buffers on top."""
+        g = dg.Grid(req.n, req.N, req.N)
+        return g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD) + 4 * g.elems * 8
+
+    def admit(self, req: Request, now: float):
+        import torch
+        w0 = prepare(req)
+        req.grid = dg.Grid(req.n, req.N, req.N)
+        key = (req.n, req.N)
+        req.stream = torch.cuda.Stream()
+        with torch.cuda.stream(req.stream):
+            req.omega = torch.from_numpy(w0).cuda()
+            if self.tune and key not in self.tiles:
+                self.tiles[key] = req.grid.tune(req.omega, reps=5)[0]
+            if key in self.tiles:
+                req.grid.set_tiles(*self.tiles[key])
+            req.ws = dg.Workspace(req.grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+            req.state = dg.State(req.grid)
+        req.slot = req.rid
+        req.admitted = now
+        self.used += req.bytes
+        self.peak_used = max(self.peak_used, self.used)
+        self.active[req.slot] = req
+        self.max_active = max(self.max_active, len(self.active))
+
+    def retire(self, req: Request, now: float):
+        req.stream.synchronize()
+        req.result = req.omega.cpu().numpy()
+        self.used -= req.bytes
+        del self.active[req.slot]
+        req.omega = req.grid = req.ws = req.state = req.stream = None
+        req.finished = now
+
+    def _step(self, req: Request):
+        import torch
+        with torch.cuda.stream(req.stream):
+            r = dg.rk_step(req.grid, req.omega, req.state, req.ws, req.dt, req.D, self.opts)
+        if not r.converged:
+            raise RuntimeError(f"request {req.rid}: the solve did not converge")
+        return r
+
+    def tick(self, now_fn):
+        futures = {slot: self.batch.submit(self._step, req)
+                   for slot, req in self.active.items()}
+        self.ticks += 1
+        for slot, f in futures.items():
+            r = f.result()
+            req = self.active[slot]
+            req.cg_iters.extend(r.cg_iters)
+            req.done_steps += 1
+            if req.done_steps >= req.steps:
+                self.retire(req, now_fn())
 
 
 def summarize(done, makespan):
@@ -203,7 +297,9 @@ def run_alone(req: Request, opts=None, tiles=None):
     grid = dg.Grid(req.n, req.N, req.N)
     if tiles is not None:
         grid.set_tiles(*tiles)
-    ws, st = dg.Workspace(grid), dg.State(grid)
+    precond = opts is not None and opts.precond != dg.DG_PRECOND_NONE
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | (dg.DG_WS_FD if precond else 0))
+    st = dg.State(grid)
     w = torch.from_numpy(w0).cuda()
     for _ in range(req.steps):
         dg.rk_step(grid, w, st, ws, req.dt, req.D,

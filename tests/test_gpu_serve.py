@@ -1,7 +1,9 @@
 """Serving loop: requests that arrive while others run are admitted between
 steps (continuous batching), every result equals the same request run
 alone (bitwise, since a batch runs each instance with the stand-alone
-device code), and a small HBM budget forces queueing instead of failure."""
+device code), and a small HBM budget forces queueing instead of failure;
+the same for the stream-per-request server with the FP32-preconditioned CG
+(its results equal the stand-alone steps bitwise too)."""
 import math
 
 import numpy as np
@@ -65,3 +67,35 @@ def test_oversized_request_is_rejected(serve):
     done = srv.run(reqs)
     assert done == [] and len(srv.rejected) == 2
     assert all(math.isnan(r.finished) for r in reqs)
+
+
+def test_stream_server_pcg_equals_alone(serve):
+    # one stream per request, the FP32-preconditioned CG, steps issued from
+    # worker threads: every result equals the same request run alone
+    from paper_1311_7477_amd import dg
+    reqs = serve.draw_requests(8, seed=5, rate=200.0, N_range=(16, 96),
+                               k0_range=(2.0, 5.0), steps=4)
+    srv = serve.StreamServer(capacity=8, workers=4)
+    assert srv.opts.precond == dg.DG_PRECOND_FD and srv.opts.precision == dg.DG_PREC_MIXED
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert srv.max_active > 1
+    for r in done:
+        assert all(1 <= k <= 4 for k in r.cg_iters), r.cg_iters
+        alone = serve.run_alone(r, srv.opts)
+        assert np.array_equal(r.result, alone), \
+            f"request {r.rid}: differs by {np.abs(r.result - alone).max():.3e}"
+    assert not srv.active and srv.used == 0
+
+
+def test_stream_server_budget_queues(serve):
+    reqs = serve.draw_requests(4, seed=6, rate=1000.0, N_range=(16, 48),
+                               k0_range=(2.0, 5.0), steps=2)
+    probe = serve.StreamServer(capacity=1)
+    biggest = max(probe.request_bytes(r) for r in reqs)
+    srv = serve.StreamServer(capacity=8, hbm_budget=biggest, workers=2)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert srv.peak_used <= biggest and srv.max_active < len(reqs)
+    order = [r.rid for r in sorted(done, key=lambda r: r.admitted)]
+    assert order == sorted(order)
