@@ -231,3 +231,45 @@ def test_precond_errors(dg):
     with pytest.raises(dg.DgError) as e:
         b.rk_step(dg.cg_opts(precond=dg.DG_PRECOND_FD))
     assert e.value.code == dg.DG_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("D", [0.0, 1e-4])
+def test_full_size_turbulence_invariants(dg, D):
+    # The decaying-turbulence workload at its full size (n = 4, 512^2,
+    # k0 = 10, seed 1, CFL 0.1) for 20 SSP-RK3 steps with the preconditioned
+    # solve: the device invariants equal the oracle's sums of the same
+    # fields; V stays at roundoff; with D = 0 E and Omega change only by the
+    # time-stepping error (~1e-15 per step, relative), with D > 0 both
+    # decrease at every step (dOmega/dt = D <omega, Lap_h omega>_W <= 0).
+    n, N = 4, 512
+    print(f"full-size invariants D={D}", flush=True)
+    w0, umax = I.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
+    dt = I.cfl_dt(n, N, umax, cfl=0.1)
+    g = O.Grid2D(n, N, N)
+    grid = dg.Grid(n, N, N)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    opts = dg.cg_opts(rtol=1e-12, precond=dg.DG_PRECOND_FD)
+    st, w = dg.State(grid), _dev(w0)
+
+    def invariants():
+        psi = torch.zeros_like(w)
+        assert dg.cg_solve_poisson(grid, w, psi, ws, opts).converged
+        return dg.invariants(grid, w, psi, ws), psi
+    (V0, E0, Om0), psi = invariants()
+    Vr, Er, Omr = O.invariants(g, w0, psi.cpu().numpy())
+    assert abs(V0 - Vr) <= 1e-12 and abs(E0 - Er) <= 1e-12 * Er and abs(Om0 - Omr) <= 1e-12 * Omr
+    hist = [(E0, Om0)]
+    for _ in range(20):
+        assert dg.rk_step(grid, w, st, ws, dt, D, opts).converged
+        (V, E, Om), _ = invariants()
+        hist.append((E, Om))
+        assert abs(V) <= 1e-12 * math.sqrt(Om0)
+    E, Om = hist[-1]
+    if D == 0.0:
+        assert abs(E - E0) <= 1e-11 * E0 and abs(Om - Om0) <= 1e-11 * Om0
+    else:
+        assert all(b[1] < a[1] and b[0] < a[0] for a, b in zip(hist, hist[1:]))
+        # the enstrophy lost over 20 steps against its initial rate
+        # D <omega, Lap_h omega>_W (the rate changes little over 20 dt)
+        rate0 = D * O.inner(g, w0, O.laplacian(g, w0))
+        assert 0.5 <= (Om - Om0) / (20 * dt * rate0) <= 2.0
