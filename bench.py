@@ -576,6 +576,10 @@ def form_dirichlet(args):
 
 
 def form_turbulence(args):
+    print(json.dumps(turbulence_runs(args)), flush=True)
+
+
+def turbulence_runs(args):
     """The full decaying-turbulence run: n = 4, 512^2 periodic cells,
     random-spectrum omega0 (k0 = 10, seed 1), CFL 0.1, `--run-steps` SSP-RK3
     steps (default 2000) for D = 0 and D = 1e-4 after 50 warm-up steps, CG
@@ -638,15 +642,16 @@ def form_turbulence(args):
                          "mean": statistics.mean(stage_ms)},
                      "cg_iters_per_rhs": {"mean": statistics.mean(iters), "max": max(iters)},
                      "invariants": track})
-    print(json.dumps({
+    return {
         "metric": "decaying turbulence run: invariants and throughput",
         "unit": "cell-updates/s", "dtype": "f64", "data": "synthetic",
         "config": {"workload": (f"decaying 2D turbulence, periodic [0,2pi]^2, n={n}, "
                                 f"{N}x{N} cells, random-spectrum omega0 (k0=10, seed 1), "
-                                f"dt={dt:.4e} (CFL 0.1), SSP-RK3, PCG (fast "
-                                f"diagonalisation) rtol {args.rtol}, extrapolated guess"),
+                                f"dt={dt:.4e} (CFL 0.1), SSP-RK3, {args.run_steps} steps "
+                                f"after 50 warm-up steps, PCG (fast diagonalisation) rtol "
+                                f"{args.rtol}, extrapolated guess"),
                    "n": n, "Nx": N, "Ny": N},
-        "runs": runs}), flush=True)
+        "runs": runs}
 
 
 def precond_leg(args, omega0, dt, tiles):
@@ -718,7 +723,9 @@ def main():
                          "the plain mixed form does not reach rtol 1e-10 beyond 128^2 "
                          "cells at n = 5")
     ap.add_argument("--run-steps", dest="run_steps", type=int, default=2000,
-                    help="--form turbulence: RK3 steps per run")
+                    help="RK3 steps of the full decaying-turbulence runs (--form turbulence, "
+                         "and the preconditioned full-run leg of the default form; 0 skips "
+                         "that leg)")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--N-max", dest="N_max", type=int, default=256)
     ap.add_argument("--N-min", dest="N_min", type=int, default=32,
@@ -859,6 +866,11 @@ def main():
     }
     if not args.no_precond:
         out["preconditioned"] = precond_leg(args, omega0, dt, tiles)
+        if args.run_steps > 0:
+            # the whole run (2000 steps by default, for D = 0 and D = 1e-4)
+            # with the preconditioned solve: per-RHS device times over every
+            # RHS, and the invariant drift
+            out["full_run_preconditioned"] = turbulence_runs(args)
     if not args.no_cpu_baseline:
         psi0 = st.psi().cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(n, N, w.cpu().numpy(), psi0, args.D, dt,

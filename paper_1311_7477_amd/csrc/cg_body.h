@@ -149,12 +149,21 @@ struct YFaces {
 // on the axes the grid marks (the last cell drops its outer coupling, the
 // first cell uses L0B / eRB and drops its outer coupling, and it is seen by
 // the second cell through lLB); the periodic kernels do not carry it.
-// ISO: square cells on two periodic axes, whose x and y blocks coincide --
-// the y operator reads the x tables (half the constants held in registers).
+// ISO: square cells and the same boundary kind on both axes, whose x and y
+// blocks coincide -- the y operator reads the x tables (half the constants
+// held in registers).
 template <int N, int WV, bool DIR = false, bool ISO = false, class T, class Src>
 __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
                                          const Src& src, const T (&u)[N * N],
                                          YFaces<N, T, WV>& lds, T (&out)[N * N]) {
+    // The Dirichlet tables of the first cells (L0B, eRB, lLB) are chosen by
+    // per-lane conditions.  Selecting a table pointer per lane would make
+    // the compiler hold a per-lane copy of the selected constants; instead
+    // every use sits in a branch whose table is the same for all its lanes
+    // (a kernel-argument constant), and only waves holding a first or second
+    // cell of a Dirichlet axis run the extra branch.
+    const T* lLy = ISO ? k.lLx : k.lLy;
+    const T* lLBy = ISO ? k.lLBx : k.lLBy;
     T hR[N], hL[N], hU[N], hD[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) hR[m] = hL[m] = hU[m] = hD[m] = 0;
@@ -167,9 +176,13 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     if (c.active && !c.yin_d) {
         T h[N * N];
         src(c.d, h);
-        const T* lf = (DIR && c.sec_y) ? k.lLBy : (ISO ? k.lLx : k.lLy);
+        if (DIR && c.sec_y) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, lf);
+            for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, lLBy);
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) hD[i] = ydot<N>(h, i, lLy);
+        }
     }
     if (c.active && !c.xin_r) {
         T h[N * N];
@@ -180,29 +193,49 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
     if (c.active && !c.xin_l) {
         T h[N * N];
         src(c.l, h);
-        const T* lf = (DIR && c.sec_x) ? k.lLBx : k.lLx;
+        if (DIR && c.sec_x) {
 #pragma unroll
-        for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, lf);
+            for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lLBx);
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j) hL[j] = xdot<N>(h, j, k.lLx);
+        }
     }
     // publish this cell's y face scalars
-    const T* lfy = (DIR && c.lo_y) ? k.lLBy : (ISO ? k.lLx : k.lLy);
+    {
+        T dn[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        lds.v[((c.wave * 2 + 0) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lR);
-        lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = ydot<N>(u, i, lfy);
+        for (int i = 0; i < N; ++i) dn[i] = ydot<N>(u, i, lLy);
+        if (DIR && c.lo_y) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) dn[i] = ydot<N>(u, i, lLBy);
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            lds.v[((c.wave * 2 + 0) * N + i) * 64 + c.lane] = ydot<N>(u, i, k.lR);
+            lds.v[((c.wave * 2 + 1) * N + i) * 64 + c.lane] = dn[i];
+        }
     }
     // x face scalars from the neighbouring lanes
-    const T* lfx = (DIR && c.lo_x) ? k.lLBx : k.lLx;
     T fR[N], fL[N];
+    {
+        T lf[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const T a = __shfl(xdot<N>(u, j, k.lR), c.lane + 1);
-        const T b = __shfl(xdot<N>(u, j, lfx), c.lane - 1);
-        fR[j] = c.xin_r ? a : hR[j];
-        fL[j] = c.xin_l ? b : hL[j];
-        if (DIR) {
-            if (c.hi_x) fR[j] = 0;
-            if (c.lo_x) fL[j] = 0;
+        for (int j = 0; j < N; ++j) lf[j] = xdot<N>(u, j, k.lLx);
+        if (DIR && c.lo_x) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) lf[j] = xdot<N>(u, j, k.lLBx);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const T a = __shfl(xdot<N>(u, j, k.lR), c.lane + 1);
+            const T b = __shfl(lf[j], c.lane - 1);
+            fR[j] = c.xin_r ? a : hR[j];
+            fL[j] = c.xin_l ? b : hL[j];
+            if (DIR) {
+                if (c.hi_x) fR[j] = 0;
+                if (c.lo_x) fL[j] = 0;
+            }
         }
     }
     __syncthreads();
@@ -216,23 +249,34 @@ __device__ __forceinline__ void lap_cell(const CellCtx& c, const OpConst<T>& k,
             if (c.lo_y) fD[i] = 0;
         }
     }
-    const T* L0x = (DIR && c.lo_x) ? k.L0Bx : k.L0x;
-    const T* L0y = (DIR && c.lo_y) ? k.L0By : (ISO ? k.L0x : k.L0y);
-    const T* eRx = (DIR && c.lo_x) ? k.eRBx : k.eRx;
-    const T* eRy = (DIR && c.lo_y) ? k.eRBy : (ISO ? k.eRx : k.eRy);
+    auto combine = [&](const T* L0x, const T* eRx, const T* L0y, const T* eRy) {
 #pragma unroll
-    for (int j = 0; j < N; ++j)
+        for (int j = 0; j < N; ++j)
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T lx = fmx(eRx[i], fR[j], k.eL[i] * fL[j]);
-            T ly = fmx(eRy[j], fU[i], k.eL[j] * fD[i]);
+            for (int i = 0; i < N; ++i) {
+                T lx = fmx(eRx[i], fR[j], k.eL[i] * fL[j]);
+                T ly = fmx(eRy[j], fU[i], k.eL[j] * fD[i]);
 #pragma unroll
-            for (int m = 0; m < N; ++m) {
-                lx = fmx(L0x[i * N + m], u[j * N + m], lx);
-                ly = fmx(L0y[j * N + m], u[m * N + i], ly);
+                for (int m = 0; m < N; ++m) {
+                    lx = fmx(L0x[i * N + m], u[j * N + m], lx);
+                    ly = fmx(L0y[j * N + m], u[m * N + i], ly);
+                }
+                out[j * N + i] = fmx(lx, k.ihx2, ly * k.ihy2);
             }
-            out[j * N + i] = fmx(lx, k.ihx2, ly * k.ihy2);
-        }
+    };
+    const T* L0y = ISO ? k.L0x : k.L0y;
+    const T* eRy = ISO ? k.eRx : k.eRy;
+    const T* L0By = ISO ? k.L0Bx : k.L0By;
+    const T* eRBy = ISO ? k.eRBx : k.eRBy;
+    if (!DIR || !(c.lo_x || c.lo_y)) {
+        combine(k.L0x, k.eRx, L0y, eRy);
+    } else if (c.lo_x && c.lo_y) {
+        combine(k.L0Bx, k.eRBx, L0By, eRBy);
+    } else if (c.lo_x) {
+        combine(k.L0Bx, k.eRBx, L0y, eRy);
+    } else {
+        combine(k.L0x, k.eRx, L0By, eRBy);
+    }
 }
 
 // <a, b>_W over one cell, accumulated in FP64

@@ -67,19 +67,28 @@ __global__ __launch_bounds__(64 * WV) void k_mixed_replace(
 int cell_blocks(const Geom& g) { return CellLaunch(g).nblocks; }
 
 // A grid with a homogeneous Dirichlet axis runs the DIR variants, built for
-// 64 x 8 cell tiles only; a periodic grid of square cells the ISO variants
-// (identical x and y blocks).
+// 64 x 8 cell tiles only; square cells with the same boundary kind on both
+// axes run the ISO variants (identical x and y blocks).
 bool dirichlet(const Geom& g) { return g.bcx || g.bcy; }
 bool iso(const Geom& g, const OpConst<double>& k) { return !dirichlet(g) && k.ihx == k.ihy; }
+bool iso_dir(const Geom& g, const OpConst<double>& k) {
+    return g.bcx && g.bcy && k.ihx == k.ihy;
+}
 
 hipError_t launch_laplace(const Geom& g, const OpConst<double>& k,
                           const double* u, double* out, hipStream_t s) {
     CellLaunch L(g);
     if (dirichlet(g)) {
         if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
-        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_laplace<NN, kDirichletCellWaves, true, false>),
-                                              dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
-                                              0, s, g, L.tilesX, L.nblocks, k, u, out));
+        if (iso_dir(g, k)) {
+            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_laplace<NN, kDirichletCellWaves, true, true>),
+                                                  dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
+                                                  0, s, g, L.tilesX, L.nblocks, k, u, out));
+        } else {
+            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_laplace<NN, kDirichletCellWaves, true, false>),
+                                                  dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
+                                                  0, s, g, L.tilesX, L.nblocks, k, u, out));
+        }
         return hipGetLastError();
     }
     if (iso(g, k)) {
@@ -103,11 +112,19 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
     CellLaunch L(g);
     if (dirichlet(g)) {
         if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
-        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN, kDirichletCellWaves, true, false>),
-                                              dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
-                                              0, s, g, L.tilesX, L.nblocks, k, omega, pa, pb,
-                                              ca, cb, x, r, d.sc, d.counters + kCntInit,
-                                              d.partials));
+        if (iso_dir(g, k)) {
+            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN, kDirichletCellWaves, true, true>),
+                                                  dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
+                                                  0, s, g, L.tilesX, L.nblocks, k, omega, pa, pb,
+                                                  ca, cb, x, r, d.sc, d.counters + kCntInit,
+                                                  d.partials));
+        } else {
+            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN, kDirichletCellWaves, true, false>),
+                                                  dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
+                                                  0, s, g, L.tilesX, L.nblocks, k, omega, pa, pb,
+                                                  ca, cb, x, r, d.sc, d.counters + kCntInit,
+                                                  d.partials));
+        }
         return hipGetLastError();
     }
     if (iso(g, k)) {
@@ -133,11 +150,19 @@ hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* 
     if (dirichlet(g)) {
         if constexpr (std::is_same<S, double>::value) {
             if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
-            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S, kDirichletCellWaves, true, false>),
-                                                  dim3(L.nblocks),
-                                                  dim3(64 * kDirichletCellWaves), 0, s, g,
-                                                  L.tilesX, L.nblocks, k, r, p0, p1, x, sc,
-                                                  d.counters + kCntDir, d.partials));
+            if (iso_dir(g, k)) {
+                DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S, kDirichletCellWaves, true, true>),
+                                                      dim3(L.nblocks),
+                                                      dim3(64 * kDirichletCellWaves), 0, s, g,
+                                                      L.tilesX, L.nblocks, k, r, p0, p1, x, sc,
+                                                      d.counters + kCntDir, d.partials));
+            } else {
+                DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S, kDirichletCellWaves, true, false>),
+                                                      dim3(L.nblocks),
+                                                      dim3(64 * kDirichletCellWaves), 0, s, g,
+                                                      L.tilesX, L.nblocks, k, r, p0, p1, x, sc,
+                                                      d.counters + kCntDir, d.partials));
+            }
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
@@ -165,11 +190,19 @@ hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S
     if (dirichlet(g)) {
         if constexpr (std::is_same<S, double>::value) {
             if (g.cw != kDirichletCellWaves) return hipErrorInvalidValue;
-            DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S, kDirichletCellWaves, true, false>),
-                                                  dim3(L.nblocks),
-                                                  dim3(64 * kDirichletCellWaves), 0, s, g,
-                                                  L.tilesX, L.nblocks, k, p0, p1, r, sc,
-                                                  d.counters + kCntRes, d.partials));
+            if (iso_dir(g, k)) {
+                DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S, kDirichletCellWaves, true, true>),
+                                                      dim3(L.nblocks),
+                                                      dim3(64 * kDirichletCellWaves), 0, s, g,
+                                                      L.tilesX, L.nblocks, k, p0, p1, r, sc,
+                                                      d.counters + kCntRes, d.partials));
+            } else {
+                DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S, kDirichletCellWaves, true, false>),
+                                                      dim3(L.nblocks),
+                                                      dim3(64 * kDirichletCellWaves), 0, s, g,
+                                                      L.tilesX, L.nblocks, k, p0, p1, r, sc,
+                                                      d.counters + kCntRes, d.partials));
+            }
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
