@@ -12,12 +12,16 @@
 //   * only the edge lanes / edge waves of a tile load a halo cell.
 //
 // The CG vectors x, r, p live in a lane-interleaved layout ("L64"): cells
-// are grouped by 64 along x and stored node-major inside a group,
-//   element (cy, cx, node e) at ((cy * G + cx / 64) * n*n + e) * 64 + cx % 64,
-// G = ceil(nx / 64), so every wave-wide load or store of one node touches
-// 512 contiguous bytes.  Fields that cross the library boundary (omega, the
-// guess, psi) keep the canonical [cy][cx][j][i] layout and are converted at
-// the start and the end of a solve.
+// are grouped by 64 along x, and inside a group the nodes are stored in
+// pairs, node pair m of all 64 cells before pair m + 1,
+//   node e of cell (cy, cx) at (cy * G + cx / 64) * 64 n^2 + (e / 2) * 128
+//                              + 2 (cx % 64) + e % 2
+// (an odd last node alone, at + (n^2 / 2) * 128 + cx % 64), G = ceil(nx / 64),
+// so a lane moves two nodes of its cell per 16-byte access and every
+// wave-wide access touches 1024 contiguous bytes (l64_at in dg_device.h).
+// Fields that cross the library boundary (omega, the guess, psi) keep the
+// canonical [cy][cx][j][i] layout and are converted at the start and the end
+// of a solve.
 #pragma once
 
 #include "dg_device.h"
@@ -27,7 +31,7 @@ namespace dgk {
 
 struct CellRef {
     long canon;   // canonical offset of node 0 (node e at +e)
-    long l64;     // L64 offset of node 0 (node e at +64 e)
+    long l64;     // L64 offset of the cell (node e at l64_at(l64, e))
 };
 
 struct CellCtx {
@@ -99,18 +103,37 @@ __device__ __forceinline__ void st_canon(T* __restrict__ f, const CellRef& c,
 
 // L64 loads and stores convert between the storage type S of a CG vector
 // and the FP64 arithmetic of the kernels.
+template <class S> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
 template <int N, class S, class C>
 __device__ __forceinline__ void ld_l64(const S* __restrict__ f, const CellRef& c,
                                        C (&u)[N * N]) {
+    using V = typename Pair2<S>::type;
+    constexpr int P = (N * N) & ~1;
 #pragma unroll
-    for (int e = 0; e < N * N; ++e) u[e] = (C)f[c.l64 + 64 * e];
+    for (int e = 0; e < P; e += 2) {
+        const V v = *reinterpret_cast<const V*>(f + l64_at<N>(c.l64, e));
+        u[e] = (C)v.x;
+        u[e + 1] = (C)v.y;
+    }
+    if (P < N * N) u[N * N - 1] = (C)f[l64_at<N>(c.l64, N * N - 1)];
 }
 
 template <int N, class S, class C>
 __device__ __forceinline__ void st_l64(S* __restrict__ f, const CellRef& c,
                                        const C (&u)[N * N]) {
+    using V = typename Pair2<S>::type;
+    constexpr int P = (N * N) & ~1;
 #pragma unroll
-    for (int e = 0; e < N * N; ++e) f[c.l64 + 64 * e] = (S)u[e];
+    for (int e = 0; e < P; e += 2) {
+        V v;
+        v.x = (S)u[e];
+        v.y = (S)u[e + 1];
+        *reinterpret_cast<V*>(f + l64_at<N>(c.l64, e)) = v;
+    }
+    if (P < N * N) f[l64_at<N>(c.l64, N * N - 1)] = (S)u[N * N - 1];
 }
 
 // Round a value to the storage type S and back: the value a stored vector

@@ -31,8 +31,12 @@ __global__ __launch_bounds__(64 * WV) void k_cg_init(
                              r, sc, counter, partials, lds);
 }
 
+// At n = 4 the periodic direction and residual kernels are held to 128
+// VGPRs (four waves per SIMD): with the paired 16-byte accesses they would
+// take 132 / 134 and drop to three, which costs more than the 20 bytes per
+// lane the residual kernel then spills.
 template <int N, class S, int WV, bool DIR, bool ISO>
-__global__ __launch_bounds__(64 * WV) void k_cg_dir(
+__global__ __launch_bounds__(64 * WV, (N == 4 && !DIR) ? 4 : 1) void k_cg_dir(
     Geom g, int tilesX, int nblocks, OpConst<double> k, const S* __restrict__ r,
     S* p0, S* p1, double* __restrict__ x, CgScalars* sc, unsigned* counter,
     double* partials) {
@@ -42,7 +46,7 @@ __global__ __launch_bounds__(64 * WV) void k_cg_dir(
 }
 
 template <int N, class S, int WV, bool DIR, bool ISO>
-__global__ __launch_bounds__(64 * WV) void k_cg_res(
+__global__ __launch_bounds__(64 * WV, (N == 4 && !DIR) ? 4 : 1) void k_cg_res(
     Geom g, int tilesX, int nblocks, OpConst<double> k, const S* p0, const S* p1,
     S* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
     __shared__ YFaces<N, double, WV> lds;

@@ -149,4 +149,17 @@ inline int pw_blocks(long rows, int cap) {
     return (int)b;
 }
 
+
+// Node e of the cell whose lane-interleaved offset is l64 (group base + lane,
+// the group base a multiple of 64 n^2): nodes are stored in pairs, so a
+// lane's nodes 2m and 2m + 1 are adjacent ([m][lane][2]) and one 16-byte
+// access (8 bytes in FP32) moves both; an odd last node follows alone.
+template <int N>
+__device__ __forceinline__ long l64_at(long l64, int e) {
+    constexpr int P = (N * N) & ~1;
+    const long lane = l64 & 63, base = l64 - lane;
+    return e < P ? base + (long)(e >> 1) * 128 + 2 * lane + (e & 1)
+                 : base + (long)(P >> 1) * 128 + lane;
+}
+
 }  // namespace dgk

@@ -24,7 +24,7 @@ int stencil_blocks(const Geom& g);
 int pointwise_block_cap();
 
 // Elements of one CG vector in the lane-interleaved layout (cells grouped by
-// 64 along x, node-major inside a group): ny * ceil(nx/64) * n*n * 64.
+// 64 along x, node pairs inside a group): ny * ceil(nx/64) * n*n * 64.
 inline size_t l64_elems(const Geom& g) {
     return (size_t)g.ny * (size_t)((g.nx + 63) / 64) * (size_t)(g.n * g.n) * 64;
 }

@@ -102,8 +102,8 @@ __device__ __forceinline__ void cg_finish_body(int b, int nb, Geom g, const OpCo
         for (int e = 0; e < N * N; ++e) {
             double a = 0.0;
             if (!zero) {
-                a = x[l64 + 64 * e];
-                if (pending) a = fmx(alpha, (double)pl[l64 + 64 * e], a);
+                a = x[l64_at<N>(l64, e)];
+                if (pending) a = fmx(alpha, (double)pl[l64_at<N>(l64, e)], a);
             }
             v[e] = a;
         }
@@ -218,8 +218,8 @@ __device__ __forceinline__ void mixed_start_body(int b, int nb, Geom g,
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 const int e = j * N + i;
-                const float f = (float)r64[l64 + 64 * e];
-                r32[l64 + 64 * e] = f;
+                const float f = (float)r64[l64_at<N>(l64, e)];
+                r32[l64_at<N>(l64, e)] = f;
                 row[i] = (double)f * (double)f;
             }
             part[0] += wrow<N>(k, j, row);
