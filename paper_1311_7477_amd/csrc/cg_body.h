@@ -543,15 +543,13 @@ __device__ __forceinline__ void cg_res_body(
     const double alpha = sc->alpha;
     SrcL64<N, S> src{p};
     double pv[N * N], q[N * N], rv[N * N];
-    if (c.active) {
-        src(c.self, pv);
-        ld_l64<N>(r, c.self, rv);
-    } else {
-        zero_cell<N>(pv);
-    }
+    if (c.active) src(c.self, pv);
+    else zero_cell<N>(pv);
     lap_cell<N, WV, DIR, ISO>(c, k, src, pv, lds, q);   // q = Lap p = -A p
     double part[1] = {0.0};
     if (c.active) {
+        // r is loaded only now, so that it is not held across the Laplacian
+        ld_l64<N>(r, c.self, rv);
 #pragma unroll
         for (int e = 0; e < N * N; ++e) rv[e] = as_stored<S>(fmx(alpha, q[e], rv[e]));
         st_l64<N>(r, c.self, rv);
