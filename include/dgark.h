@@ -265,8 +265,10 @@ int  dg_precond_apply(const dg_grid* grid, const double* r, double* z,
  * column-major, row = c n + i for cell c and node i, column = mode) with
  * L V = V diag(lam) and V^T W V = I for the 1D LDG second derivative L and
  * Gauss weights W of that axis; lam (host, N n doubles); *zero = the column
- * of the constant mode.  DG_E_UNSUPPORTED for a Dirichlet axis (its basis
- * is computed on the device).  Touches no GPU. */
+ * of the constant mode.  The cell Fourier basis is the one the transforms
+ * use on this grid: phases at the cell centres (the matrix products, up to
+ * 512 cells per axis) or at the cell edges (the FFTs).  DG_E_UNSUPPORTED for
+ * a Dirichlet axis (its basis is computed on the device).  Touches no GPU. */
 int  dg_grid_fd_basis(const dg_grid* grid, int axis, double* V, double* lam, int* zero);
 /* The 1D LDG second derivative of one axis (axis 0: x, 1: y; Sec. 6 as read
  * for dg_laplace_apply, with the Dirichlet closure on a Dirichlet axis), the

@@ -318,12 +318,18 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
 template <class T>
 int precond_step(const dg_grid* g, dg_workspace* ws, hipStream_t s) {
     T* planes = reinterpret_cast<T*>(ws->fd->img0);
-    const bool dense = ws->fd->dense;
-    hipError_t e = launch_to_image<T>(g->geom, g->k64, ws->r, true, dense, planes, s);
+    const int layout = fd_layout(ws->fd);
+    const bool dense = layout == kFdDense;
+    const int Kx = (g->nx + 1) / 2;
+    hipError_t e = layout == kFdFolded
+                       ? launch_to_planes_fold<T>(g->geom, ws->r, true, Kx, planes, s)
+                       : launch_to_image<T>(g->geom, g->k64, ws->r, true, dense, planes, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     int rc = fd_apply_image(ws->fd, sizeof(T) == sizeof(float), s);
     if (rc != DG_OK) return rc;
-    e = launch_from_image_dot<T>(g->geom, g->k64, planes, dense, ws->z, ws->r, ws->d, s);
+    e = layout == kFdFolded
+            ? launch_from_planes_fold<T>(g->geom, g->k64, planes, Kx, ws->z, ws->r, &ws->d, s)
+            : launch_from_image_dot<T>(g->geom, g->k64, planes, dense, ws->z, ws->r, ws->d, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }
@@ -641,8 +647,12 @@ int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* ze
         return periodic_only("the Bloch eigenbasis");
     FdAxis a;
     double err = 0.0;
-    const bool ok = axis == 0 ? fd_axis_basis(g->t, g->nx, g->hx, &a, &err)
-                              : fd_axis_basis(g->t, g->ny, g->hy, &a, &err);
+    // the basis the preconditioner's transforms use on this grid: phases at
+    // the cell centres for the matrix products (up to 512 cells per axis),
+    // at the cell edges for the FFTs
+    const bool shifted = g->nx <= 512 && g->ny <= 512;
+    const bool ok = axis == 0 ? fd_axis_basis(g->t, g->nx, g->hx, &a, &err, shifted)
+                              : fd_axis_basis(g->t, g->ny, g->hy, &a, &err, shifted);
     if (!ok || err > 1e-10) return fail(DG_E_INVAL, "eigenbasis construction failed (defect %.3e)", err);
     std::memcpy(V, a.V.data(), a.V.size() * sizeof(double));
     std::memcpy(lam, a.lam.data(), a.lam.size() * sizeof(double));
@@ -669,12 +679,19 @@ int dg_precond_apply(const dg_grid* g, const double* r, double* z, dg_workspace*
     if (ranges_overlap(z, r, g->elems * sizeof(double)))
         return fail(DG_E_ALIAS, "z aliases r");
     const hipStream_t s = as_stream(stream);
-    const bool dense = ws->fd->dense;
-    hipError_t e = launch_to_image<double>(g->geom, g->k64, r, false, dense, ws->fd->img0, s);
+    const int layout = fd_layout(ws->fd);
+    const bool dense = layout == kFdDense;
+    const int Kx = (g->nx + 1) / 2;
+    hipError_t e = layout == kFdFolded
+                       ? launch_to_planes_fold<double>(g->geom, r, false, Kx, ws->fd->img0, s)
+                       : launch_to_image<double>(g->geom, g->k64, r, false, dense, ws->fd->img0, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     rc = fd_apply_image(ws->fd, false, s);
     if (rc != DG_OK) return rc;
-    e = launch_from_image<double>(g->geom, g->k64, ws->fd->img0, dense, z, s);
+    e = layout == kFdFolded
+            ? launch_from_planes_fold<double>(g->geom, g->k64, ws->fd->img0, Kx, z, nullptr,
+                                              nullptr, s)
+            : launch_from_image<double>(g->geom, g->k64, ws->fd->img0, dense, z, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }

@@ -75,6 +75,9 @@ int fd_supported(const dg_grid* g);     // DG_OK, or DG_E_UNSUPPORTED with the r
 int fd_create(const dg_grid* g, FdDevice** out);
 void fd_destroy(FdDevice* fd);
 int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s);
+// Layout of the work image fd_apply_image expects and returns.
+enum FdLayout { kFdPlanes = 0, kFdFolded = 1, kFdDense = 2 };
+int fd_layout(const FdDevice* fd);
 }  // namespace dgk
 
 #define HIP_TRY(call)                                          \

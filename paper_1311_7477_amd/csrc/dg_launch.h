@@ -93,9 +93,9 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
 // Fast-diagonalisation preconditioner support (fd_kernels.hip): field ->
 // node planes U[cell + nx ny q] (from canonical or lane-interleaved), planes
 // -> canonical, planes -> z (lane-interleaved) with <r, z>_W closing the PCG
-// step, the per-wave-number mixing of the x cell transform (K blocks, M
-// row-major 2n x 2n each, cols[2k] / cols[2k+1] the cos / sin columns), and
-// the y mixing + spectral scaling + unmixing.  `dense`: the conversions
+// step, and the y mixing + spectral scaling + unmixing (K blocks, M
+// row-major 2n x 2n each, cols[2k] / cols[2k+1] the cos / sin columns of
+// wave number k).  `dense`: the conversions
 // use the dense image of the eigenbasis path instead of node planes (rows
 // along x, values scaled by sqrt(W) on the way in and by its inverse on the
 // way out), and launch_dense_divide is that path's spectral division.
@@ -112,9 +112,22 @@ hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const 
                                  hipStream_t s);
 template <class T>
 hipError_t launch_dense_divide(int mx, int my, const T* lx, const T* ly, T* c, hipStream_t s);
+// The matrix-product path on node planes folded along x (E = u[c] +
+// u[N - 1 - c] at column c < Kx = ceil(N/2), O = u[c] - u[N - 1 - c] at column
+// Kx + c): conversions in (from L64 or canonical) and out (to canonical, or
+// with d to L64 z plus <r, z>_W), and the x mixing out of place combined
+// with the fold (forward) or unfold (inverse) of the y axis, Ky = ceil(Ny/2).
 template <class T>
-hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const T* M, T* u,
-                           hipStream_t s);
+hipError_t launch_to_planes_fold(const Geom& g, const double* src, bool from_l64, int Kx, T* img,
+                                 hipStream_t s);
+template <class T>
+hipError_t launch_from_planes_fold(const Geom& g, const OpConst<double>& k, const T* img, int Kx,
+                                   double* dst, const double* r, const DevScratch* d,
+                                   hipStream_t s);
+template <class T>
+hipError_t launch_fd_mix_x_fold(bool inverse, int n, int Nx, int Ny, int Ky, int K,
+                                const int* cols, const T* M, const T* in, T* out,
+                                hipStream_t s);
 template <class T>
 hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
                            const T* Mi, const T* lx, const T* ly, int zx, int zy, T* u,

@@ -5,14 +5,19 @@
 // (q = i + n j).  The cell Fourier transforms Phi are FP64 matrix products
 // (rocBLAS), each chosen so that its output puts the next step's axis first:
 //   U  --(x transform, batched over j)-->  U1[cy + Ny (i + n kx + n Nx j)]
-//   U1 --(x mixing B_x^T W_x, in place)
+//   U1 --(x mixing B_x^T W_x)
 //   U1 --(y transform)-->                   U2[i + n kx + n Nx (j + n ky)]
 //   U2 --(y mixing, scaling, unmixing, in place)
 //   U2 --(inverse y transform)-->           U1
-//   U1 --(x unmixing B_x, in place)
+//   U1 --(x unmixing B_x)
 //   U1 --(inverse x transform, batched)-->  U
-// The transforms cost 4 n^2 Nx Ny (Nx + Ny) flops in all, n times fewer
-// than dense products with V.  Beyond 512 cells on an axis they run as real
+// Each transform is folded: with phases at the cell centres the even basis
+// columns (constant, cosines) take the same value on cells c and N - 1 - c
+// and the odd ones (sines, alternating) opposite values, so the rows are
+// first combined into sums E and differences O and each half meets its own
+// half of Phi -- two products of (N/2)^2 instead of one of N^2.  The x fold happens in the input
+// conversion, the y fold in the x mixing (and the unfolds in reverse).  The
+// transforms cost 2 n^2 Nx Ny (Nx + Ny) flops in all.  Beyond 512 cells on an axis they run as real
 // FFTs along the cells instead (rocFFT; the mixing kernels then read and
 // write half spectra, fd_kernels.hip).  The same steps run in FP64 or, for
 // the mixed-precision PCG, in FP32 (factors rounded once at setup; the
@@ -151,26 +156,47 @@ int apply_planes(const FdDevice* fd, hipStream_t s) {
     T* u0 = reinterpret_cast<T*>(fd->img0);
     T* u1 = reinterpret_cast<T*>(fd->img1);
     const rocblas_int n = fd->n, Nx = X.N, Ny = Y.N, M2 = n * n * Nx;
+    // even columns 0 .. Ke-1 and odd ones Ke .. N-1 of each (shifted) basis,
+    // Ke = ceil(N/2); folded rows: E for c < Ke, O at Ke + c
+    const rocblas_int Kx = (Nx + 1) / 2, Sx = Nx - Kx, Ky = (Ny + 1) / 2, Sy = Ny - Ky;
+    const rocblas_int ldj = Ny * n;
     const rocblas_stride plane_j = (rocblas_stride)Nx * Ny * n;   // one j of U / U1
     const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
-    // U1_j = U_j^T Phi_x: U_j is Nx x (Ny n), U1_j is (Ny n) x Nx
-    st = gemm(h, T_, N_, Ny * n, Nx, Nx, u0, Nx, plane_j, fx.phi, Nx, 0, u1, Ny * n, plane_j, n);
+    const T* phx_s = fx.phi + (size_t)Kx * Nx;   // rows 0 .. Sx-1 of the odd block
+    const T* phy_s = fy.phi + (size_t)Ky * Ny;
+    // x transform of the x-folded planes u0 (E rows 0 .. Kx-1, O rows Kx ..):
+    // U1_j[:, even] = E_j^T Phi_x,even, U1_j[:, odd] = O_j^T Phi_x,odd
+    st = gemm(h, T_, N_, ldj, Kx, Kx, u0, Nx, plane_j, fx.phi, Nx, 0, u1, ldj, plane_j, n);
+    if (st == rocblas_status_success && Sx > 0)
+        st = gemm(h, T_, N_, ldj, Sx, Sx, u0 + Kx, Nx, plane_j, phx_s, Nx, 0,
+                  u1 + (size_t)Kx * ldj, ldj, plane_j, n);
     if (st != rocblas_status_success) return blas_fail(st, "x transform");
-    hipError_t e = launch_fd_mix_x<T>(n, Nx, Ny, X.K, X.cols, fx.mf, u1, s);
+    // x mixing (B^T W) and the fold along y: u1 -> u0
+    hipError_t e = launch_fd_mix_x_fold<T>(false, n, Nx, Ny, Ky, X.K, X.cols, fx.mf, u1, u0, s);
     if (e != hipSuccess) return hip_fail(e, "x mixing launch");
-    // U2 = U1^T Phi_y: U1 is Ny x (n^2 Nx), U2 is (n^2 Nx) x Ny
-    st = gemm(h, T_, N_, M2, Ny, Ny, u1, Ny, 0, fy.phi, Ny, 0, u0, M2, 0, 1);
+    // y transform: U2 (M2 x Ny) from the y-folded rows of u0 (Ny x M2)
+    st = gemm(h, T_, N_, M2, Ky, Ky, u0, Ny, 0, fy.phi, Ny, 0, u1, M2, 0, 1);
+    if (st == rocblas_status_success && Sy > 0)
+        st = gemm(h, T_, N_, M2, Sy, Sy, u0 + Ky, Ny, 0, phy_s, Ny, 0, u1 + (size_t)Ky * M2, M2,
+                  0, 1);
     if (st != rocblas_status_success) return blas_fail(st, "y transform");
     e = launch_fd_mix_y<T>(n, Nx, Ny, Y.K, Y.cols, fy.mf, fy.mi, fx.lam, fy.lam, X.zero, Y.zero,
-                           u0, s);
+                           u1, s);
     if (e != hipSuccess) return hip_fail(e, "y mixing launch");
-    // U1 = Phi_y U2^T
-    st = gemm(h, N_, T_, Ny, M2, Ny, fy.phi, Ny, 0, u0, M2, 0, u1, Ny, 0, 1);
+    // inverse y transform into y-folded rows: u1 -> u0
+    st = gemm(h, N_, T_, Ky, M2, Ky, fy.phi, Ny, 0, u1, M2, 0, u0, Ny, 0, 1);
+    if (st == rocblas_status_success && Sy > 0)
+        st = gemm(h, N_, T_, Sy, M2, Sy, phy_s, Ny, 0, u1 + (size_t)Ky * M2, M2, 0, u0 + Ky, Ny,
+                  0, 1);
     if (st != rocblas_status_success) return blas_fail(st, "inverse y transform");
-    e = launch_fd_mix_x<T>(n, Nx, Ny, X.K, X.cols, fx.mi, u1, s);
+    // unfold along y and x unmixing (B): u0 -> u1
+    e = launch_fd_mix_x_fold<T>(true, n, Nx, Ny, Ky, X.K, X.cols, fx.mi, u0, u1, s);
     if (e != hipSuccess) return hip_fail(e, "x unmixing launch");
-    // U_j = Phi_x U1_j^T
-    st = gemm(h, N_, T_, Nx, Ny * n, Nx, fx.phi, Nx, 0, u1, Ny * n, plane_j, u0, Nx, plane_j, n);
+    // inverse x transform into x-folded planes: u1 -> u0
+    st = gemm(h, N_, T_, Kx, ldj, Kx, fx.phi, Nx, 0, u1, ldj, plane_j, u0, Nx, plane_j, n);
+    if (st == rocblas_status_success && Sx > 0)
+        st = gemm(h, N_, T_, Sx, ldj, Sx, phx_s, Nx, 0, u1 + (size_t)Kx * ldj, ldj, plane_j,
+                  u0 + Kx, Nx, plane_j, n);
     if (st != rocblas_status_success) return blas_fail(st, "inverse x transform");
     return DG_OK;
 }
@@ -519,10 +545,17 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         *out = fd;
         return DG_OK;
     }
+    // the cell transforms: FP64 GEMMs up to 512 cells per axis (at n = 4,
+    // 512^2 they beat rocFFT, whose real transforms with the wave number as
+    // the slowest output index run as a complex FFT plus two strided copies),
+    // real FFTs beyond (at n = 5, 1024^2 a preconditioned solve takes 6.0 ms
+    // against 9.6 ms with the O(N^3) products); the GEMMs use the basis with
+    // phases at the cell centres, which folds each axis to half size
+    fd->use_fft = g->nx > kFdGemmMaxCells || g->ny > kFdGemmMaxCells;
     FdFactors fx, fy;
     double ex = 0.0, ey = 0.0;
-    if (!fd_axis_factors(g->t, g->nx, g->hx, &fx, &ex) ||
-        (!fd->shared && !fd_axis_factors(g->t, g->ny, g->hy, &fy, &ey))) {
+    if (!fd_axis_factors(g->t, g->nx, g->hx, &fx, &ex, !fd->use_fft) ||
+        (!fd->shared && !fd_axis_factors(g->t, g->ny, g->hy, &fy, &ey, !fd->use_fft))) {
         delete fd;
         return fail(DG_E_INVAL, "eigenbasis construction failed");
     }
@@ -548,12 +581,6 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         return blas_fail(st, "rocblas_create_handle");
     }
     fd->blas = h;
-    // the cell transforms: FP64 GEMMs up to 512 cells per axis (at n = 4,
-    // 512^2 they beat rocFFT, whose real transforms with the wave number as
-    // the slowest output index run as a complex FFT plus two strided copies),
-    // real FFTs beyond (at n = 5, 1024^2 a preconditioned solve takes 6.0 ms
-    // against 9.6 ms with the O(N^3) products)
-    fd->use_fft = g->nx > kFdGemmMaxCells || g->ny > kFdGemmMaxCells;
     if (fd->use_fft) {
         const int rc = make_fft(g, fd);
         if (rc != DG_OK) { fd_destroy(fd); return rc; }
@@ -563,8 +590,13 @@ int fd_create(const dg_grid* g, FdDevice** out) {
     return DG_OK;
 }
 
-// img0 holds the node planes of r on entry and those of z = M r on exit
-// (FP32 planes when fp32).
+// img0 holds the work image of r on entry and that of z = M r on exit
+// (FP32 when fp32): the dense image (dense path), node planes (FFT path) or
+// node planes folded along x (matrix-product path).
+int fd_layout(const FdDevice* fd) {
+    return fd->dense ? kFdDense : (fd->use_fft ? kFdPlanes : kFdFolded);
+}
+
 int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s) {
     if (fd->dense) return fp32 ? apply_dense<float>(fd, s) : apply_dense<double>(fd, s);
     if (fd->use_fft) return fp32 ? apply_fft<float>(fd, s) : apply_fft<double>(fd, s);

@@ -123,7 +123,8 @@ void bloch_eig(const HostTables& t, int N, double h, int k, double* lam, cplx* v
 
 }  // namespace
 
-bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, double* max_err) {
+bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, double* max_err,
+                     bool shifted) {
     const int n = t.n;
     const double two_pi = 6.283185307179586476925286766559;
     const int K = N / 2 + 1;                 // wave numbers 0 .. floor(N/2)
@@ -138,23 +139,34 @@ bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, doubl
     out->mi.assign((size_t)K * s * s, 0.0);
     out->lam.assign((size_t)N * n, 0.0);
     out->zero = -1;
-    // real orthonormal Fourier basis over the cells: column 0 = constant,
-    // columns 2k-1 / 2k = cos / sin of wave number k, and for even N the
-    // last column the alternating (-1)^c
+    // real orthonormal Fourier basis over the cells, the even columns first.
+    // Unshifted (cos / sin of 2 pi k c / N, for the FFT transforms): columns
+    // 0 .. K-1 the constant, cos k and for even N the alternating (-1)^c,
+    // then the sines at K + k - 1; rows c and N - c agree on the first block.
+    // Shifted (of 2 pi k (c + 1/2) / N, for the matrix-product transforms):
+    // cells c and N - 1 - c agree on the cosines and differ in sign on the
+    // sines and, for even N, the alternating column, so the first Ke =
+    // ceil(N/2) columns are the constant and cos k < N/2, the others the sines
+    // at Ke + k - 1 and the alternating one last: two halves of N/2 columns
+    // for even N, which the transforms use to fold each axis.
     const double c0 = 1.0 / std::sqrt((double)N), c1 = std::sqrt(2.0 / N);
+    const int Ke = shifted ? (N + 1) / 2 : K;
     for (int k = 0; k < K; ++k) {
         const bool real = (k == 0) || (2 * k == N);
-        const int cc = (k == 0) ? 0 : (real ? N - 1 : 2 * k - 1);
+        const int cc = (shifted && 2 * k == N) ? N - 1 : k, cs = Ke + k - 1;
         out->ccos[k] = cc;
-        if (!real) out->csin[k] = 2 * k;
+        if (!real) out->csin[k] = cs;
         for (int cx = 0; cx < N; ++cx) {
             if (real) {
                 out->phi[(size_t)cc * N + cx] = (k == 0 || cx % 2 == 0) ? c0 : -c0;
             } else {
-                const long m = ((long)k * cx) % N;   // angle reduced exactly
-                const double ang = two_pi * (double)m / N;
+                // angle reduced exactly: 2 pi k c / N, or pi k (2c + 1) / N
+                const long m = shifted ? ((long)k * (2 * cx + 1)) % (2L * N)
+                                       : ((long)k * cx) % N;
+                const double ang = shifted ? 0.5 * two_pi * (double)m / N
+                                           : two_pi * (double)m / N;
                 out->phi[(size_t)cc * N + cx] = c1 * std::cos(ang);
-                out->phi[(size_t)(cc + 1) * N + cx] = c1 * std::sin(ang);
+                out->phi[(size_t)cs * N + cx] = c1 * std::sin(ang);
             }
         }
     }
@@ -190,6 +202,27 @@ bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, doubl
                         mi[p * s + q] = Bv[cs][ri];
                     }
             }
+            if (shifted && !real && a == n - 1) {
+                // the shifted basis column pair of wave number k is the
+                // unshifted pair rotated by phi = pi k / N: coefficients
+                // (a, b) = R (a', b'), R = [[cos, sin], [-sin, cos]] on the
+                // (cos, sin) slots of every node, so mf' = mf R, mi' = R^T mi
+                const double ph = 0.5 * two_pi * (double)k / N;
+                const double cph = std::cos(ph), sph = std::sin(ph);
+                for (int q = 0; q < s; ++q)
+                    for (int i2 = 0; i2 < n; ++i2) {
+                        double& f0 = mf[q * s + i2];
+                        double& f1 = mf[q * s + n + i2];
+                        const double g0 = f0 * cph - f1 * sph, g1 = f0 * sph + f1 * cph;
+                        f0 = g0;
+                        f1 = g1;
+                        double& m0 = mi[i2 * s + q];
+                        double& m1 = mi[(n + i2) * s + q];
+                        const double h0 = cph * m0 - sph * m1, h1 = sph * m0 + cph * m1;
+                        m0 = h0;
+                        m1 = h1;
+                    }
+            }
             out->lam[(size_t)a * N + out->ccos[k]] = lam[a];
             if (!real) out->lam[(size_t)a * N + out->csin[k]] = lam[a];
             if (k == 0 && (out->zero < 0 || std::fabs(lam[a]) < zero_abs)) {
@@ -202,9 +235,10 @@ bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, doubl
     return out->zero >= 0;
 }
 
-bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err) {
+bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err,
+                   bool shifted) {
     FdFactors f;
-    if (!fd_axis_factors(t, N, h, &f, max_err)) return false;
+    if (!fd_axis_factors(t, N, h, &f, max_err, shifted)) return false;
     const int n = t.n, s = 2 * n;
     const long NN = (long)N * n;
     out->NN = (int)NN;

@@ -21,8 +21,9 @@ struct FdAxis {
 
 // The same basis in factored form V = (Phi (x) I_n) B: Phi (N x N,
 // column-major) is the real orthonormal Fourier basis over the cells
-// (column 0 constant, 2k-1 / 2k cos / sin of wave number k, N-1 the
-// alternating one for even N), B block diagonal over the K = N/2 + 1 wave
+// (columns 0 .. K-1 the even ones: constant, cos k, and for even N the
+// alternating one; columns K + k - 1 the sines), B block diagonal over the
+// K = N/2 + 1 wave
 // numbers.  Block k couples the basis columns ccos[k] (and csin[k], -1 for
 // k = 0 and N/2) of every node i with the modes of that k: slot p = (i, cos)
 // -> i, (i, sin) -> n + i; mode q = (a, re) -> a, (a, im) -> n + a, both
@@ -42,10 +43,14 @@ struct FdFactors {
 // Builds the basis for N cells of size h from the LDG tables (h = 1 form).
 // *max_err receives the largest relative defect seen (Hermitian symmetry of
 // the symbols, eigen-residuals).  Returns false if the basis is incomplete.
-bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, double* max_err);
+// shifted: the cell Fourier basis of the matrix-product transforms (phases
+// at the cell centres c + 1/2, see fd_basis.cpp), else that of the FFT ones.
+bool fd_axis_factors(const HostTables& t, int N, double h, FdFactors* out, double* max_err,
+                     bool shifted = false);
 // Dense assembly of the same basis (host checks): column a * N + c is the
 // mode of slot (a, c), rows cx * n + i.
-bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err);
+bool fd_axis_basis(const HostTables& t, int N, double h, FdAxis* out, double* max_err,
+                   bool shifted = false);
 
 // The 1D LDG second derivative of one axis (the blocks of ldg_axis times
 // h^-2; the homogeneous Dirichlet closure when !periodic): fd_axis_apply

@@ -1,10 +1,12 @@
 // Device kernels of the fast-diagonalisation preconditioner.  Its fields
 // live in node planes: U[cell + nx ny (i + n j)] (cell = cy nx + cx), so the
 // cell Fourier transforms along x and y are plain matrix products over whole
-// planes.  Here: the conversions between the CG layouts and the planes, the
-// per-wave-number mixing of the x transform, the mixing + spectral scaling +
-// unmixing of the y transform, and the preconditioned dot product <r, z>_W
-// that closes the PCG step.
+// planes (folded along x, see k_to_planes_fold) or batched real FFTs.  Here:
+// the conversions between the CG layouts and the planes, the per-wave-number
+// mixing of the x transform (with the fold of the y axis), the mixing +
+// spectral scaling + unmixing of the y transform, the same mixings on half
+// spectra for the FFT path, the dense path's conversions and division, and
+// the preconditioned dot product <r, z>_W that closes the PCG step.
 #include <cmath>
 
 #include "cg_body.h"
@@ -80,6 +82,110 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image(Geom g, OpConst<doubl
     }
 }
 
+// The last block of a <r, z>_W reduction: rz and, past the first iteration,
+// beta = <r,z>_new / <r,z>_old; a non-positive or non-finite <r,z> ends the
+// solve as a breakdown.
+__device__ __forceinline__ void set_rz(double rz, CgScalars* sc) {
+    sc->precond = 1;
+    if (!(rz > 0.0) || !(rz < __builtin_inf())) {
+        // <r, M r> must be positive and finite for a nonzero residual:
+        // stop; x still lacks the last alpha p (after any iteration)
+        sc->done = 1;
+        sc->breakdown = 1;
+        sc->pending = sc->first != 1;
+    } else {
+        if (sc->first != 1) sc->beta = rz / sc->rz;
+        sc->rz = rz;
+    }
+}
+
+// Folded node planes of the matrix-product path: along x, cells c and
+// N - 1 - c share the even basis columns and the odd ones with opposite
+// signs, so the planes hold E[c] = u[c] + u[N - 1 - c] at column c
+// (c = 0 .. Kx - 1, Kx = ceil(N/2); u[c] alone for the middle cell of an odd
+// N) and O[c] = u[c] - u[N - 1 - c] at column Kx + c.  One thread per cell
+// pair.
+__device__ __forceinline__ bool fold_pair(int c, int N) { return 2 * c + 1 != N; }
+
+template <int N, bool FromL64, class T>
+__global__ __launch_bounds__(kPwThreads) void k_to_planes_fold(Geom g, const double* __restrict__ src,
+                                                               T* __restrict__ img, int Kx) {
+    const long pairs = (long)Kx * g.ny, cells = (long)g.nx * g.ny;
+    const int G = (g.nx + 63) / 64;
+    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < pairs;
+         t += (long)gridDim.x * kPwThreads) {
+        const int cy = (int)(t / Kx), c = (int)(t - (long)cy * Kx);
+        const bool pr = fold_pair(c, g.nx);
+        double a[N * N], b[N * N];
+        const CellRef ca = cell_ref<N>(g, G, c, cy);
+        if (FromL64) ld_l64<N>(src, ca, a);
+        else ld_canon<N>(src, ca, a);
+        if (pr) {
+            const CellRef cb = cell_ref<N>(g, G, g.nx - 1 - c, cy);
+            if (FromL64) ld_l64<N>(src, cb, b);
+            else ld_canon<N>(src, cb, b);
+        }
+        const long e0 = c + (long)g.nx * cy, o0 = Kx + c + (long)g.nx * cy;
+#pragma unroll
+        for (int q = 0; q < N * N; ++q) {
+            img[e0 + cells * q] = (T)(pr ? a[q] + b[q] : a[q]);
+            if (pr) img[o0 + cells * q] = (T)(a[q] - b[q]);
+        }
+    }
+}
+
+// Unfolding: u[c] = E[c] + O[c], u[N - 1 - c] = E[c] - O[c], stored canonical,
+// or (Dot) lane-interleaved as z with <r, z>_W reduced as in k_from_image_dot.
+template <int N, bool Dot, class T>
+__global__ __launch_bounds__(kPwThreads) void k_from_planes_fold(
+    Geom g, OpConst<double> k, const T* __restrict__ img, int Kx, double* __restrict__ dst,
+    const double* __restrict__ r, CgScalars* sc, unsigned* counter, double* partials) {
+    if (Dot && sc->done) return;
+    const long pairs = (long)Kx * g.ny, cells = (long)g.nx * g.ny;
+    const int G = (g.nx + 63) / 64;
+    double part[1] = {0.0};
+    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < pairs;
+         t += (long)gridDim.x * kPwThreads) {
+        const int cy = (int)(t / Kx), c = (int)(t - (long)cy * Kx);
+        const bool pr = fold_pair(c, g.nx);
+        const long e0 = c + (long)g.nx * cy, o0 = Kx + c + (long)g.nx * cy;
+        double a[N * N], b[N * N];
+#pragma unroll
+        for (int q = 0; q < N * N; ++q) {
+            const double ev = (double)img[e0 + cells * q];
+            const double od = pr ? (double)img[o0 + cells * q] : 0.0;
+            a[q] = ev + od;
+            b[q] = ev - od;
+        }
+        const CellRef ca = cell_ref<N>(g, G, c, cy);
+        if (Dot) {
+            double rv[N * N];
+            st_l64<N>(dst, ca, a);
+            ld_l64<N>(r, ca, rv);
+            part[0] += wdot_cell<N>(k, rv, a);
+        } else {
+            st_canon<N>(dst, ca, a);
+        }
+        if (pr) {
+            const CellRef cb = cell_ref<N>(g, G, g.nx - 1 - c, cy);
+            if (Dot) {
+                double rv[N * N];
+                st_l64<N>(dst, cb, b);
+                ld_l64<N>(r, cb, rv);
+                part[0] += wdot_cell<N>(k, rv, b);
+            } else {
+                st_canon<N>(dst, cb, b);
+            }
+        }
+    }
+    if (Dot) {
+        double tot[1];
+        if (reduce_last<1, kPwThreads>(part, partials, counter, gridDim.x, blockIdx.x, tot) &&
+            threadIdx.x == 0)
+            set_rz(tot[0], sc);
+    }
+}
+
 // z = image (to L64) and <r, z>_W; the last block sets rz and, past the
 // first iteration, beta = <r,z>_new / <r,z>_old (no-op once the solve is
 // done; a non-positive or non-finite <r,z> ends the solve as a breakdown).
@@ -109,20 +215,8 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
     }
     double tot[1];
     if (reduce_last<1, kPwThreads>(part, partials, counter, gridDim.x, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
-        sc->precond = 1;
-        const double rz = tot[0];
-        if (!(rz > 0.0) || !(rz < __builtin_inf())) {
-            // <r, M r> must be positive and finite for a nonzero residual:
-            // stop; x still lacks the last alpha p (after any iteration)
-            sc->done = 1;
-            sc->breakdown = 1;
-            sc->pending = sc->first != 1;
-        } else {
-            if (sc->first != 1) sc->beta = rz / sc->rz;
-            sc->rz = rz;
-        }
-    }
+        threadIdx.x == 0)
+        set_rz(tot[0], sc);
 }
 
 // out = M v for one 2n-vector (M row-major, S = 2n, row = output index);
@@ -149,40 +243,79 @@ __device__ __forceinline__ void mix_vec(const T* __restrict__ M, bool pair, cons
     }
 }
 
-// Mixing of the x transform, U1[cy + Ny (i + n c + n Nx j)] (c: cell
-// Fourier column along x).  Block row k = blockIdx.y is one wave number:
-// for every (cy, j) the values at columns cols[2k] (cos) and cols[2k+1]
-// (sin, -1 if none) of all nodes i form the 2n-vector (h, i) -> h n + i,
-// which is replaced by M_k times it, in place.  One lane per cy, so each
-// access is contiguous across the wave; M_k is the same for the block.
-template <int N, class T>
-__global__ __launch_bounds__(kPwThreads) void k_fd_mix_x(int Nx, int Ny,
-                                                         const int* __restrict__ cols,
-                                                         const T* __restrict__ M,
-                                                         T* __restrict__ u) {
+// The x mixing of the matrix-product path, out of place, combined with the
+// fold of the y axis (the next transform): Inv = false reads U1 and writes
+// the mixed rows folded along y (rows E[cy], cy < Ky, and O[cy] at row
+// Ky + cy, as for x above); Inv = true reads folded rows (the inverse y
+// transform's output), unfolds them to rows cy and Ny - 1 - cy and applies M.
+// One thread per (j, cy < Ky), two 2n-vectors each.
+template <int N, class T, bool Inv>
+__global__ __launch_bounds__(kPwThreads) void k_fd_mix_x_fold(int Nx, int Ny, int Ky,
+                                                              const int* __restrict__ cols,
+                                                              const T* __restrict__ M,
+                                                              const T* __restrict__ in,
+                                                              T* __restrict__ out) {
     constexpr int S = 2 * N;
     const int k = blockIdx.y;
     const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
     const bool pair = c1 >= 0;
     const T* Mk = M + (size_t)k * S * S;
-    const long per = (long)Ny * N;
+    const long per = (long)Ky * N;
     for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
          t += (long)gridDim.x * kPwThreads) {
-        const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
-        const long base = cy + (long)Ny * N * Nx * j;
-        const long o0 = base + (long)Ny * N * c0;
-        const long o1 = base + (long)Ny * N * (pair ? c1 : c0);
-        T v[S], w[S];
+        const int j = (int)(t / Ky), cy = (int)(t - (long)j * Ky);
+        const bool pr = fold_pair(cy, Ny);
+        const long jb = (long)Ny * N * Nx * j;
+        const long s0 = (long)Ny * N * c0, s1 = (long)Ny * N * (pair ? c1 : c0);
+        // rows: A (cy) and B (Ny - 1 - cy) unfolded, E (cy) and O (Ky + cy) folded
+        const long rA = jb + cy, rB = jb + (Ny - 1 - cy), rE = jb + cy, rO = jb + (Ky + cy);
+        T va[S], vb[S], wa[S], wb[S];
+        if (!Inv) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            v[i] = u[o0 + (long)Ny * i];
-            v[N + i] = pair ? u[o1 + (long)Ny * i] : T(0);
-        }
-        mix_vec<N, T>(Mk, pair, v, w);
+            for (int i = 0; i < N; ++i) {
+                const T a0 = in[rA + s0 + (long)Ny * i];
+                const T a1 = pair ? in[rA + s1 + (long)Ny * i] : T(0);
+                const T b0 = pr ? in[rB + s0 + (long)Ny * i] : T(0);
+                const T b1 = (pr && pair) ? in[rB + s1 + (long)Ny * i] : T(0);
+                va[i] = a0 + b0;
+                va[N + i] = a1 + b1;
+                vb[i] = a0 - b0;
+                vb[N + i] = a1 - b1;
+            }
+            mix_vec<N, T>(Mk, pair, va, wa);
+            if (pr) mix_vec<N, T>(Mk, pair, vb, wb);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            u[o0 + (long)Ny * i] = w[i];
-            if (pair) u[o1 + (long)Ny * i] = w[N + i];
+            for (int i = 0; i < N; ++i) {
+                out[rE + s0 + (long)Ny * i] = wa[i];
+                if (pair) out[rE + s1 + (long)Ny * i] = wa[N + i];
+                if (pr) {
+                    out[rO + s0 + (long)Ny * i] = wb[i];
+                    if (pair) out[rO + s1 + (long)Ny * i] = wb[N + i];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T e0 = in[rE + s0 + (long)Ny * i];
+                const T e1 = pair ? in[rE + s1 + (long)Ny * i] : T(0);
+                const T o0 = pr ? in[rO + s0 + (long)Ny * i] : T(0);
+                const T o1 = (pr && pair) ? in[rO + s1 + (long)Ny * i] : T(0);
+                va[i] = e0 + o0;
+                va[N + i] = e1 + o1;
+                vb[i] = e0 - o0;
+                vb[N + i] = e1 - o1;
+            }
+            mix_vec<N, T>(Mk, pair, va, wa);
+            if (pr) mix_vec<N, T>(Mk, pair, vb, wb);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                out[rA + s0 + (long)Ny * i] = wa[i];
+                if (pair) out[rA + s1 + (long)Ny * i] = wa[N + i];
+                if (pr) {
+                    out[rB + s0 + (long)Ny * i] = wb[i];
+                    if (pair) out[rB + s1 + (long)Ny * i] = wb[N + i];
+                }
+            }
         }
     }
 }
@@ -448,18 +581,57 @@ hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const 
 }
 
 template <class T>
-hipError_t launch_dense_divide(int mx, int my, const T* lx, const T* ly, T* c, hipStream_t s) {
-    const int nb = pw_blocks((long)mx * my, pointwise_block_cap());
-    hipLaunchKernelGGL((k_dense_divide<T>), dim3(nb), dim3(kPwThreads), 0, s, mx, my, lx, ly, c);
+hipError_t launch_to_planes_fold(const Geom& g, const double* src, bool from_l64, int Kx, T* img,
+                                 hipStream_t s) {
+    const int nb = pw_blocks((long)Kx * g.ny, pointwise_block_cap());
+    if (from_l64) {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_planes_fold<NN, true, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, src, img, Kx));
+    } else {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_to_planes_fold<NN, false, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, src, img, Kx));
+    }
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fd_mix_x(int n, int Nx, int Ny, int K, const int* cols, const T* M, T* u,
-                           hipStream_t s) {
-    const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_x<NN, T>), dim3(nb, K), dim3(kPwThreads), 0, s,
-                                        Nx, Ny, cols, M, u));
+hipError_t launch_from_planes_fold(const Geom& g, const OpConst<double>& k, const T* img, int Kx,
+                                   double* dst, const double* r, const DevScratch* d,
+                                   hipStream_t s) {
+    const int nb = pw_blocks((long)Kx * g.ny, pointwise_block_cap());
+    if (d) {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_planes_fold<NN, true, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, k, img, Kx, dst, r,
+                                              d->sc, d->counters + kCntDot, d->partials));
+    } else {
+        DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_planes_fold<NN, false, T>), dim3(nb),
+                                              dim3(kPwThreads), 0, s, g, k, img, Kx, dst,
+                                              nullptr, nullptr, nullptr, nullptr));
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fd_mix_x_fold(bool inverse, int n, int Nx, int Ny, int Ky, int K,
+                                const int* cols, const T* M, const T* in, T* out,
+                                hipStream_t s) {
+    const int nb = pw_blocks((long)Ky * n, pointwise_block_cap());
+    if (inverse) {
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_x_fold<NN, T, true>), dim3(nb, K),
+                                            dim3(kPwThreads), 0, s, Nx, Ny, Ky, cols, M, in,
+                                            out));
+    } else {
+        DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fd_mix_x_fold<NN, T, false>), dim3(nb, K),
+                                            dim3(kPwThreads), 0, s, Nx, Ny, Ky, cols, M, in,
+                                            out));
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_dense_divide(int mx, int my, const T* lx, const T* ly, T* c, hipStream_t s) {
+    const int nb = pw_blocks((long)mx * my, pointwise_block_cap());
+    hipLaunchKernelGGL((k_dense_divide<T>), dim3(nb), dim3(kPwThreads), 0, s, mx, my, lx, ly, c);
     return hipGetLastError();
 }
 
@@ -516,8 +688,13 @@ hipError_t launch_fft_mix_y(int n, int Nx, int Ny, int K, const int* cols, const
                                                  const T*, bool, double*, const double*,       \
                                                  const DevScratch&, hipStream_t);              \
     template hipError_t launch_dense_divide<T>(int, int, const T*, const T*, T*, hipStream_t); \
-    template hipError_t launch_fd_mix_x<T>(int, int, int, int, const int*, const T*, T*,      \
-                                           hipStream_t);                                       \
+    template hipError_t launch_to_planes_fold<T>(const Geom&, const double*, bool, int, T*,   \
+                                                 hipStream_t);                                 \
+    template hipError_t launch_from_planes_fold<T>(const Geom&, const OpConst<double>&,       \
+                                                   const T*, int, double*, const double*,     \
+                                                   const DevScratch*, hipStream_t);           \
+    template hipError_t launch_fd_mix_x_fold<T>(bool, int, int, int, int, int, const int*,    \
+                                                const T*, const T*, T*, hipStream_t);         \
     template hipError_t launch_fd_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \
                                            const T*, const T*, int, int, T*, hipStream_t);     \
     template hipError_t launch_fft_mix_x_fwd<T>(int, int, int, int, const int*, const T*,      \
