@@ -251,8 +251,10 @@ int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
  * then z = V_y [(V_y^T W_y R W_x V_x) / -(lambda_y + lambda_x)] V_x^T, the
  * constant mode dropped.  V is applied in factored form (the cell Fourier
  * transform, then 2n x 2n mixing per wave number); the transform is an FP64
- * matrix product (4 n^2 Nx Ny (Nx + Ny) flops per call) up to 512 cells per
- * axis and a real FFT (rocFFT) beyond.  On a grid with a homogeneous
+ * matrix product up to 512 cells per axis -- with phases at the cell centres,
+ * so that cells c and N - 1 - c fold each axis into two products of half
+ * size (2 n^2 Nx Ny (Nx + Ny) flops per call) -- and a real FFT (rocFFT)
+ * beyond.  On a grid with a homogeneous
  * Dirichlet axis (-Lap_h definite, z = (-Lap_h)^-1 r) both axes use dense
  * eigenbases (the Dirichlet one from rocSOLVER's symmetric eigensolver) and
  * the apply is four dense matrix products, 2 (n Nx)(n Ny)(n Nx + n Ny)
