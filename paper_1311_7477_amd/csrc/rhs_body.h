@@ -21,10 +21,18 @@ struct Tile {
     static constexpr int S = 64 / N;          // cell slots per wave
     static constexpr int TX = S - 2;          // interior cells per tile in x
     static constexpr int TY = WAVES - 2;      // interior cells per tile in y
-    // LDS stride of one cell: odd for even n so that lanes of different
-    // cells fall into different banks
-    static constexpr int CS = (N % 2 == 0) ? N * N + 1 : N * N;
+    // LDS layout of a cell's n x n values: the rows are staged by one lane
+    // each and read back by columns (and the reverse), so both access
+    // patterns must spread a wave over the banks.  For n = 2 and 4 the
+    // column index is XORed with the row index and a cell takes n^2 + n
+    // doubles: both patterns are then free of bank conflicts; odd n keep the
+    // dense n^2 stride (at most two-way conflicts).
+    static constexpr bool SWZ = (N == 2 || N == 4);
+    static constexpr int CS = SWZ ? N * N + N : N * N;
     static constexpr int LDS_FIELD = WAVES * S * CS;
+    __device__ static constexpr int at(int slot, int row, int col) {
+        return slot * CS + row * N + (SWZ ? (col ^ row) : col);
+    }
 };
 
 
@@ -117,16 +125,13 @@ __device__ __forceinline__ void col_op(const T* lds, const Ctx<N, WAVES>& c,
     using TL = Tile<N, WAVES>;
     const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
     const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
-    const T* c0 = lds + c.slot * TL::CS + c.j;
-    const T* cu = lds + up * TL::CS + c.j;
-    const T* cd = lds + dn * TL::CS + c.j;
     T col[N];
     T du = 0, dd = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        col[k] = c0[k * N];
-        du = fmx(tR[k], cu[k * N], du);
-        dd = fmx(tL[k], cd[k * N], dd);
+        col[k] = lds[TL::at(c.slot, k, c.j)];
+        du = fmx(tR[k], lds[TL::at(up, k, c.j)], du);
+        dd = fmx(tL[k], lds[TL::at(dn, k, c.j)], dd);
     }
     if (DIR) {   // zero flux on a Dirichlet boundary face (see row_op)
         T sb = 0, st = 0;
@@ -190,17 +195,14 @@ __device__ __forceinline__ void col_ldg(const T* lds, const Ctx<N, WAVES>& c, co
     using TL = Tile<N, WAVES>;
     const int up = c.slot + (c.wave + 1 < WAVES ? TL::S : 0);
     const int dn = c.slot - (c.wave > 0 ? TL::S : 0);
-    const T* c0 = lds + c.slot * TL::CS + c.j;
-    const T* cu = lds + up * TL::CS + c.j;
-    const T* cd = lds + dn * TL::CS + c.j;
     const T* tl = c.sec_d ? tLB : tL;
     T col[N];
     T du = 0, dd = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        col[k] = c0[k * N];
-        du = fmx(tR[k], cu[k * N], du);
-        dd = fmx(tl[k], cd[k * N], dd);
+        col[k] = lds[TL::at(c.slot, k, c.j)];
+        du = fmx(tR[k], lds[TL::at(up, k, c.j)], du);
+        dd = fmx(tl[k], lds[TL::at(dn, k, c.j)], dd);
     }
     if (c.at_u) du = 0;
     if (c.at_d) dd = 0;
@@ -218,7 +220,7 @@ __device__ __forceinline__ void lds_put_row(T* lds, const Ctx<N, WAVES>& c,
                                             const T (&u)[N]) {
     if (c.active) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) lds[c.slot * Tile<N, WAVES>::CS + c.j * N + i] = u[i];
+        for (int i = 0; i < N; ++i) lds[Tile<N, WAVES>::at(c.slot, c.j, i)] = u[i];
     }
 }
 
@@ -227,7 +229,7 @@ __device__ __forceinline__ void lds_put_col(T* lds, const Ctx<N, WAVES>& c,
                                             const T (&v)[N]) {
     if (c.active) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) lds[c.slot * Tile<N, WAVES>::CS + k * N + c.j] = v[k];
+        for (int k = 0; k < N; ++k) lds[Tile<N, WAVES>::at(c.slot, k, c.j)] = v[k];
     }
 }
 
@@ -235,7 +237,7 @@ template <int N, int WAVES, class T>
 __device__ __forceinline__ void lds_get_row(const T* lds, const Ctx<N, WAVES>& c,
                                             T (&u)[N]) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = lds[c.slot * Tile<N, WAVES>::CS + c.j * N + i];
+    for (int i = 0; i < N; ++i) u[i] = lds[Tile<N, WAVES>::at(c.slot, c.j, i)];
 }
 
 // Bracket and right-hand side.
