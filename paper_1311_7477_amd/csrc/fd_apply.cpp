@@ -15,11 +15,12 @@
 // columns (constant, cosines) take the same value on cells c and N - 1 - c
 // and the odd ones (sines, alternating) opposite values, so the rows are
 // first combined into sums E and differences O and each half meets its own
-// half of Phi -- two products of (N/2)^2 instead of one of N^2.  The x fold happens in the input
-// conversion, the y fold in the x mixing (and the unfolds in reverse).  The
-// transforms cost 2 n^2 Nx Ny (Nx + Ny) flops in all.  Beyond 512 cells on an axis they run as real
-// FFTs along the cells instead (rocFFT; the mixing kernels then read and
-// write half spectra, fd_kernels.hip).  The same steps run in FP64 or, for
+// half of Phi -- two products of (N/2)^2 instead of one of N^2.  The x fold
+// happens in the input conversion, the y fold in the x mixing (and the
+// unfolds in reverse).  The transforms cost 2 n^2 Nx Ny (Nx + Ny) flops in
+// all.  Beyond 512 cells on an axis they run as real FFTs along the cells
+// instead (rocFFT, with the unshifted basis; the mixing kernels then read
+// and write half spectra, fd_kernels.hip).  The same steps run in FP64 or, for
 // the mixed-precision PCG, in FP32 (factors rounded once at setup; the
 // fields then take the first half of the FP64 work fields).
 //
