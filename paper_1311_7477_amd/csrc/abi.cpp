@@ -648,9 +648,9 @@ int dg_grid_fd_basis(const dg_grid* g, int axis, double* V, double* lam, int* ze
     FdAxis a;
     double err = 0.0;
     // the basis the preconditioner's transforms use on this grid: phases at
-    // the cell centres for the matrix products (up to 512 cells per axis),
-    // at the cell edges for the FFTs
-    const bool shifted = g->nx <= 512 && g->ny <= 512;
+    // the cell centres for the matrix products (up to 512 cells per axis, or
+    // an odd count), at the cell edges for the FFTs
+    const bool shifted = !fd_uses_fft(g->nx, g->ny);
     const bool ok = axis == 0 ? fd_axis_basis(g->t, g->nx, g->hx, &a, &err, shifted)
                               : fd_axis_basis(g->t, g->ny, g->hy, &a, &err, shifted);
     if (!ok || err > 1e-10) return fail(DG_E_INVAL, "eigenbasis construction failed (defect %.3e)", err);

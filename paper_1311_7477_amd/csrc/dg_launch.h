@@ -135,13 +135,13 @@ hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const 
 // The same mixing on the half spectra of real FFTs along the cells (X, Y:
 // interleaved complex of type T; layouts in fd_kernels.hip).
 template <class T>
-hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, const int* cols, const T* Mf,
                                 const void* X, T* u1, hipStream_t s);
 template <class T>
-hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, int K, const int* cols, const T* Mi,
+hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, const int* cols, const T* Mi,
                                 const T* u1, void* X, hipStream_t s);
 template <class T>
-hipError_t launch_fft_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+hipError_t launch_fft_mix_y(int n, int Nx, int Ny, const int* cols, const T* Mf,
                             const T* Mi, const T* lx, const T* ly, int zx, int zy, void* Y,
                             hipStream_t s);
 hipError_t launch_guess(long elems, double* x, const double* pa,

@@ -18,10 +18,11 @@
 // half of Phi -- two products of (N/2)^2 instead of one of N^2.  The x fold
 // happens in the input conversion, the y fold in the x mixing (and the
 // unfolds in reverse).  The transforms cost 2 n^2 Nx Ny (Nx + Ny) flops in
-// all.  Beyond 512 cells on an axis they run as real FFTs along the cells
-// instead (rocFFT, with the unshifted basis; the mixing kernels then read
-// and write half spectra, fd_kernels.hip).  The same steps run in FP64 or, for
-// the mixed-precision PCG, in FP32 (factors rounded once at setup; the
+// all.  Beyond 512 cells on an axis (both counts even) they run as FFTs
+// along the cells instead (rocFFT, with the unshifted basis: each real row as
+// a complex row of half length, the mixing kernels then convert to and from
+// half spectra, fd_kernels.hip).  The same steps run in FP64 or, for the
+// mixed-precision PCG, in FP32 (factors rounded once at setup; the
 // fields then take the first half of the FP64 work fields).
 //
 // A grid with a homogeneous Dirichlet axis has no circulant structure along
@@ -223,18 +224,18 @@ int apply_fft(const FdDevice* fd, hipStream_t s) {
     // node planes U (b0) -> x spectra (b1) -> x-mixed real field U1 (b0)
     st = run(0, b0, b1);
     if (st != rocfft_status_success) return fft_fail(st, "x transform");
-    hipError_t e = launch_fft_mix_x_fwd<T>(n, Nx, Ny, X.K, X.cols, fx.mf, b1, (T*)b0, s);
+    hipError_t e = launch_fft_mix_x_fwd<T>(n, Nx, Ny, X.cols, fx.mf, b1, (T*)b0, s);
     if (e != hipSuccess) return hip_fail(e, "x mixing launch");
     // U1 (b0) -> y spectra (b1), mixed, divided, unmixed in place -> U1 (b0)
     st = run(1, b0, b1);
     if (st != rocfft_status_success) return fft_fail(st, "y transform");
-    e = launch_fft_mix_y<T>(n, Nx, Ny, Y.K, Y.cols, fy.mf, fy.mi, fx.lam, fy.lam, X.zero,
+    e = launch_fft_mix_y<T>(n, Nx, Ny, Y.cols, fy.mf, fy.mi, fx.lam, fy.lam, X.zero,
                             Y.zero, b1, s);
     if (e != hipSuccess) return hip_fail(e, "y mixing launch");
     st = run(2, b1, b0);
     if (st != rocfft_status_success) return fft_fail(st, "inverse y transform");
     // U1 (b0) -> x spectra (b1) -> node planes of z (b0)
-    e = launch_fft_mix_x_inv<T>(n, Nx, Ny, X.K, X.cols, fx.mi, (const T*)b0, b1, s);
+    e = launch_fft_mix_x_inv<T>(n, Nx, Ny, X.cols, fx.mi, (const T*)b0, b1, s);
     if (e != hipSuccess) return hip_fail(e, "x unmixing launch");
     st = run(3, b1, b0);
     if (st != rocfft_status_success) return fft_fail(st, "inverse x transform");
@@ -242,6 +243,17 @@ int apply_fft(const FdDevice* fd, hipStream_t s) {
 }
 
 }  // namespace
+
+// The cell transforms of a periodic grid: FP64 GEMMs up to 512 cells per
+// axis (at n = 4, 512^2 they beat the FFTs; they use the basis with phases at
+// the cell centres, which folds each axis to half size), FFTs beyond when
+// both axes have an even number of cells (each real row of N values is
+// transformed as a complex row of N/2; at n = 5, 1024^2 a preconditioned
+// solve took 6.0 ms with rocFFT's real transforms against 9.6 ms with the
+// unfolded products), the folded GEMMs again for an odd count.
+bool fd_uses_fft(int nx, int ny) {
+    return (nx > kFdGemmMaxCells || ny > kFdGemmMaxCells) && nx % 2 == 0 && ny % 2 == 0;
+}
 
 size_t fd_bytes(const dg_grid* g) {
     if (has_dirichlet(g)) {
@@ -412,29 +424,30 @@ int apply_dense(const FdDevice* fd, hipStream_t s) {
     return DG_OK;
 }
 
-// One batched 1D real FFT along an axis of length L: `count` transforms of
-// contiguous real rows (distance L) whose half spectra are stored with
-// stride `spec_stride` between wave numbers and distance 1 between
-// transforms (the wave number becomes the slowest index).
+// One batched 1D complex FFT of length H = L/2 along an axis of L cells:
+// `count` rows of L real values (distance L), each read as H interleaved
+// complex values, whose spectra are stored with stride `spec_stride` between
+// wave numbers and distance 1 between transforms (the wave number becomes
+// the slowest index); the inverse plan reads that layout back into rows.
 int make_plan(bool forward, bool fp32, size_t L, size_t count, size_t spec_stride,
               rocfft_plan* out) {
     rocfft_plan_description d = nullptr;
     rocfft_status st = rocfft_plan_description_create(&d);
     if (st != rocfft_status_success) return fft_fail(st, "plan description");
-    const size_t one = 1;
+    const size_t one = 1, H = L / 2;
     if (forward)
         st = rocfft_plan_description_set_data_layout(
-            d, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved, nullptr, nullptr,
-            1, &one, L, 1, &spec_stride, 1);
+            d, rocfft_array_type_complex_interleaved, rocfft_array_type_complex_interleaved,
+            nullptr, nullptr, 1, &one, H, 1, &spec_stride, 1);
     else
         st = rocfft_plan_description_set_data_layout(
-            d, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real, nullptr, nullptr,
-            1, &spec_stride, 1, 1, &one, L);
+            d, rocfft_array_type_complex_interleaved, rocfft_array_type_complex_interleaved,
+            nullptr, nullptr, 1, &spec_stride, 1, 1, &one, H);
     if (st == rocfft_status_success)
         st = rocfft_plan_create(out, rocfft_placement_notinplace,
-                                forward ? rocfft_transform_type_real_forward
-                                        : rocfft_transform_type_real_inverse,
-                                fp32 ? rocfft_precision_single : rocfft_precision_double, 1, &L,
+                                forward ? rocfft_transform_type_complex_forward
+                                        : rocfft_transform_type_complex_inverse,
+                                fp32 ? rocfft_precision_single : rocfft_precision_double, 1, &H,
                                 count, d);
     (void)rocfft_plan_description_destroy(d);
     if (st != rocfft_status_success) return fft_fail(st, "plan create");
@@ -546,13 +559,7 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         *out = fd;
         return DG_OK;
     }
-    // the cell transforms: FP64 GEMMs up to 512 cells per axis (at n = 4,
-    // 512^2 they beat rocFFT, whose real transforms with the wave number as
-    // the slowest output index run as a complex FFT plus two strided copies),
-    // real FFTs beyond (at n = 5, 1024^2 a preconditioned solve takes 6.0 ms
-    // against 9.6 ms with the O(N^3) products); the GEMMs use the basis with
-    // phases at the cell centres, which folds each axis to half size
-    fd->use_fft = g->nx > kFdGemmMaxCells || g->ny > kFdGemmMaxCells;
+    fd->use_fft = fd_uses_fft(g->nx, g->ny);
     FdFactors fx, fy;
     double ex = 0.0, ey = 0.0;
     if (!fd_axis_factors(g->t, g->nx, g->hx, &fx, &ex, !fd->use_fft) ||

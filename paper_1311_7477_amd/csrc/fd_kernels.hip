@@ -368,13 +368,22 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
     }
 }
 
-// ---- The same steps with the cell transforms as real FFTs (half spectra,
-// rocFFT).  A forward transform gives X_k = sum_c u_c e^{-2 pi i k c / N};
-// the orthonormal cos / sin coefficients of wave number k are then
+// ---- The same steps with the cell transforms as FFTs.  A real row u of
+// even length N is transformed as the complex row z_c = u_{2c} + i u_{2c+1}
+// of length H = N/2 (rocFFT, wave number the slowest index of the result).
+// The real row's half spectrum X_k = sum_c u_c e^{-2 pi i k c / N} follows
+// from Z_k and Z_{H-k} (indices mod H): with E = (Z_k + conj Z_{H-k}) / 2
+// and O = (Z_k - conj Z_{H-k}) / 2i, X_k = E + e^{-2 pi i k / N} O for
+// k = 0..H.  Backwards, from a half spectrum Y the complex row Z_k = E + i O
+// with E = Y_k + conj Y_{H-k} and O = (Y_k - conj Y_{H-k}) e^{2 pi i k / N}
+// (k < H) has as unnormalised inverse transform the even (real part) and odd
+// (imaginary part) samples of the real inverse transform of Y.  Wave numbers
+// k and H - k take the same two values, so block row p serves both (p = 0
+// with H).  The orthonormal cos / sin coefficients of wave number k are
 // sqrt(2/N) (Re X_k, -Im X_k) (k = 0 and N/2: 1/sqrt(N) Re X_k), and the
-// inverse (unnormalised) transform of Y_k = sqrt(2/N)/2 (a - i b), Y_0 and
-// Y_{N/2} = 1/sqrt(N) a, rebuilds sum a cos + b sin.  The mixing kernels
-// convert between the two while they mix.
+// real inverse transform of Y_k = sqrt(2/N)/2 (a - i b), Y_0 and Y_{N/2} =
+// 1/sqrt(N) a, rebuilds sum a cos + b sin.  The mixing kernels convert
+// between the three forms while they mix.
 
 template <class T> struct CplxOf;
 template <> struct CplxOf<double> { using type = double2; };
@@ -407,105 +416,206 @@ __device__ __forceinline__ C coef_to_spec(bool pair, T cn, T cp, T a, T b) {
     return z;
 }
 
-// Forward x mixing from the x spectra X[(cy + Ny (i + n j)) + M k] (M =
-// Ny n^2; block row k = blockIdx.y, lanes along cy) into the real
+// The wave numbers of block row p (H = N/2): k[0] = p and, unless p = H - p,
+// k[1] = H - p; the two spectrum rows it reads are p and (H - p) mod H; (c, s)
+// = (cos, sin) of 2 pi k / N, evaluated in FP64.
+template <class T>
+struct WavePair {
+    int nw, k[2], q;
+    T c[2], s[2];
+    __device__ WavePair(int p, int N) {
+        const int H = N / 2;
+        k[0] = p;
+        k[1] = H - p;
+        nw = k[1] == p ? 1 : 2;
+        q = (H - p) % H;
+        for (int w = 0; w < 2; ++w) {
+            const double x = 2.0 * k[w] / N;
+            c[w] = T(cospi(x));
+            s[w] = T(sinpi(x));
+        }
+    }
+};
+
+// X_k from za = Z_k and zb = Z_{H-k}; (c, s) of 2 pi k / N.
+template <class C, class T>
+__device__ __forceinline__ C unpack_half(const C za, const C zb, T c, T s) {
+    const T ex = T(0.5) * (za.x + zb.x), ey = T(0.5) * (za.y - zb.y);
+    const T ox = T(0.5) * (za.y + zb.y), oy = -T(0.5) * (za.x - zb.x);
+    C x;
+    x.x = ex + c * ox + s * oy;
+    x.y = ey + c * oy - s * ox;
+    return x;
+}
+
+// Z_k from ya = Y_k and yb = Y_{H-k}; (c, s) of 2 pi k / N.
+template <class C, class T>
+__device__ __forceinline__ C pack_half(const C ya, const C yb, T c, T s) {
+    const T ex = ya.x + yb.x, ey = ya.y - yb.y;
+    const T dx = ya.x - yb.x, dy = ya.y + yb.y;
+    const T ox = dx * c - dy * s, oy = dx * s + dy * c;
+    C z;
+    z.x = ex - oy;
+    z.y = ey + ox;
+    return z;
+}
+
+// Forward x mixing from the x spectra Z[(cy + Ny (i + n j)) + M k] (M =
+// Ny n^2, k < Nx/2; block row p = blockIdx.y, lanes along cy) into the real
 // x-transformed field U1[cy + Ny (i + n c + n Nx j)] (c: the cos / sin
 // columns of wave number k, as in the matrix-product path).
 template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_fwd(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf, T cn, T cp,
-    const typename CplxOf<T>::type* __restrict__ X, T* __restrict__ u1) {
+    const typename CplxOf<T>::type* __restrict__ Z, T* __restrict__ u1) {
+    using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    const int k = blockIdx.y;
-    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
-    const bool pair = c1 >= 0;
-    const T* Mk = Mf + (size_t)k * S * S;
+    const int p = blockIdx.y;
+    const WavePair<T> wp(p, Nx);
     const long per = (long)Ny * N, M = (long)Ny * N * N;
     for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
          t += (long)gridDim.x * kPwThreads) {
         const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
-        T v[S], w[S];
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            spec_to_coef(X[cy + (long)Ny * (i + N * j) + M * k], pair, cn, cp, v[i], v[N + i]);
-        mix_vec<N, T>(Mk, pair, v, w);
-        const long base = cy + (long)Ny * N * Nx * j;
+        C za[N], zb[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            u1[base + (long)Ny * (i + (long)N * c0)] = w[i];
-            if (pair) u1[base + (long)Ny * (i + (long)N * c1)] = w[N + i];
+            const long r = cy + (long)Ny * (i + N * j);
+            za[i] = Z[r + M * p];
+            zb[i] = Z[r + M * wp.q];
+        }
+        const long base = cy + (long)Ny * N * Nx * j;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            if (w == 1 && wp.nw == 1) break;
+            const int k = wp.k[w];
+            const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+            const bool pair = c1 >= 0;
+            T v[S], o[S];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const C x = w ? unpack_half(zb[i], za[i], wp.c[1], wp.s[1])
+                              : unpack_half(za[i], zb[i], wp.c[0], wp.s[0]);
+                spec_to_coef(x, pair, cn, cp, v[i], v[N + i]);
+            }
+            mix_vec<N, T>(Mf + (size_t)k * S * S, pair, v, o);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                u1[base + (long)Ny * (i + (long)N * c0)] = o[i];
+                if (pair) u1[base + (long)Ny * (i + (long)N * c1)] = o[N + i];
+            }
         }
     }
 }
 
-// Inverse x mixing: U1 (real coefficients) -> the x spectra, ready for the
-// inverse x transform.
+// Inverse x mixing: U1 (real coefficients) -> the packed x spectra, ready for
+// the inverse x transform.
 template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_inv(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mi, T cn, T cp,
-    const T* __restrict__ u1, typename CplxOf<T>::type* __restrict__ X) {
+    const T* __restrict__ u1, typename CplxOf<T>::type* __restrict__ Z) {
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    const int k = blockIdx.y;
-    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
-    const bool pair = c1 >= 0;
-    const T* Mk = Mi + (size_t)k * S * S;
+    const int p = blockIdx.y;
+    const WavePair<T> wp(p, Nx);
     const long per = (long)Ny * N, M = (long)Ny * N * N;
     for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
          t += (long)gridDim.x * kPwThreads) {
         const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
         const long base = cy + (long)Ny * N * Nx * j;
-        T v[S], w[S];
+        C y[2][N];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            if (w == 1 && wp.nw == 1) break;
+            const int k = wp.k[w];
+            const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+            const bool pair = c1 >= 0;
+            T v[S], o[S];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v[i] = u1[base + (long)Ny * (i + (long)N * c0)];
+                v[N + i] = pair ? u1[base + (long)Ny * (i + (long)N * c1)] : T(0);
+            }
+            mix_vec<N, T>(Mi + (size_t)k * S * S, pair, v, o);
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                y[w][i] = coef_to_spec<C>(pair, cn, cp, o[i], pair ? o[N + i] : T(0));
+        }
+        if (wp.nw == 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) y[1][i] = y[0][i];
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            v[i] = u1[base + (long)Ny * (i + (long)N * c0)];
-            v[N + i] = pair ? u1[base + (long)Ny * (i + (long)N * c1)] : T(0);
+            const long r = cy + (long)Ny * (i + N * j);
+            Z[r + M * p] = pack_half(y[0][i], y[1][i], wp.c[0], wp.s[0]);
+            if (p > 0 && wp.nw == 2)
+                Z[r + M * wp.k[1]] = pack_half(y[1][i], y[0][i], wp.c[1], wp.s[1]);
         }
-        mix_vec<N, T>(Mk, pair, v, w);
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            X[cy + (long)Ny * (i + N * j) + M * k] =
-                coef_to_spec<C>(pair, cn, cp, w[i], pair ? w[N + i] : T(0));
     }
 }
 
-// y mixing, spectral division and unmixing in place on the y spectra
-// Y[(m + n Nx j) + n^2 Nx k] (m = i + n kx; block row k = blockIdx.y, lanes
-// along m): spectrum -> y modes (Mf), divided by -(lam_x + lam_y), the
-// constant mode zeroed, -> coefficients (Mi) -> spectrum.
+// y mixing, spectral division and unmixing in place on the packed y spectra
+// Z[(m + n Nx j) + n^2 Nx k] (m = i + n kx, k < Ny/2; block row p =
+// blockIdx.y, lanes along m): spectrum -> y modes (Mf), divided by
+// -(lam_x + lam_y), the constant mode zeroed, -> coefficients (Mi) ->
+// spectrum.  Each lane reads and writes the same two spectrum rows.
 template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf,
     const T* __restrict__ Mi, const T* __restrict__ lx, const T* __restrict__ ly, int zx, int zy,
-    T cn, T cp, typename CplxOf<T>::type* __restrict__ Y) {
+    T cn, T cp, typename CplxOf<T>::type* __restrict__ Z) {
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    const int k = blockIdx.y;
-    const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
-    const bool pair = c1 >= 0;
-    const T* Mfk = Mf + (size_t)k * S * S;
-    const T* Mik = Mi + (size_t)k * S * S;
-    const long NXn = (long)N * Nx;
+    const int p = blockIdx.y;
+    const WavePair<T> wp(p, Ny);
+    const long NXn = (long)N * Nx, M = NXn * N;
     for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
          m += (long)gridDim.x * kPwThreads) {
         const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
         const int xs = i * Nx + kx;
         const T lam_x = lx[xs];
-        T v[S], w[S];
+        C za[N], zb[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-            spec_to_coef(Y[m + NXn * j + NXn * N * k], pair, cn, cp, v[j], v[N + j]);
-        mix_vec<N, T>(Mfk, pair, v, w);
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            if (q >= N && !pair) break;
-            const int ys = (q % N) * Ny + (q < N ? c0 : c1);
-            w[q] = (xs == zx && ys == zy) ? T(0) : w[q] / -(lam_x + ly[ys]);
+        for (int j = 0; j < N; ++j) {
+            za[j] = Z[m + NXn * j + M * p];
+            zb[j] = Z[m + NXn * j + M * wp.q];
         }
-        mix_vec<N, T>(Mik, pair, w, v);
+        C y[2][N];
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-            Y[m + NXn * j + NXn * N * k] = coef_to_spec<C>(pair, cn, cp, v[j], pair ? v[N + j] : T(0));
+        for (int w = 0; w < 2; ++w) {
+            if (w == 1 && wp.nw == 1) break;
+            const int k = wp.k[w];
+            const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+            const bool pair = c1 >= 0;
+            T v[S], o[S];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const C x = w ? unpack_half(zb[j], za[j], wp.c[1], wp.s[1])
+                              : unpack_half(za[j], zb[j], wp.c[0], wp.s[0]);
+                spec_to_coef(x, pair, cn, cp, v[j], v[N + j]);
+            }
+            mix_vec<N, T>(Mf + (size_t)k * S * S, pair, v, o);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (q >= N && !pair) break;
+                const int ys = (q % N) * Ny + (q < N ? c0 : c1);
+                o[q] = (xs == zx && ys == zy) ? T(0) : o[q] / -(lam_x + ly[ys]);
+            }
+            mix_vec<N, T>(Mi + (size_t)k * S * S, pair, o, v);
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                y[w][j] = coef_to_spec<C>(pair, cn, cp, v[j], pair ? v[N + j] : T(0));
+        }
+        if (wp.nw == 1) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) y[1][j] = y[0][j];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            Z[m + NXn * j + M * p] = pack_half(y[0][j], y[1][j], wp.c[0], wp.s[0]);
+            if (p > 0 && wp.nw == 2)
+                Z[m + NXn * j + M * wp.k[1]] = pack_half(y[1][j], y[0][j], wp.c[1], wp.s[1]);
+        }
     }
 }
 
@@ -646,35 +756,38 @@ hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const 
 }
 
 template <class T>
-hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, const int* cols, const T* Mf,
                                 const void* X, T* u1, hipStream_t s) {
     using C = typename CplxOf<T>::type;
     const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), dim3(nb, K), dim3(kPwThreads),
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), dim3(nb, Nx / 4 + 1),
+                                        dim3(kPwThreads),
                                         0, s, Nx, Ny, cols, Mf, cn, cp, (const C*)X, u1));
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, int K, const int* cols, const T* Mi,
+hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, const int* cols, const T* Mi,
                                 const T* u1, void* X, hipStream_t s) {
     using C = typename CplxOf<T>::type;
     const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), dim3(nb, K), dim3(kPwThreads),
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), dim3(nb, Nx / 4 + 1),
+                                        dim3(kPwThreads),
                                         0, s, Nx, Ny, cols, Mi, cn, cp, u1, (C*)X));
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fft_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
+hipError_t launch_fft_mix_y(int n, int Nx, int Ny, const int* cols, const T* Mf,
                             const T* Mi, const T* lx, const T* ly, int zx, int zy, void* Y,
                             hipStream_t s) {
     using C = typename CplxOf<T>::type;
     const int nb = pw_blocks((long)Nx * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Ny)), cp = T(std::sqrt(2.0 / Ny));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_y<NN, T>), dim3(nb, K), dim3(kPwThreads), 0,
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_y<NN, T>), dim3(nb, Ny / 4 + 1),
+                                        dim3(kPwThreads), 0,
                                         s, Nx, Ny, cols, Mf, Mi, lx, ly, zx, zy, cn, cp, (C*)Y));
     return hipGetLastError();
 }
@@ -697,11 +810,11 @@ hipError_t launch_fft_mix_y(int n, int Nx, int Ny, int K, const int* cols, const
                                                 const T*, const T*, T*, hipStream_t);         \
     template hipError_t launch_fd_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \
                                            const T*, const T*, int, int, T*, hipStream_t);     \
-    template hipError_t launch_fft_mix_x_fwd<T>(int, int, int, int, const int*, const T*,      \
+    template hipError_t launch_fft_mix_x_fwd<T>(int, int, int, const int*, const T*,      \
                                                 const void*, T*, hipStream_t);                 \
-    template hipError_t launch_fft_mix_x_inv<T>(int, int, int, int, const int*, const T*,      \
+    template hipError_t launch_fft_mix_x_inv<T>(int, int, int, const int*, const T*,      \
                                                 const T*, void*, hipStream_t);                 \
-    template hipError_t launch_fft_mix_y<T>(int, int, int, int, const int*, const T*, const T*, \
+    template hipError_t launch_fft_mix_y<T>(int, int, int, const int*, const T*, const T*, \
                                             const T*, const T*, int, int, void*, hipStream_t);
 DG_FD_INSTANTIATE(double)
 DG_FD_INSTANTIATE(float)

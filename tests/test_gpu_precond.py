@@ -61,9 +61,12 @@ def _wn(g, u):
 CASES = [(1, 5, 4, 1.0, 1.3), (2, 6, 6, 2.0, 2.0), (3, 37, 23, 2.0, 1.5),
          (4, 64, 40, 6.283185307179586, 6.283185307179586), (5, 7, 4, 1.0, 3.0),
          (4, 1, 3, 1.0, 1.0), (2, 2, 2, 1.0, 1.0), (5, 64, 64, 6.283185307179586, 6.283185307179586),
-         # beyond 512 cells on an axis the cell transforms are real FFTs: an
-         # even and an odd length, the other axis below and above 512
-         (2, 1024, 96, 6.283185307179586, 3.0), (1, 601, 520, 2.0, 2.5)]
+         # beyond 512 cells on an axis with both counts even the cell
+         # transforms are FFTs of half length: N/2 even and odd on either
+         # axis, the other axis below and above 512, a 6-cell axis (three
+         # complex values per row); an odd count keeps the folded products
+         (2, 1024, 96, 6.283185307179586, 3.0), (1, 522, 530, 1.0, 1.2),
+         (3, 516, 6, 1.5, 1.0), (1, 601, 520, 2.0, 2.5)]
 
 
 @pytest.mark.parametrize("n,nx,ny,lx,ly", CASES)
