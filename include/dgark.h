@@ -180,8 +180,8 @@ int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
  * DG_PREC_MIXED mode, plus (DG_WS_FD) the preconditioner's z vector, two
  * node-plane fields and per axis the factored eigenbasis in FP64 and FP32
  * (the N x N cell Fourier basis, 2 (N/2 + 1) mixing blocks of 2n x 2n and
- * n N eigenvalues; one set when the axes agree; rocBLAS and, beyond 512
- * cells on an axis, rocFFT keep their own work buffers on top).  On a grid
+ * n N eigenvalues; one set when the axes agree; rocBLAS and, on the FFT
+ * path, rocFFT keep their own work buffers on top).  On a grid
  * with a Dirichlet axis the preconditioner holds instead two dense work
  * images of n^2 Nx Ny doubles and per axis the dense (n N)^2 eigenbasis and
  * n N eigenvalues in FP64 and FP32.  This is the figure that admission
@@ -253,8 +253,10 @@ int  dg_cg_solve_poisson(const dg_grid* grid, const double* omega, double* psi,
  * transform, then 2n x 2n mixing per wave number); the transform is an FP64
  * matrix product up to 512 cells per axis -- with phases at the cell centres,
  * so that cells c and N - 1 - c fold each axis into two products of half
- * size (2 n^2 Nx Ny (Nx + Ny) flops per call) -- and a real FFT (rocFFT)
- * beyond.  On a grid with a homogeneous
+ * size (2 n^2 Nx Ny (Nx + Ny) flops per call) -- and beyond, when both
+ * cell counts are even, an FFT (rocFFT) of each real row read as a complex
+ * row of half length (an odd count keeps the matrix products).  On a grid
+ * with a homogeneous
  * Dirichlet axis (-Lap_h definite, z = (-Lap_h)^-1 r) both axes use dense
  * eigenbases (the Dirichlet one from rocSOLVER's symmetric eigensolver) and
  * the apply is four dense matrix products, 2 (n Nx)(n Ny)(n Nx + n Ny)
@@ -268,8 +270,8 @@ int  dg_precond_apply(const dg_grid* grid, const double* r, double* z,
  * L V = V diag(lam) and V^T W V = I for the 1D LDG second derivative L and
  * Gauss weights W of that axis; lam (host, N n doubles); *zero = the column
  * of the constant mode.  The cell Fourier basis is the one the transforms
- * use on this grid: phases at the cell centres (the matrix products, up to
- * 512 cells per axis) or at the cell edges (the FFTs).  DG_E_UNSUPPORTED for
+ * use on this grid: phases at the cell centres (the matrix products: up to
+ * 512 cells per axis, or an odd count) or at the cell edges (the FFTs).  DG_E_UNSUPPORTED for
  * a Dirichlet axis (its basis is computed on the device).  Touches no GPU. */
 int  dg_grid_fd_basis(const dg_grid* grid, int axis, double* V, double* lam, int* zero);
 /* The 1D LDG second derivative of one axis (axis 0: x, 1: y; Sec. 6 as read

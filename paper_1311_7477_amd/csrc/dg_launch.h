@@ -132,8 +132,8 @@ template <class T>
 hipError_t launch_fd_mix_y(int n, int Nx, int Ny, int K, const int* cols, const T* Mf,
                            const T* Mi, const T* lx, const T* ly, int zx, int zy, T* u,
                            hipStream_t s);
-// The same mixing on the half spectra of real FFTs along the cells (X, Y:
-// interleaved complex of type T; layouts in fd_kernels.hip).
+// The same mixing on the packed spectra of the FFTs along the cells (X, Y:
+// interleaved complex of type T, N/2 per real row; layouts in fd_kernels.hip).
 template <class T>
 hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, const int* cols, const T* Mf,
                                 const void* X, T* u1, hipStream_t s);

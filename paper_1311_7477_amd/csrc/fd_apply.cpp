@@ -76,8 +76,8 @@ int fft_fail(rocfft_status st, const char* what) {
     return fail(DG_E_HIP, "%s: rocFFT status %d", what, (int)st);
 }
 
-// Reals in one work field: the node planes, or the half spectra of the x or
-// of the y transform (N/2 + 1 complex values per transform).
+// Reals in one work field: the node planes or the packed spectra of the x or
+// y transform (N/2 complex values per real row), with room for N/2 + 1.
 size_t field_reals(int n, int Nx, int Ny) {
     const size_t nn = (size_t)n * n;
     size_t a = nn * Nx * Ny, b = nn * Ny * 2 * (Nx / 2 + 1), c = nn * Nx * 2 * (Ny / 2 + 1);

@@ -109,8 +109,9 @@ struct FdDevice {
                                                // fields (FP64, or FP32 in their
                                                // first half)
     void* blas = nullptr;                      // rocblas_handle
-    // real FFTs along the cells: plans [precision][x fwd, y fwd, y inv,
-    // x inv] (rocfft_plan, FP64 then FP32), one execution info, work buffer
+    // FFTs along the cells (each real row as a complex row of half length):
+    // plans [precision][x fwd, y fwd, y inv, x inv] (rocfft_plan, FP64 then
+    // FP32), one execution info, work buffer
     void* fft[2][4] = {{nullptr, nullptr, nullptr, nullptr},
                        {nullptr, nullptr, nullptr, nullptr}};
     void* fft_info = nullptr;

@@ -1,10 +1,10 @@
 // Device kernels of the fast-diagonalisation preconditioner.  Its fields
 // live in node planes: U[cell + nx ny (i + n j)] (cell = cy nx + cx), so the
 // cell Fourier transforms along x and y are plain matrix products over whole
-// planes (folded along x, see k_to_planes_fold) or batched real FFTs.  Here:
+// planes (folded along x, see k_to_planes_fold) or batched FFTs.  Here:
 // the conversions between the CG layouts and the planes, the per-wave-number
 // mixing of the x transform (with the fold of the y axis), the mixing +
-// spectral scaling + unmixing of the y transform, the same mixings on half
+// spectral scaling + unmixing of the y transform, the same mixings on packed
 // spectra for the FFT path, the dense path's conversions and division, and
 // the preconditioned dot product <r, z>_W that closes the PCG step.
 #include <cmath>

@@ -167,8 +167,8 @@ def test_workspace_bytes_and_field_size():
         return (N * N + 2 * K * (2 * n) ** 2 + N * n) * (8 + 4) + 2 * K * 4
 
     def field(n, Nx, Ny):
-        # a work field holds the node planes or the half spectra of the
-        # real FFTs along x or y (N/2 + 1 complex values per transform)
+        # a work field holds the node planes or the packed spectra of the
+        # FFTs along x or y, with room for N/2 + 1 complex values per row
         return 8 * n * n * max(Nx * Ny, Ny * 2 * (Nx // 2 + 1), Nx * 2 * (Ny // 2 + 1))
     bfd = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
     assert bfd == b64 + F + 2 * field(4, 512, 512) + axis(512, 4)
