@@ -101,8 +101,9 @@ def _pcg(dg, n, nx, ny, w, rtol, guess=None, precond=True, max_iter=100000, mixe
     return res, psi.cpu().numpy()
 
 
+# the last cases take the FFT path (N/2 odd on both axes; one short axis)
 @pytest.mark.parametrize("n,nx,ny", [(1, 9, 7), (2, 16, 16), (3, 37, 23), (4, 13, 29),
-                                     (5, 24, 24), (3, 1, 5)])
+                                     (5, 24, 24), (3, 1, 5), (1, 522, 530), (2, 1024, 96)])
 def test_pcg_parity(dg, n, nx, ny):
     print(f"pcg n={n} nx={nx} ny={ny}", flush=True)
     g = O.Grid2D(n, nx, ny)
@@ -120,7 +121,8 @@ def test_pcg_parity(dg, n, nx, ny):
 
 
 @pytest.mark.parametrize("n,nx,ny", [(1, 9, 7), (2, 16, 16), (3, 37, 23), (4, 13, 29),
-                                     (5, 24, 24), (3, 1, 5), (4, 64, 48)])
+                                     (5, 24, 24), (3, 1, 5), (4, 64, 48), (1, 522, 530),
+                                     (2, 1024, 96)])
 def test_pcg_mixed_parity(dg, n, nx, ny):
     print(f"mixed pcg n={n} nx={nx} ny={ny}", flush=True)
     g = O.Grid2D(n, nx, ny)
