@@ -426,23 +426,15 @@ int apply_dense(const FdDevice* fd, hipStream_t s) {
 
 // One batched 1D complex FFT of length H = L/2 along an axis of L cells:
 // `count` rows of L real values (distance L), each read as H interleaved
-// complex values, whose spectra are stored with stride `spec_stride` between
-// wave numbers and distance 1 between transforms (the wave number becomes
-// the slowest index); the inverse plan reads that layout back into rows.
-int make_plan(bool forward, bool fp32, size_t L, size_t count, size_t spec_stride,
-              rocfft_plan* out) {
+// complex values, the spectra stored row by row in the same way.
+int make_plan(bool forward, bool fp32, size_t L, size_t count, rocfft_plan* out) {
     rocfft_plan_description d = nullptr;
     rocfft_status st = rocfft_plan_description_create(&d);
     if (st != rocfft_status_success) return fft_fail(st, "plan description");
     const size_t one = 1, H = L / 2;
-    if (forward)
-        st = rocfft_plan_description_set_data_layout(
-            d, rocfft_array_type_complex_interleaved, rocfft_array_type_complex_interleaved,
-            nullptr, nullptr, 1, &one, H, 1, &spec_stride, 1);
-    else
-        st = rocfft_plan_description_set_data_layout(
-            d, rocfft_array_type_complex_interleaved, rocfft_array_type_complex_interleaved,
-            nullptr, nullptr, 1, &spec_stride, 1, 1, &one, H);
+    st = rocfft_plan_description_set_data_layout(
+        d, rocfft_array_type_complex_interleaved, rocfft_array_type_complex_interleaved, nullptr,
+        nullptr, 1, &one, H, 1, &one, H);
     if (st == rocfft_status_success)
         st = rocfft_plan_create(out, rocfft_placement_notinplace,
                                 forward ? rocfft_transform_type_complex_forward
@@ -463,10 +455,10 @@ int make_fft(const dg_grid* g, FdDevice* fd) {
     const size_t bx = Ny * n * n, by = n * n * Nx;    // transforms per axis
     for (int pr = 0; pr < 2; ++pr) {
         rocfft_plan plans[4] = {nullptr, nullptr, nullptr, nullptr};
-        int rc = make_plan(true, pr == 1, Nx, bx, bx, &plans[0]);
-        if (rc == DG_OK) rc = make_plan(true, pr == 1, Ny, by, by, &plans[1]);
-        if (rc == DG_OK) rc = make_plan(false, pr == 1, Ny, by, by, &plans[2]);
-        if (rc == DG_OK) rc = make_plan(false, pr == 1, Nx, bx, bx, &plans[3]);
+        int rc = make_plan(true, pr == 1, Nx, bx, &plans[0]);
+        if (rc == DG_OK) rc = make_plan(true, pr == 1, Ny, by, &plans[1]);
+        if (rc == DG_OK) rc = make_plan(false, pr == 1, Ny, by, &plans[2]);
+        if (rc == DG_OK) rc = make_plan(false, pr == 1, Nx, bx, &plans[3]);
         for (int i = 0; i < 4; ++i) fd->fft[pr][i] = plans[i];
         if (rc != DG_OK) return rc;
         for (int i = 0; i < 4; ++i) {

@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
 
 // ---- The same steps with the cell transforms as FFTs.  A real row u of
 // even length N is transformed as the complex row z_c = u_{2c} + i u_{2c+1}
-// of length H = N/2 (rocFFT, wave number the slowest index of the result).
+// of length H = N/2 (rocFFT, spectra stored row by row like the input).
 // The real row's half spectrum X_k = sum_c u_c e^{-2 pi i k c / N} follows
 // from Z_k and Z_{H-k} (indices mod H): with E = (Z_k + conj Z_{H-k}) / 2
 // and O = (Z_k - conj Z_{H-k}) / 2i, X_k = E + e^{-2 pi i k / N} O for
@@ -378,8 +378,8 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
 // with E = Y_k + conj Y_{H-k} and O = (Y_k - conj Y_{H-k}) e^{2 pi i k / N}
 // (k < H) has as unnormalised inverse transform the even (real part) and odd
 // (imaginary part) samples of the real inverse transform of Y.  Wave numbers
-// k and H - k take the same two values, so block row p serves both (p = 0
-// with H).  The orthonormal cos / sin coefficients of wave number k are
+// k and H - k take the same two values, so the blocks of wave pair p serve
+// both (p = 0 with H).  The orthonormal cos / sin coefficients of wave number k are
 // sqrt(2/N) (Re X_k, -Im X_k) (k = 0 and N/2: 1/sqrt(N) Re X_k), and the
 // real inverse transform of Y_k = sqrt(2/N)/2 (a - i b), Y_0 and Y_{N/2} =
 // 1/sqrt(N) a, rebuilds sum a cos + b sin.  The mixing kernels convert
@@ -460,28 +460,42 @@ __device__ __forceinline__ C pack_half(const C ya, const C yb, T c, T s) {
     return z;
 }
 
-// Forward x mixing from the x spectra Z[(cy + Ny (i + n j)) + M k] (M =
-// Ny n^2, k < Nx/2; block row p = blockIdx.y, lanes along cy) into the real
-// x-transformed field U1[cy + Ny (i + n c + n Nx j)] (c: the cos / sin
-// columns of wave number k, as in the matrix-product path).
+// Block -> (wave pair p, row block rb) for the FFT mixing kernels (grid P x
+// row blocks).  Neighbouring wave pairs read neighbouring values of the same
+// spectrum rows, so they should share one L2: workgroups go to the 8 XCDs
+// in turn, and this map gives each XCD a contiguous run of (p fastest)
+// blocks; the last total mod 8 blocks keep their place.
+__device__ __forceinline__ void xcd_pair_block(int& p, int& rb) {
+    const int P = gridDim.x, total = P * gridDim.y;
+    const int b = blockIdx.x + P * blockIdx.y, full = total & ~7;
+    const int l = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
+    p = l % P;
+    rb = l / P;
+}
+
+// Forward x mixing from the x spectra Z[(cy + Ny (i + n j)) H + k] (H =
+// Nx/2, k < H; wave pair and row block from xcd_pair_block, lanes along cy)
+// into the real x-transformed field U1[cy + Ny (i + n c + n Nx j)] (c: the
+// cos / sin columns of wave number k, as in the matrix-product path).
 template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_fwd(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf, T cn, T cp,
     const typename CplxOf<T>::type* __restrict__ Z, T* __restrict__ u1) {
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    const int p = blockIdx.y;
+    int p, rb;
+    xcd_pair_block(p, rb);
     const WavePair<T> wp(p, Nx);
-    const long per = (long)Ny * N, M = (long)Ny * N * N;
-    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
-         t += (long)gridDim.x * kPwThreads) {
+    const long per = (long)Ny * N, H = Nx / 2;
+    for (long t = rb * (long)kPwThreads + threadIdx.x; t < per;
+         t += (long)gridDim.y * kPwThreads) {
         const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
         C za[N], zb[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const long r = cy + (long)Ny * (i + N * j);
-            za[i] = Z[r + M * p];
-            zb[i] = Z[r + M * wp.q];
+            za[i] = Z[r * H + p];
+            zb[i] = Z[r * H + wp.q];
         }
         const long base = cy + (long)Ny * N * Nx * j;
 #pragma unroll
@@ -515,11 +529,12 @@ __global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_inv(
     const T* __restrict__ u1, typename CplxOf<T>::type* __restrict__ Z) {
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    const int p = blockIdx.y;
+    int p, rb;
+    xcd_pair_block(p, rb);
     const WavePair<T> wp(p, Nx);
-    const long per = (long)Ny * N, M = (long)Ny * N * N;
-    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
-         t += (long)gridDim.x * kPwThreads) {
+    const long per = (long)Ny * N, H = Nx / 2;
+    for (long t = rb * (long)kPwThreads + threadIdx.x; t < per;
+         t += (long)gridDim.y * kPwThreads) {
         const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
         const long base = cy + (long)Ny * N * Nx * j;
         C y[2][N];
@@ -547,18 +562,18 @@ __global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_inv(
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const long r = cy + (long)Ny * (i + N * j);
-            Z[r + M * p] = pack_half(y[0][i], y[1][i], wp.c[0], wp.s[0]);
+            Z[r * H + p] = pack_half(y[0][i], y[1][i], wp.c[0], wp.s[0]);
             if (p > 0 && wp.nw == 2)
-                Z[r + M * wp.k[1]] = pack_half(y[1][i], y[0][i], wp.c[1], wp.s[1]);
+                Z[r * H + wp.k[1]] = pack_half(y[1][i], y[0][i], wp.c[1], wp.s[1]);
         }
     }
 }
 
 // y mixing, spectral division and unmixing in place on the packed y spectra
-// Z[(m + n Nx j) + n^2 Nx k] (m = i + n kx, k < Ny/2; block row p =
-// blockIdx.y, lanes along m): spectrum -> y modes (Mf), divided by
-// -(lam_x + lam_y), the constant mode zeroed, -> coefficients (Mi) ->
-// spectrum.  Each lane reads and writes the same two spectrum rows.
+// Z[(m + n Nx j) H + k] (m = i + n kx, H = Ny/2, k < H; wave pair and row
+// block from xcd_pair_block, lanes along m): spectrum -> y modes (Mf),
+// divided by -(lam_x + lam_y), the constant mode zeroed, -> coefficients
+// (Mi) -> spectrum.  Each lane reads and writes the same two spectrum rows.
 template <int N, class T>
 __global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf,
@@ -566,19 +581,20 @@ __global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
     T cn, T cp, typename CplxOf<T>::type* __restrict__ Z) {
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    const int p = blockIdx.y;
+    int p, rb;
+    xcd_pair_block(p, rb);
     const WavePair<T> wp(p, Ny);
-    const long NXn = (long)N * Nx, M = NXn * N;
-    for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
-         m += (long)gridDim.x * kPwThreads) {
+    const long NXn = (long)N * Nx, H = Ny / 2;
+    for (long m = rb * (long)kPwThreads + threadIdx.x; m < NXn;
+         m += (long)gridDim.y * kPwThreads) {
         const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
         const int xs = i * Nx + kx;
         const T lam_x = lx[xs];
         C za[N], zb[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            za[j] = Z[m + NXn * j + M * p];
-            zb[j] = Z[m + NXn * j + M * wp.q];
+            za[j] = Z[(m + NXn * j) * H + p];
+            zb[j] = Z[(m + NXn * j) * H + wp.q];
         }
         C y[2][N];
 #pragma unroll
@@ -612,9 +628,9 @@ __global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
         }
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            Z[m + NXn * j + M * p] = pack_half(y[0][j], y[1][j], wp.c[0], wp.s[0]);
+            Z[(m + NXn * j) * H + p] = pack_half(y[0][j], y[1][j], wp.c[0], wp.s[0]);
             if (p > 0 && wp.nw == 2)
-                Z[m + NXn * j + M * wp.k[1]] = pack_half(y[1][j], y[0][j], wp.c[1], wp.s[1]);
+                Z[(m + NXn * j) * H + wp.k[1]] = pack_half(y[1][j], y[0][j], wp.c[1], wp.s[1]);
         }
     }
 }
@@ -761,7 +777,7 @@ hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, const int* cols, const T*
     using C = typename CplxOf<T>::type;
     const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), dim3(nb, Nx / 4 + 1),
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), dim3(Nx / 4 + 1, nb),
                                         dim3(kPwThreads),
                                         0, s, Nx, Ny, cols, Mf, cn, cp, (const C*)X, u1));
     return hipGetLastError();
@@ -773,7 +789,7 @@ hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, const int* cols, const T*
     using C = typename CplxOf<T>::type;
     const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), dim3(nb, Nx / 4 + 1),
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), dim3(Nx / 4 + 1, nb),
                                         dim3(kPwThreads),
                                         0, s, Nx, Ny, cols, Mi, cn, cp, u1, (C*)X));
     return hipGetLastError();
@@ -786,7 +802,7 @@ hipError_t launch_fft_mix_y(int n, int Nx, int Ny, const int* cols, const T* Mf,
     using C = typename CplxOf<T>::type;
     const int nb = pw_blocks((long)Nx * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Ny)), cp = T(std::sqrt(2.0 / Ny));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_y<NN, T>), dim3(nb, Ny / 4 + 1),
+    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_y<NN, T>), dim3(Ny / 4 + 1, nb),
                                         dim3(kPwThreads), 0,
                                         s, Nx, Ny, cols, Mf, Mi, lx, ly, zx, zy, cn, cp, (C*)Y));
     return hipGetLastError();
