@@ -107,6 +107,10 @@ typedef struct {
     double     D;           /* viscosity */
     dg_cg_opts cg;          /* options of the three Poisson solves */
     int        record_times;/* 1: time each stage with HIP events (stats.stage_ms) */
+    int        form;        /* bracket in the right-hand side: DG_FORM_ARAKAWA
+                               (0, the conservative average) or one single form
+                               DG_FORM_PP / _PX / _XP (Sec. 2 eq. J; Sec. 6.2
+                               compares J++ with J on the Lamb dipole) */
 } dg_step_opts;
 
 typedef struct {

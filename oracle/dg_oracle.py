@@ -30,6 +30,7 @@ __all__ = [
     "to_image", "from_image", "dx", "dy", "dx_form", "dy_form",
     "bracket_forms", "bracket", "laplacian", "inner", "wmean",
     "cg_poisson", "pcg_poisson", "FastDiagonalisation", "rhs", "rk3_step",
+    "rk3_step_pcg",
     "PsiHistory", "invariants", "AB_COEFFS", "ab_step",
     "dense_operators", "dense_poisson_solve", "arakawa_fd_jacobian",
     "five_point_laplacian",
@@ -355,11 +356,15 @@ def bracket_forms(g: Grid2D, f: np.ndarray, h: np.ndarray):
     return tuple(from_image(J, g.n) for J in (Jpp, Jpx, Jxp))
 
 
-def bracket(g: Grid2D, f: np.ndarray, h: np.ndarray) -> np.ndarray:
+def bracket(g: Grid2D, f: np.ndarray, h: np.ndarray, form: str = "arakawa") -> np.ndarray:
     """Conservative dG Arakawa bracket J = (J++ + J+x + Jx+)/3 (Sec. 2 eq. J,
-    Sec. 3 end)."""
+    Sec. 3 end), or one single Jacobian form: form = "pp" (J++), "px"
+    (J+x) or "xp" (Jx+).  Sec. 6.2 time-steps the Lamb dipole with J++ alone
+    to show what the average conserves."""
     Jpp, Jpx, Jxp = bracket_forms(g, f, h)
-    return (Jpp + Jpx + Jxp) / 3.0
+    if form == "arakawa":
+        return (Jpp + Jpx + Jxp) / 3.0
+    return {"pp": Jpp, "px": Jpx, "xp": Jxp}[form]
 
 
 def laplacian(g: Grid2D, u: np.ndarray) -> np.ndarray:
@@ -542,10 +547,12 @@ def pcg_poisson(g: Grid2D, omega: np.ndarray, guess=None, rtol=1e-12,
 # --------------------------------------------------------------------------
 # Right-hand side and SSP-RK3
 # --------------------------------------------------------------------------
-def rhs(g: Grid2D, omega: np.ndarray, psi: np.ndarray, D: float) -> np.ndarray:
+def rhs(g: Grid2D, omega: np.ndarray, psi: np.ndarray, D: float,
+        form: str = "arakawa") -> np.ndarray:
     """R(omega) = -J(psi, omega) + D Delta_h omega for
-    d_t omega + {psi, omega} = D Delta omega (Sec. 1, eq. vorticity)."""
-    return -bracket(g, psi, omega) + D * laplacian(g, omega)
+    d_t omega + {psi, omega} = D Delta omega (Sec. 1, eq. vorticity); J is
+    the bracket of the given form (see bracket)."""
+    return -bracket(g, psi, omega, form) + D * laplacian(g, omega)
 
 
 class PsiHistory:
@@ -571,7 +578,7 @@ class PsiHistory:
 
 
 def rk3_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float,
-             hist: PsiHistory, rtol=1e-12, max_iter=100000):
+             hist: PsiHistory, rtol=1e-12, max_iter=100000, form: str = "arakawa"):
     """One Shu-Osher SSP-RK3 step of d_t omega = R(omega); stage times t,
     t+dt, t+dt/2; each stage solves the Poisson problem for its psi.
     Returns (omega_new, [cg iteration counts])."""
@@ -581,7 +588,7 @@ def rk3_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float,
         res = cg_poisson(g, w, hist.guess(ts), rtol, max_iter)
         hist.push(ts, res.x)
         iters.append(res.iters)
-        return rhs(g, w, res.x, D)
+        return rhs(g, w, res.x, D, form)
 
     u1 = omega + dt * stage_rhs(omega, t)
     u2 = 0.75 * omega + 0.25 * (u1 + dt * stage_rhs(u1, t + dt))
@@ -606,7 +613,7 @@ AB_COEFFS = {
 
 def ab_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float, K: int,
             rhs_hist: list, hist: PsiHistory, rtol=1e-12, max_iter=100000,
-            precond=None):
+            precond=None, form: str = "arakawa"):
     """One step of the K-step Adams-Bashforth method.  rhs_hist holds the
     right-hand sides of the previous steps, most recent first, and is
     updated in place.  While fewer than K-1 are known the step is an SSP-RK3
@@ -616,10 +623,10 @@ def ab_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float, K: int,
     the extrapolated guess.  Returns (omega_new, [cg iteration counts])."""
     res = pcg_poisson(g, omega, hist.guess(t), rtol, max_iter, precond)
     hist.push(t, res.x)
-    r_n = rhs(g, omega, res.x, D)
+    r_n = rhs(g, omega, res.x, D, form)
     if len(rhs_hist) < K - 1:
         rhs_hist.insert(0, r_n)
-        w, its = _rk3_precond(g, omega, t, dt, D, hist, rtol, max_iter, precond)
+        w, its = rk3_step_pcg(g, omega, t, dt, D, hist, rtol, max_iter, precond, form)
         return w, [res.iters] + its
     rs = [r_n] + rhs_hist[:K - 1]
     w = omega.copy()
@@ -629,15 +636,18 @@ def ab_step(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float, K: int,
     return w, [res.iters]
 
 
-def _rk3_precond(g, omega, t, dt, D, hist, rtol, max_iter, precond):
-    """rk3_step with an optional CG preconditioner (same stages)."""
+def rk3_step_pcg(g: Grid2D, omega: np.ndarray, t: float, dt: float, D: float,
+                 hist: PsiHistory, rtol=1e-12, max_iter=100000, precond=None,
+                 form: str = "arakawa"):
+    """rk3_step with the stage solves by pcg_poisson and an optional
+    preconditioner (same stages, same guesses)."""
     iters = []
 
     def stage_rhs(w, ts):
         res = pcg_poisson(g, w, hist.guess(ts), rtol, max_iter, precond)
         hist.push(ts, res.x)
         iters.append(res.iters)
-        return rhs(g, w, res.x, D)
+        return rhs(g, w, res.x, D, form)
 
     u1 = omega + dt * stage_rhs(omega, t)
     u2 = 0.75 * omega + 0.25 * (u1 + dt * stage_rhs(u1, t + dt))

@@ -80,6 +80,9 @@ int dg_ab_step(const dg_grid* g, double* omega, dg_ab_state* ab, const dg_step_o
         return fail(DG_E_INVAL, "Adams-Bashforth state was made for another grid");
     if (!std::isfinite(opts->dt) || !std::isfinite(opts->D))
         return fail(DG_E_INVAL, "dt and D must be finite");
+    double fc[4];
+    const int frc = form_coeffs(opts->form, &fc[0], &fc[1], &fc[2], &fc[3]);
+    if (frc != DG_OK) return frc;
     const hipStream_t s = (hipStream_t)stream;
     const int K = ab->K;
     dg_state* st = ab->st;
@@ -102,7 +105,7 @@ int dg_ab_step(const dg_grid* g, double* omega, dg_ab_state* ab, const dg_step_o
     double* rn = ab->R[K - 1];
     for (int j = K - 1; j > 0; --j) ab->R[j] = ab->R[j - 1];
     ab->R[0] = rn;
-    RhsParams p{1.0, 1.0, 1.0, 1.0 / 3.0, opts->D, 1.0, 0.0, 1.0, 1};
+    RhsParams p{fc[0], fc[1], fc[2], fc[3], opts->D, 1.0, 0.0, 1.0, 1};
     hipError_t e = launch_rhs(g->geom, g->k64, x, omega, nullptr, rn, p, true, s);
     if (e != hipSuccess) return hip_fail(e, "rhs launch");
     if (stats) stats->cg_iters[0] = cs.iters;

@@ -417,6 +417,19 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
 }  // namespace
 
 namespace dgk {
+int form_coeffs(int form, double* c0, double* c1, double* c2, double* scale) {
+    *c0 = *c1 = *c2 = 0.0;
+    *scale = 1.0;
+    switch (form) {
+        case DG_FORM_ARAKAWA: *c0 = *c1 = *c2 = 1.0; *scale = 1.0 / 3.0; break;
+        case DG_FORM_PP: *c0 = 1.0; break;
+        case DG_FORM_PX: *c1 = 1.0; break;
+        case DG_FORM_XP: *c2 = 1.0; break;
+        default: return fail(DG_E_INVAL, "unknown bracket form %d", form);
+    }
+    return DG_OK;
+}
+
 int periodic_only(const char* what) {
     return fail(DG_E_UNSUPPORTED, "%s is implemented for periodic grids only "
                 "(Dirichlet grids support the bracket, the Laplacian, the FP64 CG plain "
@@ -618,13 +631,8 @@ int dg_bracket_form(const dg_grid* g, const double* f, const double* gg,
     if (ranges_overlap(out, f, B) || ranges_overlap(out, gg, B))
         return fail(DG_E_ALIAS, "out aliases an input");
     RhsParams p{};
-    switch (form) {
-        case DG_FORM_ARAKAWA: p.c0 = p.c1 = p.c2 = 1.0; p.scale = 1.0 / 3.0; break;
-        case DG_FORM_PP: p.c0 = 1.0; p.scale = 1.0; break;
-        case DG_FORM_PX: p.c1 = 1.0; p.scale = 1.0; break;
-        case DG_FORM_XP: p.c2 = 1.0; p.scale = 1.0; break;
-        default: return fail(DG_E_INVAL, "unknown bracket form %d", form);
-    }
+    const int rc = form_coeffs(form, &p.c0, &p.c1, &p.c2, &p.scale);
+    if (rc != DG_OK) return rc;
     hipError_t e = launch_rhs(g->geom, g->k64, f, gg, nullptr, out, p, false,
                               as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "bracket launch");
@@ -760,6 +768,9 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
         return fail(DG_E_INVAL, "state was made for another grid");
     if (!std::isfinite(opts->dt) || !std::isfinite(opts->D))
         return fail(DG_E_INVAL, "dt and D must be finite");
+    double fc[4];
+    rc = form_coeffs(opts->form, &fc[0], &fc[1], &fc[2], &fc[3]);
+    if (rc != DG_OK) return rc;
     hipStream_t s = as_stream(stream);
     const double dt = opts->dt, t = st->t;
     const double ts[3] = {t, t + dt, t + 0.5 * dt};
@@ -785,7 +796,7 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
         if (rc == DG_E_NOCONV) { result = DG_E_NOCONV; all_conv = false; }
         else if (rc != DG_OK) return rc;
         state_push(st, fr, ts[k]);
-        RhsParams p{1.0, 1.0, 1.0, 1.0 / 3.0, opts->D, dt, ra[k], rb[k]};
+        RhsParams p{fc[0], fc[1], fc[2], fc[3], opts->D, dt, ra[k], rb[k], 0};
         hipError_t e = launch_rhs(g->geom, g->k64, x, win[k], k ? omega : nullptr,
                                   wout[k], p, true, s);
         if (e != hipSuccess) return hip_fail(e, "rhs launch");

@@ -63,6 +63,9 @@ void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
 void state_push(dg_state* st, int xi, double ts);
 // DG_E_UNSUPPORTED for an operation that needs a periodic grid.
 int periodic_only(const char* what);
+// Bracket coefficients of a DG_FORM_* (Sec. 2 eq. J): c0 J++ + c1 J+x +
+// c2 Jx+, times scale; DG_E_INVAL for an unknown form.
+int form_coeffs(int form, double* c0, double* c1, double* c2, double* scale);
 // The Poisson solve behind dg_cg_solve_poisson and the steppers: guess
 // ca pa + cb pb (canonical), result in x (canonical, must not alias pa, pb).
 int solve_poisson(const dg_grid* g, const double* omega, double* x, const double* pa,

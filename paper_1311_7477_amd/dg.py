@@ -41,7 +41,7 @@ class CgStats(ctypes.Structure):
 
 class StepOpts(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("D", ctypes.c_double), ("cg", CgOpts),
-                ("record_times", ctypes.c_int)]
+                ("record_times", ctypes.c_int), ("form", ctypes.c_int)]
 
 
 class StepStats(ctypes.Structure):
@@ -360,8 +360,9 @@ class StepResult:
 
 
 def rk_step(grid: Grid, omega, state: State, ws: Workspace, dt, D,
-            opts: CgOpts = None, record_times=False):
-    so = StepOpts(dt, D, cg_opts() if opts is None else opts, 1 if record_times else 0)
+            opts: CgOpts = None, record_times=False, form=DG_FORM_ARAKAWA):
+    so = StepOpts(dt, D, cg_opts() if opts is None else opts, 1 if record_times else 0,
+                  form)
     st = StepStats()
     _check(lib().dg_rk_step(grid.handle, _field(omega, grid, "omega"), state.handle,
                             ctypes.byref(so), ctypes.byref(st), ws.handle, _stream()),
@@ -402,8 +403,9 @@ class AbState:
             self._h = None
 
 
-def ab_step(grid: Grid, omega, ab: AbState, ws: Workspace, dt, D, opts: CgOpts = None):
-    so = StepOpts(dt, D, cg_opts() if opts is None else opts, 0)
+def ab_step(grid: Grid, omega, ab: AbState, ws: Workspace, dt, D, opts: CgOpts = None,
+            form=DG_FORM_ARAKAWA):
+    so = StepOpts(dt, D, cg_opts() if opts is None else opts, 0, form)
     st = StepStats()
     _check(lib().dg_ab_step(grid.handle, _field(omega, grid, "omega"), ab.handle,
                             ctypes.byref(so), ctypes.byref(st), ws.handle, _stream()),

@@ -102,6 +102,22 @@ def _spectrum_coefficients(k0, rng, energy):
     return K, c, c / k2
 
 
+def random_modes(n, Nx, Ny, seed=0, kmax=4):
+    """Smooth seeded field on [0, 2pi]^2 for any Nx x Ny: sum over wave
+    vectors 0 < |kx|, ky <= kmax (ky >= 0) of a N(0,1) amplitude over
+    kx^2 + ky^2 times sin(kx x + ky y + phase), phase ~ U[0, 2pi)."""
+    X, Y = node_coords(n, Nx, Ny)
+    rng = np.random.default_rng(seed)
+    w = np.zeros_like(X)
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(0, kmax + 1):
+            if kx == 0 and ky == 0:
+                continue
+            a, ph = rng.standard_normal(), rng.uniform(0.0, 2 * math.pi)
+            w += a * np.sin(kx * X + ky * Y + ph) / (kx * kx + ky * ky)
+    return w
+
+
 def random_spectrum(n, N, k0=10.0, seed=1, energy=0.5, return_umax=False):
     """Zero-mean random-spectrum vorticity on [0, 2pi]^2 (see module doc).
     With return_umax, also returns max over nodes of |u_x| + |u_y| of the

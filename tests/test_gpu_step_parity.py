@@ -1,0 +1,165 @@
+"""Parity of whole time steps (through the C ABI) with the FP64 oracle:
+the fused bracket / viscous / stage-combination kernel at every order and
+both bracket tile heights, the metric workload's first SSP-RK3 step at
+full size, and time stepping with a single Jacobian form (Sec. 2 eq. J,
+Sec. 6.2).
+
+Bars: omega after the step within 1e-12 x max |oracle omega| element-wise
+(small grids, CG at rtol 1e-13 on both sides: on these grids one step
+moves by less than 3e-15 of max |omega| between a 1e-13 solve and an exact
+one, so the bar tests the kernels, not the tolerance); the full-size step
+within 1e-12 in the relative W-norm, both sides solving with the exact
+fast-diagonalisation preconditioner.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1311_7477_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dg():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1311_7477_amd import dg as _dg
+    _dg.lib()
+    return _dg
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _wnorm_rel(g, a, b):
+    e = a - b
+    return math.sqrt(O.inner(g, e, e) / O.inner(g, b, b))
+
+
+# (nx, ny): ragged in both directions, one grid wider than a 64-cell lane
+# group and shorter than a bracket tile, the other taller than two tiles
+STEP_GRIDS = [(13, 29), (70, 9)]
+_ORACLE_STEPS = {}
+
+
+def _oracle_step(n, nx, ny, dt, D, form):
+    key = (n, nx, ny, dt, D, form)
+    if key not in _ORACLE_STEPS:
+        g = O.Grid2D(n, nx, ny)
+        w0 = I.random_modes(n, nx, ny, seed=n + nx) + 1e-2 * I.white_noise(n, nx, ny, seed=n)
+        w1, its = O.rk3_step(g, w0, 0.0, dt, D, O.PsiHistory(), rtol=1e-13,
+                             max_iter=20000, form=form)
+        _ORACLE_STEPS[key] = (g, w0, w1, its)
+    return _ORACLE_STEPS[key]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("nx,ny", STEP_GRIDS)
+@pytest.mark.parametrize("rw", [8, 16])
+def test_rk3_step_parity_every_order(dg, n, nx, ny, rw):
+    # one SSP-RK3 step, D = 1e-2, dt = 5e-2: the three stages run the fused
+    # kernel with (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), and dt |R| is a
+    # few per cent of |omega|, so R itself is checked to ~1e-10 relative
+    dt, D = 5e-2, 1e-2
+    print(f"rk3 step n={n} nx={nx} ny={ny} rw={rw}", flush=True)
+    g, w0, wref, its = _oracle_step(n, nx, ny, dt, D, "arakawa")
+    grid = dg.Grid(n, nx, ny)
+    grid.set_tiles(8, rw)
+    ws = dg.Workspace(grid)
+    st = dg.State(grid)
+    w = _dev(w0)
+    res = dg.rk_step(grid, w, st, ws, dt, D, dg.cg_opts(rtol=1e-13, max_iter=20000))
+    assert res.converged, res
+    got = w.cpu().numpy()
+    assert np.max(np.abs(got - wref)) <= 1e-12 * np.max(np.abs(wref)), \
+        np.max(np.abs(got - wref)) / np.max(np.abs(wref))
+    assert np.max(np.abs(wref - w0)) > 1e-3 * np.max(np.abs(w0))   # the step did something
+
+
+@pytest.mark.parametrize("form_name,form", [("pp", 1), ("px", 2), ("xp", 3)])
+def test_rk3_step_single_form(dg, form_name, form):
+    # dg_step_opts.form: the stepper with one Jacobian form (Sec. 6.2 runs
+    # J++ against J)
+    n, nx, ny, dt, D = 3, 13, 29, 5e-2, 1e-2
+    print(f"rk3 single form {form_name}", flush=True)
+    g, w0, wref, _ = _oracle_step(n, nx, ny, dt, D, form_name)
+    grid = dg.Grid(n, nx, ny)
+    ws = dg.Workspace(grid)
+    st = dg.State(grid)
+    w = _dev(w0)
+    res = dg.rk_step(grid, w, st, ws, dt, D, dg.cg_opts(rtol=1e-13, max_iter=20000),
+                     form=form)
+    assert res.converged
+    got = w.cpu().numpy()
+    assert np.max(np.abs(got - wref)) <= 1e-12 * np.max(np.abs(wref))
+    # and it is not the average form's step
+    _, _, w_avg, _ = _oracle_step(n, nx, ny, dt, D, "arakawa")
+    assert np.max(np.abs(got - w_avg)) > 1e-9 * np.max(np.abs(wref))
+
+
+def test_ab_step_single_form(dg):
+    # Adams-Bashforth K = 2 with J++: two steps (one RK3 start-up step, then
+    # the multistep formula)
+    n, N, dt, D, K = 2, 16, 2e-2, 1e-3, 2
+    g = O.Grid2D(n, N, N)
+    w0 = I.random_modes(n, N, N, seed=5)
+    wr, hist, rh, t = w0.copy(), O.PsiHistory(), [], 0.0
+    grid = dg.Grid(n, N, N)
+    ws = dg.Workspace(grid)
+    ab = dg.AbState(grid, K)
+    w = _dev(w0)
+    for _ in range(3):
+        res = dg.ab_step(grid, w, ab, ws, dt, D, dg.cg_opts(rtol=1e-13), form=1)
+        wr, _ = O.ab_step(g, wr, t, dt, D, K, rh, hist, rtol=1e-13, form="pp")
+        t += dt
+        assert res.converged
+    got = w.cpu().numpy()
+    assert np.max(np.abs(got - wr)) <= 1e-12 * np.max(np.abs(wr))
+
+
+def test_bad_form_rejected(dg):
+    grid = dg.Grid(2, 8, 8)
+    ws = dg.Workspace(grid)
+    st = dg.State(grid)
+    w = _dev(I.white_noise(2, 8, 8, seed=1))
+    before = w.clone()
+    with pytest.raises(dg.DgError) as ei:
+        dg.rk_step(grid, w, st, ws, 1e-3, 0.0, form=7)
+    assert ei.value.code == dg.DG_E_INVAL
+    assert torch.equal(w, before) and st.t == 0.0
+
+
+def test_metric_workload_first_step_full_size(dg):
+    # the decaying-turbulence workload at n = 4, 512^2 (seed 1, k0 = 10,
+    # CFL 0.1, D = 1e-4): its first SSP-RK3 step (three right-hand sides)
+    # against the oracle's, both solving every stage with the exact
+    # fast-diagonalisation preconditioner at rtol 1e-12
+    n, N, D = 4, 512, 1e-4
+    print("metric workload first step n=4 N=512 (oracle eigenbases ...)", flush=True)
+    w0, umax = I.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
+    dt = I.cfl_dt(n, N, umax)
+    g = O.Grid2D(n, N, N)
+    fd = O.FastDiagonalisation(g)
+    print("oracle step ...", flush=True)
+    wref, its = O.rk3_step_pcg(g, w0, 0.0, dt, D, O.PsiHistory(), rtol=1e-12,
+                               max_iter=20, precond=fd.apply)
+    print(f"oracle iterations {its}; GPU step ...", flush=True)
+    grid = dg.Grid(n, N, N)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    st = dg.State(grid)
+    w = _dev(w0)
+    res = dg.rk_step(grid, w, st, ws, dt, D,
+                     dg.cg_opts(rtol=1e-12, precond=dg.DG_PRECOND_FD))
+    assert res.converged
+    assert all(abs(a - b) <= 1 for a, b in zip(res.cg_iters, its)), (res.cg_iters, its)
+    got = w.cpu().numpy()
+    rel = _wnorm_rel(g, got, wref)
+    assert rel <= 1e-12, rel
+    # the step is not the identity at this bar: |omega1 - omega0| >> 1e-12
+    assert _wnorm_rel(g, w0, wref) > 1e-6

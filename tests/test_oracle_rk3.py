@@ -82,3 +82,66 @@ def test_decay_spatial_order_d0(n):
         errs.append(math.sqrt(O.inner(g, w - w0, w - w0)))
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert abs(orders[-1] - n) < 0.35, orders
+
+
+def test_psi_history_extrapolation_is_exact_for_linear_in_time_fields():
+    # Sec. 6: the CG guess extrapolates the last two solutions linearly in
+    # time, so a field psi(t) = A + t B must be reproduced exactly at any
+    # later time (to rounding), whatever the spacing of the two solves.
+    g = O.Grid2D(3, 6, 5)
+    rng = np.random.default_rng(11)
+    A, B = rng.standard_normal((2,) + g.shape)
+    h = O.PsiHistory()
+    assert h.guess(0.3) is None                   # no solve yet: zero guess
+    h.push(0.1, A + 0.1 * B)
+    np.testing.assert_array_equal(h.guess(0.7), A + 0.1 * B)   # one solve: itself
+    h.push(0.25, A + 0.25 * B)
+    for t in (0.25, 0.3, 0.125, 0.9):
+        np.testing.assert_allclose(h.guess(t), A + t * B, rtol=0, atol=1e-13)
+    # the oldest entry drops out: the guess now follows the newest pair
+    h.push(0.5, A + 0.5 * B + 1.0)
+    got = h.guess(0.75)
+    want = (A + 0.5 * B + 1.0) + 1.0 * ((A + 0.5 * B + 1.0) - (A + 0.25 * B))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+    # two solves at the same time: the newest one alone (no division by 0)
+    h.push(0.5, A)
+    np.testing.assert_array_equal(h.guess(0.6), A)
+
+
+@pytest.mark.parametrize("form,dE_zero,dOm_zero", [
+    ("arakawa", True, True), ("pp", False, False), ("px", False, True),
+    ("xp", True, False)])
+def test_single_form_rhs_conservation_pattern(form, dE_zero, dOm_zero):
+    # Table 2 pattern carried into the right-hand side at D = 0: with
+    # R = -J(psi, omega), dE/dt = <psi, R> and dOmega/dt = <omega, R>.
+    # The average J conserves both; J++ neither (Table 2: int fJ++ and
+    # int gJ++ nonzero); J+x conserves Omega only (int gJ+x = 0); Jx+
+    # conserves E only (int fJx+ = 0).  Also checks that rk3_step forwards
+    # the form: one step with J++ changes Omega at O(dt), the average at
+    # O(dt^3).
+    n, N = 3, 10
+    g = O.Grid2D(n, N, N)
+    # k0 = 4 on 10 cells: under-resolved enough that the single forms'
+    # truncation-level imbalance is far above rounding
+    w = I.random_spectrum(n, N, k0=4.0, seed=4)
+    psi = O.cg_poisson(g, w, rtol=1e-14).x
+    R = O.rhs(g, w, psi, 0.0, form)
+    scale = math.sqrt(O.inner(g, R, R))
+    dE = O.inner(g, psi, R) / (scale * math.sqrt(O.inner(g, psi, psi)))
+    dOm = O.inner(g, w, R) / (scale * math.sqrt(O.inner(g, w, w)))
+    assert (abs(dE) < 1e-13) == dE_zero, dE
+    assert (abs(dOm) < 1e-13) == dOm_zero, dOm
+    if not (dE_zero and dOm_zero):
+        assert max(abs(dE), abs(dOm)) > 1e-4
+    Om0 = 0.5 * O.inner(g, w, w)
+    rel = []
+    for dt in (1e-3, 2.5e-4):
+        w1, _ = O.rk3_step(g, w, 0.0, dt, 0.0, O.PsiHistory(), rtol=1e-14, form=form)
+        rel.append(abs(0.5 * O.inner(g, w1, w1) - Om0) / Om0)
+    ratio = rel[0] / rel[1]
+    if dOm_zero:
+        # only the RK3 error: the one-step change falls like dt^4
+        assert ratio > 100, rel
+    else:
+        # the bracket itself changes Omega: like dt
+        assert 3.0 < ratio < 5.0 and rel[0] > 1e-6, rel
