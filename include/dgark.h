@@ -343,6 +343,21 @@ int  dg_invariants(const dg_grid* grid, const double* omega, const double* psi,
 int  dg_invariants_dev(const dg_grid* grid, const double* omega,
                        const double* psi, double* out_dev3, dg_workspace* ws,
                        void* stream);
+/* dg_invariants_dev without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops).  The
+ * reduction scratch (at most 1024 blocks x 4 doubles of partial sums plus the
+ * ticket counters, 33 KB) is a static device array that each device holds
+ * from its first call until the process ends; any grid size fits it (the
+ * reduction launches at most 1024 blocks).  This call never allocates.  The
+ * first call on a device looks the array up and queues a counter clear on
+ * `stream`: make it outside stream capture.  Every call on one device shares
+ * that device's array, so calls that overlap in time on one device (other
+ * streams, other threads) race; calls queued on one stream do not.
+ * out_dev3: 3 doubles of device memory, written asynchronously with the
+ * same values, bit for bit, as dg_invariants_dev.  Errors: DG_E_INVAL for a
+ * NULL argument or a device index >= 64, DG_E_HIP. */
+int  dg_invariants_noalloc(const dg_grid* grid, const double* omega,
+                           const double* psi, double* out_dev3, void* stream);
 
 /* ------------------------------------------------------------- batches --- */
 /* Many independent instances (any n, any grid) advanced together: each

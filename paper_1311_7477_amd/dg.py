@@ -107,6 +107,7 @@ def lib():
                                       ctypes.POINTER(StepStats), _vp, _vp]),
         "dg_invariants": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp, _vp]),
         "dg_invariants_dev": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "dg_invariants_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
         "dg_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
         "dg_profile_read": (ctypes.c_int, [_vp, _dp]),
         "dg_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -418,6 +419,25 @@ def invariants(grid: Grid, omega, psi, ws: Workspace):
     _check(lib().dg_invariants(grid.handle, _field(omega, grid, "omega"),
                                _field(psi, grid, "psi"), out, ws.handle, _stream()))
     return tuple(out)
+
+
+def invariants_dev(grid: Grid, omega, psi, ws: Workspace, out=None):
+    """(V, E, Omega) into a device tensor of 3 doubles (asynchronous)."""
+    import torch
+    out = torch.empty(3, dtype=torch.float64, device="cuda") if out is None else out
+    _check(lib().dg_invariants_dev(grid.handle, _field(omega, grid, "omega"),
+                                   _field(psi, grid, "psi"), _vp(out.data_ptr()),
+                                   ws.handle, _stream()))
+    return out
+
+
+def invariants_noalloc(grid: Grid, omega, psi, out):
+    """(V, E, Omega) into the caller's device tensor `out` (3 doubles) with
+    no workspace and no allocation (dg_invariants_noalloc)."""
+    _check(lib().dg_invariants_noalloc(grid.handle, _field(omega, grid, "omega"),
+                                       _field(psi, grid, "psi"), _vp(out.data_ptr()),
+                                       _stream()))
+    return out
 
 
 class Batch:
