@@ -79,13 +79,31 @@ def cpu_baseline(n, N, omega0, psi0, D, dt, iters_per_rhs):
     return {
         "value": N * N / t_per_rhs,
         "unit": "cell-updates/s",
+        # scipy's sparse products and numpy's elementwise operations run on
+        # one thread (the oracle makes no BLAS calls)
         "cores": 1,
+        "host_cpu_count": os.cpu_count(),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": (f"numpy/scipy FP64 oracle at n={n}, {N}x{N}: 1 bracket+viscous "
                    f"({t_rhs:.2f} s), 1 CG setup ({t_setup:.2f} s), {k} CG iterations "
                    f"({t_iter * 1e3:.0f} ms each); per RHS = rhs + setup + "
-                   f"{iters_per_rhs:.0f} x iteration (GPU mean iterations/RHS)"),
+                   f"{iters_per_rhs:.0f} x iteration, with the GPU's mean iterations per "
+                   f"RHS (the oracle's own count agrees within 2 wherever both solve, "
+                   f"but a full oracle solve at this size would take about "
+                   f"{iters_per_rhs * t_iter / 60:.0f} minutes)"),
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def form_batch(args):
@@ -423,60 +441,157 @@ def form_serve(args):
     N log-uniform over [N_min, N_max], random spectra), continuous batching
     under an HBM budget; latency percentiles, aggregate throughput and an
     alone-vs-mix check.  --serve-solver batch: the persistent batched launches
-    with the plain FP64 CG; pcg: a stream per request with the CG
-    preconditioned by fast diagonalisation, its preconditioner in FP32 under
-    the FP64 iteration.  --rate 0 sets the arrival rate to 0.7 x the
-    measured capacity (cell-updates/s of the first four requests run alone,
-    divided by the mean request size)."""
+    with the plain FP64 CG; pcg: a stream and a worker per request with the
+    CG preconditioned by fast diagonalisation, its preconditioner in FP32
+    under the FP64 iteration.  With --rate 0 the stream runs once per load
+    factor in --loads, the arrival rate set to that factor x the measured
+    capacity (cell-updates/s of the first four requests run alone, divided
+    by the mean request size); --replay requests of each run are then run
+    alone again and compared bit for bit."""
     import numpy as np
     from paper_1311_7477_amd import dg, serve
-    reqs = serve.draw_requests(args.requests, seed=4, rate=1.0,
-                               N_range=(args.N_min, args.N_max), steps=args.req_steps)
-    if args.serve_solver == "pcg":
-        srv = serve.StreamServer(capacity=64)
-    else:
-        srv = serve.Server(capacity=64, opts=dg.cg_opts(rtol=1e-10))
+
+    def stream():
+        return serve.draw_requests(args.requests, seed=4, rate=1.0,
+                                   N_range=(args.N_min, args.N_max), steps=args.req_steps)
+
+    def server():
+        if args.serve_solver == "pcg":
+            return serve.StreamServer(capacity=64)
+        return serve.Server(capacity=64, opts=dg.cg_opts(rtol=1e-10))
+
+    reqs = stream()
+    opts = server().opts
     # capacity estimate: the first four requests run alone, one after another
     t_alone = 0.0
-    serve.run_alone(reqs[0], srv.opts, None)                 # warm-up
+    serve.run_alone(reqs[0], opts, None)                     # warm-up
     for r in reqs[:4]:
         t0 = time.perf_counter()
-        serve.run_alone(r, srv.opts, None)
+        serve.run_alone(r, opts, None)
         t_alone += time.perf_counter() - t0
         print(f"[serve] alone: request {r.rid} n={r.n} N={r.N} done", file=sys.stderr,
               flush=True)
     capacity = sum(r.cell_updates for r in reqs[:4]) / t_alone
     mean_size = float(np.mean([r.cell_updates for r in reqs]))
-    rate = args.rate if args.rate > 0 else 0.7 * capacity / mean_size
-    for r in reqs:
-        r.arrival /= rate
-    t0 = time.perf_counter()
-    done = srv.run(reqs, log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
-    makespan = time.perf_counter() - t0
-    s = serve.summarize(done, makespan)
-    # alone vs in the mix: the first four finished requests again, alone,
-    # with the tile shapes the server used
-    same = [bool(np.array_equal(r.result, serve.run_alone(r, srv.opts,
-                                                          srv.tiles.get((r.n, r.N)))))
-            for r in done[:4]]
-    s.update({
+    loads = [float(x) for x in args.loads.split(",")] if args.rate <= 0 else [None]
+    runs = []
+    for load in loads:
+        reqs = stream()
+        rate = args.rate if load is None else load * capacity / mean_size
+        for r in reqs:
+            r.arrival /= rate
+        srv = server()
+        t0 = time.perf_counter()
+        done = srv.run(reqs, log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
+        makespan = time.perf_counter() - t0
+        s = serve.summarize(done, makespan)
+        print(f"[serve] load {load}: {s}", file=sys.stderr, flush=True)
+        # alone vs in the mix: the first `replay` finished requests again,
+        # alone, with the tile shapes the server used
+        same = [bool(np.array_equal(r.result, serve.run_alone(r, srv.opts,
+                                                              srv.tiles.get((r.n, r.N)))))
+                for r in done[:args.replay]]
+        s.update({"load": load, "arrival_rate_per_s": rate, "makespan_s": makespan,
+                  "max_concurrent": srv.max_active, "failed": len(srv.failed),
+                  "rejected": len(srv.rejected), "peak_budgeted_bytes": srv.peak_used,
+                  "budget_bytes": srv.budget, "alone_equals_mix": same})
+        runs.append(s)
+    out = {
         "metric": "served DG cell-updates/s (aggregate) with p50/p99 request latency",
-        "value": s["aggregate_cell_updates_per_s"], "unit": "cell-updates/s",
-        "max_concurrent": srv.max_active, "ticks": srv.ticks,
-        "peak_budgeted_bytes": srv.peak_used, "budget_bytes": srv.budget,
-        "alone_equals_mix_first4": same, "arrival_rate_per_s": rate,
-        "capacity_cell_updates_per_s_alone": capacity,
+        "value": runs[0]["aggregate_cell_updates_per_s"], "unit": "cell-updates/s",
+        "runs": runs, "capacity_cell_updates_per_s_alone": capacity,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.requests} requests, Poisson arrivals at {rate:.3g}/s, "
+        "config": {"workload": f"{args.requests} requests, Poisson arrivals (seed 4), "
                                f"n~U{{2..5}}, N log-uniform [{args.N_min},{args.N_max}], "
                                f"{args.req_steps} RK3 steps each, k0~U[4,16], D=1e-4, "
-                               f"rtol 1e-10, HBM budget 80% of free memory, seed 4",
-                   "solver": ("stream per request, CG preconditioned by fast "
+                               f"rtol 1e-10, HBM budget 80% of free memory",
+                   "solver": ("stream and worker per request, CG preconditioned by fast "
                               "diagonalisation (FP32 preconditioner, FP64 iteration)"
                               if args.serve_solver == "pcg" else
                               "batched persistent launches, plain FP64 CG")},
-    })
-    print(json.dumps(s), flush=True)
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _dipole_wake(n, N, w):
+    """Fraction of the W-norm of omega lying farther than 1.5 R = 0.15 from
+    the dipole centre, taken as the periodic midpoint of the nodes of
+    largest and smallest omega (box [0, 1]^2): the vorticity the scheme
+    sheds outside the dipole."""
+    import numpy as np
+    from paper_1311_7477_amd import inputs
+    X, Y = inputs.node_coords(n, N, N, 0.0, 1.0, 0.0, 1.0)
+    a, b = np.unravel_index(np.argmax(w), w.shape), np.unravel_index(np.argmin(w), w.shape)
+
+    def mid(u, v):
+        d = (v - u + 0.5) % 1.0 - 0.5
+        return (u + 0.5 * d) % 1.0
+
+    cx, cy = mid(X[a], X[b]), mid(Y[a], Y[b])
+    dx = (X - cx + 0.5) % 1.0 - 0.5
+    dy = (Y - cy + 0.5) % 1.0 - 0.5
+    xi, wq = np.polynomial.legendre.leggauss(n)
+    W = np.broadcast_to((wq[:, None] * wq[None, :])[None, None], w.shape)
+    far = np.hypot(dx, dy) > 0.15
+    return float(np.sqrt(np.sum(W * w * w * far) / np.sum(W * w * w))), (float(cx), float(cy))
+
+
+def form_dipole(args):
+    """Sec. 6.2, Figs. 1-2: the Lamb dipole (box [0,1]^2, U = 1, R = 0.1,
+    D = 0) advanced to t = 0.5 with the paper's three-step Adams-Bashforth
+    method, once with the conservative bracket J = (J++ + J+x + Jx+)/3 and
+    once with J++ alone, at P = 1, N = 100 (Fig. 1) and P = 4, N = 50
+    (Fig. 2), each at two time steps dt and dt/2.  Reports eps_V, eps_E,
+    eps_Omega at t = 0.5 and their ratio between the two time steps (about
+    8 where only the third-order time stepping changes E and Omega, about 1
+    where the bracket itself does), and the share of the vorticity norm
+    shed outside the dipole."""
+    import torch
+    from paper_1311_7477_amd import dg, inputs
+    T = 0.5
+    cases = [(1, 100, 5e-4), (4, 50, 2e-4)]
+    rows = []
+    for (n, N, dt0) in cases:
+        grid = dg.Grid(n, N, N, 0.0, 1.0, 0.0, 1.0)
+        ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        opts = dg.cg_opts(rtol=1e-13, precond=dg.DG_PRECOND_FD)
+        w0 = torch.from_numpy(inputs.lamb_dipole(n, N)).cuda()
+        p0 = torch.zeros_like(w0)
+        dg.cg_solve_poisson(grid, w0, p0, ws, opts)
+        V0, E0, Om0 = dg.invariants(grid, w0, p0, ws)
+        for form_name, form in (("J", dg.DG_FORM_ARAKAWA), ("J++", dg.DG_FORM_PP)):
+            res = []
+            for dt in (dt0, dt0 / 2):
+                steps = int(round(T / dt))
+                ab = dg.AbState(grid, 3)
+                w = w0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ok = True
+                for _ in range(steps):
+                    ok = dg.ab_step(grid, w, ab, ws, dt, 0.0, opts, form=form).converged and ok
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                psi = ab.psi()
+                dg.cg_solve_poisson(grid, w, psi, ws, opts)
+                V, E, Om = dg.invariants(grid, w, psi, ws)
+                wake, centre = _dipole_wake(n, N, w.cpu().numpy())
+                res.append({"dt": dt, "steps": steps, "eps_V": abs(V),
+                            "eps_E": abs((E - E0) / E0), "eps_Omega": abs((Om - Om0) / Om0),
+                            "wake_fraction": wake, "centre": centre,
+                            "all_converged": ok, "ms_per_step": el / steps * 1e3})
+                print(f"[dipole] P={n} N={N} {form_name} {res[-1]}", file=sys.stderr,
+                      flush=True)
+            rows.append({"P": n, "N": N, "bracket": form_name, "runs": res,
+                         "ratio_eps_E_dt_over_dt2": res[0]["eps_E"] / res[1]["eps_E"],
+                         "ratio_eps_Omega_dt_over_dt2":
+                             res[0]["eps_Omega"] / res[1]["eps_Omega"]})
+    print(json.dumps({"metric": "Lamb dipole at t = 0.5: conservation of the average "
+                                "bracket J against J++ (Sec. 6.2, Figs. 1-2)",
+                      "rows": rows, "data": "synthetic (analytic Lamb dipole)", "dtype": "f64",
+                      "config": {"workload": "box [0,1]^2, U=1, R=0.1, D=0, t in [0, 0.5], "
+                                             "three-step Adams-Bashforth, PCG rtol 1e-13; "
+                                             "P=1 N=100 and P=4 N=50"}}), flush=True)
 
 
 def form_paper(args):
@@ -654,6 +769,28 @@ def turbulence_runs(args):
         "runs": runs}
 
 
+def check_solve(grid, omega, guess, ws, opts):
+    """One more solve of the kind the timed steps make (the final omega,
+    from the newest psi as guess), outside the timed region, with its true
+    relative residual ||b + Lap_h psi||_W / ||b||_W recomputed on the device
+    by the library's Laplacian: the recursive residual the CG stops on
+    can fall below what FP64 can confirm."""
+    import torch
+    from paper_1311_7477_amd import dg
+    n = grid.n
+    psi = guess.clone()
+    r = dg.cg_solve_poisson(grid, omega, psi, ws, opts)
+    xw = grid.tables()[n:2 * n]
+    hx, hy = 2 * math.pi / grid.nx, 2 * math.pi / grid.ny
+    w1 = torch.tensor(xw, dtype=torch.float64, device="cuda")
+    W = ((w1 * hy / 2)[:, None] * (w1 * hx / 2)[None, :]).expand(grid.shape)
+    b = omega - (W * omega).sum() / W.sum()
+    res = b + dg.laplace_apply(grid, psi)
+    true_rel = math.sqrt(float((W * res * res).sum()) / float((W * b * b).sum()))
+    return {"iters": r.iters, "converged": r.converged, "rtol": opts.rtol,
+            "recursive_rel_residual": r.rel_residual, "true_rel_residual": true_rel}
+
+
 def precond_leg(args, omega0, dt, tiles):
     """The same workload (fresh from omega0) with CG preconditioned by the
     exact fast-diagonalisation inverse of -Lap_h: W warm-up steps, then K
@@ -670,16 +807,19 @@ def precond_leg(args, omega0, dt, tiles):
     for _ in range(args.warmup):
         dg.rk_step(grid, w, st, ws, dt, args.D, opts)
     stage_ms, iters = [], []
+    all_conv = True
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         r = dg.rk_step(grid, w, st, ws, dt, args.D, opts, record_times=True)
         stage_ms.extend(r.stage_ms)
         iters.extend(r.cg_iters)
+        all_conv = all_conv and r.converged
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     print(f"[bench] preconditioned: iters {iters} ms {[round(x, 3) for x in stage_ms]}",
           file=sys.stderr, flush=True)
+    check = check_solve(grid, w, st.psi(), ws, opts)
     srt = sorted(stage_ms)
     return {
         "value": N * N * 3 * args.steps / T, "unit": "cell-updates/s",
@@ -687,7 +827,9 @@ def precond_leg(args, omega0, dt, tiles):
         "latency_ms_per_rhs": {"p50": srt[len(srt) // 2], "p99": srt[-1],
                                "mean": statistics.mean(stage_ms)},
         "cg_iters_per_rhs": {"mean": statistics.mean(iters), "max": max(iters)},
-        "workspace_bytes": grid.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD),
+        "all_converged": all_conv,
+        "check_solve": check,
+        "workspace_bytes": ws.held_bytes(),
         "precond_flops_per_apply": 4 * n * n * N * N * (N + N),
         "method": "PCG, M = exact (-Lap_h)^+ by fast diagonalisation: separable "
                   "Bloch eigenbases in factored form (FP64 cell Fourier transforms "
@@ -714,7 +856,7 @@ def main():
                          "HBM counters calibrate the profiler's FETCH/WRITE_SIZE")
     ap.add_argument("--form", default="rhs",
                     choices=["rhs", "batch", "mixed", "serve", "paper", "tune", "lamb",
-                             "table3", "turbulence", "dirichlet"],
+                             "table3", "turbulence", "dirichlet", "dipole"],
                     help="rhs: the headline metric (default); the others measure "
                          "the batched, mixed-precision and served forms and the "
                          "paper's bracket-timing shape")
@@ -738,6 +880,11 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0,
                     help="--form serve: arrivals per second (0: 0.7 x measured capacity)")
     ap.add_argument("--req-steps", dest="req_steps", type=int, default=10)
+    ap.add_argument("--loads", default="0.7,0.9",
+                    help="--form serve with --rate 0: arrival rates as fractions of "
+                         "the measured capacity, one run each")
+    ap.add_argument("--replay", type=int, default=8,
+                    help="--form serve: finished requests rerun alone and compared")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the single-instance RHS is not "
@@ -754,7 +901,7 @@ def main():
         {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
          "paper": form_paper, "tune": form_tune, "lamb": form_lamb,
          "table3": form_table3, "turbulence": form_turbulence,
-         "dirichlet": form_dirichlet}[args.form](args)
+         "dirichlet": form_dirichlet, "dipole": form_dipole}[args.form](args)
         return
     n, N = args.n, args.N
     if args.copy_calibration:
@@ -785,16 +932,19 @@ def main():
     stage_ms, iters = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    all_conv = True
     for k in range(args.steps):
         r = dg.rk_step(grid, w, st, ws, dt, args.D, opts, record_times=True)
         stage_ms.extend(r.stage_ms)
         iters.extend(r.cg_iters)
+        all_conv = all_conv and r.converged
         print(f"[bench] step {k}: iters {r.cg_iters} ms "
               f"{[round(x, 2) for x in r.stage_ms]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     ws.profile(False)
     ms_dir, n_dir, ms_res, n_res = ws.read_profile()
+    check = check_solve(grid, w, st.psi(), ws, opts)
 
     # achievable-bandwidth reference outside the timed region: a plain
     # 256 MiB device-to-device copy (torch copy_), timed with events
@@ -848,6 +998,8 @@ def main():
         "latency_ms_per_rhs": {"p50": pct(0.50), "p99": pct(0.99),
                                "mean": statistics.mean(stage_ms)},
         "cg_iters_per_rhs": {"mean": statistics.mean(iters), "max": max(iters)},
+        "all_converged": all_conv,
+        "check_solve": check,
         "roofline": {
             "kernel": "k_cg_dir (CG direction update: x += a p, p = r + b p, <p, A p>)",
             "bound": "hbm",
@@ -862,6 +1014,9 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "copy_GBps": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
+            "cache_note": ("the CG vectors (3 fields, %.0f MB) fit the 256 MB Infinity "
+                           "Cache at this size, so this is effective bandwidth; the "
+                           "HBM-bound figure is profiled at n=5, 1024^2" % (3 * F / 1e6)),
         },
     }
     if not args.no_precond:

@@ -185,13 +185,19 @@ int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
  * node-plane fields and per axis the factored eigenbasis in FP64 and FP32
  * (the N x N cell Fourier basis, 2 (N/2 + 1) mixing blocks of 2n x 2n and
  * n N eigenvalues; one set when the axes agree; rocBLAS and, on the FFT
- * path, rocFFT keep their own work buffers on top).  On a grid
+ * path, rocFFT keep their own work buffers on top: dg_workspace_held_bytes
+ * counts them once the workspace exists).  On a grid
  * with a Dirichlet axis the preconditioner holds instead two dense work
  * images of n^2 Nx Ny doubles and per axis the dense (n N)^2 eigenbasis and
  * n N eigenvalues in FP64 and FP32.  This is the figure that admission
  * control budgets.
  * mode = DG_PREC_FP64 or DG_PREC_MIXED, optionally | DG_WS_FD. */
 int  dg_workspace_bytes(const dg_grid* grid, int mode, size_t* bytes);
+/* Device bytes a created workspace holds: dg_workspace_bytes plus the work
+ * buffers the preconditioner's libraries hold (rocFFT's, known only once its
+ * plans exist, and what rocBLAS reports for its handle at creation).  The
+ * figure to charge once a workspace exists.  Host-only. */
+int  dg_workspace_held_bytes(const dg_workspace* ws, size_t* bytes);
 /* Allocate a workspace on the current device (hipMalloc + pinned host
  * scalars).  With DG_WS_FD on a grid with a Dirichlet axis this runs the
  * dense eigensolver (rocSOLVER) on the device, synchronously.  Errors:
@@ -393,6 +399,9 @@ int  dg_batch_use_graphs(dg_batch* b, int on);
  * Synchronises the stream.  DG_E_NOCONV if some solve hit max_iter. */
 int  dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
                       void* stream);
+/* 1 if every solve of slot's last dg_batch_rk_step converged, 0 if one hit
+ * max_iter (the step was still completed), DG_E_INVAL for an empty slot. */
+int  dg_batch_slot_converged(const dg_batch* b, int slot);
 /* Copy slot's most recent psi to out (device); asynchronous. */
 int  dg_batch_copy_psi(const dg_batch* b, int slot, double* out, void* stream);
 /* Simulation time of a slot (0 for an empty slot). */

@@ -598,8 +598,14 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
         const int rc = fd_create(g, &ws->fd);
         if (rc != DG_OK) { dg_workspace_destroy(ws); return rc; }
     }
-    ws->bytes = ws_bytes(g, mode);
+    ws->bytes = ws_bytes(g, mode) + fd_extra_bytes(ws->fd);
     *out = ws;
+    return DG_OK;
+}
+
+int dg_workspace_held_bytes(const dg_workspace* ws, size_t* bytes) {
+    if (!ws || !bytes) return fail(DG_E_INVAL, "NULL argument");
+    *bytes = ws->bytes;
     return DG_OK;
 }
 

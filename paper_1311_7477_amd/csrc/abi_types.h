@@ -77,6 +77,7 @@ size_t fd_bytes(const dg_grid* g);
 int fd_supported(const dg_grid* g);     // DG_OK, or DG_E_UNSUPPORTED with the reason
 bool fd_uses_fft(int nx, int ny);       // periodic grids: FFT (else GEMM) cell transforms
 int fd_create(const dg_grid* g, FdDevice** out);
+size_t fd_extra_bytes(const FdDevice* fd);   // library work buffers beyond fd_bytes
 void fd_destroy(FdDevice* fd);
 int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s);
 // Layout of the work image fd_apply_image expects and returns.

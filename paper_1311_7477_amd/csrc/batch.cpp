@@ -50,6 +50,7 @@ struct Slot {
     double dt = 0.0, D = 0.0;
     dg_workspace* ws = nullptr;
     dg_state* st = nullptr;
+    bool converged = true;      // every solve of the last step converged
 };
 
 struct DevList {
@@ -375,6 +376,7 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
     const double ra_a[3] = {0.0, 0.75, 1.0 / 3.0};
     const double ra_b[3] = {1.0, 0.25, 2.0 / 3.0};
     bool all_conv = true;
+    for (Slot& sl : b->slots) sl.converged = true;
     for (int k = 0; k < 3; ++k) {
         std::vector<int> xi(b->capacity, -1);
         std::vector<double> ts(b->capacity, 0.0);
@@ -432,7 +434,7 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
             Slot& sl = b->slots[i];
             if (!sl.used) continue;
             state_push(sl.st, xi[i], ts[i]);
-            if (!fin[i].converged) all_conv = false;
+            if (!fin[i].converged) { all_conv = false; sl.converged = false; }
             if (iters_out) iters_out[3 * i + k] = fin[i].iter;
         }
     }
@@ -440,6 +442,12 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
         if (sl.used) sl.st->t += sl.dt;
     if (!all_conv) return fail(DG_E_NOCONV, "a batched solve did not converge");
     return DG_OK;
+}
+
+int dg_batch_slot_converged(const dg_batch* b, int slot) {
+    if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].used)
+        return fail(DG_E_INVAL, "no instance in slot %d", slot);
+    return b->slots[slot].converged ? 1 : 0;
 }
 
 int dg_batch_copy_psi(const dg_batch* b, int slot, double* out, void* stream) {

@@ -585,9 +585,21 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         const int rc = make_fft(g, fd);
         if (rc != DG_OK) { fd_destroy(fd); return rc; }
     }
-    fd->bytes = fd_bytes(g);
+    fd->bytes = fd_bytes(g) + fd->fft_work_bytes;
     *out = fd;
     return DG_OK;
+}
+
+// Device bytes the preconditioner holds beyond fd_bytes(): rocFFT's work
+// buffer (known once the plans exist) and what rocBLAS reports for its
+// handle.
+size_t fd_extra_bytes(const FdDevice* fd) {
+    if (!fd) return 0;
+    size_t blas = 0;
+    if (fd->blas &&
+        rocblas_get_device_memory_size((rocblas_handle)fd->blas, &blas) != rocblas_status_success)
+        blas = 0;
+    return fd->fft_work_bytes + blas;
 }
 
 // img0 holds the work image of r on entry and that of z = M r on exit

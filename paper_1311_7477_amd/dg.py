@@ -78,6 +78,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_size_t)]),
         "dg_workspace_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
         "dg_workspace_destroy": (None, [_vp]),
+        "dg_workspace_held_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "dg_poisson_bracket": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
         "dg_bracket_form": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
         "dg_laplace_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -121,6 +122,7 @@ def lib():
         "dg_batch_rk_step": (ctypes.c_int, [_vp, ctypes.POINTER(CgOpts),
                                             ctypes.POINTER(ctypes.c_int), _vp]),
         "dg_batch_copy_psi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+        "dg_batch_slot_converged": (ctypes.c_int, [_vp, ctypes.c_int]),
         "dg_batch_time": (ctypes.c_double, [_vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -234,6 +236,12 @@ class Workspace:
     @property
     def handle(self):
         return self._h
+
+    def held_bytes(self):
+        """Device bytes this workspace holds, library work buffers included."""
+        b = ctypes.c_size_t()
+        _check(lib().dg_workspace_held_bytes(self._h, ctypes.byref(b)))
+        return b.value
 
     def profile(self, on=True):
         _check(lib().dg_profile_enable(self._h, 1 if on else 0))
@@ -480,6 +488,10 @@ class Batch:
 
     def time(self, slot: int) -> float:
         return lib().dg_batch_time(self._h, slot)
+
+    def converged(self, slot: int) -> bool:
+        """Whether every solve of the slot's last step converged."""
+        return _check_count(lib().dg_batch_slot_converged(self._h, slot)) == 1
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

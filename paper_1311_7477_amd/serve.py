@@ -16,19 +16,26 @@ whatever else was in flight.
 
 StreamServer runs the same loop with another engine: every admitted request
 owns a workspace with the fast-diagonalisation preconditioner and a HIP
-stream, and a tick issues one dg_rk_step per active request from a pool of
-host threads, so the requests' kernels overlap on the device; the solve is
-the preconditioned CG with its preconditioner applied in FP32 under the FP64
-iteration (rtol 1e-10 by default).  A request again gets the result of the
-same steps run alone.  All scheduling is host logic here; every computation
-runs in the HIP library.
+stream, and a host worker thread runs all of that request's steps
+(dg_rk_step on its own stream) back to back, so the requests' kernels
+overlap on the device and no request waits for another's step: a small
+request admitted beside a large one finishes on its own clock.  The solve
+is the preconditioned CG with its preconditioner applied in FP32 under the
+FP64 iteration (rtol 1e-10 by default).  A request again gets the result of
+the same steps run alone.
+
+A request whose solve does not converge (DG_E_NOCONV) or whose step fails
+otherwise is retired with `error` set while the others continue; run()
+returns the requests that finished and lists the failed ones in `failed`.
+All scheduling is host logic here; every computation runs in the HIP
+library.
 """
 from __future__ import annotations
 
 import collections
 import math
 import time
-from concurrent.futures import ThreadPoolExecutor
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -60,6 +67,9 @@ class Request:
     ws: object = None         # StreamServer: workspace, state and stream
     state: object = None
     stream: object = None
+    max_iter: int = 0         # StreamServer: per-request CG iteration cap (0: the server's)
+    error: str = None         # set when the request failed (e.g. a solve did not converge)
+    done_at: float = math.nan  # StreamServer: when its last step returned
 
     @property
     def latency(self) -> float:
@@ -120,8 +130,10 @@ class Server:
         self.max_active = 0
         self.peak_used = 0
         self.rejected = []
+        self.failed = []
         self.tune = tune
         self.tiles = {}           # (n, N) -> (cell tile height, bracket tile height)
+        self.shape_bytes = {}     # (n, N) -> device bytes measured at an admission
 
     def _engine(self):
         return dg.Batch(self.capacity)
@@ -130,8 +142,9 @@ class Server:
         return member_bytes(req.n, req.N)
 
     def fits(self, req: Request) -> bool:
+        need = self.shape_bytes.get((req.n, req.N), req.bytes)
         return (len(self.active) < self.capacity and
-                self.used + req.bytes <= self.budget)
+                self.used + need <= self.budget)
 
     def admit(self, req: Request, now: float):
         import torch
@@ -159,17 +172,29 @@ class Server:
         req.finished = now
 
     def tick(self, now_fn):
+        """One batched RK3 step of every member; a member whose solve did
+        not converge is retired with an error, the others go on."""
         its, ok = self.batch.rk_step(self.opts)
         self.ticks += 1
         for slot, req in list(self.active.items()):
             req.cg_iters.extend(its[slot])
             req.done_steps += 1
-            if req.done_steps >= req.steps:
+            if not ok and not self.batch.converged(slot):
+                req.error = (f"request {req.rid}: a solve did not converge in step "
+                             f"{req.done_steps}")
+                self.retire(req, now_fn())
+            elif req.done_steps >= req.steps:
                 self.retire(req, now_fn())
 
+    def advance(self, now_fn, wait_s):
+        """Make progress on the active requests: here one batched tick
+        (wait_s, the time to the next arrival, is not needed)."""
+        self.tick(now_fn)
+
     def run(self, requests, log=None):
-        """Serve an arrival stream in real time; returns the finished
-        requests.  Requests larger than the whole budget are rejected."""
+        """Serve an arrival stream in real time; returns the requests that
+        finished without error (failed ones are in self.failed).  Requests
+        larger than the whole budget are rejected."""
         for r in requests:
             r.bytes = self.request_bytes(r)
         reqs = sorted(requests, key=lambda r: r.arrival)
@@ -178,99 +203,157 @@ class Server:
         queue = collections.deque()
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
+        self._now = now
         while todo or queue or self.active:
             t = now()
             while todo and todo[0].arrival <= t:
                 queue.append(todo.popleft())
             while queue and self.fits(queue[0]):
-                self.admit(queue.popleft(), now())
+                req = queue.popleft()
+                if self.admit(req, now()) is False:
+                    # its measured footprint does not fit after all
+                    if req.bytes > self.budget:
+                        rejected.append(req)
+                        continue
+                    queue.appendleft(req)
+                    break
             if self.active:
-                self.tick(now)
+                self.advance(now, (todo[0].arrival - now()) if todo else None)
                 if log:
                     done = sum(not math.isnan(r.finished) for r in reqs)
-                    log(f"tick {self.ticks}: active {len(self.active)} queued "
+                    log(f"step {self.ticks}: active {len(self.active)} queued "
                         f"{len(queue)} done {done} t={now():.2f}s")
             elif todo:
                 time.sleep(max(0.0, min(todo[0].arrival - now(), 0.05)))
         self.rejected = rejected
-        return [r for r in reqs if not math.isnan(r.finished)]
+        self.failed = [r for r in reqs if r.error is not None]
+        return [r for r in reqs if not math.isnan(r.finished) and r.error is None]
 
 
 class StreamServer(Server):
-    """The request loop of Server with one stream per request: admission
-    creates the request's grid, a DG_WS_FD workspace (the preconditioner's
-    bases and plans), its state and a HIP stream; a tick runs one
-    dg_rk_step of every active request, each issued from a worker thread
-    on that request's stream (the library's calls release the GIL, and each
-    one waits only for its own stream).  Default solve: CG preconditioned by
+    """The request loop of Server with one stream and one host worker per
+    request: admission creates the request's grid, a DG_WS_FD workspace (the
+    preconditioner's bases and plans), its state and a HIP stream, then
+    hands the request to a worker thread that runs all of its steps on that
+    stream (the library's calls release the GIL and each waits only for its
+    own stream).  The main loop never waits for a step: it retires requests
+    as their workers finish and admits queued ones as memory and slots free
+    up.  Admission charges the bytes the workspace really holds (library
+    work buffers included) once it exists; a request that then does not fit
+    goes back to the head of the queue.  Default solve: CG preconditioned by
     fast diagonalisation, the preconditioner in FP32 under the FP64
     iteration, rtol 1e-10."""
 
-    def __init__(self, capacity=64, hbm_budget=None, opts=None, tune=False, workers=16):
+    def __init__(self, capacity=64, hbm_budget=None, opts=None, tune=False, workers=None):
         if opts is None:
             opts = dg.cg_opts(rtol=1e-10, precond=dg.DG_PRECOND_FD,
                               precision=dg.DG_PREC_MIXED)
-        self.workers = workers
+        self.workers = capacity if workers is None else workers
         super().__init__(capacity, hbm_budget, opts, tune)
+        self.futures = {}
 
     def _engine(self):
         return ThreadPoolExecutor(self.workers)
 
     def request_bytes(self, req: Request) -> int:
-        """Workspace (with the preconditioner), state (three fields) and
-        omega; rocBLAS and rocFFT keep their work buffers on top."""
+        """Estimate before admission: workspace (with the preconditioner),
+        state (three fields) and omega; admission replaces it by the bytes
+        the workspace reports once created."""
         g = dg.Grid(req.n, req.N, req.N)
         return g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD) + 4 * g.elems * 8
 
     def admit(self, req: Request, now: float):
         import torch
-        w0 = prepare(req)
         req.grid = dg.Grid(req.n, req.N, req.N)
         key = (req.n, req.N)
         req.stream = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(req.stream):
+                req.ws = dg.Workspace(req.grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        except dg.DgError as e:
+            req.grid = req.ws = req.stream = None
+            if e.code != dg.DG_E_NOMEM or not self.active:
+                raise
+            return False              # the device is full now: retry later
+        held = req.ws.held_bytes() + 4 * req.grid.elems * 8
+        self.shape_bytes[key] = held
+        if self.used + held > self.budget:
+            req.bytes = held
+            req.grid = req.ws = req.stream = None
+            return False
+        req.bytes = held
+        w0 = prepare(req)
         with torch.cuda.stream(req.stream):
             req.omega = torch.from_numpy(w0).cuda()
             if self.tune and key not in self.tiles:
                 self.tiles[key] = req.grid.tune(req.omega, reps=5)[0]
             if key in self.tiles:
                 req.grid.set_tiles(*self.tiles[key])
-            req.ws = dg.Workspace(req.grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
             req.state = dg.State(req.grid)
+        self._launch(req, now)
+        return True
+
+    def _launch(self, req: Request, now: float):
+        """Book an admitted request and hand it to a worker thread."""
         req.slot = req.rid
         req.admitted = now
         self.used += req.bytes
         self.peak_used = max(self.peak_used, self.used)
         self.active[req.slot] = req
         self.max_active = max(self.max_active, len(self.active))
+        self.futures[req.slot] = self.batch.submit(self._run_request, req, self._now)
 
     def retire(self, req: Request, now: float):
-        req.stream.synchronize()
-        req.result = req.omega.cpu().numpy()
+        if req.stream is not None:
+            req.stream.synchronize()
+        if req.error is None:
+            req.result = req.omega.cpu().numpy()
         self.used -= req.bytes
         del self.active[req.slot]
+        self.futures.pop(req.slot, None)
         req.omega = req.grid = req.ws = req.state = req.stream = None
-        req.finished = now
+        req.finished = req.done_at if not math.isnan(req.done_at) else now
 
-    def _step(self, req: Request):
+    def _step_once(self, req: Request, opts):
+        """One SSP-RK3 step of the request on its stream: (iterations of the
+        three solves, whether all converged)."""
         import torch
         with torch.cuda.stream(req.stream):
-            r = dg.rk_step(req.grid, req.omega, req.state, req.ws, req.dt, req.D, self.opts)
-        if not r.converged:
-            raise RuntimeError(f"request {req.rid}: the solve did not converge")
-        return r
+            r = dg.rk_step(req.grid, req.omega, req.state, req.ws, req.dt, req.D, opts)
+        return r.cg_iters, r.converged
 
-    def tick(self, now_fn):
-        futures = {slot: self.batch.submit(self._step, req)
-                   for slot, req in self.active.items()}
+    def _run_request(self, req: Request, now_fn):
+        """Worker: every step of one request, back to back."""
+        opts = self.opts
+        if opts is not None and req.max_iter:
+            opts = dg.cg_opts(opts.rtol, req.max_iter, opts.precision, opts.precond,
+                              opts.check_every)
+        try:
+            while req.done_steps < req.steps:
+                its, ok = self._step_once(req, opts)
+                req.cg_iters.extend(its)
+                req.done_steps += 1
+                if not ok:
+                    req.error = (f"request {req.rid}: a solve did not converge in "
+                                 f"step {req.done_steps}")
+                    break
+            if req.stream is not None:
+                req.stream.synchronize()
+        except Exception as e:          # a failed step retires this request only
+            req.error = f"request {req.rid}: {e}"
+        req.done_at = now_fn()
+
+    def advance(self, now_fn, wait_s):
+        """Retire the requests whose workers finished; wait for the first
+        one at most until the next arrival."""
+        timeout = 0.05 if wait_s is None else max(0.0, min(wait_s, 0.05))
+        done, _ = wait(list(self.futures.values()), timeout=timeout,
+                       return_when=FIRST_COMPLETED)
         self.ticks += 1
-        for slot, f in futures.items():
-            r = f.result()
-            req = self.active[slot]
-            req.cg_iters.extend(r.cg_iters)
-            req.done_steps += 1
-            if req.done_steps >= req.steps:
-                self.retire(req, now_fn())
-
+        for slot, f in list(self.futures.items()):
+            if f in done:
+                f.result()
+                self.retire(self.active[slot], now_fn())
 
 def summarize(done, makespan):
     lat = sorted(r.latency for r in done)
@@ -302,6 +385,8 @@ def run_alone(req: Request, opts=None, tiles=None):
     st = dg.State(grid)
     w = torch.from_numpy(w0).cuda()
     for _ in range(req.steps):
-        dg.rk_step(grid, w, st, ws, req.dt, req.D,
-                   opts if opts is not None else dg.cg_opts(rtol=1e-10))
+        r = dg.rk_step(grid, w, st, ws, req.dt, req.D,
+                       opts if opts is not None else dg.cg_opts(rtol=1e-10))
+        if not r.converged:
+            raise RuntimeError(f"request {req.rid} alone: a solve did not converge")
     return w.cpu().numpy()

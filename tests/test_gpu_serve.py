@@ -91,11 +91,62 @@ def test_stream_server_pcg_equals_alone(serve):
 def test_stream_server_budget_queues(serve):
     reqs = serve.draw_requests(4, seed=6, rate=1000.0, N_range=(16, 48),
                                k0_range=(2.0, 5.0), steps=2)
-    probe = serve.StreamServer(capacity=1)
-    biggest = max(probe.request_bytes(r) for r in reqs)
+    from paper_1311_7477_amd import dg
+    # the budget fits the largest request's real footprint (workspace with
+    # its library buffers, state and omega), not two of them
+    held = []
+    for r in reqs:
+        g = dg.Grid(r.n, r.N, r.N)
+        held.append(dg.Workspace(g, dg.DG_PREC_FP64 | dg.DG_WS_FD).held_bytes()
+                    + 4 * g.elems * 8)
+    biggest = max(held)
+    assert 2 * min(held) > biggest
     srv = serve.StreamServer(capacity=8, hbm_budget=biggest, workers=2)
     done = srv.run(reqs)
     assert len(done) == len(reqs)
     assert srv.peak_used <= biggest and srv.max_active < len(reqs)
     order = [r.rid for r in sorted(done, key=lambda r: r.admitted)]
     assert order == sorted(order)
+
+
+def test_stream_server_retires_a_failing_request_alone(serve):
+    # one request capped at one CG iteration (the FP32-preconditioned solve
+    # needs at least two at rtol 1e-10 from a zero guess): it is retired
+    # with an error, the others finish and equal their stand-alone runs
+    reqs = serve.draw_requests(5, seed=7, rate=500.0, N_range=(16, 64),
+                               k0_range=(2.0, 5.0), steps=3)
+    reqs[1].max_iter = 1
+    srv = serve.StreamServer(capacity=8)
+    done = srv.run(reqs)
+    assert [r.rid for r in srv.failed] == [reqs[1].rid]
+    assert "did not converge" in reqs[1].error
+    assert {r.rid for r in done} == {r.rid for r in reqs} - {reqs[1].rid}
+    for r in done:
+        assert np.array_equal(r.result, serve.run_alone(r, srv.opts))
+    assert not srv.active and srv.used == 0
+
+
+def test_batched_server_retires_non_converging_members(serve):
+    from paper_1311_7477_amd import dg
+    reqs = _stream(serve, count=3)
+    srv = serve.Server(capacity=4, opts=dg.cg_opts(rtol=1e-12, max_iter=1), tune=False)
+    done = srv.run(reqs)
+    assert done == [] and len(srv.failed) == 3
+    assert all(r.error and r.done_steps == 1 for r in reqs)
+    assert not srv.active and srv.used == 0
+
+
+def test_workspace_held_bytes_cover_library_buffers(serve):
+    # FFT-path grids (both counts even, beyond 512 cells) and a
+    # matrix-product one: the workspace reports at least the pre-creation
+    # figure (the difference is rocFFT's work buffer and rocBLAS's memory)
+    from paper_1311_7477_amd import dg
+    for n, N in ((2, 1040), (2, 520), (3, 64)):
+        g = dg.Grid(n, N, N)
+        ws = dg.Workspace(g, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        est = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        held = ws.held_bytes()
+        print(f"n={n} N={N}: estimate {est} B, held {held} B", flush=True)
+        assert held >= est
+        plain = dg.Workspace(g)
+        assert plain.held_bytes() == g.workspace_bytes(dg.DG_PREC_FP64)

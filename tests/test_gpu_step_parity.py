@@ -163,3 +163,36 @@ def test_metric_workload_first_step_full_size(dg):
     assert rel <= 1e-12, rel
     # the step is not the identity at this bar: |omega1 - omega0| >> 1e-12
     assert _wnorm_rel(g, w0, wref) > 1e-6
+
+
+def test_lamb_dipole_drift_j_against_jpp(dg):
+    # Sec. 6.2: with the average bracket E and Omega change only through the
+    # time stepping (AB3: halving dt divides the drift by ~8); with J++ the
+    # bracket itself changes them (the drift does not shrink with dt).
+    # P = 1, 64^2 cells, t = 0.05 (the oracle gives 2.9e-6 / 3.6e-7 for J's
+    # energy drift and 6.7e-4 for J++'s at both time steps).
+    n, N, T = 1, 64, 0.05
+    grid = dg.Grid(n, N, N, 0.0, 1.0, 0.0, 1.0)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    opts = dg.cg_opts(rtol=1e-13, precond=dg.DG_PRECOND_FD)
+    w0 = _dev(I.lamb_dipole(n, N))
+    p0 = torch.zeros_like(w0)
+    dg.cg_solve_poisson(grid, w0, p0, ws, opts)
+    _, E0, Om0 = dg.invariants(grid, w0, p0, ws)
+    drift = {}
+    for form in (0, 1):
+        for dt in (1e-3, 5e-4):
+            ab = dg.AbState(grid, 3)
+            w = w0.clone()
+            for _ in range(int(round(T / dt))):
+                assert dg.ab_step(grid, w, ab, ws, dt, 0.0, opts, form=form).converged
+            psi = ab.psi()
+            dg.cg_solve_poisson(grid, w, psi, ws, opts)
+            V, E, Om = dg.invariants(grid, w, psi, ws)
+            assert abs(V) < 1e-13
+            drift[form, dt] = (abs(E - E0) / E0, abs(Om - Om0) / Om0)
+    for q in (0, 1):
+        rJ = drift[0, 1e-3][q] / drift[0, 5e-4][q]
+        rP = drift[1, 1e-3][q] / drift[1, 5e-4][q]
+        assert 6.0 < rJ < 10.0 and drift[0, 1e-3][q] < 2e-5, drift
+        assert 0.9 < rP < 1.1 and drift[1, 5e-4][q] > 1e-4, drift

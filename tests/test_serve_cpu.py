@@ -101,3 +101,80 @@ def test_summary_percentiles():
     assert s["mean_latency_s"] == 2.5 and s["requests"] == 4
     assert s["aggregate_cell_updates_per_s"] == sum(r.cell_updates for r in reqs) / 4.0
     assert s["mean_cg_iters_per_rhs"] == 1.5
+
+
+class FailingCountingServer(CountingServer):
+    """The batched engine's tick with one request whose solve never
+    converges: it must be retired with an error while the others finish."""
+
+    def __init__(self, capacity, budget, bad):
+        super().__init__(capacity, budget)
+        self.bad = bad
+
+    def tick(self, now_fn):
+        self.ticks += 1
+        for req in list(self.active.values()):
+            req.done_steps += 1
+            if req.rid == self.bad:
+                req.error = f"request {req.rid}: a solve did not converge"
+                self.retire(req, now_fn())
+            elif req.done_steps >= req.steps:
+                self.retire(req, now_fn())
+
+
+def test_failed_request_is_retired_alone():
+    reqs = serve.draw_requests(6, seed=2, rate=1e6, N_range=(16, 64), steps=4)
+    srv = FailingCountingServer(8, 10 ** 12, bad=reqs[2].rid)
+    done = srv.run(reqs)
+    assert [r.rid for r in srv.failed] == [reqs[2].rid]
+    assert {r.rid for r in done} == {r.rid for r in reqs} - {reqs[2].rid}
+    assert all(r.done_steps == r.steps and r.error is None for r in done)
+    assert srv.used == 0 and not srv.active
+
+
+class SleepyStreamServer(serve.StreamServer):
+    """StreamServer's scheduling (a worker per request, no step barrier,
+    per-request failure) with the device step replaced by a sleep of
+    N / 16000 s; a request with max_iter = 1 'does not converge' in its
+    second step."""
+
+    def __init__(self, capacity, budget):
+        super().__init__(capacity=capacity, hbm_budget=budget, opts=None, workers=capacity)
+
+    def request_bytes(self, req):
+        return 8 * req.N * req.N
+
+    def admit(self, req, now):
+        self._launch(req, now)
+        return True
+
+    def _step_once(self, req, opts):
+        import time as _t
+        _t.sleep(req.N / 16000.0)
+        return (1, 1, 1), not (req.max_iter == 1 and req.done_steps >= 1)
+
+    def retire(self, req, now):
+        self.used -= req.bytes
+        del self.active[req.slot]
+        self.futures.pop(req.slot, None)
+        req.finished = req.done_at
+
+
+def test_stream_engine_has_no_step_barrier_and_retires_failures_alone():
+    # a large request (N = 1600: 0.1 s per step) and small ones (N = 16:
+    # 1 ms per step) admitted together: the small ones finish long before
+    # the large one although every request has 8 steps; one small request
+    # fails in its second step and is retired alone
+    reqs = serve.draw_requests(5, seed=3, rate=1e6, N_range=(16, 17), steps=8)
+    reqs[0].N = 1600
+    reqs[3].max_iter = 1
+    srv = SleepyStreamServer(8, 10 ** 12)
+    done = srv.run(reqs)
+    assert [r.rid for r in srv.failed] == [reqs[3].rid]
+    assert reqs[3].done_steps == 2 and reqs[3].error
+    assert {r.rid for r in done} == {r.rid for r in reqs} - {reqs[3].rid}
+    big = reqs[0]
+    smalls = [r for r in done if r.rid != big.rid]
+    assert all(r.done_steps == 8 for r in done)
+    assert max(r.finished for r in smalls) < 0.5 * big.finished
+    assert srv.used == 0 and not srv.active and not srv.futures
