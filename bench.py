@@ -897,13 +897,6 @@ def main():
     from paper_1311_7477_amd import dg, inputs
 
     torch.cuda.set_device(0)
-    if args.form != "rhs":
-        {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
-         "paper": form_paper, "tune": form_tune, "lamb": form_lamb,
-         "table3": form_table3, "turbulence": form_turbulence,
-         "dirichlet": form_dirichlet, "dipole": form_dipole}[args.form](args)
-        return
-    n, N = args.n, args.N
     if args.copy_calibration:
         src = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")   # 256 MiB
         dst = torch.empty_like(src)
@@ -911,6 +904,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.form != "rhs":
+        {"batch": form_batch, "mixed": form_mixed, "serve": form_serve,
+         "paper": form_paper, "tune": form_tune, "lamb": form_lamb,
+         "table3": form_table3, "turbulence": form_turbulence,
+         "dirichlet": form_dirichlet, "dipole": form_dipole}[args.form](args)
+        return
+    n, N = args.n, args.N
     omega0, umax = inputs.random_spectrum(n, N, k0=10.0, seed=1, return_umax=True)
     dt = inputs.cfl_dt(n, N, umax, cfl=0.1)
     grid = dg.Grid(n, N, N)

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_sub_mean(const BatchInst* __res
 }
 
 template <int N, int W>
-__global__ __launch_bounds__(64 * W) void kb_rhs(const BatchInst* __restrict__ inst, ItemList list) {
+__global__ __launch_bounds__(64 * W, 4) void kb_rhs(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ RhsLds<N, W, true> lds;
     DG_FOR_ITEMS(list) {
         rhs_body<N, W, true>(item_.b, B.g, B.row_tilesX, B.row_nblocks,

@@ -8,6 +8,7 @@
 // spectra for the FFT path, the dense path's conversions and division, and
 // the preconditioned dot product <r, z>_W that closes the PCG step.
 #include <cmath>
+#include <type_traits>
 
 #include "cg_body.h"
 #include "dg_launch.h"
@@ -220,27 +221,44 @@ __global__ __launch_bounds__(kPwThreads) void k_from_image_dot(
 }
 
 // out = M v for one 2n-vector (M row-major, S = 2n, row = output index);
-// `pair` false: only the leading n x n block (wave numbers 0 and N/2).
-template <int N, class T>
-__device__ __forceinline__ void mix_vec(const T* __restrict__ M, bool pair, const T* v, T* out) {
+// PAIR false: only the leading n x n block (wave numbers 0 and N/2).
+template <int N, class T, bool PAIR>
+__device__ __forceinline__ void mix_vec(const T* __restrict__ M, const T* v, T* out) {
     constexpr int S = 2 * N;
-    if (pair) {
+    constexpr int R = PAIR ? S : N;
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            T acc = 0;
+    for (int q = 0; q < R; ++q) {
+        T acc = 0;
 #pragma unroll
-            for (int p = 0; p < S; ++p) acc = fma(M[q * S + p], v[p], acc);
-            out[q] = acc;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            T acc = 0;
-#pragma unroll
-            for (int p = 0; p < N; ++p) acc = fma(M[q * S + p], v[p], acc);
-            out[q] = acc;
-        }
+        for (int p = 0; p < R; ++p) acc = fma(M[q * S + p], v[p], acc);
+        out[q] = acc;
     }
+}
+
+// 1 / d from the hardware reciprocal refined by Newton's iteration
+// r <- r + r (1 - d r) (twice in FP64, once in FP32): within about one ulp
+// of the correctly rounded quotient at a fraction of an IEEE division's
+// instructions.  The spectral division of the preconditioner only has to
+// approximate the exact inverse (the PCG iteration measures its residual in
+// FP64), so the last bit does not matter there.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+
+// Call f(std::true_type) or f(std::false_type) for a (wave-uniform) pair
+// flag, so that the mixing code is compiled with the vector length fixed.
+template <class F>
+__device__ __forceinline__ void with_pair(bool pair, F&& f) {
+    if (pair)
+        f(std::true_type{});
+    else
+        f(std::false_type{});
 }
 
 // The x mixing of the matrix-product path, out of place, combined with the
@@ -261,63 +279,43 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_x_fold(int Nx, int Ny, in
     const bool pair = c1 >= 0;
     const T* Mk = M + (size_t)k * S * S;
     const long per = (long)Ky * N;
-    for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
-         t += (long)gridDim.x * kPwThreads) {
-        const int j = (int)(t / Ky), cy = (int)(t - (long)j * Ky);
-        const bool pr = fold_pair(cy, Ny);
-        const long jb = (long)Ny * N * Nx * j;
-        const long s0 = (long)Ny * N * c0, s1 = (long)Ny * N * (pair ? c1 : c0);
-        // rows: A (cy) and B (Ny - 1 - cy) unfolded, E (cy) and O (Ky + cy) folded
-        const long rA = jb + cy, rB = jb + (Ny - 1 - cy), rE = jb + cy, rO = jb + (Ky + cy);
-        T va[S], vb[S], wa[S], wb[S];
-        if (!Inv) {
+    with_pair(pair, [&](auto pc) {
+        constexpr bool PAIR = decltype(pc)::value;
+        for (long t = blockIdx.x * (long)kPwThreads + threadIdx.x; t < per;
+             t += (long)gridDim.x * kPwThreads) {
+            const int j = (int)(t / Ky), cy = (int)(t - (long)j * Ky);
+            const bool pr = fold_pair(cy, Ny);
+            const long jb = (long)Ny * N * Nx * j;
+            const long s0 = (long)Ny * N * c0, s1 = (long)Ny * N * (PAIR ? c1 : c0);
+            // rows: A (cy) and B (Ny - 1 - cy) unfolded, E (cy) and O (Ky + cy) folded
+            const long rA = jb + cy, rB = jb + (Ny - 1 - cy), rE = jb + cy, rO = jb + (Ky + cy);
+            const long r0 = Inv ? rE : rA, r1 = Inv ? rO : rB;    // rows read
+            const long w0 = Inv ? rA : rE, w1 = Inv ? rB : rO;    // rows written
+            T va[S], vb[S], wa[S], wb[S];
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                const T a0 = in[rA + s0 + (long)Ny * i];
-                const T a1 = pair ? in[rA + s1 + (long)Ny * i] : T(0);
-                const T b0 = pr ? in[rB + s0 + (long)Ny * i] : T(0);
-                const T b1 = (pr && pair) ? in[rB + s1 + (long)Ny * i] : T(0);
+                const T a0 = in[r0 + s0 + (long)Ny * i];
+                const T a1 = PAIR ? in[r0 + s1 + (long)Ny * i] : T(0);
+                const T b0 = pr ? in[r1 + s0 + (long)Ny * i] : T(0);
+                const T b1 = (pr && PAIR) ? in[r1 + s1 + (long)Ny * i] : T(0);
                 va[i] = a0 + b0;
                 va[N + i] = a1 + b1;
                 vb[i] = a0 - b0;
                 vb[N + i] = a1 - b1;
             }
-            mix_vec<N, T>(Mk, pair, va, wa);
-            if (pr) mix_vec<N, T>(Mk, pair, vb, wb);
+            mix_vec<N, T, PAIR>(Mk, va, wa);
+            if (pr) mix_vec<N, T, PAIR>(Mk, vb, wb);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                out[rE + s0 + (long)Ny * i] = wa[i];
-                if (pair) out[rE + s1 + (long)Ny * i] = wa[N + i];
+                out[w0 + s0 + (long)Ny * i] = wa[i];
+                if (PAIR) out[w0 + s1 + (long)Ny * i] = wa[N + i];
                 if (pr) {
-                    out[rO + s0 + (long)Ny * i] = wb[i];
-                    if (pair) out[rO + s1 + (long)Ny * i] = wb[N + i];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const T e0 = in[rE + s0 + (long)Ny * i];
-                const T e1 = pair ? in[rE + s1 + (long)Ny * i] : T(0);
-                const T o0 = pr ? in[rO + s0 + (long)Ny * i] : T(0);
-                const T o1 = (pr && pair) ? in[rO + s1 + (long)Ny * i] : T(0);
-                va[i] = e0 + o0;
-                va[N + i] = e1 + o1;
-                vb[i] = e0 - o0;
-                vb[N + i] = e1 - o1;
-            }
-            mix_vec<N, T>(Mk, pair, va, wa);
-            if (pr) mix_vec<N, T>(Mk, pair, vb, wb);
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                out[rA + s0 + (long)Ny * i] = wa[i];
-                if (pair) out[rA + s1 + (long)Ny * i] = wa[N + i];
-                if (pr) {
-                    out[rB + s0 + (long)Ny * i] = wb[i];
-                    if (pair) out[rB + s1 + (long)Ny * i] = wb[N + i];
+                    out[w1 + s0 + (long)Ny * i] = wb[i];
+                    if (PAIR) out[w1 + s1 + (long)Ny * i] = wb[N + i];
                 }
             }
         }
-    }
+    });
 }
 
 // Mixing of the y transform, spectral scaling and unmixing, on
@@ -339,33 +337,36 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
     const T* Mfk = Mf + (size_t)k * S * S;
     const T* Mik = Mi + (size_t)k * S * S;
     const long NXn = (long)N * Nx;
-    for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
-         m += (long)gridDim.x * kPwThreads) {
-        const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
-        const int xs = i * Nx + kx;
-        const T lam_x = lx[xs];
-        const long o0 = m + NXn * N * c0;
-        const long o1 = m + NXn * N * (pair ? c1 : c0);
-        T v[S], w[S];
+    with_pair(pair, [&](auto pc) {
+        constexpr bool PAIR = decltype(pc)::value;
+        constexpr int R = PAIR ? S : N;
+        for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
+             m += (long)gridDim.x * kPwThreads) {
+            const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
+            const int xs = i * Nx + kx;
+            const T lam_x = lx[xs];
+            const long o0 = m + NXn * N * c0;
+            const long o1 = m + NXn * N * (PAIR ? c1 : c0);
+            T v[S], w[S];
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            v[j] = u[o0 + NXn * j];
-            v[N + j] = pair ? u[o1 + NXn * j] : T(0);
-        }
-        mix_vec<N, T>(Mfk, pair, v, w);
+            for (int j = 0; j < N; ++j) {
+                v[j] = u[o0 + NXn * j];
+                if (PAIR) v[N + j] = u[o1 + NXn * j];
+            }
+            mix_vec<N, T, PAIR>(Mfk, v, w);
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            if (q >= N && !pair) break;
-            const int ys = (q % N) * Ny + (q < N ? c0 : c1);
-            w[q] = (xs == zx && ys == zy) ? T(0) : w[q] / -(lam_x + ly[ys]);
-        }
-        mix_vec<N, T>(Mik, pair, w, v);
+            for (int q = 0; q < R; ++q) {
+                const int ys = (q % N) * Ny + (q < N ? c0 : c1);
+                w[q] = (xs == zx && ys == zy) ? T(0) : -w[q] * recip(lam_x + ly[ys]);
+            }
+            mix_vec<N, T, PAIR>(Mik, w, v);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            u[o0 + NXn * j] = v[j];
-            if (pair) u[o1 + NXn * j] = v[N + j];
+            for (int j = 0; j < N; ++j) {
+                u[o0 + NXn * j] = v[j];
+                if (PAIR) u[o1 + NXn * j] = v[N + j];
+            }
         }
-    }
+    });
 }
 
 // ---- The same steps with the cell transforms as FFTs.  A real row u of
@@ -421,19 +422,18 @@ __device__ __forceinline__ C coef_to_spec(bool pair, T cn, T cp, T a, T b) {
 // = (cos, sin) of 2 pi k / N, evaluated in FP64.
 template <class T>
 struct WavePair {
-    int nw, k[2], q;
-    T c[2], s[2];
+    int nw, k0, k1, q;
+    T c0, s0, c1, s1;
     __device__ WavePair(int p, int N) {
         const int H = N / 2;
-        k[0] = p;
-        k[1] = H - p;
-        nw = k[1] == p ? 1 : 2;
+        k0 = p;
+        k1 = H - p;
+        nw = k1 == p ? 1 : 2;
         q = (H - p) % H;
-        for (int w = 0; w < 2; ++w) {
-            const double x = 2.0 * k[w] / N;
-            c[w] = T(cospi(x));
-            s[w] = T(sinpi(x));
-        }
+        c0 = T(cospi(2.0 * k0 / N));
+        s0 = T(sinpi(2.0 * k0 / N));
+        c1 = T(cospi(2.0 * k1 / N));
+        s1 = T(sinpi(2.0 * k1 / N));
     }
 };
 
@@ -460,179 +460,282 @@ __device__ __forceinline__ C pack_half(const C ya, const C yb, T c, T s) {
     return z;
 }
 
-// Block -> (wave pair p, row block rb) for the FFT mixing kernels (grid P x
-// row blocks).  Neighbouring wave pairs read neighbouring values of the same
-// spectrum rows, so they should share one L2: workgroups go to the 8 XCDs
-// in turn, and this map gives each XCD a contiguous run of (p fastest)
-// blocks; the last total mod 8 blocks keep their place.
-__device__ __forceinline__ void xcd_pair_block(int& p, int& rb) {
+// Block -> (pair chunk pc, row block rb) for the FFT mixing kernels (grid
+// chunks x row blocks).  Neighbouring chunks read neighbouring runs of the
+// same spectrum rows (their partner columns share cache lines), so they
+// should share one L2: workgroups go to the 8 XCDs in turn, and this map
+// gives each XCD a contiguous run of (chunk fastest) blocks; the last
+// total mod 8 blocks keep their place.
+__device__ __forceinline__ void xcd_pair_block(int& pc, int& rb) {
     const int P = gridDim.x, total = P * gridDim.y;
     const int b = blockIdx.x + P * blockIdx.y, full = total & ~7;
     const int l = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
-    p = l % P;
+    pc = l % P;
     rb = l / P;
 }
 
-// Forward x mixing from the x spectra Z[(cy + Ny (i + n j)) H + k] (H =
-// Nx/2, k < H; wave pair and row block from xcd_pair_block, lanes along cy)
-// into the real x-transformed field U1[cy + Ny (i + n c + n Nx j)] (c: the
-// cos / sin columns of wave number k, as in the matrix-product path).
+// Packed spectra staged through LDS.  A block covers 64 consecutive values
+// of a row coordinate a (lanes) and TP consecutive wave pairs p0 .. p0+TP-1
+// (waves); spectrum row(a, i) (i < n) holds pair p's values at column p
+// (s = 0) and at its partner column q = (H - p) mod H (s = 1).  Global loads
+// and stores move runs of TP consecutive columns of one row (64 bytes); in
+// the compute phase wave w owns pair p0 + w, so its mixing blocks come in
+// through scalar loads, and lane a the row coordinate a0 + a, so the real
+// fields it reads or writes are 64 consecutive values.  Each run of 64
+// values of a is padded so that the 16 lanes an LDS cycle serves during the
+// loads (4 pairs x 4 values of a in FP64) hit different banks.
 template <int N, class T>
-__global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_fwd(
-    int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf, T cn, T cp,
-    const typename CplxOf<T>::type* __restrict__ Z, T* __restrict__ u1) {
+struct SpecTile {
     using C = typename CplxOf<T>::type;
-    constexpr int S = 2 * N;
-    int p, rb;
-    xcd_pair_block(p, rb);
-    const WavePair<T> wp(p, Nx);
-    const long per = (long)Ny * N, H = Nx / 2;
-    for (long t = rb * (long)kPwThreads + threadIdx.x; t < per;
-         t += (long)gridDim.y * kPwThreads) {
-        const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
-        C za[N], zb[N];
+    static constexpr int TP = 64 / (int)sizeof(C);          // 4 (FP64) or 8 (FP32)
+    static constexpr int THREADS = 64 * TP;   // = 2048 / sizeof(T), the launch bound
+    static_assert(THREADS == 2048 / (int)sizeof(T), "launch bound of the mixing kernels");
+    static constexpr int RS = sizeof(C) == 16 ? 68 : 66;    // padded run of 64 values
+    static constexpr int SIZE = N * 2 * TP * RS;
+    __device__ static constexpr int at(int i, int s, int p, int a) {
+        return ((i * 2 + s) * TP + p) * RS + a;
+    }
+};
+
+// Load the block's tile: row(a, i) = base + a + stride * i for a < A, pairs
+// p < P (entries outside stay zero).  Every thread issues its 2n loads
+// before its first LDS store, so they are all in flight together.
+template <int N, class T>
+__device__ __forceinline__ void spec_load(const typename CplxOf<T>::type* __restrict__ Z,
+                                          long H, int P, int p0, int a0, int A, long base,
+                                          long stride, typename CplxOf<T>::type* L) {
+    using TL = SpecTile<N, T>;
+    using C = typename CplxOf<T>::type;
+    constexpr int ITER = N * 64 * 2 * TL::TP / TL::THREADS;     // = 2n
+    C v[ITER];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const long r = cy + (long)Ny * (i + N * j);
-            za[i] = Z[r * H + p];
-            zb[i] = Z[r * H + wp.q];
-        }
-        const long base = cy + (long)Ny * N * Nx * j;
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            if (w == 1 && wp.nw == 1) break;
-            const int k = wp.k[w];
-            const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
-            const bool pair = c1 >= 0;
-            T v[S], o[S];
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const C x = w ? unpack_half(zb[i], za[i], wp.c[1], wp.s[1])
-                              : unpack_half(za[i], zb[i], wp.c[0], wp.s[0]);
-                spec_to_coef(x, pair, cn, cp, v[i], v[N + i]);
-            }
-            mix_vec<N, T>(Mf + (size_t)k * S * S, pair, v, o);
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                u1[base + (long)Ny * (i + (long)N * c0)] = o[i];
-                if (pair) u1[base + (long)Ny * (i + (long)N * c1)] = o[N + i];
-            }
+    for (int it = 0; it < ITER; ++it) {
+        const int e = threadIdx.x + it * TL::THREADS;
+        const int p = e % TL::TP, s = (e / TL::TP) & 1;
+        const int a = (e / (2 * TL::TP)) & 63, i = e / (2 * TL::TP * 64);
+        const int pp = p0 + p;
+        v[it].x = T(0);
+        v[it].y = T(0);
+        if (pp < P && a0 + a < A) {
+            const long col = s ? (pp == 0 ? 0 : H - pp) : pp;    // (H - pp) mod H
+            v[it] = Z[(base + a0 + a + stride * i) * H + col];
         }
     }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int e = threadIdx.x + it * TL::THREADS;
+        const int p = e % TL::TP, s = (e / TL::TP) & 1;
+        const int a = (e / (2 * TL::TP)) & 63, i = e / (2 * TL::TP * 64);
+        L[TL::at(i, s, p, a)] = v[it];
+    }
+}
+
+// Store the tile back: column p from s = 0 and column H - p from s = 1
+// (p > 0 with H - p != p; column 0 packs the wave numbers 0 and H).
+template <int N, class T>
+__device__ __forceinline__ void spec_store(typename CplxOf<T>::type* __restrict__ Z, long H,
+                                           int P, int p0, int a0, int A, long base, long stride,
+                                           const typename CplxOf<T>::type* L) {
+    using TL = SpecTile<N, T>;
+    constexpr int ITER = N * 64 * 2 * TL::TP / TL::THREADS;     // = 2n
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int e = threadIdx.x + it * TL::THREADS;
+        const int p = e % TL::TP, s = (e / TL::TP) & 1;
+        const int a = (e / (2 * TL::TP)) & 63, i = e / (2 * TL::TP * 64);
+        const int pp = p0 + p;
+        if (pp >= P || a0 + a >= A) continue;
+        if (s && (pp == 0 || H - pp == pp)) continue;
+        const long col = s ? H - pp : pp;
+        Z[(base + a0 + a + stride * i) * H + col] = L[TL::at(i, s, p, a)];
+    }
+}
+
+// Forward x mixing from the x spectra Z[(cy + Ny (i + n j)) H + k] (H =
+// Nx/2, k < H) into the real x-transformed field U1[cy + Ny (i + n c +
+// n Nx j)] (c: the cos / sin columns of wave number k, as in the
+// matrix-product path).  Grid: pair chunks x (cy blocks of 64, j).
+template <int N, class T>
+__global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_fwd(
+    int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf, T cn, T cp,
+    const typename CplxOf<T>::type* __restrict__ Z, T* __restrict__ u1) {
+    using TL = SpecTile<N, T>;
+    using C = typename CplxOf<T>::type;
+    constexpr int S = 2 * N;
+    __shared__ C L[TL::SIZE];
+    int pc, rb;
+    xcd_pair_block(pc, rb);
+    const int ab = (Ny + 63) / 64;
+    const int j = rb / ab, a0 = (rb - j * ab) * 64;
+    const long H = Nx / 2, base = (long)Ny * N * j;
+    const int P = Nx / 4 + 1, p0 = pc * TL::TP;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), a = threadIdx.x & 63;
+    const int p = p0 + w, cy = a0 + a;
+    spec_load<N, T>(Z, H, P, p0, a0, Ny, base, Ny, L);
+    __syncthreads();
+    if (p >= P || cy >= Ny) return;
+    const WavePair<T> wp(p, Nx);
+    C za[N], zb[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        za[i] = L[TL::at(i, 0, w, a)];
+        zb[i] = L[TL::at(i, 1, w, a)];
+    }
+    const long out0 = cy + (long)Ny * N * Nx * j;
+    // wave number k from its own half-spectrum value and its partner's
+    auto one = [&](int k, const T* Mk, const C* zk, const C* zh, T c, T sn) {
+        const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
+        with_pair(c1 >= 0, [&](auto pc) {
+            constexpr bool PAIR = decltype(pc)::value;
+            T v[S], o[S];
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                spec_to_coef(unpack_half(zk[i], zh[i], c, sn), PAIR, cn, cp, v[i], v[N + i]);
+            mix_vec<N, T, PAIR>(Mk, v, o);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                u1[out0 + (long)Ny * (i + (long)N * c0)] = o[i];
+                if (PAIR) u1[out0 + (long)Ny * (i + (long)N * c1)] = o[N + i];
+            }
+        });
+    };
+    one(wp.k0, Mf + (size_t)wp.k0 * S * S, za, zb, wp.c0, wp.s0);
+    if (wp.nw == 2) one(wp.k1, Mf + (size_t)wp.k1 * S * S, zb, za, wp.c1, wp.s1);
 }
 
 // Inverse x mixing: U1 (real coefficients) -> the packed x spectra, ready for
-// the inverse x transform.
+// the inverse x transform (the packed values go through the LDS tile so the
+// spectrum rows are written in runs).
 template <int N, class T>
-__global__ __launch_bounds__(kPwThreads) void k_fft_mix_x_inv(
+__global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_inv(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mi, T cn, T cp,
     const T* __restrict__ u1, typename CplxOf<T>::type* __restrict__ Z) {
+    using TL = SpecTile<N, T>;
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    int p, rb;
-    xcd_pair_block(p, rb);
-    const WavePair<T> wp(p, Nx);
-    const long per = (long)Ny * N, H = Nx / 2;
-    for (long t = rb * (long)kPwThreads + threadIdx.x; t < per;
-         t += (long)gridDim.y * kPwThreads) {
-        const int j = (int)(t / Ny), cy = (int)(t - (long)j * Ny);
-        const long base = cy + (long)Ny * N * Nx * j;
-        C y[2][N];
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            if (w == 1 && wp.nw == 1) break;
-            const int k = wp.k[w];
+    __shared__ C L[TL::SIZE];
+    int pc, rb;
+    xcd_pair_block(pc, rb);
+    const int ab = (Ny + 63) / 64;
+    const int j = rb / ab, a0 = (rb - j * ab) * 64;
+    const long H = Nx / 2, base = (long)Ny * N * j;
+    const int P = Nx / 4 + 1, p0 = pc * TL::TP;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), a = threadIdx.x & 63;
+    const int p = p0 + w, cy = a0 + a;
+    __syncthreads();
+    if (p < P && cy < Ny) {
+        const WavePair<T> wp(p, Nx);
+        const long in0 = cy + (long)Ny * N * Nx * j;
+        // half-spectrum values of wave number k from its real coefficients
+        auto one = [&](int k, const T* Mk, C* y) {
             const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
-            const bool pair = c1 >= 0;
-            T v[S], o[S];
+            with_pair(c1 >= 0, [&](auto pc) {
+                constexpr bool PAIR = decltype(pc)::value;
+                T v[S], o[S];
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                v[i] = u1[base + (long)Ny * (i + (long)N * c0)];
-                v[N + i] = pair ? u1[base + (long)Ny * (i + (long)N * c1)] : T(0);
-            }
-            mix_vec<N, T>(Mi + (size_t)k * S * S, pair, v, o);
+                for (int i = 0; i < N; ++i) {
+                    v[i] = u1[in0 + (long)Ny * (i + (long)N * c0)];
+                    if (PAIR) v[N + i] = u1[in0 + (long)Ny * (i + (long)N * c1)];
+                }
+                mix_vec<N, T, PAIR>(Mk, v, o);
 #pragma unroll
-            for (int i = 0; i < N; ++i)
-                y[w][i] = coef_to_spec<C>(pair, cn, cp, o[i], pair ? o[N + i] : T(0));
-        }
-        if (wp.nw == 1) {
+                for (int i = 0; i < N; ++i)
+                    y[i] = coef_to_spec<C>(PAIR, cn, cp, o[i], PAIR ? o[N + i] : T(0));
+            });
+        };
+        C y0[N], y1[N];
+        one(wp.k0, Mi + (size_t)wp.k0 * S * S, y0);
+        if (wp.nw == 2) {
+            one(wp.k1, Mi + (size_t)wp.k1 * S * S, y1);
+        } else {
 #pragma unroll
-            for (int i = 0; i < N; ++i) y[1][i] = y[0][i];
+            for (int i = 0; i < N; ++i) y1[i] = y0[i];
         }
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const long r = cy + (long)Ny * (i + N * j);
-            Z[r * H + p] = pack_half(y[0][i], y[1][i], wp.c[0], wp.s[0]);
-            if (p > 0 && wp.nw == 2)
-                Z[r * H + wp.k[1]] = pack_half(y[1][i], y[0][i], wp.c[1], wp.s[1]);
+            L[TL::at(i, 0, w, a)] = pack_half(y0[i], y1[i], wp.c0, wp.s0);
+            L[TL::at(i, 1, w, a)] = pack_half(y1[i], y0[i], wp.c1, wp.s1);
         }
     }
+    __syncthreads();
+    spec_store<N, T>(Z, H, P, p0, a0, Ny, base, Ny, L);
 }
 
 // y mixing, spectral division and unmixing in place on the packed y spectra
-// Z[(m + n Nx j) H + k] (m = i + n kx, H = Ny/2, k < H; wave pair and row
-// block from xcd_pair_block, lanes along m): spectrum -> y modes (Mf),
-// divided by -(lam_x + lam_y), the constant mode zeroed, -> coefficients
-// (Mi) -> spectrum.  Each lane reads and writes the same two spectrum rows.
+// Z[(m + n Nx j) H + k] (m = i + n kx, H = Ny/2, k < H): spectrum -> y
+// modes (Mf), divided by -(lam_x + lam_y), the constant mode zeroed, ->
+// coefficients (Mi) -> spectrum.  A block reads and writes only the columns
+// of its own pairs (p and H - p), so working in place is safe.  Grid: pair
+// chunks x m blocks of 64.
 template <int N, class T>
-__global__ __launch_bounds__(kPwThreads) void k_fft_mix_y(
+__global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_y(
     int Nx, int Ny, const int* __restrict__ cols, const T* __restrict__ Mf,
     const T* __restrict__ Mi, const T* __restrict__ lx, const T* __restrict__ ly, int zx, int zy,
     T cn, T cp, typename CplxOf<T>::type* __restrict__ Z) {
+    using TL = SpecTile<N, T>;
     using C = typename CplxOf<T>::type;
     constexpr int S = 2 * N;
-    int p, rb;
-    xcd_pair_block(p, rb);
-    const WavePair<T> wp(p, Ny);
+    __shared__ C L[TL::SIZE];
+    int pc, rb;
+    xcd_pair_block(pc, rb);
     const long NXn = (long)N * Nx, H = Ny / 2;
-    for (long m = rb * (long)kPwThreads + threadIdx.x; m < NXn;
-         m += (long)gridDim.y * kPwThreads) {
+    const int P = Ny / 4 + 1, p0 = pc * TL::TP, a0 = rb * 64;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), a = threadIdx.x & 63;
+    const int p = p0 + w;
+    spec_load<N, T>(Z, H, P, p0, a0, (int)NXn, 0, NXn, L);
+    __syncthreads();
+    const long m = a0 + a;
+    if (p < P && m < NXn) {
+        const WavePair<T> wp(p, Ny);
         const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
         const int xs = i * Nx + kx;
         const T lam_x = lx[xs];
         C za[N], zb[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            za[j] = Z[(m + NXn * j) * H + p];
-            zb[j] = Z[(m + NXn * j) * H + wp.q];
+        for (int jj = 0; jj < N; ++jj) {
+            za[jj] = L[TL::at(jj, 0, w, a)];
+            zb[jj] = L[TL::at(jj, 1, w, a)];
         }
-        C y[2][N];
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            if (w == 1 && wp.nw == 1) break;
-            const int k = wp.k[w];
+        // wave number k: spectrum -> y modes, divided, -> spectrum
+        auto one = [&](int k, const T* Mfk, const T* Mik, const C* zk, const C* zh, T c, T sn,
+                       C* y) {
             const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
-            const bool pair = c1 >= 0;
-            T v[S], o[S];
+            with_pair(c1 >= 0, [&](auto pc) {
+                constexpr bool PAIR = decltype(pc)::value;
+                constexpr int R = PAIR ? S : N;
+                T v[S], o[S];
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                const C x = w ? unpack_half(zb[j], za[j], wp.c[1], wp.s[1])
-                              : unpack_half(za[j], zb[j], wp.c[0], wp.s[0]);
-                spec_to_coef(x, pair, cn, cp, v[j], v[N + j]);
-            }
-            mix_vec<N, T>(Mf + (size_t)k * S * S, pair, v, o);
+                for (int jj = 0; jj < N; ++jj)
+                    spec_to_coef(unpack_half(zk[jj], zh[jj], c, sn), PAIR, cn, cp, v[jj],
+                                 v[N + jj]);
+                mix_vec<N, T, PAIR>(Mfk, v, o);
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
-                if (q >= N && !pair) break;
-                const int ys = (q % N) * Ny + (q < N ? c0 : c1);
-                o[q] = (xs == zx && ys == zy) ? T(0) : o[q] / -(lam_x + ly[ys]);
-            }
-            mix_vec<N, T>(Mi + (size_t)k * S * S, pair, o, v);
+                for (int q = 0; q < R; ++q) {
+                    const int ys = (q % N) * Ny + (q < N ? c0 : c1);
+                    o[q] = (xs == zx && ys == zy) ? T(0) : -o[q] * recip(lam_x + ly[ys]);
+                }
+                mix_vec<N, T, PAIR>(Mik, o, v);
 #pragma unroll
-            for (int j = 0; j < N; ++j)
-                y[w][j] = coef_to_spec<C>(pair, cn, cp, v[j], pair ? v[N + j] : T(0));
+                for (int jj = 0; jj < N; ++jj)
+                    y[jj] = coef_to_spec<C>(PAIR, cn, cp, v[jj], PAIR ? v[N + jj] : T(0));
+            });
+        };
+        C y0[N], y1[N];
+        one(wp.k0, Mf + (size_t)wp.k0 * S * S, Mi + (size_t)wp.k0 * S * S, za, zb, wp.c0, wp.s0, y0);
+        if (wp.nw == 2) {
+            one(wp.k1, Mf + (size_t)wp.k1 * S * S, Mi + (size_t)wp.k1 * S * S, zb, za, wp.c1, wp.s1, y1);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) y1[jj] = y0[jj];
         }
-        if (wp.nw == 1) {
 #pragma unroll
-            for (int j = 0; j < N; ++j) y[1][j] = y[0][j];
-        }
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            Z[(m + NXn * j) * H + p] = pack_half(y[0][j], y[1][j], wp.c[0], wp.s[0]);
-            if (p > 0 && wp.nw == 2)
-                Z[(m + NXn * j) * H + wp.k[1]] = pack_half(y[1][j], y[0][j], wp.c[1], wp.s[1]);
+        for (int jj = 0; jj < N; ++jj) {
+            L[TL::at(jj, 0, w, a)] = pack_half(y0[jj], y1[jj], wp.c0, wp.s0);
+            L[TL::at(jj, 1, w, a)] = pack_half(y1[jj], y0[jj], wp.c1, wp.s1);
         }
     }
+    __syncthreads();
+    spec_store<N, T>(Z, H, P, p0, a0, (int)NXn, 0, NXn, L);
 }
 
 // Spectral division of the dense path: C[a + mx b] /= -(lam_x[a] + lam_y[b])
@@ -775,11 +878,13 @@ template <class T>
 hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, const int* cols, const T* Mf,
                                 const void* X, T* u1, hipStream_t s) {
     using C = typename CplxOf<T>::type;
-    const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), dim3(Nx / 4 + 1, nb),
-                                        dim3(kPwThreads),
-                                        0, s, Nx, Ny, cols, Mf, cn, cp, (const C*)X, u1));
+    DG_DISPATCH_N(n, {
+        using TL = SpecTile<NN, T>;
+        const dim3 grid((Nx / 4 + 1 + TL::TP - 1) / TL::TP, ((Ny + 63) / 64) * NN);
+        hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), grid, dim3(TL::THREADS), 0, s, Nx, Ny,
+                           cols, Mf, cn, cp, (const C*)X, u1);
+    });
     return hipGetLastError();
 }
 
@@ -787,11 +892,13 @@ template <class T>
 hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, const int* cols, const T* Mi,
                                 const T* u1, void* X, hipStream_t s) {
     using C = typename CplxOf<T>::type;
-    const int nb = pw_blocks((long)Ny * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), dim3(Nx / 4 + 1, nb),
-                                        dim3(kPwThreads),
-                                        0, s, Nx, Ny, cols, Mi, cn, cp, u1, (C*)X));
+    DG_DISPATCH_N(n, {
+        using TL = SpecTile<NN, T>;
+        const dim3 grid((Nx / 4 + 1 + TL::TP - 1) / TL::TP, ((Ny + 63) / 64) * NN);
+        hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), grid, dim3(TL::THREADS), 0, s, Nx, Ny,
+                           cols, Mi, cn, cp, u1, (C*)X);
+    });
     return hipGetLastError();
 }
 
@@ -800,11 +907,13 @@ hipError_t launch_fft_mix_y(int n, int Nx, int Ny, const int* cols, const T* Mf,
                             const T* Mi, const T* lx, const T* ly, int zx, int zy, void* Y,
                             hipStream_t s) {
     using C = typename CplxOf<T>::type;
-    const int nb = pw_blocks((long)Nx * n, pointwise_block_cap());
     const T cn = T(1.0 / std::sqrt((double)Ny)), cp = T(std::sqrt(2.0 / Ny));
-    DG_DISPATCH_N(n, hipLaunchKernelGGL((k_fft_mix_y<NN, T>), dim3(Ny / 4 + 1, nb),
-                                        dim3(kPwThreads), 0,
-                                        s, Nx, Ny, cols, Mf, Mi, lx, ly, zx, zy, cn, cp, (C*)Y));
+    DG_DISPATCH_N(n, {
+        using TL = SpecTile<NN, T>;
+        const dim3 grid((Ny / 4 + 1 + TL::TP - 1) / TL::TP, ((long)Nx * NN + 63) / 64);
+        hipLaunchKernelGGL((k_fft_mix_y<NN, T>), grid, dim3(TL::THREADS), 0, s, Nx, Ny, cols,
+                           Mf, Mi, lx, ly, zx, zy, cn, cp, (C*)Y);
+    });
     return hipGetLastError();
 }
 

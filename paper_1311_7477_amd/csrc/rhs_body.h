@@ -246,12 +246,21 @@ __device__ __forceinline__ void lds_get_row(const T* lds, const Ctx<N, WAVES>& c
 // eq. J); one of them alone gives a single form.  With VISC the kernel
 // forms R = -J(f, g) + D Lap_h g and stores a * wn + b * (g + dt R)
 // (SSP-RK3 stage combination; wn may be null when a == 0).
+//
+// b = c2 Dx f g - c1 f Dx g needs only x operators, so it is formed before
+// the first barrier and staged with f and g: one column phase then
+// evaluates every y operator (Dy f, Dy g, Dy b and the viscous Ly g) and one
+// transpose brings back Dy f, Dy g and the sum D Ly g - scale Dy b
+// (three barriers in all).  The two halo waves (first and last cell row of
+// the tile) only feed their neighbours' y operators with rows of f, g and
+// b: they skip the column phase and everything after it (a wave-uniform
+// branch).
 
 template <int N, int WAVES, bool VISC>
 struct RhsLds {
     double A[Tile<N, WAVES>::LDS_FIELD];
     double B[Tile<N, WAVES>::LDS_FIELD];
-    double C[VISC ? Tile<N, WAVES>::LDS_FIELD : 1];
+    double C[Tile<N, WAVES>::LDS_FIELD];
 };
 
 template <int N, int WAVES, bool VISC, bool DIR = false>
@@ -264,75 +273,88 @@ __device__ __forceinline__ void rhs_body(
     double* lB = L.B;
     double* lC = L.C;
     const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks, b);
+    const bool inner = c.wave > 0 && c.wave < WAVES - 1;   // wave-uniform
 
     double F[N], G[N];
     load_vec(f, c.row, F);
     load_vec(gg, c.row, G);
 
-    double DxF[N], DxG[N], LxG[N], DyF[N], DyG[N], LyG[N];
+    double DxF[N], DxG[N], LxG[N];
     row_op<N, double, DIR>(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
     row_op<N, double, DIR>(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
-    if (VISC && !DIR) row_op(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.ihx2, LxG);
-    if (VISC && DIR)
-        row_ldg(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.L0Bx, k.eRBx, k.lLBx, k.ihx2,
-                LxG, c.at_l, c.at_r);
-
-    lds_put_row(lA, c, F);
-    lds_put_row(lB, c, G);
-    __syncthreads();
     {
-        double cF[N], cG[N], cL[N];
-        col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
-        col_op<N, WAVES, double, DIR>(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
-        if (VISC && !DIR) col_op(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.ihy2, cL);
-        if (VISC && DIR)
-            col_ldg(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.L0By, k.eRBy, k.lLBy, k.ihy2, cL);
-        __syncthreads();
-        lds_put_col(lA, c, cF);
-        lds_put_col(lB, c, cG);
-        if (VISC) lds_put_col(lC, c, cL);
+        double Bv[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) Bv[i] = ra.c2 * (DxF[i] * G[i]) - ra.c1 * (F[i] * DxG[i]);
+        lds_put_row(lA, c, F);
+        lds_put_row(lB, c, G);
+        lds_put_row(lC, c, Bv);
+    }
+    if (VISC && inner) {
+        if (DIR)
+            row_ldg(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.L0Bx, k.eRBx, k.lLBx, k.ihx2,
+                    LxG, c.at_l, c.at_r);
+        else
+            row_op(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.ihx2, LxG);
     }
     __syncthreads();
+
+    // column phase: Dy f, Dy g, Dy b (and Ly g) on this lane's column; the
+    // barriers stay in uniform control flow, the halo waves just idle
+    double cF[N], cG[N], cq[N];
+    if (inner) {
+        col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cF);
+        col_op<N, WAVES, double, DIR>(lB, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cG);
+        col_op<N, WAVES, double, DIR>(lC, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cq);
+        if (VISC) {
+            double cL[N];
+            if (DIR)
+                col_ldg(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.L0By, k.eRBy, k.lLBy, k.ihy2,
+                        cL);
+            else
+                col_op(lB, c, k.L0y, k.eRy, k.lR, k.eL, k.lLy, k.ihy2, cL);
+#pragma unroll
+            for (int m = 0; m < N; ++m) cq[m] = ra.D * cL[m] - ra.scale * cq[m];
+        }
+    }
+    __syncthreads();
+    if (inner) {
+        lds_put_col(lA, c, cF);
+        lds_put_col(lB, c, cG);
+        lds_put_col(lC, c, cq);
+    }
+    __syncthreads();
+    if (!inner) return;        // no barrier follows
+    double DyF[N], DyG[N], Q[N];
     lds_get_row(lA, c, DyF);
     lds_get_row(lB, c, DyG);
-    if (VISC) lds_get_row(lC, c, LyG);
-    __syncthreads();
+    lds_get_row(lC, c, Q);
 
-    double J[N], A[N], B[N];
+    double J[N], A[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         J[i] = ra.c0 * (DxF[i] * DyG[i] - DyF[i] * DxG[i]);
         A[i] = ra.c1 * (F[i] * DyG[i]) - ra.c2 * (DyF[i] * G[i]);
-        B[i] = ra.c2 * (DxF[i] * G[i]) - ra.c1 * (F[i] * DxG[i]);
     }
-    double DxA[N], DyB[N];
+    double DxA[N];
     row_op<N, double, DIR>(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA, c.at_l, c.at_r);
-    lds_put_row(lA, c, B);
-    __syncthreads();
-    {
-        double cb[N];
-        col_op<N, WAVES, double, DIR>(lA, c, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihy, cb);
-        __syncthreads();
-        lds_put_col(lA, c, cb);
-    }
-    __syncthreads();
-    lds_get_row(lA, c, DyB);
 
     if (!c.interior) return;
     double o[N];
     if (VISC) {
+        // Q = D Ly g - scale Dy b
         double wnr[N];
         if (ra.a != 0.0) load_vec(wn, c.row, wnr);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const double Jv = ra.scale * (J[i] + DxA[i] + DyB[i]);
-            const double R = ra.D * (LxG[i] + LyG[i]) - Jv;
+            const double R = (ra.D * LxG[i] + Q[i]) - ra.scale * (J[i] + DxA[i]);
             const double s = ra.b * (G[i] + ra.dt * R);
             o[i] = ra.only_r ? R : ((ra.a != 0.0) ? ra.a * wnr[i] + s : s);
         }
     } else {
+        // Q = Dy b
 #pragma unroll
-        for (int i = 0; i < N; ++i) o[i] = ra.scale * (J[i] + DxA[i] + DyB[i]);
+        for (int i = 0; i < N; ++i) o[i] = ra.scale * (J[i] + DxA[i] + Q[i]);
     }
     store_vec(out, c.row, o);
 }

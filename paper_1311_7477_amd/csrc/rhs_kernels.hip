@@ -6,7 +6,7 @@
 namespace dgk {
 
 template <int N, int WAVES, bool VISC, bool DIR>
-__global__ __launch_bounds__(64 * WAVES) void k_rhs(
+__global__ __launch_bounds__(64 * WAVES, 4) void k_rhs(
     Geom g, int tilesX, int nblocks, OpConst<double> k,
     const double* __restrict__ f, const double* __restrict__ gg,
     const double* __restrict__ wn, double* __restrict__ out, RhsArgs ra) {
