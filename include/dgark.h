@@ -184,7 +184,8 @@ int  dg_grid_tune(dg_grid* grid, const double* omega, int reps, double* ms_out5,
  * DG_PREC_MIXED mode, plus (DG_WS_FD) the preconditioner's z vector, two
  * node-plane fields and per axis the factored eigenbasis in FP64 and FP32
  * (the N x N cell Fourier basis, 2 (N/2 + 1) mixing blocks of 2n x 2n and
- * n N eigenvalues; one set when the axes agree; rocBLAS and, on the FFT
+ * n N eigenvalues; one set when the axes agree), a copy of omega and three
+ * sets of device scalars for RK steps queued ahead (rocBLAS and, on the FFT
  * path, rocFFT keep their own work buffers on top: dg_workspace_held_bytes
  * counts them once the workspace exists).  On a grid
  * with a Dirichlet axis the preconditioner holds instead two dense work
@@ -294,7 +295,10 @@ int  dg_grid_axis_operator(const dg_grid* grid, int axis, double* L);
 /* ------------------------------------------------------------ stepping --- */
 /* History of Poisson solutions used for the CG initial guess: the
  * linear-in-time extrapolation of the two most recent solves (Sec. 6,
- * initial guess from the last two solutions).  Owns three device fields. */
+ * initial guess from the last two solutions).  Owns five device fields:
+ * two hold the history, three take the solves of a step (so a step queued
+ * ahead of its convergence checks can be taken again from the history it
+ * started from). */
 int  dg_state_create(const dg_grid* grid, double t0, dg_state** out);
 void dg_state_destroy(dg_state* st);                 /* NULL-safe */
 /* Device pointer to the most recent psi (NULL before the first solve). */
@@ -308,7 +312,12 @@ double dg_state_time(const dg_state* st);
  * by CG (opts->cg) from the extrapolated guess, then one fused kernel forms
  * the bracket, the viscous term and the stage combination.  omega is updated
  * in place; state->t advances by dt.  Synchronises the stream.  Returns
- * DG_E_NOCONV if a solve hit max_iter (the step is still completed). */
+ * DG_E_NOCONV if a solve hit max_iter (the step is still completed).
+ * With DG_PRECOND_FD in FP64 the three stages are queued with one PCG
+ * iteration each and checked once at the end of the step (one host round
+ * trip per step); if a stage has not converged, omega and the psi history
+ * are restored and the step is taken again with every solve polled after
+ * each iteration -- the result is the same either way. */
 int  dg_rk_step(const dg_grid* grid, double* omega, dg_state* state,
                 const dg_step_opts* opts, dg_step_stats* stats,
                 dg_workspace* ws, void* stream);

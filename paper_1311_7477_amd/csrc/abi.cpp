@@ -55,7 +55,7 @@ void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
         }
     }
     int fr = 0;
-    while (fr == st->ia || fr == st->ib) ++fr;
+    while (fr == st->ia || fr == st->ib || fr == st->resv[0] || fr == st->resv[1]) ++fr;
     *x = st->buf[fr];
     *xi = fr;
 }
@@ -130,7 +130,8 @@ size_t ws_bytes(const dg_grid* g, int mode) {
     b += (size_t)blocks * 4 * sizeof(double);           // partials
     b += sizeof(CgScalars) + kCntCount * sizeof(unsigned) + 4 * sizeof(double);
     if ((mode & ~DG_WS_FD) == DG_PREC_MIXED) b += 3 * L * sizeof(float);
-    if (mode & DG_WS_FD) b += L * sizeof(double) + fd_bytes(g);
+    if (mode & DG_WS_FD)
+        b += L * sizeof(double) + F + 3 * sizeof(CgScalars) + fd_bytes(g);   // z, wbak, sc3
     return b;
 }
 
@@ -314,9 +315,10 @@ int cg_mixed(const dg_grid* g, const double* omega, double* x, const double* pa,
     return DG_OK;
 }
 
-// z = M r on node planes in the precision T, then z and <r, z>_W in FP64.
+// z = M r on node planes in the precision T, then z and <r, z>_W in FP64
+// (device scalars in d.sc).
 template <class T>
-int precond_step(const dg_grid* g, dg_workspace* ws, hipStream_t s) {
+int precond_step(const dg_grid* g, dg_workspace* ws, const DevScratch& d, hipStream_t s) {
     T* planes = reinterpret_cast<T*>(ws->fd->img0);
     const int layout = fd_layout(ws->fd);
     const bool dense = layout == kFdDense;
@@ -328,48 +330,54 @@ int precond_step(const dg_grid* g, dg_workspace* ws, hipStream_t s) {
     int rc = fd_apply_image(ws->fd, sizeof(T) == sizeof(float), s);
     if (rc != DG_OK) return rc;
     e = layout == kFdFolded
-            ? launch_from_planes_fold<T>(g->geom, g->k64, planes, Kx, ws->z, ws->r, &ws->d, s)
-            : launch_from_image_dot<T>(g->geom, g->k64, planes, dense, ws->z, ws->r, ws->d, s);
+            ? launch_from_planes_fold<T>(g->geom, g->k64, planes, Kx, ws->z, ws->r, &d, s)
+            : launch_from_image_dot<T>(g->geom, g->k64, planes, dense, ws->z, ws->r, d, s);
     if (e != hipSuccess) return hip_fail(e, "image conversion launch");
     return DG_OK;
 }
 
-// FP64 CG preconditioned by the fast-diagonalisation inverse of -Lap_h:
-// z = M r on node planes (cell Fourier transforms + per-wave-number mixing),
-// then the usual direction / residual kernels with p built from z.  The host
-// polls after every iteration (an exact preconditioner converges in one or
-// two).  fp32: M is applied in FP32 (the mixed-precision form: the solve's
-// bulk work in FP32, every residual, solution and step length in FP64, so
-// the FP64 iteration refines the FP32 solves; about one extra iteration).
-int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
-           double ca, const double* pb, double cb, const dg_cg_opts& o, bool fp32,
-           dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+int pcg_iteration(const dg_grid* g, bool fp32, const DevScratch& d, dg_workspace* ws,
+                  hipStream_t s);
+
+// Queue the setup of a preconditioned solve and `iters` iterations (z = M r
+// on node planes -- cell Fourier transforms + per-wave-number mixing --
+// then the direction / residual kernels with p built from z) on the device
+// scalars d.sc, reading nothing back.  Once the device flag says the solve
+// is done the CG kernels exit at once; the preconditioner's library
+// transforms of a later iteration still run.  fp32: M is applied in FP32
+// (the mixed-precision form: the solve's bulk work in FP32, every residual,
+// solution and step length in FP64, so the FP64 iteration refines the FP32
+// solves).
+int pcg_queue(const dg_grid* g, const double* omega, const double* pa, double ca,
+              const double* pb, double cb, const dg_cg_opts& o, bool fp32, int iters,
+              const DevScratch& d, dg_workspace* ws, hipStream_t s) {
     const double tol2 = o.rtol * o.rtol;
-    hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area,
-                                  tol2, o.max_iter, ws->d, s);
+    hipError_t e = launch_cg_mean(g->geom, g->k64, omega, pa, pb, ca, cb, g->area, tol2,
+                                  o.max_iter, d, s);
     if (e != hipSuccess) return hip_fail(e, "cg mean launch");
-    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, ws->x, ws->r, ws->d, s);
+    e = launch_cg_init(g->geom, g->k64, omega, pa, pb, ca, cb, ws->x, ws->r, d, s);
     if (e != hipSuccess) return hip_fail(e, "cg init launch");
-    int rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
-    if (rc != DG_OK) return rc;
-    CgScalars h = ws->host[2];
-    while (!h.done) {
-        rc = fp32 ? precond_step<float>(g, ws, s) : precond_step<double>(g, ws, s);
+    for (int it = 0; it < iters; ++it) {
+        int rc = pcg_iteration(g, fp32, d, ws, s);
         if (rc != DG_OK) return rc;
-        e = launch_cg_dir<double>(g->geom, g->k64, ws->x, ws->z, ws->p0, ws->p1,
-                                      ws->d.sc, ws->d, s);
-        if (e == hipSuccess)
-            e = launch_cg_res<double>(g->geom, g->k64, ws->r, ws->p0, ws->p1, ws->d.sc,
-                                      ws->d, s);
-        if (e != hipSuccess) return hip_fail(e, "pcg iteration launch");
-        rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
-        if (rc != DG_OK) return rc;
-        h = ws->host[2];
     }
-    e = launch_cg_finish<double>(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area,
-                                 ws->d, s);
-    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
-    HIP_TRY(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+int pcg_iteration(const dg_grid* g, bool fp32, const DevScratch& d, dg_workspace* ws,
+                  hipStream_t s) {
+    int rc = fp32 ? precond_step<float>(g, ws, d, s) : precond_step<double>(g, ws, d, s);
+    if (rc != DG_OK) return rc;
+    hipError_t e = launch_cg_dir<double>(g->geom, g->k64, ws->x, ws->z, ws->p0, ws->p1, d.sc,
+                                         d, s);
+    if (e == hipSuccess)
+        e = launch_cg_res<double>(g->geom, g->k64, ws->r, ws->p0, ws->p1, d.sc, d, s);
+    if (e != hipSuccess) return hip_fail(e, "pcg iteration launch");
+    return DG_OK;
+}
+
+// Fill the solve statistics from final device scalars (host copy h).
+int pcg_result(const CgScalars& h, dg_cg_stats* st) {
     const double rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     if (st) {
         st->iters = h.iter;
@@ -382,6 +390,33 @@ int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
                     "relative residual %.3e%s", h.iter, rel,
                     h.breakdown ? " (breakdown or non-finite data)" : "");
     return DG_OK;
+}
+
+// FP64 CG preconditioned by the fast-diagonalisation inverse of -Lap_h.
+// The first iteration is queued with the setup (an exact preconditioner
+// almost always needs one; if r_0 already met the tolerance its kernels
+// exit at once), then the host reads the device scalars after every
+// iteration: one round trip per iteration.
+int cg_pcg(const dg_grid* g, const double* omega, double* x, const double* pa,
+           double ca, const double* pb, double cb, const dg_cg_opts& o, bool fp32,
+           dg_cg_stats* st, dg_workspace* ws, hipStream_t s) {
+    int rc = pcg_queue(g, omega, pa, ca, pb, cb, o, fp32, 1, ws->d, ws, s);
+    if (rc != DG_OK) return rc;
+    rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+    if (rc != DG_OK) return rc;
+    CgScalars h = ws->host[2];
+    while (!h.done) {
+        rc = pcg_iteration(g, fp32, ws->d, ws, s);
+        if (rc != DG_OK) return rc;
+        rc = read_scalars(ws, ws->d.sc, &ws->host[2], s);
+        if (rc != DG_OK) return rc;
+        h = ws->host[2];
+    }
+    hipError_t e = launch_cg_finish<double>(g->geom, g->k64, ws->x, ws->p0, ws->p1, x, g->area,
+                                            ws->d, s);
+    if (e != hipSuccess) return hip_fail(e, "cg finish launch");
+    HIP_TRY(hipStreamSynchronize(s));
+    return pcg_result(h, st);
 }
 
 int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* pa,
@@ -417,6 +452,29 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
 }  // namespace
 
 namespace dgk {
+int state_create(const dg_grid* g, double t0, int nbuf, dg_state** out) {
+    if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (nbuf != 3 && nbuf != 5) return fail(DG_E_INVAL, "a state holds 3 or 5 buffers");
+    dg_state* st = new (std::nothrow) dg_state;
+    if (!st) return fail(DG_E_NOMEM, "host allocation failed");
+    std::memset(st, 0, sizeof *st);
+    st->n = g->n; st->nx = g->nx; st->ny = g->ny; st->elems = g->elems;
+    st->nbuf = nbuf;
+    st->ia = st->ib = -1;
+    st->resv[0] = st->resv[1] = -1;
+    st->t = t0;
+    for (int i = 0; i < nbuf; ++i) {
+        if (hipMalloc((void**)&st->buf[i], g->elems * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            dg_state_destroy(st);
+            return fail(DG_E_NOMEM, "state allocation failed");
+        }
+    }
+    *out = st;
+    return DG_OK;
+}
+
 int form_coeffs(int form, double* c0, double* c1, double* c2, double* scale) {
     *c0 = *c1 = *c2 = 0.0;
     *scale = 1.0;
@@ -512,8 +570,8 @@ void dg_workspace_destroy(dg_workspace* ws) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ws->device);
     void* bufs[] = {ws->x, ws->r, ws->p0, ws->p1, ws->s1, ws->s2, ws->r32,
-                    ws->q0, ws->q1, ws->z, ws->d.sc, ws->d.counters, ws->d.partials,
-                    ws->d.out3};
+                    ws->q0, ws->q1, ws->z, ws->wbak, ws->sc3, ws->d.sc, ws->d.counters,
+                    ws->d.partials, ws->d.out3};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     fd_destroy(ws->fd);
@@ -563,7 +621,9 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
         ok = alloc((void**)&ws->r32, f32) && alloc((void**)&ws->q0, f32) &&
              alloc((void**)&ws->q1, f32);
     }
-    if (ok && (mode & DG_WS_FD)) ok = alloc((void**)&ws->z, L * sizeof(double));
+    if (ok && (mode & DG_WS_FD))
+        ok = alloc((void**)&ws->z, L * sizeof(double)) && alloc((void**)&ws->wbak, F) &&
+             alloc((void**)&ws->sc3, 3 * sizeof(CgScalars));
     if (ok) ok = hipHostMalloc((void**)&ws->host, 4 * sizeof(CgScalars)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -592,6 +652,7 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     // counters must start at zero (each reduction resets its own)
     e = hipMemset(ws->d.counters, 0, kCntCount * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(ws->d.sc, 0, sizeof(CgScalars));
+    if (e == hipSuccess && ws->sc3) e = hipMemset(ws->sc3, 0, 3 * sizeof(CgScalars));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { dg_workspace_destroy(ws); return hip_fail(e, "workspace init"); }
     if (mode & DG_WS_FD) {
@@ -725,23 +786,7 @@ int dg_cg_solve_poisson(const dg_grid* g, const double* omega, double* psi,
 }
 
 int dg_state_create(const dg_grid* g, double t0, dg_state** out) {
-    if (!g || !out) return fail(DG_E_INVAL, "NULL argument");
-    *out = nullptr;
-    dg_state* st = new (std::nothrow) dg_state;
-    if (!st) return fail(DG_E_NOMEM, "host allocation failed");
-    std::memset(st, 0, sizeof *st);
-    st->n = g->n; st->nx = g->nx; st->ny = g->ny; st->elems = g->elems;
-    st->ia = st->ib = -1;
-    st->t = t0;
-    for (auto& b : st->buf) {
-        if (hipMalloc((void**)&b, g->elems * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            dg_state_destroy(st);
-            return fail(DG_E_NOMEM, "state allocation failed");
-        }
-    }
-    *out = st;
-    return DG_OK;
+    return state_create(g, t0, 5, out);
 }
 
 void dg_state_destroy(dg_state* st) {
@@ -764,6 +809,80 @@ int dg_state_copy_psi(const dg_state* st, double* out, void* stream) {
     return DG_OK;
 }
 
+namespace {
+
+constexpr int kRedo = 1;   // a queued step must be taken again synchronously
+
+// One SSP-RK3 step with the three preconditioned stage solves queued ahead
+// of any convergence check: each stage runs the setup, one PCG iteration
+// (the exact preconditioner's usual count), the finish and the fused RHS
+// kernel, on its own device scalars; the host reads the three stages'
+// scalars once, at the end.  omega is saved first and the psi history the
+// step starts from stays in the state's reserved buffers, so when a stage
+// has not converged (the first step from a zero guess, say) both are
+// restored and kRedo is returned: the caller takes the step again with the
+// solves polled after every iteration.
+int rk_step_queued(const dg_grid* g, double* omega, dg_state* st, const dg_step_opts* opts,
+                   const double (&fc)[4], dg_step_stats* stats, dg_workspace* ws,
+                   hipStream_t s) {
+    const double dt = opts->dt, t = st->t;
+    const double ts[3] = {t, t + dt, t + 0.5 * dt};
+    const double ra[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double rb[3] = {1.0, 0.25, 2.0 / 3.0};
+    double* win[3] = {omega, ws->s1, ws->s2};
+    double* wout[3] = {ws->s1, ws->s2, omega};
+    const dg_state saved = *st;
+    st->resv[0] = st->ia;
+    st->resv[1] = st->ib;
+    const bool timing = opts->record_times != 0;
+    HIP_TRY(hipMemcpyAsync(ws->wbak, omega, g->elems * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    if (timing) HIP_TRY(hipEventRecord(ws->tev[0], s));
+    for (int k = 0; k < 3; ++k) {
+        const double* pa;
+        const double* pb;
+        double ca, cb;
+        double* x;
+        int fr;
+        state_guess(st, ts[k], &pa, &ca, &pb, &cb, &x, &fr);
+        DevScratch d = ws->d;
+        d.sc = ws->sc3 + k;
+        int rc = pcg_queue(g, win[k], pa, ca, pb, cb, opts->cg, false, 1, d, ws, s);
+        if (rc != DG_OK) return rc;
+        hipError_t e = launch_cg_finish<double>(g->geom, g->k64, ws->x, ws->p0, ws->p1, x,
+                                                g->area, d, s);
+        if (e != hipSuccess) return hip_fail(e, "cg finish launch");
+        state_push(st, fr, ts[k]);
+        RhsParams p{fc[0], fc[1], fc[2], fc[3], opts->D, dt, ra[k], rb[k], 0};
+        e = launch_rhs(g->geom, g->k64, x, win[k], k ? omega : nullptr, wout[k], p, true, s);
+        if (e != hipSuccess) return hip_fail(e, "rhs launch");
+        if (timing) HIP_TRY(hipEventRecord(ws->tev[k + 1], s));
+    }
+    HIP_TRY(hipMemcpyAsync(ws->host, ws->sc3, 3 * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) ok = ok && ws->host[k].converged;
+    st->resv[0] = st->resv[1] = -1;
+    if (!ok) {
+        HIP_TRY(hipMemcpyAsync(omega, ws->wbak, g->elems * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+        *st = saved;
+        return kRedo;
+    }
+    st->t = t + dt;
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        for (int k = 0; k < 3; ++k) stats->cg_iters[k] = ws->host[k].iter;
+        stats->converged = 1;
+        if (timing)
+            for (int k = 0; k < 3; ++k)
+                HIP_TRY(hipEventElapsedTime(&stats->stage_ms[k], ws->tev[k], ws->tev[k + 1]));
+    }
+    return DG_OK;
+}
+
+}  // namespace
+
 int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
                const dg_step_opts* opts, dg_step_stats* stats, dg_workspace* ws,
                void* stream) {
@@ -778,6 +897,12 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
     rc = form_coeffs(opts->form, &fc[0], &fc[1], &fc[2], &fc[3]);
     if (rc != DG_OK) return rc;
     hipStream_t s = as_stream(stream);
+    // FP64 preconditioned solves: queue the whole step, verify once
+    if (opts->cg.precond == DG_PRECOND_FD && opts->cg.precision == DG_PREC_FP64 && ws->fd &&
+        ws->sc3 && st->nbuf == 5 && opts->cg.rtol > 0 && opts->cg.max_iter >= 1) {
+        rc = rk_step_queued(g, omega, st, opts, fc, stats, ws, s);
+        if (rc != kRedo) return rc;
+    }
     const double dt = opts->dt, t = st->t;
     const double ts[3] = {t, t + dt, t + 0.5 * dt};
     const double ra[3] = {0.0, 0.75, 1.0 / 3.0};

@@ -28,6 +28,8 @@ struct dg_workspace {
     double *s1, *s2;           // RK stage fields, canonical layout
     float *r32, *q0, *q1;      // mixed precision: FP32 residual and directions
     double* z;                 // preconditioned residual (DG_WS_FD workspaces)
+    double* wbak;              // DG_WS_FD: omega at the start of a queued RK step
+    CgScalars* sc3;            // DG_WS_FD: device scalars of the three queued stage solves
     dgk::FdDevice* fd;         // fast-diagonalisation preconditioner, or NULL
     DevScratch d;
     CgScalars* host;           // pinned, 4 slots (2 poll slots + 2 spare)
@@ -45,8 +47,11 @@ struct dg_workspace {
 struct dg_state {
     int n, nx, ny;
     size_t elems;
-    double* buf[3];
+    double* buf[5];            // nbuf of them allocated
+    int nbuf;                  // 3, or 5 so that a queued RK step keeps the
+                               // history it started from until it is verified
     int ia, ib;                // indices of the newest / previous solution (-1 none)
+    int resv[2];               // buffers a new solve must not take (-1 none)
     double ta, tb, t;
     int count;
 };
@@ -61,6 +66,8 @@ void state_guess(const dg_state* st, double ts, const double** pa, double* ca,
                  const double** pb, double* cb, double** x, int* xi);
 // Record that buffer xi now holds the solve at time ts.
 void state_push(dg_state* st, int xi, double ts);
+// A state with nbuf (3 or 5) history buffers; dg_state_create makes 5.
+int state_create(const dg_grid* g, double t0, int nbuf, dg_state** out);
 // DG_E_UNSUPPORTED for an operation that needs a periodic grid.
 int periodic_only(const char* what);
 // Bracket coefficients of a DG_FORM_* (Sec. 2 eq. J): c0 J++ + c1 J+x +

@@ -306,7 +306,7 @@ int dg_batch_attach(dg_batch* b, const dg_grid* g, double* omega, double dt,
     Slot& sl = b->slots[i];
     int rc = dg_workspace_create(g, DG_PREC_FP64, &sl.ws);
     if (rc != DG_OK) return rc;
-    rc = dg_state_create(g, t0, &sl.st);
+    rc = state_create(g, t0, 3, &sl.st);    // batched steps are never queued ahead
     if (rc != DG_OK) { dg_workspace_destroy(sl.ws); sl.ws = nullptr; return rc; }
     sl.used = true;
     sl.grid = g;

@@ -43,6 +43,11 @@ import numpy as np
 from . import dg, inputs
 
 
+# device fields a stream-served request holds besides its workspace: the
+# five of its dg_state and omega
+STATE_FIELDS = 6
+
+
 @dataclass
 class Request:
     rid: int
@@ -257,10 +262,10 @@ class StreamServer(Server):
 
     def request_bytes(self, req: Request) -> int:
         """Estimate before admission: workspace (with the preconditioner),
-        state (three fields) and omega; admission replaces it by the bytes
+        state (five fields) and omega; admission replaces it by the bytes
         the workspace reports once created."""
         g = dg.Grid(req.n, req.N, req.N)
-        return g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD) + 4 * g.elems * 8
+        return g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD) + STATE_FIELDS * g.elems * 8
 
     def admit(self, req: Request, now: float):
         import torch
@@ -275,7 +280,7 @@ class StreamServer(Server):
             if e.code != dg.DG_E_NOMEM or not self.active:
                 raise
             return False              # the device is full now: retry later
-        held = req.ws.held_bytes() + 4 * req.grid.elems * 8
+        held = req.ws.held_bytes() + STATE_FIELDS * req.grid.elems * 8
         self.shape_bytes[key] = held
         if self.used + held > self.budget:
             req.bytes = held

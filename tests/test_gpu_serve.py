@@ -98,7 +98,7 @@ def test_stream_server_budget_queues(serve):
     for r in reqs:
         g = dg.Grid(r.n, r.N, r.N)
         held.append(dg.Workspace(g, dg.DG_PREC_FP64 | dg.DG_WS_FD).held_bytes()
-                    + 4 * g.elems * 8)
+                    + serve.STATE_FIELDS * g.elems * 8)
     biggest = max(held)
     assert 2 * min(held) > biggest
     srv = serve.StreamServer(capacity=8, hbm_budget=biggest, workers=2)
