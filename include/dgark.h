@@ -116,7 +116,10 @@ typedef struct {
 typedef struct {
     int   cg_iters[3];      /* CG operator applications of each stage's solve */
     float stage_ms[3];      /* device time of each stage (solve + RHS), if recorded */
-    int   converged;        /* 1 if all three solves converged */
+    int   converged;        /* 1 if all three solves converged; 2 if they all
+                               stopped but one only at the attainable FP64
+                               accuracy (dg_cg_stats.converged == 2, mixed
+                               mode); 0 if one did not converge */
 } dg_step_stats;
 
 /* Text of the last error on this thread ("" if none). */

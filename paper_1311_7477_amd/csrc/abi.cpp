@@ -912,7 +912,7 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
     const bool timing = opts->record_times != 0;
     int result = DG_OK;
     if (stats) std::memset(stats, 0, sizeof *stats);
-    bool all_conv = true;
+    bool all_conv = true, stalled = false;
     if (timing) HIP_TRY(hipEventRecord(ws->tev[0], s));
     for (int k = 0; k < 3; ++k) {
         // guess: linear extrapolation in time through the two newest solves
@@ -926,6 +926,7 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
         rc = cg_dispatch(g, win[k], x, pa, ca, pb, cb, &opts->cg, &cs, ws, s);
         if (rc == DG_E_NOCONV) { result = DG_E_NOCONV; all_conv = false; }
         else if (rc != DG_OK) return rc;
+        if (cs.converged == 2) stalled = true;
         state_push(st, fr, ts[k]);
         RhsParams p{fc[0], fc[1], fc[2], fc[3], opts->D, dt, ra[k], rb[k], 0};
         hipError_t e = launch_rhs(g->geom, g->k64, x, win[k], k ? omega : nullptr,
@@ -943,7 +944,7 @@ int dg_rk_step(const dg_grid* g, double* omega, dg_state* st,
             if (stats) stats->stage_ms[k] = ms;
         }
     }
-    if (stats) stats->converged = all_conv ? 1 : 0;
+    if (stats) stats->converged = all_conv ? (stalled ? 2 : 1) : 0;
     if (result != DG_OK) return fail(result, "a stage solve did not converge");
     return DG_OK;
 }

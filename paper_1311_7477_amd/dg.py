@@ -366,6 +366,7 @@ class StepResult:
     cg_iters: tuple
     stage_ms: tuple
     converged: bool
+    stalled: bool = False     # a mixed-mode solve stopped at the attainable FP64 accuracy
 
 
 def rk_step(grid: Grid, omega, state: State, ws: Workspace, dt, D,
@@ -376,7 +377,8 @@ def rk_step(grid: Grid, omega, state: State, ws: Workspace, dt, D,
     _check(lib().dg_rk_step(grid.handle, _field(omega, grid, "omega"), state.handle,
                             ctypes.byref(so), ctypes.byref(st), ws.handle, _stream()),
            allow=(DG_E_NOCONV,))
-    return StepResult(tuple(st.cg_iters), tuple(st.stage_ms), bool(st.converged))
+    return StepResult(tuple(st.cg_iters), tuple(st.stage_ms), bool(st.converged),
+                      st.converged == 2)
 
 
 class AbState:
@@ -419,7 +421,8 @@ def ab_step(grid: Grid, omega, ab: AbState, ws: Workspace, dt, D, opts: CgOpts =
     _check(lib().dg_ab_step(grid.handle, _field(omega, grid, "omega"), ab.handle,
                             ctypes.byref(so), ctypes.byref(st), ws.handle, _stream()),
            allow=(DG_E_NOCONV,))
-    return StepResult(tuple(st.cg_iters), tuple(st.stage_ms), bool(st.converged))
+    return StepResult(tuple(st.cg_iters), tuple(st.stage_ms), bool(st.converged),
+                      st.converged == 2)
 
 
 def invariants(grid: Grid, omega, psi, ws: Workspace):
