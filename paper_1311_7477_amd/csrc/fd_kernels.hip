@@ -481,21 +481,34 @@ __device__ __forceinline__ void xcd_pair_block(int& pc, int& rb) {
 // and stores move runs of TP consecutive columns of one row (64 bytes); in
 // the compute phase wave w owns pair p0 + w, so its mixing blocks come in
 // through scalar loads, and lane a the row coordinate a0 + a, so the real
-// fields it reads or writes are 64 consecutive values.  Each run of 64
-// values of a is padded so that the 16 lanes an LDS cycle serves during the
-// loads (4 pairs x 4 values of a in FP64) hit different banks.
+// fields it reads or writes are 64 consecutive values.  In the load and
+// store phases a thread's element e runs over (pair, low bit of a, s, rest
+// of a, row i), pair fastest; with runs of 64 values padded to 66 the lanes
+// one LDS cycle serves (16 of 16-byte or 32 of 8-byte values) then fall in
+// distinct banks.
 template <int N, class T>
 struct SpecTile {
     using C = typename CplxOf<T>::type;
     static constexpr int TP = 64 / (int)sizeof(C);          // 4 (FP64) or 8 (FP32)
     static constexpr int THREADS = 64 * TP;   // = 2048 / sizeof(T), the launch bound
     static_assert(THREADS == 2048 / (int)sizeof(T), "launch bound of the mixing kernels");
-    static constexpr int RS = sizeof(C) == 16 ? 68 : 66;    // padded run of 64 values
+    static constexpr int RS = 66;                            // padded run of 64 values
     static constexpr int SIZE = N * 2 * TP * RS;
     __device__ static constexpr int at(int i, int s, int p, int a) {
         return ((i * 2 + s) * TP + p) * RS + a;
     }
 };
+
+// Element e of a tile in the load / store phases: pair p (fastest), low bit
+// of a, s, a / 2, row i.
+template <int TP>
+__device__ __forceinline__ void spec_elem(int e, int& p, int& s, int& a, int& i) {
+    p = e % TP;
+    const int al = (e / TP) & 1;
+    s = (e / (2 * TP)) & 1;
+    a = 2 * ((e / (4 * TP)) & 31) + al;
+    i = e / (4 * TP * 32);
+}
 
 // Load the block's tile: row(a, i) = base + a + stride * i for a < A, pairs
 // p < P (entries outside stay zero).  Every thread issues its 2n loads
@@ -511,8 +524,8 @@ __device__ __forceinline__ void spec_load(const typename CplxOf<T>::type* __rest
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
         const int e = threadIdx.x + it * TL::THREADS;
-        const int p = e % TL::TP, s = (e / TL::TP) & 1;
-        const int a = (e / (2 * TL::TP)) & 63, i = e / (2 * TL::TP * 64);
+        int p, s, a, i;
+        spec_elem<TL::TP>(e, p, s, a, i);
         const int pp = p0 + p;
         v[it].x = T(0);
         v[it].y = T(0);
@@ -524,8 +537,8 @@ __device__ __forceinline__ void spec_load(const typename CplxOf<T>::type* __rest
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
         const int e = threadIdx.x + it * TL::THREADS;
-        const int p = e % TL::TP, s = (e / TL::TP) & 1;
-        const int a = (e / (2 * TL::TP)) & 63, i = e / (2 * TL::TP * 64);
+        int p, s, a, i;
+        spec_elem<TL::TP>(e, p, s, a, i);
         L[TL::at(i, s, p, a)] = v[it];
     }
 }
@@ -541,8 +554,8 @@ __device__ __forceinline__ void spec_store(typename CplxOf<T>::type* __restrict_
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
         const int e = threadIdx.x + it * TL::THREADS;
-        const int p = e % TL::TP, s = (e / TL::TP) & 1;
-        const int a = (e / (2 * TL::TP)) & 63, i = e / (2 * TL::TP * 64);
+        int p, s, a, i;
+        spec_elem<TL::TP>(e, p, s, a, i);
         const int pp = p0 + p;
         if (pp >= P || a0 + a >= A) continue;
         if (s && (pp == 0 || H - pp == pp)) continue;
