@@ -53,6 +53,15 @@ __device__ __forceinline__ void store_vec(T* __restrict__ f, long off,
 // write-back or invalidate is needed because only atomics carry data
 // between blocks; results for the next kernel are ordinary stores made
 // visible by the kernel boundary.
+//
+// The guarantee relied on: s_waitcnt with every counter at zero returns only
+// after the wave's agent-scope atomic stores have been performed at the
+// device's point of coherence, so they precede the ticket's atomic add there;
+// the last block's agent-scope atomic loads read that point.  This is the
+// instruction sequence the memory model's agent-scope release / acquire
+// lowering emits for atomic data on this target; the L2 write-back /
+// invalidate such a release / acquire would add concerns non-atomic data,
+// which this reduction never passes between blocks.
 // b is the block's index among the nblocks blocks of this reduction (its
 // partial slot).  Returns true in the last block, where tot[] holds the sums.
 // ---------------------------------------------------------------------------
