@@ -465,6 +465,14 @@ __device__ __forceinline__ void cg_init_body(
 //   alpha_k = <r,r>_W / <p_k, q>_W.
 // p is double-buffered (pin -> pout) because halo cells read p_{k-1} of the
 // neighbouring tiles while p_k is written.  q is applied to p_k as stored.
+// FP64 directions update x every other iteration: at odd k the update waits;
+// at even k the cell first reads p_{k-2} from pout (its own cell, before p_k
+// replaces it) and applies alpha_{k-2} p_{k-2}, then alpha_{k-1} p_{k-1} --
+// the same two roundings in the same order as one update per iteration, so x
+// is unchanged bit for bit, while x is read and written half as often.  The
+// updates still missing when the solve stops are sc->pending (0, 1 or 2; the
+// finish kernel applies them).  FP32-stored directions keep one update per
+// iteration (their residual replacement needs x current).
 template <int N, class S, int WV, bool DIR = false, bool ISO = false>
 __device__ __forceinline__ void cg_dir_body(
     int b, Geom g, int tilesX, int nblocks, const OpConst<double>& k,
@@ -473,31 +481,48 @@ __device__ __forceinline__ void cg_dir_body(
     YFaces<N, double, WV>& lds) {
     if (sc->done) return;
     // iteration k reads p_{k-1} from buffer k mod 2 and writes p_k to the other
-    const S* pin = (sc->iter & 1) ? p1 : p0;
-    S* pout = (sc->iter & 1) ? p0 : p1;
+    const int it = sc->iter;
+    const S* pin = (it & 1) ? p1 : p0;
+    S* pout = (it & 1) ? p0 : p1;
+    constexpr bool kPair = !kStoredLow<S>;
+    const bool upd_x = !kPair || !(it & 1);
     const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
-    // first = 1: p = r; otherwise x += alpha p_old, p = r + beta p_old
+    // first = 1: p = r; otherwise x += alpha p_old (at even k also the
+    // update before it), p = r + beta p_old
     const int first = sc->first;
     const double alpha = sc->alpha;
+    const double alpha_prev = sc->alpha_prev;
     SrcDirection<N, S> src{r, pin, sc->beta, sc->cr, first == 1};
     double p[N * N], q[N * N], rv[N * N];
     if (c.active) {
-        ld_l64<N>(r, c.self, p);
-#pragma unroll
-        for (int e = 0; e < N * N; ++e) rv[e] = p[e];
         if (first != 1) {
             double po[N * N];
             ld_l64<N>(pin, c.self, po);
+            // x first, so that at most three cell vectors are live at once
+            if (upd_x) {
+                double xv[N * N];
+                ld_l64<N>(x, c.self, xv);
+                if (kPair) {
+                    double pp[N * N];
+                    ld_l64<N>(pout, c.self, pp);
+#pragma unroll
+                    for (int e = 0; e < N * N; ++e) xv[e] = fmx(alpha_prev, pp[e], xv[e]);
+                }
+#pragma unroll
+                for (int e = 0; e < N * N; ++e) xv[e] = fmx(alpha, po[e], xv[e]);
+                st_l64<N>(x, c.self, xv);
+            }
+            ld_l64<N>(r, c.self, p);
 #pragma unroll
             for (int e = 0; e < N * N; ++e) {
+                rv[e] = p[e];
                 const double ru = kStoredLow<S> ? src.cr * p[e] : p[e];
                 p[e] = as_stored<S>(fmx(src.beta, po[e], ru));
             }
-            double xv[N * N];
-            ld_l64<N>(x, c.self, xv);
+        } else {
+            ld_l64<N>(r, c.self, p);
 #pragma unroll
-            for (int e = 0; e < N * N; ++e) xv[e] = fmx(alpha, po[e], xv[e]);
-            st_l64<N>(x, c.self, xv);
+            for (int e = 0; e < N * N; ++e) rv[e] = p[e];
         }
     } else {
         zero_cell<N>(p);
@@ -521,11 +546,13 @@ __device__ __forceinline__ void cg_dir_body(
         sc->first = 0;
         sc->cr = 1.0;
         if (tot[0] > 0.0 && tot[0] == tot[0]) {
+            sc->alpha_prev = alpha;
             sc->alpha = (kStoredLow<S> ? tot[NV - 1] : sc->rz) / tot[0];
-        } else {  // breakdown (or non-finite data): stop, x is current
+        } else {  // breakdown (or non-finite data): stop; x lacks
+                  // alpha_{k-1} p_{k-1} (still in pin) if its update waited
             sc->done = 1;
             sc->breakdown = 1;
-            sc->pending = 0;
+            sc->pending = upd_x ? 0 : 1;
         }
     }
 }
@@ -565,14 +592,17 @@ __device__ __forceinline__ void cg_res_body(
         }
         sc->rr = rrn;
         if (kStoredLow<S> && rrn > sc->rr_max) sc->rr_max = rrn;
+        // x lacks alpha_k p_k, and alpha_{k-1} p_{k-1} too after an odd k
+        // with FP64 directions
+        const int pend = (!kStoredLow<S> && (sc->iter & 1)) ? 2 : 1;
         sc->iter += 1;
         if (rrn <= sc->tol2 * sc->bb) {
             sc->done = 1;
             sc->converged = 1;
-            sc->pending = 1;
+            sc->pending = pend;
         } else if (sc->iter >= sc->max_iter || !(rrn == rrn)) {
             sc->done = 1;
-            sc->pending = 1;
+            sc->pending = pend;
             if (!(rrn == rrn)) sc->breakdown = 1;
         }
     }

@@ -103,6 +103,8 @@ struct CgScalars {
     double bb;        // <b, b>_W
     double pq;        // <p, A p>_W
     double alpha, beta;
+    double alpha_prev; // alpha of the iteration before the last (FP64
+                       // directions: x takes two updates at a time)
     double tol2;      // rtol^2
     double mean_omega, mean_guess, mean_x;
     double ww;        // <omega, omega>_W

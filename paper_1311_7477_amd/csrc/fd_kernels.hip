@@ -90,10 +90,11 @@ __device__ __forceinline__ void set_rz(double rz, CgScalars* sc) {
     sc->precond = 1;
     if (!(rz > 0.0) || !(rz < __builtin_inf())) {
         // <r, M r> must be positive and finite for a nonzero residual:
-        // stop; x still lacks the last alpha p (after any iteration)
+        // stop; x still lacks the last alpha p after any iteration, and the
+        // one before it after an odd one (iter = the next iteration's k)
         sc->done = 1;
         sc->breakdown = 1;
-        sc->pending = sc->first != 1;
+        sc->pending = sc->first == 1 ? 0 : ((sc->iter & 1) ? 1 : 2);
     } else {
         if (sc->first != 1) sc->beta = rz / sc->rz;
         sc->rz = rz;

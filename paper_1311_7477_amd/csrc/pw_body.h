@@ -65,6 +65,7 @@ __device__ __forceinline__ void cg_mean_body(int b, int nb, long rows, const OpC
         sc->ca = ca;
         sc->cb = cb;
         sc->alpha = 0.0;
+        sc->alpha_prev = 0.0;
         sc->beta = 0.0;
         sc->done = 0;
         sc->converged = 0;
@@ -79,17 +80,20 @@ __device__ __forceinline__ void cg_mean_body(int b, int nb, long rows, const OpC
     }
 }
 
-// End of a solve: psi = x + alpha p_last (pending update; p_last = the
-// buffer written by the last direction update) or psi = 0 when b = 0,
+// End of a solve: psi = x plus the pending updates or psi = 0 when b = 0,
 // converted from the lane-interleaved layout to canonical; partial W-mean.
+// pending = 1: x + alpha p_last (p_last = the buffer written by the last
+// direction update); 2: first alpha_prev times the other buffer (the
+// direction before), then alpha p_last.
 template <int N, class P>
 __device__ __forceinline__ void cg_finish_body(int b, int nb, Geom g, const OpConst<double>& k, const double* __restrict__ x,
     const P* __restrict__ p0, const P* __restrict__ p1,
     double* __restrict__ psi, double area, CgScalars* sc, unsigned* counter,
     double* partials) {
     const int pending = sc->pending, zero = sc->zero;
-    const double alpha = sc->alpha;
+    const double alpha = sc->alpha, alpha_prev = sc->alpha_prev;
     const P* pl = (sc->iter & 1) ? p1 : p0;
+    const P* pb = (sc->iter & 1) ? p0 : p1;
     const long cells = (long)g.nx * g.ny;
     const int G = (g.nx + 63) / 64;
     double part[1] = {0.0};
@@ -103,6 +107,7 @@ __device__ __forceinline__ void cg_finish_body(int b, int nb, Geom g, const OpCo
             double a = 0.0;
             if (!zero) {
                 a = x[l64_at<N>(l64, e)];
+                if (pending == 2) a = fmx(alpha_prev, (double)pb[l64_at<N>(l64, e)], a);
                 if (pending) a = fmx(alpha, (double)pl[l64_at<N>(l64, e)], a);
             }
             v[e] = a;
