@@ -110,7 +110,7 @@ def form_batch(args):
     """Batched form: 64 instances with n uniform over {2..5}, N log-uniform
     over [64, N_max], random spectra with peak k0 uniform over [4, 16]; the
     same members stepped one by one with dg_rk_step and together in one
-    batch (persistent launches, graph replay).  Reports aggregate
+    batch (fused launches, graph replay).  Reports aggregate
     cell-updates/s per RHS of both and checks bitwise equality."""
     import numpy as np
     import torch
@@ -450,7 +450,7 @@ def form_serve(args):
     """Serving: a seeded Poisson stream of requests (n uniform over {2..5},
     N log-uniform over [N_min, N_max], random spectra), continuous batching
     under an HBM budget; latency percentiles, aggregate throughput and an
-    alone-vs-mix check.  --serve-solver batch: the persistent batched launches
+    alone-vs-mix check.  --serve-solver batch: the fused batched launches
     with the plain FP64 CG; pcg: a stream and a worker per request with the
     CG preconditioned by fast diagonalisation, its preconditioner in FP32
     under the FP64 iteration.  With --rate 0 the stream runs once per load
@@ -518,7 +518,7 @@ def form_serve(args):
                    "solver": ("stream and worker per request, CG preconditioned by fast "
                               "diagonalisation (FP32 preconditioner, FP64 iteration)"
                               if args.serve_solver == "pcg" else
-                              "batched persistent launches, plain FP64 CG")},
+                              "batched fused launches, plain FP64 CG")},
     }
     print(json.dumps(out), flush=True)
 

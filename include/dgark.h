@@ -379,8 +379,8 @@ int  dg_invariants_noalloc(const dg_grid* grid, const double* omega,
 
 /* ------------------------------------------------------------- batches --- */
 /* Many independent instances (any n, any grid) advanced together: each
- * kernel kind runs as one persistent launch per polynomial order over a
- * device-resident (instance, block) work list, and the setup, CG-chunk and
+ * kernel kind runs as one fused launch per polynomial order over a
+ * device-resident (instance, block) work list (one block per item), and the setup, CG-chunk and
  * finish/RHS sequences of an RK stage are replayed as HIP graphs.  Every
  * instance is cut into the same blocks and uses the same device code as
  * dg_rk_step, so its result is bitwise the same alone or in any batch.

@@ -1,6 +1,6 @@
-// C ABI of batches: independent instances that advance together, one
-// persistent launch per kernel kind and polynomial order, captured in HIP
-// graphs.  Instances can be attached and detached between steps (the
+// C ABI of batches: independent instances that advance together, one fused
+// launch (one block per work item) per kernel kind and polynomial order,
+// captured in HIP graphs.  Instances can be attached and detached between steps (the
 // serving loop's continuous batching); each keeps its own workspace, state
 // and device CG scalars, and its arithmetic is that of dg_rk_step.
 #include <hip/hip_runtime.h>
@@ -21,7 +21,7 @@ namespace {
 enum ListKind { kCell = 0, kRow, kPwRows, kPwCells, kPwElems, kListCount };
 
 // Launch groups: one per (polynomial order, cell tile height, bracket tile
-// height); every kernel kind of a group is one persistent launch.
+// height); every kernel kind of a group is one fused launch.
 constexpr int kCellShapes[3] = {4, 8, 16};
 constexpr int kRowShapes[2] = {8, 16};
 constexpr int kShapes = 6;
@@ -79,14 +79,17 @@ struct dg_batch {
     bool use_graphs = true;
     bool graphs_valid = false;
     int chunk = 16;                // CG iterations per captured chunk (even)
-    hipGraphExec_t g_setup = nullptr, g_chunk = nullptr, g_finish = nullptr;
+    hipGraphExec_t g_setup = nullptr, g_finish = nullptr;
+    hipGraphExec_t g_chunk[kGroups] = {};   // CG chunk of each launch group
 };
 
 namespace {
 
 void destroy_graphs(dg_batch* b) {
-    for (hipGraphExec_t* g : {&b->g_setup, &b->g_chunk, &b->g_finish})
+    for (hipGraphExec_t* g : {&b->g_setup, &b->g_finish})
         if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+    for (hipGraphExec_t& g : b->g_chunk)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     b->graphs_valid = false;
 }
 
@@ -96,7 +99,7 @@ ItemList list_of(const dg_batch* b, int gi, int kind) {
 
 int grid_of(const dg_batch* b, int gi, int kind) {
     const int c = b->lists[gi][kind].count;
-    return c < 1 ? 1 : (c > 65535 ? 65535 : c);
+    return c < 1 ? 1 : c;   // one block per item
 }
 
 // Rebuild the per-order work lists (instance, local block) on the host and
@@ -165,18 +168,19 @@ int enqueue_setup(dg_batch* b, hipStream_t s) {
     return DG_OK;
 }
 
-int enqueue_chunk(dg_batch* b, hipStream_t s) {
-    for (int i = 0; i < b->chunk; ++i)
-        for (int gi = 0; gi < kGroups; ++gi) {
-            if (!(b->group_mask & (1u << gi))) continue;
-            const GroupShape q = shape_of(gi);
-            hipError_t e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Dir, b->d_inst,
-                                        list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
-            if (e == hipSuccess)
-                e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Res, b->d_inst,
-                                 list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
-            if (e != hipSuccess) return hip_fail(e, "batch CG launch");
-        }
+// b->chunk CG iterations of launch group gi.  The groups hold disjoint
+// instances, so each advances by its own chunks: a group whose members have
+// all converged is no longer replayed while the others iterate.
+int enqueue_chunk(dg_batch* b, int gi, hipStream_t s) {
+    const GroupShape q = shape_of(gi);
+    for (int i = 0; i < b->chunk; ++i) {
+        hipError_t e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Dir, b->d_inst,
+                                    list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
+        if (e == hipSuccess)
+            e = launch_batch(q.n, q.cw, q.rw, BatchKernel::Res, b->d_inst,
+                             list_of(b, gi, kCell), grid_of(b, gi, kCell), s);
+        if (e != hipSuccess) return hip_fail(e, "batch CG launch");
+    }
     return DG_OK;
 }
 
@@ -197,9 +201,10 @@ int enqueue_finish(dg_batch* b, hipStream_t s) {
     return DG_OK;
 }
 
-int capture(dg_batch* b, int (*fn)(dg_batch*, hipStream_t), hipGraphExec_t* out) {
+template <class Fn>
+int capture(dg_batch* b, Fn&& fn, hipGraphExec_t* out) {
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    int rc = fn(b, b->cap);
+    int rc = fn(b->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (rc != DG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -213,9 +218,13 @@ int capture(dg_batch* b, int (*fn)(dg_batch*, hipStream_t), hipGraphExec_t* out)
 int ensure_graphs(dg_batch* b) {
     if (b->graphs_valid) return DG_OK;
     destroy_graphs(b);
-    int rc = capture(b, enqueue_setup, &b->g_setup);
-    if (rc == DG_OK) rc = capture(b, enqueue_chunk, &b->g_chunk);
-    if (rc == DG_OK) rc = capture(b, enqueue_finish, &b->g_finish);
+    int rc = capture(b, [b](hipStream_t s) { return enqueue_setup(b, s); }, &b->g_setup);
+    for (int gi = 0; gi < kGroups && rc == DG_OK; ++gi)
+        if (b->group_mask & (1u << gi))
+            rc = capture(b, [b, gi](hipStream_t s) { return enqueue_chunk(b, gi, s); },
+                         &b->g_chunk[gi]);
+    if (rc == DG_OK)
+        rc = capture(b, [b](hipStream_t s) { return enqueue_finish(b, s); }, &b->g_finish);
     if (rc != DG_OK) { destroy_graphs(b); return rc; }
     b->graphs_valid = true;
     return DG_OK;
@@ -229,10 +238,13 @@ int run(dg_batch* b, int (*fn)(dg_batch*, hipStream_t), hipGraphExec_t g, hipStr
     return fn(b, s);
 }
 
-bool all_done(const dg_batch* b, const CgScalars* h) {
+// Launch groups with a member whose solve is still running (h: polled
+// scalars).
+unsigned running_groups(const dg_batch* b, const CgScalars* h) {
+    unsigned m = 0;
     for (int i = 0; i < b->capacity; ++i)
-        if (b->slots[i].used && !h[i].done) return false;
-    return true;
+        if (b->slots[i].used && !h[i].done) m |= 1u << group_of(b->h_inst[i].g);
+    return m;
 }
 
 }  // namespace
@@ -402,11 +414,20 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
                                hipMemcpyHostToDevice, s));
         int rc = run(b, enqueue_setup, b->g_setup, s);
         if (rc != DG_OK) return rc;
-        // CG chunks, polled one chunk behind
+        // CG chunks, polled one chunk behind; a group drops out once all its
+        // members were seen done
         int issued = 0, round = 0, prev = -1;
+        unsigned live = b->group_mask;
         for (;;) {
-            rc = run(b, enqueue_chunk, b->g_chunk, s);
-            if (rc != DG_OK) return rc;
+            for (int gi = 0; gi < kGroups; ++gi) {
+                if (!(live & (1u << gi))) continue;
+                if (b->use_graphs) {
+                    HIP_TRY(hipGraphLaunch(b->g_chunk[gi], s));
+                } else {
+                    rc = enqueue_chunk(b, gi, s);
+                    if (rc != DG_OK) return rc;
+                }
+            }
             issued += b->chunk;
             const int slot = round & 1;
             HIP_TRY(hipMemcpyAsync(b->h_sc + slot * b->capacity, b->d_sc,
@@ -419,7 +440,8 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
             }
             if (prev >= 0) {
                 HIP_TRY(hipEventSynchronize(b->ev[prev]));
-                if (all_done(b, b->h_sc + prev * b->capacity)) break;
+                live &= running_groups(b, b->h_sc + prev * b->capacity);
+                if (!live) break;
             }
             prev = slot;
             ++round;

@@ -46,7 +46,7 @@ struct BatchInst {
 enum class BatchKernel { Mean, Init, Dir, Res, Finish, SubMean, Rhs };
 
 void fill_batch_geometry(BatchInst& b);
-// One persistent launch of `kind` for polynomial order n with cell tiles of
+// One fused launch of `kind` for polynomial order n with cell tiles of
 // cw waves (Init, Dir, Res) and bracket tiles of rw waves (Rhs).
 hipError_t launch_batch(int n, int cw, int rw, BatchKernel kind, const BatchInst* inst,
                         const ItemList& list, int grid, hipStream_t s);

@@ -1,8 +1,9 @@
 // Batched launches: many independent instances (any grid sizes; one
-// polynomial order and one tile shape per launch) in one persistent
-// grid-stride launch per kernel kind.  Every instance is described by a BatchInst record in device
-// memory and cut into the same blocks as its single-instance launch; the
-// work list holds (instance, local block index) items.  Each item runs the
+// polynomial order and one tile shape per launch) in one launch per kernel
+// kind, one block per work item.  Every instance is described by a BatchInst
+// record in device memory and cut into the same blocks as its
+// single-instance launch; the work list holds (instance, local block index)
+// items.  Each item runs the
 // very same device body as the single-instance kernel with the same local
 // block index, so an instance's arithmetic and reduction order -- and hence
 // its result, bit for bit -- do not depend on what else is in the batch.
@@ -16,11 +17,13 @@
 
 namespace dgk {
 
-// Loop over this launch's items; the per-item early exits of the bodies are
-// uniform per block, and the barrier at the end of each item protects the
-// block's LDS before the next item reuses it.
+// Block b runs item b of this launch's list (the launch has one block per
+// item); the per-item early exits of the bodies are uniform per block.  One
+// item per block rather than a grid-stride loop: the loop kept the records'
+// values live across iterations (157 instead of 134 VGPRs for the n = 4
+// direction kernel).
 #define DG_FOR_ITEMS(list)                                                   \
-    for (int it_ = blockIdx.x; it_ < *(list).count; it_ += gridDim.x)        \
+    if (const int it_ = blockIdx.x; it_ < *(list).count)                     \
         if (const BatchItem item_ = (list).items[it_]; true)                 \
             if (const BatchInst& B = inst[item_.inst]; B.active)
 
@@ -31,39 +34,35 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* __rest
         cg_mean_body<N>(item_.b, B.nb_rows, B.rows, B.k, B.w_in, B.pa, B.pb,
                         B.ca, B.cb, B.area, B.tol2, B.max_iter, 0, B.sc,
                         B.counters + kCntMean, B.partials);
-        __syncthreads();
     }
 }
 
 template <int N, int WV>
-__global__ __launch_bounds__(64 * WV) void kb_cg_init(const BatchInst* __restrict__ inst, ItemList list) {
+__global__ __launch_bounds__(64 * WV, (N <= 4 ? 4 : 1)) void kb_cg_init(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_init_body<N, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k, B.w_in,
                         B.pa, B.pb, B.ca, B.cb, B.x, B.r, B.sc,
                         B.counters + kCntInit, B.partials, lds);
-        __syncthreads();
     }
 }
 
 template <int N, int WV>
-__global__ __launch_bounds__(64 * WV) void kb_cg_dir(const BatchInst* __restrict__ inst, ItemList list) {
+__global__ __launch_bounds__(64 * WV, (N <= 4 ? 4 : 1)) void kb_cg_dir(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_dir_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
                                B.r, B.p0, B.p1, B.x, B.sc, B.counters + kCntDir, B.partials, lds);
-        __syncthreads();
     }
 }
 
 template <int N, int WV>
-__global__ __launch_bounds__(64 * WV) void kb_cg_res(const BatchInst* __restrict__ inst, ItemList list) {
+__global__ __launch_bounds__(64 * WV, (N <= 4 ? 4 : 1)) void kb_cg_res(const BatchInst* __restrict__ inst, ItemList list) {
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_res_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
                                B.p0, B.p1, B.r, B.sc,
                                B.counters + kCntRes, B.partials, lds);
-        __syncthreads();
     }
 }
 
@@ -73,7 +72,6 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_finish(const BatchInst* __re
     DG_FOR_ITEMS(list) {
         cg_finish_body<N>(item_.b, B.nb_cells, B.g, B.k, B.x, B.p0, B.p1, B.psi,
                           B.area, B.sc, B.counters + kCntFinish, B.partials);
-        __syncthreads();
     }
 }
 
@@ -90,7 +88,6 @@ __global__ __launch_bounds__(64 * W, 4) void kb_rhs(const BatchInst* __restrict_
     DG_FOR_ITEMS(list) {
         rhs_body<N, W, true>(item_.b, B.g, B.row_tilesX, B.row_nblocks,
                                      B.k, B.psi, B.w_in, B.w_n, B.w_out, B.ra, lds);
-        __syncthreads();
     }
 }
 

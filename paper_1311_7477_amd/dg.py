@@ -452,7 +452,7 @@ def invariants_noalloc(grid: Grid, omega, psi, out):
 
 
 class Batch:
-    """Instances advanced together by batched persistent launches (see
+    """Instances advanced together by batched fused launches (see
     dg_batch_* in include/dgark.h).  Members keep references to their grid
     and omega tensor while attached."""
 

@@ -3,7 +3,7 @@
 A request asks for `steps` SSP-RK3 steps of one instance (polynomial order
 n, an N x N periodic grid, an initial vorticity).  The server keeps every
 admitted request's state resident on the device and advances all of them
-together, one batched RK3 step per tick (dg_batch_rk_step: one persistent
+together, one batched RK3 step per tick (dg_batch_rk_step: one fused
 launch per kernel kind and polynomial order, graph-replayed).  Requests that
 arrive while others run wait in a FIFO queue and are admitted between ticks
 as soon as a slot is free and their device footprint
