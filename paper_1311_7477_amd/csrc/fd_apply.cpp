@@ -18,7 +18,7 @@
 // half of Phi -- two products of (N/2)^2 instead of one of N^2.  The x fold
 // happens in the input conversion, the y fold in the x mixing (and the
 // unfolds in reverse).  The transforms cost 2 n^2 Nx Ny (Nx + Ny) flops in
-// all.  Beyond 512 cells on an axis (both counts even) they run as FFTs
+// all.  Beyond 32 cells on an axis (both counts even) they run as FFTs
 // along the cells instead (rocFFT, with the unshifted basis: each real row as
 // a complex row of half length, the mixing kernels then convert to and from
 // half spectra, fd_kernels.hip).  The same steps run in FP64 or, for the
@@ -70,7 +70,7 @@ int blas_fail(rocblas_status st, const char* what) {
                 rocblas_status_to_string(st));
 }
 
-constexpr int kFdGemmMaxCells = 512;
+constexpr int kFdGemmMaxCells = 32;
 
 int fft_fail(rocfft_status st, const char* what) {
     return fail(DG_E_HIP, "%s: rocFFT status %d", what, (int)st);
@@ -244,13 +244,14 @@ int apply_fft(const FdDevice* fd, hipStream_t s) {
 
 }  // namespace
 
-// The cell transforms of a periodic grid: FP64 GEMMs up to 512 cells per
-// axis (at n = 4, 512^2 they beat the FFTs; they use the basis with phases at
-// the cell centres, which folds each axis to half size), FFTs beyond when
-// both axes have an even number of cells (each real row of N values is
-// transformed as a complex row of N/2; at n = 5, 1024^2 a preconditioned
-// solve took 6.0 ms with rocFFT's real transforms against 9.6 ms with the
-// unfolded products), the folded GEMMs again for an odd count.
+// The cell transforms of a periodic grid: FFTs when both axes have an even
+// number of cells and one has more than 32 (each real row of N values is
+// transformed as a complex row of N/2), the folded GEMMs otherwise (the basis
+// with phases at the cell centres folds each axis to half size; an odd count
+// cannot be packed into half-length rows).  One FP64 apply with the FFTs
+// against the folded GEMMs: 41 / 60 us at n = 4, 64^2; 82 / 129 us at
+// n = 4, 256^2; 142 / 270 us at n = 4, 512^2; 210 / 401 us at n = 5, 512^2
+// (every order and size from 64 to 512 cells favours the FFTs).
 bool fd_uses_fft(int nx, int ny) {
     return (nx > kFdGemmMaxCells || ny > kFdGemmMaxCells) && nx % 2 == 0 && ny % 2 == 0;
 }
