@@ -179,16 +179,20 @@ int cg_loop(const Geom& geom, const OpConst<double>& k, T* x, T* r, T* p0, T* p1
         int m = max_iter - issued;
         if (m > chunk) m = chunk;
         const int slot = round & 1;
+        // the sampled iteration alternates between the first and the second
+        // of a chunk, so that FP64 solves time direction updates with and
+        // without the x update alike
+        const int ti = (round & 1) && m > 1 ? 1 : 0;
         for (int i = 0; i < m; ++i) {
             hipError_t e;
-            if (ws->prof_on && i == 0) {
+            if (ws->prof_on && i == ti) {
                 e = launch_cg_dir_timed<T>(geom, k, x, r, p0, p1, sc, ws->d, s,
                                            ws->pev[slot][0], ws->pev[slot][1]);
                 if (e != hipSuccess) return hip_fail(e, "cg direction launch");
                 e = launch_cg_res_timed<T>(geom, k, r, p0, p1, sc, ws->d, s,
                                            ws->pev[slot][2], ws->pev[slot][3]);
                 if (e != hipSuccess) return hip_fail(e, "cg residual launch");
-                ws->pev_iter[slot] = issued;
+                ws->pev_iter[slot] = issued + i;
             } else {
                 e = launch_cg_iter<T>(geom, k, x, r, p0, p1, sc, ws->d, s);
                 if (e != hipSuccess) return hip_fail(e, "cg iteration launch");

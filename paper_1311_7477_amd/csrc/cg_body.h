@@ -361,13 +361,13 @@ struct SrcDirection {                   // p = r (first) or cr r + beta p_old, L
 };
 
 template <int N>
-struct SrcGuess {                       // x0 = ca pa + cb pb - mean, canonical
+struct SrcGuess {                       // x0 = ca pa + cb pb, canonical
     const double* pa;
     const double* pb;
-    double ca, cb, m;
+    double ca, cb;
     __device__ void operator()(const CellRef& c, double (&u)[N * N]) const {
 #pragma unroll
-        for (int e = 0; e < N * N; ++e) u[e] = -m;
+        for (int e = 0; e < N * N; ++e) u[e] = 0.0;
         if (ca != 0.0) {
             double a[N * N];
             ld_canon<N>(pa, c, a);
@@ -404,7 +404,8 @@ __device__ __forceinline__ void laplace_body(
     if (c.active) st_canon<N>(out, c.self, lap);
 }
 
-// CG setup (stencil part): x0 = guess - mean(guess) (to L64);
+// CG setup (stencil part): x0 = guess (to L64; its mean is left in, see
+// cg_mean_body);
 // r0 = (omega - mean(omega)) + Lap_h x0 (to L64); partials <r0,r0>_W, <b,b>_W.
 template <int N, int WV, bool DIR = false, bool ISO = false>
 __device__ __forceinline__ void cg_init_body(
@@ -415,7 +416,7 @@ __device__ __forceinline__ void cg_init_body(
     unsigned* counter, double* partials,
     YFaces<N, double, WV>& lds) {
     const CellCtx c = make_cell_ctx<N, WV>(g, tilesX, nblocks, b);
-    SrcGuess<N> src{pa, pb, ca, cb, sc->mean_guess};
+    SrcGuess<N> src{pa, pb, ca, cb};
     const double mo = sc->mean_omega;
     double x0[N * N], lap[N * N];
     if (c.active) src(c.self, x0);

@@ -106,7 +106,7 @@ struct CgScalars {
     double alpha_prev; // alpha of the iteration before the last (FP64
                        // directions: x takes two updates at a time)
     double tol2;      // rtol^2
-    double mean_omega, mean_guess, mean_x;
+    double mean_omega, mean_x;
     double ww;        // <omega, omega>_W
     double zero_tol2; // b counts as zero when <b,b>_W <= zero_tol2 * ww
     double ca, cb;    // guess = ca * psi_a + cb * psi_b (device copies)

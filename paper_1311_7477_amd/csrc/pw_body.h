@@ -18,47 +18,36 @@ __device__ __forceinline__ double wrow(const OpConst<T>& k, int j, const double 
     return s * (double)k.w[j] * k.wq;
 }
 
-// Means of omega and of the guess ca psi_a + cb psi_b, and <omega, omega>_W;
-// the last block also initialises every CG scalar for the coming solve.
-// With a Dirichlet axis (dir != 0) -Lap_h is definite and nothing is
-// subtracted: the means the later kernels remove are stored as zero.
+// Mean of omega and <omega, omega>_W; the last block also initialises every
+// CG scalar for the coming solve.  The guess ca psi_a + cb psi_b keeps its
+// mean: Lap_h annihilates constants, so the initial residual does not see it,
+// the directions never carry one, and the end of the solve removes the mean of
+// the solution (pa, pb: read by the setup kernel only).  With a Dirichlet axis
+// (dir != 0) -Lap_h is definite and nothing is subtracted: the mean the later
+// kernels remove is stored as zero.
 template <int N>
 __device__ __forceinline__ void cg_mean_body(int b, int nb, long rows, const OpConst<double>& k, const double* __restrict__ omega,
     const double* __restrict__ pa, const double* __restrict__ pb, double ca,
     double cb, double area, double tol2, int max_iter, int dir, CgScalars* sc,
     unsigned* counter, double* partials) {
-    double part[3] = {0.0, 0.0, 0.0};
+    (void)pa;
+    (void)pb;
+    double part[2] = {0.0, 0.0};
     for (long row = b * (long)kPwThreads + threadIdx.x; row < rows;
          row += (long)nb * kPwThreads) {
         const int j = (int)(row % N);
-        double w[N], gs[N], w2[N];
+        double w[N], w2[N];
         load_vec(omega, row * N, w);
-#pragma unroll
-        for (int i = 0; i < N; ++i) gs[i] = 0.0;
-        if (ca != 0.0) {
-            double a[N];
-            load_vec(pa, row * N, a);
-#pragma unroll
-            for (int i = 0; i < N; ++i) gs[i] += ca * a[i];
-        }
-        if (cb != 0.0) {
-            double b[N];
-            load_vec(pb, row * N, b);
-#pragma unroll
-            for (int i = 0; i < N; ++i) gs[i] += cb * b[i];
-        }
 #pragma unroll
         for (int i = 0; i < N; ++i) w2[i] = w[i] * w[i];
         part[0] += wrow<N>(k, j, w);
-        part[1] += wrow<N>(k, j, gs);
-        part[2] += wrow<N>(k, j, w2);
+        part[1] += wrow<N>(k, j, w2);
     }
-    double tot[3];
-    if (reduce_last<3, kPwThreads>(part, partials, counter, nb, b, tot) &&
+    double tot[2];
+    if (reduce_last<2, kPwThreads>(part, partials, counter, nb, b, tot) &&
         threadIdx.x == 0) {
         sc->mean_omega = dir ? 0.0 : tot[0] / area;
-        sc->mean_guess = dir ? 0.0 : tot[1] / area;
-        sc->ww = tot[2];
+        sc->ww = tot[1];
         sc->zero_tol2 = 1e-28;   // (1e-14)^2: b below the mean-removal rounding
         sc->tol2 = tol2;
         sc->max_iter = max_iter;

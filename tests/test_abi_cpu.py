@@ -171,8 +171,8 @@ def test_workspace_bytes_and_field_size():
         # FFTs along x or y, with room for N/2 + 1 complex values per row
         return 8 * n * n * max(Nx * Ny, Ny * 2 * (Nx // 2 + 1), Nx * 2 * (Ny // 2 + 1))
     # ... plus, for RK steps queued ahead, a copy of omega and three sets of
-    # device CG scalars (19 doubles and 10 ints each)
-    queued = F + 3 * (19 * 8 + 10 * 4)
+    # device CG scalars (18 doubles and 10 ints each)
+    queued = F + 3 * (18 * 8 + 10 * 4)
     bfd = g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD)
     assert bfd == b64 + F + 2 * field(4, 512, 512) + axis(512, 4) + queued
     # unequal axes keep both factor sets
@@ -180,7 +180,7 @@ def test_workspace_bytes_and_field_size():
     extra = r.workspace_bytes(dg.DG_WS_FD) - r.workspace_bytes(dg.DG_PREC_FP64)
     L6 = 5 * 1 * 4 * 64
     assert extra == (L6 * 8 + 2 * field(2, 6, 5) + axis(6, 2) + axis(5, 2)
-                     + r.elems * 8 + 3 * (19 * 8 + 10 * 4))
+                     + r.elems * 8 + 3 * (18 * 8 + 10 * 4))
     # ragged nx: the interleaved vectors are padded to whole groups of 64 cells
     h = dg.Grid(3, 100, 7)
     L = 7 * 2 * 9 * 64
@@ -196,12 +196,12 @@ def test_workspace_bytes_and_field_size():
     Ld = 24 * 1 * 9 * 64
     extra = d.workspace_bytes(dg.DG_WS_FD) - d.workspace_bytes(dg.DG_PREC_FP64)
     assert extra == (Ld * 8 + 2 * 8 * 9 * 40 * 24 + dense(40, 3) + dense(24, 3)
-                     + d.elems * 8 + 3 * (19 * 8 + 10 * 4))
+                     + d.elems * 8 + 3 * (18 * 8 + 10 * 4))
     sq = dg.Grid(2, 16, 16, bc_x=dg.DG_BC_DIRICHLET, bc_y=dg.DG_BC_DIRICHLET)
     Ls = 16 * 1 * 4 * 64
     extra = sq.workspace_bytes(dg.DG_WS_FD) - sq.workspace_bytes(dg.DG_PREC_FP64)
     assert extra == (Ls * 8 + 2 * 8 * 4 * 16 * 16 + dense(16, 2)
-                     + sq.elems * 8 + 3 * (19 * 8 + 10 * 4))
+                     + sq.elems * 8 + 3 * (18 * 8 + 10 * 4))
 
 
 def test_null_arguments_are_rejected():
