@@ -364,7 +364,7 @@ int  dg_invariants_dev(const dg_grid* grid, const double* omega,
 /* dg_invariants_dev without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops).  The
  * reduction scratch (at most 1024 blocks x 4 doubles of partial sums plus the
- * ticket counters, 33 KB) is a static device array that each device holds
+ * ticket counters, 47 KB) is a static device array that each device holds
  * from its first call until the process ends; any grid size fits it (the
  * reduction launches at most 1024 blocks).  This call never allocates.  The
  * first call on a device looks the array up and queues a counter clear on

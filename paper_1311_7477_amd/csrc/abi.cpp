@@ -128,7 +128,7 @@ size_t ws_bytes(const dg_grid* g, int mode) {
     if (blocks < pointwise_block_cap()) blocks = pointwise_block_cap();
     size_t b = 4 * L * sizeof(double) + 2 * F;          // x, r, p0, p1; s1, s2
     b += (size_t)blocks * 4 * sizeof(double);           // partials
-    b += sizeof(CgScalars) + kCntCount * sizeof(unsigned) + 4 * sizeof(double);
+    b += sizeof(CgScalars) + kCntBytes + 4 * sizeof(double);
     if ((mode & ~DG_WS_FD) == DG_PREC_MIXED) b += 3 * L * sizeof(float);
     if (mode & DG_WS_FD)
         b += L * sizeof(double) + F + 3 * sizeof(CgScalars) + fd_bytes(g);   // z, wbak, sc3
@@ -617,7 +617,7 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
               alloc((void**)&ws->p1, L * sizeof(double)) &&
               alloc((void**)&ws->s1, F) && alloc((void**)&ws->s2, F) &&
               alloc((void**)&ws->d.sc, sizeof(CgScalars)) &&
-              alloc((void**)&ws->d.counters, kCntCount * sizeof(unsigned)) &&
+              alloc((void**)&ws->d.counters, kCntBytes) &&
               alloc((void**)&ws->d.partials, (size_t)blocks * 4 * sizeof(double)) &&
               alloc((void**)&ws->d.out3, 4 * sizeof(double));
     if (ok && (mode & ~DG_WS_FD) == DG_PREC_MIXED) {
@@ -654,7 +654,7 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
             }
     ws->pev_iter[0] = ws->pev_iter[1] = -1;
     // counters must start at zero (each reduction resets its own)
-    e = hipMemset(ws->d.counters, 0, kCntCount * sizeof(unsigned));
+    e = hipMemset(ws->d.counters, 0, kCntBytes);
     if (e == hipSuccess) e = hipMemset(ws->d.sc, 0, sizeof(CgScalars));
     if (e == hipSuccess && ws->sc3) e = hipMemset(ws->sc3, 0, 3 * sizeof(CgScalars));
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_mean(const BatchInst* __rest
     DG_FOR_ITEMS(list) {
         cg_mean_body<N>(item_.b, B.nb_rows, B.rows, B.k, B.w_in, B.pa, B.pb,
                         B.ca, B.cb, B.area, B.tol2, B.max_iter, 0, B.sc,
-                        B.counters + kCntMean, B.partials);
+                        B.counters + kCntMean * kCntStride, B.partials);
     }
 }
 
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64 * WV, (N <= 4 ? 4 : 1)) void kb_cg_init(const Ba
     DG_FOR_ITEMS(list) {
         cg_init_body<N, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k, B.w_in,
                         B.pa, B.pb, B.ca, B.cb, B.x, B.r, B.sc,
-                        B.counters + kCntInit, B.partials, lds);
+                        B.counters + kCntInit * kCntStride, B.partials, lds);
     }
 }
 
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64 * WV, (N <= 4 ? 4 : 1)) void kb_cg_dir(const Bat
     __shared__ YFaces<N, double, WV> lds;
     DG_FOR_ITEMS(list) {
         cg_dir_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
-                               B.r, B.p0, B.p1, B.x, B.sc, B.counters + kCntDir, B.partials, lds);
+                               B.r, B.p0, B.p1, B.x, B.sc, B.counters + kCntDir * kCntStride, B.partials, lds);
     }
 }
 
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(64 * WV, (N <= 4 ? 4 : 1)) void kb_cg_res(const Bat
     DG_FOR_ITEMS(list) {
         cg_res_body<N, double, WV>(item_.b, B.g, B.cell_tilesX, B.cell_nblocks, B.k,
                                B.p0, B.p1, B.r, B.sc,
-                               B.counters + kCntRes, B.partials, lds);
+                               B.counters + kCntRes * kCntStride, B.partials, lds);
     }
 }
 
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kPwThreads) void kb_cg_finish(const BatchInst* __re
                                                            ItemList list) {
     DG_FOR_ITEMS(list) {
         cg_finish_body<N>(item_.b, B.nb_cells, B.g, B.k, B.x, B.p0, B.p1, B.psi,
-                          B.area, B.sc, B.counters + kCntFinish, B.partials);
+                          B.area, B.sc, B.counters + kCntFinish * kCntStride, B.partials);
     }
 }
 

@@ -120,13 +120,13 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
             DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN, kDirichletCellWaves, true, true>),
                                                   dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
                                                   0, s, g, L.tilesX, L.nblocks, k, omega, pa, pb,
-                                                  ca, cb, x, r, d.sc, d.counters + kCntInit,
+                                                  ca, cb, x, r, d.sc, d.counters + kCntInit * kCntStride,
                                                   d.partials));
         } else {
             DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_init<NN, kDirichletCellWaves, true, false>),
                                                   dim3(L.nblocks), dim3(64 * kDirichletCellWaves),
                                                   0, s, g, L.tilesX, L.nblocks, k, omega, pa, pb,
-                                                  ca, cb, x, r, d.sc, d.counters + kCntInit,
+                                                  ca, cb, x, r, d.sc, d.counters + kCntInit * kCntStride,
                                                   d.partials));
         }
         return hipGetLastError();
@@ -136,13 +136,13 @@ hipError_t launch_cg_init(const Geom& g, const OpConst<double>& k,
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, omega, pa, pb, ca, cb, x, r,
-                                              d.sc, d.counters + kCntInit, d.partials));
+                                              d.sc, d.counters + kCntInit * kCntStride, d.partials));
     } else {
         DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_init<NN, WW, false, false>),
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, omega, pa, pb, ca, cb, x, r,
-                                              d.sc, d.counters + kCntInit, d.partials));
+                                              d.sc, d.counters + kCntInit * kCntStride, d.partials));
     }
     return hipGetLastError();
 }
@@ -159,13 +159,13 @@ hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* 
                                                       dim3(L.nblocks),
                                                       dim3(64 * kDirichletCellWaves), 0, s, g,
                                                       L.tilesX, L.nblocks, k, r, p0, p1, x, sc,
-                                                      d.counters + kCntDir, d.partials));
+                                                      d.counters + kCntDir * kCntStride, d.partials));
             } else {
                 DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_dir<NN, S, kDirichletCellWaves, true, false>),
                                                       dim3(L.nblocks),
                                                       dim3(64 * kDirichletCellWaves), 0, s, g,
                                                       L.tilesX, L.nblocks, k, r, p0, p1, x, sc,
-                                                      d.counters + kCntDir, d.partials));
+                                                      d.counters + kCntDir * kCntStride, d.partials));
             }
             return hipGetLastError();
         }
@@ -176,13 +176,13 @@ hipError_t launch_cg_dir(const Geom& g, const OpConst<double>& k, double* x, S* 
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, r, p0, p1, x, sc,
-                                              d.counters + kCntDir, d.partials));
+                                              d.counters + kCntDir * kCntStride, d.partials));
     } else {
         DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_dir<NN, S, WW, false, false>),
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, r, p0, p1, x, sc,
-                                              d.counters + kCntDir, d.partials));
+                                              d.counters + kCntDir * kCntStride, d.partials));
     }
     return hipGetLastError();
 }
@@ -199,13 +199,13 @@ hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S
                                                       dim3(L.nblocks),
                                                       dim3(64 * kDirichletCellWaves), 0, s, g,
                                                       L.tilesX, L.nblocks, k, p0, p1, r, sc,
-                                                      d.counters + kCntRes, d.partials));
+                                                      d.counters + kCntRes * kCntStride, d.partials));
             } else {
                 DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_res<NN, S, kDirichletCellWaves, true, false>),
                                                       dim3(L.nblocks),
                                                       dim3(64 * kDirichletCellWaves), 0, s, g,
                                                       L.tilesX, L.nblocks, k, p0, p1, r, sc,
-                                                      d.counters + kCntRes, d.partials));
+                                                      d.counters + kCntRes * kCntStride, d.partials));
             }
             return hipGetLastError();
         }
@@ -216,13 +216,13 @@ hipError_t launch_cg_res(const Geom& g, const OpConst<double>& k, S* r, S* p0, S
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, p0, p1, r, sc,
-                                              d.counters + kCntRes, d.partials));
+                                              d.counters + kCntRes * kCntStride, d.partials));
     } else {
         DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_cg_res<NN, S, WW, false, false>),
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, p0, p1, r, sc,
-                                              d.counters + kCntRes, d.partials));
+                                              d.counters + kCntRes * kCntStride, d.partials));
     }
     return hipGetLastError();
 }
@@ -241,14 +241,14 @@ hipError_t launch_cg_dir_timed(const Geom& g, const OpConst<double>& k, double* 
                                                         dim3(L.nblocks),
                                                         dim3(64 * WW), 0, s, start, stop, 0, g,
                                                         L.tilesX, L.nblocks, k, (const S*)r, p0,
-                                                        p1, x, sc, d.counters + kCntDir,
+                                                        p1, x, sc, d.counters + kCntDir * kCntStride,
                                                         d.partials));
     } else {
         DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_dir<NN, S, WW, false, false>),
                                                         dim3(L.nblocks),
                                                         dim3(64 * WW), 0, s, start, stop, 0, g,
                                                         L.tilesX, L.nblocks, k, (const S*)r, p0,
-                                                        p1, x, sc, d.counters + kCntDir,
+                                                        p1, x, sc, d.counters + kCntDir * kCntStride,
                                                         d.partials));
     }
     return hipGetLastError();
@@ -265,14 +265,14 @@ hipError_t launch_cg_res_timed(const Geom& g, const OpConst<double>& k, S* r, S*
                                                         dim3(L.nblocks),
                                                         dim3(64 * WW), 0, s, start, stop, 0, g,
                                                         L.tilesX, L.nblocks, k, (const S*)p0,
-                                                        (const S*)p1, r, sc, d.counters + kCntRes,
+                                                        (const S*)p1, r, sc, d.counters + kCntRes * kCntStride,
                                                         d.partials));
     } else {
         DG_DISPATCH_NW(g.n, g.cw, hipExtLaunchKernelGGL((k_cg_res<NN, S, WW, false, false>),
                                                         dim3(L.nblocks),
                                                         dim3(64 * WW), 0, s, start, stop, 0, g,
                                                         L.tilesX, L.nblocks, k, (const S*)p0,
-                                                        (const S*)p1, r, sc, d.counters + kCntRes,
+                                                        (const S*)p1, r, sc, d.counters + kCntRes * kCntStride,
                                                         d.partials));
     }
     return hipGetLastError();
@@ -320,13 +320,13 @@ hipError_t launch_mixed_replace(const Geom& g, const OpConst<double>& k,
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, omega, x, q0, q1, r32,
-                                              d.sc, d.counters + kCntDot, d.partials));
+                                              d.sc, d.counters + kCntDot * kCntStride, d.partials));
     } else {
         DG_DISPATCH_NW(g.n, g.cw, hipLaunchKernelGGL((k_mixed_replace<NN, WW, false>),
                                                      dim3(L.nblocks),
                                               dim3(64 * WW), 0, s, g, L.tilesX,
                                               L.nblocks, k, omega, x, q0, q1, r32,
-                                              d.sc, d.counters + kCntDot, d.partials));
+                                              d.sc, d.counters + kCntDot * kCntStride, d.partials));
     }
     return hipGetLastError();
 }

@@ -122,13 +122,21 @@ struct CgScalars {
     int precond;      // 1: beta and rz come from the preconditioned dot kernel
 };
 
-// Counters for the last-block-done reductions, one per kernel kind.
+// Ticket counters of the last-block-done reductions, one set per kernel kind:
+// a global counter and kTicketGroups group counters, each on a 64-byte line
+// of its own (atomics on one line are performed one after the other, about
+// 12 ns apiece, so blocks finishing together queue on a single counter).
 enum CounterId { kCntMean = 0, kCntInit, kCntDir, kCntRes, kCntFinish,
                  kCntInv, kCntDot, kCntCount };
+constexpr int kTicketGroups = 32;
+constexpr int kCntLine = 16;                               // counters per 64 bytes
+constexpr int kCntStride = (1 + kTicketGroups) * kCntLine; // one kind's set
+constexpr size_t kCntBytes = (size_t)kCntCount * kCntStride * sizeof(unsigned);
 
 struct DevScratch {
     CgScalars* sc;          // device scalars
-    unsigned* counters;     // kCntCount counters, zero between launches
+    unsigned* counters;     // kCntCount sets of kCntStride counters (kind k at
+                            // counters + k * kCntStride), zero between launches
     double* partials;       // per-block partial sums (capacity max_blocks * 4)
     double* out3;           // 3 doubles (invariants / generic reductions)
     int max_blocks;

@@ -814,11 +814,11 @@ hipError_t launch_from_image_dot(const Geom& g, const OpConst<double>& k, const 
     if (dense) {
         DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN, true, T>), dim3(nb),
                                               dim3(kPwThreads), 0, s, g, k, img, z, r, d.sc,
-                                              d.counters + kCntDot, d.partials));
+                                              d.counters + kCntDot * kCntStride, d.partials));
     } else {
         DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_image_dot<NN, false, T>), dim3(nb),
                                               dim3(kPwThreads), 0, s, g, k, img, z, r, d.sc,
-                                              d.counters + kCntDot, d.partials));
+                                              d.counters + kCntDot * kCntStride, d.partials));
     }
     return hipGetLastError();
 }
@@ -845,7 +845,7 @@ hipError_t launch_from_planes_fold(const Geom& g, const OpConst<double>& k, cons
     if (d) {
         DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_planes_fold<NN, true, T>), dim3(nb),
                                               dim3(kPwThreads), 0, s, g, k, img, Kx, dst, r,
-                                              d->sc, d->counters + kCntDot, d->partials));
+                                              d->sc, d->counters + kCntDot * kCntStride, d->partials));
     } else {
         DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_from_planes_fold<NN, false, T>), dim3(nb),
                                               dim3(kPwThreads), 0, s, g, k, img, Kx, dst,

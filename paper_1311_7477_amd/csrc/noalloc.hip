@@ -15,18 +15,18 @@ using namespace dgk;
 namespace {
 
 // The pointwise reductions launch at most pointwise_block_cap() blocks, each
-// publishing up to 4 doubles; the ticket counters sit in the first 256 bytes.
+// publishing up to 4 doubles; the ticket counters (every kind's set, as in a
+// workspace) come first, rounded up to 256 bytes.
 constexpr int kScratchBlocks = 1024;
-constexpr size_t kScratchCounterBytes = 256;
+constexpr size_t kScratchCounterBytes = (kCntBytes + 255) / 256 * 256;
 constexpr size_t kScratchBytes =
     kScratchCounterBytes + (size_t)kScratchBlocks * 4 * sizeof(double);
-static_assert(kCntCount * sizeof(unsigned) <= kScratchCounterBytes,
-              "ticket counters must fit their slot");
+static_assert(kCntBytes <= kScratchCounterBytes, "ticket counters must fit their slot");
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 __global__ void k_clear_counters(unsigned* c, int count) {
-    if ((int)threadIdx.x < count) c[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) c[i] = 0u;
 }
 
 constexpr int kMaxDevices = 64;
@@ -43,8 +43,8 @@ int scratch_on(int dev, hipStream_t s, void** out) {
         hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
         if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
         if (!p) return fail(DG_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
-        hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, s, (unsigned*)p,
-                           (int)kCntCount);
+        hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(256), 0, s, (unsigned*)p,
+                           (int)(kCntBytes / sizeof(unsigned)));
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "scratch counter clear launch");
         g_scratch[dev] = p;

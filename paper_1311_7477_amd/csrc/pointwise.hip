@@ -97,7 +97,7 @@ hipError_t launch_cg_mean(const Geom& g, const OpConst<double>& k,
                                           dim3(kPwThreads), 0, s, rows, k, omega,
                                           pa, pb, ca, cb, area, tol2, max_iter,
                                           (g.bcx || g.bcy) ? 1 : 0, d.sc,
-                                          d.counters + kCntMean, d.partials));
+                                          d.counters + kCntMean * kCntStride, d.partials));
     return hipGetLastError();
 }
 
@@ -110,7 +110,7 @@ hipError_t launch_cg_finish(const Geom& g, const OpConst<double>& k,
     const int nb = pw_blocks(cells, pointwise_block_cap());
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_cg_finish<NN, P>), dim3(nb),
                                           dim3(kPwThreads), 0, s, g, k, x, p0, p1,
-                                          psi, area, d.sc, d.counters + kCntFinish,
+                                          psi, area, d.sc, d.counters + kCntFinish * kCntStride,
                                           d.partials));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -133,7 +133,7 @@ hipError_t launch_mean_sub(const Geom& g, const OpConst<double>& k, double* x,
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mean_canon<NN>),
                                           dim3(pw_blocks(rows, pointwise_block_cap())),
                                           dim3(kPwThreads), 0, s, rows, k, x, area,
-                                          d.sc, d.counters + kCntFinish, d.partials));
+                                          d.sc, d.counters + kCntFinish * kCntStride, d.partials));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long elems = rows * g.n;
@@ -149,7 +149,7 @@ hipError_t launch_invariants(const Geom& g, const OpConst<double>& k,
     const int nb = pw_blocks(rows, pointwise_block_cap());
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_invariants<NN>), dim3(nb),
                                           dim3(kPwThreads), 0, s, rows, k, omega,
-                                          psi, out3, d.counters + kCntInv,
+                                          psi, out3, d.counters + kCntInv * kCntStride,
                                           d.partials));
     return hipGetLastError();
 }
@@ -161,7 +161,7 @@ hipError_t launch_mixed_start(const Geom& g, const OpConst<double>& k,
     const int nb = pw_blocks(cells, pointwise_block_cap());
     DG_DISPATCH_N(g.n, hipLaunchKernelGGL((k_mixed_start<NN>), dim3(nb),
                                           dim3(kPwThreads), 0, s, g, k, r64, r32,
-                                          d.sc, d.counters + kCntMean, d.partials));
+                                          d.sc, d.counters + kCntMean * kCntStride, d.partials));
     return hipGetLastError();
 }
 
