@@ -842,8 +842,10 @@ def precond_leg(args, omega0, dt, tiles):
         "workspace_bytes": ws.held_bytes(),
         "precond_flops_per_apply": 4 * n * n * N * N * (N + N),
         "method": "PCG, M = exact (-Lap_h)^+ by fast diagonalisation: separable "
-                  "Bloch eigenbases in factored form (FP64 cell Fourier transforms "
-                  "as matrix products, 2n x 2n mixing per wave number)",
+                  "Bloch eigenbases in factored form (FP64 cell Fourier transforms by "
+                  "half-length FFTs when both cell counts are even and an axis exceeds "
+                  "32 cells, else as folded matrix products; 2n x 2n mixing per wave "
+                  "number)",
     }
 
 
