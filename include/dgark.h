@@ -63,6 +63,15 @@ extern "C" {
    preconditioner (factored separable eigenbases of the 1D LDG operators, in
    FP64 and FP32, and two node-plane work fields) */
 #define DG_WS_FD       0x10
+/* workspace option, with DG_WS_FD: on a periodic grid, transform along the
+   cells with the folded matrix products even where the half-length FFTs
+   apply (both cell counts even, an axis beyond 32 cells).  No rocFFT plans
+   are made: their creation compiles kernels for every new transform length
+   (about 1-2 s per grid size), while a product-path workspace is ready in
+   milliseconds; its applies are slower (one FP64 apply at n = 4: 129 against
+   82 us at 256^2, 270 against 142 us at 512^2).  For short-lived workspaces,
+   such as served requests of many different sizes. */
+#define DG_WS_FD_PRODUCTS 0x20
 
 /* CG preconditioners (dg_cg_opts.precond) */
 #define DG_PRECOND_NONE 0       /* plain CG, as in Sec. 6 */

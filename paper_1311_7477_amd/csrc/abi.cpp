@@ -116,8 +116,12 @@ int check_ws(const dg_grid* g, const dg_workspace* ws) {
     return DG_OK;
 }
 
+// precision part of a workspace mode
+int prec_of(int mode) { return mode & ~(DG_WS_FD | DG_WS_FD_PRODUCTS); }
+
 bool valid_mode(int mode) {
-    const int prec = mode & ~DG_WS_FD;
+    const int prec = prec_of(mode);
+    if ((mode & DG_WS_FD_PRODUCTS) && !(mode & DG_WS_FD)) return false;
     return prec == DG_PREC_FP64 || prec == DG_PREC_MIXED;
 }
 
@@ -129,7 +133,7 @@ size_t ws_bytes(const dg_grid* g, int mode) {
     size_t b = 4 * L * sizeof(double) + 2 * F;          // x, r, p0, p1; s1, s2
     b += (size_t)blocks * 4 * sizeof(double);           // partials
     b += sizeof(CgScalars) + kCntBytes + 4 * sizeof(double);
-    if ((mode & ~DG_WS_FD) == DG_PREC_MIXED) b += 3 * L * sizeof(float);
+    if (prec_of(mode) == DG_PREC_MIXED) b += 3 * L * sizeof(float);
     if (mode & DG_WS_FD)
         b += L * sizeof(double) + F + 3 * sizeof(CgScalars) + fd_bytes(g);   // z, wbak, sc3
     return b;
@@ -445,7 +449,7 @@ int cg_dispatch(const dg_grid* g, const double* omega, double* x, const double* 
         return cg_pcg(g, omega, x, pa, ca, pb, cb, o, o.precision == DG_PREC_MIXED, st, ws, s);
     }
     if (o.precision == DG_PREC_MIXED) {
-        if ((ws->mode & ~DG_WS_FD) != DG_PREC_MIXED)
+        if (prec_of(ws->mode) != DG_PREC_MIXED)
             return fail(DG_E_WORKSPACE, "mixed precision needs a DG_PREC_MIXED workspace");
         return cg_mixed(g, omega, x, pa, ca, pb, cb, o, st, ws, s);
     }
@@ -620,7 +624,7 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
               alloc((void**)&ws->d.counters, kCntBytes) &&
               alloc((void**)&ws->d.partials, (size_t)blocks * 4 * sizeof(double)) &&
               alloc((void**)&ws->d.out3, 4 * sizeof(double));
-    if (ok && (mode & ~DG_WS_FD) == DG_PREC_MIXED) {
+    if (ok && prec_of(mode) == DG_PREC_MIXED) {
         const size_t f32 = L * sizeof(float);
         ok = alloc((void**)&ws->r32, f32) && alloc((void**)&ws->q0, f32) &&
              alloc((void**)&ws->q1, f32);
@@ -660,7 +664,7 @@ int dg_workspace_create(const dg_grid* g, int mode, dg_workspace** out) {
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { dg_workspace_destroy(ws); return hip_fail(e, "workspace init"); }
     if (mode & DG_WS_FD) {
-        const int rc = fd_create(g, &ws->fd);
+        const int rc = fd_create(g, (mode & DG_WS_FD_PRODUCTS) != 0, &ws->fd);
         if (rc != DG_OK) { dg_workspace_destroy(ws); return rc; }
     }
     ws->bytes = ws_bytes(g, mode) + fd_extra_bytes(ws->fd);

@@ -83,7 +83,7 @@ int solve_poisson(const dg_grid* g, const double* omega, double* x, const double
 size_t fd_bytes(const dg_grid* g);
 int fd_supported(const dg_grid* g);     // DG_OK, or DG_E_UNSUPPORTED with the reason
 bool fd_uses_fft(int nx, int ny);       // periodic grids: FFT (else GEMM) cell transforms
-int fd_create(const dg_grid* g, FdDevice** out);
+int fd_create(const dg_grid* g, bool products, FdDevice** out);   // products: no FFTs
 size_t fd_extra_bytes(const FdDevice* fd);   // library work buffers beyond fd_bytes
 void fd_destroy(FdDevice* fd);
 int fd_apply_image(const FdDevice* fd, bool fp32, hipStream_t s);

@@ -525,7 +525,7 @@ int fd_create_dense(const dg_grid* g, FdDevice* fd) {
 
 }  // namespace
 
-int fd_create(const dg_grid* g, FdDevice** out) {
+int fd_create(const dg_grid* g, bool products, FdDevice** out) {
     *out = nullptr;
     int rc0 = fd_supported(g);
     if (rc0 != DG_OK) return rc0;
@@ -552,7 +552,7 @@ int fd_create(const dg_grid* g, FdDevice** out) {
         *out = fd;
         return DG_OK;
     }
-    fd->use_fft = fd_uses_fft(g->nx, g->ny);
+    fd->use_fft = !products && fd_uses_fft(g->nx, g->ny);
     FdFactors fx, fy;
     double ex = 0.0, ey = 0.0;
     if (!fd_axis_factors(g->t, g->nx, g->hx, &fx, &ex, !fd->use_fft) ||

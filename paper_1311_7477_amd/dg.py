@@ -21,6 +21,7 @@ DG_E_NOCONV, DG_E_UNSUPPORTED, DG_E_WORKSPACE = -5, -6, -7
 DG_BC_PERIODIC, DG_BC_DIRICHLET = 0, 1
 DG_PREC_FP64, DG_PREC_MIXED = 0, 1
 DG_WS_FD = 0x10
+DG_WS_FD_PRODUCTS = 0x20      # with DG_WS_FD: folded matrix products, no rocFFT plans
 DG_PRECOND_NONE, DG_PRECOND_FD = 0, 1
 DG_FORM_ARAKAWA, DG_FORM_PP, DG_FORM_PX, DG_FORM_XP = 0, 1, 2, 3
 

@@ -235,10 +235,28 @@ class Server:
         return [r for r in reqs if not math.isnan(r.finished) and r.error is None]
 
 
+# Preconditioner workspaces of requests with at most this many cells per
+# axis transform with the folded matrix products (DG_WS_FD_PRODUCTS): a
+# request is about 100 steps, and the rocFFT plans of a new grid size (kernels
+# compiled per transform length: 1-2 s) cost more there than the products
+# lose per step (n = 4, 338^2: 1.3 s of set-up, against 0.46 ms per step that
+# the products lose).
+PRODUCTS_MAX_CELLS = 512
+
+
+def ws_mode(N, precond=True):
+    """Workspace mode of a request on an N x N grid."""
+    if not precond:
+        return dg.DG_PREC_FP64
+    mode = dg.DG_PREC_FP64 | dg.DG_WS_FD
+    return mode | dg.DG_WS_FD_PRODUCTS if N <= PRODUCTS_MAX_CELLS else mode
+
+
 class StreamServer(Server):
     """The request loop of Server with one stream and one host worker per
     request: admission creates the request's grid, a DG_WS_FD workspace (the
-    preconditioner's bases and plans), its state and a HIP stream, then
+    preconditioner's bases and plans; the folded products up to
+    PRODUCTS_MAX_CELLS cells per axis), its state and a HIP stream, then
     hands the request to a worker thread that runs all of its steps on that
     stream (the library's calls release the GIL and each waits only for its
     own stream).  The main loop never waits for a step: it retires requests
@@ -265,7 +283,7 @@ class StreamServer(Server):
         state (five fields) and omega; admission replaces it by the bytes
         the workspace reports once created."""
         g = dg.Grid(req.n, req.N, req.N)
-        return g.workspace_bytes(dg.DG_PREC_FP64 | dg.DG_WS_FD) + STATE_FIELDS * g.elems * 8
+        return g.workspace_bytes(ws_mode(req.N)) + STATE_FIELDS * g.elems * 8
 
     def admit(self, req: Request, now: float):
         import torch
@@ -274,7 +292,7 @@ class StreamServer(Server):
         req.stream = torch.cuda.Stream()
         try:
             with torch.cuda.stream(req.stream):
-                req.ws = dg.Workspace(req.grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+                req.ws = dg.Workspace(req.grid, ws_mode(req.N))
         except dg.DgError as e:
             req.grid = req.ws = req.stream = None
             if e.code != dg.DG_E_NOMEM or not self.active:
@@ -386,7 +404,7 @@ def run_alone(req: Request, opts=None, tiles=None):
     if tiles is not None:
         grid.set_tiles(*tiles)
     precond = opts is not None and opts.precond != dg.DG_PRECOND_NONE
-    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | (dg.DG_WS_FD if precond else 0))
+    ws = dg.Workspace(grid, ws_mode(req.N, precond))
     st = dg.State(grid)
     w = torch.from_numpy(w0).cuda()
     for _ in range(req.steps):

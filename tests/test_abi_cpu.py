@@ -187,6 +187,13 @@ def test_workspace_bytes_and_field_size():
     assert h.workspace_bytes(dg.DG_PREC_FP64) >= 4 * L * 8 + 2 * h.elems * 8
     with pytest.raises(dg.DgError):
         g.workspace_bytes(7)
+    # the product-path option changes no allocation and needs DG_WS_FD
+    assert g.workspace_bytes(dg.DG_WS_FD | dg.DG_WS_FD_PRODUCTS) == bfd
+    assert (g.workspace_bytes(dg.DG_PREC_MIXED | dg.DG_WS_FD | dg.DG_WS_FD_PRODUCTS)
+            == g.workspace_bytes(dg.DG_PREC_MIXED | dg.DG_WS_FD))
+    with pytest.raises(dg.DgError) as e:
+        g.workspace_bytes(dg.DG_WS_FD_PRODUCTS)
+    assert e.value.code == dg.DG_E_INVAL
     # a Dirichlet axis: two dense work images and per axis the dense
     # (n N)^2 eigenbasis and n N eigenvalues in FP64 and FP32
     def dense(N, n):

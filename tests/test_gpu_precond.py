@@ -90,6 +90,34 @@ def test_precond_apply_parity(dg, n, nx, ny, lx, ly):
     assert _wn(g, b + O.laplacian(g, got)) <= 1e-11 * _wn(g, b)
 
 
+@pytest.mark.parametrize("n,nx,ny,lx,ly", [c for c in CASES
+                                            if c[1] % 2 == 0 and c[2] % 2 == 0
+                                            and max(c[1], c[2]) > 32])
+def test_precond_apply_products_option(dg, n, nx, ny, lx, ly):
+    # grids that take the FFT path by default, with DG_WS_FD_PRODUCTS: the
+    # folded matrix products, against the oracle at the same bar, and against
+    # the FFT path (two exact inverses: within 2e-14 kappa)
+    print(f"precond apply (products) n={n} nx={nx} ny={ny}", flush=True)
+    g = O.Grid2D(n, nx, ny, 0.0, lx, 0.0, ly)
+    r = I.white_noise(n, nx, ny, seed=5 * n + nx) + 0.7
+    grid = dg.Grid(n, nx, ny, 0.0, lx, 0.0, ly)
+    ws_p = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD | dg.DG_WS_FD_PRODUCTS)
+    ws_f = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    got = dg.precond_apply(grid, _dev(r), ws_p).cpu().numpy()
+    fft = dg.precond_apply(grid, _dev(r), ws_f).cpu().numpy()
+    fd = O.FastDiagonalisation(g)
+    ref = fd.apply(r)
+    inv = np.abs(fd.inv_mu[fd.inv_mu != 0])
+    kappa = inv.max() / inv.min()
+    scale = np.max(np.abs(ref))
+    d = (got - O.wmean(g, got)) - (ref - O.wmean(g, ref))
+    assert np.max(np.abs(d)) <= 2e-14 * kappa * scale
+    d = (got - O.wmean(g, got)) - (fft - O.wmean(g, fft))
+    assert np.max(np.abs(d)) <= 2e-14 * kappa * scale
+    b = r - O.wmean(g, r)
+    assert _wn(g, b + O.laplacian(g, got)) <= 1e-11 * _wn(g, b)
+
+
 def _pcg(dg, n, nx, ny, w, rtol, guess=None, precond=True, max_iter=100000, mixed=False):
     grid = dg.Grid(n, nx, ny)
     ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
