@@ -30,8 +30,12 @@ def test_traffic_lookup_follows_the_kernel_sources(tmp_path, monkeypatch):
     if t["kernel_source_sha256_16"] == bench.kernel_source_hash():
         for cw in (4, 8, 16):
             b = bench.measured_traffic(F, cw)
-            # at least the algorithmic 5F, at most the 5F plus the halo rows
-            assert 5 * F <= b <= 1.4 * 5 * F
+            # at least the algorithmic 4.5F per launch (odd k 3F, even k 6F:
+            # x is updated every other iteration), at most that plus the halo
+            assert 4.5 * F <= b <= 1.4 * 4.5 * F
+            par = t["by_parity"][str(cw)]
+            assert 3 * F <= par["odd_k"] <= 1.4 * 3 * F
+            assert 6 * F <= par["even_k"] <= 1.4 * 6 * F
     # a summary taken on other sources is not reported
     stale = dict(t, kernel_source_sha256_16="0" * 16)
     p = tmp_path / "traffic.json"
