@@ -196,3 +196,37 @@ def test_lamb_dipole_drift_j_against_jpp(dg):
         rP = drift[1, 1e-3][q] / drift[1, 5e-4][q]
         assert 6.0 < rJ < 10.0 and drift[0, 1e-3][q] < 2e-5, drift
         assert 0.9 < rP < 1.1 and drift[1, 5e-4][q] > 1e-4, drift
+
+
+def test_preconditioned_steps_queued_and_redone_against_oracle(dg):
+    # FP64 preconditioned RK3 steps run queued ahead: one PCG iteration per
+    # stage, the three stages' scalars checked once per step (the fallback to
+    # polled solves, for a stage that needs more, runs in the full-size
+    # first-step test above, whose first stage starts from a zero guess).
+    # Here every stage converges in one iteration on both sides; four steps,
+    # each against the oracle's within 1e-12 in the relative W-norm, so the
+    # queued stages' guesses (the extrapolated history) are checked too.
+    n, N, D = 3, 40, 1e-2
+    print(f"queued preconditioned steps n={n} N={N}", flush=True)
+    w0, umax = I.random_spectrum(n, N, k0=4.0, seed=7, return_umax=True)
+    dt = I.cfl_dt(n, N, umax)
+    g = O.Grid2D(n, N, N)
+    fd = O.FastDiagonalisation(g)
+    grid = dg.Grid(n, N, N)
+    ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+    st = dg.State(grid)
+    w = _dev(w0)
+    opts = dg.cg_opts(rtol=1e-12, precond=dg.DG_PRECOND_FD)
+    wref, hist, t = w0.copy(), O.PsiHistory(), 0.0
+    iters = []
+    for k in range(4):
+        wref, its = O.rk3_step_pcg(g, wref, t, dt, D, hist, rtol=1e-12, max_iter=20,
+                                   precond=fd.apply)
+        t += dt
+        res = dg.rk_step(grid, w, st, ws, dt, D, opts)
+        assert res.converged
+        assert all(abs(a - b) <= 1 for a, b in zip(res.cg_iters, its)), (k, res.cg_iters, its)
+        iters.append(tuple(res.cg_iters))
+        rel = _wnorm_rel(g, w.cpu().numpy(), wref)
+        assert rel <= 1e-12, (k, rel)
+    assert all(i == 1 for step in iters for i in step), iters
