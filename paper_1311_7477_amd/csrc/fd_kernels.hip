@@ -381,7 +381,12 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
 // (k < H) has as unnormalised inverse transform the even (real part) and odd
 // (imaginary part) samples of the real inverse transform of Y.  Wave numbers
 // k and H - k take the same two values, so the blocks of wave pair p serve
-// both (p = 0 with H).  The orthonormal cos / sin coefficients of wave number k are
+// both (p = 0 with H, both in column 0).  For even H the wave number H/2 =
+// N/4 is its own partner; its column rides in pair 0's partner slot, which
+// would otherwise hold column 0 a second time, so the pairs are p = 0 .. P - 1
+// with P = H/2 (even H) or (H + 1)/2 (odd H), and a launch has no chunk of
+// pairs holding H/2 alone.  The orthonormal cos / sin coefficients of wave
+// number k are
 // sqrt(2/N) (Re X_k, -Im X_k) (k = 0 and N/2: 1/sqrt(N) Re X_k), and the
 // real inverse transform of Y_k = sqrt(2/N)/2 (a - i b), Y_0 and Y_{N/2} =
 // 1/sqrt(N) a, rebuilds sum a cos + b sin.  The mixing kernels convert
@@ -418,19 +423,30 @@ __device__ __forceinline__ C coef_to_spec(bool pair, T cn, T cp, T a, T b) {
     return z;
 }
 
-// The wave numbers of block row p (H = N/2): k[0] = p and, unless p = H - p,
-// k[1] = H - p; the two spectrum rows it reads are p and (H - p) mod H; (c, s)
-// = (cos, sin) of 2 pi k / N, evaluated in FP64.
+// Wave pairs of a packed spectrum of half length H (see above).
+__host__ __device__ constexpr int spec_pairs(long H) {
+    return (int)((H & 1) ? (H + 1) / 2 : H / 2);
+}
+
+// The column held in pair p's partner slot: H - p, or for p = 0 the column
+// H/2 (even H) or 0 (odd H).
+__device__ __forceinline__ long partner_col(int p, long H) {
+    return p ? H - p : ((H & 1) ? 0 : H / 2);
+}
+
+// The wave numbers of pair p (H = N/2): k0 = p and k1 = H - p, with (c, s) =
+// (cos, sin) of 2 pi k / N evaluated in FP64; mid: pair 0 of an even H also
+// carries the wave number H/2 (cos, sin of pi/2 = 0, 1 exactly).
 template <class T>
 struct WavePair {
-    int nw, k0, k1, q;
+    int k0, k1;
+    bool mid;
     T c0, s0, c1, s1;
     __device__ WavePair(int p, int N) {
         const int H = N / 2;
         k0 = p;
         k1 = H - p;
-        nw = k1 == p ? 1 : 2;
-        q = (H - p) % H;
+        mid = p == 0 && !(H & 1);
         c0 = T(cospi(2.0 * k0 / N));
         s0 = T(sinpi(2.0 * k0 / N));
         c1 = T(cospi(2.0 * k1 / N));
@@ -531,7 +547,7 @@ __device__ __forceinline__ void spec_load(const typename CplxOf<T>::type* __rest
         v[it].x = T(0);
         v[it].y = T(0);
         if (pp < P && a0 + a < A) {
-            const long col = s ? (pp == 0 ? 0 : H - pp) : pp;    // (H - pp) mod H
+            const long col = s ? partner_col(pp, H) : pp;
             v[it] = Z[(base + a0 + a + stride * i) * H + col];
         }
     }
@@ -544,8 +560,9 @@ __device__ __forceinline__ void spec_load(const typename CplxOf<T>::type* __rest
     }
 }
 
-// Store the tile back: column p from s = 0 and column H - p from s = 1
-// (p > 0 with H - p != p; column 0 packs the wave numbers 0 and H).
+// Store the tile back: column p from s = 0 and the partner column from s = 1
+// (except pair 0 of an odd H, whose partner slot repeats column 0; column 0
+// packs the wave numbers 0 and H).
 template <int N, class T>
 __device__ __forceinline__ void spec_store(typename CplxOf<T>::type* __restrict__ Z, long H,
                                            int P, int p0, int a0, int A, long base, long stride,
@@ -559,8 +576,8 @@ __device__ __forceinline__ void spec_store(typename CplxOf<T>::type* __restrict_
         spec_elem<TL::TP>(e, p, s, a, i);
         const int pp = p0 + p;
         if (pp >= P || a0 + a >= A) continue;
-        if (s && (pp == 0 || H - pp == pp)) continue;
-        const long col = s ? H - pp : pp;
+        if (s && pp == 0 && (H & 1)) continue;
+        const long col = s ? partner_col(pp, H) : pp;
         Z[(base + a0 + a + stride * i) * H + col] = L[TL::at(i, s, p, a)];
     }
 }
@@ -582,18 +599,21 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_fwd(
     const int ab = (Ny + 63) / 64;
     const int j = rb / ab, a0 = (rb - j * ab) * 64;
     const long H = Nx / 2, base = (long)Ny * N * j;
-    const int P = Nx / 4 + 1, p0 = pc * TL::TP;
+    const int P = spec_pairs(H), p0 = pc * TL::TP;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), a = threadIdx.x & 63;
     const int p = p0 + w, cy = a0 + a;
     spec_load<N, T>(Z, H, P, p0, a0, Ny, base, Ny, L);
     __syncthreads();
     if (p >= P || cy >= Ny) return;
     const WavePair<T> wp(p, Nx);
+    // pair 0 reads column 0 for both of its wave numbers (the partner slot
+    // holds the wave number H/2 of an even H, done last)
+    const int sb = p ? 1 : 0;
     C za[N], zb[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         za[i] = L[TL::at(i, 0, w, a)];
-        zb[i] = L[TL::at(i, 1, w, a)];
+        zb[i] = L[TL::at(i, sb, w, a)];
     }
     const long out0 = cy + (long)Ny * N * Nx * j;
     // wave number k from its own half-spectrum value and its partner's
@@ -614,7 +634,13 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_fwd(
         });
     };
     one(wp.k0, Mf + (size_t)wp.k0 * S * S, za, zb, wp.c0, wp.s0);
-    if (wp.nw == 2) one(wp.k1, Mf + (size_t)wp.k1 * S * S, zb, za, wp.c1, wp.s1);
+    one(wp.k1, Mf + (size_t)wp.k1 * S * S, zb, za, wp.c1, wp.s1);
+    if (wp.mid) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) za[i] = L[TL::at(i, 1, w, a)];
+        const int km = (int)(H / 2);
+        one(km, Mf + (size_t)km * S * S, za, za, T(0), T(1));
+    }
 }
 
 // Inverse x mixing: U1 (real coefficients) -> the packed x spectra, ready for
@@ -633,7 +659,7 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_inv(
     const int ab = (Ny + 63) / 64;
     const int j = rb / ab, a0 = (rb - j * ab) * 64;
     const long H = Nx / 2, base = (long)Ny * N * j;
-    const int P = Nx / 4 + 1, p0 = pc * TL::TP;
+    const int P = spec_pairs(H), p0 = pc * TL::TP;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), a = threadIdx.x & 63;
     const int p = p0 + w, cy = a0 + a;
     __syncthreads();
@@ -659,16 +685,18 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_inv(
         };
         C y0[N], y1[N];
         one(wp.k0, Mi + (size_t)wp.k0 * S * S, y0);
-        if (wp.nw == 2) {
-            one(wp.k1, Mi + (size_t)wp.k1 * S * S, y1);
-        } else {
-#pragma unroll
-            for (int i = 0; i < N; ++i) y1[i] = y0[i];
-        }
+        one(wp.k1, Mi + (size_t)wp.k1 * S * S, y1);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             L[TL::at(i, 0, w, a)] = pack_half(y0[i], y1[i], wp.c0, wp.s0);
             L[TL::at(i, 1, w, a)] = pack_half(y1[i], y0[i], wp.c1, wp.s1);
+        }
+        if (wp.mid) {
+            // the wave number H/2 is its own partner
+            const int km = (int)(H / 2);
+            one(km, Mi + (size_t)km * S * S, y0);
+#pragma unroll
+            for (int i = 0; i < N; ++i) L[TL::at(i, 1, w, a)] = pack_half(y0[i], y0[i], T(0), T(1));
         }
     }
     __syncthreads();
@@ -693,7 +721,7 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_y(
     int pc, rb;
     xcd_pair_block(pc, rb);
     const long NXn = (long)N * Nx, H = Ny / 2;
-    const int P = Ny / 4 + 1, p0 = pc * TL::TP, a0 = rb * 64;
+    const int P = spec_pairs(H), p0 = pc * TL::TP, a0 = rb * 64;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), a = threadIdx.x & 63;
     const int p = p0 + w;
     spec_load<N, T>(Z, H, P, p0, a0, (int)NXn, 0, NXn, L);
@@ -704,11 +732,14 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_y(
         const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
         const int xs = i * Nx + kx;
         const T lam_x = lx[xs];
+        // pair 0 reads column 0 for both of its wave numbers (the partner
+        // slot holds the wave number H/2 of an even H, done last)
+        const int sb = p ? 1 : 0;
         C za[N], zb[N];
 #pragma unroll
         for (int jj = 0; jj < N; ++jj) {
             za[jj] = L[TL::at(jj, 0, w, a)];
-            zb[jj] = L[TL::at(jj, 1, w, a)];
+            zb[jj] = L[TL::at(jj, sb, w, a)];
         }
         // wave number k: spectrum -> y modes, divided, -> spectrum
         auto one = [&](int k, const T* Mfk, const T* Mik, const C* zk, const C* zh, T c, T sn,
@@ -736,16 +767,22 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_y(
         };
         C y0[N], y1[N];
         one(wp.k0, Mf + (size_t)wp.k0 * S * S, Mi + (size_t)wp.k0 * S * S, za, zb, wp.c0, wp.s0, y0);
-        if (wp.nw == 2) {
-            one(wp.k1, Mf + (size_t)wp.k1 * S * S, Mi + (size_t)wp.k1 * S * S, zb, za, wp.c1, wp.s1, y1);
-        } else {
+        one(wp.k1, Mf + (size_t)wp.k1 * S * S, Mi + (size_t)wp.k1 * S * S, zb, za, wp.c1, wp.s1, y1);
+        if (wp.mid) {
 #pragma unroll
-            for (int jj = 0; jj < N; ++jj) y1[jj] = y0[jj];
+            for (int jj = 0; jj < N; ++jj) za[jj] = L[TL::at(jj, 1, w, a)];
         }
 #pragma unroll
         for (int jj = 0; jj < N; ++jj) {
             L[TL::at(jj, 0, w, a)] = pack_half(y0[jj], y1[jj], wp.c0, wp.s0);
             L[TL::at(jj, 1, w, a)] = pack_half(y1[jj], y0[jj], wp.c1, wp.s1);
+        }
+        if (wp.mid) {
+            const int km = (int)(H / 2);
+            one(km, Mf + (size_t)km * S * S, Mi + (size_t)km * S * S, za, za, T(0), T(1), y0);
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj)
+                L[TL::at(jj, 1, w, a)] = pack_half(y0[jj], y0[jj], T(0), T(1));
         }
     }
     __syncthreads();
@@ -895,7 +932,7 @@ hipError_t launch_fft_mix_x_fwd(int n, int Nx, int Ny, const int* cols, const T*
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
     DG_DISPATCH_N(n, {
         using TL = SpecTile<NN, T>;
-        const dim3 grid((Nx / 4 + 1 + TL::TP - 1) / TL::TP, ((Ny + 63) / 64) * NN);
+        const dim3 grid((spec_pairs(Nx / 2) + TL::TP - 1) / TL::TP, ((Ny + 63) / 64) * NN);
         hipLaunchKernelGGL((k_fft_mix_x_fwd<NN, T>), grid, dim3(TL::THREADS), 0, s, Nx, Ny,
                            cols, Mf, cn, cp, (const C*)X, u1);
     });
@@ -909,7 +946,7 @@ hipError_t launch_fft_mix_x_inv(int n, int Nx, int Ny, const int* cols, const T*
     const T cn = T(1.0 / std::sqrt((double)Nx)), cp = T(std::sqrt(2.0 / Nx));
     DG_DISPATCH_N(n, {
         using TL = SpecTile<NN, T>;
-        const dim3 grid((Nx / 4 + 1 + TL::TP - 1) / TL::TP, ((Ny + 63) / 64) * NN);
+        const dim3 grid((spec_pairs(Nx / 2) + TL::TP - 1) / TL::TP, ((Ny + 63) / 64) * NN);
         hipLaunchKernelGGL((k_fft_mix_x_inv<NN, T>), grid, dim3(TL::THREADS), 0, s, Nx, Ny,
                            cols, Mi, cn, cp, u1, (C*)X);
     });
@@ -924,7 +961,7 @@ hipError_t launch_fft_mix_y(int n, int Nx, int Ny, const int* cols, const T* Mf,
     const T cn = T(1.0 / std::sqrt((double)Ny)), cp = T(std::sqrt(2.0 / Ny));
     DG_DISPATCH_N(n, {
         using TL = SpecTile<NN, T>;
-        const dim3 grid((Ny / 4 + 1 + TL::TP - 1) / TL::TP, ((long)Nx * NN + 63) / 64);
+        const dim3 grid((spec_pairs(Ny / 2) + TL::TP - 1) / TL::TP, ((long)Nx * NN + 63) / 64);
         hipLaunchKernelGGL((k_fft_mix_y<NN, T>), grid, dim3(TL::THREADS), 0, s, Nx, Ny, cols,
                            Mf, Mi, lx, ly, zx, zy, cn, cp, (C*)Y);
     });

@@ -66,7 +66,10 @@ CASES = [(1, 5, 4, 1.0, 1.3), (2, 6, 6, 2.0, 2.0), (3, 37, 23, 2.0, 1.5),
          # axis, the other axis below and above 512, a 6-cell axis (three
          # complex values per row); an odd count keeps the folded products
          (2, 1024, 96, 6.283185307179586, 3.0), (1, 522, 530, 1.0, 1.2),
-         (3, 516, 6, 1.5, 1.0), (1, 601, 520, 2.0, 2.5)]
+         (3, 516, 6, 1.5, 1.0), (1, 601, 520, 2.0, 2.5),
+         # a 4-cell axis on the FFT path: its one wave pair carries the wave
+         # numbers 0, 2 (column 0) and 1 (the partner slot)
+         (2, 40, 4, 1.0, 1.0)]
 
 
 @pytest.mark.parametrize("n,nx,ny,lx,ly", CASES)
