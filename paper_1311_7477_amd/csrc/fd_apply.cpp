@@ -506,6 +506,29 @@ void fd_destroy(FdDevice* fd) {
 
 namespace {
 
+// The FFT mixing kernels read only the first n rows of each 2n x 2n block:
+// rows n + q must be [-T1 | T0] of rows q = [T0 | T1], in the forward and
+// the inverse blocks, and the cos and sin modes of a wave number must share
+// their eigenvalues, exactly (the unshifted basis is built that way).
+static bool complex_blocks(const FdFactors& f) {
+    const int n = f.n, S = 2 * n;
+    for (int k = 0; k < f.K; ++k) {
+        if (f.csin[k] < 0) continue;
+        for (const std::vector<double>* m : {&f.mf, &f.mi}) {
+            const double* b = m->data() + (size_t)k * S * S;
+            for (int q = 0; q < n; ++q)
+                for (int p = 0; p < n; ++p)
+                    if (b[(n + q) * S + p] != -b[q * S + n + p] ||
+                        b[(n + q) * S + n + p] != b[q * S + p])
+                        return false;
+        }
+        for (int a = 0; a < n; ++a)
+            if (f.lam[(size_t)a * f.N + f.ccos[k]] != f.lam[(size_t)a * f.N + f.csin[k]])
+                return false;
+    }
+    return true;
+}
+
 int fd_create_dense(const dg_grid* g, FdDevice* fd) {
     const size_t img = (size_t)g->n * g->n * g->nx * g->ny * sizeof(double);
     if (hipMalloc((void**)&fd->img0, img) != hipSuccess ||
@@ -563,6 +586,10 @@ int fd_create(const dg_grid* g, bool products, FdDevice** out) {
     if (ex > 1e-10 || ey > 1e-10) {
         delete fd;
         return fail(DG_E_INVAL, "eigenbasis defect %.3e too large", ex > ey ? ex : ey);
+    }
+    if (fd->use_fft && (!complex_blocks(fx) || (!fd->shared && !complex_blocks(fy)))) {
+        delete fd;
+        return fail(DG_E_INVAL, "mixing blocks lack the structure the FFT mixing kernels use");
     }
     bool ok = upload_axis(fx, &fd->x);
     if (ok && fd->shared) fd->y = fd->x;

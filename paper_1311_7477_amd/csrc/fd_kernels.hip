@@ -423,6 +423,36 @@ __device__ __forceinline__ C coef_to_spec(bool pair, T cn, T cp, T a, T b) {
     return z;
 }
 
+// out = M v for the mixing blocks of the unshifted basis, which have the
+// structure of a complex product: rows n + q are [-T1 | T0] of rows q =
+// [T0 | T1] (forward and inverse alike, exactly: the same products with one
+// sign flipped), so only the first n rows are read and every output keeps
+// the summation order of the full product.  PAIR false: the n x n block.
+template <int N, class T, bool PAIR>
+__device__ __forceinline__ void mix_vec_c(const T* __restrict__ M, const T* v, T* out) {
+    constexpr int S = 2 * N;
+    if constexpr (!PAIR) {
+        mix_vec<N, T, false>(M, v, out);
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            T top = 0, bot = 0;
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                top = fma(M[q * S + p], v[p], top);
+                bot = fma(-M[q * S + N + p], v[p], bot);
+            }
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                top = fma(M[q * S + N + p], v[N + p], top);
+                bot = fma(M[q * S + p], v[N + p], bot);
+            }
+            out[q] = top;
+            out[N + q] = bot;
+        }
+    }
+}
+
 // Wave pairs of a packed spectrum of half length H (see above).
 __host__ __device__ constexpr int spec_pairs(long H) {
     return (int)((H & 1) ? (H + 1) / 2 : H / 2);
@@ -625,7 +655,7 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_fwd(
 #pragma unroll
             for (int i = 0; i < N; ++i)
                 spec_to_coef(unpack_half(zk[i], zh[i], c, sn), PAIR, cn, cp, v[i], v[N + i]);
-            mix_vec<N, T, PAIR>(Mk, v, o);
+            mix_vec_c<N, T, PAIR>(Mk, v, o);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 u1[out0 + (long)Ny * (i + (long)N * c0)] = o[i];
@@ -677,7 +707,7 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_x_inv(
                     v[i] = u1[in0 + (long)Ny * (i + (long)N * c0)];
                     if (PAIR) v[N + i] = u1[in0 + (long)Ny * (i + (long)N * c1)];
                 }
-                mix_vec<N, T, PAIR>(Mk, v, o);
+                mix_vec_c<N, T, PAIR>(Mk, v, o);
 #pragma unroll
                 for (int i = 0; i < N; ++i)
                     y[i] = coef_to_spec<C>(PAIR, cn, cp, o[i], PAIR ? o[N + i] : T(0));
@@ -753,13 +783,17 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_y(
                 for (int jj = 0; jj < N; ++jj)
                     spec_to_coef(unpack_half(zk[jj], zh[jj], c, sn), PAIR, cn, cp, v[jj],
                                  v[N + jj]);
-                mix_vec<N, T, PAIR>(Mfk, v, o);
+                mix_vec_c<N, T, PAIR>(Mfk, v, o);
+                // the cos and sin modes of one (b, k) share the eigenvalue
+                // ly[b Ny + c0]; the constant mode is a cos mode (k = 0)
 #pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int ys = (q % N) * Ny + (q < N ? c0 : c1);
-                    o[q] = (xs == zx && ys == zy) ? T(0) : -o[q] * recip(lam_x + ly[ys]);
+                for (int q = 0; q < N; ++q) {
+                    const int ys = q * Ny + c0;
+                    const T r = recip(lam_x + ly[ys]);
+                    o[q] = (xs == zx && ys == zy) ? T(0) : -o[q] * r;
+                    if (PAIR) o[N + q] = -o[N + q] * r;
                 }
-                mix_vec<N, T, PAIR>(Mik, o, v);
+                mix_vec_c<N, T, PAIR>(Mik, o, v);
 #pragma unroll
                 for (int jj = 0; jj < N; ++jj)
                     y[jj] = coef_to_spec<C>(PAIR, cn, cp, v[jj], PAIR ? v[N + jj] : T(0));
