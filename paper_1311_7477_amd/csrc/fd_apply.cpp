@@ -506,10 +506,12 @@ void fd_destroy(FdDevice* fd) {
 
 namespace {
 
-// The FFT mixing kernels read only the first n rows of each 2n x 2n block:
-// rows n + q must be [-T1 | T0] of rows q = [T0 | T1], in the forward and
-// the inverse blocks, and the cos and sin modes of a wave number must share
-// their eigenvalues, exactly (the unshifted basis is built that way).
+// The mixing kernels read only the first n rows of each 2n x 2n block: rows
+// n + q must be [-T1 | T0] of rows q = [T0 | T1], in the forward and the
+// inverse blocks, and the cos and sin modes of a wave number must share their
+// eigenvalues, exactly (both cell Fourier bases are built that way: the
+// shifted one is the unshifted one times a rotation per node, itself a
+// complex product).
 static bool complex_blocks(const FdFactors& f) {
     const int n = f.n, S = 2 * n;
     for (int k = 0; k < f.K; ++k) {
@@ -587,9 +589,9 @@ int fd_create(const dg_grid* g, bool products, FdDevice** out) {
         delete fd;
         return fail(DG_E_INVAL, "eigenbasis defect %.3e too large", ex > ey ? ex : ey);
     }
-    if (fd->use_fft && (!complex_blocks(fx) || (!fd->shared && !complex_blocks(fy)))) {
+    if (!complex_blocks(fx) || (!fd->shared && !complex_blocks(fy))) {
         delete fd;
-        return fail(DG_E_INVAL, "mixing blocks lack the structure the FFT mixing kernels use");
+        return fail(DG_E_INVAL, "mixing blocks lack the structure the mixing kernels use");
     }
     bool ok = upload_axis(fx, &fd->x);
     if (ok && fd->shared) fd->y = fd->x;

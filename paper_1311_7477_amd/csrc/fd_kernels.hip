@@ -236,6 +236,37 @@ __device__ __forceinline__ void mix_vec(const T* __restrict__ M, const T* v, T* 
     }
 }
 
+// out = M v for the mixing blocks, which have the structure of a complex
+// product: rows n + q are [-T1 | T0] of rows q = [T0 | T1] (forward and
+// inverse, unshifted and shifted bases alike, exactly: the same products with
+// one sign flipped; the host checks it), so only the first n rows are read
+// and every output keeps the summation order of the full product.  PAIR
+// false: the n x n block.
+template <int N, class T, bool PAIR>
+__device__ __forceinline__ void mix_vec_c(const T* __restrict__ M, const T* v, T* out) {
+    constexpr int S = 2 * N;
+    if constexpr (!PAIR) {
+        mix_vec<N, T, false>(M, v, out);
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            T top = 0, bot = 0;
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                top = fma(M[q * S + p], v[p], top);
+                bot = fma(-M[q * S + N + p], v[p], bot);
+            }
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                top = fma(M[q * S + N + p], v[N + p], top);
+                bot = fma(M[q * S + p], v[N + p], bot);
+            }
+            out[q] = top;
+            out[N + q] = bot;
+        }
+    }
+}
+
 // 1 / d from the hardware reciprocal refined by Newton's iteration
 // r <- r + r (1 - d r) (twice in FP64, once in FP32): within about one ulp
 // of the correctly rounded quotient at a fraction of an IEEE division's
@@ -304,8 +335,8 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_x_fold(int Nx, int Ny, in
                 vb[i] = a0 - b0;
                 vb[N + i] = a1 - b1;
             }
-            mix_vec<N, T, PAIR>(Mk, va, wa);
-            if (pr) mix_vec<N, T, PAIR>(Mk, vb, wb);
+            mix_vec_c<N, T, PAIR>(Mk, va, wa);
+            if (pr) mix_vec_c<N, T, PAIR>(Mk, vb, wb);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 out[w0 + s0 + (long)Ny * i] = wa[i];
@@ -340,7 +371,6 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
     const long NXn = (long)N * Nx;
     with_pair(pair, [&](auto pc) {
         constexpr bool PAIR = decltype(pc)::value;
-        constexpr int R = PAIR ? S : N;
         for (long m = blockIdx.x * (long)kPwThreads + threadIdx.x; m < NXn;
              m += (long)gridDim.x * kPwThreads) {
             const int kx = (int)(m / N), i = (int)(m - (long)kx * N);
@@ -354,13 +384,17 @@ __global__ __launch_bounds__(kPwThreads) void k_fd_mix_y(
                 v[j] = u[o0 + NXn * j];
                 if (PAIR) v[N + j] = u[o1 + NXn * j];
             }
-            mix_vec<N, T, PAIR>(Mfk, v, w);
+            mix_vec_c<N, T, PAIR>(Mfk, v, w);
+            // the cos and sin modes of one (b, k) share the eigenvalue
+            // ly[b Ny + c0]; the constant mode is a cos mode (k = 0)
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int ys = (q % N) * Ny + (q < N ? c0 : c1);
-                w[q] = (xs == zx && ys == zy) ? T(0) : -w[q] * recip(lam_x + ly[ys]);
+            for (int q = 0; q < N; ++q) {
+                const int ys = q * Ny + c0;
+                const T r = recip(lam_x + ly[ys]);
+                w[q] = (xs == zx && ys == zy) ? T(0) : -w[q] * r;
+                if (PAIR) w[N + q] = -w[N + q] * r;
             }
-            mix_vec<N, T, PAIR>(Mik, w, v);
+            mix_vec_c<N, T, PAIR>(Mik, w, v);
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 u[o0 + NXn * j] = v[j];
@@ -421,36 +455,6 @@ __device__ __forceinline__ C coef_to_spec(bool pair, T cn, T cp, T a, T b) {
         z.y = T(0);
     }
     return z;
-}
-
-// out = M v for the mixing blocks of the unshifted basis, which have the
-// structure of a complex product: rows n + q are [-T1 | T0] of rows q =
-// [T0 | T1] (forward and inverse alike, exactly: the same products with one
-// sign flipped), so only the first n rows are read and every output keeps
-// the summation order of the full product.  PAIR false: the n x n block.
-template <int N, class T, bool PAIR>
-__device__ __forceinline__ void mix_vec_c(const T* __restrict__ M, const T* v, T* out) {
-    constexpr int S = 2 * N;
-    if constexpr (!PAIR) {
-        mix_vec<N, T, false>(M, v, out);
-    } else {
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            T top = 0, bot = 0;
-#pragma unroll
-            for (int p = 0; p < N; ++p) {
-                top = fma(M[q * S + p], v[p], top);
-                bot = fma(-M[q * S + N + p], v[p], bot);
-            }
-#pragma unroll
-            for (int p = 0; p < N; ++p) {
-                top = fma(M[q * S + N + p], v[N + p], top);
-                bot = fma(M[q * S + p], v[N + p], bot);
-            }
-            out[q] = top;
-            out[N + q] = bot;
-        }
-    }
 }
 
 // Wave pairs of a packed spectrum of half length H (see above).
