@@ -781,7 +781,6 @@ __global__ __launch_bounds__(2048 / sizeof(T)) void k_fft_mix_y(
             const int c0 = cols[2 * k], c1 = cols[2 * k + 1];
             with_pair(c1 >= 0, [&](auto pc) {
                 constexpr bool PAIR = decltype(pc)::value;
-                constexpr int R = PAIR ? S : N;
                 T v[S], o[S];
 #pragma unroll
                 for (int jj = 0; jj < N; ++jj)
