@@ -68,8 +68,10 @@ CASES = [(1, 5, 4, 1.0, 1.3), (2, 6, 6, 2.0, 2.0), (3, 37, 23, 2.0, 1.5),
          (2, 1024, 96, 6.283185307179586, 3.0), (1, 522, 530, 1.0, 1.2),
          (3, 516, 6, 1.5, 1.0), (1, 601, 520, 2.0, 2.5),
          # a 4-cell axis on the FFT path: its one wave pair carries the wave
-         # numbers 0, 2 (column 0) and 1 (the partner slot)
-         (2, 40, 4, 1.0, 1.0)]
+         # numbers 0, 2 (column 0) and 1 (the partner slot); short axes whose
+         # few pairs leave most of a tile's pair slots empty (8 cells: pairs
+         # 0, 1 and the merged wave number 2; 6 cells: half length 3, odd)
+         (2, 40, 4, 1.0, 1.0), (3, 48, 8, 2.0, 1.0), (2, 36, 6, 1.0, 1.5)]
 
 
 @pytest.mark.parametrize("n,nx,ny,lx,ly", CASES)
@@ -153,7 +155,7 @@ def test_pcg_parity(dg, n, nx, ny):
 
 @pytest.mark.parametrize("n,nx,ny", [(1, 9, 7), (2, 16, 16), (3, 37, 23), (4, 13, 29),
                                      (5, 24, 24), (3, 1, 5), (4, 64, 48), (1, 522, 530),
-                                     (2, 1024, 96)])
+                                     (2, 1024, 96), (3, 48, 8), (2, 36, 6)])
 def test_pcg_mixed_parity(dg, n, nx, ny):
     print(f"mixed pcg n={n} nx={nx} ny={ny}", flush=True)
     g = O.Grid2D(n, nx, ny)
