@@ -528,6 +528,10 @@ __device__ __forceinline__ void cg_dir_body(
     } else {
         zero_cell<N>(p);
     }
+    // <r, p>_W (FP32-stored directions) before the Laplacian, so that r is not
+    // held across it
+    double rp = 0.0;
+    if (kStoredLow<S> && c.active) rp = wdot_cell<N>(k, rv, p);
     lap_cell<N, WV, DIR, ISO>(c, k, src, p, lds, q);
     constexpr int NV = kStoredLow<S> ? 2 : 1;
     double part[NV];
@@ -538,7 +542,7 @@ __device__ __forceinline__ void cg_dir_body(
 #pragma unroll
         for (int e = 0; e < N * N; ++e) q[e] = -q[e];
         part[0] = wdot_cell<N>(k, p, q);
-        if (kStoredLow<S>) part[NV - 1] = wdot_cell<N>(k, rv, p);
+        if (kStoredLow<S>) part[NV - 1] = rp;
     }
     double tot[NV];
     if (reduce_last<NV, 64 * WV>(part, partials, counter, nblocks, b, tot) &&
