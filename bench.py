@@ -111,7 +111,11 @@ def form_batch(args):
     over [64, N_max], random spectra with peak k0 uniform over [4, 16]; the
     same members stepped one by one with dg_rk_step and together in one
     batch (fused launches, graph replay).  Reports aggregate
-    cell-updates/s per RHS of both and checks bitwise equality."""
+    cell-updates/s per RHS of both and checks bitwise equality.  With
+    --batch-precond fd or fd-products the members hold the fast-
+    diagonalisation preconditioner (with fd-products on the folded matrix
+    products, no FFT plans) and the batch steps them one after the other
+    through dg_rk_step, so the two runs differ only in the loop's place."""
     import numpy as np
     import torch
     from paper_1311_7477_amd import dg, inputs
@@ -124,7 +128,10 @@ def form_batch(args):
         w0, umax = inputs.random_spectrum(n, N, k0=k0, seed=int(rng.integers(1 << 30)),
                                           return_umax=True)
         members.append((n, N, w0, inputs.cfl_dt(n, N, umax, cfl=0.1)))
-    opts = dg.cg_opts(rtol=args.rtol)
+    fd_flags = {"none": 0, "fd": dg.DG_WS_FD,
+                "fd-products": dg.DG_WS_FD | dg.DG_WS_FD_PRODUCTS}[args.batch_precond]
+    opts = dg.cg_opts(rtol=args.rtol,
+                      precond=dg.DG_PRECOND_FD if fd_flags else dg.DG_PRECOND_NONE)
     cells = sum(N * N for (_, N, _, _) in members)
     steps = args.steps
 
@@ -140,7 +147,8 @@ def form_batch(args):
     for (n, N, w0, dt) in members:
         g = dg.Grid(n, N, N)
         g.set_tiles(*shapes[(n, N)])
-        singles.append((g, dg.Workspace(g), dg.State(g), torch.from_numpy(w0).cuda(), dt))
+        singles.append((g, dg.Workspace(g, dg.DG_PREC_FP64 | fd_flags), dg.State(g),
+                        torch.from_numpy(w0).cuda(), dt))
     print(f"[batch] {len(members)} members, {cells} cells, {len(shapes)} tuned shapes",
           file=sys.stderr, flush=True)
     for (g, ws, st, w, dt) in singles:            # warm-up step
@@ -158,6 +166,8 @@ def form_batch(args):
 
     # batched
     batch = dg.Batch(len(members))
+    if fd_flags:
+        batch.use_precond(fd_flags)
     bw = []
     for (n, N, w0, dt) in members:
         g = dg.Grid(n, N, N)
@@ -186,7 +196,8 @@ def form_batch(args):
         "config": {"workload": f"{args.members} instances, n~U{{2..5}}, N log-uniform "
                                f"[64,{args.N_max}], k0~U[4,16], D={args.D}, CFL 0.1, "
                                f"CG rtol {args.rtol}, seed 2",
-                   "total_cells": cells, "graphs": True},
+                   "total_cells": cells, "graphs": not fd_flags,
+                   "precond": args.batch_precond},
     }), flush=True)
 
 
@@ -887,6 +898,10 @@ def main():
     ap.add_argument("--N-max", dest="N_max", type=int, default=256)
     ap.add_argument("--N-min", dest="N_min", type=int, default=32,
                     help="--form serve: smallest grid of the request stream")
+    ap.add_argument("--batch-precond", dest="batch_precond", default="none",
+                    choices=["none", "fd", "fd-products"],
+                    help="--form batch: members with the fast-diagonalisation "
+                         "preconditioner (fd-products: on the folded matrix products)")
     ap.add_argument("--serve-solver", dest="serve_solver", default="batch",
                     choices=["batch", "pcg"],
                     help="--form serve: batched plain CG, or a stream per request with "

@@ -414,10 +414,23 @@ int  dg_batch_detach(dg_batch* b, int slot);
 int  dg_batch_member_bytes(const dg_grid* grid, size_t* bytes);
 /* 1 (default): replay captured HIP graphs; 0: launch kernels directly. */
 int  dg_batch_use_graphs(dg_batch* b, int on);
-/* One SSP-RK3 step of every attached instance (FP64 CG, opts->precision
- * must be DG_PREC_FP64 and opts->precond DG_PRECOND_NONE).  iters_out, if not NULL, receives the CG
- * iterations of slot i's stage k at [3 i + k] (capacity * 3 ints).
- * Synchronises the stream.  DG_E_NOCONV if some solve hit max_iter. */
+/* Give the members attached from now on workspaces with the fast-
+ * diagonalisation preconditioner (ws_fd_flags: DG_WS_FD, optionally with
+ * DG_WS_FD_PRODUCTS; 0: none, the default), so that dg_batch_rk_step can
+ * take opts->precond = DG_PRECOND_FD.  Such a member also holds
+ * dg_workspace_bytes(grid, DG_PREC_FP64 | ws_fd_flags) instead of the plain
+ * workspace, and two more fields of psi history.  Only while no member is
+ * attached: DG_E_INVAL otherwise, or for other flags. */
+int  dg_batch_use_precond(dg_batch* b, int ws_fd_flags);
+/* One SSP-RK3 step of every attached instance.  With opts->precond =
+ * DG_PRECOND_NONE (FP64 CG, opts->precision must be DG_PREC_FP64) the
+ * members advance together in fused launches.  With DG_PRECOND_FD (FP64 or
+ * DG_PREC_MIXED) each member takes its step through dg_rk_step on this
+ * stream in turn, with the same results as a stand-alone step
+ * (DG_E_WORKSPACE unless dg_batch_use_precond preceded the attaches).
+ * iters_out, if not NULL, receives the CG iterations of slot i's stage k at
+ * [3 i + k] (capacity * 3 ints).  Synchronises the stream.  DG_E_NOCONV if
+ * some solve hit max_iter (the step was still completed). */
 int  dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
                       void* stream);
 /* 1 if every solve of slot's last dg_batch_rk_step converged, 0 if one hit

@@ -78,6 +78,7 @@ struct dg_batch {
     hipStream_t cap = nullptr;     // capture stream
     bool use_graphs = true;
     bool graphs_valid = false;
+    int fd_flags = 0;              // preconditioner of the members' workspaces (0: none)
     int chunk = 16;                // CG iterations per captured chunk (even)
     hipGraphExec_t g_setup = nullptr, g_finish = nullptr;
     hipGraphExec_t g_chunk[kGroups] = {};   // CG chunk of each launch group
@@ -316,9 +317,11 @@ int dg_batch_attach(dg_batch* b, const dg_grid* g, double* omega, double dt,
     while (i < b->capacity && b->slots[i].used) ++i;
     if (i == b->capacity) return fail(DG_E_INVAL, "batch is full (%d slots)", b->capacity);
     Slot& sl = b->slots[i];
-    int rc = dg_workspace_create(g, DG_PREC_FP64, &sl.ws);
+    int rc = dg_workspace_create(g, DG_PREC_FP64 | b->fd_flags, &sl.ws);
     if (rc != DG_OK) return rc;
-    rc = state_create(g, t0, 3, &sl.st);    // batched steps are never queued ahead
+    // the fused steps are never queued ahead; preconditioned members step
+    // through dg_rk_step, whose queued steps keep two more psi buffers
+    rc = state_create(g, t0, b->fd_flags ? 5 : 3, &sl.st);
     if (rc != DG_OK) { dg_workspace_destroy(sl.ws); sl.ws = nullptr; return rc; }
     sl.used = true;
     sl.grid = g;
@@ -357,9 +360,53 @@ int dg_batch_detach(dg_batch* b, int slot) {
     return DG_OK;
 }
 
+int dg_batch_use_precond(dg_batch* b, int ws_fd_flags) {
+    if (!b) return fail(DG_E_INVAL, "NULL argument");
+    if (ws_fd_flags != 0 && ws_fd_flags != DG_WS_FD &&
+        ws_fd_flags != (DG_WS_FD | DG_WS_FD_PRODUCTS))
+        return fail(DG_E_INVAL, "ws_fd_flags must be 0, DG_WS_FD or DG_WS_FD | DG_WS_FD_PRODUCTS");
+    for (const Slot& sl : b->slots)
+        if (sl.used) return fail(DG_E_INVAL, "the preconditioner is chosen before members attach");
+    b->fd_flags = ws_fd_flags;
+    return DG_OK;
+}
+
 int dg_batch_use_graphs(dg_batch* b, int on) {
     if (!b) return fail(DG_E_INVAL, "NULL argument");
     b->use_graphs = on != 0;
+    return DG_OK;
+}
+
+// Preconditioned steps: the preconditioner's transforms and bases are per
+// grid, so each member takes its step through dg_rk_step on the batch's
+// stream (queued FP64-preconditioned stages, or the polled FP32-applied
+// preconditioner), one member after the other: the same kernels and results
+// as stand-alone steps, without the fused launches.
+static int rk_step_members(dg_batch* b, const dg_cg_opts& o, int* iters_out, void* stream) {
+    if (!b->fd_flags)
+        return fail(DG_E_WORKSPACE, "preconditioned batch steps need dg_batch_use_precond "
+                    "before the members attach");
+    bool all_conv = true;
+    for (int i = 0; i < b->capacity; ++i) {
+        Slot& sl = b->slots[i];
+        if (!sl.used) continue;
+        dg_step_opts so;
+        std::memset(&so, 0, sizeof so);
+        so.dt = sl.dt;
+        so.D = sl.D;
+        so.cg = o;
+        so.form = DG_FORM_ARAKAWA;
+        dg_step_stats st;
+        std::memset(&st, 0, sizeof st);
+        const int rc = dg_rk_step(sl.grid, sl.omega, sl.st, &so, &st, sl.ws, stream);
+        if (rc != DG_OK && rc != DG_E_NOCONV) return rc;
+        sl.converged = rc == DG_OK;
+        all_conv = all_conv && sl.converged;
+        if (iters_out)
+            for (int k = 0; k < 3; ++k) iters_out[3 * i + k] = st.cg_iters[k];
+    }
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    if (!all_conv) return fail(DG_E_NOCONV, "a batched solve did not converge");
     return DG_OK;
 }
 
@@ -370,9 +417,10 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
     if (opts) o = *opts;
     else { o.rtol = 1e-12; o.max_iter = 100000; o.precision = DG_PREC_FP64;
            o.precond = DG_PRECOND_NONE; o.check_every = 0; }
-    if (o.precision != DG_PREC_FP64 || o.precond != DG_PRECOND_NONE)
-        return fail(DG_E_UNSUPPORTED, "batches run the unpreconditioned FP64 CG only");
     if (!(o.rtol > 0) || o.max_iter < 0) return fail(DG_E_INVAL, "bad CG options");
+    if (o.precond == DG_PRECOND_FD) return rk_step_members(b, o, iters_out, stream);
+    if (o.precision != DG_PREC_FP64 || o.precond != DG_PRECOND_NONE)
+        return fail(DG_E_UNSUPPORTED, "fused batch steps run the unpreconditioned FP64 CG");
     hipStream_t s = (hipStream_t)stream;
     int used = 0;
     for (const Slot& sl : b->slots) used += sl.used;

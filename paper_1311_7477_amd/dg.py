@@ -120,6 +120,7 @@ def lib():
         "dg_batch_detach": (ctypes.c_int, [_vp, ctypes.c_int]),
         "dg_batch_member_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "dg_batch_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "dg_batch_use_precond": (ctypes.c_int, [_vp, ctypes.c_int]),
         "dg_batch_rk_step": (ctypes.c_int, [_vp, ctypes.POINTER(CgOpts),
                                             ctypes.POINTER(ctypes.c_int), _vp]),
         "dg_batch_copy_psi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
@@ -463,6 +464,12 @@ class Batch:
         self._h, self.capacity = h, capacity
         self.members = {}
         _check(lib().dg_batch_use_graphs(h, 1 if use_graphs else 0))
+
+    def use_precond(self, ws_fd_flags: int = DG_WS_FD):
+        """Members attached from now on get the fast-diagonalisation
+        preconditioner (call before attaching), so that rk_step can take
+        cg_opts(precond=DG_PRECOND_FD)."""
+        _check(lib().dg_batch_use_precond(self._h, ws_fd_flags))
 
     def attach(self, grid: Grid, omega, dt: float, D: float, t0: float = 0.0) -> int:
         slot = ctypes.c_int()

@@ -225,6 +225,7 @@ def test_null_arguments_are_rejected():
     assert L.dg_poisson_bracket(g.handle, x, ctypes.c_void_p(0x100000), x, None) == dg.DG_E_ALIAS
     assert L.dg_bracket_form(g.handle, ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000),
                              ctypes.c_void_p(0x30000), 9, None) == dg.DG_E_INVAL
+    assert L.dg_batch_use_precond(None, dg.DG_WS_FD) == dg.DG_E_INVAL
 
 
 @pytest.mark.parametrize("n,N,length", [(1, 7, 1.0), (2, 6, 2.0), (3, 5, 6.283185307179586),

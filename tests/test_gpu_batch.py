@@ -122,3 +122,40 @@ def test_batch_errors(dg):
     assert ei.value.code == dg.DG_E_UNSUPPORTED
     with pytest.raises(dg.DgError):
         batch.detach(5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_preconditioned_batch_bitwise_equals_alone(dg, precision):
+    # Members of a batch made with dg_batch_use_precond take preconditioned
+    # steps (each through dg_rk_step on the batch's stream): bitwise the same
+    # omega and psi as the instance stepped alone with the same options, on
+    # both transform paths (45 and 20 cells: folded products; 48 and 600:
+    # FFTs), with iteration counts reported per stage.
+    print(f"preconditioned batch {precision}", flush=True)
+    members = [(2, 45, 4.0, 21), (4, 48, 6.0, 22), (3, 600, 8.0, 23), (5, 20, 4.0, 24)]
+    prec = dg.DG_PREC_MIXED if precision == "mixed" else dg.DG_PREC_FP64
+    D, steps = 1e-4, 2
+    opts = dg.cg_opts(rtol=1e-11, precond=dg.DG_PRECOND_FD, precision=prec)
+    batch = dg.Batch(len(members))
+    batch.use_precond()
+    inst = []
+    for (n, N, k0, seed) in members:
+        grid, w0, dt = _member(dg, n, N, k0, seed)
+        w = torch.from_numpy(w0).cuda()
+        inst.append((batch.attach(grid, w, dt, D), grid, w0, dt, w))
+    its_b = []
+    for _ in range(steps):
+        its, ok = batch.rk_step(opts)
+        assert ok
+        its_b.append(its)
+    for slot, grid, w0, dt, w in inst:
+        assert batch.converged(slot)
+        assert abs(batch.time(slot) - steps * dt) <= 1e-15 * steps * dt
+        ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        st = dg.State(grid)
+        wa = torch.from_numpy(w0).cuda()
+        its_a = [dg.rk_step(grid, wa, st, ws, dt, D, opts).cg_iters for _ in range(steps)]
+        assert np.array_equal(w.cpu().numpy(), wa.cpu().numpy())
+        assert np.array_equal(batch.psi(slot).cpu().numpy(), st.psi().cpu().numpy())
+        assert [tuple(i[slot]) for i in its_b] == [tuple(i) for i in its_a]
+        assert all(1 <= k <= 4 for i in its_a for k in i)

@@ -264,10 +264,21 @@ def test_precond_errors(dg):
     with pytest.raises(dg.DgError) as e:
         dg.precond_apply(grid, w, both, out=w)
     assert e.value.code == dg.DG_E_ALIAS
+    # a batch takes preconditioned steps only with the preconditioner chosen
+    # before its members attach
     b = dg.Batch(2)
     b.attach(grid, w.clone(), 1e-3, 0.0)
     with pytest.raises(dg.DgError) as e:
         b.rk_step(dg.cg_opts(precond=dg.DG_PRECOND_FD))
+    assert e.value.code == dg.DG_E_WORKSPACE
+    with pytest.raises(dg.DgError) as e:
+        b.use_precond()
+    assert e.value.code == dg.DG_E_INVAL
+    with pytest.raises(dg.DgError) as e:
+        dg.Batch(1).use_precond(0x40)
+    assert e.value.code == dg.DG_E_INVAL
+    with pytest.raises(dg.DgError) as e:
+        b.rk_step(dg.cg_opts(precision=dg.DG_PREC_MIXED))
     assert e.value.code == dg.DG_E_UNSUPPORTED
 
 
