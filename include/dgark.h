@@ -419,8 +419,10 @@ int  dg_batch_use_graphs(dg_batch* b, int on);
  * DG_WS_FD_PRODUCTS; 0: none, the default), so that dg_batch_rk_step can
  * take opts->precond = DG_PRECOND_FD.  Such a member also holds
  * dg_workspace_bytes(grid, DG_PREC_FP64 | ws_fd_flags) instead of the plain
- * workspace, and two more fields of psi history.  Only while no member is
- * attached: DG_E_INVAL otherwise, or for other flags. */
+ * workspace, and two more fields of psi history.  Such a batch also takes
+ * grids with a homogeneous Dirichlet axis (their fused steps are refused:
+ * DG_E_UNSUPPORTED).  Only while no member is attached: DG_E_INVAL
+ * otherwise, or for other flags. */
 int  dg_batch_use_precond(dg_batch* b, int ws_fd_flags);
 /* One SSP-RK3 step of every attached instance.  With opts->precond =
  * DG_PRECOND_NONE (FP64 CG, opts->precision must be DG_PREC_FP64) the

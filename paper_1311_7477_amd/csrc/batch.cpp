@@ -311,7 +311,11 @@ void dg_batch_destroy(dg_batch* b) {
 int dg_batch_attach(dg_batch* b, const dg_grid* g, double* omega, double dt,
                     double D, double t0, int* slot) {
     if (!b || !g || !omega || !slot) return fail(DG_E_INVAL, "NULL argument");
-    if (g->geom.bcx || g->geom.bcy) return periodic_only("time stepping");
+    // the fused kernels carry no Dirichlet closure; members of a batch with
+    // the preconditioner step through dg_rk_step, which has it
+    if ((g->geom.bcx || g->geom.bcy) && !b->fd_flags)
+        return periodic_only("the fused batch steps (a batch made with dg_batch_use_precond "
+                             "takes Dirichlet members)");
     if (!std::isfinite(dt) || !std::isfinite(D)) return fail(DG_E_INVAL, "dt, D must be finite");
     int i = 0;
     while (i < b->capacity && b->slots[i].used) ++i;
@@ -421,6 +425,9 @@ int dg_batch_rk_step(dg_batch* b, const dg_cg_opts* opts, int* iters_out,
     if (o.precond == DG_PRECOND_FD) return rk_step_members(b, o, iters_out, stream);
     if (o.precision != DG_PREC_FP64 || o.precond != DG_PRECOND_NONE)
         return fail(DG_E_UNSUPPORTED, "fused batch steps run the unpreconditioned FP64 CG");
+    for (const Slot& sl : b->slots)
+        if (sl.used && (sl.grid->geom.bcx || sl.grid->geom.bcy))
+            return periodic_only("the fused batch steps");
     hipStream_t s = (hipStream_t)stream;
     int used = 0;
     for (const Slot& sl : b->slots) used += sl.used;

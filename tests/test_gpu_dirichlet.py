@@ -301,3 +301,36 @@ def test_dirichlet_grid_rejects_other_paths(dg):
     with pytest.raises(dg.DgError) as e:
         dg.Workspace(big, dg.DG_PREC_FP64 | dg.DG_WS_FD)
     assert e.value.code == dg.DG_E_UNSUPPORTED
+
+
+def test_preconditioned_batch_takes_dirichlet_members(dg):
+    # a batch made with dg_batch_use_precond takes Dirichlet grids (each
+    # member steps through dg_rk_step): bitwise the stand-alone steps; the
+    # fused, unpreconditioned steps of such a batch are refused
+    print("preconditioned batch with dirichlet members", flush=True)
+    n, D, dt, steps = 3, 1e-3, 2e-3, 2
+    opts = dg.cg_opts(rtol=1e-12, precond=dg.DG_PRECOND_FD)
+    shapes = [(40, 36, "dirichlet", "dirichlet"), (32, 44, "periodic", "dirichlet"),
+              (48, 48, "periodic", "periodic")]
+    batch = dg.Batch(len(shapes))
+    batch.use_precond()
+    inst = []
+    for nx, ny, bx, by in shapes:
+        g = O.Grid2D(n, nx, ny, bc_x=bx, bc_y=by)
+        X, Y = g.node_coords()
+        w0 = np.sin(X) * np.sin(Y) + 0.3 * np.sin(2 * X) * np.sin(3 * Y)
+        grid = dg.Grid(n, nx, ny, bc_x=CODE[bx], bc_y=CODE[by])
+        w = _dev(w0)
+        inst.append((batch.attach(grid, w, dt, D), grid, w0, w))
+    for _ in range(steps):
+        its, ok = batch.rk_step(opts)
+        assert ok
+    for slot, grid, w0, w in inst:
+        ws, st, wa = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD), dg.State(grid), _dev(w0)
+        for _ in range(steps):
+            assert dg.rk_step(grid, wa, st, ws, dt, D, opts).converged
+        assert np.array_equal(w.cpu().numpy(), wa.cpu().numpy())
+        assert np.array_equal(batch.psi(slot).cpu().numpy(), st.psi().cpu().numpy())
+    with pytest.raises(dg.DgError) as e:
+        batch.rk_step(dg.cg_opts(rtol=1e-12))
+    assert e.value.code == dg.DG_E_UNSUPPORTED
