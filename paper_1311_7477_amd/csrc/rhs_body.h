@@ -275,6 +275,11 @@ __device__ __forceinline__ void rhs_body(
     const auto c = make_ctx<N, WAVES>(g, tilesX, nblocks, b);
     const bool inner = c.wave > 0 && c.wave < WAVES - 1;   // wave-uniform
 
+    // At n = 3, Dx f, Dx g and the viscous Lx g are formed again after the
+    // column phase rather than held across its barriers (the same operations,
+    // so the same values): fewer registers, more waves per SIMD.  At n = 4
+    // and 5 that costs more than it saves.
+    constexpr bool kLate = N == 3;
     double F[N], G[N];
     load_vec(f, c.row, F);
     load_vec(gg, c.row, G);
@@ -290,7 +295,7 @@ __device__ __forceinline__ void rhs_body(
         lds_put_row(lB, c, G);
         lds_put_row(lC, c, Bv);
     }
-    if (VISC && inner) {
+    if (VISC && inner && !kLate) {
         if (DIR)
             row_ldg(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.L0Bx, k.eRBx, k.lLBx, k.ihx2,
                     LxG, c.at_l, c.at_r);
@@ -330,6 +335,10 @@ __device__ __forceinline__ void rhs_body(
     lds_get_row(lB, c, DyG);
     lds_get_row(lC, c, Q);
 
+    if (kLate) {
+        row_op<N, double, DIR>(F, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxF, c.at_l, c.at_r);
+        row_op<N, double, DIR>(G, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxG, c.at_l, c.at_r);
+    }
     double J[N], A[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -338,6 +347,13 @@ __device__ __forceinline__ void rhs_body(
     }
     double DxA[N];
     row_op<N, double, DIR>(A, c.lane, k.C0, k.cR, k.sR, k.cL, k.sL, k.ihx, DxA, c.at_l, c.at_r);
+    if (VISC && kLate) {
+        if (DIR)
+            row_ldg(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.L0Bx, k.eRBx, k.lLBx, k.ihx2,
+                    LxG, c.at_l, c.at_r);
+        else
+            row_op(G, c.lane, k.L0x, k.eRx, k.lR, k.eL, k.lLx, k.ihx2, LxG);
+    }
 
     if (!c.interior) return;
     double o[N];
