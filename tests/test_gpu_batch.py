@@ -124,7 +124,7 @@ def test_batch_errors(dg):
         batch.detach(5)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64-products"])
 def test_preconditioned_batch_bitwise_equals_alone(dg, precision):
     # Members of a batch made with dg_batch_use_precond take preconditioned
     # steps (each through dg_rk_step on the batch's stream): bitwise the same
@@ -134,10 +134,12 @@ def test_preconditioned_batch_bitwise_equals_alone(dg, precision):
     print(f"preconditioned batch {precision}", flush=True)
     members = [(2, 45, 4.0, 21), (4, 48, 6.0, 22), (3, 600, 8.0, 23), (5, 20, 4.0, 24)]
     prec = dg.DG_PREC_MIXED if precision == "mixed" else dg.DG_PREC_FP64
+    # fp64-products: every member's preconditioner on the folded products
+    fd = dg.DG_WS_FD | (dg.DG_WS_FD_PRODUCTS if precision.endswith("products") else 0)
     D, steps = 1e-4, 2
     opts = dg.cg_opts(rtol=1e-11, precond=dg.DG_PRECOND_FD, precision=prec)
     batch = dg.Batch(len(members))
-    batch.use_precond()
+    batch.use_precond(fd)
     inst = []
     for (n, N, k0, seed) in members:
         grid, w0, dt = _member(dg, n, N, k0, seed)
@@ -151,7 +153,7 @@ def test_preconditioned_batch_bitwise_equals_alone(dg, precision):
     for slot, grid, w0, dt, w in inst:
         assert batch.converged(slot)
         assert abs(batch.time(slot) - steps * dt) <= 1e-15 * steps * dt
-        ws = dg.Workspace(grid, dg.DG_PREC_FP64 | dg.DG_WS_FD)
+        ws = dg.Workspace(grid, dg.DG_PREC_FP64 | fd)
         st = dg.State(grid)
         wa = torch.from_numpy(w0).cuda()
         its_a = [dg.rk_step(grid, wa, st, ws, dt, D, opts).cg_iters for _ in range(steps)]
